@@ -1,0 +1,119 @@
+"""Oracle pins for the time stepping and the Parareal iteration (Sections 2.3, 3)."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import synth
+from oracle.residual import Discretization
+from oracle import propagate as P
+
+
+def _q1_laplacian_fluid(m):
+    """Q1 stiffness over the fluid cells, from 1d P1 matrices (Kronecker form)."""
+    def k1(h):
+        return np.array([[1.0, -1.0], [-1.0, 1.0]]) / h
+
+    def m1(h):
+        return np.array([[2.0, 1.0], [1.0, 2.0]]) * h / 6.0
+
+    def glob1(x, f):
+        n = len(x)
+        A = np.zeros((n, n))
+        for i in range(n - 1):
+            A[i:i + 2, i:i + 2] += f(x[i + 1] - x[i])
+        return A
+
+    x, y = m.axes
+    K = np.kron(glob1(y, m1), glob1(x, k1)) + np.kron(glob1(y, k1), glob1(x, m1))
+    for c in np.nonzero(m.solid)[0]:
+        hx, hy = m.h[c]
+        Kl = np.kron(m1(hy), k1(hx)) + np.kron(k1(hy), m1(hx))
+        n = m.conn[c]
+        K[np.ix_(n, n)] -= Kl
+    return sp.csr_matrix(K)
+
+
+def test_kinematic_and_harmonic_invariants():
+    """After every step: solid nodes move with the trapezoidal velocity, fluid u is discrete-harmonic."""
+    p = synth.workload("c1")
+    D = Discretization(p)
+    m = D.mesh
+    L = _q1_laplacian_fluid(m)
+    k = p["k_fine"]
+    th = 0.5 + p["theta0"] * k
+    U = np.zeros((m.n_nodes, 5))
+    solid_rows = m.in_NS & ~D.dirichlet[:, 2]
+    fluid_rows = ~m.in_NS & ~D.dirichlet[:, 2]
+    for n in range(1, 6):
+        Un = P.newton_step(D, U, n * k, k)
+        du = Un[:, 2:4] - U[:, 2:4]
+        kin = k * (th * Un[:, 0:2] + (1 - th) * U[:, 0:2])
+        assert np.abs(du[solid_rows] - kin[solid_rows]).max() <= 1e-12 * np.abs(kin[solid_rows]).max()
+        Lu = L @ Un[:, 2:4]
+        scale = abs(L).max() * np.abs(Un[:, 2:4]).max()
+        assert np.abs(Lu[fluid_rows]).max() <= 1e-11 * scale
+        U = Un
+    assert np.abs(U[:, 2:4]).max() > 0  # the bar did move
+
+
+def _self_convergence(theta_fixed):
+    """Ratios of successive differences ||U_k - U_{k/2}|| at T for v and u.
+
+    A softer bar (mu_s = 5e3) and a more viscous fluid (nu_f = 1e-2) put the
+    step sizes 0.1/4 .. 0.1/32 in the asymptotic range of the scheme; with the
+    workload's stiff bar the solid's own period (~0.05) is not resolved by
+    these steps.
+    """
+    p = synth.workload("c1", theta_fixed=theta_fixed, mu_s=5e3, nu_f=1e-2, ramp_time=0.2)
+    p["lambda_s"] = synth.lame_lambda(p["mu_s"], p["nu_s"])
+    D = Discretization(p)
+    U0 = np.zeros((D.mesh.n_nodes, 5))
+    T = 0.1
+    sols = [P.propagate(D, U0, 0.0, T, n) for n in (4, 8, 16, 32)]
+    ratios = []
+    for sl in (slice(0, 2), slice(2, 4)):
+        e = [np.linalg.norm(sols[j][:, sl] - sols[j + 1][:, sl]) for j in range(3)]
+        ratios.append(e[1] / e[2])
+    return ratios
+
+
+def test_shifted_cn_second_order():
+    """theta = 1/2 + k: self-convergence ratio -> 4 (second order, Section 2.3)."""
+    r = _self_convergence(None)
+    for x in r:
+        assert 3.3 < x < 4.7, r
+
+
+def test_backward_euler_first_order():
+    """theta = 1 is backward Euler, first order (Section 2.3): ratio -> 2."""
+    r = _self_convergence(1.0)
+    for x in r:
+        assert 1.7 < x < 2.3, r
+
+
+def _small_parareal_problem():
+    return synth.workload("c1", T=0.2, N=4, dt_fine=0.0125, dt_coarse=0.05)
+
+
+def test_parareal_finite_termination_and_K_equals_N():
+    """After i iterations slices 0..i are exact; K = N gives the sequential fine solution."""
+    p = _small_parareal_problem()
+    assert (p["m"], p["M"]) == (4, 1)
+    D = Discretization(p)
+    U0 = np.zeros((D.mesh.n_nodes, 5))
+    seq = P.sequential(D, p, U0)
+    hist = []
+    Upar, it = P.parareal(D, p, U0, tol=0.0, history=hist)
+    assert it == p["N"]
+
+    def rel(a, b):
+        nb = np.linalg.norm(b)
+        return np.linalg.norm(a - b) / nb if nb > 0 else np.linalg.norm(a - b)
+
+    for i, (Ui, _) in enumerate(hist):
+        for l in range(0, i + 2):
+            assert rel(Ui[l][:, :4], seq[l][:, :4]) <= 1e-12, (i, l)
+    # the iterate before convergence is not yet exact on the last slice
+    assert rel(hist[0][0][p["N"]][:, :4], seq[p["N"]][:, :4]) > 1e-8
+    for l in range(p["N"] + 1):
+        assert rel(Upar[l][:, :4], seq[l][:, :4]) <= 1e-12
