@@ -1,0 +1,162 @@
+/*
+ * fsi.h -- C ABI of the MI355X fine propagator for monolithic ALE
+ * fluid-structure interaction (Margenberg & Richter, "Parallel time-stepping
+ * for fluid-structure interactions").
+ *
+ * The library integrates the semi-discrete ALE-FSI system of eqs. (ALE),
+ * (ALE:stress), discretised as in eqs. (variational), (test) with equal-order
+ * Q1 elements on an interface-fitted quadrilateral mesh (Section 2.2), by the
+ * shifted Crank-Nicolson step of Section 2.3 with theta = 1/2 + theta0 k.
+ * Each step is solved by Newton's method with an exact Jacobian; the linear
+ * systems are solved by restarted FGMRES preconditioned with a geometric
+ * multigrid V-cycle (colored multiplicative Vanka smoother).  The propagators
+ * and the Parareal iteration follow Section 3, eq. (parareal:iteration).
+ *
+ * Conventions (all entry points):
+ *   - Every call returns fsi_status (FSI_OK = 0, errors < 0).  No C++
+ *     exception crosses the ABI.
+ *   - State vectors are device arrays of float64 in node-major layout
+ *     U[b][node][comp], comp = (v_x, v_y, u_x, u_y, p) in 2d, node index
+ *     i + (nx+1) j.  The caller owns every array it passes; the library keeps
+ *     no caller pointer after a call returns.
+ *   - The library owns the fsi_problem handle and all device workspace; it is
+ *     sized in fsi_setup for up to params.max_batch slices per call.
+ *   - Work is enqueued on the given HIP stream; calls return after
+ *     completion because the host needs the convergence status.
+ *   - Host arrays (t0_host, stats) are read/written synchronously.
+ *   - Calls on one fsi_problem must not overlap (the workspace is shared).
+ */
+#ifndef FSI_H
+#define FSI_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FSI_OK = 0,
+  FSI_ERR_ARG = -1,        /* invalid argument (null pointer, size out of range, bad params) */
+  FSI_ERR_HIP = -2,        /* a HIP runtime call failed */
+  FSI_ERR_OOM = -3,        /* device allocation failed */
+  FSI_ERR_NEWTON = -4,     /* Newton did not converge within newton_maxit in some slice */
+  FSI_ERR_LINEAR = -5,     /* FGMRES did not reach its tolerance within gmres_maxit */
+  FSI_ERR_NONFINITE = -6,  /* non-finite input or iterate */
+  FSI_ERR_PARAREAL = -7    /* Parareal did not reach its tolerance within max_iter */
+} fsi_status;
+
+enum { FSI_FP64 = 0, FSI_MIXED = 1 };
+
+typedef struct fsi_problem fsi_problem;
+
+/* Problem description.  SI units as in Table "parameters" of Section 4. */
+typedef struct {
+  int32_t dim;               /* 2 (the only dimension built) */
+  int32_t level;             /* refinement level l >= 1 of the level-0 mesh */
+  /* level-0 tensor mesh: per axis nseg segments, breakpoints seg_pts[a][0..nseg],
+     seg_cells[a][s] level-0 cells in segment s; the bar faces must be breakpoints */
+  int32_t nseg[3];
+  double seg_pts[3][5];
+  int32_t seg_cells[3][4];
+  double solid_lo[3], solid_hi[3];   /* elastic bar: cells whose centre lies inside */
+  double rho_f, nu_f, rho_s, mu_s, lambda_s;
+  double inflow_peak;        /* peak of the parabolic inflow profile */
+  double ramp_time;          /* s(t) = (1 - cos(pi t / ramp_time)) / 2 for t < ramp_time, then 1 */
+  double theta0;             /* theta = 1/2 + theta0 k */
+  double lps_alpha0;         /* local-projection constant: alpha_K = alpha0 h_K^2 / (rho_f nu_f) */
+  double cip_gamma;          /* coarsest multigrid level only: gradient-jump pressure penalty */
+  int32_t precision;         /* FSI_FP64 or FSI_MIXED (FP32 FGMRES/multigrid, FP64 Newton residual) */
+  int32_t gmres_restart;     /* Krylov basis size (<= 64) */
+  int32_t gmres_maxit;       /* total FGMRES iterations per linear solve */
+  int32_t newton_maxit;
+  int32_t vanka_sweeps;      /* pre- and post-smoothing sweeps per level */
+  double vanka_omega;        /* Vanka damping */
+  double newton_rtol;        /* stop when every field's update <= rtol * |field|_inf */
+  double lin_rtol;           /* FGMRES relative tolerance of the row-scaled residual */
+  int32_t max_batch;         /* largest number of slices per call */
+} fsi_params;
+
+#define FSI_MAX_SLICES 1024
+typedef struct {
+  int32_t newton_its[FSI_MAX_SLICES];   /* Newton iterations summed over the steps, per slice */
+  int32_t krylov_its[FSI_MAX_SLICES];   /* FGMRES iterations summed over the steps, per slice */
+  int32_t slice_status[FSI_MAX_SLICES]; /* fsi_status of the slice */
+  double stage_ms[8];                   /* 0 residual, 1 Jacobian+smoother setup, 2 linear solve,
+                                           3 update, 4 total, 5 coarse (Parareal), 6 fine (Parareal) */
+  int32_t parareal_iters;
+  int32_t newton_total, krylov_total;   /* totals over all slices of the call */
+} fsi_stats;
+
+/* Build the mesh hierarchy, node classes, constant stabilisation operators and
+   device workspace for params->max_batch slices.  *out receives the handle.
+   Errors: FSI_ERR_ARG (bad params), FSI_ERR_OOM, FSI_ERR_HIP. */
+fsi_status fsi_setup(const fsi_params* params, fsi_problem** out);
+
+/* Number of mesh nodes and of unknowns (5 per node in 2d) on the finest level. */
+fsi_status fsi_sizes(const fsi_problem* pb, int64_t* n_nodes, int64_t* n_dofs);
+
+/* U0_dev[n_dofs] := zero state with the Dirichlet data of t = 0. */
+fsi_status fsi_initial_state(fsi_problem* pb, double* U0_dev, hipStream_t stream);
+
+/* Fine propagator F of Section 3: for each of B slices b, m uniform steps of
+   size k = slice_len / m from t0_host[b] (host array), starting from
+   U_in_dev[b] and writing the final state to U_out_dev[b] (both [B][n_dofs],
+   may alias).  The pressure of U_in only seeds Newton.  Per-slice status and
+   iteration counts go to stats (host, may be NULL).  Non-finite input gives
+   FSI_ERR_NONFINITE before any work; a slice that fails keeps its last iterate. */
+fsi_status fine_propagate(fsi_problem* pb, int32_t B, const double* t0_host, double slice_len,
+                          int32_t m, const double* U_in_dev, double* U_out_dev,
+                          fsi_stats* stats, hipStream_t stream);
+
+/* Coarse propagator C of Section 3: the same scheme with M steps of size
+   K = slice_len / M (theta = 1/2 + theta0 K).  Arguments as fine_propagate. */
+fsi_status coarse_propagate(fsi_problem* pb, int32_t B, const double* t0_host, double slice_len,
+                            int32_t M, const double* U_in_dev, double* U_out_dev,
+                            fsi_stats* stats, hipStream_t stream);
+
+/* Parareal, eq. (parareal:iteration): N slices of length T/N on [0, T], fine
+   propagator with m steps, coarse with M steps per slice.  Writes the slice
+   boundary states U_bnd_dev[N+1][n_dofs] (U_bnd[0] = U0).  Stops when the
+   largest relative change over the boundaries of v and u is below tol or after
+   max_iter (<= N) iterations; the last fine sweep batches all unconverged
+   slices in one call.  Returns FSI_ERR_PARAREAL if tol was not met. */
+fsi_status parareal_run(fsi_problem* pb, double T, int32_t N, int32_t m, int32_t M, double tol,
+                        int32_t max_iter, const double* U0_dev, double* U_bnd_dev,
+                        fsi_stats* stats, hipStream_t stream);
+
+/* Test and benchmark entry points (same conventions).
+   fsi_debug_residual: R_out[b] = residual of one step t_host[b]-k -> t_host[b]
+     at the new state U[b] with old state Uo[b] (Dirichlet rows included).
+   fsi_debug_jacobian_apply: assemble the Jacobian at (U[b], Uo[b]) on the
+     finest level and return Y[b] = J X[b] (FP64 path), or the FP32 copy's
+     product in the mixed path.
+   fsi_debug_vcycle: one V-cycle of the multigrid built at (U, Uo): Y = M^{-1} X. */
+fsi_status fsi_debug_residual(fsi_problem* pb, int32_t B, const double* U, const double* Uo,
+                              const double* t_host, double k, double* R_out, hipStream_t stream);
+fsi_status fsi_debug_jacobian_apply(fsi_problem* pb, int32_t B, const double* U, const double* Uo,
+                                    const double* t_host, double k, const double* X, double* Y,
+                                    hipStream_t stream);
+fsi_status fsi_debug_vcycle(fsi_problem* pb, int32_t B, const double* U, const double* Uo,
+                            const double* t_host, double k, const double* X, double* Y,
+                            hipStream_t stream);
+
+/* Per-kernel timing over the calls made while enabled (HIP events on the
+   caller's stream around every launch of the named kernel family).
+   fsi_profile_enable(pb, 1) starts collecting (and clears), 0 stops.
+   fsi_profile_query returns the launch count and summed milliseconds of
+   kernel family `which` (0 = Vanka smoothing pass, 1 = fine SpMV,
+   2 = element Jacobian, 3 = residual) and the algorithmic bytes those
+   launches moved. */
+fsi_status fsi_profile_enable(fsi_problem* pb, int32_t on);
+fsi_status fsi_profile_query(const fsi_problem* pb, int32_t which, int64_t* launches, double* ms,
+                             double* bytes);
+
+void fsi_destroy(fsi_problem* pb);
+const char* fsi_status_string(fsi_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FSI_H */

@@ -1,0 +1,991 @@
+// Host driver: mesh hierarchy and constant operators (setup), Newton's method
+// per time step with a multigrid-preconditioned FGMRES inner solve, the fine
+// and coarse propagators, Parareal, and the C ABI of include/fsi.h.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "kernels.h"
+
+using namespace fsi;
+
+#define HIPCHK(x)                                   \
+  do {                                              \
+    hipError_t e_ = (x);                            \
+    if (e_ != hipSuccess) {                         \
+      std::fprintf(stderr, "fsi: %s failed: %s (%s:%d)\n", #x, hipGetErrorString(e_), __FILE__, __LINE__); \
+      return FSI_ERR_HIP;                           \
+    }                                               \
+  } while (0)
+
+#define CHK(x)                        \
+  do {                                \
+    fsi_status s_ = (x);              \
+    if (s_ != FSI_OK) return s_;      \
+  } while (0)
+
+namespace {
+
+constexpr int TPB = 256;
+constexpr int MAXLEV = 8;
+constexpr int NCHUNK_MAX = 1024;
+
+struct Level {
+  int nx = 0, ny = 0, nn = 0, ncell = 0;
+  std::vector<double> x, y, pst;
+  std::vector<uint8_t> solid, cls, dmask;
+  double *d_x = nullptr, *d_y = nullptr, *d_pst = nullptr;
+  uint8_t *d_solid = nullptr, *d_cls = nullptr, *d_dmask = nullptr;
+  // batch workspace
+  double *U = nullptr, *Uo = nullptr, *Dsc = nullptr;
+  void *J = nullptr, *Ainv = nullptr, *x_ = nullptr, *b_ = nullptr, *r_ = nullptr, *t_ = nullptr;
+  Geom geom() const {
+    Geom g;
+    g.nx = nx; g.ny = ny; g.nn = nn; g.ncell = ncell;
+    g.x = d_x; g.y = d_y; g.solid = d_solid; g.cls = d_cls; g.dmask = d_dmask; g.pst = d_pst;
+    return g;
+  }
+};
+
+struct Prof {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[4];
+  double bytes[4] = {0, 0, 0, 0};
+  int64_t launches[4] = {0, 0, 0, 0};
+};
+
+}  // namespace
+
+struct fsi_problem {
+  fsi_params p;
+  int nlev = 0;          // levels 0..nlev-1, nlev-1 finest
+  Level lev[MAXLEV];
+  int Bmax = 0;
+  bool mixed = false;
+  size_t ssz = 8;        // sizeof(S)
+  int R = 30;
+  // finest-level Newton data (double)
+  double *U = nullptr, *Uold = nullptr, *Res = nullptr, *Re = nullptr, *Ke = nullptr, *tdev = nullptr;
+  int *nact = nullptr;   // Newton-active slices (device)
+  int *gact = nullptr;   // FGMRES-active slices (device)
+  int *flag = nullptr;
+  // FGMRES workspace
+  void *V = nullptr, *Z = nullptr, *w = nullptr, *xs = nullptr, *tmp = nullptr;
+  double *H = nullptr, *hcol = nullptr, *hcol2 = nullptr, *cs = nullptr, *sn = nullptr, *gv = nullptr,
+         *res = nullptr, *beta0 = nullptr, *beta = nullptr, *ycoef = nullptr, *partial = nullptr;
+  int *gstate = nullptr, *ncol = nullptr;
+  // coarsest level block LU
+  double *cDinv = nullptr, *cW = nullptr, *cL = nullptr;
+  int cbs = 0, cnsb = 0;
+  // Newton norms
+  double *npart = nullptr, *nmax = nullptr;
+  int nchunk_n = 1, chunk_n = 1;
+  Prof prof;
+  std::vector<void*> allocs;
+};
+
+namespace {
+
+// ------------------------------------------------------------------ helpers
+template <class T>
+fsi_status dalloc(fsi_problem* pb, T** p, size_t n) {
+  void* q = nullptr;
+  if (n == 0) n = 1;
+  if (hipMalloc(&q, n * sizeof(T)) != hipSuccess) return FSI_ERR_OOM;
+  if (hipMemset(q, 0, n * sizeof(T)) != hipSuccess) return FSI_ERR_HIP;
+  pb->allocs.push_back(q);
+  *p = (T*)q;
+  return FSI_OK;
+}
+fsi_status dalloc_bytes(fsi_problem* pb, void** p, size_t bytes) {
+  void* q = nullptr;
+  if (bytes == 0) bytes = 1;
+  if (hipMalloc(&q, bytes) != hipSuccess) return FSI_ERR_OOM;
+  if (hipMemset(q, 0, bytes) != hipSuccess) return FSI_ERR_HIP;
+  pb->allocs.push_back(q);
+  *p = q;
+  return FSI_OK;
+}
+template <class T>
+fsi_status upload(fsi_problem* pb, T** d, const std::vector<T>& h) {
+  CHK(dalloc(pb, d, h.size()));
+  HIPCHK(hipMemcpy(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  return FSI_OK;
+}
+
+inline dim3 grid1(int n, int B) { return dim3((n + TPB - 1) / TPB, B); }
+
+// ---------------------------------------------------------------- setup
+// Axis coordinates of level l: every level-0 segment split into cells*2^l equal parts.
+std::vector<double> axis_points(const fsi_params& p, int a, int l) {
+  std::vector<double> pts;
+  for (int s = 0; s < p.nseg[a]; ++s) {
+    const double lo = p.seg_pts[a][s], hi = p.seg_pts[a][s + 1];
+    const int n = p.seg_cells[a][s] << l;
+    for (int q = 0; q < n; ++q) pts.push_back(lo + (hi - lo) * q / n);
+  }
+  pts.push_back(p.seg_pts[a][p.nseg[a]]);
+  return pts;
+}
+
+// Q1 Laplace stiffness of an hx x hy rectangle (2x2 Gauss rule, exact), local order (0,0),(1,0),(0,1),(1,1).
+void q1_stiffness(double hx, double hy, double K[4][4]) {
+  const double g[2] = {0.5 - 0.5 / std::sqrt(3.0), 0.5 + 0.5 / std::sqrt(3.0)};
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b) K[a][b] = 0.0;
+  for (int q = 0; q < 4; ++q) {
+    const double xi = g[q & 1], eta = g[q >> 1];
+    const double gx[4] = {-(1 - eta) / hx, (1 - eta) / hx, -eta / hx, eta / hx};
+    const double gy[4] = {-(1 - xi) / hy, -xi / hy, (1 - xi) / hy, xi / hy};
+    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 4; ++b) K[a][b] += 0.25 * hx * hy * (gx[a] * gx[b] + gy[a] * gy[b]);
+  }
+}
+
+void add_pst(Level& L, int nr, int nc, double v) {
+  const int ir = nr % (L.nx + 1), jr = nr / (L.nx + 1);
+  const int ic = nc % (L.nx + 1), jc = nc / (L.nx + 1);
+  L.pst[(size_t)pslot_of(ic - ir, jc - jr) * L.nn + nr] += v;
+}
+
+// Two-level local projection: alpha_K (grad(p - i2h p), grad(q - i2h q))_K over fluid cells,
+// i2h = Q1 interpolation on the parent (2x2 cells) of K.
+void build_lps(Level& L, const fsi_params& p) {
+  for (int j = 0; j < L.ny; ++j)
+    for (int i = 0; i < L.nx; ++i) {
+      const int cell = i + L.nx * j;
+      if (L.solid[cell]) continue;
+      const double hx = L.x[i + 1] - L.x[i], hy = L.y[j + 1] - L.y[j];
+      const double alpha = p.lps_alpha0 * hx * hy / (p.rho_f * p.nu_f);
+      double K[4][4];
+      q1_stiffness(hx, hy, K);
+      const int ox = i - (i & 1), oy = j - (j & 1);   // parent patch origin node
+      const int cx = i & 1, cy = j & 1;
+      // kappa[a][9]: fluctuation at fine node a in terms of the 9 patch nodes
+      double kap[4][9];
+      for (int a = 0; a < 4; ++a) {
+        for (int q = 0; q < 9; ++q) kap[a][q] = 0.0;
+        const int px = cx + (a & 1), py = cy + (a >> 1);
+        kap[a][px + 3 * py] += 1.0;
+        const double sx = 0.5 * px, sy = 0.5 * py;
+        for (int b = 0; b < 4; ++b) {
+          const double wx = (b & 1) ? sx : 1.0 - sx, wy = (b >> 1) ? sy : 1.0 - sy;
+          kap[a][2 * (b & 1) + 3 * 2 * (b >> 1)] -= wx * wy;
+        }
+      }
+      for (int q = 0; q < 9; ++q)
+        for (int r = 0; r < 9; ++r) {
+          double s = 0.0;
+          for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < 4; ++b) s += kap[a][q] * K[a][b] * kap[b][r];
+          if (s == 0.0) continue;
+          const int nq = (ox + q % 3) + (L.nx + 1) * (oy + q / 3);
+          const int nr = (ox + r % 3) + (L.nx + 1) * (oy + r / 3);
+          add_pst(L, nq, nr, alpha * s);
+        }
+    }
+}
+
+// Coarsest level: gradient-jump penalty gamma h_F h_n^3 / (rho nu) int_F [d_n p][d_n q] over
+// interior faces between fluid cells (a preconditioner-only stabilisation; level 0 has no parents).
+void build_cip(Level& L, const fsi_params& p) {
+  const double g[2] = {0.5 - 0.5 / std::sqrt(3.0), 0.5 + 0.5 / std::sqrt(3.0)};
+  for (int j = 0; j < L.ny; ++j)
+    for (int i = 0; i < L.nx; ++i)
+      for (int dir = 0; dir < 2; ++dir) {
+        const int i2 = i + (dir == 0), j2 = j + (dir == 1);
+        if (i2 >= L.nx || j2 >= L.ny) continue;
+        const int c1 = i + L.nx * j, c2 = i2 + L.nx * j2;
+        if (L.solid[c1] || L.solid[c2]) continue;
+        const double h1x = L.x[i + 1] - L.x[i], h1y = L.y[j + 1] - L.y[j];
+        const double h2x = L.x[i2 + 1] - L.x[i2], h2y = L.y[j2 + 1] - L.y[j2];
+        const double hF = dir == 0 ? h1y : h1x;
+        const double hn = dir == 0 ? 0.5 * (h1x + h2x) : 0.5 * (h1y + h2y);
+        int nodes[8];
+        const int n1 = i + (L.nx + 1) * j, n2 = i2 + (L.nx + 1) * j2;
+        const int off[4] = {0, 1, L.nx + 1, L.nx + 2};
+        for (int a = 0; a < 4; ++a) { nodes[a] = n1 + off[a]; nodes[4 + a] = n2 + off[a]; }
+        for (int q = 0; q < 2; ++q) {
+          const double s = g[q];
+          double c[8];
+          for (int a = 0; a < 4; ++a) {
+            const int ax = a & 1, ay = a >> 1;
+            if (dir == 0) {   // face x = const: cell 1 at xi = 1, cell 2 at xi = 0; normal derivative d/dx
+              const double fy = ay ? s : 1.0 - s;
+              c[a] = (ax ? 1.0 : -1.0) * fy / h1x;
+              c[4 + a] = -(ax ? 1.0 : -1.0) * fy / h2x;
+            } else {
+              const double fx = ax ? s : 1.0 - s;
+              c[a] = (ay ? 1.0 : -1.0) * fx / h1y;
+              c[4 + a] = -(ay ? 1.0 : -1.0) * fx / h2y;
+            }
+          }
+          const double w = p.cip_gamma * 0.5 * hF * hn * hn * hn / (p.rho_f * p.nu_f);
+          for (int a = 0; a < 8; ++a)
+            for (int b = 0; b < 8; ++b) add_pst(L, nodes[a], nodes[b], w * c[a] * c[b]);
+        }
+      }
+}
+
+fsi_status build_level(fsi_problem* pb, int l) {
+  const fsi_params& p = pb->p;
+  Level& L = pb->lev[l];
+  L.x = axis_points(p, 0, l);
+  L.y = axis_points(p, 1, l);
+  L.nx = (int)L.x.size() - 1;
+  L.ny = (int)L.y.size() - 1;
+  L.nn = (L.nx + 1) * (L.ny + 1);
+  L.ncell = L.nx * L.ny;
+  L.solid.assign(L.ncell, 0);
+  for (int j = 0; j < L.ny; ++j)
+    for (int i = 0; i < L.nx; ++i) {
+      const double xc = 0.5 * (L.x[i] + L.x[i + 1]), yc = 0.5 * (L.y[j] + L.y[j + 1]);
+      L.solid[i + L.nx * j] = (xc > p.solid_lo[0] && xc < p.solid_hi[0] && yc > p.solid_lo[1] && yc < p.solid_hi[1]);
+    }
+  L.cls.assign(L.nn, 0);
+  for (int j = 0; j < L.ny; ++j)
+    for (int i = 0; i < L.nx; ++i) {
+      const uint8_t bit = L.solid[i + L.nx * j] ? CL_NS : CL_NF;
+      for (int a = 0; a < 4; ++a) L.cls[(i + (a & 1)) + (L.nx + 1) * (j + (a >> 1))] |= bit;
+    }
+  L.dmask.assign(L.nn, 0);
+  for (int j = 0; j <= L.ny; ++j)
+    for (int i = 0; i <= L.nx; ++i) {
+      const int n = i + (L.nx + 1) * j;
+      const bool inflow = i == 0, outflow = i == L.nx, wall = (j == 0 || j == L.ny);
+      uint8_t m = 0;
+      if (inflow || wall) m |= DM_V;
+      if (inflow || outflow || wall) m |= DM_U;
+      if (!(L.cls[n] & CL_NF)) m |= DM_P;
+      L.dmask[n] = m;
+      if (inflow && !wall) L.cls[n] |= CL_INFLOW;
+    }
+  L.pst.assign((size_t)NPST * L.nn, 0.0);
+  if (l >= 1)
+    build_lps(L, p);
+  else
+    build_cip(L, p);
+  CHK(upload(pb, &L.d_x, L.x));
+  CHK(upload(pb, &L.d_y, L.y));
+  CHK(upload(pb, &L.d_pst, L.pst));
+  CHK(upload(pb, &L.d_solid, L.solid));
+  CHK(upload(pb, &L.d_cls, L.cls));
+  CHK(upload(pb, &L.d_dmask, L.dmask));
+  // batch workspace
+  const int B = pb->Bmax;
+  const size_t ss = pb->ssz;
+  CHK(dalloc(pb, &L.U, (size_t)B * L.nn * NC));
+  CHK(dalloc(pb, &L.Uo, (size_t)B * L.nn * NC));
+  CHK(dalloc(pb, &L.Dsc, (size_t)B * L.nn * NC));
+  CHK(dalloc_bytes(pb, &L.J, (size_t)B * NSLOT * BLK * L.nn * ss));
+  if (l >= 1) CHK(dalloc_bytes(pb, &L.Ainv, (size_t)B * NE * NE * L.ncell * ss));
+  CHK(dalloc_bytes(pb, &L.x_, (size_t)B * L.nn * NC * ss));
+  CHK(dalloc_bytes(pb, &L.b_, (size_t)B * L.nn * NC * ss));
+  CHK(dalloc_bytes(pb, &L.r_, (size_t)B * L.nn * NC * ss));
+  CHK(dalloc_bytes(pb, &L.t_, (size_t)B * L.nn * NC * ss));
+  return FSI_OK;
+}
+
+// ------------------------------------------------------------ profiling
+void prof_rec(fsi_problem* pb, hipEvent_t* e, hipStream_t st) {
+  Prof& P = pb->prof;
+  if (P.used >= P.pool.size()) {
+    hipEvent_t ev;
+    (void)hipEventCreate(&ev);
+    P.pool.push_back(ev);
+  }
+  *e = P.pool[P.used++];
+  (void)hipEventRecord(*e, st);
+}
+struct ProfScope {
+  fsi_problem* pb;
+  int fam;
+  hipStream_t st;
+  hipEvent_t e0{}, e1{};
+  double bytes;
+  ProfScope(fsi_problem* p, int f, hipStream_t s, double by) : pb(p), fam(f), st(s), bytes(by) {
+    if (pb->prof.on) prof_rec(pb, &e0, st);
+  }
+  ~ProfScope() {
+    if (!pb->prof.on) return;
+    prof_rec(pb, &e1, st);
+    pb->prof.ev[fam].push_back({e0, e1});
+    pb->prof.bytes[fam] += bytes;
+    pb->prof.launches[fam] += 1;
+  }
+};
+
+StepPar step_par(const fsi_problem* pb, double k) {
+  StepPar sp;
+  sp.k = k;
+  sp.theta = 0.5 + pb->p.theta0 * k;
+  sp.rho_f = pb->p.rho_f; sp.nu_f = pb->p.nu_f; sp.rho_s = pb->p.rho_s;
+  sp.mu_s = pb->p.mu_s; sp.lambda_s = pb->p.lambda_s;
+  sp.peak = pb->p.inflow_peak; sp.ramp_time = pb->p.ramp_time;
+  return sp;
+}
+
+// ------------------------------------------------------------ assembly
+fsi_status residual(fsi_problem* pb, int B, const StepPar& sp, const double* U, const double* Uo, double* R,
+                    const int* act, hipStream_t st) {
+  Level& F = pb->lev[pb->nlev - 1];
+  const Geom g = F.geom();
+  {
+    ProfScope ps(pb, 3, st, (double)B * (F.nn * NC * 8.0 * 3 + F.ncell * NE * 8.0 * 2));
+    k_elem_residual<<<grid1(g.ncell, B), TPB, 0, st>>>(g, sp, U, Uo, pb->Re, act);
+    k_gather_residual<<<grid1(g.nn, B), TPB, 0, st>>>(g, sp, pb->Re, U, pb->tdev, R, act);
+  }
+  HIPCHK(hipGetLastError());
+  return FSI_OK;
+}
+
+template <class S>
+fsi_status assemble_levels(fsi_problem* pb, int B, const StepPar& sp, const int* act, hipStream_t st) {
+  const int L = pb->nlev - 1;
+  for (int l = L; l >= 0; --l) {
+    Level& lv = pb->lev[l];
+    const Geom g = lv.geom();
+    const double* U = (l == L) ? pb->U : lv.U;
+    const double* Uo = (l == L) ? pb->Uold : lv.Uo;
+    if (l < L) {
+      const Level& f = pb->lev[l + 1];
+      const double* Uf = (l + 1 == L) ? pb->U : f.U;
+      const double* Uof = (l + 1 == L) ? pb->Uold : f.Uo;
+      k_inject<<<grid1(g.nn, B), TPB, 0, st>>>(g, f.geom(), Uf, lv.U, B);
+      k_inject<<<grid1(g.nn, B), TPB, 0, st>>>(g, f.geom(), Uof, lv.Uo, B);
+    }
+    {
+      ProfScope ps(pb, 2, st, (double)B * (g.ncell * NE * NE * 8.0 + 2.0 * g.nn * NC * 8));
+      k_elem_jacobian<false><<<dim3((g.ncell + 127) / 128, B), 128, 0, st>>>(g, sp, U, Uo, pb->Ke, act);
+    }
+    k_gather_jacobian<S><<<grid1(g.nn, B), TPB, 0, st>>>(g, sp.k, pb->Ke, (S*)lv.J, lv.Dsc, act);
+    if (l >= 1) {
+      k_vanka_factor<S><<<dim3((g.ncell * 32 + TPB - 1) / TPB, B), TPB, 0, st>>>(g, sp.k, (const S*)lv.J,
+                                                                              (S*)lv.Ainv, act);
+    } else {
+      const size_t lds = (size_t)3 * pb->cbs * pb->cbs * sizeof(double);
+      k_coarse_factor<S><<<B, TPB, lds, st>>>(g, sp.k, (const S*)lv.J, pb->cbs, pb->cnsb, pb->cDinv, pb->cW, pb->cL,
+                                              act);
+    }
+    HIPCHK(hipGetLastError());
+  }
+  return FSI_OK;
+}
+
+// ------------------------------------------------------------ multigrid
+template <class S>
+void smooth(fsi_problem* pb, int l, int B, double k, int sweeps, bool zero_first, S* x, S* tmp, const S* b,
+            const int* act, hipStream_t st) {
+  Level& lv = pb->lev[l];
+  const Geom g = lv.geom();
+  const S om = (S)pb->p.vanka_omega;
+  S* cur = x;
+  S* oth = tmp;
+  for (int s = 0; s < sweeps; ++s)
+    for (int c = 0; c < 4; ++c) {
+      const int cx = c & 1, cy = c >> 1;
+      const int nb = ((g.nx + cx) / 2 + 1) * ((g.ny + cy) / 2 + 1);
+      const int zero = (zero_first && s == 0 && c == 0) ? 1 : 0;
+      {
+        const double per = (double)NSLOT * BLK * g.nn * sizeof(S) + (double)NE * NE * g.ncell / 4 * sizeof(S) +
+                           3.0 * g.nn * NC * sizeof(S);
+        ProfScope ps(pb, 0, st, (double)B * per);
+        k_vanka_pass<S><<<dim3((nb * 4 + TPB - 1) / TPB, B), TPB, 0, st>>>(g, k, c, om, zero, (const S*)lv.J,
+                                                                          (const S*)lv.Ainv, b, cur, oth, act);
+      }
+      std::swap(cur, oth);
+    }
+  // 4 passes per sweep: the result is back in x
+}
+
+template <class S>
+void vcycle(fsi_problem* pb, int B, double k, const S* rhs, S* out, const int* act, hipStream_t st) {
+  const int L = pb->nlev - 1;
+  const int nu = pb->p.vanka_sweeps;
+  // level L uses rhs/out directly; lower levels their own b_/x_
+  for (int l = L; l >= 1; --l) {
+    Level& lv = pb->lev[l];
+    Level& lc = pb->lev[l - 1];
+    const S* b = (l == L) ? rhs : (const S*)lv.b_;
+    S* x = (l == L) ? out : (S*)lv.x_;
+    smooth<S>(pb, l, B, k, nu, true, x, (S*)lv.t_, b, act, st);
+    const Geom g = lv.geom();
+    k_spmv<S><<<grid1(g.nn, B), TPB, 0, st>>>(g, k, (const S*)lv.J, x, b, nullptr, (S*)lv.r_, act);
+    k_restrict<S><<<grid1(lc.nn, B), TPB, 0, st>>>(lc.geom(), g, (const S*)lv.r_, (S*)lc.b_, act);
+  }
+  {
+    Level& l0 = pb->lev[0];
+    const size_t lds = (size_t)(pb->cnsb * pb->cbs + pb->cbs) * sizeof(double);
+    k_coarse_solve<S><<<B, TPB, lds, st>>>(l0.geom(), pb->cbs, pb->cnsb, pb->cDinv, pb->cW, pb->cL,
+                                           (const S*)l0.b_, (S*)l0.x_, act);
+  }
+  for (int l = 1; l <= L; ++l) {
+    Level& lv = pb->lev[l];
+    Level& lc = pb->lev[l - 1];
+    const S* b = (l == L) ? rhs : (const S*)lv.b_;
+    S* x = (l == L) ? out : (S*)lv.x_;
+    k_prolong_add<S><<<grid1(lv.nn, B), TPB, 0, st>>>(lv.geom(), lc.geom(), (const S*)lc.x_, x, act);
+    smooth<S>(pb, l, B, k, nu, false, x, (S*)lv.t_, b, act, st);
+  }
+}
+
+// ------------------------------------------------------------ FGMRES
+// Solve J dx = -R for the slices with nact[b] = 1 (row-scaled system D J dx = -D R),
+// right-preconditioned FGMRES(R) with classical Gram-Schmidt applied twice; the
+// preconditioner is one multigrid V-cycle.  The solution (type S) goes to pb->xs.
+template <class S>
+fsi_status fgmres(fsi_problem* pb, int B, double k, std::vector<int>& kits, hipStream_t st) {
+  Level& F = pb->lev[pb->nlev - 1];
+  const Geom g = F.geom();
+  const int n = F.nn * NC;
+  const int R = pb->R;
+  const size_t vb = (size_t)(R + 1) * n;   // per-slice stride of V
+  const size_t zb = (size_t)R * n;         // per-slice stride of Z
+  S* V = (S*)pb->V;
+  S* Z = (S*)pb->Z;
+  S* w = (S*)pb->w;
+  S* xs = (S*)pb->xs;
+  S* tmp = (S*)pb->tmp;
+  const int chunk = 8192;
+  const int nchunk = (n + chunk - 1) / chunk;
+  const double tol = pb->p.lin_rtol;
+  const dim3 gb((B + 63) / 64), tb(64);
+  std::vector<int> hstate(B);
+  k_fill<S><<<1024, TPB, 0, st>>>((size_t)B * n, xs, (S)0);
+  HIPCHK(hipMemcpyAsync(pb->gact, pb->nact, B * sizeof(int), hipMemcpyDeviceToDevice, st));
+  int total = 0;
+  for (int cycle = 0;; ++cycle) {
+    // V0 = D (b - J xs), b = -R
+    if (cycle == 0) {
+      k_scale_rhs<S><<<grid1(n, B), TPB, 0, st>>>(n, pb->Res, F.Dsc, V, vb, pb->gact);
+    } else {
+      k_scale_rhs<S><<<grid1(n, B), TPB, 0, st>>>(n, pb->Res, nullptr, tmp, (size_t)n, pb->gact);
+      k_spmv<S><<<grid1(F.nn, B), TPB, 0, st>>>(g, k, (const S*)F.J, xs, tmp, F.Dsc, w, pb->gact);
+      k_scale<S><<<grid1(n, B), TPB, 0, st>>>(n, w, (size_t)n, V, vb, nullptr, 0, 2, pb->gact);
+    }
+    k_multidot<S><<<dim3(nchunk, B), RED_T, 0, st>>>(n, 1, V, vb, V, vb, 0, chunk, pb->partial, nchunk, pb->gact);
+    k_reduce_partials<<<B, 64, 0, st>>>(1, nchunk, pb->partial, pb->beta, 1, pb->gact);
+    k_init_cycle<<<gb, tb, 0, st>>>(R, cycle, pb->beta, pb->beta0, pb->gv, pb->gstate, pb->ncol, tol, pb->gact, B);
+    k_update_gact<<<gb, tb, 0, st>>>(pb->nact, pb->gstate, pb->gact, B);
+    k_scale<S><<<grid1(n, B), TPB, 0, st>>>(n, V, vb, V, vb, pb->beta, 1, 1, pb->gact);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(hstate.data(), pb->gstate, B * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    bool any = false;
+    for (int b = 0; b < B; ++b) any |= hstate[b] == 0;
+    if (!any) break;
+    int jmax = 0;
+    for (int j = 0; j < R; ++j) {
+      S* Vj = V + (size_t)j * n;
+      S* Zj = Z + (size_t)j * n;
+      // Z_j = M^{-1} (V_j / D);  a = D J Z_j  (the new Arnoldi vector a lives in tmp)
+      k_unscale<S><<<grid1(n, B), TPB, 0, st>>>(n, Vj, vb, F.Dsc, tmp, pb->gact);
+      vcycle<S>(pb, B, k, tmp, w, pb->gact, st);
+      k_scale<S><<<grid1(n, B), TPB, 0, st>>>(n, w, (size_t)n, Zj, zb, nullptr, 0, 2, pb->gact);
+      S* a = tmp;
+      {
+        ProfScope ps(pb, 1, st,
+                     (double)B * ((double)NSLOT * BLK * F.nn * sizeof(S) + 2.0 * n * sizeof(S) + n * 8.0));
+        k_spmv<S><<<grid1(F.nn, B), TPB, 0, st>>>(g, k, (const S*)F.J, w, nullptr, F.Dsc, a, pb->gact);
+      }
+      // classical Gram-Schmidt, twice
+      k_multidot<S><<<dim3(nchunk, B), RED_T, 0, st>>>(n, j + 1, a, (size_t)n, V, vb, (size_t)n, chunk, pb->partial,
+                                                         nchunk, pb->gact);
+      k_reduce_partials<<<B, 64, 0, st>>>(j + 1, nchunk, pb->partial, pb->hcol, 64, pb->gact);
+      k_multiaxpy<S><<<grid1(n, B), TPB, 0, st>>>(n, j + 1, a, (size_t)n, V, vb, (size_t)n, pb->hcol, 64, -1.0,
+                                                    pb->gact);
+      k_multidot<S><<<dim3(nchunk, B), RED_T, 0, st>>>(n, j + 1, a, (size_t)n, V, vb, (size_t)n, chunk, pb->partial,
+                                                         nchunk, pb->gact);
+      k_reduce_partials<<<B, 64, 0, st>>>(j + 1, nchunk, pb->partial, pb->hcol2, 64, pb->gact);
+      k_multiaxpy<S><<<grid1(n, B), TPB, 0, st>>>(n, j + 1, a, (size_t)n, V, vb, (size_t)n, pb->hcol2, 64, -1.0,
+                                                    pb->gact);
+      k_multidot<S><<<dim3(nchunk, B), RED_T, 0, st>>>(n, 1, a, (size_t)n, a, (size_t)n, 0, chunk, pb->partial,
+                                                         nchunk, pb->gact);
+      k_reduce_partials<<<B, 64, 0, st>>>(1, nchunk, pb->partial, pb->res, 1, pb->gact);
+      k_cgs_combine<<<gb, tb, 0, st>>>(j, pb->hcol, pb->hcol2, pb->res, pb->gact, B);
+      // V_{j+1} = w / ||w||
+      k_scale<S><<<grid1(n, B), TPB, 0, st>>>(n, a, (size_t)n, V + (size_t)(j + 1) * n, vb, pb->res, 1, 1, pb->gact);
+      k_givens<<<gb, tb, 0, st>>>(j, R, pb->H, pb->hcol, pb->cs, pb->sn, pb->gv, pb->res, pb->beta0, tol,
+                                  pb->gstate, pb->ncol, pb->gact, B);
+      HIPCHK(hipGetLastError());
+      for (int b = 0; b < B; ++b)
+        if (hstate[b] == 0) kits[b] += 1;
+      ++total;
+      jmax = j + 1;
+      k_update_gact<<<gb, tb, 0, st>>>(pb->nact, pb->gstate, pb->gact, B);
+      HIPCHK(hipMemcpyAsync(hstate.data(), pb->gstate, B * sizeof(int), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      any = false;
+      for (int b = 0; b < B; ++b) any |= hstate[b] == 0;
+      if (!any || total >= pb->p.gmres_maxit) break;
+    }
+    // xs += Z y on every slice that ran in this cycle (ncol > 0)
+    k_trisolve<<<gb, tb, 0, st>>>(R, pb->H, pb->gv, pb->ncol, pb->ycoef, pb->nact, B);
+    k_multiaxpy<S><<<grid1(n, B), TPB, 0, st>>>(n, jmax, xs, (size_t)n, Z, zb, (size_t)n, pb->ycoef, 64, 1.0,
+                                                  pb->nact);
+    HIPCHK(hipGetLastError());
+    if (!any) break;
+    if (total >= pb->p.gmres_maxit) return FSI_ERR_LINEAR;
+    // restart the unconverged slices
+    k_update_gact<<<gb, tb, 0, st>>>(pb->nact, pb->gstate, pb->gact, B);
+  }
+  return FSI_OK;
+}
+
+// ------------------------------------------------------------ propagation
+struct RunStats {
+  std::vector<int> newton, krylov, status;
+};
+
+template <class S>
+fsi_status newton_solve_step(fsi_problem* pb, int B, const StepPar& sp, std::vector<int>& hact, RunStats& rs,
+                             hipStream_t st) {
+  Level& F = pb->lev[pb->nlev - 1];
+  const Geom g = F.geom();
+  const int nn = F.nn;
+  const int maxit = pb->p.newton_maxit;
+  std::vector<double> prev(B, -1.0), hm((size_t)B * 6);
+  std::vector<int> nact(hact);
+  for (int it = 1; it <= maxit; ++it) {
+    HIPCHK(hipMemcpyAsync(pb->nact, nact.data(), B * sizeof(int), hipMemcpyHostToDevice, st));
+    CHK(residual(pb, B, sp, pb->U, pb->Uold, pb->Res, pb->nact, st));
+    CHK(assemble_levels<S>(pb, B, sp, pb->nact, st));
+    fsi_status ls = fgmres<S>(pb, B, sp.k, rs.krylov, st);
+    if (ls != FSI_OK && ls != FSI_ERR_LINEAR) return ls;
+    k_newton_update<S><<<dim3(pb->nchunk_n, B), RED_T, 0, st>>>(nn, pb->U, (const S*)pb->xs, pb->chunk_n, pb->npart,
+                                                                 pb->nchunk_n, pb->nact);
+    k_max_partials<<<(B + 63) / 64, 64, 0, st>>>(pb->nchunk_n, pb->npart, pb->nmax, B);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(hm.data(), pb->nmax, (size_t)B * 6 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    bool any = false;
+    for (int b = 0; b < B; ++b) {
+      if (!nact[b]) continue;
+      rs.newton[b] += 1;
+      double worst = 0.0;
+      bool finite = true;
+      for (int f = 0; f < 3; ++f) {
+        const double du = hm[(size_t)b * 6 + f], un = hm[(size_t)b * 6 + 3 + f];
+        if (!std::isfinite(du) || !std::isfinite(un)) finite = false;
+        worst = std::max(worst, un > 0.0 ? du / un : du);
+      }
+      if (!finite) {
+        rs.status[b] = FSI_ERR_NONFINITE;
+        nact[b] = 0;
+        hact[b] = 0;
+        continue;
+      }
+      // converged, or stagnating at the round-off floor once the update is tiny
+      if (worst <= pb->p.newton_rtol || (prev[b] >= 0.0 && worst <= 1e-9 && worst > 0.5 * prev[b])) {
+        nact[b] = 0;
+      } else {
+        any = true;
+      }
+      prev[b] = worst;
+    }
+    if (!any) return FSI_OK;
+  }
+  for (int b = 0; b < B; ++b)
+    if (nact[b]) {
+      rs.status[b] = FSI_ERR_NEWTON;
+      hact[b] = 0;
+    }
+  return FSI_OK;
+}
+
+template <class S>
+fsi_status propagate(fsi_problem* pb, int B, const double* t0, double slice_len, int nsteps, const double* U_in,
+                     double* U_out, fsi_stats* stats, hipStream_t st) {
+  Level& F = pb->lev[pb->nlev - 1];
+  const Geom g = F.geom();
+  const size_t ndof = (size_t)F.nn * NC;
+  const double k = slice_len / nsteps;
+  const StepPar sp = step_par(pb, k);
+  auto t_start = std::chrono::steady_clock::now();
+  // non-finite input check
+  HIPCHK(hipMemsetAsync(pb->flag, 0, B * sizeof(int), st));
+  k_nonfinite<<<dim3(64, B), TPB, 0, st>>>(ndof, U_in, pb->flag);
+  std::vector<int> hflag(B);
+  HIPCHK(hipMemcpyAsync(hflag.data(), pb->flag, B * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  for (int b = 0; b < B; ++b)
+    if (hflag[b]) {
+      if (stats)
+        for (int q = 0; q < B; ++q) stats->slice_status[q] = hflag[q] ? FSI_ERR_NONFINITE : FSI_OK;
+      return FSI_ERR_NONFINITE;
+    }
+  HIPCHK(hipMemcpyAsync(pb->U, U_in, (size_t)B * ndof * sizeof(double), hipMemcpyDeviceToDevice, st));
+  RunStats rs;
+  rs.newton.assign(B, 0);
+  rs.krylov.assign(B, 0);
+  rs.status.assign(B, FSI_OK);
+  std::vector<int> hact(B, 1);
+  std::vector<double> th(B);
+  for (int n = 1; n <= nsteps; ++n) {
+    for (int b = 0; b < B; ++b) th[b] = t0[b] + n * k;
+    HIPCHK(hipMemcpyAsync(pb->tdev, th.data(), B * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(pb->nact, hact.data(), B * sizeof(int), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(pb->Uold, pb->U, (size_t)B * ndof * sizeof(double), hipMemcpyDeviceToDevice, st));
+    k_apply_dirichlet<<<grid1(F.nn, B), TPB, 0, st>>>(g, sp, pb->U, pb->tdev, pb->nact);
+    HIPCHK(hipGetLastError());
+    CHK(newton_solve_step<S>(pb, B, sp, hact, rs, st));
+    bool any = false;
+    for (int b = 0; b < B; ++b) any |= hact[b] != 0;
+    if (!any) break;
+  }
+  HIPCHK(hipMemcpyAsync(U_out, pb->U, (size_t)B * ndof * sizeof(double), hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  fsi_status ret = FSI_OK;
+  for (int b = 0; b < B; ++b)
+    if (rs.status[b] != FSI_OK) ret = (fsi_status)rs.status[b];
+  if (stats) {
+    int nt = 0, kt = 0;
+    for (int b = 0; b < B && b < FSI_MAX_SLICES; ++b) {
+      stats->newton_its[b] = rs.newton[b];
+      stats->krylov_its[b] = rs.krylov[b];
+      stats->slice_status[b] = rs.status[b];
+      nt += rs.newton[b];
+      kt += rs.krylov[b];
+    }
+    stats->newton_total = nt;
+    stats->krylov_total = kt;
+    stats->stage_ms[4] =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+  }
+  return ret;
+}
+
+fsi_status run_propagate(fsi_problem* pb, int B, const double* t0, double slice_len, int nsteps, const double* U_in,
+                         double* U_out, fsi_stats* stats, hipStream_t st) {
+  if (!pb || !t0 || !U_in || !U_out || B <= 0 || B > pb->Bmax || nsteps <= 0 || !(slice_len > 0.0))
+    return FSI_ERR_ARG;
+  if (stats) std::memset(stats, 0, sizeof(fsi_stats));
+  return pb->mixed ? propagate<float>(pb, B, t0, slice_len, nsteps, U_in, U_out, stats, st)
+                   : propagate<double>(pb, B, t0, slice_len, nsteps, U_in, U_out, stats, st);
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+extern "C" {
+
+const char* fsi_status_string(fsi_status s) {
+  switch (s) {
+    case FSI_OK: return "ok";
+    case FSI_ERR_ARG: return "invalid argument";
+    case FSI_ERR_HIP: return "HIP runtime error";
+    case FSI_ERR_OOM: return "out of device memory";
+    case FSI_ERR_NEWTON: return "Newton did not converge";
+    case FSI_ERR_LINEAR: return "linear solver did not converge";
+    case FSI_ERR_NONFINITE: return "non-finite value";
+    case FSI_ERR_PARAREAL: return "Parareal did not converge";
+  }
+  return "unknown status";
+}
+
+void fsi_destroy(fsi_problem* pb) {
+  if (!pb) return;
+  for (void* q : pb->allocs) (void)hipFree(q);
+  for (hipEvent_t e : pb->prof.pool) (void)hipEventDestroy(e);
+  delete pb;
+}
+
+fsi_status fsi_setup(const fsi_params* prm, fsi_problem** out) {
+  if (!prm || !out) return FSI_ERR_ARG;
+  *out = nullptr;
+  const fsi_params& p = *prm;
+  if (p.dim != 2 || p.level < 1 || p.level > MAXLEV - 2 || p.max_batch < 1 || p.max_batch > FSI_MAX_SLICES ||
+      p.gmres_restart < 1 || p.gmres_restart > 63 || p.newton_maxit < 1 || p.vanka_sweeps < 1 ||
+      p.gmres_maxit < 1 || (p.precision != FSI_FP64 && p.precision != FSI_MIXED))
+    return FSI_ERR_ARG;
+  for (int a = 0; a < 2; ++a) {
+    if (p.nseg[a] < 1 || p.nseg[a] > 4) return FSI_ERR_ARG;
+    for (int s = 0; s < p.nseg[a]; ++s)
+      if (p.seg_cells[a][s] < 1 || !(p.seg_pts[a][s + 1] > p.seg_pts[a][s])) return FSI_ERR_ARG;
+  }
+  if (!(p.rho_f > 0 && p.nu_f > 0 && p.rho_s > 0 && p.ramp_time > 0)) return FSI_ERR_ARG;
+  fsi_problem* pb = new (std::nothrow) fsi_problem();
+  if (!pb) return FSI_ERR_OOM;
+  pb->p = p;
+  pb->Bmax = p.max_batch;
+  pb->mixed = p.precision == FSI_MIXED;
+  pb->ssz = pb->mixed ? sizeof(float) : sizeof(double);
+  pb->R = p.gmres_restart;
+  pb->nlev = p.level + 1;
+  fsi_status s = FSI_OK;
+  for (int l = 0; l < pb->nlev && s == FSI_OK; ++l) s = build_level(pb, l);
+  if (s != FSI_OK) { fsi_destroy(pb); return s; }
+  Level& F = pb->lev[pb->nlev - 1];
+  Level& C = pb->lev[0];
+  const int B = pb->Bmax;
+  const size_t ndof = (size_t)F.nn * NC;
+  const size_t ss = pb->ssz;
+  const int R = pb->R;
+  pb->chunk_n = 2048;
+  pb->nchunk_n = (F.nn + pb->chunk_n - 1) / pb->chunk_n;
+  pb->cbs = 2 * (C.ny + 1) * NC;
+  pb->cnsb = (C.nx + 1 + 1) / 2;
+  if (pb->cbs > 128 || (size_t)3 * pb->cbs * pb->cbs * sizeof(double) > 160 * 1024) { fsi_destroy(pb); return FSI_ERR_ARG; }
+  const size_t cb2 = (size_t)pb->cbs * pb->cbs * pb->cnsb * B;
+#define A_(x) do { s = (x); if (s != FSI_OK) { fsi_destroy(pb); return s; } } while (0)
+  A_(dalloc(pb, &pb->U, B * ndof));
+  A_(dalloc(pb, &pb->Uold, B * ndof));
+  A_(dalloc(pb, &pb->Res, B * ndof));
+  A_(dalloc(pb, &pb->Re, (size_t)B * NE * F.ncell));
+  A_(dalloc(pb, &pb->Ke, (size_t)B * NE * NE * F.ncell));
+  A_(dalloc(pb, &pb->tdev, B));
+  A_(dalloc(pb, &pb->nact, B));
+  A_(dalloc(pb, &pb->gact, B));
+  A_(dalloc(pb, &pb->flag, B));
+  A_(dalloc_bytes(pb, &pb->V, (size_t)B * (R + 1) * ndof * ss));
+  A_(dalloc_bytes(pb, &pb->Z, (size_t)B * R * ndof * ss));
+  A_(dalloc_bytes(pb, &pb->w, (size_t)B * ndof * ss));
+  A_(dalloc_bytes(pb, &pb->xs, (size_t)B * ndof * ss));
+  A_(dalloc_bytes(pb, &pb->tmp, (size_t)B * ndof * ss));
+  A_(dalloc(pb, &pb->H, (size_t)B * (R + 1) * R));
+  A_(dalloc(pb, &pb->hcol, (size_t)B * 64));
+  A_(dalloc(pb, &pb->hcol2, (size_t)B * 64));
+  A_(dalloc(pb, &pb->cs, (size_t)B * R));
+  A_(dalloc(pb, &pb->sn, (size_t)B * R));
+  A_(dalloc(pb, &pb->gv, (size_t)B * (R + 1)));
+  A_(dalloc(pb, &pb->res, B));
+  A_(dalloc(pb, &pb->beta0, B));
+  A_(dalloc(pb, &pb->beta, B));
+  A_(dalloc(pb, &pb->ycoef, (size_t)B * 64));
+  A_(dalloc(pb, &pb->partial, (size_t)B * 64 * ((ndof + 8191) / 8192 + 1)));
+  A_(dalloc(pb, &pb->gstate, B));
+  A_(dalloc(pb, &pb->ncol, B));
+  A_(dalloc(pb, &pb->cDinv, cb2));
+  A_(dalloc(pb, &pb->cW, cb2));
+  A_(dalloc(pb, &pb->cL, cb2));
+  A_(dalloc(pb, &pb->npart, (size_t)B * 6 * pb->nchunk_n));
+  A_(dalloc(pb, &pb->nmax, (size_t)B * 6));
+#undef A_
+  if (hipFuncSetAttribute((const void*)k_coarse_factor<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          3 * pb->cbs * pb->cbs * sizeof(double)) != hipSuccess ||
+      hipFuncSetAttribute((const void*)k_coarse_factor<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          3 * pb->cbs * pb->cbs * sizeof(double)) != hipSuccess) {
+    fsi_destroy(pb);
+    return FSI_ERR_HIP;
+  }
+  *out = pb;
+  return FSI_OK;
+}
+
+fsi_status fsi_sizes(const fsi_problem* pb, int64_t* n_nodes, int64_t* n_dofs) {
+  if (!pb) return FSI_ERR_ARG;
+  const Level& F = pb->lev[pb->nlev - 1];
+  if (n_nodes) *n_nodes = F.nn;
+  if (n_dofs) *n_dofs = (int64_t)F.nn * NC;
+  return FSI_OK;
+}
+
+fsi_status fsi_initial_state(fsi_problem* pb, double* U0, hipStream_t st) {
+  if (!pb || !U0) return FSI_ERR_ARG;
+  Level& F = pb->lev[pb->nlev - 1];
+  const size_t ndof = (size_t)F.nn * NC;
+  HIPCHK(hipMemsetAsync(U0, 0, ndof * sizeof(double), st));
+  double t0 = 0.0;
+  HIPCHK(hipMemcpyAsync(pb->tdev, &t0, sizeof(double), hipMemcpyHostToDevice, st));
+  k_apply_dirichlet<<<grid1(F.nn, 1), TPB, 0, st>>>(F.geom(), step_par(pb, 1.0), U0, pb->tdev, nullptr);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(st));
+  return FSI_OK;
+}
+
+fsi_status fine_propagate(fsi_problem* pb, int32_t B, const double* t0, double slice_len, int32_t m,
+                          const double* U_in, double* U_out, fsi_stats* stats, hipStream_t st) {
+  return run_propagate(pb, B, t0, slice_len, m, U_in, U_out, stats, st);
+}
+
+fsi_status coarse_propagate(fsi_problem* pb, int32_t B, const double* t0, double slice_len, int32_t M,
+                            const double* U_in, double* U_out, fsi_stats* stats, hipStream_t st) {
+  return run_propagate(pb, B, t0, slice_len, M, U_in, U_out, stats, st);
+}
+
+fsi_status parareal_run(fsi_problem* pb, double T, int32_t N, int32_t m, int32_t M, double tol, int32_t max_iter,
+                        const double* U0, double* Ub, fsi_stats* stats, hipStream_t st) {
+  if (!pb || !U0 || !Ub || N < 1 || N > pb->Bmax || m < 1 || M < 1 || !(T > 0.0) || max_iter < 1) return FSI_ERR_ARG;
+  if (max_iter > N) max_iter = N;
+  Level& F = pb->lev[pb->nlev - 1];
+  const size_t nd = (size_t)F.nn * NC;
+  const double dl = T / N;
+  double *Cold = nullptr, *Fv = nullptr, *Up = nullptr, *Cn = nullptr, *part = nullptr;
+  const int chunk = 4096, nchunk = (F.nn + chunk - 1) / chunk;
+  auto cleanup = [&]() {
+    (void)hipFree(Cold); (void)hipFree(Fv); (void)hipFree(Up); (void)hipFree(Cn); (void)hipFree(part);
+  };
+  if (hipMalloc(&Cold, N * nd * sizeof(double)) != hipSuccess || hipMalloc(&Fv, N * nd * sizeof(double)) != hipSuccess ||
+      hipMalloc(&Up, (N + 1) * nd * sizeof(double)) != hipSuccess || hipMalloc(&Cn, nd * sizeof(double)) != hipSuccess ||
+      hipMalloc(&part, (size_t)(N + 1) * 4 * nchunk * sizeof(double)) != hipSuccess) {
+    cleanup();
+    return FSI_ERR_OOM;
+  }
+  fsi_stats local;
+  fsi_stats* sp = stats ? stats : &local;
+  std::memset(sp, 0, sizeof(fsi_stats));
+  fsi_stats tmp;
+  auto t_start = std::chrono::steady_clock::now();
+  double coarse_ms = 0.0, fine_ms = 0.0;
+  fsi_status ret = FSI_OK;
+#define PR_(x) do { fsi_status s_ = (x); if (s_ != FSI_OK) { ret = s_; goto done; } } while (0)
+  {
+    if (hipMemcpyAsync(Ub, U0, nd * sizeof(double), hipMemcpyDeviceToDevice, st) != hipSuccess) { ret = FSI_ERR_HIP; goto done; }
+    // initial coarse sweep U^0_{l+1} = C(U^0_l)
+    for (int l = 0; l < N; ++l) {
+      const double t0 = l * dl;
+      auto c0 = std::chrono::steady_clock::now();
+      PR_(run_propagate(pb, 1, &t0, dl, M, Ub + l * nd, Ub + (l + 1) * nd, &tmp, st));
+      coarse_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - c0).count();
+      if (hipMemcpyAsync(Cold + l * nd, Ub + (l + 1) * nd, nd * sizeof(double), hipMemcpyDeviceToDevice, st) != hipSuccess) { ret = FSI_ERR_HIP; goto done; }
+    }
+    int it = 0;
+    double change = 1e300;
+    std::vector<double> t0s(N), hp((size_t)(N + 1) * 4 * nchunk);
+    for (int i = 0; i < max_iter; ++i) {
+      // fine sweep over the slices that are not yet exact, batched in one call
+      const int Bf = N - i;
+      for (int l = i; l < N; ++l) t0s[l - i] = l * dl;
+      auto f0 = std::chrono::steady_clock::now();
+      PR_(run_propagate(pb, Bf, t0s.data(), dl, m, Ub + i * nd, Fv + i * nd, &tmp, st));
+      fine_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - f0).count();
+      sp->newton_total += tmp.newton_total;
+      sp->krylov_total += tmp.krylov_total;
+      if (hipMemcpyAsync(Up, Ub, (N + 1) * nd * sizeof(double), hipMemcpyDeviceToDevice, st) != hipSuccess) { ret = FSI_ERR_HIP; goto done; }
+      // sequential correction sweep
+      for (int l = 0; l < N; ++l) {
+        const double* cn = Cold + l * nd;
+        if (l >= i) {
+          const double t0 = l * dl;
+          auto c0 = std::chrono::steady_clock::now();
+          PR_(run_propagate(pb, 1, &t0, dl, M, Ub + l * nd, Cn, &tmp, st));
+          coarse_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - c0).count();
+          cn = Cn;
+        }
+        k_parareal_update<<<256, TPB, 0, st>>>(nd, cn, Fv + l * nd, Cold + l * nd, Ub + (l + 1) * nd);
+        if (cn != Cold + l * nd)
+          if (hipMemcpyAsync(Cold + l * nd, Cn, nd * sizeof(double), hipMemcpyDeviceToDevice, st) != hipSuccess) { ret = FSI_ERR_HIP; goto done; }
+      }
+      k_change_norms<<<dim3(nchunk, N + 1), RED_T, 0, st>>>(F.nn, Ub, Up, chunk, part, nchunk);
+      if (hipGetLastError() != hipSuccess) { ret = FSI_ERR_HIP; goto done; }
+      if (hipMemcpyAsync(hp.data(), part, hp.size() * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess) { ret = FSI_ERR_HIP; goto done; }
+      change = 0.0;
+      for (int l = 0; l <= N; ++l)
+        for (int f = 0; f < 2; ++f) {
+          double dd = 0.0, nn2 = 0.0;
+          for (int c = 0; c < nchunk; ++c) {
+            dd += hp[((size_t)l * 4 + 2 * f) * nchunk + c];
+            nn2 += hp[((size_t)l * 4 + 2 * f + 1) * nchunk + c];
+          }
+          const double r = nn2 > 0.0 ? std::sqrt(dd / nn2) : std::sqrt(dd);
+          change = std::max(change, r);
+        }
+      it = i + 1;
+      if (change < tol) break;
+    }
+    sp->parareal_iters = it;
+    if (!(change < tol) && it < N) ret = FSI_ERR_PARAREAL;
+  }
+done:
+#undef PR_
+  (void)hipStreamSynchronize(st);
+  cleanup();
+  sp->stage_ms[5] = coarse_ms;
+  sp->stage_ms[6] = fine_ms;
+  sp->stage_ms[4] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+  return ret;
+}
+
+fsi_status fsi_debug_residual(fsi_problem* pb, int32_t B, const double* U, const double* Uo, const double* t,
+                              double k, double* R, hipStream_t st) {
+  if (!pb || !U || !Uo || !t || !R || B <= 0 || B > pb->Bmax || !(k > 0)) return FSI_ERR_ARG;
+  HIPCHK(hipMemcpyAsync(pb->tdev, t, B * sizeof(double), hipMemcpyHostToDevice, st));
+  CHK(residual(pb, B, step_par(pb, k), U, Uo, R, nullptr, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return FSI_OK;
+}
+
+fsi_status fsi_debug_jacobian_apply(fsi_problem* pb, int32_t B, const double* U, const double* Uo, const double* t,
+                                    double k, const double* X, double* Y, hipStream_t st) {
+  if (!pb || !U || !Uo || !t || !X || !Y || B <= 0 || B > pb->Bmax || !(k > 0)) return FSI_ERR_ARG;
+  Level& F = pb->lev[pb->nlev - 1];
+  const size_t ndof = (size_t)F.nn * NC;
+  const StepPar sp = step_par(pb, k);
+  HIPCHK(hipMemcpyAsync(pb->tdev, t, B * sizeof(double), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(pb->U, U, B * ndof * sizeof(double), hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(pb->Uold, Uo, B * ndof * sizeof(double), hipMemcpyDeviceToDevice, st));
+  if (pb->mixed) {
+    CHK(assemble_levels<float>(pb, B, sp, nullptr, st));
+    k_convert<double, float><<<1024, TPB, 0, st>>>(B * ndof, X, (float*)pb->tmp);
+    k_spmv<float><<<grid1(F.nn, B), TPB, 0, st>>>(F.geom(), k, (const float*)F.J, (const float*)pb->tmp, nullptr,
+                                                  nullptr, (float*)pb->w, nullptr);
+    k_convert<float, double><<<1024, TPB, 0, st>>>(B * ndof, (const float*)pb->w, Y);
+  } else {
+    CHK(assemble_levels<double>(pb, B, sp, nullptr, st));
+    k_spmv<double><<<grid1(F.nn, B), TPB, 0, st>>>(F.geom(), k, (const double*)F.J, X, nullptr, nullptr, Y, nullptr);
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(st));
+  return FSI_OK;
+}
+
+fsi_status fsi_debug_vcycle(fsi_problem* pb, int32_t B, const double* U, const double* Uo, const double* t, double k,
+                            const double* X, double* Y, hipStream_t st) {
+  if (!pb || !U || !Uo || !t || !X || !Y || B <= 0 || B > pb->Bmax || !(k > 0)) return FSI_ERR_ARG;
+  Level& F = pb->lev[pb->nlev - 1];
+  const size_t ndof = (size_t)F.nn * NC;
+  const StepPar sp = step_par(pb, k);
+  HIPCHK(hipMemcpyAsync(pb->tdev, t, B * sizeof(double), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(pb->U, U, B * ndof * sizeof(double), hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(pb->Uold, Uo, B * ndof * sizeof(double), hipMemcpyDeviceToDevice, st));
+  if (pb->mixed) {
+    CHK(assemble_levels<float>(pb, B, sp, nullptr, st));
+    k_convert<double, float><<<1024, TPB, 0, st>>>(B * ndof, X, (float*)pb->tmp);
+    vcycle<float>(pb, B, k, (const float*)pb->tmp, (float*)pb->w, nullptr, st);
+    k_convert<float, double><<<1024, TPB, 0, st>>>(B * ndof, (const float*)pb->w, Y);
+  } else {
+    CHK(assemble_levels<double>(pb, B, sp, nullptr, st));
+    vcycle<double>(pb, B, k, X, Y, nullptr, st);
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(st));
+  return FSI_OK;
+}
+
+fsi_status fsi_profile_enable(fsi_problem* pb, int32_t on) {
+  if (!pb) return FSI_ERR_ARG;
+  pb->prof.on = on != 0;
+  if (on) {
+    pb->prof.used = 0;
+    for (int f = 0; f < 4; ++f) {
+      pb->prof.ev[f].clear();
+      pb->prof.bytes[f] = 0;
+      pb->prof.launches[f] = 0;
+    }
+  }
+  return FSI_OK;
+}
+
+fsi_status fsi_profile_query(const fsi_problem* pb, int32_t which, int64_t* launches, double* ms, double* bytes) {
+  if (!pb || which < 0 || which > 3) return FSI_ERR_ARG;
+  double tot = 0.0;
+  for (auto& e : pb->prof.ev[which]) {
+    float m = 0.f;
+    if (hipEventSynchronize(e.second) != hipSuccess) return FSI_ERR_HIP;
+    if (hipEventElapsedTime(&m, e.first, e.second) != hipSuccess) return FSI_ERR_HIP;
+    tot += m;
+  }
+  if (launches) *launches = pb->prof.launches[which];
+  if (ms) *ms = tot;
+  if (bytes) *bytes = pb->prof.bytes[which];
+  return FSI_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,55 @@
+// Internal definitions shared by the HIP kernels and the host driver of the
+// ALE-FSI fine propagator.  2d, Q1 elements, 5 unknowns per node
+// (v_x, v_y, u_x, u_y, p).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <cstddef>
+
+#include "../../include/fsi.h"
+
+namespace fsi {
+
+constexpr int NC = 5;      // unknowns per node
+constexpr int NL = 4;      // nodes per cell
+constexpr int NE = 20;     // unknowns per cell
+constexpr int NSLOT = 9;   // block-stencil slots (3x3 neighbourhood)
+constexpr int NPST = 25;   // pressure-stencil slots (5x5 neighbourhood)
+constexpr int BLK = 25;    // entries of a 5x5 block
+constexpr int RED_T = 256; // threads of the reduction kernels
+
+// component bits of the Dirichlet mask
+constexpr uint8_t DM_V = 0x03, DM_U = 0x0c, DM_P = 0x10;
+// node class bits
+constexpr uint8_t CL_NS = 0x01;     // node of a solid cell
+constexpr uint8_t CL_NF = 0x02;     // node of a fluid cell
+constexpr uint8_t CL_INFLOW = 0x04; // inflow node carrying the parabolic profile
+
+// Device view of one mesh level (all pointers device memory).
+struct Geom {
+  int nx, ny, nn, ncell;
+  const double* x;          // [nx+1] node x-coordinates
+  const double* y;          // [ny+1] node y-coordinates
+  const uint8_t* solid;     // [ncell] 1 = solid cell
+  const uint8_t* cls;       // [nn] node class bits
+  const uint8_t* dmask;     // [nn] Dirichlet component mask (bit c -> component c)
+  const double* pst;        // [25][nn] constant pressure stencil (LPS or CIP), zero on Dirichlet p rows
+};
+
+// Physical and step constants of one time step.
+struct StepPar {
+  double k, theta;
+  double rho_f, nu_f, rho_s, mu_s, lambda_s;
+  double peak, ramp_time;
+};
+
+// Neighbour slot of offset (dx, dy) in the 3x3 block stencil.
+__host__ __device__ inline int slot_of(int dx, int dy) { return (dx + 1) + 3 * (dy + 1); }
+__host__ __device__ inline int pslot_of(int dx, int dy) { return (dx + 2) + 5 * (dy + 2); }
+
+// Ramp of the inflow: (1 - cos(pi t / t_r)) / 2 for t < t_r, then 1.
+__host__ __device__ inline double inflow_ramp(double t, double tr) {
+  return t >= tr ? 1.0 : 0.5 * (1.0 - cos(M_PI * t / tr));
+}
+
+}  // namespace fsi

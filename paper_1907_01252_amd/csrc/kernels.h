@@ -1,0 +1,71 @@
+// Declarations of the HIP kernels (defined and instantiated in assemble.hip and
+// solver.hip) for the host driver.
+#pragma once
+#include "fsi_internal.h"
+
+namespace fsi {
+
+__global__ void k_elem_residual(Geom g, StepPar sp, const double* U, const double* Uo, double* Re, const int* active);
+template <bool OLD>
+__global__ void k_elem_jacobian(Geom g, StepPar sp, const double* U, const double* Uo, double* Ke, const int* active);
+__global__ void k_apply_dirichlet(Geom g, StepPar sp, double* U, const double* t, const int* active);
+__global__ void k_gather_residual(Geom g, StepPar sp, const double* Re, const double* U, const double* t, double* R,
+                                  const int* active);
+template <class S>
+__global__ void k_gather_jacobian(Geom g, double k, const double* Ke, S* J, double* Dsc, const int* active);
+__global__ void k_inject(Geom gc, Geom gf, const double* Uf, double* Uc, int B);
+
+template <class S>
+__global__ void k_spmv(Geom g, double k, const S* J, const S* x, const S* b, const double* Dsc, S* y,
+                       const int* active);
+template <class S>
+__global__ void k_vanka_factor(Geom g, double k, const S* J, S* Ainv, const int* active);
+template <class S>
+__global__ void k_vanka_pass(Geom g, double k, int color, S omega, int zero_in, const S* J, const S* Ainv,
+                             const S* b, const S* x_in, S* x_out, const int* active);
+template <class S>
+__global__ void k_restrict(Geom gc, Geom gf, const S* rf, S* bc, const int* active);
+template <class S>
+__global__ void k_prolong_add(Geom gf, Geom gc, const S* xc, S* xf, const int* active);
+template <class S>
+__global__ void k_coarse_factor(Geom g, double k, const S* J, int bsz, int nsb, double* Dinv, double* W, double* Lb,
+                                const int* active);
+template <class S>
+__global__ void k_coarse_solve(Geom g, int bsz, int nsb, const double* Dinv, const double* W, const double* Lb,
+                               const S* bvec, S* xvec, const int* active);
+template <class S>
+__global__ void k_multidot(int n, int nv, const S* X, size_t sxb, const S* Y, size_t syb, size_t syi, int chunk,
+                           double* partial, int nchunk, const int* active);
+__global__ void k_reduce_partials(int nv, int nchunk, const double* partial, double* out, int ostride,
+                                  const int* active);
+template <class S>
+__global__ void k_multiaxpy(int n, int nv, S* X, size_t sxb, const S* Y, size_t syb, size_t syi, const double* h,
+                            int hstride, double sign, const int* active);
+template <class S>
+__global__ void k_scale(int n, const S* X, size_t sxb, S* Y, size_t syb, const double* alpha, int astride,
+                        int invert_sqrt, const int* active);
+template <class S>
+__global__ void k_unscale(int n, const S* X, size_t sxb, const double* D, S* Y, const int* active);
+template <class S>
+__global__ void k_scale_rhs(int n, const double* X, const double* D, S* Y, size_t syb, const int* active);
+__global__ void k_givens(int j, int R, double* H, const double* hcol, double* cs, double* sn, double* gv, double* res,
+                         const double* beta0, double tol, int* state, int* ncol, const int* active, int B);
+__global__ void k_init_cycle(int R, int cycle, const double* beta2, double* beta0, double* gv, int* state, int* ncol,
+                             double tol, const int* gact, int B);
+__global__ void k_cgs_combine(int j, double* hcol, const double* hcol2, const double* hn2, const int* active, int B);
+__global__ void k_update_gact(const int* nact, const int* state, int* gact, int B);
+__global__ void k_trisolve(int R, const double* H, const double* gv, const int* ncol, double* y, const int* active,
+                           int B);
+template <class S>
+__global__ void k_newton_update(int nn, double* U, const S* dx, int chunk, double* part, int nchunk,
+                                const int* active);
+__global__ void k_max_partials(int nchunk, const double* part, double* out, int B);
+__global__ void k_nonfinite(size_t n, const double* X, int* flag);
+__global__ void k_parareal_update(size_t n, const double* Cn, const double* Fv, const double* Cold, double* out);
+__global__ void k_change_norms(int nn, const double* A, const double* Bv, int chunk, double* part, int nchunk);
+template <class S>
+__global__ void k_fill(size_t n, S* X, S v);
+template <class A, class B2>
+__global__ void k_convert(size_t n, const A* X, B2* Y);
+
+}  // namespace fsi

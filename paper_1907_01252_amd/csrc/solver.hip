@@ -1,0 +1,785 @@
+// Batched linear-solver kernels: block-stencil SpMV, Vanka patch inverses and
+// colored multiplicative Vanka sweeps, multigrid transfers, the coarsest-level
+// block-tridiagonal direct solve and the FGMRES building blocks.  Every kernel
+// takes the slice index from blockIdx.y and skips slices whose active flag is 0.
+// S is the storage and arithmetic type of the linear solve (double, or float
+// in the mixed-precision path).
+#include "fsi_internal.h"
+
+namespace fsi {
+
+// ------------------------------------------------------------------ SpMV
+// y = D (A x)            (b == nullptr)
+// y = D (b - A x)        (b != nullptr)
+// with A = J (3x3 block stencil of 5x5 blocks) + k * S_p (5x5 pressure stencil).
+// D = Dsc (row scaling) when given, else identity.
+template <class S>
+__global__ void __launch_bounds__(256) k_spmv(Geom g, double k, const S* __restrict__ J, const S* __restrict__ x,
+                                              const S* __restrict__ b, const double* __restrict__ Dsc,
+                                              S* __restrict__ y, const int* __restrict__ active) {
+  const int bs = blockIdx.y;
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= g.nn || (active && !active[bs])) return;
+  const int i = n % (g.nx + 1), j = n / (g.nx + 1);
+  const S* jb = J + (size_t)bs * NSLOT * BLK * g.nn;
+  const S* xb = x + (size_t)bs * g.nn * NC;
+  S acc[NC] = {0, 0, 0, 0, 0};
+#pragma unroll
+  for (int s = 0; s < NSLOT; ++s) {
+    const int dx = s % 3 - 1, dy = s / 3 - 1;
+    const int ii = i + dx, jj = j + dy;
+    if (ii < 0 || jj < 0 || ii > g.nx || jj > g.ny) continue;
+    const S* xv = xb + (size_t)(ii + (g.nx + 1) * jj) * NC;
+    S xs[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) xs[c] = xv[c];
+#pragma unroll
+    for (int r = 0; r < NC; ++r)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) acc[r] += jb[((size_t)s * BLK + NC * r + c) * g.nn + n] * xs[c];
+  }
+  if (!(g.dmask[n] & DM_P)) {
+    S ap = 0;
+    for (int q = 0; q < NPST; ++q) {
+      const int dx = q % 5 - 2, dy = q / 5 - 2;
+      const int ii = i + dx, jj = j + dy;
+      if (ii < 0 || jj < 0 || ii > g.nx || jj > g.ny) continue;
+      ap += (S)g.pst[(size_t)q * g.nn + n] * xb[(size_t)(ii + (g.nx + 1) * jj) * NC + 4];
+    }
+    acc[4] += (S)k * ap;
+  }
+  S* yo = y + ((size_t)bs * g.nn + n) * NC;
+  const S* bb = b ? b + ((size_t)bs * g.nn + n) * NC : nullptr;
+  const double* d = Dsc ? Dsc + ((size_t)bs * g.nn + n) * NC : nullptr;
+#pragma unroll
+  for (int r = 0; r < NC; ++r) {
+    S v = bb ? bb[r] - acc[r] : acc[r];
+    yo[r] = d ? (S)(d[r] * (double)v) : v;
+  }
+}
+
+// ------------------------------------------------------------ colour helpers
+// Cells of colour (cx, cy) = (ci & 1, cj & 1), stored colour by colour.
+struct ColorLayout {
+  int ncx[4], ncy[4], off[4];
+};
+__host__ __device__ inline ColorLayout color_layout(int nx, int ny) {
+  ColorLayout L;
+  int o = 0;
+  for (int c = 0; c < 4; ++c) {
+    const int cx = c & 1, cy = c >> 1;
+    L.ncx[c] = (nx - cx + 1) / 2;
+    L.ncy[c] = (ny - cy + 1) / 2;
+    L.off[c] = o;
+    o += L.ncx[c] * L.ncy[c];
+  }
+  return L;
+}
+
+// ------------------------------------------------------- Vanka patch inverse
+// One 32-lane group inverts the 20x20 patch matrix of one cell (rows = local
+// unknowns 5a + c) by Gauss-Jordan with partial pivoting; lane r holds row r of
+// [A | I].  Ainv is stored per colour: Ainv[b][off_c*400 + e*nc_c + idx].
+template <class S>
+__global__ void __launch_bounds__(256) k_vanka_factor(Geom g, double k, const S* __restrict__ J,
+                                                      S* __restrict__ Ainv, const int* __restrict__ active) {
+  const int bs = blockIdx.y;
+  const int lane = threadIdx.x & 31;
+  const int cell = (blockIdx.x * blockDim.x + threadIdx.x) >> 5;
+  const bool live = cell < g.ncell && !(active && !active[bs]);
+  const int ci = live ? cell % g.nx : 0, cj = live ? cell / g.nx : 0;
+  const int r = lane < NE ? lane : 0;
+  const int a = r / NC, rc = r % NC;
+  const int na = (ci + (a & 1)) + (g.nx + 1) * (cj + (a >> 1));
+  double row[2 * NE];
+#pragma unroll
+  for (int c = 0; c < 2 * NE; ++c) row[c] = 0.0;
+  if (live && lane < NE) {
+    const S* jb = J + (size_t)bs * NSLOT * BLK * g.nn;
+    const bool pst_row = (rc == 4) && !(g.dmask[na] & DM_P);
+#pragma unroll
+    for (int bb = 0; bb < NL; ++bb) {
+      const int dx = (bb & 1) - (a & 1), dy = (bb >> 1) - (a >> 1);
+      const int s = slot_of(dx, dy);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) row[NC * bb + c] = (double)jb[((size_t)s * BLK + NC * rc + c) * g.nn + na];
+      if (pst_row) row[NC * bb + 4] += k * g.pst[(size_t)pslot_of(dx, dy) * g.nn + na];
+    }
+#pragma unroll
+    for (int c = 0; c < NE; ++c) row[NE + c] = (c == r) ? 1.0 : 0.0;
+  }
+  bool used = !(lane < NE);
+  int mycol = 0;
+#pragma unroll
+  for (int jc = 0; jc < NE; ++jc) {
+    double cand = used ? -1.0 : fabs(row[jc]);
+    int idx = lane;
+#pragma unroll
+    for (int off = 16; off > 0; off >>= 1) {
+      const double oc = __shfl_xor(cand, off, 32);
+      const int oi = __shfl_xor(idx, off, 32);
+      if (oc > cand || (oc == cand && oi < idx)) { cand = oc; idx = oi; }
+    }
+    double pv = __shfl(row[jc], idx, 32);
+    if (pv == 0.0) pv = 1.0;   // singular patch: leave the column alone
+    const double f = (lane == idx) ? 0.0 : row[jc] / pv;
+#pragma unroll
+    for (int c = 0; c < 2 * NE; ++c) {
+      const double pr = __shfl(row[c], idx, 32);
+      row[c] = (lane == idx) ? pr / pv : row[c] - f * pr;
+    }
+    if (lane == idx) { used = true; mycol = jc; }
+  }
+  if (live && lane < NE) {
+    const ColorLayout L = color_layout(g.nx, g.ny);
+    const int col = (ci & 1) + 2 * (cj & 1);
+    const int nc = L.ncx[col] * L.ncy[col];
+    const int idx = (ci >> 1) + L.ncx[col] * (cj >> 1);
+    S* out = Ainv + (size_t)bs * NE * NE * g.ncell + (size_t)L.off[col] * NE * NE;
+#pragma unroll
+    for (int c = 0; c < NE; ++c) out[(size_t)(NE * mycol + c) * nc + idx] = (S)row[NE + c];
+  }
+}
+
+// ------------------------------------------------------ colored Vanka pass
+// One multiplicative pass over the cells of one colour: for every cell of the
+// colour, r_P = (b - A x_in) on the patch, x_out[P] = x_in[P] + omega Ainv r_P.
+// Patches of one colour do not overlap, so all of them update at once from the
+// same x_in; nodes outside every patch of the colour are copied.  Four lanes
+// (one per patch node) cooperate on a cell; "virtual" cells beyond the mesh
+// edge only copy.  zero_in: x_in is taken as zero (first sweep of a cycle).
+template <class S>
+__global__ void __launch_bounds__(256) k_vanka_pass(Geom g, double k, int color, S omega, int zero_in,
+                                                    const S* __restrict__ J, const S* __restrict__ Ainv,
+                                                    const S* __restrict__ b, const S* __restrict__ x_in,
+                                                    S* __restrict__ x_out, const int* __restrict__ active) {
+  const int bs = blockIdx.y;
+  if (active && !active[bs]) return;
+  const int cx = color & 1, cy = color >> 1;
+  const int nbx = (g.nx + cx) / 2 + 1, nby = (g.ny + cy) / 2 + 1;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int blk = t >> 2, a = t & 3;
+  const bool inb = blk < nbx * nby;
+  const int mx = inb ? blk % nbx : 0, my = inb ? blk / nbx : 0;
+  const int ci = 2 * mx - cx, cj = 2 * my - cy;
+  const int ni = ci + (a & 1), nj = cj + (a >> 1);
+  const bool valid = inb && ni >= 0 && nj >= 0 && ni <= g.nx && nj <= g.ny;
+  const bool real = inb && ci >= 0 && cj >= 0 && ci < g.nx && cj < g.ny;
+  const int n = valid ? ni + (g.nx + 1) * nj : 0;
+  const S* xb = x_in + (size_t)bs * g.nn * NC;
+  S r[NC] = {0, 0, 0, 0, 0};
+  S xo[NC] = {0, 0, 0, 0, 0};
+  if (valid) {
+    const S* bb = b + ((size_t)bs * g.nn + n) * NC;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) r[c] = bb[c];
+    if (!zero_in) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) xo[c] = xb[(size_t)n * NC + c];
+    }
+    if (real && !zero_in) {
+      const S* jb = J + (size_t)bs * NSLOT * BLK * g.nn;
+#pragma unroll
+      for (int s = 0; s < NSLOT; ++s) {
+        const int dx = s % 3 - 1, dy = s / 3 - 1;
+        const int ii = ni + dx, jj = nj + dy;
+        if (ii < 0 || jj < 0 || ii > g.nx || jj > g.ny) continue;
+        const S* xv = xb + (size_t)(ii + (g.nx + 1) * jj) * NC;
+        S xs[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) xs[c] = xv[c];
+#pragma unroll
+        for (int rr = 0; rr < NC; ++rr)
+#pragma unroll
+          for (int c = 0; c < NC; ++c) r[rr] -= jb[((size_t)s * BLK + NC * rr + c) * g.nn + n] * xs[c];
+      }
+      if (!(g.dmask[n] & DM_P)) {
+        S ap = 0;
+        for (int q = 0; q < NPST; ++q) {
+          const int dx = q % 5 - 2, dy = q / 5 - 2;
+          const int ii = ni + dx, jj = nj + dy;
+          if (ii < 0 || jj < 0 || ii > g.nx || jj > g.ny) continue;
+          ap += (S)g.pst[(size_t)q * g.nn + n] * xb[(size_t)(ii + (g.nx + 1) * jj) * NC + 4];
+        }
+        r[4] -= (S)k * ap;
+      }
+    }
+  }
+  // patch residual from the four lanes of the cell
+  S rp[NE];
+  const int base = (threadIdx.x & ~3) & 63;
+#pragma unroll
+  for (int bb = 0; bb < NL; ++bb)
+#pragma unroll
+    for (int c = 0; c < NC; ++c) rp[NC * bb + c] = __shfl(r[c], base + bb, 64);
+  if (!valid) return;
+  S* xw = x_out + ((size_t)bs * g.nn + n) * NC;
+  if (!real) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) xw[c] = xo[c];
+    return;
+  }
+  const ColorLayout L = color_layout(g.nx, g.ny);
+  const int nc = L.ncx[color] * L.ncy[color];
+  const int idx = (ci >> 1) + L.ncx[color] * (cj >> 1);
+  const S* ai = Ainv + (size_t)bs * NE * NE * g.ncell + (size_t)L.off[color] * NE * NE;
+#pragma unroll
+  for (int rr = 0; rr < NC; ++rr) {
+    S z = 0;
+    const int row = NC * a + rr;
+#pragma unroll
+    for (int c = 0; c < NE; ++c) z += ai[(size_t)(NE * row + c) * nc + idx] * rp[c];
+    xw[rr] = xo[rr] + omega * z;
+  }
+}
+
+// --------------------------------------------------------- grid transfers
+// b_c = P^T r_f (bilinear weights), zero on coarse Dirichlet components and
+// ignoring fine Dirichlet components (P has zero rows there).
+template <class S>
+__global__ void k_restrict(Geom gc, Geom gf, const S* __restrict__ rf, S* __restrict__ bc,
+                           const int* __restrict__ active) {
+  const int bs = blockIdx.y;
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= gc.nn || (active && !active[bs])) return;
+  const int I = n % (gc.nx + 1), Jc = n / (gc.nx + 1);
+  const uint8_t mc = gc.dmask[n];
+  S acc[NC] = {0, 0, 0, 0, 0};
+  for (int dy = -1; dy <= 1; ++dy)
+    for (int dx = -1; dx <= 1; ++dx) {
+      const int fi = 2 * I + dx, fj = 2 * Jc + dy;
+      if (fi < 0 || fj < 0 || fi > gf.nx || fj > gf.ny) continue;
+      const S w = (S)((dx ? 0.5 : 1.0) * (dy ? 0.5 : 1.0));
+      const int nf = fi + (gf.nx + 1) * fj;
+      const uint8_t mf = gf.dmask[nf];
+      const S* rv = rf + ((size_t)bs * gf.nn + nf) * NC;
+      for (int c = 0; c < NC; ++c)
+        if (!(mf & (1u << c))) acc[c] += w * rv[c];
+    }
+  S* o = bc + ((size_t)bs * gc.nn + n) * NC;
+  for (int c = 0; c < NC; ++c) o[c] = (mc & (1u << c)) ? (S)0 : acc[c];
+}
+
+// x_f += P x_c on non-Dirichlet fine components (coarse Dirichlet values are zero).
+template <class S>
+__global__ void k_prolong_add(Geom gf, Geom gc, const S* __restrict__ xc, S* __restrict__ xf,
+                              const int* __restrict__ active) {
+  const int bs = blockIdx.y;
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= gf.nn || (active && !active[bs])) return;
+  const int fi = n % (gf.nx + 1), fj = n / (gf.nx + 1);
+  const int i0 = fi >> 1, j0 = fj >> 1;
+  const int i1 = (fi & 1) ? i0 + 1 : i0, j1 = (fj & 1) ? j0 + 1 : j0;
+  const S wx = (fi & 1) ? (S)0.5 : (S)1.0, wy = (fj & 1) ? (S)0.5 : (S)1.0;
+  const uint8_t mf = gf.dmask[n];
+  S add[NC] = {0, 0, 0, 0, 0};
+  const int ci[2] = {i0, i1}, cj[2] = {j0, j1};
+  for (int q = 0; q < 4; ++q) {
+    const int ii = ci[q & 1], jj = cj[q >> 1];
+    if (((q & 1) && i1 == i0) || ((q >> 1) && j1 == j0)) continue;
+    const int nc = ii + (gc.nx + 1) * jj;
+    const uint8_t mc = gc.dmask[nc];
+    const S* xv = xc + ((size_t)bs * gc.nn + nc) * NC;
+    for (int c = 0; c < NC; ++c)
+      if (!(mc & (1u << c))) add[c] += wx * wy * xv[c];
+  }
+  S* xo = xf + ((size_t)bs * gf.nn + n) * NC;
+  for (int c = 0; c < NC; ++c)
+    if (!(mf & (1u << c))) xo[c] += add[c];
+}
+
+// ------------------------------------------- coarsest level: block LU
+// Unknowns ordered by super-columns of two x-node columns (bs = 2 (ny+1) 5);
+// the 3x3 block stencil plus the 5x5 pressure stencil make the matrix block
+// tridiagonal.  Factor: Delta_0 = D_0, Delta_K = D_K - L_K W_{K-1},
+// W_K = Delta_K^{-1} U_K.  Stored per slice: Dinv_K, W_K, L_K (bs x bs each).
+template <class S>
+__device__ inline double coarse_entry(const Geom& g, double k, const S* jb, int bs, int K, int l, int K2, int l2) {
+  // row: super-column K local l; column: super-column K2 local l2
+  const int r = l % NC, nl = l / NC, colx = nl / (g.ny + 1), jr = nl % (g.ny + 1);
+  const int c = l2 % NC, nl2 = l2 / NC, colx2 = nl2 / (g.ny + 1), jc = nl2 % (g.ny + 1);
+  const int ir = 2 * K + colx, ic = 2 * K2 + colx2;
+  if (ir > g.nx || ic > g.nx) return (K == K2 && l == l2) ? 1.0 : 0.0;   // padding: identity
+  const int dx = ic - ir, dy = jc - jr;
+  const int n = ir + (g.nx + 1) * jr;
+  double v = 0.0;
+  if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1)
+    v = (double)jb[((size_t)slot_of(dx, dy) * BLK + NC * r + c) * g.nn + n];
+  if (r == 4 && c == 4 && dx >= -2 && dx <= 2 && dy >= -2 && dy <= 2 && !(g.dmask[n] & DM_P))
+    v += k * g.pst[(size_t)pslot_of(dx, dy) * g.nn + n];
+  return v;
+}
+
+// One workgroup per slice; dynamic LDS holds [Delta | I] (bs x 2bs) and a bs x bs tile.
+template <class S>
+__global__ void __launch_bounds__(256) k_coarse_factor(Geom g, double k, const S* __restrict__ J, int bsz, int nsb,
+                                                       double* __restrict__ Dinv, double* __restrict__ W,
+                                                       double* __restrict__ Lb, const int* __restrict__ active) {
+  extern __shared__ double lds[];
+  const int bs = blockIdx.x;
+  if (active && !active[bs]) return;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const S* jb = J + (size_t)bs * NSLOT * BLK * g.nn;
+  double* M = lds;                       // bsz x 2bsz
+  double* T = lds + 2 * bsz * bsz;       // bsz x bsz scratch
+  __shared__ int piv_row;
+  __shared__ double piv_val;
+  __shared__ unsigned char used[128];
+  __shared__ double fac[128];
+  __shared__ int colmap[128];
+  const size_t B2 = (size_t)bsz * bsz;
+  double* dinv = Dinv + (size_t)bs * nsb * B2;
+  double* w = W + (size_t)bs * nsb * B2;
+  double* lb = Lb + (size_t)bs * nsb * B2;
+  for (int K = 0; K < nsb; ++K) {
+    // M = [D_K | I]
+    for (int e = tid; e < bsz * bsz; e += nt) {
+      const int r = e / bsz, c = e % bsz;
+      M[r * 2 * bsz + c] = coarse_entry<S>(g, k, jb, bs, K, r, K, c);
+      M[r * 2 * bsz + bsz + c] = (r == c) ? 1.0 : 0.0;
+    }
+    if (K > 0) {
+      // L_K and Delta_K = D_K - L_K W_{K-1}
+      for (int e = tid; e < bsz * bsz; e += nt) {
+        const int r = e / bsz, c = e % bsz;
+        const double v = coarse_entry<S>(g, k, jb, bs, K, r, K - 1, c);
+        T[e] = v;
+        lb[K * B2 + e] = v;
+      }
+      __syncthreads();
+      const double* wp = w + (K - 1) * B2;
+      for (int e = tid; e < bsz * bsz; e += nt) {
+        const int r = e / bsz, c = e % bsz;
+        double s = 0.0;
+        for (int q = 0; q < bsz; ++q) s += T[r * bsz + q] * wp[q * bsz + c];
+        M[r * 2 * bsz + c] -= s;
+      }
+    }
+    for (int e = tid; e < bsz; e += nt) used[e] = 0;
+    __syncthreads();
+    // Gauss-Jordan with partial pivoting on [Delta | I]; colmap[jc] = pivot row of column jc
+    for (int jc = 0; jc < bsz; ++jc) {
+      if (tid == 0) {
+        int best = 0;
+        double bv = -1.0;
+        for (int r = 0; r < bsz; ++r)
+          if (!used[r] && fabs(M[r * 2 * bsz + jc]) > bv) { bv = fabs(M[r * 2 * bsz + jc]); best = r; }
+        piv_row = best;
+        const double pv = M[best * 2 * bsz + jc];
+        piv_val = (pv == 0.0) ? 1.0 : pv;
+        used[best] = 1;
+        colmap[jc] = best;
+      }
+      __syncthreads();
+      const int pr = piv_row;
+      const double pv = piv_val;
+      for (int r = tid; r < bsz; r += nt) fac[r] = (r == pr) ? 0.0 : M[r * 2 * bsz + jc] / pv;
+      __syncthreads();
+      for (int e = tid; e < bsz * 2 * bsz; e += nt) {
+        const int r = e / (2 * bsz), c = e % (2 * bsz);
+        if (r != pr && fac[r] != 0.0) M[e] -= fac[r] * M[pr * 2 * bsz + c];
+      }
+      __syncthreads();
+      for (int c = tid; c < 2 * bsz; c += nt) M[pr * 2 * bsz + c] /= pv;
+      __syncthreads();
+    }
+    // Dinv_K row jc = right half of row piv(jc)
+    for (int e = tid; e < bsz * bsz; e += nt) {
+      const int jr = e / bsz, c = e % bsz;
+      dinv[K * B2 + e] = M[colmap[jr] * 2 * bsz + bsz + c];
+    }
+    __syncthreads();
+    if (K < nsb - 1) {
+      // W_K = Dinv_K U_K with U_K the block (K, K+1)
+      for (int e = tid; e < bsz * bsz; e += nt) {
+        const int r = e / bsz, c = e % bsz;
+        T[e] = coarse_entry<S>(g, k, jb, bs, K, r, K + 1, c);
+      }
+      __syncthreads();
+      for (int e = tid; e < bsz * bsz; e += nt) {
+        const int r = e / bsz, c = e % bsz;
+        double s = 0.0;
+        for (int q = 0; q < bsz; ++q) s += dinv[K * B2 + r * bsz + q] * T[q * bsz + c];
+        w[K * B2 + e] = s;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Solve with the block factors: y_K = Dinv_K (b_K - L_K y_{K-1}); x_K = y_K - W_K x_{K+1}.
+template <class S>
+__global__ void __launch_bounds__(256) k_coarse_solve(Geom g, int bsz, int nsb, const double* __restrict__ Dinv,
+                                                      const double* __restrict__ W, const double* __restrict__ Lb,
+                                                      const S* __restrict__ bvec, S* __restrict__ xvec,
+                                                      const int* __restrict__ active) {
+  extern __shared__ double lds[];
+  const int bs = blockIdx.x;
+  if (active && !active[bs]) return;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const size_t B2 = (size_t)bsz * bsz;
+  double* y = lds;              // nsb * bsz
+  double* tmp = lds + nsb * bsz;  // bsz
+  const S* bb = bvec + (size_t)bs * g.nn * NC;
+  S* xb = xvec + (size_t)bs * g.nn * NC;
+  const double* dinv = Dinv + (size_t)bs * nsb * B2;
+  const double* w = W + (size_t)bs * nsb * B2;
+  const double* lb = Lb + (size_t)bs * nsb * B2;
+  auto gidx = [&](int K, int l) -> int {   // global dof index or -1 (padding)
+    const int c = l % NC, nl = l / NC, colx = nl / (g.ny + 1), jn = nl % (g.ny + 1);
+    const int i = 2 * K + colx;
+    if (i > g.nx) return -1;
+    return (i + (g.nx + 1) * jn) * NC + c;
+  };
+  for (int K = 0; K < nsb; ++K) {
+    for (int l = tid; l < bsz; l += nt) {
+      const int gi = gidx(K, l);
+      double v = gi >= 0 ? (double)bb[gi] : 0.0;
+      if (K > 0) {
+        const double* L = lb + K * B2 + (size_t)l * bsz;
+        const double* yp = y + (K - 1) * bsz;
+        for (int q = 0; q < bsz; ++q) v -= L[q] * yp[q];
+      }
+      tmp[l] = v;
+    }
+    __syncthreads();
+    for (int l = tid; l < bsz; l += nt) {
+      const double* D = dinv + K * B2 + (size_t)l * bsz;
+      double s = 0.0;
+      for (int q = 0; q < bsz; ++q) s += D[q] * tmp[q];
+      y[K * bsz + l] = s;
+    }
+    __syncthreads();
+  }
+  for (int K = nsb - 2; K >= 0; --K) {
+    for (int l = tid; l < bsz; l += nt) {
+      const double* Wr = w + K * B2 + (size_t)l * bsz;
+      const double* xn = y + (K + 1) * bsz;
+      double s = 0.0;
+      for (int q = 0; q < bsz; ++q) s += Wr[q] * xn[q];
+      tmp[l] = y[K * bsz + l] - s;
+    }
+    __syncthreads();
+    for (int l = tid; l < bsz; l += nt) y[K * bsz + l] = tmp[l];
+    __syncthreads();
+  }
+  for (int K = 0; K < nsb; ++K)
+    for (int l = tid; l < bsz; l += nt) {
+      const int gi = gidx(K, l);
+      if (gi >= 0) xb[gi] = (S)y[K * bsz + l];
+    }
+}
+
+// ------------------------------------------------------------ FGMRES pieces
+__device__ inline double block_sum(double v, double* sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (t < s) sh[t] += sh[t + s];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// partial[b][i][chunk] = sum over the chunk of X[b] . Y_i[b] for i < nv
+// (X and the Y_i are vectors of length n with strides sx, sy per slice / per i).
+template <class S>
+__global__ void __launch_bounds__(RED_T) k_multidot(int n, int nv, const S* __restrict__ X, size_t sxb,
+                                                    const S* __restrict__ Y, size_t syb, size_t syi, int chunk,
+                                                    double* __restrict__ partial, int nchunk,
+                                                    const int* __restrict__ active) {
+  __shared__ double sh[RED_T];
+  const int b = blockIdx.y, ch = blockIdx.x;
+  if (active && !active[b]) return;
+  const int lo = ch * chunk, hi = min(n, lo + chunk);
+  const S* x = X + b * sxb;
+  for (int i = 0; i < nv; ++i) {
+    const S* y = Y + b * syb + i * syi;
+    S acc = 0;
+    for (int e = lo + threadIdx.x; e < hi; e += blockDim.x) acc += x[e] * y[e];
+    const double s = block_sum((double)acc, sh);
+    if (threadIdx.x == 0) partial[((size_t)b * 64 + i) * nchunk + ch] = s;
+  }
+}
+
+// out[b][i] = sum over chunks of partial[b][i][*] (fixed order)
+__global__ void k_reduce_partials(int nv, int nchunk, const double* __restrict__ partial, double* __restrict__ out,
+                                  int ostride, const int* __restrict__ active) {
+  const int b = blockIdx.x;
+  if (active && !active[b]) return;
+  for (int i = threadIdx.x; i < nv; i += blockDim.x) {
+    double s = 0.0;
+    for (int c = 0; c < nchunk; ++c) s += partial[((size_t)b * 64 + i) * nchunk + c];
+    out[(size_t)b * ostride + i] = s;
+  }
+}
+
+// X[b] -= sum_{i<nv} h[b][i] Y_i[b]
+template <class S>
+__global__ void k_multiaxpy(int n, int nv, S* __restrict__ X, size_t sxb, const S* __restrict__ Y, size_t syb,
+                            size_t syi, const double* __restrict__ h, int hstride, double sign,
+                            const int* __restrict__ active) {
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  S acc = X[b * sxb + e];
+  for (int i = 0; i < nv; ++i) acc += (S)(sign * h[(size_t)b * hstride + i]) * Y[b * syb + i * syi + e];
+  X[b * sxb + e] = acc;
+}
+
+// Y[b] = alpha[b] X[b]  (alpha per slice, from a device array with a stride)
+template <class S>
+__global__ void k_scale(int n, const S* __restrict__ X, size_t sxb, S* __restrict__ Y, size_t syb,
+                        const double* __restrict__ alpha, int astride, int invert_sqrt,
+                        const int* __restrict__ active) {
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  double a = 1.0;   // mode 2: plain copy
+  if (invert_sqrt == 0) a = alpha[(size_t)b * astride];
+  if (invert_sqrt == 1) { a = alpha[(size_t)b * astride]; a = a > 0.0 ? 1.0 / sqrt(a) : 0.0; }
+  Y[b * syb + e] = (S)(a * (double)X[b * sxb + e]);
+}
+
+// Y[b] = X[b] / D[b]  (undo the row scaling: preconditioner input)
+template <class S>
+__global__ void k_unscale(int n, const S* __restrict__ X, size_t sxb, const double* __restrict__ D, S* __restrict__ Y,
+                          const int* __restrict__ active) {
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  Y[(size_t)b * n + e] = (S)((double)X[b * sxb + e] / D[(size_t)b * n + e]);
+}
+
+// Y[b] = D[b] * X[b] (scaled right-hand side), X double
+template <class S>
+__global__ void k_scale_rhs(int n, const double* __restrict__ X, const double* __restrict__ D, S* __restrict__ Y,
+                            size_t syb, const int* __restrict__ active) {
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const double d = D ? D[(size_t)b * n + e] : 1.0;
+  Y[b * syb + e] = (S)(-X[(size_t)b * n + e] * d);
+}
+
+// Start of an FGMRES cycle: beta = ||r||, g = (beta, 0, ...), state and column count.
+__global__ void k_init_cycle(int R, int cycle, const double* __restrict__ beta2, double* __restrict__ beta0,
+                             double* __restrict__ gv, int* __restrict__ state, int* __restrict__ ncol, double tol,
+                             const int* __restrict__ gact, int B) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  ncol[b] = 0;
+  if (!gact[b]) { state[b] = 1; return; }
+  const double beta = sqrt(fmax(beta2[b], 0.0));
+  if (cycle == 0) beta0[b] = beta;
+  for (int i = 0; i <= R; ++i) gv[(size_t)b * (R + 1) + i] = 0.0;
+  gv[(size_t)b * (R + 1)] = beta;
+  state[b] = (beta <= tol * beta0[b] || beta == 0.0) ? 1 : 0;
+}
+
+// hcol[b][i] += hcol2[b][i] (i <= j); hcol[b][j+1] = ||w||^2
+__global__ void k_cgs_combine(int j, double* __restrict__ hcol, const double* __restrict__ hcol2,
+                              const double* __restrict__ hn2, const int* __restrict__ active, int B) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B || (active && !active[b])) return;
+  for (int i = 0; i <= j; ++i) hcol[(size_t)b * 64 + i] += hcol2[(size_t)b * 64 + i];
+  hcol[(size_t)b * 64 + j + 1] = hn2[b];
+}
+
+// gact[b] = nact[b] && state[b] == 0
+__global__ void k_update_gact(const int* __restrict__ nact, const int* __restrict__ state, int* __restrict__ gact,
+                              int B) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  gact[b] = (nact[b] && state[b] == 0) ? 1 : 0;
+}
+
+// Arnoldi bookkeeping for column j of every active slice: Hcol = h (j+2 entries,
+// the last one the squared norm of w after orthogonalisation), apply the stored
+// Givens rotations, create a new one, update g and the residual estimate.
+// state[b]: 0 running, 1 converged, 2 breakdown.
+__global__ void k_givens(int j, int R, double* __restrict__ H, const double* __restrict__ hcol,
+                         double* __restrict__ cs, double* __restrict__ sn, double* __restrict__ gv,
+                         double* __restrict__ res, const double* __restrict__ beta0, double tol,
+                         int* __restrict__ state, int* __restrict__ ncol, const int* __restrict__ active, int B) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  if ((active && !active[b]) || state[b] != 0) return;
+  ncol[b] = j + 1;
+  double* h = H + (size_t)b * (R + 1) * R;   // column-major: h[i + (R+1) j]
+  for (int i = 0; i <= j; ++i) h[i + (R + 1) * j] = hcol[(size_t)b * 64 + i];
+  double hn = sqrt(fmax(hcol[(size_t)b * 64 + j + 1], 0.0));
+  h[j + 1 + (R + 1) * j] = hn;
+  for (int i = 0; i < j; ++i) {
+    const double c = cs[(size_t)b * R + i], s = sn[(size_t)b * R + i];
+    const double a = h[i + (R + 1) * j], bb = h[i + 1 + (R + 1) * j];
+    h[i + (R + 1) * j] = c * a + s * bb;
+    h[i + 1 + (R + 1) * j] = -s * a + c * bb;
+  }
+  const double a = h[j + (R + 1) * j], bb = h[j + 1 + (R + 1) * j];
+  const double r = hypot(a, bb);
+  const double c = r > 0 ? a / r : 1.0, s = r > 0 ? bb / r : 0.0;
+  cs[(size_t)b * R + j] = c;
+  sn[(size_t)b * R + j] = s;
+  h[j + (R + 1) * j] = r;
+  h[j + 1 + (R + 1) * j] = 0.0;
+  const double gj = gv[(size_t)b * (R + 1) + j];
+  gv[(size_t)b * (R + 1) + j] = c * gj;
+  gv[(size_t)b * (R + 1) + j + 1] = -s * gj;
+  res[b] = fabs(gv[(size_t)b * (R + 1) + j + 1]);
+  if (res[b] <= tol * beta0[b]) state[b] = 1;
+  else if (hn <= 1e-300) state[b] = 2;
+}
+
+// Solve the (jmax x jmax) triangular system of each slice: y = H^{-1} g,
+// using its own column count ncol[b].
+__global__ void k_trisolve(int R, const double* __restrict__ H, const double* __restrict__ gv,
+                           const int* __restrict__ ncol, double* __restrict__ y, const int* __restrict__ active,
+                           int B) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  if (active && !active[b]) return;
+  const int m = ncol[b];
+  const double* h = H + (size_t)b * (R + 1) * R;
+  double* yy = y + (size_t)b * 64;
+  for (int i = 0; i < 64; ++i) yy[i] = 0.0;
+  for (int i = m - 1; i >= 0; --i) {
+    double s = gv[(size_t)b * (R + 1) + i];
+    for (int q = i + 1; q < m; ++q) s -= h[i + (R + 1) * q] * yy[q];
+    const double d = h[i + (R + 1) * i];
+    yy[i] = d != 0.0 ? s / d : 0.0;
+  }
+}
+
+// ------------------------------------------------------------ Newton update
+// U[b] += dx[b] (on active slices), then per-slice maxima of |dx| and |U| per
+// field (v, u, p) into part[b][6][chunk].
+template <class S>
+__global__ void __launch_bounds__(RED_T) k_newton_update(int nn, double* __restrict__ U, const S* __restrict__ dx,
+                                                         int chunk, double* __restrict__ part, int nchunk,
+                                                         const int* __restrict__ active) {
+  __shared__ double sh[RED_T];
+  const int b = blockIdx.y, ch = blockIdx.x;
+  if (active && !active[b]) return;
+  const int lo = ch * chunk, hi = min(nn, lo + chunk);
+  double m[6] = {0, 0, 0, 0, 0, 0};
+  for (int n = lo + threadIdx.x; n < hi; n += blockDim.x) {
+    double* u = U + ((size_t)b * nn + n) * NC;
+    const S* d = dx + ((size_t)b * nn + n) * NC;
+    for (int c = 0; c < NC; ++c) {
+      const double dv = (double)d[c];
+      const double un = u[c] + dv;
+      u[c] = un;
+      const int f = c < 2 ? 0 : (c < 4 ? 1 : 2);
+      m[f] = fmax(m[f], fabs(dv));
+      m[3 + f] = fmax(m[3 + f], fabs(un));
+      if (!isfinite(un)) m[f] = INFINITY;
+    }
+  }
+  for (int q = 0; q < 6; ++q) {
+    const int t = threadIdx.x;
+    sh[t] = m[q];
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+      if (t < s) sh[t] = fmax(sh[t], sh[t + s]);
+      __syncthreads();
+    }
+    if (t == 0) part[((size_t)b * 6 + q) * nchunk + ch] = sh[0];
+    __syncthreads();
+  }
+}
+
+// max over chunks -> out[b][6]
+__global__ void k_max_partials(int nchunk, const double* __restrict__ part, double* __restrict__ out, int B) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  for (int q = 0; q < 6; ++q) {
+    double m = 0.0;
+    for (int c = 0; c < nchunk; ++c) m = fmax(m, part[((size_t)b * 6 + q) * nchunk + c]);
+    out[(size_t)b * 6 + q] = m;
+  }
+}
+
+// Parareal correction of one boundary (eq. (parareal:iteration)): out = Cn + Fv - Cold, FP64.
+__global__ void k_parareal_update(size_t n, const double* __restrict__ Cn, const double* __restrict__ Fv,
+                                  const double* __restrict__ Cold, double* __restrict__ out) {
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
+    out[e] = Cn[e] + Fv[e] - Cold[e];
+}
+
+// Per boundary b: sums of squares of (A - B) and of A for the velocity and the
+// displacement components -> part[b][4][chunk].
+__global__ void __launch_bounds__(RED_T) k_change_norms(int nn, const double* __restrict__ A,
+                                                        const double* __restrict__ Bv, int chunk,
+                                                        double* __restrict__ part, int nchunk) {
+  __shared__ double sh[RED_T];
+  const int b = blockIdx.y, ch = blockIdx.x;
+  const int lo = ch * chunk, hi = min(nn, lo + chunk);
+  double s[4] = {0, 0, 0, 0};
+  for (int n = lo + threadIdx.x; n < hi; n += blockDim.x) {
+    const double* a = A + ((size_t)b * nn + n) * NC;
+    const double* o = Bv + ((size_t)b * nn + n) * NC;
+    for (int c = 0; c < 4; ++c) {
+      const double d = a[c] - o[c];
+      s[(c >> 1) * 2] += d * d;
+      s[(c >> 1) * 2 + 1] += a[c] * a[c];
+    }
+  }
+  for (int q = 0; q < 4; ++q) {
+    const double r = block_sum(s[q], sh);
+    if (threadIdx.x == 0) part[((size_t)b * 4 + q) * nchunk + ch] = r;
+  }
+}
+
+// flag[b] = 1 if any entry of X[b] is not finite
+__global__ void k_nonfinite(size_t n, const double* __restrict__ X, int* __restrict__ flag) {
+  const int b = blockIdx.y;
+  for (size_t e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
+    if (!isfinite(X[(size_t)b * n + e])) flag[b] = 1;
+}
+
+template <class S>
+__global__ void k_fill(size_t n, S* __restrict__ X, S v) {
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) X[e] = v;
+}
+
+template <class A, class B2>
+__global__ void k_convert(size_t n, const A* __restrict__ X, B2* __restrict__ Y) {
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
+    Y[e] = (B2)X[e];
+}
+
+// explicit instantiations
+#define INST(S)                                                                                                   \
+  template __global__ void k_spmv<S>(Geom, double, const S*, const S*, const S*, const double*, S*, const int*); \
+  template __global__ void k_vanka_factor<S>(Geom, double, const S*, S*, const int*);                            \
+  template __global__ void k_vanka_pass<S>(Geom, double, int, S, int, const S*, const S*, const S*, const S*, S*, \
+                                           const int*);                                                          \
+  template __global__ void k_restrict<S>(Geom, Geom, const S*, S*, const int*);                                  \
+  template __global__ void k_prolong_add<S>(Geom, Geom, const S*, S*, const int*);                               \
+  template __global__ void k_coarse_factor<S>(Geom, double, const S*, int, int, double*, double*, double*,       \
+                                              const int*);                                                       \
+  template __global__ void k_coarse_solve<S>(Geom, int, int, const double*, const double*, const double*,        \
+                                             const S*, S*, const int*);                                          \
+  template __global__ void k_multidot<S>(int, int, const S*, size_t, const S*, size_t, size_t, int, double*, int, \
+                                         const int*);                                                            \
+  template __global__ void k_multiaxpy<S>(int, int, S*, size_t, const S*, size_t, size_t, const double*, int,    \
+                                          double, const int*);                                                   \
+  template __global__ void k_scale<S>(int, const S*, size_t, S*, size_t, const double*, int, int, const int*);   \
+  template __global__ void k_unscale<S>(int, const S*, size_t, const double*, S*, const int*);                   \
+  template __global__ void k_scale_rhs<S>(int, const double*, const double*, S*, size_t, const int*);            \
+  template __global__ void k_newton_update<S>(int, double*, const S*, int, double*, int, const int*);            \
+  template __global__ void k_fill<S>(size_t, S*, S);
+INST(double)
+INST(float)
+template __global__ void k_convert<double, float>(size_t, const double*, float*);
+template __global__ void k_convert<float, double>(size_t, const float*, double*);
+
+}  // namespace fsi

@@ -1,0 +1,207 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle.
+
+Tolerances: FP64 path 1e-10 relative per field at slice boundaries (element
+residual / Jacobian products 1e-12); mixed-precision path 1e-6 relative per
+field after the FP64 Newton refinement.  Inputs are seeded (synth).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle.residual import Discretization
+from oracle import propagate as P
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def fsi():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1907_01252_amd import fsi as f
+    f.load()
+    return f
+
+
+def _dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+FIELDS = {"v": slice(0, 2), "u": slice(2, 4), "p": slice(4, 5)}
+
+
+def field_rel(a, b, norm="max"):
+    """per-field relative difference of node-major arrays [..., nodes, 5]"""
+    out = {}
+    for k, sl in FIELDS.items():
+        x, y = a[..., sl], b[..., sl]
+        if norm == "max":
+            out[k] = np.abs(x - y).max() / max(np.abs(y).max(), 1e-300)
+        else:
+            out[k] = np.linalg.norm(x - y) / max(np.linalg.norm(y), 1e-300)
+    return out
+
+
+@pytest.fixture(scope="module")
+def c1(fsi):
+    p = synth.workload("c1", seed=1)
+    prob = fsi.Problem(fsi.make_params(p, precision="fp64", max_batch=4))
+    return p, prob, Discretization(p)
+
+
+def test_residual_parity(fsi, c1):
+    p, prob, D = c1
+    _say("case: residual parity c1 B=3")
+    B = 3
+    U = np.stack([synth.random_state(p, 100 + b) for b in range(B)])
+    Uo = np.stack([synth.random_state(p, 200 + b) for b in range(B)])
+    t = [0.05, 0.3, 0.0731]
+    k = p["k_fine"]
+    R = torch.zeros(B, prob.n_nodes, 5, dtype=torch.float64, device="cuda")
+    prob.debug_residual(B, _dev(U), _dev(Uo), t, k, R)
+    Rg = _host(R)
+    for b in range(B):
+        Ro = D.residual(U[b], Uo[b], t[b], k)
+        err = field_rel(Rg[b], Ro)
+        assert max(err.values()) <= 1e-12, (b, err)
+
+
+def test_jacobian_parity(fsi, c1):
+    p, prob, D = c1
+    _say("case: jacobian parity c1 B=2")
+    B = 2
+    U = np.stack([synth.random_state(p, 300 + b) for b in range(B)])
+    Uo = np.stack([synth.random_state(p, 400 + b) for b in range(B)])
+    X = np.stack([synth.random_state(p, 500 + b) for b in range(B)])
+    t = [0.02, 0.5]
+    k = p["k_fine"]
+    Y = torch.zeros(B, prob.n_nodes, 5, dtype=torch.float64, device="cuda")
+    prob.debug_jacobian_apply(B, _dev(U), _dev(Uo), t, k, _dev(X), Y)
+    Yg = _host(Y)
+    for b in range(B):
+        A = D.jacobian(U[b], Uo[b], t[b], k)
+        Yo = (A @ X[b].ravel()).reshape(-1, 5)
+        err = field_rel(Yg[b], Yo)
+        assert max(err.values()) <= 1e-12, (b, err)
+
+
+def test_vcycle_contracts(fsi, c1):
+    """The multigrid V-cycle is a contraction on the Newton Jacobian: ||(I - M^-1 J) e|| < ||e||."""
+    p, prob, D = c1
+    _say("case: vcycle contraction c1")
+    k = p["k_fine"]
+    U0 = np.zeros((D.mesh.n_nodes, 5))
+    U1 = P.propagate(D, U0, 0.0, 3 * k, 3)
+    t = [4 * k]
+    Ug = D.apply_dirichlet(U1, t[0])
+    rng = np.random.default_rng(3)
+    e = rng.normal(size=U1.shape) * np.array([0.3, 0.3, 1e-3, 1e-3, 100.0])
+    e[D.dirichlet] = 0.0
+    Ud, Uod = _dev(Ug[None]), _dev(U1[None])
+    E = _dev(e[None])
+    AE = torch.zeros_like(E)
+    ME = torch.zeros_like(E)
+    ratios = []
+    for _ in range(6):
+        prob.debug_jacobian_apply(1, Ud, Uod, t, k, E, AE)
+        prob.debug_vcycle(1, Ud, Uod, t, k, AE, ME)
+        E2 = E - ME
+        r = (torch.linalg.norm(E2) / torch.linalg.norm(E)).item()
+        ratios.append(r)
+        E = E2.contiguous()
+    assert max(ratios[2:]) < 0.9, ratios
+
+
+def test_fine_propagate_parity_fp64(fsi, c1):
+    p, prob, D = c1
+    _say("case: fine_propagate fp64 c1 B=2 m=3")
+    k = p["k_fine"]
+    m = 3
+    dl = m * k
+    U0 = np.zeros((D.mesh.n_nodes, 5))
+    Ua = P.propagate(D, U0, 0.0, 2 * dl, 6)          # a state at t = 2 dl
+    inputs = [U0, Ua]
+    t0 = [0.0, 2 * dl]
+    ref = [P.propagate(D, inputs[b], t0[b], dl, m) for b in range(2)]
+    Uin = _dev(np.stack(inputs))
+    Uout = torch.zeros_like(Uin)
+    code, st = prob.fine_propagate(2, t0, dl, m, Uin, Uout)
+    Ug = _host(Uout)
+    for b in range(2):
+        err = field_rel(Ug[b], ref[b], norm="l2")
+        _say("slice", b, "newton", st.newton_its[b], "krylov", st.krylov_its[b], "err", err)
+        assert max(err.values()) <= 1e-10, (b, err)
+
+
+def test_batched_equals_sequential(fsi, c1):
+    p, prob, D = c1
+    _say("case: batched vs sequential c1 B=3")
+    k = p["k_fine"]
+    dl = 2 * k
+    U0 = np.zeros((D.mesh.n_nodes, 5))
+    ins = np.stack([P.propagate(D, U0, 0.0, q * dl, 2 * q) if q else U0 for q in range(3)])
+    t0 = [q * dl for q in range(3)]
+    Uin = _dev(ins)
+    Ub = torch.zeros_like(Uin)
+    prob.fine_propagate(3, t0, dl, 2, Uin, Ub)
+    Us = torch.zeros_like(Uin)
+    for q in range(3):
+        out = torch.zeros_like(Uin[q:q + 1])
+        prob.fine_propagate(1, [t0[q]], dl, 2, Uin[q:q + 1].contiguous(), out)
+        Us[q] = out[0]
+    err = field_rel(_host(Ub), _host(Us), norm="l2")
+    assert max(err.values()) <= 1e-10, err
+
+
+def test_fine_propagate_parity_mixed(fsi):
+    p = synth.workload("c1", seed=2)
+    _say("case: fine_propagate mixed c1 B=2 m=3")
+    prob = fsi.Problem(fsi.make_params(p, precision="mixed", max_batch=2))
+    D = Discretization(p)
+    k = p["k_fine"]
+    m = 3
+    dl = m * k
+    U0 = np.zeros((D.mesh.n_nodes, 5))
+    Ua = P.propagate(D, U0, 0.0, dl, 3)
+    t0 = [0.0, dl]
+    ref = [P.propagate(D, U0, 0.0, dl, m), P.propagate(D, Ua, dl, dl, m)]
+    Uin = _dev(np.stack([U0, Ua]))
+    Uout = torch.zeros_like(Uin)
+    prob.fine_propagate(2, t0, dl, m, Uin, Uout)
+    Ug = _host(Uout)
+    for b in range(2):
+        err = field_rel(Ug[b], ref[b], norm="l2")
+        _say("mixed slice", b, err)
+        assert max(err.values()) <= 1e-6, (b, err)
+
+
+def test_parareal_K_equals_N(fsi):
+    """Parareal with N iterations reproduces the sequential fine solution (Section 4.1 statement)."""
+    p = synth.workload("c1", T=0.06, N=3, dt_fine=0.01, dt_coarse=0.02, seed=3)
+    _say("case: parareal K=N c1-small N=3")
+    prob = fsi.Problem(fsi.make_params(p, precision="fp64", max_batch=3))
+    D = Discretization(p)
+    U0 = np.zeros((D.mesh.n_nodes, 5))
+    seq = P.sequential(D, p, U0)
+    Ub = torch.zeros(p["N"] + 1, prob.n_nodes, 5, dtype=torch.float64, device="cuda")
+    code, st = prob.parareal_run(p["T"], p["N"], p["m"], p["M"], 0.0, p["N"], _dev(U0), Ub, raise_on_error=False)
+    assert code in (fsi.FSI_OK, fsi.FSI_ERR_PARAREAL)
+    assert st.parareal_iters == p["N"]
+    Ug = _host(Ub)
+    for l in range(1, p["N"] + 1):
+        err = field_rel(Ug[l], seq[l], norm="l2")
+        assert max(err["v"], err["u"]) <= 1e-10, (l, err)
