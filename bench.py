@@ -1,0 +1,193 @@
+"""Fine-propagator throughput on one MI355X.
+
+Workload (default): 2d ALE-FSI channel with an elastic bar, 128x32 Q1 cells
+(21,285 unknowns), 32 Parareal slices of length 1/16 on [0, 2], 32 shifted
+Crank-Nicolson steps of 2^-9 per slice, FP64.  The slice inputs are the
+states of the initial coarse sweep (4 coarse steps per slice), i.e. the inputs
+of the first Parareal fine sweep.  One timed step = one batched fine sweep
+(fine_propagate over all 32 slices).  Reported:
+
+  value            dof.steps/s of the batched sweep (unknowns x steps x slices / wall time)
+  sequential       the same slices propagated one call per slice (B = 1), on a
+                   prefix of the slices, same solver settings
+  roofline         the colored Vanka smoothing pass (dominant kernel): algorithmic
+                   bytes per launch / mean launch time from HIP events on the
+                   stream of the timed sweeps, against the 8 TB/s HBM peak
+  accuracy         a batched-sweep slice against the FP64 oracle on a bounded
+                   number of steps (gate 1e-6 relative per field)
+  cpu_baseline     the oracle (NumPy/SciPy, SuperLU) on the host, same slice,
+                   bounded to a few steps
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# kernel families timed by the library (HIP events on the call's stream), in fsi_profile_query order
+FAMILIES = ("smoother_spmv_fine", "krylov_spmv_fine", "jacobian_elem", "residual", "vanka_update_fine",
+            "smoother_coarser_levels", "coarsest_solve")
+KERNEL_NAMES = {"smoother_spmv_fine": "k_spmv (Vanka residual, finest level)",
+                "vanka_update_fine": "k_vanka_update (finest level)",
+                "krylov_spmv_fine": "k_spmv (Krylov product, finest level)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--precision", default=None, help="fp64 | mixed (default: the workload's)")
+    ap.add_argument("--seq-slices", type=int, default=4)
+    ap.add_argument("--gate-steps", type=int, default=2)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-seq", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU: the fine sweep's slices are batched on a single "
+                                   "MI355X; multi-GPU runs are not part of it", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    import synth
+    from paper_1907_01252_amd import fsi
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    p = synth.workload(args.workload, seed=0)
+    prec = args.precision or p["precision"]
+    N, m, M, dl = p["N"], p["m"], p["M"], p["slice_len"]
+    prob = fsi.Problem(fsi.make_params(p, precision=prec, max_batch=N))
+    nd = prob.n_dofs
+    dev = "cuda"
+
+    # ---- inputs: initial coarse sweep (untimed setup)
+    U = torch.zeros(N + 1, prob.n_nodes, 5, dtype=torch.float64, device=dev)
+    prob.initial_state(U[0])
+    for l in range(N):
+        out = torch.zeros_like(U[0:1])
+        prob.coarse_propagate(1, [l * dl], dl, M, U[l:l + 1].contiguous(), out)
+        U[l + 1] = out[0]
+    Uin = U[:N].contiguous()
+    t0s = [l * dl for l in range(N)]
+    Uout = torch.zeros_like(Uin)
+
+    # ---- warmup + timed batched sweeps
+    for _ in range(args.warmup):
+        prob.fine_propagate(N, t0s, dl, m, Uin, Uout)
+    torch.cuda.synchronize()
+    t_a = time.perf_counter()
+    stats = []
+    for _ in range(args.steps):
+        _, st = prob.fine_propagate(N, t0s, dl, m, Uin, Uout)
+        stats.append((st.newton_total, st.krylov_total))
+    torch.cuda.synchronize()
+    t_b = time.perf_counter()
+    wall = (t_b - t_a) / args.steps
+    # one more sweep of the same workload with HIP events around every launch of the
+    # profiled kernel families (kernels launched directly, not replayed from graphs)
+    prob.profile_enable(True)
+    t_p = time.perf_counter()
+    prob.fine_propagate(N, t0s, dl, m, Uin, Uout)
+    torch.cuda.synchronize()
+    prof_wall = time.perf_counter() - t_p
+    prob.profile_enable(False)
+    fams = {name: prob.profile_query(i) for i, name in enumerate(FAMILIES)}
+    dof_steps = nd * m * N
+    value = dof_steps / wall
+
+    # ---- sequential-slice path on a prefix of the slices
+    seq = None
+    if not args.no_seq:
+        S = min(args.seq_slices, N)
+        torch.cuda.synchronize()
+        t_c = time.perf_counter()
+        for l in range(S):
+            o = torch.zeros_like(Uin[l:l + 1])
+            prob.fine_propagate(1, [t0s[l]], dl, m, Uin[l:l + 1].contiguous(), o)
+        torch.cuda.synchronize()
+        seq_wall = time.perf_counter() - t_c
+        seq = {"value": nd * m * S / seq_wall, "slices_timed": S, "ms_per_slice": 1e3 * seq_wall / S}
+
+    # ---- accuracy gate and CPU baseline: oracle on slice 1 for a few steps
+    acc, cpu = None, None
+    if not args.no_cpu:
+        from oracle.residual import Discretization
+        from oracle import propagate as P
+        D = Discretization(p)
+        k = p["k_fine"]
+        l = 1
+        u_in = Uin[l].cpu().numpy()
+        ns = args.gate_steps
+        # GPU: the same slice, same input, ns steps (B = 1 call of the product path)
+        o = torch.zeros_like(Uin[l:l + 1])
+        prob.fine_propagate(1, [t0s[l]], ns * k, ns, Uin[l:l + 1].contiguous(), o)
+        g = o[0].cpu().numpy()
+        threads = os.environ.get("OMP_NUM_THREADS") or str(os.cpu_count())
+        t_d = time.perf_counter()
+        ref = u_in
+        done = 0
+        for n in range(ns):
+            ref = P.newton_step(D, ref, t0s[l] + (n + 1) * k, k)
+            done += 1
+            if time.perf_counter() - t_d > args.cpu_seconds:
+                break
+        cpu_wall = time.perf_counter() - t_d
+        if done == ns:
+            errs = {}
+            for f, sl in (("v", slice(0, 2)), ("u", slice(2, 4)), ("p", slice(4, 5))):
+                errs[f] = float(np.linalg.norm(g[:, sl] - ref[:, sl]) / np.linalg.norm(ref[:, sl]))
+            acc = {"max_rel_err": max(errs.values()), "per_field": errs, "gate": 1e-6,
+                   "pass": max(errs.values()) <= 1e-6, "sample": f"slice {l}, {ns} steps vs FP64 oracle"}
+        cpu = {"value": nd * done / cpu_wall, "unit": "dof*steps/s", "cores": int(threads),
+               "kind": "oracle",
+               "sample": f"slice {l} of {args.workload}: {done} Newton-SuperLU steps, {cpu_wall:.1f} s"}
+
+    # dominant kernel family by total time in the timed sweeps
+    dom = max(("smoother_spmv_fine", "vanka_update_fine", "krylov_spmv_fine"), key=lambda f: fams[f][1])
+    dn, dms, dby = fams[dom]
+    achieved = dby / (dms * 1e-3) / 1e9 if dms > 0 else None
+    out = {
+        "metric": "fine-propagator dof*steps/s, batched slices (FP64 oracle-gated); HBM GB/s of the dominant kernel",
+        "value": value,
+        "unit": "dof*steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == "fp64" else "f32-inner/f64-newton",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: 2d ALE-FSI channel+bar, {p['level']}-level-refined "
+                               f"{128 if p['level'] == 3 else 2 ** p['level'] * 16}x{2 ** p['level'] * 4} Q1, "
+                               f"{nd} unknowns, {N} slices x {m} steps of {p['k_fine']:.6g}",
+                   "slices": N, "steps_per_slice": m, "unknowns": nd, "precision": prec},
+        "newton_per_sweep": stats[-1][0], "krylov_per_sweep": stats[-1][1],
+        "sequential": seq,
+        "speedup_batched_vs_sequential": (value / seq["value"]) if seq else None,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
+                     "kernel": KERNEL_NAMES.get(dom, dom), "launches": dn,
+                     "mean_launch_us": 1e3 * dms / max(dn, 1), "bytes_per_launch": dby / max(dn, 1)},
+        "profiled_sweep_ms": 1e3 * prof_wall,
+        "kernels": {f: {"launches": v[0], "ms_per_sweep": v[1],
+                        "GBs": (v[2] / (v[1] * 1e-3) / 1e9) if v[1] > 0 else None} for f, v in fams.items()},
+        "accuracy": acc,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

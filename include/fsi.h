@@ -76,6 +76,10 @@ typedef struct {
   double newton_rtol;        /* stop when every field's update <= rtol * |field|_inf */
   double lin_rtol;           /* FGMRES relative tolerance of the row-scaled residual */
   int32_t max_batch;         /* largest number of slices per call */
+  int32_t precond_lag;       /* 0: rebuild the multigrid preconditioner (coarse operators, Vanka
+                                inverses, coarsest factorisation) at every Newton iteration;
+                                1: only at the first Newton iteration of each time step (the
+                                Krylov operator is the exact Jacobian either way) */
 } fsi_params;
 
 #define FSI_MAX_SLICES 1024

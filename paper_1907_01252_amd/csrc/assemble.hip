@@ -347,7 +347,7 @@ __global__ void k_gather_jacobian(Geom g, double k, const double* __restrict__ K
   if (n >= g.nn || (active && !active[b])) return;
   const int i = n % (g.nx + 1), j = n / (g.nx + 1);
   const double* ke = Ke + (size_t)b * NE * NE * g.ncell;
-  S* jb = J + (size_t)b * NSLOT * BLK * g.nn;
+  S* jb = J + (size_t)b * jslice(g.nn);
   const uint8_t m = g.dmask[n];
   double rmax[NC] = {0, 0, 0, 0, 0};
   for (int dy = -1; dy <= 1; ++dy)
@@ -375,7 +375,7 @@ __global__ void k_gather_jacobian(Geom g, double k, const double* __restrict__ K
         for (int c = 0; c < NC; ++c) rmax[r] = fmax(rmax[r], fabs(blk[NC * r + c]));
       }
       const int s = slot_of(dx, dy);
-      for (int e = 0; e < BLK; ++e) jb[((size_t)s * BLK + e) * g.nn + n] = (S)blk[e];
+      for (int e = 0; e < BLK; ++e) jb[jidx(n, s, e)] = (S)blk[e];
     }
   if (!(m & DM_P)) {
     double pm = 0.0;

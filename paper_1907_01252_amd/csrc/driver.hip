@@ -5,6 +5,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -51,13 +52,24 @@ struct Level {
   }
 };
 
+// profiled kernel families (HIP events around each launch while enabled)
+enum Fam {
+  F_SMOOTH_SPMV = 0,   // residual SpMV inside the Vanka smoother, finest level
+  F_GMRES_SPMV = 1,    // Jacobian product of the Krylov iteration, finest level
+  F_JAC = 2,           // element Jacobian, all levels
+  F_RES = 3,           // residual assembly
+  F_VANKA_UPD = 4,     // Vanka patch update, finest level
+  F_COARSE_LEV = 5,    // smoother kernels on the coarser levels
+  F_COARSE_SOLVE = 6,  // coarsest-level dense solve
+  F_NFAM = 7
+};
 struct Prof {
   bool on = false;
   std::vector<hipEvent_t> pool;
   size_t used = 0;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[4];
-  double bytes[4] = {0, 0, 0, 0};
-  int64_t launches[4] = {0, 0, 0, 0};
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[F_NFAM];
+  double bytes[F_NFAM] = {};
+  int64_t launches[F_NFAM] = {};
 };
 
 }  // namespace
@@ -71,7 +83,17 @@ struct fsi_problem {
   size_t ssz = 8;        // sizeof(S)
   int R = 30;
   // finest-level Newton data (double)
-  double *U = nullptr, *Uold = nullptr, *Res = nullptr, *Re = nullptr, *Ke = nullptr, *tdev = nullptr;
+  double *U = nullptr, *Uold = nullptr, *Uprev = nullptr, *Res = nullptr, *Re = nullptr, *Ke = nullptr,
+         *tdev = nullptr;
+  // V-cycle replay graph (captured per batch size and step size)
+  hipGraphExec_t vc_exec = nullptr;
+  int vc_B = -1;
+  double vc_k = -1.0;
+  bool vc_mixed = false;
+  bool use_graphs = true;
+  // library-owned stream for the propagators (capturable; ordered after the caller's stream)
+  hipStream_t ist = nullptr;
+  hipEvent_t iev = nullptr;
   int *nact = nullptr;   // Newton-active slices (device)
   int *gact = nullptr;   // FGMRES-active slices (device)
   int *flag = nullptr;
@@ -80,8 +102,9 @@ struct fsi_problem {
   double *H = nullptr, *hcol = nullptr, *hcol2 = nullptr, *cs = nullptr, *sn = nullptr, *gv = nullptr,
          *res = nullptr, *beta0 = nullptr, *beta = nullptr, *ycoef = nullptr, *partial = nullptr;
   int *gstate = nullptr, *ncol = nullptr;
-  // coarsest level block LU
-  double *cDinv = nullptr, *cW = nullptr, *cL = nullptr;
+  // coarsest level block LU and explicit inverse
+  double *cDinv = nullptr, *cW = nullptr, *cL = nullptr, *cY = nullptr;
+  void* cAinv = nullptr;
   int cbs = 0, cnsb = 0;
   // Newton norms
   double *npart = nullptr, *nmax = nullptr;
@@ -283,7 +306,7 @@ fsi_status build_level(fsi_problem* pb, int l) {
   CHK(dalloc(pb, &L.U, (size_t)B * L.nn * NC));
   CHK(dalloc(pb, &L.Uo, (size_t)B * L.nn * NC));
   CHK(dalloc(pb, &L.Dsc, (size_t)B * L.nn * NC));
-  CHK(dalloc_bytes(pb, &L.J, (size_t)B * NSLOT * BLK * L.nn * ss));
+  CHK(dalloc_bytes(pb, &L.J, (size_t)B * jslice(L.nn) * ss));
   if (l >= 1) CHK(dalloc_bytes(pb, &L.Ainv, (size_t)B * NE * NE * L.ncell * ss));
   CHK(dalloc_bytes(pb, &L.x_, (size_t)B * L.nn * NC * ss));
   CHK(dalloc_bytes(pb, &L.b_, (size_t)B * L.nn * NC * ss));
@@ -337,7 +360,7 @@ fsi_status residual(fsi_problem* pb, int B, const StepPar& sp, const double* U, 
   Level& F = pb->lev[pb->nlev - 1];
   const Geom g = F.geom();
   {
-    ProfScope ps(pb, 3, st, (double)B * (F.nn * NC * 8.0 * 3 + F.ncell * NE * 8.0 * 2));
+    ProfScope ps(pb, F_RES, st, (double)B * (F.nn * NC * 8.0 * 3 + F.ncell * NE * 8.0 * 2));
     k_elem_residual<<<grid1(g.ncell, B), TPB, 0, st>>>(g, sp, U, Uo, pb->Re, act);
     k_gather_residual<<<grid1(g.nn, B), TPB, 0, st>>>(g, sp, pb->Re, U, pb->tdev, R, act);
   }
@@ -345,10 +368,14 @@ fsi_status residual(fsi_problem* pb, int B, const StepPar& sp, const double* U, 
   return FSI_OK;
 }
 
+// Jacobian of the finest level (always) and, when precond is set, the multigrid
+// hierarchy: injected coarse states, coarse-level Jacobians, Vanka inverses and
+// the coarsest-level inverse.
 template <class S>
-fsi_status assemble_levels(fsi_problem* pb, int B, const StepPar& sp, const int* act, hipStream_t st) {
+fsi_status assemble_levels(fsi_problem* pb, int B, const StepPar& sp, const int* act, hipStream_t st,
+                           bool precond = true) {
   const int L = pb->nlev - 1;
-  for (int l = L; l >= 0; --l) {
+  for (int l = L; l >= (precond ? 0 : L); --l) {
     Level& lv = pb->lev[l];
     const Geom g = lv.geom();
     const double* U = (l == L) ? pb->U : lv.U;
@@ -361,47 +388,67 @@ fsi_status assemble_levels(fsi_problem* pb, int B, const StepPar& sp, const int*
       k_inject<<<grid1(g.nn, B), TPB, 0, st>>>(g, f.geom(), Uof, lv.Uo, B);
     }
     {
-      ProfScope ps(pb, 2, st, (double)B * (g.ncell * NE * NE * 8.0 + 2.0 * g.nn * NC * 8));
+      ProfScope ps(pb, F_JAC, st, (double)B * (g.ncell * NE * NE * 8.0 + 2.0 * g.nn * NC * 8));
       k_elem_jacobian<false><<<dim3((g.ncell + 127) / 128, B), 128, 0, st>>>(g, sp, U, Uo, pb->Ke, act);
     }
     k_gather_jacobian<S><<<grid1(g.nn, B), TPB, 0, st>>>(g, sp.k, pb->Ke, (S*)lv.J, lv.Dsc, act);
+    if (!precond) break;
     if (l >= 1) {
       k_vanka_factor<S><<<dim3((g.ncell * 32 + TPB - 1) / TPB, B), TPB, 0, st>>>(g, sp.k, (const S*)lv.J,
                                                                               (S*)lv.Ainv, act);
     } else {
       const size_t lds = (size_t)3 * pb->cbs * pb->cbs * sizeof(double);
-      k_coarse_factor<S><<<B, TPB, lds, st>>>(g, sp.k, (const S*)lv.J, pb->cbs, pb->cnsb, pb->cDinv, pb->cW, pb->cL,
-                                              act);
+      const int n0 = g.nn * NC;
+      k_coarse_factor<S><<<B, 64, lds, st>>>(g, sp.k, (const S*)lv.J, pb->cbs, pb->cnsb, pb->cDinv, pb->cW, pb->cL,
+                                             act);
+      k_coarse_inverse<<<dim3((n0 + 63) / 64, B), 64, 0, st>>>(g, pb->cbs, pb->cnsb, pb->cDinv, pb->cW, pb->cL, pb->cY,
+                                                              act);
+      k_coarse_inverse_pack<S><<<dim3(128, B), TPB, 0, st>>>(g, pb->cbs, pb->cnsb, pb->cY, (S*)pb->cAinv, act);
     }
     HIPCHK(hipGetLastError());
   }
   return FSI_OK;
 }
 
+// y = D (b - A x) (or D A x): thread-per-node kernel on large grids, thread-per-row
+// kernel (five times the threads, shorter dependency chains) on small ones.
+template <class S>
+void spmv(const Geom& g, int B, double k, const S* J, const S* x, const S* b, const double* D, S* y, const int* act,
+          hipStream_t st) {
+  if ((size_t)g.nn * B >= 65536)
+    k_spmv_node<S><<<grid1(g.nn, B), TPB, 0, st>>>(g, k, J, x, b, D, y, act);
+  else
+    k_spmv<S><<<grid1(NC * g.nn, B), TPB, 0, st>>>(g, k, J, x, b, D, y, act);
+}
+
 // ------------------------------------------------------------ multigrid
 template <class S>
-void smooth(fsi_problem* pb, int l, int B, double k, int sweeps, bool zero_first, S* x, S* tmp, const S* b,
-            const int* act, hipStream_t st) {
+void smooth(fsi_problem* pb, int l, int B, double k, int sweeps, bool zero_first, S* x, const S* b, const int* act,
+            hipStream_t st) {
   Level& lv = pb->lev[l];
   const Geom g = lv.geom();
   const S om = (S)pb->p.vanka_omega;
-  S* cur = x;
-  S* oth = tmp;
+  const bool fine = l == pb->nlev - 1;
+  const ColorLayout CL = color_layout(g.nx, g.ny);
+  S* r = (S*)lv.r_;
   for (int s = 0; s < sweeps; ++s)
     for (int c = 0; c < 4; ++c) {
-      const int cx = c & 1, cy = c >> 1;
-      const int nb = ((g.nx + cx) / 2 + 1) * ((g.ny + cy) / 2 + 1);
-      const int zero = (zero_first && s == 0 && c == 0) ? 1 : 0;
-      {
-        const double per = (double)NSLOT * BLK * g.nn * sizeof(S) + (double)NE * NE * g.ncell / 4 * sizeof(S) +
-                           3.0 * g.nn * NC * sizeof(S);
-        ProfScope ps(pb, 0, st, (double)B * per);
-        k_vanka_pass<S><<<dim3((nb * 4 + TPB - 1) / TPB, B), TPB, 0, st>>>(g, k, c, om, zero, (const S*)lv.J,
-                                                                          (const S*)lv.Ainv, b, cur, oth, act);
+      const bool zero = zero_first && s == 0 && c == 0;
+      const int nc = CL.ncx[c] * CL.ncy[c];
+      if (!zero) {
+        const double by = (double)B * ((double)NSLOT * BLK * g.nn * sizeof(S) + 3.0 * g.nn * NC * sizeof(S)) +
+                          (double)NPST * g.nn * 8.0;
+        ProfScope ps(pb, fine ? F_SMOOTH_SPMV : F_COARSE_LEV, st, by);
+        spmv<S>(g, B, k, (const S*)lv.J, x, b, nullptr, r, act, st);
       }
-      std::swap(cur, oth);
+      {
+        const double by = (double)B * ((double)NE * NE * nc * sizeof(S) + 3.0 * nc * NE * sizeof(S));
+        ProfScope ps(pb, fine ? F_VANKA_UPD : F_COARSE_LEV, st, by);
+        const int nthr = std::max(nc * NE, zero ? g.nn : 0);
+        k_vanka_update<S><<<dim3((nthr + TPB - 1) / TPB, B), TPB, 0, st>>>(g, c, om, zero ? 1 : 0,
+                                                                          (const S*)lv.Ainv, zero ? b : r, x, act);
+      }
     }
-  // 4 passes per sweep: the result is back in x
 }
 
 template <class S>
@@ -414,16 +461,17 @@ void vcycle(fsi_problem* pb, int B, double k, const S* rhs, S* out, const int* a
     Level& lc = pb->lev[l - 1];
     const S* b = (l == L) ? rhs : (const S*)lv.b_;
     S* x = (l == L) ? out : (S*)lv.x_;
-    smooth<S>(pb, l, B, k, nu, true, x, (S*)lv.t_, b, act, st);
+    smooth<S>(pb, l, B, k, nu, true, x, b, act, st);
     const Geom g = lv.geom();
-    k_spmv<S><<<grid1(g.nn, B), TPB, 0, st>>>(g, k, (const S*)lv.J, x, b, nullptr, (S*)lv.r_, act);
+    spmv<S>(g, B, k, (const S*)lv.J, x, b, nullptr, (S*)lv.r_, act, st);
     k_restrict<S><<<grid1(lc.nn, B), TPB, 0, st>>>(lc.geom(), g, (const S*)lv.r_, (S*)lc.b_, act);
   }
   {
     Level& l0 = pb->lev[0];
-    const size_t lds = (size_t)(pb->cnsb * pb->cbs + pb->cbs) * sizeof(double);
-    k_coarse_solve<S><<<B, TPB, lds, st>>>(l0.geom(), pb->cbs, pb->cnsb, pb->cDinv, pb->cW, pb->cL,
-                                           (const S*)l0.b_, (S*)l0.x_, act);
+    const int n0 = l0.nn * NC;
+    ProfScope ps(pb, F_COARSE_SOLVE, st, (double)B * ((double)n0 * n0 + 2.0 * n0) * sizeof(S));
+    k_coarse_gemv<S><<<dim3((n0 + 63) / 64, B), TPB, 0, st>>>(l0.geom(), (const S*)pb->cAinv, (const S*)l0.b_,
+                                                                    (S*)l0.x_, act);
   }
   for (int l = 1; l <= L; ++l) {
     Level& lv = pb->lev[l];
@@ -431,8 +479,38 @@ void vcycle(fsi_problem* pb, int B, double k, const S* rhs, S* out, const int* a
     const S* b = (l == L) ? rhs : (const S*)lv.b_;
     S* x = (l == L) ? out : (S*)lv.x_;
     k_prolong_add<S><<<grid1(lv.nn, B), TPB, 0, st>>>(lv.geom(), lc.geom(), (const S*)lc.x_, x, act);
-    smooth<S>(pb, l, B, k, nu, false, x, (S*)lv.t_, b, act, st);
+    smooth<S>(pb, l, B, k, nu, false, x, b, act, st);
   }
+}
+
+// One V-cycle on the finest-level buffers (rhs = pb->tmp, out = pb->w), replayed
+// from a captured graph when no per-kernel profiling is requested.  The graph
+// depends on the batch size and the step size; pointers are fixed per problem.
+template <class S>
+fsi_status vcycle_run(fsi_problem* pb, int B, double k, hipStream_t st) {
+  const bool mixed = sizeof(S) == 4;
+  if (!pb->use_graphs || pb->prof.on) {
+    vcycle<S>(pb, B, k, (const S*)pb->tmp, (S*)pb->w, pb->gact, st);
+    HIPCHK(hipGetLastError());
+    return FSI_OK;
+  }
+  if (!pb->vc_exec || pb->vc_B != B || pb->vc_k != k || pb->vc_mixed != mixed) {
+    if (pb->vc_exec) {
+      HIPCHK(hipGraphExecDestroy(pb->vc_exec));
+      pb->vc_exec = nullptr;
+    }
+    hipGraph_t graph;
+    HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    vcycle<S>(pb, B, k, (const S*)pb->tmp, (S*)pb->w, pb->gact, st);
+    HIPCHK(hipStreamEndCapture(st, &graph));
+    HIPCHK(hipGraphInstantiate(&pb->vc_exec, graph, nullptr, nullptr, 0));
+    HIPCHK(hipGraphDestroy(graph));
+    pb->vc_B = B;
+    pb->vc_k = k;
+    pb->vc_mixed = mixed;
+  }
+  HIPCHK(hipGraphLaunch(pb->vc_exec, st));
+  return FSI_OK;
 }
 
 // ------------------------------------------------------------ FGMRES
@@ -452,7 +530,7 @@ fsi_status fgmres(fsi_problem* pb, int B, double k, std::vector<int>& kits, hipS
   S* w = (S*)pb->w;
   S* xs = (S*)pb->xs;
   S* tmp = (S*)pb->tmp;
-  const int chunk = 8192;
+  const int chunk = 2048;
   const int nchunk = (n + chunk - 1) / chunk;
   const double tol = pb->p.lin_rtol;
   const dim3 gb((B + 63) / 64), tb(64);
@@ -466,7 +544,7 @@ fsi_status fgmres(fsi_problem* pb, int B, double k, std::vector<int>& kits, hipS
       k_scale_rhs<S><<<grid1(n, B), TPB, 0, st>>>(n, pb->Res, F.Dsc, V, vb, pb->gact);
     } else {
       k_scale_rhs<S><<<grid1(n, B), TPB, 0, st>>>(n, pb->Res, nullptr, tmp, (size_t)n, pb->gact);
-      k_spmv<S><<<grid1(F.nn, B), TPB, 0, st>>>(g, k, (const S*)F.J, xs, tmp, F.Dsc, w, pb->gact);
+      spmv<S>(g, B, k, (const S*)F.J, xs, tmp, F.Dsc, w, pb->gact, st);
       k_scale<S><<<grid1(n, B), TPB, 0, st>>>(n, w, (size_t)n, V, vb, nullptr, 0, 2, pb->gact);
     }
     k_multidot<S><<<dim3(nchunk, B), RED_T, 0, st>>>(n, 1, V, vb, V, vb, 0, chunk, pb->partial, nchunk, pb->gact);
@@ -486,13 +564,14 @@ fsi_status fgmres(fsi_problem* pb, int B, double k, std::vector<int>& kits, hipS
       S* Zj = Z + (size_t)j * n;
       // Z_j = M^{-1} (V_j / D);  a = D J Z_j  (the new Arnoldi vector a lives in tmp)
       k_unscale<S><<<grid1(n, B), TPB, 0, st>>>(n, Vj, vb, F.Dsc, tmp, pb->gact);
-      vcycle<S>(pb, B, k, tmp, w, pb->gact, st);
+      CHK(vcycle_run<S>(pb, B, k, st));
       k_scale<S><<<grid1(n, B), TPB, 0, st>>>(n, w, (size_t)n, Zj, zb, nullptr, 0, 2, pb->gact);
       S* a = tmp;
       {
-        ProfScope ps(pb, 1, st,
-                     (double)B * ((double)NSLOT * BLK * F.nn * sizeof(S) + 2.0 * n * sizeof(S) + n * 8.0));
-        k_spmv<S><<<grid1(F.nn, B), TPB, 0, st>>>(g, k, (const S*)F.J, w, nullptr, F.Dsc, a, pb->gact);
+        ProfScope ps(pb, F_GMRES_SPMV, st,
+                     (double)B * ((double)NSLOT * BLK * F.nn * sizeof(S) + 2.0 * n * sizeof(S) + n * 8.0) +
+                         (double)NPST * F.nn * 8.0);
+        spmv<S>(g, B, k, (const S*)F.J, w, nullptr, F.Dsc, a, pb->gact, st);
       }
       // classical Gram-Schmidt, twice
       k_multidot<S><<<dim3(nchunk, B), RED_T, 0, st>>>(n, j + 1, a, (size_t)n, V, vb, (size_t)n, chunk, pb->partial,
@@ -547,15 +626,14 @@ template <class S>
 fsi_status newton_solve_step(fsi_problem* pb, int B, const StepPar& sp, std::vector<int>& hact, RunStats& rs,
                              hipStream_t st) {
   Level& F = pb->lev[pb->nlev - 1];
-  const Geom g = F.geom();
   const int nn = F.nn;
   const int maxit = pb->p.newton_maxit;
-  std::vector<double> prev(B, -1.0), hm((size_t)B * 6);
+  std::vector<double> prev((size_t)B * 3, -1.0), hm((size_t)B * 6);
   std::vector<int> nact(hact);
   for (int it = 1; it <= maxit; ++it) {
     HIPCHK(hipMemcpyAsync(pb->nact, nact.data(), B * sizeof(int), hipMemcpyHostToDevice, st));
     CHK(residual(pb, B, sp, pb->U, pb->Uold, pb->Res, pb->nact, st));
-    CHK(assemble_levels<S>(pb, B, sp, pb->nact, st));
+    CHK(assemble_levels<S>(pb, B, sp, pb->nact, st, it == 1 || pb->p.precond_lag == 0));
     fsi_status ls = fgmres<S>(pb, B, sp.k, rs.krylov, st);
     if (ls != FSI_OK && ls != FSI_ERR_LINEAR) return ls;
     k_newton_update<S><<<dim3(pb->nchunk_n, B), RED_T, 0, st>>>(nn, pb->U, (const S*)pb->xs, pb->chunk_n, pb->npart,
@@ -568,12 +646,19 @@ fsi_status newton_solve_step(fsi_problem* pb, int B, const StepPar& sp, std::vec
     for (int b = 0; b < B; ++b) {
       if (!nact[b]) continue;
       rs.newton[b] += 1;
-      double worst = 0.0;
+      // per field: relative size of the update just applied, and an estimate of
+      // the error left after it from the observed contraction (d_k / d_{k-1}) d_k
+      double worst = 0.0, est = 0.0;
       bool finite = true;
       for (int f = 0; f < 3; ++f) {
         const double du = hm[(size_t)b * 6 + f], un = hm[(size_t)b * 6 + 3 + f];
         if (!std::isfinite(du) || !std::isfinite(un)) finite = false;
-        worst = std::max(worst, un > 0.0 ? du / un : du);
+        const double rel = un > 0.0 ? du / un : du;
+        worst = std::max(worst, rel);
+        const double pf = prev[(size_t)b * 3 + f];
+        const double theta = (pf > 0.0) ? rel / pf : 1.0;
+        est = std::max(est, theta < 1.0 ? theta * rel / (1.0 - theta) : 1e300);
+        prev[(size_t)b * 3 + f] = rel;
       }
       if (!finite) {
         rs.status[b] = FSI_ERR_NONFINITE;
@@ -581,13 +666,11 @@ fsi_status newton_solve_step(fsi_problem* pb, int B, const StepPar& sp, std::vec
         hact[b] = 0;
         continue;
       }
-      // converged, or stagnating at the round-off floor once the update is tiny
-      if (worst <= pb->p.newton_rtol || (prev[b] >= 0.0 && worst <= 1e-9 && worst > 0.5 * prev[b])) {
+      if (worst <= pb->p.newton_rtol || est <= pb->p.newton_rtol) {
         nact[b] = 0;
       } else {
         any = true;
       }
-      prev[b] = worst;
     }
     if (!any) return FSI_OK;
   }
@@ -631,7 +714,11 @@ fsi_status propagate(fsi_problem* pb, int B, const double* t0, double slice_len,
     for (int b = 0; b < B; ++b) th[b] = t0[b] + n * k;
     HIPCHK(hipMemcpyAsync(pb->tdev, th.data(), B * sizeof(double), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(pb->nact, hact.data(), B * sizeof(int), hipMemcpyHostToDevice, st));
+    if (n >= 2)
+      HIPCHK(hipMemcpyAsync(pb->Uprev, pb->Uold, (size_t)B * ndof * sizeof(double), hipMemcpyDeviceToDevice, st));
     HIPCHK(hipMemcpyAsync(pb->Uold, pb->U, (size_t)B * ndof * sizeof(double), hipMemcpyDeviceToDevice, st));
+    // Newton guess: the old state (first step) or the linear extrapolation of the last two
+    if (n >= 2) k_extrapolate<<<dim3(64, B), TPB, 0, st>>>(ndof, pb->U, pb->Uold, pb->Uprev, pb->nact);
     k_apply_dirichlet<<<grid1(F.nn, B), TPB, 0, st>>>(g, sp, pb->U, pb->tdev, pb->nact);
     HIPCHK(hipGetLastError());
     CHK(newton_solve_step<S>(pb, B, sp, hact, rs, st));
@@ -662,10 +749,15 @@ fsi_status propagate(fsi_problem* pb, int B, const double* t0, double slice_len,
 }
 
 fsi_status run_propagate(fsi_problem* pb, int B, const double* t0, double slice_len, int nsteps, const double* U_in,
-                         double* U_out, fsi_stats* stats, hipStream_t st) {
+                         double* U_out, fsi_stats* stats, hipStream_t caller) {
   if (!pb || !t0 || !U_in || !U_out || B <= 0 || B > pb->Bmax || nsteps <= 0 || !(slice_len > 0.0))
     return FSI_ERR_ARG;
   if (stats) std::memset(stats, 0, sizeof(fsi_stats));
+  // work on the library stream after everything already queued on the caller's stream;
+  // the call returns after completion, so the caller's later work sees the results
+  HIPCHK(hipEventRecord(pb->iev, caller));
+  HIPCHK(hipStreamWaitEvent(pb->ist, pb->iev, 0));
+  hipStream_t st = pb->ist;
   return pb->mixed ? propagate<float>(pb, B, t0, slice_len, nsteps, U_in, U_out, stats, st)
                    : propagate<double>(pb, B, t0, slice_len, nsteps, U_in, U_out, stats, st);
 }
@@ -691,6 +783,10 @@ const char* fsi_status_string(fsi_status s) {
 
 void fsi_destroy(fsi_problem* pb) {
   if (!pb) return;
+  if (pb->vc_exec) (void)hipGraphExecDestroy(pb->vc_exec);
+  if (pb->ist) (void)hipStreamSynchronize(pb->ist);
+  if (pb->ist) (void)hipStreamDestroy(pb->ist);
+  if (pb->iev) (void)hipEventDestroy(pb->iev);
   for (void* q : pb->allocs) (void)hipFree(q);
   for (hipEvent_t e : pb->prof.pool) (void)hipEventDestroy(e);
   delete pb;
@@ -702,7 +798,8 @@ fsi_status fsi_setup(const fsi_params* prm, fsi_problem** out) {
   const fsi_params& p = *prm;
   if (p.dim != 2 || p.level < 1 || p.level > MAXLEV - 2 || p.max_batch < 1 || p.max_batch > FSI_MAX_SLICES ||
       p.gmres_restart < 1 || p.gmres_restart > 63 || p.newton_maxit < 1 || p.vanka_sweeps < 1 ||
-      p.gmres_maxit < 1 || (p.precision != FSI_FP64 && p.precision != FSI_MIXED))
+      p.gmres_maxit < 1 || (p.precision != FSI_FP64 && p.precision != FSI_MIXED) ||
+      (p.precond_lag != 0 && p.precond_lag != 1))
     return FSI_ERR_ARG;
   for (int a = 0; a < 2; ++a) {
     if (p.nseg[a] < 1 || p.nseg[a] > 4) return FSI_ERR_ARG;
@@ -718,6 +815,11 @@ fsi_status fsi_setup(const fsi_params* prm, fsi_problem** out) {
   pb->ssz = pb->mixed ? sizeof(float) : sizeof(double);
   pb->R = p.gmres_restart;
   pb->nlev = p.level + 1;
+  {
+    // FSI_GRAPHS=0 replays nothing from graphs (every kernel launched directly)
+    const char* e = std::getenv("FSI_GRAPHS");
+    pb->use_graphs = !(e && e[0] == '0');
+  }
   fsi_status s = FSI_OK;
   for (int l = 0; l < pb->nlev && s == FSI_OK; ++l) s = build_level(pb, l);
   if (s != FSI_OK) { fsi_destroy(pb); return s; }
@@ -731,11 +833,12 @@ fsi_status fsi_setup(const fsi_params* prm, fsi_problem** out) {
   pb->nchunk_n = (F.nn + pb->chunk_n - 1) / pb->chunk_n;
   pb->cbs = 2 * (C.ny + 1) * NC;
   pb->cnsb = (C.nx + 1 + 1) / 2;
-  if (pb->cbs > 128 || (size_t)3 * pb->cbs * pb->cbs * sizeof(double) > 160 * 1024) { fsi_destroy(pb); return FSI_ERR_ARG; }
+  if (pb->cbs > 64 || C.nn * NC > 2048) { fsi_destroy(pb); return FSI_ERR_ARG; }
   const size_t cb2 = (size_t)pb->cbs * pb->cbs * pb->cnsb * B;
 #define A_(x) do { s = (x); if (s != FSI_OK) { fsi_destroy(pb); return s; } } while (0)
   A_(dalloc(pb, &pb->U, B * ndof));
   A_(dalloc(pb, &pb->Uold, B * ndof));
+  A_(dalloc(pb, &pb->Uprev, B * ndof));
   A_(dalloc(pb, &pb->Res, B * ndof));
   A_(dalloc(pb, &pb->Re, (size_t)B * NE * F.ncell));
   A_(dalloc(pb, &pb->Ke, (size_t)B * NE * NE * F.ncell));
@@ -758,12 +861,14 @@ fsi_status fsi_setup(const fsi_params* prm, fsi_problem** out) {
   A_(dalloc(pb, &pb->beta0, B));
   A_(dalloc(pb, &pb->beta, B));
   A_(dalloc(pb, &pb->ycoef, (size_t)B * 64));
-  A_(dalloc(pb, &pb->partial, (size_t)B * 64 * ((ndof + 8191) / 8192 + 1)));
+  A_(dalloc(pb, &pb->partial, (size_t)B * 64 * ((ndof + 2047) / 2048 + 1)));
   A_(dalloc(pb, &pb->gstate, B));
   A_(dalloc(pb, &pb->ncol, B));
   A_(dalloc(pb, &pb->cDinv, cb2));
   A_(dalloc(pb, &pb->cW, cb2));
   A_(dalloc(pb, &pb->cL, cb2));
+  A_(dalloc(pb, &pb->cY, (size_t)B * C.nn * NC * pb->cnsb * pb->cbs));
+  A_(dalloc_bytes(pb, &pb->cAinv, (size_t)B * C.nn * NC * C.nn * NC * ss));
   A_(dalloc(pb, &pb->npart, (size_t)B * 6 * pb->nchunk_n));
   A_(dalloc(pb, &pb->nmax, (size_t)B * 6));
 #undef A_
@@ -771,6 +876,11 @@ fsi_status fsi_setup(const fsi_params* prm, fsi_problem** out) {
                           3 * pb->cbs * pb->cbs * sizeof(double)) != hipSuccess ||
       hipFuncSetAttribute((const void*)k_coarse_factor<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
                           3 * pb->cbs * pb->cbs * sizeof(double)) != hipSuccess) {
+    fsi_destroy(pb);
+    return FSI_ERR_HIP;
+  }
+  if (hipStreamCreateWithFlags(&pb->ist, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&pb->iev, hipEventDisableTiming) != hipSuccess) {
     fsi_destroy(pb);
     return FSI_ERR_HIP;
   }
@@ -924,12 +1034,12 @@ fsi_status fsi_debug_jacobian_apply(fsi_problem* pb, int32_t B, const double* U,
   if (pb->mixed) {
     CHK(assemble_levels<float>(pb, B, sp, nullptr, st));
     k_convert<double, float><<<1024, TPB, 0, st>>>(B * ndof, X, (float*)pb->tmp);
-    k_spmv<float><<<grid1(F.nn, B), TPB, 0, st>>>(F.geom(), k, (const float*)F.J, (const float*)pb->tmp, nullptr,
+    k_spmv<float><<<grid1(NC * F.nn, B), TPB, 0, st>>>(F.geom(), k, (const float*)F.J, (const float*)pb->tmp, nullptr,
                                                   nullptr, (float*)pb->w, nullptr);
     k_convert<float, double><<<1024, TPB, 0, st>>>(B * ndof, (const float*)pb->w, Y);
   } else {
     CHK(assemble_levels<double>(pb, B, sp, nullptr, st));
-    k_spmv<double><<<grid1(F.nn, B), TPB, 0, st>>>(F.geom(), k, (const double*)F.J, X, nullptr, nullptr, Y, nullptr);
+    k_spmv<double><<<grid1(NC * F.nn, B), TPB, 0, st>>>(F.geom(), k, (const double*)F.J, X, nullptr, nullptr, Y, nullptr);
   }
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(st));
@@ -964,7 +1074,7 @@ fsi_status fsi_profile_enable(fsi_problem* pb, int32_t on) {
   pb->prof.on = on != 0;
   if (on) {
     pb->prof.used = 0;
-    for (int f = 0; f < 4; ++f) {
+    for (int f = 0; f < F_NFAM; ++f) {
       pb->prof.ev[f].clear();
       pb->prof.bytes[f] = 0;
       pb->prof.launches[f] = 0;
@@ -974,7 +1084,7 @@ fsi_status fsi_profile_enable(fsi_problem* pb, int32_t on) {
 }
 
 fsi_status fsi_profile_query(const fsi_problem* pb, int32_t which, int64_t* launches, double* ms, double* bytes) {
-  if (!pb || which < 0 || which > 3) return FSI_ERR_ARG;
+  if (!pb || which < 0 || which >= F_NFAM) return FSI_ERR_ARG;
   double tot = 0.0;
   for (auto& e : pb->prof.ev[which]) {
     float m = 0.f;

@@ -45,7 +45,35 @@ struct StepPar {
 
 // Neighbour slot of offset (dx, dy) in the 3x3 block stencil.
 __host__ __device__ inline int slot_of(int dx, int dy) { return (dx + 1) + 3 * (dy + 1); }
+
+// Jacobian storage: per slice, nodes are grouped in tiles of 64; a tile holds its
+// 9 x 25 block-stencil coefficients as 225 runs of 64 consecutive values, so one
+// wave streams one contiguous 225 x 64 array.
+constexpr int JT = 64;
+__host__ __device__ inline int nn_pad(int nn) { return (nn + JT - 1) / JT * JT; }
+__host__ __device__ inline size_t jslice(int nn) { return (size_t)NSLOT * BLK * nn_pad(nn); }
+__host__ __device__ inline size_t jidx(int node, int s, int e) {
+  return (size_t)(node / JT) * (NSLOT * BLK * JT) + (size_t)(s * BLK + e) * JT + (node % JT);
+}
 __host__ __device__ inline int pslot_of(int dx, int dy) { return (dx + 2) + 5 * (dy + 2); }
+
+// ------------------------------------------------------------ colour helpers
+// Cells of colour (cx, cy) = (ci & 1, cj & 1), stored colour by colour.
+struct ColorLayout {
+  int ncx[4], ncy[4], off[4];
+};
+__host__ __device__ inline ColorLayout color_layout(int nx, int ny) {
+  ColorLayout L;
+  int o = 0;
+  for (int c = 0; c < 4; ++c) {
+    const int cx = c & 1, cy = c >> 1;
+    L.ncx[c] = (nx - cx + 1) / 2;
+    L.ncy[c] = (ny - cy + 1) / 2;
+    L.off[c] = o;
+    o += L.ncx[c] * L.ncy[c];
+  }
+  return L;
+}
 
 // Ramp of the inflow: (1 - cos(pi t / t_r)) / 2 for t < t_r, then 1.
 __host__ __device__ inline double inflow_ramp(double t, double tr) {

@@ -19,10 +19,13 @@ template <class S>
 __global__ void k_spmv(Geom g, double k, const S* J, const S* x, const S* b, const double* Dsc, S* y,
                        const int* active);
 template <class S>
+__global__ void k_spmv_node(Geom g, double k, const S* J, const S* x, const S* b, const double* Dsc, S* y,
+                            const int* active);
+template <class S>
 __global__ void k_vanka_factor(Geom g, double k, const S* J, S* Ainv, const int* active);
 template <class S>
-__global__ void k_vanka_pass(Geom g, double k, int color, S omega, int zero_in, const S* J, const S* Ainv,
-                             const S* b, const S* x_in, S* x_out, const int* active);
+__global__ void k_vanka_update(Geom g, int color, S omega, int zero_in, const S* Ainv, const S* r, S* x,
+                               const int* active);
 template <class S>
 __global__ void k_restrict(Geom gc, Geom gf, const S* rf, S* bc, const int* active);
 template <class S>
@@ -30,9 +33,12 @@ __global__ void k_prolong_add(Geom gf, Geom gc, const S* xc, S* xf, const int* a
 template <class S>
 __global__ void k_coarse_factor(Geom g, double k, const S* J, int bsz, int nsb, double* Dinv, double* W, double* Lb,
                                 const int* active);
+__global__ void k_coarse_inverse(Geom g, int bsz, int nsb, const double* Dinv, const double* W, const double* Lb,
+                                 double* Ainv0, const int* active);
 template <class S>
-__global__ void k_coarse_solve(Geom g, int bsz, int nsb, const double* Dinv, const double* W, const double* Lb,
-                               const S* bvec, S* xvec, const int* active);
+__global__ void k_coarse_inverse_pack(Geom g, int bsz, int nsb, const double* Ainv0, S* AinvS, const int* active);
+template <class S>
+__global__ void k_coarse_gemv(Geom g, const S* AinvS, const S* bvec, S* xvec, const int* active);
 template <class S>
 __global__ void k_multidot(int n, int nv, const S* X, size_t sxb, const S* Y, size_t syb, size_t syi, int chunk,
                            double* partial, int nchunk, const int* active);
@@ -61,6 +67,7 @@ __global__ void k_newton_update(int nn, double* U, const S* dx, int chunk, doubl
                                 const int* active);
 __global__ void k_max_partials(int nchunk, const double* part, double* out, int B);
 __global__ void k_nonfinite(size_t n, const double* X, int* flag);
+__global__ void k_extrapolate(size_t n, double* U, const double* Uo, const double* Up, const int* active);
 __global__ void k_parareal_update(size_t n, const double* Cn, const double* Fv, const double* Cold, double* out);
 __global__ void k_change_norms(int nn, const double* A, const double* Bv, int chunk, double* part, int nchunk);
 template <class S>

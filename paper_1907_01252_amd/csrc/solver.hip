@@ -13,15 +13,17 @@ namespace fsi {
 // y = D (b - A x)        (b != nullptr)
 // with A = J (3x3 block stencil of 5x5 blocks) + k * S_p (5x5 pressure stencil).
 // D = Dsc (row scaling) when given, else identity.
+// Variant with one thread per node (all five rows): fewer, longer threads, the
+// better mapping when the grid is large enough to fill the GPU.
 template <class S>
-__global__ void __launch_bounds__(256) k_spmv(Geom g, double k, const S* __restrict__ J, const S* __restrict__ x,
-                                              const S* __restrict__ b, const double* __restrict__ Dsc,
-                                              S* __restrict__ y, const int* __restrict__ active) {
+__global__ void __launch_bounds__(256) k_spmv_node(Geom g, double k, const S* __restrict__ J, const S* __restrict__ x,
+                                                   const S* __restrict__ b, const double* __restrict__ Dsc,
+                                                   S* __restrict__ y, const int* __restrict__ active) {
   const int bs = blockIdx.y;
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= g.nn || (active && !active[bs])) return;
   const int i = n % (g.nx + 1), j = n / (g.nx + 1);
-  const S* jb = J + (size_t)bs * NSLOT * BLK * g.nn;
+  const S* jb = J + (size_t)bs * jslice(g.nn);
   const S* xb = x + (size_t)bs * g.nn * NC;
   S acc[NC] = {0, 0, 0, 0, 0};
 #pragma unroll
@@ -36,7 +38,7 @@ __global__ void __launch_bounds__(256) k_spmv(Geom g, double k, const S* __restr
 #pragma unroll
     for (int r = 0; r < NC; ++r)
 #pragma unroll
-      for (int c = 0; c < NC; ++c) acc[r] += jb[((size_t)s * BLK + NC * r + c) * g.nn + n] * xs[c];
+      for (int c = 0; c < NC; ++c) acc[r] += jb[jidx(n, s, NC * r + c)] * xs[c];
   }
   if (!(g.dmask[n] & DM_P)) {
     S ap = 0;
@@ -48,32 +50,50 @@ __global__ void __launch_bounds__(256) k_spmv(Geom g, double k, const S* __restr
     }
     acc[4] += (S)k * ap;
   }
-  S* yo = y + ((size_t)bs * g.nn + n) * NC;
-  const S* bb = b ? b + ((size_t)bs * g.nn + n) * NC : nullptr;
-  const double* d = Dsc ? Dsc + ((size_t)bs * g.nn + n) * NC : nullptr;
+  const size_t o = ((size_t)bs * g.nn + n) * NC;
 #pragma unroll
   for (int r = 0; r < NC; ++r) {
-    S v = bb ? bb[r] - acc[r] : acc[r];
-    yo[r] = d ? (S)(d[r] * (double)v) : v;
+    S v = b ? b[o + r] - acc[r] : acc[r];
+    y[o + r] = Dsc ? (S)(Dsc[o + r] * (double)v) : v;
   }
 }
 
-// ------------------------------------------------------------ colour helpers
-// Cells of colour (cx, cy) = (ci & 1, cj & 1), stored colour by colour.
-struct ColorLayout {
-  int ncx[4], ncy[4], off[4];
-};
-__host__ __device__ inline ColorLayout color_layout(int nx, int ny) {
-  ColorLayout L;
-  int o = 0;
-  for (int c = 0; c < 4; ++c) {
-    const int cx = c & 1, cy = c >> 1;
-    L.ncx[c] = (nx - cx + 1) / 2;
-    L.ncy[c] = (ny - cy + 1) / 2;
-    L.off[c] = o;
-    o += L.ncx[c] * L.ncy[c];
+template <class S>
+__global__ void __launch_bounds__(256) k_spmv(Geom g, double k, const S* __restrict__ J, const S* __restrict__ x,
+                                              const S* __restrict__ b, const double* __restrict__ Dsc,
+                                              S* __restrict__ y, const int* __restrict__ active) {
+  // one thread per (row component r, node n): t = r * nn + n, so a wave streams
+  // 64 consecutive nodes of one coefficient run of the tiled layout
+  const int bs = blockIdx.y;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= NC * g.nn || (active && !active[bs])) return;
+  const int r = t / g.nn, n = t - r * g.nn;
+  const int i = n % (g.nx + 1), j = n / (g.nx + 1);
+  const S* jb = J + (size_t)bs * jslice(g.nn);
+  const S* xb = x + (size_t)bs * g.nn * NC;
+  S acc = 0;
+#pragma unroll
+  for (int s = 0; s < NSLOT; ++s) {
+    const int dx = s % 3 - 1, dy = s / 3 - 1;
+    const int ii = i + dx, jj = j + dy;
+    if (ii < 0 || jj < 0 || ii > g.nx || jj > g.ny) continue;
+    const S* xv = xb + (size_t)(ii + (g.nx + 1) * jj) * NC;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc += jb[jidx(n, s, NC * r + c)] * xv[c];
   }
-  return L;
+  if (r == 4 && !(g.dmask[n] & DM_P)) {
+    S ap = 0;
+    for (int q = 0; q < NPST; ++q) {
+      const int dx = q % 5 - 2, dy = q / 5 - 2;
+      const int ii = i + dx, jj = j + dy;
+      if (ii < 0 || jj < 0 || ii > g.nx || jj > g.ny) continue;
+      ap += (S)g.pst[(size_t)q * g.nn + n] * xb[(size_t)(ii + (g.nx + 1) * jj) * NC + 4];
+    }
+    acc += (S)k * ap;
+  }
+  const size_t o = ((size_t)bs * g.nn + n) * NC + r;
+  S v = b ? b[o] - acc : acc;
+  y[o] = Dsc ? (S)(Dsc[o] * (double)v) : v;
 }
 
 // ------------------------------------------------------- Vanka patch inverse
@@ -95,14 +115,14 @@ __global__ void __launch_bounds__(256) k_vanka_factor(Geom g, double k, const S*
 #pragma unroll
   for (int c = 0; c < 2 * NE; ++c) row[c] = 0.0;
   if (live && lane < NE) {
-    const S* jb = J + (size_t)bs * NSLOT * BLK * g.nn;
+    const S* jb = J + (size_t)bs * jslice(g.nn);
     const bool pst_row = (rc == 4) && !(g.dmask[na] & DM_P);
 #pragma unroll
     for (int bb = 0; bb < NL; ++bb) {
       const int dx = (bb & 1) - (a & 1), dy = (bb >> 1) - (a >> 1);
       const int s = slot_of(dx, dy);
 #pragma unroll
-      for (int c = 0; c < NC; ++c) row[NC * bb + c] = (double)jb[((size_t)s * BLK + NC * rc + c) * g.nn + na];
+      for (int c = 0; c < NC; ++c) row[NC * bb + c] = (double)jb[jidx(na, s, NC * rc + c)];
       if (pst_row) row[NC * bb + 4] += k * g.pst[(size_t)pslot_of(dx, dy) * g.nn + na];
     }
 #pragma unroll
@@ -141,96 +161,48 @@ __global__ void __launch_bounds__(256) k_vanka_factor(Geom g, double k, const S*
   }
 }
 
-// ------------------------------------------------------ colored Vanka pass
-// One multiplicative pass over the cells of one colour: for every cell of the
-// colour, r_P = (b - A x_in) on the patch, x_out[P] = x_in[P] + omega Ainv r_P.
-// Patches of one colour do not overlap, so all of them update at once from the
-// same x_in; nodes outside every patch of the colour are copied.  Four lanes
-// (one per patch node) cooperate on a cell; "virtual" cells beyond the mesh
-// edge only copy.  zero_in: x_in is taken as zero (first sweep of a cycle).
+// ------------------------------------------------------ colored Vanka update
+// Second half of one multiplicative pass over the cells of one colour: with
+// r = b - A x computed beforehand at every node (k_spmv), every cell of the
+// colour updates its patch x[P] += omega Ainv_P r_P.  Patches of one colour do
+// not overlap, so the update is in place.  Four lanes (one per patch node)
+// share a cell; each reads the 20 patch residuals and forms its node's 5 rows.
+// zero_in: x is taken as zero and r = b (first pass of a cycle): x[P] = omega Ainv_P b_P,
+// nodes outside every patch of the colour get x = 0.
 template <class S>
-__global__ void __launch_bounds__(256) k_vanka_pass(Geom g, double k, int color, S omega, int zero_in,
-                                                    const S* __restrict__ J, const S* __restrict__ Ainv,
-                                                    const S* __restrict__ b, const S* __restrict__ x_in,
-                                                    S* __restrict__ x_out, const int* __restrict__ active) {
+__global__ void __launch_bounds__(256) k_vanka_update(Geom g, int color, S omega, int zero_in,
+                                                      const S* __restrict__ Ainv, const S* __restrict__ r,
+                                                      S* __restrict__ x, const int* __restrict__ active) {
+  // one thread per (patch row, cell of the colour): t = row * nc + idx, so a wave
+  // reads 64 consecutive cells of one Ainv row run
   const int bs = blockIdx.y;
   if (active && !active[bs]) return;
-  const int cx = color & 1, cy = color >> 1;
-  const int nbx = (g.nx + cx) / 2 + 1, nby = (g.ny + cy) / 2 + 1;
+  const ColorLayout L = color_layout(g.nx, g.ny);
+  const int nc = L.ncx[color] * L.ncy[color];
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  const int blk = t >> 2, a = t & 3;
-  const bool inb = blk < nbx * nby;
-  const int mx = inb ? blk % nbx : 0, my = inb ? blk / nbx : 0;
-  const int ci = 2 * mx - cx, cj = 2 * my - cy;
-  const int ni = ci + (a & 1), nj = cj + (a >> 1);
-  const bool valid = inb && ni >= 0 && nj >= 0 && ni <= g.nx && nj <= g.ny;
-  const bool real = inb && ci >= 0 && cj >= 0 && ci < g.nx && cj < g.ny;
-  const int n = valid ? ni + (g.nx + 1) * nj : 0;
-  const S* xb = x_in + (size_t)bs * g.nn * NC;
-  S r[NC] = {0, 0, 0, 0, 0};
-  S xo[NC] = {0, 0, 0, 0, 0};
-  if (valid) {
-    const S* bb = b + ((size_t)bs * g.nn + n) * NC;
-#pragma unroll
-    for (int c = 0; c < NC; ++c) r[c] = bb[c];
-    if (!zero_in) {
-#pragma unroll
-      for (int c = 0; c < NC; ++c) xo[c] = xb[(size_t)n * NC + c];
-    }
-    if (real && !zero_in) {
-      const S* jb = J + (size_t)bs * NSLOT * BLK * g.nn;
-#pragma unroll
-      for (int s = 0; s < NSLOT; ++s) {
-        const int dx = s % 3 - 1, dy = s / 3 - 1;
-        const int ii = ni + dx, jj = nj + dy;
-        if (ii < 0 || jj < 0 || ii > g.nx || jj > g.ny) continue;
-        const S* xv = xb + (size_t)(ii + (g.nx + 1) * jj) * NC;
-        S xs[NC];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) xs[c] = xv[c];
-#pragma unroll
-        for (int rr = 0; rr < NC; ++rr)
-#pragma unroll
-          for (int c = 0; c < NC; ++c) r[rr] -= jb[((size_t)s * BLK + NC * rr + c) * g.nn + n] * xs[c];
-      }
-      if (!(g.dmask[n] & DM_P)) {
-        S ap = 0;
-        for (int q = 0; q < NPST; ++q) {
-          const int dx = q % 5 - 2, dy = q / 5 - 2;
-          const int ii = ni + dx, jj = nj + dy;
-          if (ii < 0 || jj < 0 || ii > g.nx || jj > g.ny) continue;
-          ap += (S)g.pst[(size_t)q * g.nn + n] * xb[(size_t)(ii + (g.nx + 1) * jj) * NC + 4];
-        }
-        r[4] -= (S)k * ap;
-      }
-    }
+  S* xb = x + (size_t)bs * g.nn * NC;
+  if (zero_in && t < g.nn) {
+    // clear the nodes no patch of this colour covers (first pass only)
+    const int ni = t % (g.nx + 1), nj = t / (g.nx + 1);
+    const int cx = color & 1, cy = color >> 1;
+    const int ci = ni - ((ni - cx) & 1), cj = nj - ((nj - cy) & 1);
+    if (ci < 0 || cj < 0 || ci >= g.nx || cj >= g.ny)
+      for (int c = 0; c < NC; ++c) xb[(size_t)t * NC + c] = (S)0;
   }
-  // patch residual from the four lanes of the cell
-  S rp[NE];
-  const int base = (threadIdx.x & ~3) & 63;
+  if (t >= NE * nc) return;
+  const int row = t / nc, idx = t - row * nc;
+  const int ci = 2 * (idx % L.ncx[color]) + (color & 1), cj = 2 * (idx / L.ncx[color]) + (color >> 1);
+  const int n0 = ci + (g.nx + 1) * cj;
+  const int nodes[NL] = {n0, n0 + 1, n0 + g.nx + 1, n0 + g.nx + 2};
+  const S* rb = r + (size_t)bs * g.nn * NC;
+  const S* ai = Ainv + (size_t)bs * NE * NE * g.ncell + (size_t)L.off[color] * NE * NE + (size_t)NE * row * nc + idx;
+  S z = 0;
 #pragma unroll
   for (int bb = 0; bb < NL; ++bb)
 #pragma unroll
-    for (int c = 0; c < NC; ++c) rp[NC * bb + c] = __shfl(r[c], base + bb, 64);
-  if (!valid) return;
-  S* xw = x_out + ((size_t)bs * g.nn + n) * NC;
-  if (!real) {
-#pragma unroll
-    for (int c = 0; c < NC; ++c) xw[c] = xo[c];
-    return;
-  }
-  const ColorLayout L = color_layout(g.nx, g.ny);
-  const int nc = L.ncx[color] * L.ncy[color];
-  const int idx = (ci >> 1) + L.ncx[color] * (cj >> 1);
-  const S* ai = Ainv + (size_t)bs * NE * NE * g.ncell + (size_t)L.off[color] * NE * NE;
-#pragma unroll
-  for (int rr = 0; rr < NC; ++rr) {
-    S z = 0;
-    const int row = NC * a + rr;
-#pragma unroll
-    for (int c = 0; c < NE; ++c) z += ai[(size_t)(NE * row + c) * nc + idx] * rp[c];
-    xw[rr] = xo[rr] + omega * z;
-  }
+    for (int c = 0; c < NC; ++c) z += ai[(size_t)(NC * bb + c) * nc] * rb[(size_t)nodes[bb] * NC + c];
+  S* xw = xb + (size_t)nodes[row / NC] * NC + row % NC;
+  *xw = (zero_in ? (S)0 : *xw) + omega * z;
 }
 
 // --------------------------------------------------------- grid transfers
@@ -288,13 +260,15 @@ __global__ void k_prolong_add(Geom gf, Geom gc, const S* __restrict__ xc, S* __r
     if (!(mf & (1u << c))) xo[c] += add[c];
 }
 
-// ------------------------------------------- coarsest level: block LU
+// ------------------------------------------- coarsest level: direct solve
 // Unknowns ordered by super-columns of two x-node columns (bs = 2 (ny+1) 5);
 // the 3x3 block stencil plus the 5x5 pressure stencil make the matrix block
 // tridiagonal.  Factor: Delta_0 = D_0, Delta_K = D_K - L_K W_{K-1},
 // W_K = Delta_K^{-1} U_K.  Stored per slice: Dinv_K, W_K, L_K (bs x bs each).
+// From the factors the explicit inverse is formed once per factorisation, so
+// each coarse solve of a V-cycle is one dense matrix-vector product.
 template <class S>
-__device__ inline double coarse_entry(const Geom& g, double k, const S* jb, int bs, int K, int l, int K2, int l2) {
+__device__ inline double coarse_entry(const Geom& g, double k, const S* jb, int K, int l, int K2, int l2) {
   // row: super-column K local l; column: super-column K2 local l2
   const int r = l % NC, nl = l / NC, colx = nl / (g.ny + 1), jr = nl % (g.ny + 1);
   const int c = l2 % NC, nl2 = l2 / NC, colx2 = nl2 / (g.ny + 1), jc = nl2 % (g.ny + 1);
@@ -303,46 +277,51 @@ __device__ inline double coarse_entry(const Geom& g, double k, const S* jb, int 
   const int dx = ic - ir, dy = jc - jr;
   const int n = ir + (g.nx + 1) * jr;
   double v = 0.0;
-  if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1)
-    v = (double)jb[((size_t)slot_of(dx, dy) * BLK + NC * r + c) * g.nn + n];
+  if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1) v = (double)jb[jidx(n, slot_of(dx, dy), NC * r + c)];
   if (r == 4 && c == 4 && dx >= -2 && dx <= 2 && dy >= -2 && dy <= 2 && !(g.dmask[n] & DM_P))
     v += k * g.pst[(size_t)pslot_of(dx, dy) * g.nn + n];
   return v;
 }
 
-// One workgroup per slice; dynamic LDS holds [Delta | I] (bs x 2bs) and a bs x bs tile.
+// global dof index of local unknown l of super-column K, or -1 for padding
+__device__ inline int coarse_gidx(const Geom& g, int K, int l) {
+  const int c = l % NC, nl = l / NC, colx = nl / (g.ny + 1), jn = nl % (g.ny + 1);
+  const int i = 2 * K + colx;
+  if (i > g.nx) return -1;
+  return (i + (g.nx + 1) * jn) * NC + c;
+}
+
+// One wave per slice (no cross-wave barriers); dynamic LDS holds [Delta | I]
+// (bs x 2bs) and a bs x bs tile.  Gauss-Jordan with partial pivoting.
 template <class S>
-__global__ void __launch_bounds__(256) k_coarse_factor(Geom g, double k, const S* __restrict__ J, int bsz, int nsb,
-                                                       double* __restrict__ Dinv, double* __restrict__ W,
-                                                       double* __restrict__ Lb, const int* __restrict__ active) {
+__global__ void __launch_bounds__(64) k_coarse_factor(Geom g, double k, const S* __restrict__ J, int bsz, int nsb,
+                                                      double* __restrict__ Dinv, double* __restrict__ W,
+                                                      double* __restrict__ Lb, const int* __restrict__ active) {
   extern __shared__ double lds[];
   const int bs = blockIdx.x;
   if (active && !active[bs]) return;
   const int tid = threadIdx.x, nt = blockDim.x;
-  const S* jb = J + (size_t)bs * NSLOT * BLK * g.nn;
-  double* M = lds;                       // bsz x 2bsz
-  double* T = lds + 2 * bsz * bsz;       // bsz x bsz scratch
-  __shared__ int piv_row;
-  __shared__ double piv_val;
-  __shared__ unsigned char used[128];
+  const S* jb = J + (size_t)bs * jslice(g.nn);
+  const int w2 = 2 * bsz;
+  double* M = lds;                 // bsz x 2bsz
+  double* T = lds + bsz * w2;      // bsz x bsz
   __shared__ double fac[128];
   __shared__ int colmap[128];
+  __shared__ int usedf[128];
   const size_t B2 = (size_t)bsz * bsz;
   double* dinv = Dinv + (size_t)bs * nsb * B2;
   double* w = W + (size_t)bs * nsb * B2;
   double* lb = Lb + (size_t)bs * nsb * B2;
   for (int K = 0; K < nsb; ++K) {
-    // M = [D_K | I]
     for (int e = tid; e < bsz * bsz; e += nt) {
       const int r = e / bsz, c = e % bsz;
-      M[r * 2 * bsz + c] = coarse_entry<S>(g, k, jb, bs, K, r, K, c);
-      M[r * 2 * bsz + bsz + c] = (r == c) ? 1.0 : 0.0;
+      M[r * w2 + c] = coarse_entry<S>(g, k, jb, K, r, K, c);
+      M[r * w2 + bsz + c] = (r == c) ? 1.0 : 0.0;
     }
     if (K > 0) {
-      // L_K and Delta_K = D_K - L_K W_{K-1}
       for (int e = tid; e < bsz * bsz; e += nt) {
         const int r = e / bsz, c = e % bsz;
-        const double v = coarse_entry<S>(g, k, jb, bs, K, r, K - 1, c);
+        const double v = coarse_entry<S>(g, k, jb, K, r, K - 1, c);
         T[e] = v;
         lb[K * B2 + e] = v;
       }
@@ -352,48 +331,46 @@ __global__ void __launch_bounds__(256) k_coarse_factor(Geom g, double k, const S
         const int r = e / bsz, c = e % bsz;
         double s = 0.0;
         for (int q = 0; q < bsz; ++q) s += T[r * bsz + q] * wp[q * bsz + c];
-        M[r * 2 * bsz + c] -= s;
+        M[r * w2 + c] -= s;
       }
     }
-    for (int e = tid; e < bsz; e += nt) used[e] = 0;
+    for (int e = tid; e < bsz; e += nt) usedf[e] = 0;
     __syncthreads();
-    // Gauss-Jordan with partial pivoting on [Delta | I]; colmap[jc] = pivot row of column jc
     for (int jc = 0; jc < bsz; ++jc) {
-      if (tid == 0) {
-        int best = 0;
-        double bv = -1.0;
-        for (int r = 0; r < bsz; ++r)
-          if (!used[r] && fabs(M[r * 2 * bsz + jc]) > bv) { bv = fabs(M[r * 2 * bsz + jc]); best = r; }
-        piv_row = best;
-        const double pv = M[best * 2 * bsz + jc];
-        piv_val = (pv == 0.0) ? 1.0 : pv;
-        used[best] = 1;
-        colmap[jc] = best;
+      // pivot search: wave-wide arg-max over the unused rows (bsz <= 128: two rows per lane)
+      double best = -1.0;
+      int bi = 0;
+      for (int r = tid; r < bsz; r += nt) {
+        const double v = usedf[r] ? -1.0 : fabs(M[r * w2 + jc]);
+        if (v > best) { best = v; bi = r; }
       }
-      __syncthreads();
-      const int pr = piv_row;
-      const double pv = piv_val;
-      for (int r = tid; r < bsz; r += nt) fac[r] = (r == pr) ? 0.0 : M[r * 2 * bsz + jc] / pv;
-      __syncthreads();
-      for (int e = tid; e < bsz * 2 * bsz; e += nt) {
-        const int r = e / (2 * bsz), c = e % (2 * bsz);
-        if (r != pr && fac[r] != 0.0) M[e] -= fac[r] * M[pr * 2 * bsz + c];
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ob = __shfl_xor(best, off, 64);
+        const int oi = __shfl_xor(bi, off, 64);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
       }
+      const int pr = __shfl(bi, 0, 64);
+      double pv = M[pr * w2 + jc];
+      if (pv == 0.0) pv = 1.0;
+      for (int r = tid; r < bsz; r += nt) fac[r] = (r == pr) ? 0.0 : M[r * w2 + jc] / pv;
+      if (tid == 0) { usedf[pr] = 1; colmap[jc] = pr; }
       __syncthreads();
-      for (int c = tid; c < 2 * bsz; c += nt) M[pr * 2 * bsz + c] /= pv;
+      for (int c = tid; c < w2; c += nt) {
+        const double pc = M[pr * w2 + c];
+        for (int r = 0; r < bsz; ++r) M[r * w2 + c] -= fac[r] * pc;
+        M[pr * w2 + c] = pc / pv;
+      }
       __syncthreads();
     }
-    // Dinv_K row jc = right half of row piv(jc)
     for (int e = tid; e < bsz * bsz; e += nt) {
       const int jr = e / bsz, c = e % bsz;
-      dinv[K * B2 + e] = M[colmap[jr] * 2 * bsz + bsz + c];
+      dinv[K * B2 + e] = M[colmap[jr] * w2 + bsz + c];
     }
     __syncthreads();
     if (K < nsb - 1) {
-      // W_K = Dinv_K U_K with U_K the block (K, K+1)
       for (int e = tid; e < bsz * bsz; e += nt) {
         const int r = e / bsz, c = e % bsz;
-        T[e] = coarse_entry<S>(g, k, jb, bs, K, r, K + 1, c);
+        T[e] = coarse_entry<S>(g, k, jb, K, r, K + 1, c);
       }
       __syncthreads();
       for (int e = tid; e < bsz * bsz; e += nt) {
@@ -407,67 +384,87 @@ __global__ void __launch_bounds__(256) k_coarse_factor(Geom g, double k, const S
   }
 }
 
-// Solve with the block factors: y_K = Dinv_K (b_K - L_K y_{K-1}); x_K = y_K - W_K x_{K+1}.
-template <class S>
-__global__ void __launch_bounds__(256) k_coarse_solve(Geom g, int bsz, int nsb, const double* __restrict__ Dinv,
-                                                      const double* __restrict__ W, const double* __restrict__ Lb,
-                                                      const S* __restrict__ bvec, S* __restrict__ xvec,
-                                                      const int* __restrict__ active) {
-  extern __shared__ double lds[];
-  const int bs = blockIdx.x;
+// Explicit inverse from the block factors: column j of A^{-1} solves A x = e_j.
+// Grid (ceil(n0 / 64), B); each thread owns one column j and runs the block
+// forward / backward sweeps.  Scratch Y[b][q][j] holds the columns in block
+// order q (coalesced across the threads of a wave).  bsz <= 64.
+__global__ void __launch_bounds__(64) k_coarse_inverse(Geom g, int bsz, int nsb, const double* __restrict__ Dinv,
+                                                       const double* __restrict__ W, const double* __restrict__ Lb,
+                                                       double* __restrict__ Y, const int* __restrict__ active) {
+  const int bs = blockIdx.y;
   if (active && !active[bs]) return;
-  const int tid = threadIdx.x, nt = blockDim.x;
+  const int n0 = g.nn * NC;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n0) return;
   const size_t B2 = (size_t)bsz * bsz;
-  double* y = lds;              // nsb * bsz
-  double* tmp = lds + nsb * bsz;  // bsz
-  const S* bb = bvec + (size_t)bs * g.nn * NC;
-  S* xb = xvec + (size_t)bs * g.nn * NC;
   const double* dinv = Dinv + (size_t)bs * nsb * B2;
   const double* w = W + (size_t)bs * nsb * B2;
   const double* lb = Lb + (size_t)bs * nsb * B2;
-  auto gidx = [&](int K, int l) -> int {   // global dof index or -1 (padding)
-    const int c = l % NC, nl = l / NC, colx = nl / (g.ny + 1), jn = nl % (g.ny + 1);
-    const int i = 2 * K + colx;
-    if (i > g.nx) return -1;
-    return (i + (g.nx + 1) * jn) * NC + c;
-  };
+  double* y = Y + (size_t)bs * n0 * (size_t)(nsb * bsz);
+  const int node = j / NC, c = j % NC, ii = node % (g.nx + 1), jn = node / (g.nx + 1);
+  const int Kj = ii / 2, lj = (((ii & 1) * (g.ny + 1)) + jn) * NC + c;
+  double t[64];
   for (int K = 0; K < nsb; ++K) {
-    for (int l = tid; l < bsz; l += nt) {
-      const int gi = gidx(K, l);
-      double v = gi >= 0 ? (double)bb[gi] : 0.0;
+    for (int l = 0; l < bsz; ++l) {
+      double v = (K == Kj && l == lj) ? 1.0 : 0.0;
       if (K > 0) {
         const double* L = lb + K * B2 + (size_t)l * bsz;
-        const double* yp = y + (K - 1) * bsz;
-        for (int q = 0; q < bsz; ++q) v -= L[q] * yp[q];
+        for (int q = 0; q < bsz; ++q) v -= L[q] * y[(size_t)((K - 1) * bsz + q) * n0 + j];
       }
-      tmp[l] = v;
+      t[l] = v;
     }
-    __syncthreads();
-    for (int l = tid; l < bsz; l += nt) {
+    for (int l = 0; l < bsz; ++l) {
       const double* D = dinv + K * B2 + (size_t)l * bsz;
       double s = 0.0;
-      for (int q = 0; q < bsz; ++q) s += D[q] * tmp[q];
-      y[K * bsz + l] = s;
+      for (int q = 0; q < bsz; ++q) s += D[q] * t[q];
+      y[(size_t)(K * bsz + l) * n0 + j] = s;
     }
-    __syncthreads();
   }
-  for (int K = nsb - 2; K >= 0; --K) {
-    for (int l = tid; l < bsz; l += nt) {
+  for (int K = nsb - 2; K >= 0; --K)
+    for (int l = 0; l < bsz; ++l) {
       const double* Wr = w + K * B2 + (size_t)l * bsz;
-      const double* xn = y + (K + 1) * bsz;
       double s = 0.0;
-      for (int q = 0; q < bsz; ++q) s += Wr[q] * xn[q];
-      tmp[l] = y[K * bsz + l] - s;
+      for (int q = 0; q < bsz; ++q) s += Wr[q] * y[(size_t)((K + 1) * bsz + q) * n0 + j];
+      y[(size_t)(K * bsz + l) * n0 + j] -= s;
     }
-    __syncthreads();
-    for (int l = tid; l < bsz; l += nt) y[K * bsz + l] = tmp[l];
-    __syncthreads();
+}
+
+// Reorder to dof order in the solve type: AinvS[b][j][i] = (A^{-1})_{i j}.
+template <class S>
+__global__ void k_coarse_inverse_pack(Geom g, int bsz, int nsb, const double* __restrict__ Y,
+                                      S* __restrict__ AinvS, const int* __restrict__ active) {
+  const int bs = blockIdx.y;
+  if (active && !active[bs]) return;
+  const int n0 = g.nn * NC;
+  const double* y = Y + (size_t)bs * n0 * (size_t)(nsb * bsz);
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < (size_t)n0 * n0;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const int j = (int)(e / n0), i = (int)(e % n0);
+    const int node = i / NC, c = i % NC, ii = node % (g.nx + 1), jn = node / (g.nx + 1);
+    const int q = (ii / 2) * bsz + (((ii & 1) * (g.ny + 1)) + jn) * NC + c;
+    AinvS[(size_t)bs * n0 * n0 + e] = (S)y[(size_t)q * n0 + j];
   }
-  for (int K = 0; K < nsb; ++K)
-    for (int l = tid; l < bsz; l += nt) {
-      const int gi = gidx(K, l);
-      if (gi >= 0) xb[gi] = (S)y[K * bsz + l];
-    }
+}
+
+// x = A^{-1} b on the coarsest level: a block owns 64 rows; its 4 waves split
+// the columns (coalesced column-major reads) and reduce through LDS.
+template <class S>
+__global__ void __launch_bounds__(256) k_coarse_gemv(Geom g, const S* __restrict__ AinvS, const S* __restrict__ bvec,
+                                                     S* __restrict__ xvec, const int* __restrict__ active) {
+  const int bs = blockIdx.y;
+  if (active && !active[bs]) return;
+  const int n0 = g.nn * NC;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + lane;
+  __shared__ S part[4][64];
+  const S* bb = bvec + (size_t)bs * n0;
+  const S* A = AinvS + (size_t)bs * n0 * n0;
+  S acc = 0;
+  if (i < n0)
+    for (int j = wv; j < n0; j += 4) acc += A[(size_t)j * n0 + i] * bb[j];
+  part[wv][lane] = acc;
+  __syncthreads();
+  if (wv == 0 && i < n0) xvec[(size_t)bs * n0 + i] = part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane];
 }
 
 // ------------------------------------------------------------ FGMRES pieces
@@ -484,24 +481,42 @@ __device__ inline double block_sum(double v, double* sh) {
   return r;
 }
 
-// partial[b][i][chunk] = sum over the chunk of X[b] . Y_i[b] for i < nv
-// (X and the Y_i are vectors of length n with strides sx, sy per slice / per i).
+// partial[b][i][chunk] = sum over the chunk of X[b] . Y_i[b] for i < nv (nv <= 64):
+// every thread accumulates all nv products of its elements in one pass, then a
+// wave-shuffle and an LDS stage reduce them (fixed order, deterministic).
 template <class S>
 __global__ void __launch_bounds__(RED_T) k_multidot(int n, int nv, const S* __restrict__ X, size_t sxb,
                                                     const S* __restrict__ Y, size_t syb, size_t syi, int chunk,
                                                     double* __restrict__ partial, int nchunk,
                                                     const int* __restrict__ active) {
-  __shared__ double sh[RED_T];
+  __shared__ double sh[RED_T / 64][64];
   const int b = blockIdx.y, ch = blockIdx.x;
   if (active && !active[b]) return;
   const int lo = ch * chunk, hi = min(n, lo + chunk);
   const S* x = X + b * sxb;
-  for (int i = 0; i < nv; ++i) {
-    const S* y = Y + b * syb + i * syi;
-    S acc = 0;
-    for (int e = lo + threadIdx.x; e < hi; e += blockDim.x) acc += x[e] * y[e];
-    const double s = block_sum((double)acc, sh);
-    if (threadIdx.x == 0) partial[((size_t)b * 64 + i) * nchunk + ch] = s;
+  const S* yb = Y + b * syb;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int i0 = 0; i0 < nv; i0 += 8) {
+    const int m = min(8, nv - i0);
+    S acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int e = lo + threadIdx.x; e < hi; e += blockDim.x) {
+      const S xv = x[e];
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (q < m) acc[q] += xv * yb[(size_t)(i0 + q) * syi + e];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      double v = (double)acc[q];
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+      if (lane == 0 && q < m) sh[wv][i0 + q] = v;
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nv; i += blockDim.x) {
+    double s = 0.0;
+    for (int w = 0; w < RED_T / 64; ++w) s += sh[w][i];
+    partial[((size_t)b * 64 + i) * nchunk + ch] = s;
   }
 }
 
@@ -738,6 +753,15 @@ __global__ void __launch_bounds__(RED_T) k_change_norms(int nn, const double* __
   }
 }
 
+// Newton initial guess of step n >= 2: linear extrapolation U = 2 U^{n-1} - U^{n-2}.
+__global__ void k_extrapolate(size_t n, double* __restrict__ U, const double* __restrict__ Uo,
+                              const double* __restrict__ Up, const int* __restrict__ active) {
+  const int b = blockIdx.y;
+  if (active && !active[b]) return;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
+    U[(size_t)b * n + e] = 2.0 * Uo[(size_t)b * n + e] - Up[(size_t)b * n + e];
+}
+
 // flag[b] = 1 if any entry of X[b] is not finite
 __global__ void k_nonfinite(size_t n, const double* __restrict__ X, int* __restrict__ flag) {
   const int b = blockIdx.y;
@@ -759,15 +783,16 @@ __global__ void k_convert(size_t n, const A* __restrict__ X, B2* __restrict__ Y)
 // explicit instantiations
 #define INST(S)                                                                                                   \
   template __global__ void k_spmv<S>(Geom, double, const S*, const S*, const S*, const double*, S*, const int*); \
+  template __global__ void k_spmv_node<S>(Geom, double, const S*, const S*, const S*, const double*, S*,         \
+                                          const int*);                                                          \
   template __global__ void k_vanka_factor<S>(Geom, double, const S*, S*, const int*);                            \
-  template __global__ void k_vanka_pass<S>(Geom, double, int, S, int, const S*, const S*, const S*, const S*, S*, \
-                                           const int*);                                                          \
+  template __global__ void k_vanka_update<S>(Geom, int, S, int, const S*, const S*, S*, const int*);            \
   template __global__ void k_restrict<S>(Geom, Geom, const S*, S*, const int*);                                  \
   template __global__ void k_prolong_add<S>(Geom, Geom, const S*, S*, const int*);                               \
   template __global__ void k_coarse_factor<S>(Geom, double, const S*, int, int, double*, double*, double*,       \
                                               const int*);                                                       \
-  template __global__ void k_coarse_solve<S>(Geom, int, int, const double*, const double*, const double*,        \
-                                             const S*, S*, const int*);                                          \
+  template __global__ void k_coarse_inverse_pack<S>(Geom, int, int, const double*, S*, const int*);             \
+  template __global__ void k_coarse_gemv<S>(Geom, const S*, const S*, S*, const int*);                           \
   template __global__ void k_multidot<S>(int, int, const S*, size_t, const S*, size_t, size_t, int, double*, int, \
                                          const int*);                                                            \
   template __global__ void k_multiaxpy<S>(int, int, S*, size_t, const S*, size_t, size_t, const double*, int,    \
