@@ -37,7 +37,7 @@ def newton_step(disc: Discretization, Uo, t_new, k, rtol=1e-10, maxit=30, theta=
     Jacobian is then evaluated at the real part and the iteration runs until
     both real and imaginary parts of the update have converged.
     """
-    U = disc.apply_dirichlet(Uo, t_new).astype(np.result_type(Uo, np.float64))
+    U = disc.apply_dirichlet(Uo, t_new, peak=(params or {}).get("inflow_peak"))
     if params and any(np.iscomplexobj(v) for v in params.values()):
         U = U.astype(np.complex128)
     fs = field_slices(disc.dim)

@@ -130,10 +130,11 @@ class Discretization:
         return 0.5 + self.p["theta0"] * k
 
     # ------------------------------------------------------------------ data
-    def dirichlet_values(self, t: float) -> np.ndarray:
+    def dirichlet_values(self, t: float, peak=None) -> np.ndarray:
         """g(t) on every Dirichlet dof (zero elsewhere), [nodes, comp]."""
         m, p, d = self.mesh, self.p, self.dim
-        g = np.zeros((m.n_nodes, self.nc))
+        peak = p["inflow_peak"] if peak is None else peak
+        g = np.zeros((m.n_nodes, self.nc), dtype=np.result_type(peak, np.float64))
         s = ramp(t, p["ramp_time"])
         X = m.X
         prof = np.ones(m.n_nodes)
@@ -141,12 +142,12 @@ class Discretization:
             H = m.L[q]
             prof = prof * 4.0 * X[:, q] * (H - X[:, q]) / H ** 2
         inflow_only = m.on_inflow & ~m.on_wall
-        g[inflow_only, 0] = s * p["inflow_peak"] * prof[inflow_only]
+        g[inflow_only, 0] = s * peak * prof[inflow_only]
         return g
 
-    def apply_dirichlet(self, U: np.ndarray, t: float) -> np.ndarray:
-        U = U.copy()
-        g = self.dirichlet_values(t)
+    def apply_dirichlet(self, U: np.ndarray, t: float, peak=None) -> np.ndarray:
+        g = self.dirichlet_values(t, peak=peak)
+        U = U.astype(np.result_type(U, g))
         U[self.dirichlet] = g[self.dirichlet]
         return U
 
@@ -268,8 +269,10 @@ class Discretization:
         if self.S is not None:
             R[:, 2 * self.dim] += k * (self.S @ U[:, 2 * self.dim])
         if with_dirichlet:
-            g = self.dirichlet_values(t)
+            g = self.dirichlet_values(t, peak=(params or {}).get("inflow_peak"))
             D = self.dirichlet
+            if np.iscomplexobj(g) and not np.iscomplexobj(R):
+                R = R.astype(np.complex128)
             R[D] = U[D] - g[D]
         return R
 

@@ -1,0 +1,89 @@
+"""The C-ABI library loads and exports every entry point include/fsi.h declares.
+
+CPU-only: argument validation paths return before any HIP call, so they run
+without a GPU.  The library must have been built (python -m paper_1907_01252_amd.build).
+"""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fsi.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:fsi_status|void|const char\*)\s+(\w+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1907_01252_amd import fsi
+    return fsi.load()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("fsi_setup", "fine_propagate", "coarse_propagate", "parareal_run", "fsi_destroy"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for n in declared_functions():
+        assert hasattr(lib, n), n
+
+
+def test_binding_matches_header():
+    from paper_1907_01252_amd import fsi
+    assert set(fsi.EXPORTS) == set(declared_functions())
+
+
+def test_params_struct_matches_header_field_order():
+    from paper_1907_01252_amd import fsi
+    src = open(HEADER).read()
+    body = src[src.index("typedef struct {\n  int32_t dim;"):src.index("} fsi_params;")]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    fields = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl or decl.startswith("typedef"):
+            decl = decl.replace("typedef struct {", "").strip()
+            if not decl:
+                continue
+        toks = decl.split(None, 1)
+        for name in toks[1].split(","):
+            fields.append(re.sub(r"\[.*", "", name.strip()))
+    assert [f[0] for f in fsi.Params._fields_] == fields
+
+
+def test_status_strings(lib):
+    from paper_1907_01252_amd import fsi
+    for code in (fsi.FSI_OK, fsi.FSI_ERR_ARG, fsi.FSI_ERR_NEWTON, fsi.FSI_ERR_NONFINITE, fsi.FSI_ERR_PARAREAL):
+        assert lib.fsi_status_string(code)
+    assert lib.fsi_status_string(-99) == b"unknown status"
+
+
+def test_argument_errors_without_gpu(lib):
+    from paper_1907_01252_amd import fsi
+    import synth
+    h = C.c_void_p()
+    assert lib.fsi_setup(None, C.byref(h)) == fsi.FSI_ERR_ARG
+    # invalid parameter sets are rejected before any device allocation
+    for bad in (dict(level=0), dict(dim=3), dict(max_batch=0), dict(gmres_restart=100), dict(precond_lag=5)):
+        p = fsi.make_params(synth.workload("c1"), max_batch=2)
+        for k, v in bad.items():
+            setattr(p, k, v)
+        assert lib.fsi_setup(C.byref(p), C.byref(h)) == fsi.FSI_ERR_ARG, bad
+    p = fsi.make_params(synth.workload("c1"), max_batch=2)
+    p.rho_f = -1.0
+    assert lib.fsi_setup(C.byref(p), C.byref(h)) == fsi.FSI_ERR_ARG
+    st = fsi.Stats()
+    t0 = (C.c_double * 1)(0.0)
+    assert lib.fine_propagate(None, 1, t0, 0.1, 2, None, None, C.byref(st), None) == fsi.FSI_ERR_ARG
+    assert lib.coarse_propagate(None, 1, t0, 0.1, 2, None, None, None, None) == fsi.FSI_ERR_ARG
+    assert lib.parareal_run(None, 1.0, 2, 2, 1, 1e-8, 2, None, None, None, None) == fsi.FSI_ERR_ARG
+    lib.fsi_destroy(None)
