@@ -130,6 +130,21 @@ fsi_status parareal_run(fsi_problem* pb, double T, int32_t N, int32_t m, int32_t
                         int32_t max_iter, const double* U0_dev, double* U_bnd_dev,
                         fsi_stats* stats, hipStream_t stream);
 
+/* Discrete adjoint of the time-integrated drag on the bar (FP64 path only).
+   The functional is J = k sum_{n=1}^{N m} D(U^n) over the sequential fine
+   trajectory on [0, T] (N slices of m steps from U0_dev), D = x-component of
+   the fluid traction J sigma F^{-T} n_s on the bar faces shared with fluid
+   cells (sigma of eq. (ALE:stress)).  The forward pass stores the N + 1
+   slice-boundary states, recomputes all steps in one batched call from them,
+   then sweeps backward solving (dR_n/dU^n)^T lambda_n = -k dD/dU(U^n)
+   - (dR_{n+1}/dU^n)^T lambda_{n+1} with the transposed multigrid/FGMRES
+   solver (relative tolerance 1e-12).  Outputs (host): J_out, and grad_out[3]
+   = dJ/d(inflow peak), dJ/d(mu_s) at fixed lambda_s, dJ/d(lambda_s) at fixed
+   mu_s.  Errors: FSI_ERR_ARG (bad sizes, mixed precision), solver errors as
+   in fine_propagate. */
+fsi_status adjoint_gradient(fsi_problem* pb, double T, int32_t N, int32_t m, const double* U0_dev, double* J_out,
+                            double grad_out[3], fsi_stats* stats, hipStream_t stream);
+
 /* Test and benchmark entry points (same conventions).
    fsi_debug_residual: R_out[b] = residual of one step t_host[b]-k -> t_host[b]
      at the new state U[b] with old state Uo[b] (Dirichlet rows included).

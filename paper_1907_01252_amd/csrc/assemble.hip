@@ -341,7 +341,7 @@ __global__ void k_gather_residual(Geom g, StepPar sp, const double* __restrict__
 // Dsc[b][node][c] = 1 / max_j |J_row,j| (including k S on pressure rows).
 template <class S>
 __global__ void k_gather_jacobian(Geom g, double k, const double* __restrict__ Ke, S* __restrict__ J,
-                                  double* __restrict__ Dsc, const int* __restrict__ active) {
+                                  double* __restrict__ Dsc, const int* __restrict__ active, int dir_identity) {
   const int b = blockIdx.y;
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= g.nn || (active && !active[b])) return;
@@ -371,7 +371,7 @@ __global__ void k_gather_jacobian(Geom g, double k, const double* __restrict__ K
       }
       for (int r = 0; r < NC; ++r) {
         if (m & (1u << r))
-          for (int c = 0; c < NC; ++c) blk[NC * r + c] = (dx == 0 && dy == 0 && c == r) ? 1.0 : 0.0;
+          for (int c = 0; c < NC; ++c) blk[NC * r + c] = (dir_identity && dx == 0 && dy == 0 && c == r) ? 1.0 : 0.0;
         for (int c = 0; c < NC; ++c) rmax[r] = fmax(rmax[r], fabs(blk[NC * r + c]));
       }
       const int s = slot_of(dx, dy);
@@ -382,14 +382,165 @@ __global__ void k_gather_jacobian(Geom g, double k, const double* __restrict__ K
     for (int q = 0; q < NPST; ++q) pm = fmax(pm, fabs(k * g.pst[(size_t)q * g.nn + n]));
     rmax[4] = fmax(rmax[4], pm);
   }
+  if (!Dsc) return;
   double* d = Dsc + ((size_t)b * g.nn + n) * NC;
   for (int r = 0; r < NC; ++r) d[r] = rmax[r] > 0.0 ? 1.0 / rmax[r] : 1.0;
 }
 
-template __global__ void k_gather_jacobian<double>(Geom, double, const double*, double*, double*, const int*);
-template __global__ void k_gather_jacobian<float>(Geom, double, const double*, float*, double*, const int*);
+template __global__ void k_gather_jacobian<double>(Geom, double, const double*, double*, double*, const int*, int);
+template __global__ void k_gather_jacobian<float>(Geom, double, const double*, float*, double*, const int*, int);
 template __global__ void k_elem_jacobian<false>(Geom, StepPar, const double*, const double*, double*, const int*);
 template __global__ void k_elem_jacobian<true>(Geom, StepPar, const double*, const double*, double*, const int*);
+
+// ------------------------------------------------------------------ drag
+
+// x-component of the fluid traction J sigma(v, p; F) F^{-T} n_s integrated over one face
+template <class T>
+__device__ T face_drag(const Geom& g, double rn, const DragFace& f, const T (&U)[NE]) {
+  const int i = f.cell % g.nx, j = f.cell / g.nx;
+  const double hx = g.x[i + 1] - g.x[i], hy = g.y[j + 1] - g.y[j];
+  const double len = f.axis == 0 ? hy : hx;
+  const double gq[2] = {GA, GB};
+  T tot = T(0.0);
+  for (int q = 0; q < 2; ++q) {
+    const double xi = f.axis == 0 ? (double)f.side : gq[q];
+    const double eta = f.axis == 0 ? gq[q] : (double)f.side;
+    const double N[NL] = {(1 - xi) * (1 - eta), xi * (1 - eta), (1 - xi) * eta, xi * eta};
+    const double Gx[NL] = {-(1 - eta) / hx, (1 - eta) / hx, -eta / hx, eta / hx};
+    const double Gy[NL] = {-(1 - xi) / hy, -xi / hy, (1 - xi) / hy, xi / hy};
+    Pt<T> pt;
+    eval_point<T, T>(U, N, Gx, Gy, pt);
+    T F[2][2], J, Fi[2][2], A[2][2];
+    def_grad(pt.gu, F, J, Fi);
+    mat_mul(pt.gv, Fi, A);
+    T s00 = 2.0 * rn * A[0][0] - pt.p, s01 = rn * (A[0][1] + A[1][0]);
+    // (J sigma F^{-T} n_s)_x = J sign sum_j sigma_0j Fi[axis][j]
+    T tr = J * (double)f.sign * (s00 * Fi[f.axis][0] + s01 * Fi[f.axis][1]);
+    tot += 0.5 * len * tr;
+  }
+  return tot;
+}
+
+__device__ inline void load_cell_state(const Geom& g, const double* U, int cell, double (&Ue)[NE]) {
+  const int i = cell % g.nx, j = cell / g.nx;
+  const int n0 = i + (g.nx + 1) * j;
+  const int nodes[NL] = {n0, n0 + 1, n0 + g.nx + 1, n0 + g.nx + 2};
+  for (int a = 0; a < NL; ++a)
+    for (int c = 0; c < NC; ++c) Ue[NC * a + c] = U[(size_t)nodes[a] * NC + c];
+}
+
+// vals[s] = D(U_s) for nstates states spaced by stride doubles (one thread per state, faces in order)
+__global__ void k_drag_values(Geom g, double rn, const DragFace* __restrict__ faces, int nf,
+                              const double* __restrict__ U, size_t stride, int nstates, double* __restrict__ vals) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nstates) return;
+  const double* u = U + (size_t)s * stride;
+  double tot = 0.0;
+  for (int q = 0; q < nf; ++q) {
+    double Ue[NE];
+    load_cell_state(g, u, faces[q].cell, Ue);
+    tot += face_drag<double>(g, rn, faces[q], Ue);
+  }
+  vals[s] = tot;
+}
+
+// grad += scale * dD/dU at U (single thread: faces and local unknowns in a fixed order)
+__global__ void k_drag_gradient(Geom g, double rn, const DragFace* __restrict__ faces, int nf,
+                                const double* __restrict__ U, double scale, double* __restrict__ grad) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  for (int q = 0; q < nf; ++q) {
+    double Ue[NE];
+    load_cell_state(g, U, faces[q].cell, Ue);
+    const int i = faces[q].cell % g.nx, j = faces[q].cell / g.nx;
+    const int n0 = i + (g.nx + 1) * j;
+    const int nodes[NL] = {n0, n0 + 1, n0 + g.nx + 1, n0 + g.nx + 2};
+    for (int d = 0; d < NE; ++d) {
+      Dual Ud[NE];
+      for (int e = 0; e < NE; ++e) Ud[e] = Dual(Ue[e], e == d ? 1.0 : 0.0);
+      const Dual v = face_drag<Dual>(g, rn, faces[q], Ud);
+      grad[(size_t)nodes[d / NC] * NC + d % NC] += scale * v.d;
+    }
+  }
+}
+
+// out[0..2] += lam^T dR/dq for q = (inflow peak, mu_s, lambda_s) at the step (U, Uo) of time t.
+// One workgroup; Dirichlet rows are excluded except the inflow rows (which carry the peak).
+__global__ void __launch_bounds__(256) k_param_sens(Geom g, StepPar sp, const double* __restrict__ U,
+                                                    const double* __restrict__ Uo, const double* __restrict__ lam,
+                                                    double t, double* __restrict__ out) {
+  __shared__ double sh[3][256];
+  double acc[3] = {0.0, 0.0, 0.0};
+  // inflow peak: R_i = U_i - s(t) peak prof(y_i) on the inflow rows
+  const double H = g.y[g.ny], ramp = inflow_ramp(t, sp.ramp_time);
+  for (int n = threadIdx.x; n < g.nn; n += blockDim.x)
+    if (g.cls[n] & CL_INFLOW) {
+      const double y = g.y[n / (g.nx + 1)];
+      acc[0] -= lam[(size_t)n * NC] * ramp * 4.0 * y * (H - y) / (H * H);
+    }
+  // solid stress: d/dmu and d/dlambda of k theta F Sigma(E) + k (1-theta) F° Sigma(E°)
+  const double k = sp.k, th = sp.theta;
+  const double gq[2] = {GA, GB};
+  for (int cell = threadIdx.x; cell < g.ncell; cell += blockDim.x) {
+    if (!g.solid[cell]) continue;
+    CellIn ci = load_cell(g, cell);
+    double Ue[NE], Uoe[NE], le[NE];
+    for (int a = 0; a < NL; ++a)
+      for (int c = 0; c < NC; ++c) {
+        const size_t o = (size_t)ci.nodes[a] * NC + c;
+        Ue[NC * a + c] = U[o];
+        Uoe[NC * a + c] = Uo[o];
+        le[NC * a + c] = (g.dmask[ci.nodes[a]] & (1u << c)) ? 0.0 : lam[o];
+      }
+    const double w = 0.25 * ci.c.hx * ci.c.hy;
+    for (int q = 0; q < 4; ++q) {
+      const double xi = gq[q & 1], eta = gq[q >> 1];
+      const double N[NL] = {(1 - xi) * (1 - eta), xi * (1 - eta), (1 - xi) * eta, xi * eta};
+      const double Gx[NL] = {-(1 - eta) / ci.c.hx, (1 - eta) / ci.c.hx, -eta / ci.c.hx, eta / ci.c.hx};
+      const double Gy[NL] = {-(1 - xi) / ci.c.hy, -xi / ci.c.hy, (1 - xi) / ci.c.hy, xi / ci.c.hy};
+      Pt<double> f, o;
+      eval_point<double, double>(Ue, N, Gx, Gy, f);
+      eval_point<double, double>(Uoe, N, Gx, Gy, o);
+      double F[2][2], J, Fi[2][2], Fo[2][2], Jo, Foi[2][2];
+      def_grad(f.gu, F, J, Fi);
+      def_grad(o.gu, Fo, Jo, Foi);
+      double dmu[2][2], dla[2][2];
+      for (int pass = 0; pass < 2; ++pass) {
+        const double (*Fx)[2] = pass == 0 ? F : Fo;
+        const double wt = pass == 0 ? k * th : k * (1.0 - th);
+        const double E00 = 0.5 * (Fx[0][0] * Fx[0][0] + Fx[1][0] * Fx[1][0] - 1.0);
+        const double E01 = 0.5 * (Fx[0][0] * Fx[0][1] + Fx[1][0] * Fx[1][1]);
+        const double E11 = 0.5 * (Fx[0][1] * Fx[0][1] + Fx[1][1] * Fx[1][1] - 1.0);
+        const double trE = E00 + E11;
+        // F (2E) and F (tr E I)
+        const double m00 = Fx[0][0] * 2 * E00 + Fx[0][1] * 2 * E01, m01 = Fx[0][0] * 2 * E01 + Fx[0][1] * 2 * E11;
+        const double m10 = Fx[1][0] * 2 * E00 + Fx[1][1] * 2 * E01, m11 = Fx[1][0] * 2 * E01 + Fx[1][1] * 2 * E11;
+        if (pass == 0) {
+          dmu[0][0] = wt * m00; dmu[0][1] = wt * m01; dmu[1][0] = wt * m10; dmu[1][1] = wt * m11;
+          for (int a2 = 0; a2 < 2; ++a2)
+            for (int b2 = 0; b2 < 2; ++b2) dla[a2][b2] = wt * Fx[a2][b2] * trE;
+        } else {
+          dmu[0][0] += wt * m00; dmu[0][1] += wt * m01; dmu[1][0] += wt * m10; dmu[1][1] += wt * m11;
+          for (int a2 = 0; a2 < 2; ++a2)
+            for (int b2 = 0; b2 < 2; ++b2) dla[a2][b2] += wt * Fx[a2][b2] * trE;
+        }
+      }
+      for (int a = 0; a < NL; ++a)
+        for (int i2 = 0; i2 < 2; ++i2) {
+          acc[1] += w * le[NC * a + i2] * (dmu[i2][0] * Gx[a] + dmu[i2][1] * Gy[a]);
+          acc[2] += w * le[NC * a + i2] * (dla[i2][0] * Gx[a] + dla[i2][1] * Gy[a]);
+        }
+    }
+  }
+  for (int q = 0; q < 3; ++q) sh[q][threadIdx.x] = acc[q];
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s)
+      for (int q = 0; q < 3; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int q = 0; q < 3; ++q) out[q] += sh[q][0];
+}
 
 // Coarse state by injection: coarse node (I, J) takes fine node (2I, 2J).
 __global__ void k_inject(Geom gc, Geom gf, const double* __restrict__ Uf, double* __restrict__ Uc, int B) {

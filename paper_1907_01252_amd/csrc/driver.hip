@@ -104,6 +104,14 @@ struct fsi_problem {
   int *gstate = nullptr, *ncol = nullptr;
   // coarsest level block LU and explicit inverse
   double *cDinv = nullptr, *cW = nullptr, *cL = nullptr, *cY = nullptr;
+  // adjoint scratch (allocated on the first adjoint call)
+  double *Jtmp = nullptr, *Jcopy = nullptr, *Jold = nullptr, *traj = nullptr, *abnd = nullptr, *lam = nullptr,
+         *lamn = nullptr, *arhs = nullptr, *ay = nullptr, *dvals = nullptr, *agrad = nullptr;
+  double *aout = nullptr, *traj_out = nullptr;
+  double adj_rtol = 1e-12;
+  DragFace* faces = nullptr;
+  int nfaces = 0;
+  size_t traj_cap = 0;
   void* cAinv = nullptr;
   int cbs = 0, cnsb = 0;
   // Newton norms
@@ -373,7 +381,7 @@ fsi_status residual(fsi_problem* pb, int B, const StepPar& sp, const double* U, 
 // the coarsest-level inverse.
 template <class S>
 fsi_status assemble_levels(fsi_problem* pb, int B, const StepPar& sp, const int* act, hipStream_t st,
-                           bool precond = true) {
+                           bool precond = true, bool transpose = false, double* save_fine = nullptr) {
   const int L = pb->nlev - 1;
   for (int l = L; l >= (precond ? 0 : L); --l) {
     Level& lv = pb->lev[l];
@@ -391,7 +399,14 @@ fsi_status assemble_levels(fsi_problem* pb, int B, const StepPar& sp, const int*
       ProfScope ps(pb, F_JAC, st, (double)B * (g.ncell * NE * NE * 8.0 + 2.0 * g.nn * NC * 8));
       k_elem_jacobian<false><<<dim3((g.ncell + 127) / 128, B), 128, 0, st>>>(g, sp, U, Uo, pb->Ke, act);
     }
-    k_gather_jacobian<S><<<grid1(g.nn, B), TPB, 0, st>>>(g, sp.k, pb->Ke, (S*)lv.J, lv.Dsc, act);
+    k_gather_jacobian<S><<<grid1(g.nn, B), TPB, 0, st>>>(g, sp.k, pb->Ke, (S*)lv.J, lv.Dsc, act, 1);
+    if (transpose) {
+      // adjoint: the operator of every level becomes the transpose of the free block (B = 1)
+      const size_t bytes = jslice(g.nn) * sizeof(S);
+      if (l == L && save_fine) HIPCHK(hipMemcpyAsync(save_fine, lv.J, bytes, hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemcpyAsync(pb->Jtmp, lv.J, bytes, hipMemcpyDeviceToDevice, st));
+      k_transpose_J<double><<<grid1(g.nn, 1), TPB, 0, st>>>(g, sp.k, (const double*)pb->Jtmp, (double*)lv.J, lv.Dsc);
+    }
     if (!precond) break;
     if (l >= 1) {
       k_vanka_factor<S><<<dim3((g.ncell * 32 + TPB - 1) / TPB, B), TPB, 0, st>>>(g, sp.k, (const S*)lv.J,
@@ -722,6 +737,9 @@ fsi_status propagate(fsi_problem* pb, int B, const double* t0, double slice_len,
     k_apply_dirichlet<<<grid1(F.nn, B), TPB, 0, st>>>(g, sp, pb->U, pb->tdev, pb->nact);
     HIPCHK(hipGetLastError());
     CHK(newton_solve_step<S>(pb, B, sp, hact, rs, st));
+    if (pb->traj_out)
+      HIPCHK(hipMemcpyAsync(pb->traj_out + (size_t)(n - 1) * B * ndof, pb->U, (size_t)B * ndof * sizeof(double),
+                            hipMemcpyDeviceToDevice, st));
     bool any = false;
     for (int b = 0; b < B; ++b) any |= hact[b] != 0;
     if (!any) break;
@@ -760,6 +778,166 @@ fsi_status run_propagate(fsi_problem* pb, int B, const double* t0, double slice_
   hipStream_t st = pb->ist;
   return pb->mixed ? propagate<float>(pb, B, t0, slice_len, nsteps, U_in, U_out, stats, st)
                    : propagate<double>(pb, B, t0, slice_len, nsteps, U_in, U_out, stats, st);
+}
+
+// ------------------------------------------------------------ adjoint
+// Drag faces of the finest level: bar faces shared with a fluid cell.
+std::vector<DragFace> drag_faces(const Level& L) {
+  std::vector<DragFace> f;
+  for (int j = 0; j < L.ny; ++j)
+    for (int i = 0; i < L.nx; ++i) {
+      if (!L.solid[i + L.nx * j]) continue;
+      const int di[4] = {-1, 1, 0, 0}, dj[4] = {0, 0, -1, 1};
+      for (int q = 0; q < 4; ++q) {
+        const int ii = i + di[q], jj = j + dj[q];
+        if (ii < 0 || jj < 0 || ii >= L.nx || jj >= L.ny) continue;
+        const int c = ii + L.nx * jj;
+        if (L.solid[c]) continue;
+        DragFace d;
+        d.cell = c;
+        d.axis = q < 2 ? 0 : 1;
+        d.sign = (q % 2) ? 1 : -1;
+        d.side = d.sign > 0 ? 0 : 1;
+        f.push_back(d);
+      }
+    }
+  return f;
+}
+
+fsi_status adjoint_alloc(fsi_problem* pb, size_t nstates, int N) {
+  Level& F = pb->lev[pb->nlev - 1];
+  const size_t nd = (size_t)F.nn * NC;
+  if (!pb->Jtmp) {
+    CHK(dalloc(pb, &pb->Jtmp, jslice(F.nn)));
+    CHK(dalloc(pb, &pb->Jcopy, jslice(F.nn)));
+    CHK(dalloc(pb, &pb->Jold, jslice(F.nn)));
+    CHK(dalloc(pb, &pb->lam, nd));
+    CHK(dalloc(pb, &pb->lamn, nd));
+    CHK(dalloc(pb, &pb->arhs, nd));
+    CHK(dalloc(pb, &pb->ay, nd));
+    CHK(dalloc(pb, &pb->agrad, 3));
+    CHK(dalloc(pb, &pb->abnd, (size_t)(pb->Bmax + 1) * nd));
+    CHK(dalloc(pb, &pb->aout, (size_t)pb->Bmax * nd));
+    std::vector<DragFace> f = drag_faces(F);
+    pb->nfaces = (int)f.size();
+    CHK(dalloc(pb, &pb->faces, f.size()));
+    HIPCHK(hipMemcpy(pb->faces, f.data(), f.size() * sizeof(DragFace), hipMemcpyHostToDevice));
+  }
+  if (nstates > pb->traj_cap) {
+    CHK(dalloc(pb, &pb->traj, nstates * nd));
+    CHK(dalloc(pb, &pb->dvals, nstates));
+    pb->traj_cap = nstates;
+  }
+  (void)N;
+  return FSI_OK;
+}
+
+// Sequential fine solve with slice-boundary checkpoints, a batched recompute of
+// every step from the checkpoints, the functional J = k sum D(U^n), and the
+// backward sweep of transposed Newton-Jacobian solves (FP64).
+fsi_status adjoint_run(fsi_problem* pb, double T, int N, int m, const double* U0, double* J_out, double* grad_out,
+                       fsi_stats* stats, hipStream_t caller) {
+  Level& F = pb->lev[pb->nlev - 1];
+  const Geom g = F.geom();
+  const size_t nd = (size_t)F.nn * NC;
+  const double dl = T / N, k = dl / m;
+  const StepPar sp = step_par(pb, k);
+  const double rn = pb->p.rho_f * pb->p.nu_f;
+  const size_t S = (size_t)N * m;
+  CHK(adjoint_alloc(pb, S, N));
+  auto t_start = std::chrono::steady_clock::now();
+  fsi_stats tmp;
+  int ntot = 0, ktot = 0;
+  // forward: sequential slices, checkpoints abnd[0..N]
+  HIPCHK(hipMemcpyAsync(pb->abnd, U0, nd * sizeof(double), hipMemcpyDeviceToDevice, caller));
+  for (int l = 0; l < N; ++l) {
+    const double t0 = l * dl;
+    CHK(run_propagate(pb, 1, &t0, dl, m, pb->abnd + l * nd, pb->abnd + (l + 1) * nd, &tmp, caller));
+    ntot += tmp.newton_total;
+    ktot += tmp.krylov_total;
+  }
+  // recompute all slices at once from the checkpoints, keeping every step: traj[n-1][l]
+  std::vector<double> t0s(N);
+  for (int l = 0; l < N; ++l) t0s[l] = l * dl;
+  pb->traj_out = pb->traj;
+  fsi_status rs = run_propagate(pb, N, t0s.data(), dl, m, pb->abnd, pb->aout, &tmp, caller);
+  pb->traj_out = nullptr;
+  CHK(rs);
+  ntot += tmp.newton_total;
+  ktot += tmp.krylov_total;
+  hipStream_t st = pb->ist;
+  HIPCHK(hipEventRecord(pb->iev, caller));
+  HIPCHK(hipStreamWaitEvent(st, pb->iev, 0));
+  // U^s (s = 1..S) and the old state its step started from
+  auto cur = [&](size_t s) -> const double* {
+    const size_t l = (s - 1) / m, n = (s - 1) % m + 1;
+    return pb->traj + ((n - 1) * (size_t)N + l) * nd;
+  };
+  auto prev = [&](size_t s) -> const double* {
+    const size_t l = (s - 1) / m, n = (s - 1) % m + 1;
+    return n == 1 ? pb->abnd + l * nd : pb->traj + ((n - 2) * (size_t)N + l) * nd;
+  };
+  // functional
+  k_drag_values<<<(unsigned)((S + 63) / 64), 64, 0, st>>>(g, rn, pb->faces, pb->nfaces, pb->traj, nd, (int)S,
+                                                          pb->dvals);
+  std::vector<double> dv(S);
+  HIPCHK(hipMemcpyAsync(dv.data(), pb->dvals, S * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemsetAsync(pb->agrad, 0, 3 * sizeof(double), st));
+  HIPCHK(hipStreamSynchronize(st));
+  double J = 0.0;
+  for (size_t s = 0; s < S; ++s) J += k * dv[s];
+  // backward sweep: (dR_s/dU^s)^T lam_s = -k dD/dU(U^s) - (dR_{s+1}/dU^s)^T lam_{s+1}
+  const double saved_tol = pb->p.lin_rtol;
+  pb->p.lin_rtol = pb->adj_rtol;
+  const int one = 1;
+  HIPCHK(hipMemcpyAsync(pb->nact, &one, sizeof(int), hipMemcpyHostToDevice, st));
+  fsi_status ret = FSI_OK;
+  std::vector<int> kits(1, 0);
+  for (size_t s = S; s >= 1; --s) {
+    const size_t l = (s - 1) / m, n = (s - 1) % m + 1;
+    const double ts = l * dl + n * k;
+    HIPCHK(hipMemsetAsync(pb->arhs, 0, nd * sizeof(double), st));
+    k_drag_gradient<<<1, 1, 0, st>>>(g, rn, pb->faces, pb->nfaces, cur(s), -k, pb->arhs);
+    if (s < S) {
+      k_elem_jacobian<true><<<dim3((g.ncell + 127) / 128, 1), 128, 0, st>>>(g, sp, cur(s + 1), prev(s + 1), pb->Ke,
+                                                                           nullptr);
+      k_gather_jacobian<double><<<grid1(g.nn, 1), TPB, 0, st>>>(g, k, pb->Ke, pb->Jold, nullptr, nullptr, 0);
+      k_spmv_T<double><<<grid1(g.nn, 1), TPB, 0, st>>>(g, k, pb->Jold, pb->lamn, pb->ay, 0);
+      k_daxpy<<<64, TPB, 0, st>>>(nd, -1.0, pb->ay, pb->arhs);
+    }
+    // transposed multigrid hierarchy at (U^s, U^{s-1})
+    HIPCHK(hipMemcpyAsync(pb->U, cur(s), nd * sizeof(double), hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(pb->Uold, prev(s), nd * sizeof(double), hipMemcpyDeviceToDevice, st));
+    CHK(assemble_levels<double>(pb, 1, sp, pb->nact, st, true, true, pb->Jcopy));
+    // free unknowns: Krylov solve with the Dirichlet entries of the right-hand side removed
+    k_adjoint_rhs<<<grid1(g.nn, 1), TPB, 0, st>>>(g, pb->arhs, pb->Res);
+    HIPCHK(hipGetLastError());
+    fsi_status ls = fgmres<double>(pb, 1, k, kits, st);
+    if (ls != FSI_OK) { ret = ls; break; }
+    HIPCHK(hipMemcpyAsync(pb->lam, pb->xs, nd * sizeof(double), hipMemcpyDeviceToDevice, st));
+    // Dirichlet unknowns: lam_D = rhs_D - (J^T lam)_D
+    k_spmv_T<double><<<grid1(g.nn, 1), TPB, 0, st>>>(g, k, pb->Jcopy, pb->lam, pb->ay, 1);
+    k_fix_dirichlet<<<grid1(g.nn, 1), TPB, 0, st>>>(g, pb->lam, pb->arhs, pb->ay);
+    k_param_sens<<<1, TPB, 0, st>>>(g, sp, cur(s), prev(s), pb->lam, ts, pb->agrad);
+    HIPCHK(hipGetLastError());
+    std::swap(pb->lam, pb->lamn);
+  }
+  pb->p.lin_rtol = saved_tol;
+  double gh[3] = {0, 0, 0};
+  HIPCHK(hipMemcpyAsync(gh, pb->agrad, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (J_out) *J_out = J;
+  if (grad_out)
+    for (int q = 0; q < 3; ++q) grad_out[q] = gh[q];
+  if (stats) {
+    std::memset(stats, 0, sizeof(fsi_stats));
+    stats->newton_total = ntot;
+    stats->krylov_total = ktot + kits[0];
+    stats->krylov_its[0] = kits[0];
+    stats->stage_ms[4] =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+  }
+  return ret;
 }
 
 }  // namespace
@@ -1011,6 +1189,13 @@ done:
   sp->stage_ms[6] = fine_ms;
   sp->stage_ms[4] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
   return ret;
+}
+
+fsi_status adjoint_gradient(fsi_problem* pb, double T, int32_t N, int32_t m, const double* U0, double* J_out,
+                            double* grad_out, fsi_stats* stats, hipStream_t st) {
+  if (!pb || !U0 || !J_out || !grad_out || N < 1 || N > pb->Bmax || m < 1 || !(T > 0.0)) return FSI_ERR_ARG;
+  if (pb->mixed) return FSI_ERR_ARG;   // the adjoint runs in the FP64 path
+  return adjoint_run(pb, T, N, m, U0, J_out, grad_out, stats, st);
 }
 
 fsi_status fsi_debug_residual(fsi_problem* pb, int32_t B, const double* U, const double* Uo, const double* t,

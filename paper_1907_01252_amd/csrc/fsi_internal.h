@@ -75,6 +75,13 @@ __host__ __device__ inline ColorLayout color_layout(int nx, int ny) {
   return L;
 }
 
+// A bar face shared with a fluid cell: fluid cell index, face axis (0: x, 1: y),
+// side of the face in the fluid cell (0: low, 1: high) and the sign of the solid's
+// outward normal n_s = sign e_axis.
+struct DragFace {
+  int cell, axis, side, sign;
+};
+
 // Ramp of the inflow: (1 - cos(pi t / t_r)) / 2 for t < t_r, then 1.
 __host__ __device__ inline double inflow_ramp(double t, double tr) {
   return t >= tr ? 1.0 : 0.5 * (1.0 - cos(M_PI * t / tr));

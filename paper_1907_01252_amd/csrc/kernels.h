@@ -12,7 +12,21 @@ __global__ void k_apply_dirichlet(Geom g, StepPar sp, double* U, const double* t
 __global__ void k_gather_residual(Geom g, StepPar sp, const double* Re, const double* U, const double* t, double* R,
                                   const int* active);
 template <class S>
-__global__ void k_gather_jacobian(Geom g, double k, const double* Ke, S* J, double* Dsc, const int* active);
+__global__ void k_gather_jacobian(Geom g, double k, const double* Ke, S* J, double* Dsc, const int* active,
+                                  int dir_identity);
+__global__ void k_drag_values(Geom g, double rn, const DragFace* faces, int nf, const double* U, size_t stride,
+                              int nstates, double* vals);
+__global__ void k_drag_gradient(Geom g, double rn, const DragFace* faces, int nf, const double* U, double scale,
+                                double* grad);
+__global__ void k_param_sens(Geom g, StepPar sp, const double* U, const double* Uo, const double* lam, double t,
+                             double* out);
+template <class S>
+__global__ void k_transpose_J(Geom g, double k, const S* J, S* Jt, double* Dsc);
+template <class S>
+__global__ void k_spmv_T(Geom g, double k, const S* J, const S* x, S* y, int with_pst);
+__global__ void k_fix_dirichlet(Geom g, double* lam, const double* rhs, const double* y);
+__global__ void k_adjoint_rhs(Geom g, const double* rhs, double* Res);
+__global__ void k_daxpy(size_t n, double a, const double* x, double* y);
 __global__ void k_inject(Geom gc, Geom gf, const double* Uf, double* Uc, int B);
 
 template <class S>

@@ -96,6 +96,100 @@ __global__ void __launch_bounds__(256) k_spmv(Geom g, double k, const S* __restr
   y[o] = Dsc ? (S)(Dsc[o] * (double)v) : v;
 }
 
+// ------------------------------------------------------------ transposes
+// Jt = J^T with the Dirichlet rows of Jt replaced by identity rows (the
+// transposed system of the free unknowns), and the row scaling of Jt.
+// (J^T)_{(i,r),(j,c)} = J_{(j,c),(i,r)}: node j = i + offset(s) stores it in the
+// slot of offset -offset(s), entry (c, r).
+template <class S>
+__global__ void k_transpose_J(Geom g, double k, const S* __restrict__ J, S* __restrict__ Jt, double* __restrict__ Dsc) {
+  const int bs = blockIdx.y;
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= g.nn) return;
+  const int i = n % (g.nx + 1), j = n / (g.nx + 1);
+  const S* jb = J + (size_t)bs * jslice(g.nn);
+  S* jt = Jt + (size_t)bs * jslice(g.nn);
+  const uint8_t m = g.dmask[n];
+  double rmax[NC] = {0, 0, 0, 0, 0};
+  for (int s = 0; s < NSLOT; ++s) {
+    const int dx = s % 3 - 1, dy = s / 3 - 1;
+    const int ii = i + dx, jj = j + dy;
+    const bool ok = ii >= 0 && jj >= 0 && ii <= g.nx && jj <= g.ny;
+    const int nb = ok ? ii + (g.nx + 1) * jj : 0;
+    for (int r = 0; r < NC; ++r)
+      for (int c = 0; c < NC; ++c) {
+        double v = ok ? (double)jb[jidx(nb, slot_of(-dx, -dy), NC * c + r)] : 0.0;
+        if (m & (1u << r)) v = (s == 4 && c == r) ? 1.0 : 0.0;
+        jt[jidx(n, s, NC * r + c)] = (S)v;
+        rmax[r] = fmax(rmax[r], fabs(v));
+      }
+  }
+  if (!(m & DM_P))
+    for (int q = 0; q < NPST; ++q) rmax[4] = fmax(rmax[4], fabs(k * g.pst[(size_t)q * g.nn + n]));
+  if (Dsc)
+    for (int r = 0; r < NC; ++r) Dsc[((size_t)bs * g.nn + n) * NC + r] = rmax[r] > 0.0 ? 1.0 / rmax[r] : 1.0;
+}
+
+// y = J^T x for the stored block stencil (no Dirichlet modification) plus, when
+// with_pst, k S x_p (S is symmetric).
+template <class S>
+__global__ void k_spmv_T(Geom g, double k, const S* __restrict__ J, const S* __restrict__ x, S* __restrict__ y,
+                         int with_pst) {
+  const int bs = blockIdx.y;
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= g.nn) return;
+  const int i = n % (g.nx + 1), j = n / (g.nx + 1);
+  const S* jb = J + (size_t)bs * jslice(g.nn);
+  const S* xb = x + (size_t)bs * g.nn * NC;
+  S acc[NC] = {0, 0, 0, 0, 0};
+  for (int s = 0; s < NSLOT; ++s) {
+    // row node m = n - offset(s) holds the entry in slot s
+    const int dx = s % 3 - 1, dy = s / 3 - 1;
+    const int ii = i - dx, jj = j - dy;
+    if (ii < 0 || jj < 0 || ii > g.nx || jj > g.ny) continue;
+    const int mr = ii + (g.nx + 1) * jj;
+    for (int r = 0; r < NC; ++r) {
+      const S xr = xb[(size_t)mr * NC + r];
+      for (int c = 0; c < NC; ++c) acc[c] += jb[jidx(mr, s, NC * r + c)] * xr;
+    }
+  }
+  if (with_pst && !(g.dmask[n] & DM_P)) {
+    S ap = 0;
+    for (int q = 0; q < NPST; ++q) {
+      const int dx = q % 5 - 2, dy = q / 5 - 2;
+      const int ii = i + dx, jj = j + dy;
+      if (ii < 0 || jj < 0 || ii > g.nx || jj > g.ny) continue;
+      ap += (S)g.pst[(size_t)q * g.nn + n] * xb[(size_t)(ii + (g.nx + 1) * jj) * NC + 4];
+    }
+    acc[4] += (S)k * ap;
+  }
+  for (int c = 0; c < NC; ++c) y[((size_t)bs * g.nn + n) * NC + c] = acc[c];
+}
+
+// Dirichlet unknowns of the adjoint: lam_D = rhs_D - (J^T lam)_D with lam_D = 0 in y.
+__global__ void k_fix_dirichlet(Geom g, double* __restrict__ lam, const double* __restrict__ rhs,
+                                const double* __restrict__ y) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= g.nn) return;
+  const uint8_t m = g.dmask[n];
+  for (int c = 0; c < NC; ++c)
+    if (m & (1u << c)) lam[(size_t)n * NC + c] = rhs[(size_t)n * NC + c] - y[(size_t)n * NC + c];
+}
+
+// y += a x (FP64)
+__global__ void k_daxpy(size_t n, double a, const double* __restrict__ x, double* __restrict__ y) {
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
+    y[e] += a * x[e];
+}
+
+// rhs_reduced = rhs with the Dirichlet entries set to zero; Res = -rhs_reduced
+__global__ void k_adjoint_rhs(Geom g, const double* __restrict__ rhs, double* __restrict__ Res) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= g.nn) return;
+  const uint8_t m = g.dmask[n];
+  for (int c = 0; c < NC; ++c) Res[(size_t)n * NC + c] = (m & (1u << c)) ? 0.0 : -rhs[(size_t)n * NC + c];
+}
+
 // ------------------------------------------------------- Vanka patch inverse
 // One 32-lane group inverts the 20x20 patch matrix of one cell (rows = local
 // unknowns 5a + c) by Gauss-Jordan with partial pivoting; lane r holds row r of
@@ -804,6 +898,8 @@ __global__ void k_convert(size_t n, const A* __restrict__ X, B2* __restrict__ Y)
   template __global__ void k_fill<S>(size_t, S*, S);
 INST(double)
 INST(float)
+template __global__ void k_transpose_J<double>(Geom, double, const double*, double*, double*);
+template __global__ void k_spmv_T<double>(Geom, double, const double*, const double*, double*, int);
 template __global__ void k_convert<double, float>(size_t, const double*, float*);
 template __global__ void k_convert<float, double>(size_t, const float*, double*);
 

@@ -22,7 +22,7 @@ MAX_SLICES = 1024
 
 # entry points declared in include/fsi.h
 EXPORTS = ("fsi_setup", "fsi_sizes", "fsi_initial_state", "fine_propagate", "coarse_propagate",
-           "parareal_run", "fsi_debug_residual", "fsi_debug_jacobian_apply", "fsi_debug_vcycle",
+           "parareal_run", "adjoint_gradient", "fsi_debug_residual", "fsi_debug_jacobian_apply", "fsi_debug_vcycle",
            "fsi_profile_enable", "fsi_profile_query", "fsi_destroy", "fsi_status_string")
 
 
@@ -68,6 +68,7 @@ def load():
     for f in (lib.fine_propagate, lib.coarse_propagate):
         f.argtypes = [vp, i32, dp, dbl, i32, vp, vp, C.POINTER(Stats), vp]
     lib.parareal_run.argtypes = [vp, dbl, i32, i32, i32, dbl, i32, vp, vp, C.POINTER(Stats), vp]
+    lib.adjoint_gradient.argtypes = [vp, dbl, i32, i32, vp, dp, dp, C.POINTER(Stats), vp]
     lib.fsi_debug_residual.argtypes = [vp, i32, vp, vp, dp, dbl, vp, vp]
     lib.fsi_debug_jacobian_apply.argtypes = [vp, i32, vp, vp, dp, dbl, vp, vp, vp]
     lib.fsi_debug_vcycle.argtypes = [vp, i32, vp, vp, dp, dbl, vp, vp, vp]
@@ -193,6 +194,15 @@ class Problem:
             _check(code, "parareal_run")
         return code, st
 
+    def adjoint_gradient(self, T, N, m, U0):
+        """(J, dJ/d(peak, mu_s, lambda_s), stats) of the time-integrated drag (FP64 path)."""
+        st = Stats()
+        J = C.c_double()
+        g = (C.c_double * 3)()
+        _check(load().adjoint_gradient(self.h, float(T), int(N), int(m), _ptr(U0), C.byref(J), g, C.byref(st),
+                                       _stream()), "adjoint_gradient")
+        return J.value, np.array(g[:]), st
+
     def debug_residual(self, B, U, Uo, t, k, R):
         arr, ptr = _dvec(t)
         _check(load().fsi_debug_residual(self.h, B, _ptr(U), _ptr(Uo), ptr, float(k), _ptr(R), _stream()),
@@ -216,3 +226,33 @@ class Problem:
         _check(load().fsi_profile_query(self.h, int(which), C.byref(n), C.byref(ms), C.byref(by)),
                "fsi_profile_query")
         return n.value, ms.value, by.value
+
+
+def drag_objective(workload: dict, **solver):
+    """torch.autograd.Function factory: J(peak, mu_s, lambda_s) = time-integrated drag.
+
+    forward() builds a problem with the given parameters, runs adjoint_gradient
+    (sequential fine solve, batched recompute, backward sweep) and returns J;
+    backward() returns grad_output * dJ/dq from the same call.
+    """
+    import torch
+
+    class DragObjective(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, peak, mu_s, lambda_s):
+            d = dict(workload)
+            d.update(inflow_peak=float(peak), mu_s=float(mu_s), lambda_s=float(lambda_s))
+            prob = Problem(make_params(d, precision="fp64", max_batch=d["N"], **solver))
+            U0 = torch.zeros(prob.n_nodes, 5, dtype=torch.float64, device="cuda")
+            prob.initial_state(U0)
+            J, grad, _ = prob.adjoint_gradient(d["T"], d["N"], d["m"], U0)
+            prob.close()
+            ctx.save_for_backward(torch.as_tensor(grad, dtype=torch.float64))
+            return torch.tensor(J, dtype=torch.float64)
+
+        @staticmethod
+        def backward(ctx, gout):
+            (grad,) = ctx.saved_tensors
+            return gout * grad[0], gout * grad[1], gout * grad[2]
+
+    return DragObjective

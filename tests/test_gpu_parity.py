@@ -227,3 +227,34 @@ def test_parareal_K_equals_N(fsi):
     for l in range(1, p["N"] + 1):
         err = field_rel(Ug[l], seq[l], norm="l2")
         assert max(err["v"], err["u"]) <= 1e-10, (l, err)
+
+
+def test_adjoint_gradient_parity(fsi):
+    """GPU discrete adjoint vs the oracle adjoint (same functional, same trajectory)."""
+    from oracle import adjoint as A
+    p = synth.workload("c1", T=0.04, N=2, dt_fine=0.01)
+    _say("case: adjoint gradient c1-small N=2 m=2")
+    D = Discretization(p)
+    U0 = np.zeros((D.mesh.n_nodes, 5))
+    Jo, go = A.adjoint_gradient(D, p, U0)
+    prob = fsi.Problem(fsi.make_params(p, precision="fp64", max_batch=2))
+    Jg, gg, st = prob.adjoint_gradient(p["T"], p["N"], p["m"], _dev(U0))
+    _say("J", Jg, Jo, "grad", gg, go, "krylov", st.krylov_total)
+    assert abs(Jg - Jo) <= 1e-10 * abs(Jo)
+    assert np.all(np.abs(gg - go) <= 1e-9 * np.abs(go)), (gg, go)
+
+
+def test_drag_objective_autograd(fsi):
+    """torch.autograd.Function around the adjoint: backward returns the adjoint gradient."""
+    p = synth.workload("c1", T=0.02, N=1, dt_fine=0.01)
+    _say("case: autograd drag objective c1-small")
+    Fn = fsi.drag_objective(p)
+    q = [torch.tensor(p[k], dtype=torch.float64, requires_grad=True) for k in ("inflow_peak", "mu_s", "lambda_s")]
+    J = Fn.apply(*q)
+    J.backward()
+    from oracle import adjoint as A
+    D = Discretization(p)
+    Jo, go = A.adjoint_gradient(D, p, np.zeros((D.mesh.n_nodes, 5)))
+    assert abs(J.item() - Jo) <= 1e-10 * abs(Jo)
+    for i in range(3):
+        assert abs(q[i].grad.item() - go[i]) <= 1e-9 * abs(go[i])
