@@ -32,12 +32,36 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+METRIC = "fine-propagator dof\u00b7steps/s batched vs sequential slices at 1e-6 rel; HBM GB/s"
 # kernel families timed by the library (HIP events on the call's stream), in fsi_profile_query order
 FAMILIES = ("smoother_spmv_fine", "krylov_spmv_fine", "jacobian_elem", "residual", "vanka_update_fine",
             "smoother_coarser_levels", "coarsest_solve")
-KERNEL_NAMES = {"smoother_spmv_fine": "k_spmv (Vanka residual, finest level)",
+KERNEL_NAMES = {"smoother_spmv_fine": "k_spmv_node<double> (Vanka residual, finest level)",
                 "vanka_update_fine": "k_vanka_update (finest level)",
                 "krylov_spmv_fine": "k_spmv (Krylov product, finest level)"}
+
+
+def counter_traffic(kernel_family, prec):
+    """HBM bytes per launch of the dominant kernel from the committed counter runs, or None.
+
+    profiles/traffic.json records FETCH_SIZE/WRITE_SIZE means (calibrated with a
+    copy kernel) and a hash of the kernel's source at the time of the runs; a
+    changed kernel gives None.
+    """
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if kernel_family != "smoother_spmv_fine" or prec != "fp64" or not os.path.exists(path):
+        return None
+    tr = json.load(open(path))
+    src = open(os.path.join(ROOT, "paper_1907_01252_amd", "csrc", "solver.hip")).read()
+    i = src.index("__global__ void __launch_bounds__(256) k_spmv_node(")
+    body = src[i:src.index("\n}\n", i) + 3]
+    hdr = open(os.path.join(ROOT, "paper_1907_01252_amd", "csrc", "fsi_internal.h")).read()
+    j = hdr.index("__host__ __device__ inline size_t jidx(")
+    jb = hdr[j:hdr.index("}\n", j) + 2]
+    if hashlib.sha256((body + jb).encode()).hexdigest()[:16] != tr["source_hash"]:
+        return None
+    return tr["traffic_bytes_per_launch"]
 
 
 def main():
@@ -52,6 +76,13 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-seq", action="store_true")
+    ap.add_argument("--steps-per-slice", type=int, default=None,
+                    help="override m (shorter sweeps for hardware-counter runs; same kernels and sizes)")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="before the sweep, copy this many MB with a plain device copy (counter calibration)")
+    ap.add_argument("--no-profile-sweep", action="store_true")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="time one adjoint_gradient call of the c4 workload instead of the fine sweep")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU: the fine sweep's slices are batched on a single "
@@ -63,9 +94,14 @@ def main():
     from paper_1907_01252_amd import fsi
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.adjoint:
+        return adjoint_bench(args)
     p = synth.workload(args.workload, seed=0)
     prec = args.precision or p["precision"]
     N, m, M, dl = p["N"], p["m"], p["M"], p["slice_len"]
+    if args.steps_per_slice:
+        dl = dl * args.steps_per_slice / m
+        m, M = args.steps_per_slice, 1
     prob = fsi.Problem(fsi.make_params(p, precision=prec, max_batch=N))
     nd = prob.n_dofs
     dev = "cuda"
@@ -81,6 +117,14 @@ def main():
     t0s = [l * dl for l in range(N)]
     Uout = torch.zeros_like(Uin)
 
+    if args.calib_copy_mb:
+        n = args.calib_copy_mb * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     # ---- warmup + timed batched sweeps
     for _ in range(args.warmup):
         prob.fine_propagate(N, t0s, dl, m, Uin, Uout)
@@ -95,13 +139,16 @@ def main():
     wall = (t_b - t_a) / args.steps
     # one more sweep of the same workload with HIP events around every launch of the
     # profiled kernel families (kernels launched directly, not replayed from graphs)
-    prob.profile_enable(True)
-    t_p = time.perf_counter()
-    prob.fine_propagate(N, t0s, dl, m, Uin, Uout)
-    torch.cuda.synchronize()
-    prof_wall = time.perf_counter() - t_p
-    prob.profile_enable(False)
-    fams = {name: prob.profile_query(i) for i, name in enumerate(FAMILIES)}
+    prof_wall = 0.0
+    fams = {name: (0, 0.0, 0.0) for name in FAMILIES}
+    if not args.no_profile_sweep:
+        prob.profile_enable(True)
+        t_p = time.perf_counter()
+        prob.fine_propagate(N, t0s, dl, m, Uin, Uout)
+        torch.cuda.synchronize()
+        prof_wall = time.perf_counter() - t_p
+        prob.profile_enable(False)
+        fams = {name: prob.profile_query(i) for i, name in enumerate(FAMILIES)}
     dof_steps = nd * m * N
     value = dof_steps / wall
 
@@ -148,7 +195,7 @@ def main():
                 errs[f] = float(np.linalg.norm(g[:, sl] - ref[:, sl]) / np.linalg.norm(ref[:, sl]))
             acc = {"max_rel_err": max(errs.values()), "per_field": errs, "gate": 1e-6,
                    "pass": max(errs.values()) <= 1e-6, "sample": f"slice {l}, {ns} steps vs FP64 oracle"}
-        cpu = {"value": nd * done / cpu_wall, "unit": "dof*steps/s", "cores": int(threads),
+        cpu = {"value": nd * done / cpu_wall, "unit": "dof\u00b7steps/s", "cores": int(threads),
                "kind": "oracle",
                "sample": f"slice {l} of {args.workload}: {done} Newton-SuperLU steps, {cpu_wall:.1f} s"}
 
@@ -157,9 +204,9 @@ def main():
     dn, dms, dby = fams[dom]
     achieved = dby / (dms * 1e-3) / 1e9 if dms > 0 else None
     out = {
-        "metric": "fine-propagator dof*steps/s, batched slices (FP64 oracle-gated); HBM GB/s of the dominant kernel",
+        "metric": METRIC,
         "value": value,
-        "unit": "dof*steps/s",
+        "unit": "dof\u00b7steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
@@ -177,7 +224,8 @@ def main():
         "sequential": seq,
         "speedup_batched_vs_sequential": (value / seq["value"]) if seq else None,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
+                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+                     "traffic": counter_traffic(dom, prec) if args.workload == "c2" else None,
                      "kernel": KERNEL_NAMES.get(dom, dom), "launches": dn,
                      "mean_launch_us": 1e3 * dms / max(dn, 1), "bytes_per_launch": dby / max(dn, 1)},
         "profiled_sweep_ms": 1e3 * prof_wall,
@@ -187,6 +235,32 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
+
+
+def adjoint_bench(args):
+    """One adjoint_gradient call: J = time-integrated drag over [0, T], gradient w.r.t. (peak, mu_s, lambda_s)."""
+    import torch
+    import synth
+    from paper_1907_01252_amd import fsi
+    name = "c4" if args.workload == "c2" else args.workload
+    p = synth.workload(name, seed=0)
+    prob = fsi.Problem(fsi.make_params(p, precision="fp64", max_batch=p["N"]))
+    U0 = torch.zeros(prob.n_nodes, 5, dtype=torch.float64, device="cuda")
+    prob.initial_state(U0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J, g, st = prob.adjoint_gradient(p["T"], p["N"], p["m"], U0)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    steps = p["N"] * p["m"]
+    print(json.dumps({
+        "metric": "adjoint gradient of the time-integrated drag: wall time of one call",
+        "value": wall, "unit": "s", "higher_is_better": False, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{name}: 2d ALE-FSI, {prob.n_dofs} unknowns, {p['N']} slices x {p['m']} steps, T={p['T']}"},
+        "J": J, "grad": {"inflow_peak": g[0], "mu_s": g[1], "lambda_s": g[2]},
+        "newton_forward": st.newton_total, "krylov_total": st.krylov_total,
+        "krylov_backward": st.krylov_its[0], "steps": steps, "ms_per_backward_step": None,
+    }))
 
 
 if __name__ == "__main__":
