@@ -81,6 +81,8 @@ def main():
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="before the sweep, copy this many MB with a plain device copy (counter calibration)")
     ap.add_argument("--no-profile-sweep", action="store_true")
+    ap.add_argument("--set", action="append", default=[], metavar="KEY=VALUE",
+                    help="solver parameter override (fsi_params field), e.g. vanka_sweeps_coarse=1")
     ap.add_argument("--adjoint", action="store_true",
                     help="time one adjoint_gradient call of the c4 workload instead of the fine sweep")
     args = ap.parse_args()
@@ -102,7 +104,8 @@ def main():
     if args.steps_per_slice:
         dl = dl * args.steps_per_slice / m
         m, M = args.steps_per_slice, 1
-    prob = fsi.Problem(fsi.make_params(p, precision=prec, max_batch=N))
+    overrides = {kv.split("=")[0]: float(kv.split("=")[1]) for kv in args.set}
+    prob = fsi.Problem(fsi.make_params(p, precision=prec, max_batch=N, **overrides))
     nd = prob.n_dofs
     dev = "cuda"
 
@@ -219,7 +222,8 @@ def main():
         "config": {"workload": f"{args.workload}: 2d ALE-FSI channel+bar, {p['level']}-level-refined "
                                f"{128 if p['level'] == 3 else 2 ** p['level'] * 16}x{2 ** p['level'] * 4} Q1, "
                                f"{nd} unknowns, {N} slices x {m} steps of {p['k_fine']:.6g}",
-                   "slices": N, "steps_per_slice": m, "unknowns": nd, "precision": prec},
+                   "slices": N, "steps_per_slice": m, "unknowns": nd, "precision": prec,
+                   "solver_overrides": overrides},
         "newton_per_sweep": stats[-1][0], "krylov_per_sweep": stats[-1][1],
         "sequential": seq,
         "speedup_batched_vs_sequential": (value / seq["value"]) if seq else None,

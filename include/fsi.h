@@ -74,12 +74,18 @@ typedef struct {
   int32_t vanka_sweeps;      /* pre- and post-smoothing sweeps per level */
   double vanka_omega;        /* Vanka damping */
   double newton_rtol;        /* stop when every field's update <= rtol * |field|_inf */
-  double lin_rtol;           /* FGMRES relative tolerance of the row-scaled residual */
+  double lin_rtol;           /* smallest FGMRES relative tolerance (row-scaled residual); the
+                                tolerance of Newton iteration j > 1 of a slice is
+                                min(1e-2, max(lin_rtol, 0.1 newton_rtol / e)), e the error
+                                estimate after iteration j - 1 */
   int32_t max_batch;         /* largest number of slices per call */
+  int32_t vanka_sweeps_coarse; /* pre- and post-smoothing sweeps on the levels below the finest */
   int32_t precond_lag;       /* 0: rebuild the multigrid preconditioner (coarse operators, Vanka
                                 inverses, coarsest factorisation) at every Newton iteration;
                                 1: only at the first Newton iteration of each time step (the
                                 Krylov operator is the exact Jacobian either way) */
+  double lin_rtol_first;     /* FGMRES relative tolerance of the first Newton iteration of a step
+                                (0 < lin_rtol_first < 1) */
 } fsi_params;
 
 #define FSI_MAX_SLICES 1024

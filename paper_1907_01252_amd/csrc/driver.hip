@@ -91,6 +91,7 @@ struct fsi_problem {
   double vc_k = -1.0;
   bool vc_mixed = false;
   bool use_graphs = true;
+  bool verbose = false;   // FSI_VERBOSE=1: Newton progress of slice 0 on stderr
   // library-owned stream for the propagators (capturable; ordered after the caller's stream)
   hipStream_t ist = nullptr;
   hipEvent_t iev = nullptr;
@@ -102,6 +103,8 @@ struct fsi_problem {
   double *H = nullptr, *hcol = nullptr, *hcol2 = nullptr, *cs = nullptr, *sn = nullptr, *gv = nullptr,
          *res = nullptr, *beta0 = nullptr, *beta = nullptr, *ycoef = nullptr, *partial = nullptr;
   int *gstate = nullptr, *ncol = nullptr;
+  double* ltol = nullptr;              // per-slice FGMRES tolerance (device)
+  std::vector<double> ltol_h;
   // coarsest level block LU and explicit inverse
   double *cDinv = nullptr, *cW = nullptr, *cL = nullptr, *cY = nullptr;
   // adjoint scratch (allocated on the first adjoint call)
@@ -412,13 +415,12 @@ fsi_status assemble_levels(fsi_problem* pb, int B, const StepPar& sp, const int*
       k_vanka_factor<S><<<dim3((g.ncell * 32 + TPB - 1) / TPB, B), TPB, 0, st>>>(g, sp.k, (const S*)lv.J,
                                                                               (S*)lv.Ainv, act);
     } else {
-      const size_t lds = (size_t)3 * pb->cbs * pb->cbs * sizeof(double);
-      const int n0 = g.nn * NC;
-      k_coarse_factor<S><<<B, 64, lds, st>>>(g, sp.k, (const S*)lv.J, pb->cbs, pb->cnsb, pb->cDinv, pb->cW, pb->cL,
-                                             act);
-      k_coarse_inverse<<<dim3((n0 + 63) / 64, B), 64, 0, st>>>(g, pb->cbs, pb->cnsb, pb->cDinv, pb->cW, pb->cL, pb->cY,
-                                                              act);
-      k_coarse_inverse_pack<S><<<dim3(128, B), TPB, 0, st>>>(g, pb->cbs, pb->cnsb, pb->cY, (S*)pb->cAinv, act);
+      const size_t lds_f = (size_t)5 * pb->cbs * pb->cbs * sizeof(double);
+      const size_t lds_i = (size_t)3 * pb->cbs * pb->cbs * sizeof(double);
+      k_coarse_factor<S><<<B, TPB, lds_f, st>>>(g, sp.k, (const S*)lv.J, pb->cbs, pb->cnsb, pb->cDinv, pb->cW,
+                                                pb->cL, act);
+      k_coarse_inverse<S><<<dim3(pb->cnsb, B), TPB, lds_i, st>>>(g, pb->cbs, pb->cnsb, pb->cDinv, pb->cW, pb->cL,
+                                                                 pb->cY, (S*)pb->cAinv, act);
     }
     HIPCHK(hipGetLastError());
   }
@@ -469,14 +471,13 @@ void smooth(fsi_problem* pb, int l, int B, double k, int sweeps, bool zero_first
 template <class S>
 void vcycle(fsi_problem* pb, int B, double k, const S* rhs, S* out, const int* act, hipStream_t st) {
   const int L = pb->nlev - 1;
-  const int nu = pb->p.vanka_sweeps;
   // level L uses rhs/out directly; lower levels their own b_/x_
   for (int l = L; l >= 1; --l) {
     Level& lv = pb->lev[l];
     Level& lc = pb->lev[l - 1];
     const S* b = (l == L) ? rhs : (const S*)lv.b_;
     S* x = (l == L) ? out : (S*)lv.x_;
-    smooth<S>(pb, l, B, k, nu, true, x, b, act, st);
+    smooth<S>(pb, l, B, k, l == L ? pb->p.vanka_sweeps : pb->p.vanka_sweeps_coarse, true, x, b, act, st);
     const Geom g = lv.geom();
     spmv<S>(g, B, k, (const S*)lv.J, x, b, nullptr, (S*)lv.r_, act, st);
     k_restrict<S><<<grid1(lc.nn, B), TPB, 0, st>>>(lc.geom(), g, (const S*)lv.r_, (S*)lc.b_, act);
@@ -494,7 +495,7 @@ void vcycle(fsi_problem* pb, int B, double k, const S* rhs, S* out, const int* a
     const S* b = (l == L) ? rhs : (const S*)lv.b_;
     S* x = (l == L) ? out : (S*)lv.x_;
     k_prolong_add<S><<<grid1(lv.nn, B), TPB, 0, st>>>(lv.geom(), lc.geom(), (const S*)lc.x_, x, act);
-    smooth<S>(pb, l, B, k, nu, false, x, b, act, st);
+    smooth<S>(pb, l, B, k, l == L ? pb->p.vanka_sweeps : pb->p.vanka_sweeps_coarse, false, x, b, act, st);
   }
 }
 
@@ -547,9 +548,9 @@ fsi_status fgmres(fsi_problem* pb, int B, double k, std::vector<int>& kits, hipS
   S* tmp = (S*)pb->tmp;
   const int chunk = 2048;
   const int nchunk = (n + chunk - 1) / chunk;
-  const double tol = pb->p.lin_rtol;
   const dim3 gb((B + 63) / 64), tb(64);
   std::vector<int> hstate(B);
+  HIPCHK(hipMemcpyAsync(pb->ltol, pb->ltol_h.data(), B * sizeof(double), hipMemcpyHostToDevice, st));
   k_fill<S><<<1024, TPB, 0, st>>>((size_t)B * n, xs, (S)0);
   HIPCHK(hipMemcpyAsync(pb->gact, pb->nact, B * sizeof(int), hipMemcpyDeviceToDevice, st));
   int total = 0;
@@ -564,7 +565,8 @@ fsi_status fgmres(fsi_problem* pb, int B, double k, std::vector<int>& kits, hipS
     }
     k_multidot<S><<<dim3(nchunk, B), RED_T, 0, st>>>(n, 1, V, vb, V, vb, 0, chunk, pb->partial, nchunk, pb->gact);
     k_reduce_partials<<<B, 64, 0, st>>>(1, nchunk, pb->partial, pb->beta, 1, pb->gact);
-    k_init_cycle<<<gb, tb, 0, st>>>(R, cycle, pb->beta, pb->beta0, pb->gv, pb->gstate, pb->ncol, tol, pb->gact, B);
+    k_init_cycle<<<gb, tb, 0, st>>>(R, cycle, pb->beta, pb->beta0, pb->gv, pb->gstate, pb->ncol, pb->ltol, pb->gact,
+                                    B);
     k_update_gact<<<gb, tb, 0, st>>>(pb->nact, pb->gstate, pb->gact, B);
     k_scale<S><<<grid1(n, B), TPB, 0, st>>>(n, V, vb, V, vb, pb->beta, 1, 1, pb->gact);
     HIPCHK(hipGetLastError());
@@ -605,7 +607,7 @@ fsi_status fgmres(fsi_problem* pb, int B, double k, std::vector<int>& kits, hipS
       k_cgs_combine<<<gb, tb, 0, st>>>(j, pb->hcol, pb->hcol2, pb->res, pb->gact, B);
       // V_{j+1} = w / ||w||
       k_scale<S><<<grid1(n, B), TPB, 0, st>>>(n, a, (size_t)n, V + (size_t)(j + 1) * n, vb, pb->res, 1, 1, pb->gact);
-      k_givens<<<gb, tb, 0, st>>>(j, R, pb->H, pb->hcol, pb->cs, pb->sn, pb->gv, pb->res, pb->beta0, tol,
+      k_givens<<<gb, tb, 0, st>>>(j, R, pb->H, pb->hcol, pb->cs, pb->sn, pb->gv, pb->res, pb->beta0, pb->ltol,
                                   pb->gstate, pb->ncol, pb->gact, B);
       HIPCHK(hipGetLastError());
       for (int b = 0; b < B; ++b)
@@ -643,9 +645,18 @@ fsi_status newton_solve_step(fsi_problem* pb, int B, const StepPar& sp, std::vec
   Level& F = pb->lev[pb->nlev - 1];
   const int nn = F.nn;
   const int maxit = pb->p.newton_maxit;
-  std::vector<double> prev((size_t)B * 3, -1.0), hm((size_t)B * 6);
+  std::vector<double> prev((size_t)B * 3, -1.0), hm((size_t)B * 6), est_prev(B, 1e300);
   std::vector<int> nact(hact);
   for (int it = 1; it <= maxit; ++it) {
+    // per-slice Krylov tolerance (inexact Newton): the first iteration only has to bring
+    // the extrapolated guess close enough for the quadratic phase; later ones are tight
+    // while the error estimate is large and loose once it is near the Newton tolerance,
+    // where the update only has to be resolved to a few digits:
+    // eta = clamp(0.1 rtol / est, lin_rtol, 1e-2)
+    for (int b = 0; b < B; ++b)
+      pb->ltol_h[b] = it == 1 ? pb->p.lin_rtol_first
+                              : std::min(1e-2, std::max(pb->p.lin_rtol, 0.1 * pb->p.newton_rtol / est_prev[b]));
+    const int k0 = rs.krylov[0];
     HIPCHK(hipMemcpyAsync(pb->nact, nact.data(), B * sizeof(int), hipMemcpyHostToDevice, st));
     CHK(residual(pb, B, sp, pb->U, pb->Uold, pb->Res, pb->nact, st));
     CHK(assemble_levels<S>(pb, B, sp, pb->nact, st, it == 1 || pb->p.precond_lag == 0));
@@ -681,6 +692,11 @@ fsi_status newton_solve_step(fsi_problem* pb, int B, const StepPar& sp, std::vec
         hact[b] = 0;
         continue;
       }
+      if (pb->verbose && b == 0)
+        std::fprintf(stderr, "fsi newton it %d slice 0: rel(v,u,p) = %.3e %.3e %.3e  est %.3e  krylov %d\n", it,
+                     hm[3] > 0 ? hm[0] / hm[3] : hm[0], hm[4] > 0 ? hm[1] / hm[4] : hm[1],
+                     hm[5] > 0 ? hm[2] / hm[5] : hm[2], est, rs.krylov[0] - k0);
+      est_prev[b] = est;
       if (worst <= pb->p.newton_rtol || est <= pb->p.newton_rtol) {
         nact[b] = 0;
       } else {
@@ -887,8 +903,7 @@ fsi_status adjoint_run(fsi_problem* pb, double T, int N, int m, const double* U0
   double J = 0.0;
   for (size_t s = 0; s < S; ++s) J += k * dv[s];
   // backward sweep: (dR_s/dU^s)^T lam_s = -k dD/dU(U^s) - (dR_{s+1}/dU^s)^T lam_{s+1}
-  const double saved_tol = pb->p.lin_rtol;
-  pb->p.lin_rtol = pb->adj_rtol;
+  pb->ltol_h[0] = pb->adj_rtol;
   const int one = 1;
   HIPCHK(hipMemcpyAsync(pb->nact, &one, sizeof(int), hipMemcpyHostToDevice, st));
   fsi_status ret = FSI_OK;
@@ -922,7 +937,6 @@ fsi_status adjoint_run(fsi_problem* pb, double T, int N, int m, const double* U0
     HIPCHK(hipGetLastError());
     std::swap(pb->lam, pb->lamn);
   }
-  pb->p.lin_rtol = saved_tol;
   double gh[3] = {0, 0, 0};
   HIPCHK(hipMemcpyAsync(gh, pb->agrad, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
@@ -976,8 +990,9 @@ fsi_status fsi_setup(const fsi_params* prm, fsi_problem** out) {
   const fsi_params& p = *prm;
   if (p.dim != 2 || p.level < 1 || p.level > MAXLEV - 2 || p.max_batch < 1 || p.max_batch > FSI_MAX_SLICES ||
       p.gmres_restart < 1 || p.gmres_restart > 63 || p.newton_maxit < 1 || p.vanka_sweeps < 1 ||
+      p.vanka_sweeps_coarse < 1 ||
       p.gmres_maxit < 1 || (p.precision != FSI_FP64 && p.precision != FSI_MIXED) ||
-      (p.precond_lag != 0 && p.precond_lag != 1))
+      (p.precond_lag != 0 && p.precond_lag != 1) || !(p.lin_rtol_first > 0.0 && p.lin_rtol_first < 1.0))
     return FSI_ERR_ARG;
   for (int a = 0; a < 2; ++a) {
     if (p.nseg[a] < 1 || p.nseg[a] > 4) return FSI_ERR_ARG;
@@ -997,6 +1012,8 @@ fsi_status fsi_setup(const fsi_params* prm, fsi_problem** out) {
     // FSI_GRAPHS=0 replays nothing from graphs (every kernel launched directly)
     const char* e = std::getenv("FSI_GRAPHS");
     pb->use_graphs = !(e && e[0] == '0');
+    const char* v = std::getenv("FSI_VERBOSE");
+    pb->verbose = v && v[0] == '1';
   }
   fsi_status s = FSI_OK;
   for (int l = 0; l < pb->nlev && s == FSI_OK; ++l) s = build_level(pb, l);
@@ -1042,18 +1059,20 @@ fsi_status fsi_setup(const fsi_params* prm, fsi_problem** out) {
   A_(dalloc(pb, &pb->partial, (size_t)B * 64 * ((ndof + 2047) / 2048 + 1)));
   A_(dalloc(pb, &pb->gstate, B));
   A_(dalloc(pb, &pb->ncol, B));
+  A_(dalloc(pb, &pb->ltol, B));
+  pb->ltol_h.assign(B, p.lin_rtol);
   A_(dalloc(pb, &pb->cDinv, cb2));
   A_(dalloc(pb, &pb->cW, cb2));
   A_(dalloc(pb, &pb->cL, cb2));
-  A_(dalloc(pb, &pb->cY, (size_t)B * C.nn * NC * pb->cnsb * pb->cbs));
+  A_(dalloc(pb, &pb->cY, (size_t)B * pb->cnsb * pb->cnsb * pb->cbs * pb->cbs));
   A_(dalloc_bytes(pb, &pb->cAinv, (size_t)B * C.nn * NC * C.nn * NC * ss));
   A_(dalloc(pb, &pb->npart, (size_t)B * 6 * pb->nchunk_n));
   A_(dalloc(pb, &pb->nmax, (size_t)B * 6));
 #undef A_
   if (hipFuncSetAttribute((const void*)k_coarse_factor<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          3 * pb->cbs * pb->cbs * sizeof(double)) != hipSuccess ||
+                          5 * pb->cbs * pb->cbs * sizeof(double)) != hipSuccess ||
       hipFuncSetAttribute((const void*)k_coarse_factor<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          3 * pb->cbs * pb->cbs * sizeof(double)) != hipSuccess) {
+                          5 * pb->cbs * pb->cbs * sizeof(double)) != hipSuccess) {
     fsi_destroy(pb);
     return FSI_ERR_HIP;
   }

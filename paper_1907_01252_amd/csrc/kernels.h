@@ -47,10 +47,9 @@ __global__ void k_prolong_add(Geom gf, Geom gc, const S* xc, S* xf, const int* a
 template <class S>
 __global__ void k_coarse_factor(Geom g, double k, const S* J, int bsz, int nsb, double* Dinv, double* W, double* Lb,
                                 const int* active);
-__global__ void k_coarse_inverse(Geom g, int bsz, int nsb, const double* Dinv, const double* W, const double* Lb,
-                                 double* Ainv0, const int* active);
 template <class S>
-__global__ void k_coarse_inverse_pack(Geom g, int bsz, int nsb, const double* Ainv0, S* AinvS, const int* active);
+__global__ void k_coarse_inverse(Geom g, int bsz, int nsb, const double* Dinv, const double* W, const double* Lb,
+                                 double* Ysc, S* AinvS, const int* active);
 template <class S>
 __global__ void k_coarse_gemv(Geom g, const S* AinvS, const S* bvec, S* xvec, const int* active);
 template <class S>
@@ -69,9 +68,9 @@ __global__ void k_unscale(int n, const S* X, size_t sxb, const double* D, S* Y, 
 template <class S>
 __global__ void k_scale_rhs(int n, const double* X, const double* D, S* Y, size_t syb, const int* active);
 __global__ void k_givens(int j, int R, double* H, const double* hcol, double* cs, double* sn, double* gv, double* res,
-                         const double* beta0, double tol, int* state, int* ncol, const int* active, int B);
+                         const double* beta0, const double* tolv, int* state, int* ncol, const int* active, int B);
 __global__ void k_init_cycle(int R, int cycle, const double* beta2, double* beta0, double* gv, int* state, int* ncol,
-                             double tol, const int* gact, int B);
+                             const double* tolv, const int* gact, int B);
 __global__ void k_cgs_combine(int j, double* hcol, const double* hcol2, const double* hn2, const int* active, int B);
 __global__ void k_update_gact(const int* nact, const int* state, int* gact, int B);
 __global__ void k_trisolve(int R, const double* H, const double* gv, const int* ncol, double* y, const int* active,

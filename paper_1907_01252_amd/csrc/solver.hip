@@ -385,70 +385,81 @@ __device__ inline int coarse_gidx(const Geom& g, int K, int l) {
   return (i + (g.nx + 1) * jn) * NC + c;
 }
 
-// One wave per slice (no cross-wave barriers); dynamic LDS holds [Delta | I]
-// (bs x 2bs) and a bs x bs tile.  Gauss-Jordan with partial pivoting.
+// C = alpha A B for bs x bs row-major tiles in LDS (all threads of the block)
+__device__ inline void tile_gemm(int bsz, const double* A, const double* Bm, double* C, double alpha) {
+  for (int e = threadIdx.x; e < bsz * bsz; e += blockDim.x) {
+    const int r = e / bsz, c = e % bsz;
+    double s = 0.0;
+    for (int q = 0; q < bsz; ++q) s += A[r * bsz + q] * Bm[q * bsz + c];
+    C[e] = alpha * s;
+  }
+}
+
+// One workgroup per slice.  LDS: [Delta | I] (bs x 2bs), L_K, U_K and W_{K-1}
+// (bs x bs each).  Gauss-Jordan with partial pivoting: wave 0 finds the pivot and
+// the row factors, then every thread owns columns of [Delta | I] for the update.
 template <class S>
-__global__ void __launch_bounds__(64) k_coarse_factor(Geom g, double k, const S* __restrict__ J, int bsz, int nsb,
-                                                      double* __restrict__ Dinv, double* __restrict__ W,
-                                                      double* __restrict__ Lb, const int* __restrict__ active) {
+__global__ void __launch_bounds__(256) k_coarse_factor(Geom g, double k, const S* __restrict__ J, int bsz, int nsb,
+                                                       double* __restrict__ Dinv, double* __restrict__ W,
+                                                       double* __restrict__ Lb, const int* __restrict__ active) {
   extern __shared__ double lds[];
   const int bs = blockIdx.x;
   if (active && !active[bs]) return;
   const int tid = threadIdx.x, nt = blockDim.x;
   const S* jb = J + (size_t)bs * jslice(g.nn);
   const int w2 = 2 * bsz;
-  double* M = lds;                 // bsz x 2bsz
-  double* T = lds + bsz * w2;      // bsz x bsz
-  __shared__ double fac[128];
-  __shared__ int colmap[128];
-  __shared__ int usedf[128];
-  const size_t B2 = (size_t)bsz * bsz;
+  const int B2i = bsz * bsz;
+  double* M = lds;                  // bsz x 2bsz
+  double* Lt = M + bsz * w2;        // bsz x bsz
+  double* Ut = Lt + B2i;
+  double* Wp = Ut + B2i;
+  __shared__ double fac[64];
+  __shared__ int colmap[64];
+  __shared__ int usedf[64];
+  __shared__ int piv_row;
+  __shared__ double piv_val;
+  const size_t B2 = (size_t)B2i;
   double* dinv = Dinv + (size_t)bs * nsb * B2;
   double* w = W + (size_t)bs * nsb * B2;
   double* lb = Lb + (size_t)bs * nsb * B2;
   for (int K = 0; K < nsb; ++K) {
-    for (int e = tid; e < bsz * bsz; e += nt) {
+    for (int e = tid; e < B2i; e += nt) {
       const int r = e / bsz, c = e % bsz;
       M[r * w2 + c] = coarse_entry<S>(g, k, jb, K, r, K, c);
       M[r * w2 + bsz + c] = (r == c) ? 1.0 : 0.0;
-    }
-    if (K > 0) {
-      for (int e = tid; e < bsz * bsz; e += nt) {
-        const int r = e / bsz, c = e % bsz;
-        const double v = coarse_entry<S>(g, k, jb, K, r, K - 1, c);
-        T[e] = v;
-        lb[K * B2 + e] = v;
-      }
-      __syncthreads();
-      const double* wp = w + (K - 1) * B2;
-      for (int e = tid; e < bsz * bsz; e += nt) {
-        const int r = e / bsz, c = e % bsz;
-        double s = 0.0;
-        for (int q = 0; q < bsz; ++q) s += T[r * bsz + q] * wp[q * bsz + c];
-        M[r * w2 + c] -= s;
-      }
+      if (K > 0) Lt[e] = coarse_entry<S>(g, k, jb, K, r, K - 1, c);
+      if (K < nsb - 1) Ut[e] = coarse_entry<S>(g, k, jb, K, r, K + 1, c);
     }
     for (int e = tid; e < bsz; e += nt) usedf[e] = 0;
     __syncthreads();
-    for (int jc = 0; jc < bsz; ++jc) {
-      // pivot search: wave-wide arg-max over the unused rows (bsz <= 128: two rows per lane)
-      double best = -1.0;
-      int bi = 0;
-      for (int r = tid; r < bsz; r += nt) {
-        const double v = usedf[r] ? -1.0 : fabs(M[r * w2 + jc]);
-        if (v > best) { best = v; bi = r; }
+    if (K > 0) {
+      for (int e = tid; e < B2i; e += nt) {
+        lb[K * B2 + e] = Lt[e];
+        const int r = e / bsz, c = e % bsz;
+        double s = 0.0;
+        for (int q = 0; q < bsz; ++q) s += Lt[r * bsz + q] * Wp[q * bsz + c];
+        M[r * w2 + c] -= s;
       }
-      for (int off = 32; off > 0; off >>= 1) {
-        const double ob = __shfl_xor(best, off, 64);
-        const int oi = __shfl_xor(bi, off, 64);
-        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-      }
-      const int pr = __shfl(bi, 0, 64);
-      double pv = M[pr * w2 + jc];
-      if (pv == 0.0) pv = 1.0;
-      for (int r = tid; r < bsz; r += nt) fac[r] = (r == pr) ? 0.0 : M[r * w2 + jc] / pv;
-      if (tid == 0) { usedf[pr] = 1; colmap[jc] = pr; }
       __syncthreads();
+    }
+    for (int jc = 0; jc < bsz; ++jc) {
+      if (tid < 64) {
+        double best = -1.0;
+        int bi = 0;
+        if (tid < bsz && !usedf[tid]) { best = fabs(M[tid * w2 + jc]); bi = tid; }
+        for (int off = 32; off > 0; off >>= 1) {
+          const double ob = __shfl_xor(best, off, 64);
+          const int oi = __shfl_xor(bi, off, 64);
+          if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+        }
+        double pv = M[bi * w2 + jc];
+        if (pv == 0.0) pv = 1.0;
+        if (tid < bsz) fac[tid] = (tid == bi) ? 0.0 : M[tid * w2 + jc] / pv;
+        if (tid == 0) { usedf[bi] = 1; colmap[jc] = bi; piv_row = bi; piv_val = pv; }
+      }
+      __syncthreads();
+      const int pr = piv_row;
+      const double pv = piv_val;
       for (int c = tid; c < w2; c += nt) {
         const double pc = M[pr * w2 + c];
         for (int r = 0; r < bsz; ++r) M[r * w2 + c] -= fac[r] * pc;
@@ -456,87 +467,78 @@ __global__ void __launch_bounds__(64) k_coarse_factor(Geom g, double k, const S*
       }
       __syncthreads();
     }
-    for (int e = tid; e < bsz * bsz; e += nt) {
+    // Dinv_K (row jc of the inverse sits in the row that pivoted column jc), kept in Lt for W
+    for (int e = tid; e < B2i; e += nt) {
       const int jr = e / bsz, c = e % bsz;
-      dinv[K * B2 + e] = M[colmap[jr] * w2 + bsz + c];
+      const double v = M[colmap[jr] * w2 + bsz + c];
+      dinv[K * B2 + e] = v;
+      Lt[e] = v;
     }
     __syncthreads();
     if (K < nsb - 1) {
-      for (int e = tid; e < bsz * bsz; e += nt) {
-        const int r = e / bsz, c = e % bsz;
-        T[e] = coarse_entry<S>(g, k, jb, K, r, K + 1, c);
-      }
+      tile_gemm(bsz, Lt, Ut, Wp, 1.0);   // W_K = Dinv_K U_K
       __syncthreads();
-      for (int e = tid; e < bsz * bsz; e += nt) {
-        const int r = e / bsz, c = e % bsz;
-        double s = 0.0;
-        for (int q = 0; q < bsz; ++q) s += dinv[K * B2 + r * bsz + q] * T[q * bsz + c];
-        w[K * B2 + e] = s;
-      }
+      for (int e = tid; e < B2i; e += nt) w[K * B2 + e] = Wp[e];
     }
     __syncthreads();
   }
 }
 
-// Explicit inverse from the block factors: column j of A^{-1} solves A x = e_j.
-// Grid (ceil(n0 / 64), B); each thread owns one column j and runs the block
-// forward / backward sweeps.  Scratch Y[b][q][j] holds the columns in block
-// order q (coalesced across the threads of a wave).  bsz <= 64.
-__global__ void __launch_bounds__(64) k_coarse_inverse(Geom g, int bsz, int nsb, const double* __restrict__ Dinv,
-                                                       const double* __restrict__ W, const double* __restrict__ Lb,
-                                                       double* __restrict__ Y, const int* __restrict__ active) {
-  const int bs = blockIdx.y;
+// Explicit inverse from the block factors, one workgroup per (column super-block
+// Kc, slice): the columns of block Kc solve A X = E_Kc.  Forward: Y_K = 0 (K < Kc),
+// Y_Kc = Dinv_Kc, Y_K = -Dinv_K L_K Y_{K-1}; backward: X_K = Y_K - W_K X_{K+1}.
+// Block products run on LDS tiles; Y blocks go through a global scratch.
+// The result is written in dof order, column-major: AinvS[b][j][i].
+template <class S>
+__global__ void __launch_bounds__(256) k_coarse_inverse(Geom g, int bsz, int nsb, const double* __restrict__ Dinv,
+                                                        const double* __restrict__ W, const double* __restrict__ Lb,
+                                                        double* __restrict__ Ysc, S* __restrict__ AinvS,
+                                                        const int* __restrict__ active) {
+  extern __shared__ double lds[];
+  const int Kc = blockIdx.x, bs = blockIdx.y;
   if (active && !active[bs]) return;
-  const int n0 = g.nn * NC;
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n0) return;
-  const size_t B2 = (size_t)bsz * bsz;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int B2i = bsz * bsz;
+  const size_t B2 = (size_t)B2i;
+  double* At = lds;
+  double* Y = At + B2i;
+  double* T = Y + B2i;
   const double* dinv = Dinv + (size_t)bs * nsb * B2;
   const double* w = W + (size_t)bs * nsb * B2;
   const double* lb = Lb + (size_t)bs * nsb * B2;
-  double* y = Y + (size_t)bs * n0 * (size_t)(nsb * bsz);
-  const int node = j / NC, c = j % NC, ii = node % (g.nx + 1), jn = node / (g.nx + 1);
-  const int Kj = ii / 2, lj = (((ii & 1) * (g.ny + 1)) + jn) * NC + c;
-  double t[64];
-  for (int K = 0; K < nsb; ++K) {
-    for (int l = 0; l < bsz; ++l) {
-      double v = (K == Kj && l == lj) ? 1.0 : 0.0;
-      if (K > 0) {
-        const double* L = lb + K * B2 + (size_t)l * bsz;
-        for (int q = 0; q < bsz; ++q) v -= L[q] * y[(size_t)((K - 1) * bsz + q) * n0 + j];
-      }
-      t[l] = v;
-    }
-    for (int l = 0; l < bsz; ++l) {
-      const double* D = dinv + K * B2 + (size_t)l * bsz;
-      double s = 0.0;
-      for (int q = 0; q < bsz; ++q) s += D[q] * t[q];
-      y[(size_t)(K * bsz + l) * n0 + j] = s;
-    }
-  }
-  for (int K = nsb - 2; K >= 0; --K)
-    for (int l = 0; l < bsz; ++l) {
-      const double* Wr = w + K * B2 + (size_t)l * bsz;
-      double s = 0.0;
-      for (int q = 0; q < bsz; ++q) s += Wr[q] * y[(size_t)((K + 1) * bsz + q) * n0 + j];
-      y[(size_t)(K * bsz + l) * n0 + j] -= s;
-    }
-}
-
-// Reorder to dof order in the solve type: AinvS[b][j][i] = (A^{-1})_{i j}.
-template <class S>
-__global__ void k_coarse_inverse_pack(Geom g, int bsz, int nsb, const double* __restrict__ Y,
-                                      S* __restrict__ AinvS, const int* __restrict__ active) {
-  const int bs = blockIdx.y;
-  if (active && !active[bs]) return;
+  double* ys = Ysc + ((size_t)bs * nsb + Kc) * nsb * B2;
   const int n0 = g.nn * NC;
-  const double* y = Y + (size_t)bs * n0 * (size_t)(nsb * bsz);
-  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < (size_t)n0 * n0;
-       e += (size_t)gridDim.x * blockDim.x) {
-    const int j = (int)(e / n0), i = (int)(e % n0);
-    const int node = i / NC, c = i % NC, ii = node % (g.nx + 1), jn = node / (g.nx + 1);
-    const int q = (ii / 2) * bsz + (((ii & 1) * (g.ny + 1)) + jn) * NC + c;
-    AinvS[(size_t)bs * n0 * n0 + e] = (S)y[(size_t)q * n0 + j];
+  S* out = AinvS + (size_t)bs * n0 * n0;
+  for (int e = tid; e < B2i; e += nt) { Y[e] = dinv[Kc * B2 + e]; ys[Kc * B2 + e] = Y[e]; }
+  __syncthreads();
+  for (int K = Kc + 1; K < nsb; ++K) {
+    for (int e = tid; e < B2i; e += nt) At[e] = lb[K * B2 + e];
+    __syncthreads();
+    tile_gemm(bsz, At, Y, T, 1.0);          // T = L_K Y_{K-1}
+    __syncthreads();
+    for (int e = tid; e < B2i; e += nt) At[e] = dinv[K * B2 + e];
+    __syncthreads();
+    tile_gemm(bsz, At, T, Y, -1.0);         // Y_K = -Dinv_K T
+    __syncthreads();
+    for (int e = tid; e < B2i; e += nt) ys[K * B2 + e] = Y[e];
+    __syncthreads();
+  }
+  // backward: Y holds X_{nsb-1}
+  for (int K = nsb - 1; K >= 0; --K) {
+    if (K < nsb - 1) {
+      for (int e = tid; e < B2i; e += nt) At[e] = w[K * B2 + e];
+      __syncthreads();
+      tile_gemm(bsz, At, Y, T, 1.0);        // T = W_K X_{K+1}
+      __syncthreads();
+      for (int e = tid; e < B2i; e += nt) Y[e] = (K >= Kc ? ys[K * B2 + e] : 0.0) - T[e];
+      __syncthreads();
+    }
+    for (int e = tid; e < B2i; e += nt) {
+      const int l = e / bsz, c = e % bsz;
+      const int i = coarse_gidx(g, K, l), j = coarse_gidx(g, Kc, c);
+      if (i >= 0 && j >= 0) out[(size_t)j * n0 + i] = (S)Y[e];
+    }
+    __syncthreads();
   }
 }
 
@@ -680,8 +682,8 @@ __global__ void k_scale_rhs(int n, const double* __restrict__ X, const double* _
 
 // Start of an FGMRES cycle: beta = ||r||, g = (beta, 0, ...), state and column count.
 __global__ void k_init_cycle(int R, int cycle, const double* __restrict__ beta2, double* __restrict__ beta0,
-                             double* __restrict__ gv, int* __restrict__ state, int* __restrict__ ncol, double tol,
-                             const int* __restrict__ gact, int B) {
+                             double* __restrict__ gv, int* __restrict__ state, int* __restrict__ ncol,
+                             const double* __restrict__ tolv, const int* __restrict__ gact, int B) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= B) return;
   ncol[b] = 0;
@@ -690,7 +692,7 @@ __global__ void k_init_cycle(int R, int cycle, const double* __restrict__ beta2,
   if (cycle == 0) beta0[b] = beta;
   for (int i = 0; i <= R; ++i) gv[(size_t)b * (R + 1) + i] = 0.0;
   gv[(size_t)b * (R + 1)] = beta;
-  state[b] = (beta <= tol * beta0[b] || beta == 0.0) ? 1 : 0;
+  state[b] = (beta <= tolv[b] * beta0[b] || beta == 0.0) ? 1 : 0;
 }
 
 // hcol[b][i] += hcol2[b][i] (i <= j); hcol[b][j+1] = ||w||^2
@@ -716,7 +718,7 @@ __global__ void k_update_gact(const int* __restrict__ nact, const int* __restric
 // state[b]: 0 running, 1 converged, 2 breakdown.
 __global__ void k_givens(int j, int R, double* __restrict__ H, const double* __restrict__ hcol,
                          double* __restrict__ cs, double* __restrict__ sn, double* __restrict__ gv,
-                         double* __restrict__ res, const double* __restrict__ beta0, double tol,
+                         double* __restrict__ res, const double* __restrict__ beta0, const double* __restrict__ tolv,
                          int* __restrict__ state, int* __restrict__ ncol, const int* __restrict__ active, int B) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= B) return;
@@ -743,7 +745,7 @@ __global__ void k_givens(int j, int R, double* __restrict__ H, const double* __r
   gv[(size_t)b * (R + 1) + j] = c * gj;
   gv[(size_t)b * (R + 1) + j + 1] = -s * gj;
   res[b] = fabs(gv[(size_t)b * (R + 1) + j + 1]);
-  if (res[b] <= tol * beta0[b]) state[b] = 1;
+  if (res[b] <= tolv[b] * beta0[b]) state[b] = 1;
   else if (hn <= 1e-300) state[b] = 2;
 }
 
@@ -885,7 +887,8 @@ __global__ void k_convert(size_t n, const A* __restrict__ X, B2* __restrict__ Y)
   template __global__ void k_prolong_add<S>(Geom, Geom, const S*, S*, const int*);                               \
   template __global__ void k_coarse_factor<S>(Geom, double, const S*, int, int, double*, double*, double*,       \
                                               const int*);                                                       \
-  template __global__ void k_coarse_inverse_pack<S>(Geom, int, int, const double*, S*, const int*);             \
+  template __global__ void k_coarse_inverse<S>(Geom, int, int, const double*, const double*, const double*,      \
+                                               double*, S*, const int*);                                          \
   template __global__ void k_coarse_gemv<S>(Geom, const S*, const S*, S*, const int*);                           \
   template __global__ void k_multidot<S>(int, int, const S*, size_t, const S*, size_t, size_t, int, double*, int, \
                                          const int*);                                                            \

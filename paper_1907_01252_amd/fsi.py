@@ -37,7 +37,8 @@ class Params(C.Structure):
         ("precision", C.c_int32), ("gmres_restart", C.c_int32), ("gmres_maxit", C.c_int32),
         ("newton_maxit", C.c_int32), ("vanka_sweeps", C.c_int32), ("vanka_omega", C.c_double),
         ("newton_rtol", C.c_double), ("lin_rtol", C.c_double), ("max_batch", C.c_int32),
-        ("precond_lag", C.c_int32),
+        ("vanka_sweeps_coarse", C.c_int32), ("precond_lag", C.c_int32),
+        ("lin_rtol_first", C.c_double),
     ]
 
 
@@ -97,7 +98,8 @@ def _check(code, where):
 
 
 SOLVER_DEFAULTS = dict(cip_gamma=1e-4, gmres_restart=30, gmres_maxit=300, newton_maxit=30,
-                       vanka_sweeps=2, vanka_omega=0.9, newton_rtol=1e-10, lin_rtol=1e-6, precond_lag=1)
+                       vanka_sweeps=2, vanka_omega=0.9, newton_rtol=1e-10, lin_rtol=1e-6,
+                       vanka_sweeps_coarse=1, precond_lag=1, lin_rtol_first=1e-3)
 
 
 def make_params(d: dict, precision=None, max_batch=None, **solver) -> Params:
