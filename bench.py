@@ -34,34 +34,42 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 METRIC = "fine-propagator dof\u00b7steps/s batched vs sequential slices at 1e-6 rel; HBM GB/s"
 # kernel families timed by the library (HIP events on the call's stream), in fsi_profile_query order
-FAMILIES = ("smoother_spmv_fine", "krylov_spmv_fine", "jacobian_elem", "residual", "vanka_update_fine",
-            "smoother_coarser_levels", "coarsest_solve")
-KERNEL_NAMES = {"smoother_spmv_fine": "k_spmv_node<double> (Vanka residual, finest level)",
-                "vanka_update_fine": "k_vanka_update (finest level)",
-                "krylov_spmv_fine": "k_spmv (Krylov product, finest level)"}
+FAMILIES = ("vanka_pass_fine", "krylov_spmv_fine", "jacobian_elem", "residual", "level_residual_fine",
+            "coarser_levels", "coarsest_solve")
+KERNEL_NAMES = {"vanka_pass_fine": "k_vanka_color (fused residual + patch update, finest level)",
+                "krylov_spmv_fine": "k_spmv (Krylov product, finest level)",
+                "level_residual_fine": "k_spmv (residual before restriction, finest level)"}
 
 
 def counter_traffic(kernel_family, prec):
     """HBM bytes per launch of the dominant kernel from the committed counter runs, or None.
 
-    profiles/traffic.json records FETCH_SIZE/WRITE_SIZE means (calibrated with a
-    copy kernel) and a hash of the kernel's source at the time of the runs; a
-    changed kernel gives None.
+    profiles/traffic.json records the kernel family, FETCH_SIZE/WRITE_SIZE means
+    (calibrated with a copy kernel) and a hash of the kernel's source at the
+    time of the runs; another family, precision or a changed kernel gives None.
     """
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
-    if kernel_family != "smoother_spmv_fine" or prec != "fp64" or not os.path.exists(path):
+    if not os.path.exists(path):
         return None
     tr = json.load(open(path))
+    if tr.get("family") != kernel_family or tr.get("precision") != prec:
+        return None
+    if kernel_source_hash(tr["kernel_function"]) != tr["source_hash"]:
+        return None
+    return tr["traffic_bytes_per_launch"]
+
+
+def kernel_source_hash(fn):
+    """Hash of a kernel's body in solver.hip plus the Jacobian index map it reads through."""
+    import hashlib
     src = open(os.path.join(ROOT, "paper_1907_01252_amd", "csrc", "solver.hip")).read()
-    i = src.index("__global__ void __launch_bounds__(256) k_spmv_node(")
+    i = src.index(f"void __launch_bounds__(256) {fn}(")
     body = src[i:src.index("\n}\n", i) + 3]
     hdr = open(os.path.join(ROOT, "paper_1907_01252_amd", "csrc", "fsi_internal.h")).read()
     j = hdr.index("__host__ __device__ inline size_t jidx(")
     jb = hdr[j:hdr.index("}\n", j) + 2]
-    if hashlib.sha256((body + jb).encode()).hexdigest()[:16] != tr["source_hash"]:
-        return None
-    return tr["traffic_bytes_per_launch"]
+    return hashlib.sha256((body + jb).encode()).hexdigest()[:16]
 
 
 def main():
@@ -203,7 +211,7 @@ def main():
                "sample": f"slice {l} of {args.workload}: {done} Newton-SuperLU steps, {cpu_wall:.1f} s"}
 
     # dominant kernel family by total time in the timed sweeps
-    dom = max(("smoother_spmv_fine", "vanka_update_fine", "krylov_spmv_fine"), key=lambda f: fams[f][1])
+    dom = max(("vanka_pass_fine", "krylov_spmv_fine", "level_residual_fine"), key=lambda f: fams[f][1])
     dn, dms, dby = fams[dom]
     achieved = dby / (dms * 1e-3) / 1e9 if dms > 0 else None
     out = {

@@ -171,9 +171,11 @@ fsi_status fsi_debug_vcycle(fsi_problem* pb, int32_t B, const double* U, const d
    caller's stream around every launch of the named kernel family).
    fsi_profile_enable(pb, 1) starts collecting (and clears), 0 stops.
    fsi_profile_query returns the launch count and summed milliseconds of
-   kernel family `which` (0 = Vanka smoothing pass, 1 = fine SpMV,
-   2 = element Jacobian, 3 = residual) and the algorithmic bytes those
-   launches moved. */
+   kernel family `which` and the algorithmic bytes those launches moved:
+   0 = fused Vanka colour pass on the finest level, 1 = Jacobian product of
+   the Krylov iteration, 2 = element Jacobian (all levels), 3 = residual,
+   4 = residual before restriction on the finest level, 5 = every smoother
+   and residual kernel of the coarser levels, 6 = coarsest-level solve. */
 fsi_status fsi_profile_enable(fsi_problem* pb, int32_t on);
 fsi_status fsi_profile_query(const fsi_problem* pb, int32_t which, int64_t* launches, double* ms,
                              double* bytes);

@@ -54,11 +54,11 @@ struct Level {
 
 // profiled kernel families (HIP events around each launch while enabled)
 enum Fam {
-  F_SMOOTH_SPMV = 0,   // residual SpMV inside the Vanka smoother, finest level
+  F_SMOOTH = 0,        // fused Vanka colour pass (residual + patch update), finest level
   F_GMRES_SPMV = 1,    // Jacobian product of the Krylov iteration, finest level
   F_JAC = 2,           // element Jacobian, all levels
   F_RES = 3,           // residual assembly
-  F_VANKA_UPD = 4,     // Vanka patch update, finest level
+  F_LEVEL_RES = 4,     // residual before restriction, finest level
   F_COARSE_LEV = 5,    // smoother kernels on the coarser levels
   F_COARSE_SOLVE = 6,  // coarsest-level dense solve
   F_NFAM = 7
@@ -412,8 +412,8 @@ fsi_status assemble_levels(fsi_problem* pb, int B, const StepPar& sp, const int*
     }
     if (!precond) break;
     if (l >= 1) {
-      k_vanka_factor<S><<<dim3((g.ncell * 32 + TPB - 1) / TPB, B), TPB, 0, st>>>(g, sp.k, (const S*)lv.J,
-                                                                              (S*)lv.Ainv, act);
+      k_vanka_factor<S><<<dim3((g.ncell + VF_PATCHES - 1) / VF_PATCHES, B), VF_PATCHES * 32, 0, st>>>(
+          g, sp.k, (const S*)lv.J, (S*)lv.Ainv, act);
     } else {
       const size_t lds_f = (size_t)5 * pb->cbs * pb->cbs * sizeof(double);
       const size_t lds_i = (size_t)3 * pb->cbs * pb->cbs * sizeof(double);
@@ -427,15 +427,11 @@ fsi_status assemble_levels(fsi_problem* pb, int B, const StepPar& sp, const int*
   return FSI_OK;
 }
 
-// y = D (b - A x) (or D A x): thread-per-node kernel on large grids, thread-per-row
-// kernel (five times the threads, shorter dependency chains) on small ones.
+// y = D (b - A x) (or D A x)
 template <class S>
 void spmv(const Geom& g, int B, double k, const S* J, const S* x, const S* b, const double* D, S* y, const int* act,
           hipStream_t st) {
-  if ((size_t)g.nn * B >= 65536)
-    k_spmv_node<S><<<grid1(g.nn, B), TPB, 0, st>>>(g, k, J, x, b, D, y, act);
-  else
-    k_spmv<S><<<grid1(NC * g.nn, B), TPB, 0, st>>>(g, k, J, x, b, D, y, act);
+  k_spmv<S><<<dim3((g.nn + 63) / 64, B), SPMV_THREADS, 0, st>>>(g, k, J, x, b, D, y, act);
 }
 
 // ------------------------------------------------------------ multigrid
@@ -446,25 +442,24 @@ void smooth(fsi_problem* pb, int l, int B, double k, int sweeps, bool zero_first
   const Geom g = lv.geom();
   const S om = (S)pb->p.vanka_omega;
   const bool fine = l == pb->nlev - 1;
-  const ColorLayout CL = color_layout(g.nx, g.ny);
-  S* r = (S*)lv.r_;
+  // the passes alternate between x and the level's residual buffer; four colours
+  // per sweep leave the result in x
+  S* buf[2] = {x, (S*)lv.r_};
+  int cur = 0;
   for (int s = 0; s < sweeps; ++s)
     for (int c = 0; c < 4; ++c) {
       const bool zero = zero_first && s == 0 && c == 0;
-      const int nc = CL.ncx[c] * CL.ncy[c];
-      if (!zero) {
-        const double by = (double)B * ((double)NSLOT * BLK * g.nn * sizeof(S) + 3.0 * g.nn * NC * sizeof(S)) +
-                          (double)NPST * g.nn * 8.0;
-        ProfScope ps(pb, fine ? F_SMOOTH_SPMV : F_COARSE_LEV, st, by);
-        spmv<S>(g, B, k, (const S*)lv.J, x, b, nullptr, r, act, st);
-      }
-      {
-        const double by = (double)B * ((double)NE * NE * nc * sizeof(S) + 3.0 * nc * NE * sizeof(S));
-        ProfScope ps(pb, fine ? F_VANKA_UPD : F_COARSE_LEV, st, by);
-        const int nthr = std::max(nc * NE, zero ? g.nn : 0);
-        k_vanka_update<S><<<dim3((nthr + TPB - 1) / TPB, B), TPB, 0, st>>>(g, c, om, zero ? 1 : 0,
-                                                                          (const S*)lv.Ainv, zero ? b : r, x, act);
-      }
+      const int nc = color_info(g.nx, g.ny, c).nc;
+      const double vec = 3.0 * g.nn * NC * sizeof(S);
+      const double by = zero ? (double)B * ((double)NE * NE * nc * sizeof(S) + 2.0 * g.nn * NC * sizeof(S))
+                             : (double)B * ((double)NSLOT * BLK * g.nn * sizeof(S) + (double)NE * NE * nc * sizeof(S) +
+                                            vec) +
+                                   (double)NPST * g.nn * 8.0;
+      ProfScope ps(pb, fine ? F_SMOOTH : F_COARSE_LEV, st, by);
+      const int npb = (nc + VC_CELLS - 1) / VC_CELLS, ncopy = (g.nn + VC_THREADS - 1) / VC_THREADS;
+      k_vanka_color<S><<<dim3(npb + ncopy, B), VC_THREADS, 0, st>>>(g, k, c, om, zero ? 1 : 0, (const S*)lv.J,
+                                                             (const S*)lv.Ainv, b, buf[cur], buf[cur ^ 1], act);
+      cur ^= 1;
     }
 }
 
@@ -479,7 +474,12 @@ void vcycle(fsi_problem* pb, int B, double k, const S* rhs, S* out, const int* a
     S* x = (l == L) ? out : (S*)lv.x_;
     smooth<S>(pb, l, B, k, l == L ? pb->p.vanka_sweeps : pb->p.vanka_sweeps_coarse, true, x, b, act, st);
     const Geom g = lv.geom();
-    spmv<S>(g, B, k, (const S*)lv.J, x, b, nullptr, (S*)lv.r_, act, st);
+    {
+      const double by = (double)B * ((double)NSLOT * BLK * g.nn * sizeof(S) + 3.0 * g.nn * NC * sizeof(S)) +
+                        (double)NPST * g.nn * 8.0;
+      ProfScope ps(pb, l == L ? F_LEVEL_RES : F_COARSE_LEV, st, by);
+      spmv<S>(g, B, k, (const S*)lv.J, x, b, nullptr, (S*)lv.r_, act, st);
+    }
     k_restrict<S><<<grid1(lc.nn, B), TPB, 0, st>>>(lc.geom(), g, (const S*)lv.r_, (S*)lc.b_, act);
   }
   {
@@ -1238,12 +1238,14 @@ fsi_status fsi_debug_jacobian_apply(fsi_problem* pb, int32_t B, const double* U,
   if (pb->mixed) {
     CHK(assemble_levels<float>(pb, B, sp, nullptr, st));
     k_convert<double, float><<<1024, TPB, 0, st>>>(B * ndof, X, (float*)pb->tmp);
-    k_spmv<float><<<grid1(NC * F.nn, B), TPB, 0, st>>>(F.geom(), k, (const float*)F.J, (const float*)pb->tmp, nullptr,
-                                                  nullptr, (float*)pb->w, nullptr);
+    k_spmv<float><<<dim3((F.nn + 63) / 64, B), SPMV_THREADS, 0, st>>>(F.geom(), k, (const float*)F.J,
+                                                                      (const float*)pb->tmp, nullptr, nullptr,
+                                                                      (float*)pb->w, nullptr);
     k_convert<float, double><<<1024, TPB, 0, st>>>(B * ndof, (const float*)pb->w, Y);
   } else {
     CHK(assemble_levels<double>(pb, B, sp, nullptr, st));
-    k_spmv<double><<<grid1(NC * F.nn, B), TPB, 0, st>>>(F.geom(), k, (const double*)F.J, X, nullptr, nullptr, Y, nullptr);
+    k_spmv<double><<<dim3((F.nn + 63) / 64, B), SPMV_THREADS, 0, st>>>(F.geom(), k, (const double*)F.J, X, nullptr,
+                                                                        nullptr, Y, nullptr);
   }
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(st));

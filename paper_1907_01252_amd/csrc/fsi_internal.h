@@ -50,6 +50,10 @@ __host__ __device__ inline int slot_of(int dx, int dy) { return (dx + 1) + 3 * (
 // 9 x 25 block-stencil coefficients as 225 runs of 64 consecutive values, so one
 // wave streams one contiguous 225 x 64 array.
 constexpr int JT = 64;
+constexpr int SPMV_THREADS = 5 * 64;   // row-variant SpMV block: five waves over 64 nodes
+constexpr int VC_CELLS = 16;           // cells per block of the fused Vanka pass
+constexpr int VC_THREADS = 5 * 64;     // its five waves (one per row of a patch node)
+constexpr int VF_PATCHES = 8;          // patches per block of the Vanka factor kernel (32 lanes each)
 __host__ __device__ inline int nn_pad(int nn) { return (nn + JT - 1) / JT * JT; }
 __host__ __device__ inline size_t jslice(int nn) { return (size_t)NSLOT * BLK * nn_pad(nn); }
 __host__ __device__ inline size_t jidx(int node, int s, int e) {
@@ -58,21 +62,24 @@ __host__ __device__ inline size_t jidx(int node, int s, int e) {
 __host__ __device__ inline int pslot_of(int dx, int dy) { return (dx + 2) + 5 * (dy + 2); }
 
 // ------------------------------------------------------------ colour helpers
-// Cells of colour (cx, cy) = (ci & 1, cj & 1), stored colour by colour.
-struct ColorLayout {
-  int ncx[4], ncy[4], off[4];
+// Cells of colour c = (i mod 2) + 2 (j mod 2): ncx per row, nc in total, and
+// the offset of the colour's block in the per-colour Vanka inverse storage
+// (colours stored in order 0..3).  Computed without arrays, so a colour that
+// is only known at run time costs no private memory.
+struct ColorInfo {
+  int ncx, nc, off;
 };
-__host__ __device__ inline ColorLayout color_layout(int nx, int ny) {
-  ColorLayout L;
-  int o = 0;
-  for (int c = 0; c < 4; ++c) {
-    const int cx = c & 1, cy = c >> 1;
-    L.ncx[c] = (nx - cx + 1) / 2;
-    L.ncy[c] = (ny - cy + 1) / 2;
-    L.off[c] = o;
-    o += L.ncx[c] * L.ncy[c];
+__host__ __device__ inline ColorInfo color_info(int nx, int ny, int c) {
+  ColorInfo ci;
+  ci.off = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int nq = ((nx - (q & 1) + 1) / 2) * ((ny - (q >> 1) + 1) / 2);
+    if (q < c) ci.off += nq;
   }
-  return L;
+  ci.ncx = (nx - (c & 1) + 1) / 2;
+  ci.nc = ci.ncx * ((ny - (c >> 1) + 1) / 2);
+  return ci;
 }
 
 // A bar face shared with a fluid cell: fluid cell index, face axis (0: x, 1: y),

@@ -33,13 +33,10 @@ template <class S>
 __global__ void k_spmv(Geom g, double k, const S* J, const S* x, const S* b, const double* Dsc, S* y,
                        const int* active);
 template <class S>
-__global__ void k_spmv_node(Geom g, double k, const S* J, const S* x, const S* b, const double* Dsc, S* y,
-                            const int* active);
-template <class S>
 __global__ void k_vanka_factor(Geom g, double k, const S* J, S* Ainv, const int* active);
 template <class S>
-__global__ void k_vanka_update(Geom g, int color, S omega, int zero_in, const S* Ainv, const S* r, S* x,
-                               const int* active);
+__global__ void k_vanka_color(Geom g, double k, int color, S omega, int zero_in, const S* J, const S* Ainv,
+                              const S* b, const S* xo, S* xn, const int* active);
 template <class S>
 __global__ void k_restrict(Geom gc, Geom gf, const S* rf, S* bc, const int* active);
 template <class S>

@@ -8,89 +8,67 @@
 
 namespace fsi {
 
+// Neighbour offsets of the 3x3 block stencil of node (i, j), without branches:
+// an out-of-mesh neighbour maps onto the node itself.  The Jacobian stores
+// zeros in those slots (and the pressure stencil for such pairs), so the
+// product adds exactly nothing and every load of a row can be in flight at once.
+__device__ inline void slot_offsets(const Geom& g, int i, int j, int (&off)[NSLOT]) {
+  const int W = g.nx + 1;
+  const int xm = i > 0 ? -1 : 0, xp = i < g.nx ? 1 : 0;
+  const int ym = j > 0 ? -W : 0, yp = j < g.ny ? W : 0;
+  off[0] = ym + xm; off[1] = ym; off[2] = ym + xp;
+  off[3] = xm;      off[4] = 0;  off[5] = xp;
+  off[6] = yp + xm; off[7] = yp; off[8] = yp + xp;
+}
+
+// k * sum_q pst[q][n] x_p(neighbour q) over the 5x5 pressure stencil (clamped
+// neighbours, zero coefficients outside the mesh and on Dirichlet pressure rows).
+template <class S>
+__device__ inline S pst_row(const Geom& g, double k, int n, int i, int j, const S* __restrict__ xb) {
+  const int W = g.nx + 1;
+  int cx[5], cy[5];
+#pragma unroll
+  for (int d = 0; d < 5; ++d) {
+    cx[d] = min(max(i + d - 2, 0), g.nx);
+    cy[d] = W * min(max(j + d - 2, 0), g.ny);
+  }
+  S ap = 0;
+#pragma unroll
+  for (int q = 0; q < NPST; ++q) ap += (S)g.pst[(size_t)q * g.nn + n] * xb[(size_t)(cx[q % 5] + cy[q / 5]) * NC + 4];
+  return (S)k * ap;
+}
+
 // ------------------------------------------------------------------ SpMV
 // y = D (A x)            (b == nullptr)
 // y = D (b - A x)        (b != nullptr)
 // with A = J (3x3 block stencil of 5x5 blocks) + k * S_p (5x5 pressure stencil).
 // D = Dsc (row scaling) when given, else identity.
-// Variant with one thread per node (all five rows): fewer, longer threads, the
-// better mapping when the grid is large enough to fill the GPU.
+// One thread per (node, row): a block of five waves takes 64 consecutive
+// nodes, wave r forming row r, so the five rows of a node read its
+// neighbours' x through the same CU's cache, and a wave streams 64
+// consecutive values of each coefficient run of the tiled layout.
 template <class S>
-__global__ void __launch_bounds__(256) k_spmv_node(Geom g, double k, const S* __restrict__ J, const S* __restrict__ x,
-                                                   const S* __restrict__ b, const double* __restrict__ Dsc,
-                                                   S* __restrict__ y, const int* __restrict__ active) {
+__global__ void __launch_bounds__(SPMV_THREADS) k_spmv(Geom g, double k, const S* __restrict__ J,
+                                                       const S* __restrict__ x, const S* __restrict__ b,
+                                                       const double* __restrict__ Dsc, S* __restrict__ y,
+                                                       const int* __restrict__ active) {
   const int bs = blockIdx.y;
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = threadIdx.x >> 6;
+  const int n = blockIdx.x * 64 + (threadIdx.x & 63);
   if (n >= g.nn || (active && !active[bs])) return;
   const int i = n % (g.nx + 1), j = n / (g.nx + 1);
   const S* jb = J + (size_t)bs * jslice(g.nn);
   const S* xb = x + (size_t)bs * g.nn * NC;
-  S acc[NC] = {0, 0, 0, 0, 0};
-#pragma unroll
-  for (int s = 0; s < NSLOT; ++s) {
-    const int dx = s % 3 - 1, dy = s / 3 - 1;
-    const int ii = i + dx, jj = j + dy;
-    if (ii < 0 || jj < 0 || ii > g.nx || jj > g.ny) continue;
-    const S* xv = xb + (size_t)(ii + (g.nx + 1) * jj) * NC;
-    S xs[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) xs[c] = xv[c];
-#pragma unroll
-    for (int r = 0; r < NC; ++r)
-#pragma unroll
-      for (int c = 0; c < NC; ++c) acc[r] += jb[jidx(n, s, NC * r + c)] * xs[c];
-  }
-  if (!(g.dmask[n] & DM_P)) {
-    S ap = 0;
-    for (int q = 0; q < NPST; ++q) {
-      const int dx = q % 5 - 2, dy = q / 5 - 2;
-      const int ii = i + dx, jj = j + dy;
-      if (ii < 0 || jj < 0 || ii > g.nx || jj > g.ny) continue;
-      ap += (S)g.pst[(size_t)q * g.nn + n] * xb[(size_t)(ii + (g.nx + 1) * jj) * NC + 4];
-    }
-    acc[4] += (S)k * ap;
-  }
-  const size_t o = ((size_t)bs * g.nn + n) * NC;
-#pragma unroll
-  for (int r = 0; r < NC; ++r) {
-    S v = b ? b[o + r] - acc[r] : acc[r];
-    y[o + r] = Dsc ? (S)(Dsc[o + r] * (double)v) : v;
-  }
-}
-
-template <class S>
-__global__ void __launch_bounds__(256) k_spmv(Geom g, double k, const S* __restrict__ J, const S* __restrict__ x,
-                                              const S* __restrict__ b, const double* __restrict__ Dsc,
-                                              S* __restrict__ y, const int* __restrict__ active) {
-  // one thread per (row component r, node n): t = r * nn + n, so a wave streams
-  // 64 consecutive nodes of one coefficient run of the tiled layout
-  const int bs = blockIdx.y;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= NC * g.nn || (active && !active[bs])) return;
-  const int r = t / g.nn, n = t - r * g.nn;
-  const int i = n % (g.nx + 1), j = n / (g.nx + 1);
-  const S* jb = J + (size_t)bs * jslice(g.nn);
-  const S* xb = x + (size_t)bs * g.nn * NC;
+  int off[NSLOT];
+  slot_offsets(g, i, j, off);
   S acc = 0;
 #pragma unroll
   for (int s = 0; s < NSLOT; ++s) {
-    const int dx = s % 3 - 1, dy = s / 3 - 1;
-    const int ii = i + dx, jj = j + dy;
-    if (ii < 0 || jj < 0 || ii > g.nx || jj > g.ny) continue;
-    const S* xv = xb + (size_t)(ii + (g.nx + 1) * jj) * NC;
+    const S* xv = xb + (size_t)(n + off[s]) * NC;
 #pragma unroll
     for (int c = 0; c < NC; ++c) acc += jb[jidx(n, s, NC * r + c)] * xv[c];
   }
-  if (r == 4 && !(g.dmask[n] & DM_P)) {
-    S ap = 0;
-    for (int q = 0; q < NPST; ++q) {
-      const int dx = q % 5 - 2, dy = q / 5 - 2;
-      const int ii = i + dx, jj = j + dy;
-      if (ii < 0 || jj < 0 || ii > g.nx || jj > g.ny) continue;
-      ap += (S)g.pst[(size_t)q * g.nn + n] * xb[(size_t)(ii + (g.nx + 1) * jj) * NC + 4];
-    }
-    acc += (S)k * ap;
-  }
+  if (r == 4) acc += pst_row<S>(g, k, n, i, j, xb);
   const size_t o = ((size_t)bs * g.nn + n) * NC + r;
   S v = b ? b[o] - acc : acc;
   y[o] = Dsc ? (S)(Dsc[o] * (double)v) : v;
@@ -192,41 +170,47 @@ __global__ void k_adjoint_rhs(Geom g, const double* __restrict__ rhs, double* __
 
 // ------------------------------------------------------- Vanka patch inverse
 // One 32-lane group inverts the 20x20 patch matrix of one cell (rows = local
-// unknowns 5a + c) by Gauss-Jordan with partial pivoting; lane r holds row r of
-// [A | I].  Ainv is stored per colour: Ainv[b][off_c*400 + e*nc_c + idx].
+// unknowns 5a + c) by Gauss-Jordan with partial pivoting.  [A | I] lives in
+// LDS, lane r owning row r; per column the pivot row is found by a shuffle
+// reduction and every other row eliminates the column with the (unscaled)
+// pivot row.  Rows are scaled by their pivots at the end, which gives the
+// same inverse as scaling at each step.  Ainv is stored per colour:
+// Ainv[b][off_c*400 + e*nc_c + idx], e = 20 * row + column.
+constexpr int VF_LD = 2 * NE + 1;      // padded LDS row of [A | I]
 template <class S>
-__global__ void __launch_bounds__(256) k_vanka_factor(Geom g, double k, const S* __restrict__ J,
+__global__ void __launch_bounds__(VF_PATCHES * 32) k_vanka_factor(Geom g, double k, const S* __restrict__ J,
                                                       S* __restrict__ Ainv, const int* __restrict__ active) {
+  __shared__ double M[VF_PATCHES][NE][VF_LD];
   const int bs = blockIdx.y;
-  const int lane = threadIdx.x & 31;
-  const int cell = (blockIdx.x * blockDim.x + threadIdx.x) >> 5;
-  const bool live = cell < g.ncell && !(active && !active[bs]);
+  if (active && !active[bs]) return;   // uniform over the block
+  const int grp = threadIdx.x >> 5, lane = threadIdx.x & 31;
+  const int cell = blockIdx.x * VF_PATCHES + grp;
+  const bool live = cell < g.ncell;
   const int ci = live ? cell % g.nx : 0, cj = live ? cell / g.nx : 0;
-  const int r = lane < NE ? lane : 0;
-  const int a = r / NC, rc = r % NC;
-  const int na = (ci + (a & 1)) + (g.nx + 1) * (cj + (a >> 1));
-  double row[2 * NE];
-#pragma unroll
-  for (int c = 0; c < 2 * NE; ++c) row[c] = 0.0;
-  if (live && lane < NE) {
-    const S* jb = J + (size_t)bs * jslice(g.nn);
-    const bool pst_row = (rc == 4) && !(g.dmask[na] & DM_P);
-#pragma unroll
-    for (int bb = 0; bb < NL; ++bb) {
-      const int dx = (bb & 1) - (a & 1), dy = (bb >> 1) - (a >> 1);
-      const int s = slot_of(dx, dy);
-#pragma unroll
-      for (int c = 0; c < NC; ++c) row[NC * bb + c] = (double)jb[jidx(na, s, NC * rc + c)];
-      if (pst_row) row[NC * bb + 4] += k * g.pst[(size_t)pslot_of(dx, dy) * g.nn + na];
+  double(*Mp)[VF_LD] = M[grp];
+  if (lane < NE) {
+    const int a = lane / NC, rc = lane % NC;
+    const int na = (ci + (a & 1)) + (g.nx + 1) * (cj + (a >> 1));
+    if (live) {
+      const S* jb = J + (size_t)bs * jslice(g.nn);
+      const bool pst_row = (rc == 4) && !(g.dmask[na] & DM_P);
+      for (int bb = 0; bb < NL; ++bb) {
+        const int dx = (bb & 1) - (a & 1), dy = (bb >> 1) - (a >> 1);
+        const int s = slot_of(dx, dy);
+        for (int c = 0; c < NC; ++c) Mp[lane][NC * bb + c] = (double)jb[jidx(na, s, NC * rc + c)];
+        if (pst_row) Mp[lane][NC * bb + 4] += k * g.pst[(size_t)pslot_of(dx, dy) * g.nn + na];
+      }
+    } else {
+      for (int c = 0; c < NE; ++c) Mp[lane][c] = (c == lane) ? 1.0 : 0.0;
     }
-#pragma unroll
-    for (int c = 0; c < NE; ++c) row[NE + c] = (c == r) ? 1.0 : 0.0;
+    for (int c = 0; c < NE; ++c) Mp[lane][NE + c] = (c == lane) ? 1.0 : 0.0;
   }
-  bool used = !(lane < NE);
+  __syncthreads();
+  bool used = lane >= NE;
   int mycol = 0;
-#pragma unroll
   for (int jc = 0; jc < NE; ++jc) {
-    double cand = used ? -1.0 : fabs(row[jc]);
+    const double v = lane < NE ? Mp[lane][jc] : 0.0;
+    double cand = used ? -1.0 : fabs(v);
     int idx = lane;
 #pragma unroll
     for (int off = 16; off > 0; off >>= 1) {
@@ -234,69 +218,96 @@ __global__ void __launch_bounds__(256) k_vanka_factor(Geom g, double k, const S*
       const int oi = __shfl_xor(idx, off, 32);
       if (oc > cand || (oc == cand && oi < idx)) { cand = oc; idx = oi; }
     }
-    double pv = __shfl(row[jc], idx, 32);
+    double pv = Mp[idx][jc];
     if (pv == 0.0) pv = 1.0;   // singular patch: leave the column alone
-    const double f = (lane == idx) ? 0.0 : row[jc] / pv;
-#pragma unroll
-    for (int c = 0; c < 2 * NE; ++c) {
-      const double pr = __shfl(row[c], idx, 32);
-      row[c] = (lane == idx) ? pr / pv : row[c] - f * pr;
-    }
     if (lane == idx) { used = true; mycol = jc; }
+    const double f = (lane < NE && lane != idx) ? v / pv : 0.0;
+    if (f != 0.0)
+      for (int c = jc; c < 2 * NE; ++c) Mp[lane][c] -= f * Mp[idx][c];
+    __syncthreads();
   }
   if (live && lane < NE) {
-    const ColorLayout L = color_layout(g.nx, g.ny);
-    const int col = (ci & 1) + 2 * (cj & 1);
-    const int nc = L.ncx[col] * L.ncy[col];
-    const int idx = (ci >> 1) + L.ncx[col] * (cj >> 1);
-    S* out = Ainv + (size_t)bs * NE * NE * g.ncell + (size_t)L.off[col] * NE * NE;
-#pragma unroll
-    for (int c = 0; c < NE; ++c) out[(size_t)(NE * mycol + c) * nc + idx] = (S)row[NE + c];
+    const ColorInfo L = color_info(g.nx, g.ny, (ci & 1) + 2 * (cj & 1));
+    const int nc = L.nc;
+    const int idx = (ci >> 1) + L.ncx * (cj >> 1);
+    const double d = Mp[lane][mycol] != 0.0 ? 1.0 / Mp[lane][mycol] : 1.0;
+    S* out = Ainv + (size_t)bs * NE * NE * g.ncell + (size_t)L.off * NE * NE;
+    for (int c = 0; c < NE; ++c) out[(size_t)(NE * mycol + c) * nc + idx] = (S)(Mp[lane][NE + c] * d);
   }
 }
 
-// ------------------------------------------------------ colored Vanka update
-// Second half of one multiplicative pass over the cells of one colour: with
-// r = b - A x computed beforehand at every node (k_spmv), every cell of the
-// colour updates its patch x[P] += omega Ainv_P r_P.  Patches of one colour do
-// not overlap, so the update is in place.  Four lanes (one per patch node)
-// share a cell; each reads the 20 patch residuals and forms its node's 5 rows.
-// zero_in: x is taken as zero and r = b (first pass of a cycle): x[P] = omega Ainv_P b_P,
-// nodes outside every patch of the colour get x = 0.
+// ------------------------------------------------------ colored Vanka pass
+// One multiplicative pass over the cells of one colour, residual and patch
+// update fused: every cell P of the colour forms r_P = b_P - (A x_old)_P on its
+// four nodes and writes x_new[P] = x_old[P] + omega Ainv_P r_P.  The cells of
+// one colour do not share nodes, so each node is written by at most one patch;
+// the nodes no patch of the colour covers are copied.  x_old and x_new are
+// different buffers (other patches read x_old at the shared neighbours).
+// zero_in: x_old is taken as zero (first pass of a cycle): r_P = b_P and the
+// uncovered nodes get zero.
+// Thread mapping: a block of VC_CELLS consecutive cells of the colour has five
+// waves, wave r forming row r of every patch node; lanes 0-31 take the lower
+// node pair of the 16 cells, lanes 32-63 the upper pair, so within one cell
+// row a wave reads two runs of 32 consecutive nodes.  The 20 patch residuals
+// meet in LDS; the same thread then forms patch row 5a + r of Ainv_P r_P.
+// Extra blocks past the patch blocks copy the uncovered nodes.
 template <class S>
-__global__ void __launch_bounds__(256) k_vanka_update(Geom g, int color, S omega, int zero_in,
-                                                      const S* __restrict__ Ainv, const S* __restrict__ r,
-                                                      S* __restrict__ x, const int* __restrict__ active) {
-  // one thread per (patch row, cell of the colour): t = row * nc + idx, so a wave
-  // reads 64 consecutive cells of one Ainv row run
+__global__ void __launch_bounds__(VC_THREADS) k_vanka_color(Geom g, double k, int color, S omega, int zero_in,
+                                                            const S* __restrict__ J, const S* __restrict__ Ainv,
+                                                            const S* __restrict__ b, const S* __restrict__ xo,
+                                                            S* __restrict__ xn, const int* __restrict__ active) {
+  __shared__ S rs[NE][VC_CELLS];
   const int bs = blockIdx.y;
-  if (active && !active[bs]) return;
-  const ColorLayout L = color_layout(g.nx, g.ny);
-  const int nc = L.ncx[color] * L.ncy[color];
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  S* xb = x + (size_t)bs * g.nn * NC;
-  if (zero_in && t < g.nn) {
-    // clear the nodes no patch of this colour covers (first pass only)
+  if (active && !active[bs]) return;   // uniform over the block
+  const ColorInfo L = color_info(g.nx, g.ny, color);
+  const int nc = L.nc;
+  const int npb = (nc + VC_CELLS - 1) / VC_CELLS;
+  const S* xob = xo + (size_t)bs * g.nn * NC;
+  S* xnb = xn + (size_t)bs * g.nn * NC;
+  if ((int)blockIdx.x >= npb) {
+    const int t = ((int)blockIdx.x - npb) * VC_THREADS + threadIdx.x;
+    if (t >= g.nn) return;
     const int ni = t % (g.nx + 1), nj = t / (g.nx + 1);
     const int cx = color & 1, cy = color >> 1;
     const int ci = ni - ((ni - cx) & 1), cj = nj - ((nj - cy) & 1);
     if (ci < 0 || cj < 0 || ci >= g.nx || cj >= g.ny)
-      for (int c = 0; c < NC; ++c) xb[(size_t)t * NC + c] = (S)0;
+      for (int c = 0; c < NC; ++c) xnb[(size_t)t * NC + c] = zero_in ? (S)0 : xob[(size_t)t * NC + c];
+    return;
   }
-  if (t >= NE * nc) return;
-  const int row = t / nc, idx = t - row * nc;
-  const int ci = 2 * (idx % L.ncx[color]) + (color & 1), cj = 2 * (idx / L.ncx[color]) + (color >> 1);
-  const int n0 = ci + (g.nx + 1) * cj;
-  const int nodes[NL] = {n0, n0 + 1, n0 + g.nx + 1, n0 + g.nx + 2};
-  const S* rb = r + (size_t)bs * g.nn * NC;
-  const S* ai = Ainv + (size_t)bs * NE * NE * g.ncell + (size_t)L.off[color] * NE * NE + (size_t)NE * row * nc + idx;
+  const int r = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int a = ((lane >> 5) << 1) | (lane & 1);
+  const int jc = (lane & 31) >> 1;
+  const int idx = blockIdx.x * VC_CELLS + jc;
+  const bool live = idx < nc;
+  int n = 0;
+  if (live) {
+    const int ci = 2 * (idx % L.ncx) + (color & 1), cj = 2 * (idx / L.ncx) + (color >> 1);
+    n = ci + (a & 1) + (g.nx + 1) * (cj + (a >> 1));
+    S acc = 0;
+    if (!zero_in) {
+      const int i = n % (g.nx + 1), j = n / (g.nx + 1);
+      const S* jb = J + (size_t)bs * jslice(g.nn);
+      int off[NSLOT];
+      slot_offsets(g, i, j, off);
+#pragma unroll
+      for (int s = 0; s < NSLOT; ++s) {
+        const S* xv = xob + (size_t)(n + off[s]) * NC;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc += jb[jidx(n, s, NC * r + c)] * xv[c];
+      }
+      if (r == 4) acc += pst_row<S>(g, k, n, i, j, xob);
+    }
+    rs[NC * a + r][jc] = b[((size_t)bs * g.nn + n) * NC + r] - acc;
+  }
+  __syncthreads();
+  if (!live) return;
+  const S* ai = Ainv + (size_t)bs * NE * NE * g.ncell + (size_t)L.off * NE * NE + idx;
+  const int row = NC * a + r;
   S z = 0;
 #pragma unroll
-  for (int bb = 0; bb < NL; ++bb)
-#pragma unroll
-    for (int c = 0; c < NC; ++c) z += ai[(size_t)(NC * bb + c) * nc] * rb[(size_t)nodes[bb] * NC + c];
-  S* xw = xb + (size_t)nodes[row / NC] * NC + row % NC;
-  *xw = (zero_in ? (S)0 : *xw) + omega * z;
+  for (int e = 0; e < NE; ++e) z += ai[(size_t)(NE * row + e) * nc] * rs[e][jc];
+  const size_t o = (size_t)n * NC + r;
+  xnb[o] = (zero_in ? (S)0 : xob[o]) + omega * z;
 }
 
 // --------------------------------------------------------- grid transfers
@@ -879,10 +890,9 @@ __global__ void k_convert(size_t n, const A* __restrict__ X, B2* __restrict__ Y)
 // explicit instantiations
 #define INST(S)                                                                                                   \
   template __global__ void k_spmv<S>(Geom, double, const S*, const S*, const S*, const double*, S*, const int*); \
-  template __global__ void k_spmv_node<S>(Geom, double, const S*, const S*, const S*, const double*, S*,         \
-                                          const int*);                                                          \
   template __global__ void k_vanka_factor<S>(Geom, double, const S*, S*, const int*);                            \
-  template __global__ void k_vanka_update<S>(Geom, int, S, int, const S*, const S*, S*, const int*);            \
+  template __global__ void k_vanka_color<S>(Geom, double, int, S, int, const S*, const S*, const S*, const S*,   \
+                                            S*, const int*);                                                     \
   template __global__ void k_restrict<S>(Geom, Geom, const S*, S*, const int*);                                  \
   template __global__ void k_prolong_add<S>(Geom, Geom, const S*, S*, const int*);                               \
   template __global__ void k_coarse_factor<S>(Geom, double, const S*, int, int, double*, double*, double*,       \
