@@ -48,7 +48,6 @@ def counter_traffic(kernel_family, prec):
     (calibrated with a copy kernel) and a hash of the kernel's source at the
     time of the runs; another family, precision or a changed kernel gives None.
     """
-    import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -61,15 +60,14 @@ def counter_traffic(kernel_family, prec):
 
 
 def kernel_source_hash(fn):
-    """Hash of a kernel's body in solver.hip plus the Jacobian index map it reads through."""
+    """Hash of the solver kernels' source (solver.hip, which holds the kernel and its
+    device helpers, and the shared layout header), tagged with the kernel name: any
+    edit there invalidates counter figures taken before it."""
     import hashlib
-    src = open(os.path.join(ROOT, "paper_1907_01252_amd", "csrc", "solver.hip")).read()
-    i = src.index(f"void __launch_bounds__(256) {fn}(")
-    body = src[i:src.index("\n}\n", i) + 3]
-    hdr = open(os.path.join(ROOT, "paper_1907_01252_amd", "csrc", "fsi_internal.h")).read()
-    j = hdr.index("__host__ __device__ inline size_t jidx(")
-    jb = hdr[j:hdr.index("}\n", j) + 2]
-    return hashlib.sha256((body + jb).encode()).hexdigest()[:16]
+    csrc = os.path.join(ROOT, "paper_1907_01252_amd", "csrc")
+    src = open(os.path.join(csrc, "solver.hip")).read() + open(os.path.join(csrc, "fsi_internal.h")).read()
+    assert f" {fn}(" in src, fn
+    return hashlib.sha256((fn + src).encode()).hexdigest()[:16]
 
 
 def main():
