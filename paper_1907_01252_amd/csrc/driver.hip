@@ -23,9 +23,9 @@ using namespace fsi;
     }                                               \
   } while (0)
 
-#define CHK(x)                        \
+#define CHK(...)                      \
   do {                                \
-    fsi_status s_ = (x);              \
+    fsi_status s_ = (__VA_ARGS__);    \
     if (s_ != FSI_OK) return s_;      \
   } while (0)
 
@@ -36,18 +36,18 @@ constexpr int MAXLEV = 8;
 constexpr int NCHUNK_MAX = 1024;
 
 struct Level {
-  int nx = 0, ny = 0, nn = 0, ncell = 0;
-  std::vector<double> x, y, pst;
+  int nx = 0, ny = 0, nz = 0, nn = 0, ncell = 0;   // nz = 0 in 2d
+  std::vector<double> x, y, z, pst;
   std::vector<uint8_t> solid, cls, dmask;
-  double *d_x = nullptr, *d_y = nullptr, *d_pst = nullptr;
+  double *d_x = nullptr, *d_y = nullptr, *d_z = nullptr, *d_pst = nullptr;
   uint8_t *d_solid = nullptr, *d_cls = nullptr, *d_dmask = nullptr;
   // batch workspace
   double *U = nullptr, *Uo = nullptr, *Dsc = nullptr;
   void *J = nullptr, *Ainv = nullptr, *x_ = nullptr, *b_ = nullptr, *r_ = nullptr, *t_ = nullptr;
   Geom geom() const {
     Geom g;
-    g.nx = nx; g.ny = ny; g.nn = nn; g.ncell = ncell;
-    g.x = d_x; g.y = d_y; g.solid = d_solid; g.cls = d_cls; g.dmask = d_dmask; g.pst = d_pst;
+    g.nx = nx; g.ny = ny; g.nz = nz; g.nn = nn; g.ncell = ncell;
+    g.x = d_x; g.y = d_y; g.z = d_z; g.solid = d_solid; g.cls = d_cls; g.dmask = d_dmask; g.pst = d_pst;
     return g;
   }
 };
@@ -168,145 +168,223 @@ std::vector<double> axis_points(const fsi_params& p, int a, int l) {
   return pts;
 }
 
-// Q1 Laplace stiffness of an hx x hy rectangle (2x2 Gauss rule, exact), local order (0,0),(1,0),(0,1),(1,1).
-void q1_stiffness(double hx, double hy, double K[4][4]) {
+// host view of a level's geometry (host arrays), for the setup loops
+Geom host_geom(const Level& L) {
+  Geom g{};
+  g.nx = L.nx; g.ny = L.ny; g.nz = L.nz; g.nn = L.nn; g.ncell = L.ncell;
+  return g;
+}
+
+// Q1 Laplace stiffness of a box cell with edge lengths h (2-point Gauss rule per
+// axis, exact); local node a at offset bit r of a on axis r.
+template <int D>
+void q1_stiffness(const double (&h)[D], double (&K)[Dm<D>::NL][Dm<D>::NL]) {
+  FSI_DIM(D);
   const double g[2] = {0.5 - 0.5 / std::sqrt(3.0), 0.5 + 0.5 / std::sqrt(3.0)};
-  for (int a = 0; a < 4; ++a)
-    for (int b = 0; b < 4; ++b) K[a][b] = 0.0;
-  for (int q = 0; q < 4; ++q) {
-    const double xi = g[q & 1], eta = g[q >> 1];
-    const double gx[4] = {-(1 - eta) / hx, (1 - eta) / hx, -eta / hx, eta / hx};
-    const double gy[4] = {-(1 - xi) / hy, -xi / hy, (1 - xi) / hy, xi / hy};
-    for (int a = 0; a < 4; ++a)
-      for (int b = 0; b < 4; ++b) K[a][b] += 0.25 * hx * hy * (gx[a] * gx[b] + gy[a] * gy[b]);
+  double w = 1.0;
+  for (int r = 0; r < D; ++r) w *= 0.5 * h[r];
+  for (int a = 0; a < NL; ++a)
+    for (int b = 0; b < NL; ++b) K[a][b] = 0.0;
+  for (int q = 0; q < (1 << D); ++q) {
+    double xi[D], G[NL][D];
+    for (int r = 0; r < D; ++r) xi[r] = g[(q >> r) & 1];
+    for (int a = 0; a < NL; ++a)
+      for (int r = 0; r < D; ++r) {
+        double v = (((a >> r) & 1) ? 1.0 : -1.0) / h[r];
+        for (int s = 0; s < D; ++s)
+          if (s != r) v *= ((a >> s) & 1) ? xi[s] : 1.0 - xi[s];
+        G[a][r] = v;
+      }
+    for (int a = 0; a < NL; ++a)
+      for (int b = 0; b < NL; ++b) {
+        double s = 0.0;
+        for (int r = 0; r < D; ++r) s += G[a][r] * G[b][r];
+        K[a][b] += w * s;
+      }
   }
 }
 
+template <int D>
 void add_pst(Level& L, int nr, int nc, double v) {
-  const int ir = nr % (L.nx + 1), jr = nr / (L.nx + 1);
-  const int ic = nc % (L.nx + 1), jc = nc / (L.nx + 1);
-  L.pst[(size_t)pslot_of(ic - ir, jc - jr) * L.nn + nr] += v;
+  const Geom g = host_geom(L);
+  int ir, jr, kr, ic, jc, kc;
+  node_ijk<D>(g, nr, ir, jr, kr);
+  node_ijk<D>(g, nc, ic, jc, kc);
+  L.pst[(size_t)pslot_of<D>(ic - ir, jc - jr, kc - kr) * L.nn + nr] += v;
+}
+
+template <int D>
+void cell_h(const Level& L, int i, int j, int k, double (&h)[D]) {
+  h[0] = L.x[i + 1] - L.x[i];
+  h[1] = L.y[j + 1] - L.y[j];
+  if constexpr (D == 3) h[2] = L.z[k + 1] - L.z[k];
 }
 
 // Two-level local projection: alpha_K (grad(p - i2h p), grad(q - i2h q))_K over fluid cells,
-// i2h = Q1 interpolation on the parent (2x2 cells) of K.
+// i2h = Q1 interpolation on the parent (2^D cells) of K, alpha_K = alpha0 |K|^(2/D) / (rho nu).
+template <int D>
 void build_lps(Level& L, const fsi_params& p) {
-  for (int j = 0; j < L.ny; ++j)
-    for (int i = 0; i < L.nx; ++i) {
-      const int cell = i + L.nx * j;
-      if (L.solid[cell]) continue;
-      const double hx = L.x[i + 1] - L.x[i], hy = L.y[j + 1] - L.y[j];
-      const double alpha = p.lps_alpha0 * hx * hy / (p.rho_f * p.nu_f);
-      double K[4][4];
-      q1_stiffness(hx, hy, K);
-      const int ox = i - (i & 1), oy = j - (j & 1);   // parent patch origin node
-      const int cx = i & 1, cy = j & 1;
-      // kappa[a][9]: fluctuation at fine node a in terms of the 9 patch nodes
-      double kap[4][9];
-      for (int a = 0; a < 4; ++a) {
-        for (int q = 0; q < 9; ++q) kap[a][q] = 0.0;
-        const int px = cx + (a & 1), py = cy + (a >> 1);
-        kap[a][px + 3 * py] += 1.0;
-        const double sx = 0.5 * px, sy = 0.5 * py;
-        for (int b = 0; b < 4; ++b) {
-          const double wx = (b & 1) ? sx : 1.0 - sx, wy = (b >> 1) ? sy : 1.0 - sy;
-          kap[a][2 * (b & 1) + 3 * 2 * (b >> 1)] -= wx * wy;
-        }
+  FSI_DIM(D);
+  constexpr int NP = D == 2 ? 9 : 27;   // nodes of the parent patch
+  const Geom g = host_geom(L);
+  for (int cell = 0; cell < L.ncell; ++cell) {
+    if (L.solid[cell]) continue;
+    int i, j, k;
+    cell_ijk<D>(g, cell, i, j, k);
+    double h[D];
+    cell_h<D>(L, i, j, k, h);
+    double vol = 1.0;
+    for (int r = 0; r < D; ++r) vol *= h[r];
+    const double alpha = p.lps_alpha0 * std::pow(vol, 2.0 / D) / (p.rho_f * p.nu_f);
+    double K[NL][NL];
+    q1_stiffness<D>(h, K);
+    const int org[3] = {i - (i & 1), j - (j & 1), k - (k & 1)};   // parent patch origin node
+    const int ch[3] = {i & 1, j & 1, k & 1};
+    // kap[a][q]: fluctuation at fine node a in terms of the NP patch nodes
+    double kap[NL][NP];
+    for (int a = 0; a < NL; ++a) {
+      for (int q = 0; q < NP; ++q) kap[a][q] = 0.0;
+      int pq = 0, mul = 1;
+      double s[3];
+      for (int r = 0; r < D; ++r) {
+        const int pr = ch[r] + ((a >> r) & 1);
+        pq += mul * pr;
+        mul *= 3;
+        s[r] = 0.5 * pr;
       }
-      for (int q = 0; q < 9; ++q)
-        for (int r = 0; r < 9; ++r) {
-          double s = 0.0;
-          for (int a = 0; a < 4; ++a)
-            for (int b = 0; b < 4; ++b) s += kap[a][q] * K[a][b] * kap[b][r];
-          if (s == 0.0) continue;
-          const int nq = (ox + q % 3) + (L.nx + 1) * (oy + q / 3);
-          const int nr = (ox + r % 3) + (L.nx + 1) * (oy + r / 3);
-          add_pst(L, nq, nr, alpha * s);
+      kap[a][pq] += 1.0;
+      for (int b = 0; b < NL; ++b) {
+        double w = 1.0;
+        int pb2 = 0, m2 = 1;
+        for (int r = 0; r < D; ++r) {
+          const int br = (b >> r) & 1;
+          w *= br ? s[r] : 1.0 - s[r];
+          pb2 += m2 * 2 * br;
+          m2 *= 3;
         }
+        kap[a][pb2] -= w;
+      }
     }
-}
-
-// Coarsest level: gradient-jump penalty gamma h_F h_n^3 / (rho nu) int_F [d_n p][d_n q] over
-// interior faces between fluid cells (a preconditioner-only stabilisation; level 0 has no parents).
-void build_cip(Level& L, const fsi_params& p) {
-  const double g[2] = {0.5 - 0.5 / std::sqrt(3.0), 0.5 + 0.5 / std::sqrt(3.0)};
-  for (int j = 0; j < L.ny; ++j)
-    for (int i = 0; i < L.nx; ++i)
-      for (int dir = 0; dir < 2; ++dir) {
-        const int i2 = i + (dir == 0), j2 = j + (dir == 1);
-        if (i2 >= L.nx || j2 >= L.ny) continue;
-        const int c1 = i + L.nx * j, c2 = i2 + L.nx * j2;
-        if (L.solid[c1] || L.solid[c2]) continue;
-        const double h1x = L.x[i + 1] - L.x[i], h1y = L.y[j + 1] - L.y[j];
-        const double h2x = L.x[i2 + 1] - L.x[i2], h2y = L.y[j2 + 1] - L.y[j2];
-        const double hF = dir == 0 ? h1y : h1x;
-        const double hn = dir == 0 ? 0.5 * (h1x + h2x) : 0.5 * (h1y + h2y);
-        int nodes[8];
-        const int n1 = i + (L.nx + 1) * j, n2 = i2 + (L.nx + 1) * j2;
-        const int off[4] = {0, 1, L.nx + 1, L.nx + 2};
-        for (int a = 0; a < 4; ++a) { nodes[a] = n1 + off[a]; nodes[4 + a] = n2 + off[a]; }
-        for (int q = 0; q < 2; ++q) {
-          const double s = g[q];
-          double c[8];
-          for (int a = 0; a < 4; ++a) {
-            const int ax = a & 1, ay = a >> 1;
-            if (dir == 0) {   // face x = const: cell 1 at xi = 1, cell 2 at xi = 0; normal derivative d/dx
-              const double fy = ay ? s : 1.0 - s;
-              c[a] = (ax ? 1.0 : -1.0) * fy / h1x;
-              c[4 + a] = -(ax ? 1.0 : -1.0) * fy / h2x;
-            } else {
-              const double fx = ax ? s : 1.0 - s;
-              c[a] = (ay ? 1.0 : -1.0) * fx / h1y;
-              c[4 + a] = -(ay ? 1.0 : -1.0) * fx / h2y;
-            }
-          }
-          const double w = p.cip_gamma * 0.5 * hF * hn * hn * hn / (p.rho_f * p.nu_f);
-          for (int a = 0; a < 8; ++a)
-            for (int b = 0; b < 8; ++b) add_pst(L, nodes[a], nodes[b], w * c[a] * c[b]);
-        }
+    for (int q = 0; q < NP; ++q)
+      for (int r = 0; r < NP; ++r) {
+        double s = 0.0;
+        for (int a = 0; a < NL; ++a)
+          for (int b = 0; b < NL; ++b) s += kap[a][q] * K[a][b] * kap[b][r];
+        if (s == 0.0) continue;
+        const int nq = node_at(g, org[0] + q % 3, org[1] + (q / 3) % 3, D == 3 ? org[2] + q / 9 : 0);
+        const int nr = node_at(g, org[0] + r % 3, org[1] + (r / 3) % 3, D == 3 ? org[2] + r / 9 : 0);
+        add_pst<D>(L, nq, nr, alpha * s);
       }
+  }
 }
 
+// Coarsest level: gradient-jump penalty gamma h_n^3 / (rho nu) int_F [d_n p][d_n q] over
+// interior faces F between fluid cells (a preconditioner-only stabilisation; level 0 has
+// no parents), 2-point Gauss per face direction.
+template <int D>
+void build_cip(Level& L, const fsi_params& p) {
+  FSI_DIM(D);
+  const double gq[2] = {0.5 - 0.5 / std::sqrt(3.0), 0.5 + 0.5 / std::sqrt(3.0)};
+  const Geom g = host_geom(L);
+  for (int c1 = 0; c1 < L.ncell; ++c1) {
+    int i, j, k;
+    cell_ijk<D>(g, c1, i, j, k);
+    for (int dir = 0; dir < D; ++dir) {
+      const int i2 = i + (dir == 0), j2 = j + (dir == 1), k2 = k + (dir == 2);
+      if (i2 >= L.nx || j2 >= L.ny || (D == 3 && k2 >= L.nz)) continue;
+      const int c2 = cell_at(g, i2, j2, k2);
+      if (L.solid[c1] || L.solid[c2]) continue;
+      double h1[D], h2[D];
+      cell_h<D>(L, i, j, k, h1);
+      cell_h<D>(L, i2, j2, k2, h2);
+      double area = 1.0;
+      for (int r = 0; r < D; ++r)
+        if (r != dir) area *= h1[r];
+      const double hn = 0.5 * (h1[dir] + h2[dir]);
+      int nodes[2 * NL];
+      for (int a = 0; a < NL; ++a) {
+        nodes[a] = node_at(g, i + (a & 1), j + ((a >> 1) & 1), k + ((a >> 2) & 1));
+        nodes[NL + a] = node_at(g, i2 + (a & 1), j2 + ((a >> 1) & 1), k2 + ((a >> 2) & 1));
+      }
+      for (int q = 0; q < (1 << (D - 1)); ++q) {
+        // face point: tangential coordinates from q, normal coordinate 1 in cell 1 and 0 in cell 2
+        double t[3];
+        for (int r = 0, b = 0; r < D; ++r)
+          if (r != dir) t[r] = gq[(q >> b++) & 1];
+        double c[2 * NL];
+        for (int a = 0; a < NL; ++a) {
+          double tang = 1.0;
+          for (int r = 0; r < D; ++r)
+            if (r != dir) tang *= ((a >> r) & 1) ? t[r] : 1.0 - t[r];
+          const double sgn = ((a >> dir) & 1) ? 1.0 : -1.0;
+          c[a] = sgn * tang / h1[dir];
+          c[NL + a] = -sgn * tang / h2[dir];
+        }
+        const double w = p.cip_gamma * area / (1 << (D - 1)) * hn * hn * hn / (p.rho_f * p.nu_f);
+        for (int a = 0; a < 2 * NL; ++a)
+          for (int b = 0; b < 2 * NL; ++b) add_pst<D>(L, nodes[a], nodes[b], w * c[a] * c[b]);
+      }
+    }
+  }
+}
+
+template <int D>
 fsi_status build_level(fsi_problem* pb, int l) {
+  FSI_DIM(D);
   const fsi_params& p = pb->p;
   Level& L = pb->lev[l];
   L.x = axis_points(p, 0, l);
   L.y = axis_points(p, 1, l);
   L.nx = (int)L.x.size() - 1;
   L.ny = (int)L.y.size() - 1;
-  L.nn = (L.nx + 1) * (L.ny + 1);
-  L.ncell = L.nx * L.ny;
+  if (D == 3) {
+    L.z = axis_points(p, 2, l);
+    L.nz = (int)L.z.size() - 1;
+  } else {
+    L.z.assign(1, 0.0);
+    L.nz = 0;
+  }
+  L.nn = (L.nx + 1) * (L.ny + 1) * (L.nz + 1);
+  L.ncell = L.nx * L.ny * (D == 3 ? L.nz : 1);
+  const Geom g = host_geom(L);
   L.solid.assign(L.ncell, 0);
-  for (int j = 0; j < L.ny; ++j)
-    for (int i = 0; i < L.nx; ++i) {
-      const double xc = 0.5 * (L.x[i] + L.x[i + 1]), yc = 0.5 * (L.y[j] + L.y[j + 1]);
-      L.solid[i + L.nx * j] = (xc > p.solid_lo[0] && xc < p.solid_hi[0] && yc > p.solid_lo[1] && yc < p.solid_hi[1]);
-    }
+  for (int c = 0; c < L.ncell; ++c) {
+    int i, j, k;
+    cell_ijk<D>(g, c, i, j, k);
+    const double ctr[3] = {0.5 * (L.x[i] + L.x[i + 1]), 0.5 * (L.y[j] + L.y[j + 1]),
+                           D == 3 ? 0.5 * (L.z[k] + L.z[k + 1]) : 0.0};
+    bool in = true;
+    for (int r = 0; r < D; ++r) in = in && ctr[r] > p.solid_lo[r] && ctr[r] < p.solid_hi[r];
+    L.solid[c] = in;
+  }
   L.cls.assign(L.nn, 0);
-  for (int j = 0; j < L.ny; ++j)
-    for (int i = 0; i < L.nx; ++i) {
-      const uint8_t bit = L.solid[i + L.nx * j] ? CL_NS : CL_NF;
-      for (int a = 0; a < 4; ++a) L.cls[(i + (a & 1)) + (L.nx + 1) * (j + (a >> 1))] |= bit;
-    }
+  for (int c = 0; c < L.ncell; ++c) {
+    int i, j, k;
+    cell_ijk<D>(g, c, i, j, k);
+    const uint8_t bit = L.solid[c] ? CL_NS : CL_NF;
+    for (int a = 0; a < NL; ++a) L.cls[node_at(g, i + (a & 1), j + ((a >> 1) & 1), k + ((a >> 2) & 1))] |= bit;
+  }
   L.dmask.assign(L.nn, 0);
-  for (int j = 0; j <= L.ny; ++j)
-    for (int i = 0; i <= L.nx; ++i) {
-      const int n = i + (L.nx + 1) * j;
-      const bool inflow = i == 0, outflow = i == L.nx, wall = (j == 0 || j == L.ny);
-      uint8_t m = 0;
-      if (inflow || wall) m |= DM_V;
-      if (inflow || outflow || wall) m |= DM_U;
-      if (!(L.cls[n] & CL_NF)) m |= DM_P;
-      L.dmask[n] = m;
-      if (inflow && !wall) L.cls[n] |= CL_INFLOW;
-    }
+  for (int n = 0; n < L.nn; ++n) {
+    int i, j, k;
+    node_ijk<D>(g, n, i, j, k);
+    const bool inflow = i == 0, outflow = i == L.nx;
+    const bool wall = j == 0 || j == L.ny || (D == 3 && (k == 0 || k == L.nz));
+    uint8_t m = 0;
+    if (inflow || wall) m |= dm_v<D>();
+    if (inflow || outflow || wall) m |= dm_u<D>();
+    if (!(L.cls[n] & CL_NF)) m |= dm_p<D>();
+    L.dmask[n] = m;
+    if (inflow && !wall) L.cls[n] |= CL_INFLOW;
+  }
   L.pst.assign((size_t)NPST * L.nn, 0.0);
   if (l >= 1)
-    build_lps(L, p);
+    build_lps<D>(L, p);
   else
-    build_cip(L, p);
+    build_cip<D>(L, p);
   CHK(upload(pb, &L.d_x, L.x));
   CHK(upload(pb, &L.d_y, L.y));
+  CHK(upload(pb, &L.d_z, L.z));
   CHK(upload(pb, &L.d_pst, L.pst));
   CHK(upload(pb, &L.d_solid, L.solid));
   CHK(upload(pb, &L.d_cls, L.cls));
@@ -317,8 +395,9 @@ fsi_status build_level(fsi_problem* pb, int l) {
   CHK(dalloc(pb, &L.U, (size_t)B * L.nn * NC));
   CHK(dalloc(pb, &L.Uo, (size_t)B * L.nn * NC));
   CHK(dalloc(pb, &L.Dsc, (size_t)B * L.nn * NC));
-  CHK(dalloc_bytes(pb, &L.J, (size_t)B * jslice(L.nn) * ss));
-  if (l >= 1) CHK(dalloc_bytes(pb, &L.Ainv, (size_t)B * NE * NE * L.ncell * ss));
+  CHK(dalloc_bytes(pb, &L.J, (size_t)B * jslice<D>(L.nn) * ss));
+  // Vanka inverses: every smoothed level (in 3d level 0 is smoothed too)
+  if (l >= 1 || D == 3) CHK(dalloc_bytes(pb, &L.Ainv, (size_t)B * NE * NE * L.ncell * ss));
   CHK(dalloc_bytes(pb, &L.x_, (size_t)B * L.nn * NC * ss));
   CHK(dalloc_bytes(pb, &L.b_, (size_t)B * L.nn * NC * ss));
   CHK(dalloc_bytes(pb, &L.r_, (size_t)B * L.nn * NC * ss));
@@ -366,14 +445,16 @@ StepPar step_par(const fsi_problem* pb, double k) {
 }
 
 // ------------------------------------------------------------ assembly
+template <int D>
 fsi_status residual(fsi_problem* pb, int B, const StepPar& sp, const double* U, const double* Uo, double* R,
                     const int* act, hipStream_t st) {
+  FSI_DIM(D);
   Level& F = pb->lev[pb->nlev - 1];
   const Geom g = F.geom();
   {
     ProfScope ps(pb, F_RES, st, (double)B * (F.nn * NC * 8.0 * 3 + F.ncell * NE * 8.0 * 2));
-    k_elem_residual<<<grid1(g.ncell, B), TPB, 0, st>>>(g, sp, U, Uo, pb->Re, act);
-    k_gather_residual<<<grid1(g.nn, B), TPB, 0, st>>>(g, sp, pb->Re, U, pb->tdev, R, act);
+    k_elem_residual<D><<<grid1(g.ncell, B), TPB, 0, st>>>(g, sp, U, Uo, pb->Re, act);
+    k_gather_residual<D><<<grid1(g.nn, B), TPB, 0, st>>>(g, sp, pb->Re, U, pb->tdev, R, act);
   }
   HIPCHK(hipGetLastError());
   return FSI_OK;
@@ -381,10 +462,12 @@ fsi_status residual(fsi_problem* pb, int B, const StepPar& sp, const double* U, 
 
 // Jacobian of the finest level (always) and, when precond is set, the multigrid
 // hierarchy: injected coarse states, coarse-level Jacobians, Vanka inverses and
-// the coarsest-level inverse.
-template <class S>
+// the coarsest-level solver (2d: explicit inverse; 3d: Vanka inverses, the
+// level is smoothed).
+template <int D, class S>
 fsi_status assemble_levels(fsi_problem* pb, int B, const StepPar& sp, const int* act, hipStream_t st,
                            bool precond = true, bool transpose = false, double* save_fine = nullptr) {
+  FSI_DIM(D);
   const int L = pb->nlev - 1;
   for (int l = L; l >= (precond ? 0 : L); --l) {
     Level& lv = pb->lev[l];
@@ -395,25 +478,25 @@ fsi_status assemble_levels(fsi_problem* pb, int B, const StepPar& sp, const int*
       const Level& f = pb->lev[l + 1];
       const double* Uf = (l + 1 == L) ? pb->U : f.U;
       const double* Uof = (l + 1 == L) ? pb->Uold : f.Uo;
-      k_inject<<<grid1(g.nn, B), TPB, 0, st>>>(g, f.geom(), Uf, lv.U, B);
-      k_inject<<<grid1(g.nn, B), TPB, 0, st>>>(g, f.geom(), Uof, lv.Uo, B);
+      k_inject<D><<<grid1(g.nn, B), TPB, 0, st>>>(g, f.geom(), Uf, lv.U);
+      k_inject<D><<<grid1(g.nn, B), TPB, 0, st>>>(g, f.geom(), Uof, lv.Uo);
     }
     {
       ProfScope ps(pb, F_JAC, st, (double)B * (g.ncell * NE * NE * 8.0 + 2.0 * g.nn * NC * 8));
-      k_elem_jacobian<false><<<dim3((g.ncell + 127) / 128, B), 128, 0, st>>>(g, sp, U, Uo, pb->Ke, act);
+      k_elem_jacobian<D, false><<<dim3((g.ncell + 127) / 128, B), 128, 0, st>>>(g, sp, U, Uo, pb->Ke, act);
     }
-    k_gather_jacobian<S><<<grid1(g.nn, B), TPB, 0, st>>>(g, sp.k, pb->Ke, (S*)lv.J, lv.Dsc, act, 1);
+    k_gather_jacobian<D, S><<<grid1(g.nn, B), TPB, 0, st>>>(g, sp.k, pb->Ke, (S*)lv.J, lv.Dsc, act, 1);
     if (transpose) {
-      // adjoint: the operator of every level becomes the transpose of the free block (B = 1)
-      const size_t bytes = jslice(g.nn) * sizeof(S);
+      // adjoint (2d): the operator of every level becomes the transpose of the free block (B = 1)
+      const size_t bytes = jslice<D>(g.nn) * sizeof(S);
       if (l == L && save_fine) HIPCHK(hipMemcpyAsync(save_fine, lv.J, bytes, hipMemcpyDeviceToDevice, st));
       HIPCHK(hipMemcpyAsync(pb->Jtmp, lv.J, bytes, hipMemcpyDeviceToDevice, st));
       k_transpose_J<double><<<grid1(g.nn, 1), TPB, 0, st>>>(g, sp.k, (const double*)pb->Jtmp, (double*)lv.J, lv.Dsc);
     }
     if (!precond) break;
-    if (l >= 1) {
-      k_vanka_factor<S><<<dim3((g.ncell + VF_PATCHES - 1) / VF_PATCHES, B), VF_PATCHES * 32, 0, st>>>(
-          g, sp.k, (const S*)lv.J, (S*)lv.Ainv, act);
+    if (l >= 1 || D == 3) {
+      k_vanka_factor<D, S><<<dim3((g.ncell + vf_patches<D>() - 1) / vf_patches<D>(), B),
+                             vf_lanes<D>() * vf_patches<D>(), 0, st>>>(g, sp.k, (const S*)lv.J, (S*)lv.Ainv, act);
     } else {
       const size_t lds_f = (size_t)5 * pb->cbs * pb->cbs * sizeof(double);
       const size_t lds_i = (size_t)3 * pb->cbs * pb->cbs * sizeof(double);
@@ -428,43 +511,51 @@ fsi_status assemble_levels(fsi_problem* pb, int B, const StepPar& sp, const int*
 }
 
 // y = D (b - A x) (or D A x)
-template <class S>
-void spmv(const Geom& g, int B, double k, const S* J, const S* x, const S* b, const double* D, S* y, const int* act,
+template <int D, class S>
+void spmv(const Geom& g, int B, double k, const S* J, const S* x, const S* b, const double* Dv, S* y, const int* act,
           hipStream_t st) {
-  k_spmv<S><<<dim3((g.nn + 63) / 64, B), SPMV_THREADS, 0, st>>>(g, k, J, x, b, D, y, act);
+  k_spmv<D, S><<<dim3((g.nn + 63) / 64, B), spmv_threads<D>(), 0, st>>>(g, k, J, x, b, Dv, y, act);
 }
 
 // ------------------------------------------------------------ multigrid
-template <class S>
+template <int D, class S>
 void smooth(fsi_problem* pb, int l, int B, double k, int sweeps, bool zero_first, S* x, const S* b, const int* act,
             hipStream_t st) {
+  FSI_DIM(D);
   Level& lv = pb->lev[l];
   const Geom g = lv.geom();
   const S om = (S)pb->p.vanka_omega;
   const bool fine = l == pb->nlev - 1;
-  // the passes alternate between x and the level's residual buffer; four colours
-  // per sweep leave the result in x
+  constexpr int NCOL = Dm<D>::NCOL, VC = vc_cells<D>();
+  // the passes alternate between x and the level's residual buffer; an even
+  // number of colours per sweep leaves the result in x
   S* buf[2] = {x, (S*)lv.r_};
   int cur = 0;
   for (int s = 0; s < sweeps; ++s)
-    for (int c = 0; c < 4; ++c) {
+    for (int c = 0; c < NCOL; ++c) {
       const bool zero = zero_first && s == 0 && c == 0;
-      const int nc = color_info(g.nx, g.ny, c).nc;
+      const int nc = color_info<D>(g, c).nc;
       const double vec = 3.0 * g.nn * NC * sizeof(S);
       const double by = zero ? (double)B * ((double)NE * NE * nc * sizeof(S) + 2.0 * g.nn * NC * sizeof(S))
                              : (double)B * ((double)NSLOT * BLK * g.nn * sizeof(S) + (double)NE * NE * nc * sizeof(S) +
                                             vec) +
                                    (double)NPST * g.nn * 8.0;
       ProfScope ps(pb, fine ? F_SMOOTH : F_COARSE_LEV, st, by);
-      const int npb = (nc + VC_CELLS - 1) / VC_CELLS, ncopy = (g.nn + VC_THREADS - 1) / VC_THREADS;
-      k_vanka_color<S><<<dim3(npb + ncopy, B), VC_THREADS, 0, st>>>(g, k, c, om, zero ? 1 : 0, (const S*)lv.J,
-                                                             (const S*)lv.Ainv, b, buf[cur], buf[cur ^ 1], act);
+      const int npb = (nc + VC - 1) / VC, ncopy = (g.nn + NC * 64 - 1) / (NC * 64);
+      k_vanka_color<D, S><<<dim3(npb + ncopy, B), NC * 64, 0, st>>>(g, k, c, om, zero ? 1 : 0, (const S*)lv.J,
+                                                                     (const S*)lv.Ainv, b, buf[cur], buf[cur ^ 1],
+                                                                     act);
       cur ^= 1;
     }
 }
 
-template <class S>
+// Sweeps of the Vanka smoother that stand in for a direct solve on the 3d
+// coarsest level (17 x 5 x 5 nodes at the workloads' level-0 mesh).
+constexpr int COARSEST_SWEEPS_3D = 4;
+
+template <int D, class S>
 void vcycle(fsi_problem* pb, int B, double k, const S* rhs, S* out, const int* act, hipStream_t st) {
+  FSI_DIM(D);
   const int L = pb->nlev - 1;
   // level L uses rhs/out directly; lower levels their own b_/x_
   for (int l = L; l >= 1; --l) {
@@ -472,41 +563,45 @@ void vcycle(fsi_problem* pb, int B, double k, const S* rhs, S* out, const int* a
     Level& lc = pb->lev[l - 1];
     const S* b = (l == L) ? rhs : (const S*)lv.b_;
     S* x = (l == L) ? out : (S*)lv.x_;
-    smooth<S>(pb, l, B, k, l == L ? pb->p.vanka_sweeps : pb->p.vanka_sweeps_coarse, true, x, b, act, st);
+    smooth<D, S>(pb, l, B, k, l == L ? pb->p.vanka_sweeps : pb->p.vanka_sweeps_coarse, true, x, b, act, st);
     const Geom g = lv.geom();
     {
       const double by = (double)B * ((double)NSLOT * BLK * g.nn * sizeof(S) + 3.0 * g.nn * NC * sizeof(S)) +
                         (double)NPST * g.nn * 8.0;
       ProfScope ps(pb, l == L ? F_LEVEL_RES : F_COARSE_LEV, st, by);
-      spmv<S>(g, B, k, (const S*)lv.J, x, b, nullptr, (S*)lv.r_, act, st);
+      spmv<D, S>(g, B, k, (const S*)lv.J, x, b, nullptr, (S*)lv.r_, act, st);
     }
-    k_restrict<S><<<grid1(lc.nn, B), TPB, 0, st>>>(lc.geom(), g, (const S*)lv.r_, (S*)lc.b_, act);
+    k_restrict<D, S><<<grid1(lc.nn, B), TPB, 0, st>>>(lc.geom(), g, (const S*)lv.r_, (S*)lc.b_, act);
   }
   {
     Level& l0 = pb->lev[0];
     const int n0 = l0.nn * NC;
-    ProfScope ps(pb, F_COARSE_SOLVE, st, (double)B * ((double)n0 * n0 + 2.0 * n0) * sizeof(S));
-    k_coarse_gemv<S><<<dim3((n0 + 63) / 64, B), TPB, 0, st>>>(l0.geom(), (const S*)pb->cAinv, (const S*)l0.b_,
-                                                                    (S*)l0.x_, act);
+    if constexpr (D == 2) {
+      ProfScope ps(pb, F_COARSE_SOLVE, st, (double)B * ((double)n0 * n0 + 2.0 * n0) * sizeof(S));
+      k_coarse_gemv<S><<<dim3((n0 + 63) / 64, B), TPB, 0, st>>>(l0.geom(), (const S*)pb->cAinv, (const S*)l0.b_,
+                                                                (S*)l0.x_, act);
+    } else {
+      smooth<D, S>(pb, 0, B, k, COARSEST_SWEEPS_3D, true, (S*)l0.x_, (const S*)l0.b_, act, st);
+    }
   }
   for (int l = 1; l <= L; ++l) {
     Level& lv = pb->lev[l];
     Level& lc = pb->lev[l - 1];
     const S* b = (l == L) ? rhs : (const S*)lv.b_;
     S* x = (l == L) ? out : (S*)lv.x_;
-    k_prolong_add<S><<<grid1(lv.nn, B), TPB, 0, st>>>(lv.geom(), lc.geom(), (const S*)lc.x_, x, act);
-    smooth<S>(pb, l, B, k, l == L ? pb->p.vanka_sweeps : pb->p.vanka_sweeps_coarse, false, x, b, act, st);
+    k_prolong_add<D, S><<<grid1(lv.nn, B), TPB, 0, st>>>(lv.geom(), lc.geom(), (const S*)lc.x_, x, act);
+    smooth<D, S>(pb, l, B, k, l == L ? pb->p.vanka_sweeps : pb->p.vanka_sweeps_coarse, false, x, b, act, st);
   }
 }
 
 // One V-cycle on the finest-level buffers (rhs = pb->tmp, out = pb->w), replayed
 // from a captured graph when no per-kernel profiling is requested.  The graph
 // depends on the batch size and the step size; pointers are fixed per problem.
-template <class S>
+template <int D, class S>
 fsi_status vcycle_run(fsi_problem* pb, int B, double k, hipStream_t st) {
   const bool mixed = sizeof(S) == 4;
   if (!pb->use_graphs || pb->prof.on) {
-    vcycle<S>(pb, B, k, (const S*)pb->tmp, (S*)pb->w, pb->gact, st);
+    vcycle<D, S>(pb, B, k, (const S*)pb->tmp, (S*)pb->w, pb->gact, st);
     HIPCHK(hipGetLastError());
     return FSI_OK;
   }
@@ -517,7 +612,7 @@ fsi_status vcycle_run(fsi_problem* pb, int B, double k, hipStream_t st) {
     }
     hipGraph_t graph;
     HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-    vcycle<S>(pb, B, k, (const S*)pb->tmp, (S*)pb->w, pb->gact, st);
+    vcycle<D, S>(pb, B, k, (const S*)pb->tmp, (S*)pb->w, pb->gact, st);
     HIPCHK(hipStreamEndCapture(st, &graph));
     HIPCHK(hipGraphInstantiate(&pb->vc_exec, graph, nullptr, nullptr, 0));
     HIPCHK(hipGraphDestroy(graph));
@@ -533,8 +628,9 @@ fsi_status vcycle_run(fsi_problem* pb, int B, double k, hipStream_t st) {
 // Solve J dx = -R for the slices with nact[b] = 1 (row-scaled system D J dx = -D R),
 // right-preconditioned FGMRES(R) with classical Gram-Schmidt applied twice; the
 // preconditioner is one multigrid V-cycle.  The solution (type S) goes to pb->xs.
-template <class S>
+template <int D, class S>
 fsi_status fgmres(fsi_problem* pb, int B, double k, std::vector<int>& kits, hipStream_t st) {
+  FSI_DIM(D);
   Level& F = pb->lev[pb->nlev - 1];
   const Geom g = F.geom();
   const int n = F.nn * NC;
@@ -560,7 +656,7 @@ fsi_status fgmres(fsi_problem* pb, int B, double k, std::vector<int>& kits, hipS
       k_scale_rhs<S><<<grid1(n, B), TPB, 0, st>>>(n, pb->Res, F.Dsc, V, vb, pb->gact);
     } else {
       k_scale_rhs<S><<<grid1(n, B), TPB, 0, st>>>(n, pb->Res, nullptr, tmp, (size_t)n, pb->gact);
-      spmv<S>(g, B, k, (const S*)F.J, xs, tmp, F.Dsc, w, pb->gact, st);
+      spmv<D, S>(g, B, k, (const S*)F.J, xs, tmp, F.Dsc, w, pb->gact, st);
       k_scale<S><<<grid1(n, B), TPB, 0, st>>>(n, w, (size_t)n, V, vb, nullptr, 0, 2, pb->gact);
     }
     k_multidot<S><<<dim3(nchunk, B), RED_T, 0, st>>>(n, 1, V, vb, V, vb, 0, chunk, pb->partial, nchunk, pb->gact);
@@ -581,14 +677,14 @@ fsi_status fgmres(fsi_problem* pb, int B, double k, std::vector<int>& kits, hipS
       S* Zj = Z + (size_t)j * n;
       // Z_j = M^{-1} (V_j / D);  a = D J Z_j  (the new Arnoldi vector a lives in tmp)
       k_unscale<S><<<grid1(n, B), TPB, 0, st>>>(n, Vj, vb, F.Dsc, tmp, pb->gact);
-      CHK(vcycle_run<S>(pb, B, k, st));
+      CHK(vcycle_run<D, S>(pb, B, k, st));
       k_scale<S><<<grid1(n, B), TPB, 0, st>>>(n, w, (size_t)n, Zj, zb, nullptr, 0, 2, pb->gact);
       S* a = tmp;
       {
         ProfScope ps(pb, F_GMRES_SPMV, st,
                      (double)B * ((double)NSLOT * BLK * F.nn * sizeof(S) + 2.0 * n * sizeof(S) + n * 8.0) +
                          (double)NPST * F.nn * 8.0);
-        spmv<S>(g, B, k, (const S*)F.J, w, nullptr, F.Dsc, a, pb->gact, st);
+        spmv<D, S>(g, B, k, (const S*)F.J, w, nullptr, F.Dsc, a, pb->gact, st);
       }
       // classical Gram-Schmidt, twice
       k_multidot<S><<<dim3(nchunk, B), RED_T, 0, st>>>(n, j + 1, a, (size_t)n, V, vb, (size_t)n, chunk, pb->partial,
@@ -639,7 +735,7 @@ struct RunStats {
   std::vector<int> newton, krylov, status;
 };
 
-template <class S>
+template <int D, class S>
 fsi_status newton_solve_step(fsi_problem* pb, int B, const StepPar& sp, std::vector<int>& hact, RunStats& rs,
                              hipStream_t st) {
   Level& F = pb->lev[pb->nlev - 1];
@@ -658,11 +754,11 @@ fsi_status newton_solve_step(fsi_problem* pb, int B, const StepPar& sp, std::vec
                               : std::min(1e-2, std::max(pb->p.lin_rtol, 0.1 * pb->p.newton_rtol / est_prev[b]));
     const int k0 = rs.krylov[0];
     HIPCHK(hipMemcpyAsync(pb->nact, nact.data(), B * sizeof(int), hipMemcpyHostToDevice, st));
-    CHK(residual(pb, B, sp, pb->U, pb->Uold, pb->Res, pb->nact, st));
-    CHK(assemble_levels<S>(pb, B, sp, pb->nact, st, it == 1 || pb->p.precond_lag == 0));
-    fsi_status ls = fgmres<S>(pb, B, sp.k, rs.krylov, st);
+    CHK(residual<D>(pb, B, sp, pb->U, pb->Uold, pb->Res, pb->nact, st));
+    CHK(assemble_levels<D, S>(pb, B, sp, pb->nact, st, it == 1 || pb->p.precond_lag == 0));
+    fsi_status ls = fgmres<D, S>(pb, B, sp.k, rs.krylov, st);
     if (ls != FSI_OK && ls != FSI_ERR_LINEAR) return ls;
-    k_newton_update<S><<<dim3(pb->nchunk_n, B), RED_T, 0, st>>>(nn, pb->U, (const S*)pb->xs, pb->chunk_n, pb->npart,
+    k_newton_update<D, S><<<dim3(pb->nchunk_n, B), RED_T, 0, st>>>(nn, pb->U, (const S*)pb->xs, pb->chunk_n, pb->npart,
                                                                  pb->nchunk_n, pb->nact);
     k_max_partials<<<(B + 63) / 64, 64, 0, st>>>(pb->nchunk_n, pb->npart, pb->nmax, B);
     HIPCHK(hipGetLastError());
@@ -713,9 +809,10 @@ fsi_status newton_solve_step(fsi_problem* pb, int B, const StepPar& sp, std::vec
   return FSI_OK;
 }
 
-template <class S>
+template <int D, class S>
 fsi_status propagate(fsi_problem* pb, int B, const double* t0, double slice_len, int nsteps, const double* U_in,
                      double* U_out, fsi_stats* stats, hipStream_t st) {
+  FSI_DIM(D);
   Level& F = pb->lev[pb->nlev - 1];
   const Geom g = F.geom();
   const size_t ndof = (size_t)F.nn * NC;
@@ -750,9 +847,9 @@ fsi_status propagate(fsi_problem* pb, int B, const double* t0, double slice_len,
     HIPCHK(hipMemcpyAsync(pb->Uold, pb->U, (size_t)B * ndof * sizeof(double), hipMemcpyDeviceToDevice, st));
     // Newton guess: the old state (first step) or the linear extrapolation of the last two
     if (n >= 2) k_extrapolate<<<dim3(64, B), TPB, 0, st>>>(ndof, pb->U, pb->Uold, pb->Uprev, pb->nact);
-    k_apply_dirichlet<<<grid1(F.nn, B), TPB, 0, st>>>(g, sp, pb->U, pb->tdev, pb->nact);
+    k_apply_dirichlet<D><<<grid1(F.nn, B), TPB, 0, st>>>(g, sp, pb->U, pb->tdev, pb->nact);
     HIPCHK(hipGetLastError());
-    CHK(newton_solve_step<S>(pb, B, sp, hact, rs, st));
+    CHK(newton_solve_step<D, S>(pb, B, sp, hact, rs, st));
     if (pb->traj_out)
       HIPCHK(hipMemcpyAsync(pb->traj_out + (size_t)(n - 1) * B * ndof, pb->U, (size_t)B * ndof * sizeof(double),
                             hipMemcpyDeviceToDevice, st));
@@ -792,8 +889,11 @@ fsi_status run_propagate(fsi_problem* pb, int B, const double* t0, double slice_
   HIPCHK(hipEventRecord(pb->iev, caller));
   HIPCHK(hipStreamWaitEvent(pb->ist, pb->iev, 0));
   hipStream_t st = pb->ist;
-  return pb->mixed ? propagate<float>(pb, B, t0, slice_len, nsteps, U_in, U_out, stats, st)
-                   : propagate<double>(pb, B, t0, slice_len, nsteps, U_in, U_out, stats, st);
+  if (pb->p.dim == 3)
+    return pb->mixed ? propagate<3, float>(pb, B, t0, slice_len, nsteps, U_in, U_out, stats, st)
+                     : propagate<3, double>(pb, B, t0, slice_len, nsteps, U_in, U_out, stats, st);
+  return pb->mixed ? propagate<2, float>(pb, B, t0, slice_len, nsteps, U_in, U_out, stats, st)
+                   : propagate<2, double>(pb, B, t0, slice_len, nsteps, U_in, U_out, stats, st);
 }
 
 // ------------------------------------------------------------ adjoint
@@ -821,12 +921,13 @@ std::vector<DragFace> drag_faces(const Level& L) {
 }
 
 fsi_status adjoint_alloc(fsi_problem* pb, size_t nstates, int N) {
+  FSI_DIM(2);
   Level& F = pb->lev[pb->nlev - 1];
   const size_t nd = (size_t)F.nn * NC;
   if (!pb->Jtmp) {
-    CHK(dalloc(pb, &pb->Jtmp, jslice(F.nn)));
-    CHK(dalloc(pb, &pb->Jcopy, jslice(F.nn)));
-    CHK(dalloc(pb, &pb->Jold, jslice(F.nn)));
+    CHK(dalloc(pb, &pb->Jtmp, jslice<2>(F.nn)));
+    CHK(dalloc(pb, &pb->Jcopy, jslice<2>(F.nn)));
+    CHK(dalloc(pb, &pb->Jold, jslice<2>(F.nn)));
     CHK(dalloc(pb, &pb->lam, nd));
     CHK(dalloc(pb, &pb->lamn, nd));
     CHK(dalloc(pb, &pb->arhs, nd));
@@ -853,6 +954,7 @@ fsi_status adjoint_alloc(fsi_problem* pb, size_t nstates, int N) {
 // backward sweep of transposed Newton-Jacobian solves (FP64).
 fsi_status adjoint_run(fsi_problem* pb, double T, int N, int m, const double* U0, double* J_out, double* grad_out,
                        fsi_stats* stats, hipStream_t caller) {
+  FSI_DIM(2);
   Level& F = pb->lev[pb->nlev - 1];
   const Geom g = F.geom();
   const size_t nd = (size_t)F.nn * NC;
@@ -914,20 +1016,20 @@ fsi_status adjoint_run(fsi_problem* pb, double T, int N, int m, const double* U0
     HIPCHK(hipMemsetAsync(pb->arhs, 0, nd * sizeof(double), st));
     k_drag_gradient<<<1, 1, 0, st>>>(g, rn, pb->faces, pb->nfaces, cur(s), -k, pb->arhs);
     if (s < S) {
-      k_elem_jacobian<true><<<dim3((g.ncell + 127) / 128, 1), 128, 0, st>>>(g, sp, cur(s + 1), prev(s + 1), pb->Ke,
+      k_elem_jacobian<2, true><<<dim3((g.ncell + 127) / 128, 1), 128, 0, st>>>(g, sp, cur(s + 1), prev(s + 1), pb->Ke,
                                                                            nullptr);
-      k_gather_jacobian<double><<<grid1(g.nn, 1), TPB, 0, st>>>(g, k, pb->Ke, pb->Jold, nullptr, nullptr, 0);
+      k_gather_jacobian<2, double><<<grid1(g.nn, 1), TPB, 0, st>>>(g, k, pb->Ke, pb->Jold, nullptr, nullptr, 0);
       k_spmv_T<double><<<grid1(g.nn, 1), TPB, 0, st>>>(g, k, pb->Jold, pb->lamn, pb->ay, 0);
       k_daxpy<<<64, TPB, 0, st>>>(nd, -1.0, pb->ay, pb->arhs);
     }
     // transposed multigrid hierarchy at (U^s, U^{s-1})
     HIPCHK(hipMemcpyAsync(pb->U, cur(s), nd * sizeof(double), hipMemcpyDeviceToDevice, st));
     HIPCHK(hipMemcpyAsync(pb->Uold, prev(s), nd * sizeof(double), hipMemcpyDeviceToDevice, st));
-    CHK(assemble_levels<double>(pb, 1, sp, pb->nact, st, true, true, pb->Jcopy));
+    CHK(assemble_levels<2, double>(pb, 1, sp, pb->nact, st, true, true, pb->Jcopy));
     // free unknowns: Krylov solve with the Dirichlet entries of the right-hand side removed
     k_adjoint_rhs<<<grid1(g.nn, 1), TPB, 0, st>>>(g, pb->arhs, pb->Res);
     HIPCHK(hipGetLastError());
-    fsi_status ls = fgmres<double>(pb, 1, k, kits, st);
+    fsi_status ls = fgmres<2, double>(pb, 1, k, kits, st);
     if (ls != FSI_OK) { ret = ls; break; }
     HIPCHK(hipMemcpyAsync(pb->lam, pb->xs, nd * sizeof(double), hipMemcpyDeviceToDevice, st));
     // Dirichlet unknowns: lam_D = rhs_D - (J^T lam)_D
@@ -988,13 +1090,14 @@ fsi_status fsi_setup(const fsi_params* prm, fsi_problem** out) {
   if (!prm || !out) return FSI_ERR_ARG;
   *out = nullptr;
   const fsi_params& p = *prm;
-  if (p.dim != 2 || p.level < 1 || p.level > MAXLEV - 2 || p.max_batch < 1 || p.max_batch > FSI_MAX_SLICES ||
+  if ((p.dim != 2 && p.dim != 3) || p.level < 1 || p.level > MAXLEV - 2 || p.max_batch < 1 ||
+      p.max_batch > FSI_MAX_SLICES ||
       p.gmres_restart < 1 || p.gmres_restart > 63 || p.newton_maxit < 1 || p.vanka_sweeps < 1 ||
       p.vanka_sweeps_coarse < 1 ||
       p.gmres_maxit < 1 || (p.precision != FSI_FP64 && p.precision != FSI_MIXED) ||
       (p.precond_lag != 0 && p.precond_lag != 1) || !(p.lin_rtol_first > 0.0 && p.lin_rtol_first < 1.0))
     return FSI_ERR_ARG;
-  for (int a = 0; a < 2; ++a) {
+  for (int a = 0; a < p.dim; ++a) {
     if (p.nseg[a] < 1 || p.nseg[a] > 4) return FSI_ERR_ARG;
     for (int s = 0; s < p.nseg[a]; ++s)
       if (p.seg_cells[a][s] < 1 || !(p.seg_pts[a][s + 1] > p.seg_pts[a][s])) return FSI_ERR_ARG;
@@ -1016,19 +1119,23 @@ fsi_status fsi_setup(const fsi_params* prm, fsi_problem** out) {
     pb->verbose = v && v[0] == '1';
   }
   fsi_status s = FSI_OK;
-  for (int l = 0; l < pb->nlev && s == FSI_OK; ++l) s = build_level(pb, l);
+  for (int l = 0; l < pb->nlev && s == FSI_OK; ++l) s = p.dim == 3 ? build_level<3>(pb, l) : build_level<2>(pb, l);
   if (s != FSI_OK) { fsi_destroy(pb); return s; }
   Level& F = pb->lev[pb->nlev - 1];
   Level& C = pb->lev[0];
   const int B = pb->Bmax;
+  const int NC = p.dim == 3 ? Dm<3>::NC : Dm<2>::NC;
+  const int NE = p.dim == 3 ? Dm<3>::NE : Dm<2>::NE;
   const size_t ndof = (size_t)F.nn * NC;
   const size_t ss = pb->ssz;
   const int R = pb->R;
   pb->chunk_n = 2048;
   pb->nchunk_n = (F.nn + pb->chunk_n - 1) / pb->chunk_n;
-  pb->cbs = 2 * (C.ny + 1) * NC;
-  pb->cnsb = (C.nx + 1 + 1) / 2;
-  if (pb->cbs > 64 || C.nn * NC > 2048) { fsi_destroy(pb); return FSI_ERR_ARG; }
+  // 2d coarsest level: block-tridiagonal direct solve over super-columns of two node columns
+  const bool direct = p.dim == 2;
+  pb->cbs = direct ? 2 * (C.ny + 1) * NC : 1;
+  pb->cnsb = direct ? (C.nx + 1 + 1) / 2 : 1;
+  if (direct && (pb->cbs > 64 || C.nn * NC > 2048)) { fsi_destroy(pb); return FSI_ERR_ARG; }
   const size_t cb2 = (size_t)pb->cbs * pb->cbs * pb->cnsb * B;
 #define A_(x) do { s = (x); if (s != FSI_OK) { fsi_destroy(pb); return s; } } while (0)
   A_(dalloc(pb, &pb->U, B * ndof));
@@ -1065,7 +1172,7 @@ fsi_status fsi_setup(const fsi_params* prm, fsi_problem** out) {
   A_(dalloc(pb, &pb->cW, cb2));
   A_(dalloc(pb, &pb->cL, cb2));
   A_(dalloc(pb, &pb->cY, (size_t)B * pb->cnsb * pb->cnsb * pb->cbs * pb->cbs));
-  A_(dalloc_bytes(pb, &pb->cAinv, (size_t)B * C.nn * NC * C.nn * NC * ss));
+  A_(dalloc_bytes(pb, &pb->cAinv, direct ? (size_t)B * C.nn * NC * C.nn * NC * ss : 1));
   A_(dalloc(pb, &pb->npart, (size_t)B * 6 * pb->nchunk_n));
   A_(dalloc(pb, &pb->nmax, (size_t)B * 6));
 #undef A_
@@ -1089,18 +1196,21 @@ fsi_status fsi_sizes(const fsi_problem* pb, int64_t* n_nodes, int64_t* n_dofs) {
   if (!pb) return FSI_ERR_ARG;
   const Level& F = pb->lev[pb->nlev - 1];
   if (n_nodes) *n_nodes = F.nn;
-  if (n_dofs) *n_dofs = (int64_t)F.nn * NC;
+  if (n_dofs) *n_dofs = (int64_t)F.nn * (2 * pb->p.dim + 1);
   return FSI_OK;
 }
 
 fsi_status fsi_initial_state(fsi_problem* pb, double* U0, hipStream_t st) {
   if (!pb || !U0) return FSI_ERR_ARG;
   Level& F = pb->lev[pb->nlev - 1];
-  const size_t ndof = (size_t)F.nn * NC;
+  const size_t ndof = (size_t)F.nn * (2 * pb->p.dim + 1);
   HIPCHK(hipMemsetAsync(U0, 0, ndof * sizeof(double), st));
   double t0 = 0.0;
   HIPCHK(hipMemcpyAsync(pb->tdev, &t0, sizeof(double), hipMemcpyHostToDevice, st));
-  k_apply_dirichlet<<<grid1(F.nn, 1), TPB, 0, st>>>(F.geom(), step_par(pb, 1.0), U0, pb->tdev, nullptr);
+  if (pb->p.dim == 3)
+    k_apply_dirichlet<3><<<grid1(F.nn, 1), TPB, 0, st>>>(F.geom(), step_par(pb, 1.0), U0, pb->tdev, nullptr);
+  else
+    k_apply_dirichlet<2><<<grid1(F.nn, 1), TPB, 0, st>>>(F.geom(), step_par(pb, 1.0), U0, pb->tdev, nullptr);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(st));
   return FSI_OK;
@@ -1121,7 +1231,7 @@ fsi_status parareal_run(fsi_problem* pb, double T, int32_t N, int32_t m, int32_t
   if (!pb || !U0 || !Ub || N < 1 || N > pb->Bmax || m < 1 || M < 1 || !(T > 0.0) || max_iter < 1) return FSI_ERR_ARG;
   if (max_iter > N) max_iter = N;
   Level& F = pb->lev[pb->nlev - 1];
-  const size_t nd = (size_t)F.nn * NC;
+  const size_t nd = (size_t)F.nn * (2 * pb->p.dim + 1);
   const double dl = T / N;
   double *Cold = nullptr, *Fv = nullptr, *Up = nullptr, *Cn = nullptr, *part = nullptr;
   const int chunk = 4096, nchunk = (F.nn + chunk - 1) / chunk;
@@ -1179,7 +1289,10 @@ fsi_status parareal_run(fsi_problem* pb, double T, int32_t N, int32_t m, int32_t
         if (cn != Cold + l * nd)
           if (hipMemcpyAsync(Cold + l * nd, Cn, nd * sizeof(double), hipMemcpyDeviceToDevice, st) != hipSuccess) { ret = FSI_ERR_HIP; goto done; }
       }
-      k_change_norms<<<dim3(nchunk, N + 1), RED_T, 0, st>>>(F.nn, Ub, Up, chunk, part, nchunk);
+      if (pb->p.dim == 3)
+        k_change_norms<3><<<dim3(nchunk, N + 1), RED_T, 0, st>>>(F.nn, Ub, Up, chunk, part, nchunk);
+      else
+        k_change_norms<2><<<dim3(nchunk, N + 1), RED_T, 0, st>>>(F.nn, Ub, Up, chunk, part, nchunk);
       if (hipGetLastError() != hipSuccess) { ret = FSI_ERR_HIP; goto done; }
       if (hipMemcpyAsync(hp.data(), part, hp.size() * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
           hipStreamSynchronize(st) != hipSuccess) { ret = FSI_ERR_HIP; goto done; }
@@ -1213,7 +1326,7 @@ done:
 fsi_status adjoint_gradient(fsi_problem* pb, double T, int32_t N, int32_t m, const double* U0, double* J_out,
                             double* grad_out, fsi_stats* stats, hipStream_t st) {
   if (!pb || !U0 || !J_out || !grad_out || N < 1 || N > pb->Bmax || m < 1 || !(T > 0.0)) return FSI_ERR_ARG;
-  if (pb->mixed) return FSI_ERR_ARG;   // the adjoint runs in the FP64 path
+  if (pb->mixed || pb->p.dim != 2) return FSI_ERR_ARG;   // the adjoint runs in the 2d FP64 path
   return adjoint_run(pb, T, N, m, U0, J_out, grad_out, stats, st);
 }
 
@@ -1221,58 +1334,64 @@ fsi_status fsi_debug_residual(fsi_problem* pb, int32_t B, const double* U, const
                               double k, double* R, hipStream_t st) {
   if (!pb || !U || !Uo || !t || !R || B <= 0 || B > pb->Bmax || !(k > 0)) return FSI_ERR_ARG;
   HIPCHK(hipMemcpyAsync(pb->tdev, t, B * sizeof(double), hipMemcpyHostToDevice, st));
-  CHK(residual(pb, B, step_par(pb, k), U, Uo, R, nullptr, st));
+  if (pb->p.dim == 3)
+    CHK(residual<3>(pb, B, step_par(pb, k), U, Uo, R, nullptr, st));
+  else
+    CHK(residual<2>(pb, B, step_par(pb, k), U, Uo, R, nullptr, st));
   HIPCHK(hipStreamSynchronize(st));
   return FSI_OK;
 }
 
-fsi_status fsi_debug_jacobian_apply(fsi_problem* pb, int32_t B, const double* U, const double* Uo, const double* t,
-                                    double k, const double* X, double* Y, hipStream_t st) {
-  if (!pb || !U || !Uo || !t || !X || !Y || B <= 0 || B > pb->Bmax || !(k > 0)) return FSI_ERR_ARG;
+}  // extern "C"
+
+namespace {
+
+// Debug entries: assemble the hierarchy at (U, Uo, t, k), then Y = J X (what = 0)
+// or Y = one V-cycle applied to X (what = 1); FP64 in and out.
+template <int D, class S>
+fsi_status debug_apply(fsi_problem* pb, int B, const double* U, const double* Uo, const double* t, double k,
+                       const double* X, double* Y, int what, hipStream_t st) {
+  FSI_DIM(D);
   Level& F = pb->lev[pb->nlev - 1];
   const size_t ndof = (size_t)F.nn * NC;
   const StepPar sp = step_par(pb, k);
   HIPCHK(hipMemcpyAsync(pb->tdev, t, B * sizeof(double), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(pb->U, U, B * ndof * sizeof(double), hipMemcpyDeviceToDevice, st));
   HIPCHK(hipMemcpyAsync(pb->Uold, Uo, B * ndof * sizeof(double), hipMemcpyDeviceToDevice, st));
-  if (pb->mixed) {
-    CHK(assemble_levels<float>(pb, B, sp, nullptr, st));
-    k_convert<double, float><<<1024, TPB, 0, st>>>(B * ndof, X, (float*)pb->tmp);
-    k_spmv<float><<<dim3((F.nn + 63) / 64, B), SPMV_THREADS, 0, st>>>(F.geom(), k, (const float*)F.J,
-                                                                      (const float*)pb->tmp, nullptr, nullptr,
-                                                                      (float*)pb->w, nullptr);
-    k_convert<float, double><<<1024, TPB, 0, st>>>(B * ndof, (const float*)pb->w, Y);
-  } else {
-    CHK(assemble_levels<double>(pb, B, sp, nullptr, st));
-    k_spmv<double><<<dim3((F.nn + 63) / 64, B), SPMV_THREADS, 0, st>>>(F.geom(), k, (const double*)F.J, X, nullptr,
-                                                                        nullptr, Y, nullptr);
-  }
+  CHK(assemble_levels<D, S>(pb, B, sp, nullptr, st));
+  k_convert<double, S><<<1024, TPB, 0, st>>>(B * ndof, X, (S*)pb->tmp);
+  if (what == 0)
+    spmv<D, S>(F.geom(), B, k, (const S*)F.J, (const S*)pb->tmp, nullptr, nullptr, (S*)pb->w, nullptr, st);
+  else
+    vcycle<D, S>(pb, B, k, (const S*)pb->tmp, (S*)pb->w, nullptr, st);
+  k_convert<S, double><<<1024, TPB, 0, st>>>(B * ndof, (const S*)pb->w, Y);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(st));
   return FSI_OK;
+}
+
+fsi_status debug_dispatch(fsi_problem* pb, int B, const double* U, const double* Uo, const double* t, double k,
+                          const double* X, double* Y, int what, hipStream_t st) {
+  if (!pb || !U || !Uo || !t || !X || !Y || B <= 0 || B > pb->Bmax || !(k > 0)) return FSI_ERR_ARG;
+  if (pb->p.dim == 3)
+    return pb->mixed ? debug_apply<3, float>(pb, B, U, Uo, t, k, X, Y, what, st)
+                     : debug_apply<3, double>(pb, B, U, Uo, t, k, X, Y, what, st);
+  return pb->mixed ? debug_apply<2, float>(pb, B, U, Uo, t, k, X, Y, what, st)
+                   : debug_apply<2, double>(pb, B, U, Uo, t, k, X, Y, what, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+fsi_status fsi_debug_jacobian_apply(fsi_problem* pb, int32_t B, const double* U, const double* Uo, const double* t,
+                                    double k, const double* X, double* Y, hipStream_t st) {
+  return debug_dispatch(pb, B, U, Uo, t, k, X, Y, 0, st);
 }
 
 fsi_status fsi_debug_vcycle(fsi_problem* pb, int32_t B, const double* U, const double* Uo, const double* t, double k,
                             const double* X, double* Y, hipStream_t st) {
-  if (!pb || !U || !Uo || !t || !X || !Y || B <= 0 || B > pb->Bmax || !(k > 0)) return FSI_ERR_ARG;
-  Level& F = pb->lev[pb->nlev - 1];
-  const size_t ndof = (size_t)F.nn * NC;
-  const StepPar sp = step_par(pb, k);
-  HIPCHK(hipMemcpyAsync(pb->tdev, t, B * sizeof(double), hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(pb->U, U, B * ndof * sizeof(double), hipMemcpyDeviceToDevice, st));
-  HIPCHK(hipMemcpyAsync(pb->Uold, Uo, B * ndof * sizeof(double), hipMemcpyDeviceToDevice, st));
-  if (pb->mixed) {
-    CHK(assemble_levels<float>(pb, B, sp, nullptr, st));
-    k_convert<double, float><<<1024, TPB, 0, st>>>(B * ndof, X, (float*)pb->tmp);
-    vcycle<float>(pb, B, k, (const float*)pb->tmp, (float*)pb->w, nullptr, st);
-    k_convert<float, double><<<1024, TPB, 0, st>>>(B * ndof, (const float*)pb->w, Y);
-  } else {
-    CHK(assemble_levels<double>(pb, B, sp, nullptr, st));
-    vcycle<double>(pb, B, k, X, Y, nullptr, st);
-  }
-  HIPCHK(hipGetLastError());
-  HIPCHK(hipStreamSynchronize(st));
-  return FSI_OK;
+  return debug_dispatch(pb, B, U, Uo, t, k, X, Y, 1, st);
 }
 
 fsi_status fsi_profile_enable(fsi_problem* pb, int32_t on) {

@@ -1,6 +1,9 @@
 // Internal definitions shared by the HIP kernels and the host driver of the
-// ALE-FSI fine propagator.  2d, Q1 elements, 5 unknowns per node
-// (v_x, v_y, u_x, u_y, p).
+// ALE-FSI fine propagator.  Q1 elements on tensor-product meshes in 2d
+// (quadrilaterals, 5 unknowns per node: v_x, v_y, u_x, u_y, p) and 3d
+// (hexahedra, 7 unknowns per node: v_x, v_y, v_z, u_x, u_y, u_z, p).  Every
+// kernel and driver routine that depends on the dimension takes it as the
+// template parameter D and reads its sizes from Dm<D>.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <cstdint>
@@ -10,81 +13,171 @@
 
 namespace fsi {
 
-constexpr int NC = 5;      // unknowns per node
-constexpr int NL = 4;      // nodes per cell
-constexpr int NE = 20;     // unknowns per cell
-constexpr int NSLOT = 9;   // block-stencil slots (3x3 neighbourhood)
-constexpr int NPST = 25;   // pressure-stencil slots (5x5 neighbourhood)
-constexpr int BLK = 25;    // entries of a 5x5 block
-constexpr int RED_T = 256; // threads of the reduction kernels
+template <int D>
+struct Dm;
+template <>
+struct Dm<2> {
+  static constexpr int NC = 5;      // unknowns per node
+  static constexpr int NL = 4;      // nodes per cell
+  static constexpr int NE = 20;     // unknowns per cell
+  static constexpr int NSLOT = 9;   // block-stencil slots (3x3 neighbourhood)
+  static constexpr int NPST = 25;   // pressure-stencil slots (5x5 neighbourhood)
+  static constexpr int BLK = 25;    // entries of a 5x5 block
+  static constexpr int NCOL = 4;    // cell colours of the Vanka sweep
+};
+template <>
+struct Dm<3> {
+  static constexpr int NC = 7;
+  static constexpr int NL = 8;
+  static constexpr int NE = 56;
+  static constexpr int NSLOT = 27;  // 3x3x3
+  static constexpr int NPST = 125;  // 5x5x5
+  static constexpr int BLK = 49;    // 7x7
+  static constexpr int NCOL = 8;
+};
 
-// component bits of the Dirichlet mask
-constexpr uint8_t DM_V = 0x03, DM_U = 0x0c, DM_P = 0x10;
+// Local copies of the sizes of dimension D inside a templated function.
+#define FSI_DIM(D)                                      \
+  [[maybe_unused]] constexpr int NC = Dm<D>::NC;       \
+  [[maybe_unused]] constexpr int NL = Dm<D>::NL;       \
+  [[maybe_unused]] constexpr int NE = Dm<D>::NE;       \
+  [[maybe_unused]] constexpr int NSLOT = Dm<D>::NSLOT; \
+  [[maybe_unused]] constexpr int NPST = Dm<D>::NPST;   \
+  [[maybe_unused]] constexpr int BLK = Dm<D>::BLK;     \
+  [[maybe_unused]] constexpr int PC = 2 * D   // component index of p
+
+constexpr int RED_T = 256;  // threads of the reduction kernels
+
+// component bits of the Dirichlet mask: v = bits 0..D-1, u = bits D..2D-1, p = bit 2D
+template <int D>
+__host__ __device__ constexpr uint8_t dm_v() { return (uint8_t)((1u << D) - 1u); }
+template <int D>
+__host__ __device__ constexpr uint8_t dm_u() { return (uint8_t)(((1u << D) - 1u) << D); }
+template <int D>
+__host__ __device__ constexpr uint8_t dm_p() { return (uint8_t)(1u << (2 * D)); }
 // node class bits
 constexpr uint8_t CL_NS = 0x01;     // node of a solid cell
 constexpr uint8_t CL_NF = 0x02;     // node of a fluid cell
 constexpr uint8_t CL_INFLOW = 0x04; // inflow node carrying the parabolic profile
 
-// Device view of one mesh level (all pointers device memory).
+// Device view of one mesh level (all pointers device memory).  Node (i, j, k)
+// has index i + (nx+1) (j + (ny+1) k), cell (i, j, k) index i + nx (j + ny k);
+// in 2d nz = 0, k = 0 and z is unused.
 struct Geom {
-  int nx, ny, nn, ncell;
+  int nx, ny, nz, nn, ncell;
   const double* x;          // [nx+1] node x-coordinates
-  const double* y;          // [ny+1] node y-coordinates
+  const double* y;          // [ny+1]
+  const double* z;          // [nz+1] (3d)
   const uint8_t* solid;     // [ncell] 1 = solid cell
   const uint8_t* cls;       // [nn] node class bits
   const uint8_t* dmask;     // [nn] Dirichlet component mask (bit c -> component c)
-  const double* pst;        // [25][nn] constant pressure stencil (LPS or CIP), zero on Dirichlet p rows
+  const double* pst;        // [NPST][nn] constant pressure stencil (LPS or CIP), zero on Dirichlet p rows
 };
 
-// Physical and step constants of one time step.
-struct StepPar {
-  double k, theta;
-  double rho_f, nu_f, rho_s, mu_s, lambda_s;
-  double peak, ramp_time;
-};
+template <int D>
+__host__ __device__ inline void node_ijk(const Geom& g, int n, int& i, int& j, int& k) {
+  const int W = g.nx + 1;
+  if constexpr (D == 2) {
+    k = 0;
+    j = n / W;
+    i = n - j * W;
+  } else {
+    const int P = W * (g.ny + 1);
+    k = n / P;
+    const int r = n - k * P;
+    j = r / W;
+    i = r - j * W;
+  }
+}
+template <int D>
+__host__ __device__ inline void cell_ijk(const Geom& g, int c, int& i, int& j, int& k) {
+  if constexpr (D == 2) {
+    k = 0;
+    j = c / g.nx;
+    i = c - j * g.nx;
+  } else {
+    const int P = g.nx * g.ny;
+    k = c / P;
+    const int r = c - k * P;
+    j = r / g.nx;
+    i = r - j * g.nx;
+  }
+}
+__host__ __device__ inline int node_at(const Geom& g, int i, int j, int k) {
+  return i + (g.nx + 1) * (j + (g.ny + 1) * k);
+}
+__host__ __device__ inline int cell_at(const Geom& g, int i, int j, int k) { return i + g.nx * (j + g.ny * k); }
 
-// Neighbour slot of offset (dx, dy) in the 3x3 block stencil.
-__host__ __device__ inline int slot_of(int dx, int dy) { return (dx + 1) + 3 * (dy + 1); }
+// Neighbour slot of offset (dx, dy, dz) in the 3x3(x3) block stencil, and of
+// the 5x5(x5) pressure stencil.
+template <int D>
+__host__ __device__ inline int slot_of(int dx, int dy, int dz) {
+  return (dx + 1) + 3 * (dy + 1) + (D == 3 ? 9 * (dz + 1) : 0);
+}
+template <int D>
+__host__ __device__ inline int pslot_of(int dx, int dy, int dz) {
+  return (dx + 2) + 5 * (dy + 2) + (D == 3 ? 25 * (dz + 2) : 0);
+}
 
 // Jacobian storage: per slice, nodes are grouped in tiles of 64; a tile holds its
-// 9 x 25 block-stencil coefficients as 225 runs of 64 consecutive values, so one
-// wave streams one contiguous 225 x 64 array.
+// NSLOT x BLK block-stencil coefficients as runs of 64 consecutive values, so
+// one wave streams one contiguous array.
 constexpr int JT = 64;
-constexpr int SPMV_THREADS = 5 * 64;   // row-variant SpMV block: five waves over 64 nodes
-constexpr int VC_CELLS = 16;           // cells per block of the fused Vanka pass
-constexpr int VC_THREADS = 5 * 64;     // its five waves (one per row of a patch node)
-constexpr int VF_PATCHES = 8;          // patches per block of the Vanka factor kernel (32 lanes each)
 __host__ __device__ inline int nn_pad(int nn) { return (nn + JT - 1) / JT * JT; }
-__host__ __device__ inline size_t jslice(int nn) { return (size_t)NSLOT * BLK * nn_pad(nn); }
-__host__ __device__ inline size_t jidx(int node, int s, int e) {
-  return (size_t)(node / JT) * (NSLOT * BLK * JT) + (size_t)(s * BLK + e) * JT + (node % JT);
+template <int D>
+__host__ __device__ inline size_t jslice(int nn) {
+  return (size_t)Dm<D>::NSLOT * Dm<D>::BLK * nn_pad(nn);
 }
-__host__ __device__ inline int pslot_of(int dx, int dy) { return (dx + 2) + 5 * (dy + 2); }
+template <int D>
+__host__ __device__ inline size_t jidx(int node, int s, int e) {
+  return (size_t)(node / JT) * (Dm<D>::NSLOT * Dm<D>::BLK * JT) + (size_t)(s * Dm<D>::BLK + e) * JT + (node % JT);
+}
+
+// Launch shapes: the SpMV and the fused Vanka pass run one wave per row of a
+// node (NC waves), the Vanka factor one lane group per patch row set.
+template <int D>
+__host__ __device__ constexpr int spmv_threads() { return Dm<D>::NC * 64; }
+template <int D>
+__host__ __device__ constexpr int vc_cells() { return 64 / Dm<D>::NL; }      // cells per fused-pass block
+template <int D>
+__host__ __device__ constexpr int vf_lanes() { return D == 2 ? 32 : 64; }    // lanes per patch (>= NE)
+template <int D>
+__host__ __device__ constexpr int vf_patches() { return D == 2 ? 8 : 1; }    // patches per factor block
 
 // ------------------------------------------------------------ colour helpers
-// Cells of colour c = (i mod 2) + 2 (j mod 2): ncx per row, nc in total, and
-// the offset of the colour's block in the per-colour Vanka inverse storage
-// (colours stored in order 0..3).  Computed without arrays, so a colour that
-// is only known at run time costs no private memory.
+// Cells of colour c = (i mod 2) + 2 (j mod 2) + 4 (k mod 2): ncx per row, ncy
+// rows per plane, nc in total, and the offset of the colour's block in the
+// per-colour Vanka inverse storage (colours stored in order).  Computed
+// without arrays, so a colour only known at run time costs no private memory.
 struct ColorInfo {
-  int ncx, nc, off;
+  int ncx, ncy, nc, off;
 };
-__host__ __device__ inline ColorInfo color_info(int nx, int ny, int c) {
+template <int D>
+__host__ __device__ inline ColorInfo color_info(const Geom& g, int c) {
   ColorInfo ci;
   ci.off = 0;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int nq = ((nx - (q & 1) + 1) / 2) * ((ny - (q >> 1) + 1) / 2);
+  for (int q = 0; q < Dm<D>::NCOL; ++q) {
+    const int nq = ((g.nx - (q & 1) + 1) / 2) * ((g.ny - ((q >> 1) & 1) + 1) / 2) *
+                   (D == 3 ? (g.nz - ((q >> 2) & 1) + 1) / 2 : 1);
     if (q < c) ci.off += nq;
   }
-  ci.ncx = (nx - (c & 1) + 1) / 2;
-  ci.nc = ci.ncx * ((ny - (c >> 1) + 1) / 2);
+  ci.ncx = (g.nx - (c & 1) + 1) / 2;
+  ci.ncy = (g.ny - ((c >> 1) & 1) + 1) / 2;
+  ci.nc = ci.ncx * ci.ncy * (D == 3 ? (g.nz - ((c >> 2) & 1) + 1) / 2 : 1);
   return ci;
 }
+// Colour and index within the colour of cell (i, j, k).
+template <int D>
+__host__ __device__ inline void cell_colour(const Geom& g, int i, int j, int k, int& col, int& idx, ColorInfo& L) {
+  col = (i & 1) + 2 * (j & 1) + (D == 3 ? 4 * (k & 1) : 0);
+  L = color_info<D>(g, col);
+  idx = (i >> 1) + L.ncx * ((j >> 1) + L.ncy * (k >> 1));
+}
 
-// A bar face shared with a fluid cell: fluid cell index, face axis (0: x, 1: y),
-// side of the face in the fluid cell (0: low, 1: high) and the sign of the solid's
-// outward normal n_s = sign e_axis.
+// A bar face shared with a fluid cell (2d): fluid cell index, face axis (0: x,
+// 1: y), side of the face in the fluid cell (0: low, 1: high) and the sign of
+// the solid's outward normal n_s = sign e_axis.
 struct DragFace {
   int cell, axis, side, sign;
 };
@@ -93,5 +186,12 @@ struct DragFace {
 __host__ __device__ inline double inflow_ramp(double t, double tr) {
   return t >= tr ? 1.0 : 0.5 * (1.0 - cos(M_PI * t / tr));
 }
+
+// Physical and step constants of one time step.
+struct StepPar {
+  double k, theta;
+  double rho_f, nu_f, rho_s, mu_s, lambda_s;
+  double peak, ramp_time;
+};
 
 }  // namespace fsi

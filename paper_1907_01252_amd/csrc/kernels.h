@@ -1,19 +1,27 @@
 // Declarations of the HIP kernels (defined and instantiated in assemble.hip and
-// solver.hip) for the host driver.
+// solver.hip) for the host driver.  D is the space dimension (2 or 3), S the
+// storage type of the linear solve.
 #pragma once
 #include "fsi_internal.h"
 
 namespace fsi {
 
+template <int D>
 __global__ void k_elem_residual(Geom g, StepPar sp, const double* U, const double* Uo, double* Re, const int* active);
-template <bool OLD>
+template <int D, bool OLD>
 __global__ void k_elem_jacobian(Geom g, StepPar sp, const double* U, const double* Uo, double* Ke, const int* active);
+template <int D>
 __global__ void k_apply_dirichlet(Geom g, StepPar sp, double* U, const double* t, const int* active);
+template <int D>
 __global__ void k_gather_residual(Geom g, StepPar sp, const double* Re, const double* U, const double* t, double* R,
                                   const int* active);
-template <class S>
+template <int D, class S>
 __global__ void k_gather_jacobian(Geom g, double k, const double* Ke, S* J, double* Dsc, const int* active,
                                   int dir_identity);
+template <int D>
+__global__ void k_inject(Geom gc, Geom gf, const double* Uf, double* Uc);
+
+// 2d adjoint
 __global__ void k_drag_values(Geom g, double rn, const DragFace* faces, int nf, const double* U, size_t stride,
                               int nstates, double* vals);
 __global__ void k_drag_gradient(Geom g, double rn, const DragFace* faces, int nf, const double* U, double scale,
@@ -27,20 +35,20 @@ __global__ void k_spmv_T(Geom g, double k, const S* J, const S* x, S* y, int wit
 __global__ void k_fix_dirichlet(Geom g, double* lam, const double* rhs, const double* y);
 __global__ void k_adjoint_rhs(Geom g, const double* rhs, double* Res);
 __global__ void k_daxpy(size_t n, double a, const double* x, double* y);
-__global__ void k_inject(Geom gc, Geom gf, const double* Uf, double* Uc, int B);
 
-template <class S>
+template <int D, class S>
 __global__ void k_spmv(Geom g, double k, const S* J, const S* x, const S* b, const double* Dsc, S* y,
                        const int* active);
-template <class S>
+template <int D, class S>
 __global__ void k_vanka_factor(Geom g, double k, const S* J, S* Ainv, const int* active);
-template <class S>
+template <int D, class S>
 __global__ void k_vanka_color(Geom g, double k, int color, S omega, int zero_in, const S* J, const S* Ainv,
                               const S* b, const S* xo, S* xn, const int* active);
-template <class S>
+template <int D, class S>
 __global__ void k_restrict(Geom gc, Geom gf, const S* rf, S* bc, const int* active);
-template <class S>
+template <int D, class S>
 __global__ void k_prolong_add(Geom gf, Geom gc, const S* xc, S* xf, const int* active);
+// 2d coarsest level
 template <class S>
 __global__ void k_coarse_factor(Geom g, double k, const S* J, int bsz, int nsb, double* Dinv, double* W, double* Lb,
                                 const int* active);
@@ -49,6 +57,7 @@ __global__ void k_coarse_inverse(Geom g, int bsz, int nsb, const double* Dinv, c
                                  double* Ysc, S* AinvS, const int* active);
 template <class S>
 __global__ void k_coarse_gemv(Geom g, const S* AinvS, const S* bvec, S* xvec, const int* active);
+
 template <class S>
 __global__ void k_multidot(int n, int nv, const S* X, size_t sxb, const S* Y, size_t syb, size_t syi, int chunk,
                            double* partial, int nchunk, const int* active);
@@ -72,13 +81,14 @@ __global__ void k_cgs_combine(int j, double* hcol, const double* hcol2, const do
 __global__ void k_update_gact(const int* nact, const int* state, int* gact, int B);
 __global__ void k_trisolve(int R, const double* H, const double* gv, const int* ncol, double* y, const int* active,
                            int B);
-template <class S>
+template <int D, class S>
 __global__ void k_newton_update(int nn, double* U, const S* dx, int chunk, double* part, int nchunk,
                                 const int* active);
 __global__ void k_max_partials(int nchunk, const double* part, double* out, int B);
 __global__ void k_nonfinite(size_t n, const double* X, int* flag);
 __global__ void k_extrapolate(size_t n, double* U, const double* Uo, const double* Up, const int* active);
 __global__ void k_parareal_update(size_t n, const double* Cn, const double* Fv, const double* Cold, double* out);
+template <int D>
 __global__ void k_change_norms(int nn, const double* A, const double* Bv, int chunk, double* part, int nchunk);
 template <class S>
 __global__ void k_fill(size_t n, S* X, S v);

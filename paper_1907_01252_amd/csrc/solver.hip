@@ -1,80 +1,88 @@
 // Batched linear-solver kernels: block-stencil SpMV, Vanka patch inverses and
 // colored multiplicative Vanka sweeps, multigrid transfers, the coarsest-level
-// block-tridiagonal direct solve and the FGMRES building blocks.  Every kernel
-// takes the slice index from blockIdx.y and skips slices whose active flag is 0.
-// S is the storage and arithmetic type of the linear solve (double, or float
-// in the mixed-precision path).
+// block-tridiagonal direct solve (2d) and the FGMRES building blocks.  Every
+// kernel takes the slice index from blockIdx.y and skips slices whose active
+// flag is 0.  S is the storage and arithmetic type of the linear solve
+// (double, or float in the mixed-precision path); D the space dimension.
 #include "fsi_internal.h"
 
 namespace fsi {
 
-// Neighbour offsets of the 3x3 block stencil of node (i, j), without branches:
-// an out-of-mesh neighbour maps onto the node itself.  The Jacobian stores
-// zeros in those slots (and the pressure stencil for such pairs), so the
-// product adds exactly nothing and every load of a row can be in flight at once.
-__device__ inline void slot_offsets(const Geom& g, int i, int j, int (&off)[NSLOT]) {
-  const int W = g.nx + 1;
-  const int xm = i > 0 ? -1 : 0, xp = i < g.nx ? 1 : 0;
-  const int ym = j > 0 ? -W : 0, yp = j < g.ny ? W : 0;
-  off[0] = ym + xm; off[1] = ym; off[2] = ym + xp;
-  off[3] = xm;      off[4] = 0;  off[5] = xp;
-  off[6] = yp + xm; off[7] = yp; off[8] = yp + xp;
+using D2 = Dm<2>;
+
+// Neighbour node offsets of the 3^D block stencil of node (i, j, k), without
+// branches: an out-of-mesh neighbour maps onto the node itself.  The Jacobian
+// stores zeros in those slots (and the pressure stencil for such pairs), so
+// the product adds exactly nothing and every load of a row can be in flight
+// at once.
+template <int D>
+__device__ inline void slot_offsets(const Geom& g, int i, int j, int k, int (&off)[Dm<D>::NSLOT]) {
+  const int W = g.nx + 1, P = W * (g.ny + 1);
+  const int o[3][3] = {{i > 0 ? -1 : 0, 0, i < g.nx ? 1 : 0},
+                       {j > 0 ? -W : 0, 0, j < g.ny ? W : 0},
+                       {k > 0 ? -P : 0, 0, k < g.nz ? P : 0}};
+#pragma unroll
+  for (int s = 0; s < Dm<D>::NSLOT; ++s) off[s] = o[0][s % 3] + o[1][(s / 3) % 3] + (D == 3 ? o[2][s / 9] : 0);
 }
 
-// k * sum_q pst[q][n] x_p(neighbour q) over the 5x5 pressure stencil (clamped
+// k * sum_q pst[q][n] x_p(neighbour q) over the 5^D pressure stencil (clamped
 // neighbours, zero coefficients outside the mesh and on Dirichlet pressure rows).
-template <class S>
-__device__ inline S pst_row(const Geom& g, double k, int n, int i, int j, const S* __restrict__ xb) {
-  const int W = g.nx + 1;
-  int cx[5], cy[5];
+template <int D, class S>
+__device__ inline S pst_row(const Geom& g, double k, int n, int i, int j, int kk, const S* __restrict__ xb) {
+  FSI_DIM(D);
+  int cx[5], cy[5], cz[5];
 #pragma unroll
   for (int d = 0; d < 5; ++d) {
     cx[d] = min(max(i + d - 2, 0), g.nx);
-    cy[d] = W * min(max(j + d - 2, 0), g.ny);
+    cy[d] = (g.nx + 1) * min(max(j + d - 2, 0), g.ny);
+    cz[d] = D == 3 ? (g.nx + 1) * (g.ny + 1) * min(max(kk + d - 2, 0), g.nz) : 0;
   }
   S ap = 0;
 #pragma unroll
-  for (int q = 0; q < NPST; ++q) ap += (S)g.pst[(size_t)q * g.nn + n] * xb[(size_t)(cx[q % 5] + cy[q / 5]) * NC + 4];
+  for (int q = 0; q < NPST; ++q)
+    ap += (S)g.pst[(size_t)q * g.nn + n] * xb[(size_t)(cx[q % 5] + cy[(q / 5) % 5] + cz[q / 25]) * NC + PC];
   return (S)k * ap;
 }
 
 // ------------------------------------------------------------------ SpMV
 // y = D (A x)            (b == nullptr)
 // y = D (b - A x)        (b != nullptr)
-// with A = J (3x3 block stencil of 5x5 blocks) + k * S_p (5x5 pressure stencil).
+// with A = J (3^D block stencil of NC x NC blocks) + k * S_p (pressure stencil).
 // D = Dsc (row scaling) when given, else identity.
-// One thread per (node, row): a block of five waves takes 64 consecutive
-// nodes, wave r forming row r, so the five rows of a node read its
-// neighbours' x through the same CU's cache, and a wave streams 64
-// consecutive values of each coefficient run of the tiled layout.
-template <class S>
-__global__ void __launch_bounds__(SPMV_THREADS) k_spmv(Geom g, double k, const S* __restrict__ J,
-                                                       const S* __restrict__ x, const S* __restrict__ b,
-                                                       const double* __restrict__ Dsc, S* __restrict__ y,
-                                                       const int* __restrict__ active) {
+// One thread per (node, row): a block of NC waves takes 64 consecutive nodes,
+// wave r forming row r, so the rows of a node read its neighbours' x through
+// the same CU's cache, and a wave streams 64 consecutive values of each
+// coefficient run of the tiled layout.
+template <int D, class S>
+__global__ void __launch_bounds__(Dm<D>::NC * 64) k_spmv(Geom g, double k, const S* __restrict__ J,
+                                                         const S* __restrict__ x, const S* __restrict__ b,
+                                                         const double* __restrict__ Dsc, S* __restrict__ y,
+                                                         const int* __restrict__ active) {
+  FSI_DIM(D);
   const int bs = blockIdx.y;
   const int r = threadIdx.x >> 6;
   const int n = blockIdx.x * 64 + (threadIdx.x & 63);
   if (n >= g.nn || (active && !active[bs])) return;
-  const int i = n % (g.nx + 1), j = n / (g.nx + 1);
-  const S* jb = J + (size_t)bs * jslice(g.nn);
+  int i, j, kk;
+  node_ijk<D>(g, n, i, j, kk);
+  const S* jb = J + (size_t)bs * jslice<D>(g.nn);
   const S* xb = x + (size_t)bs * g.nn * NC;
   int off[NSLOT];
-  slot_offsets(g, i, j, off);
+  slot_offsets<D>(g, i, j, kk, off);
   S acc = 0;
 #pragma unroll
   for (int s = 0; s < NSLOT; ++s) {
     const S* xv = xb + (size_t)(n + off[s]) * NC;
 #pragma unroll
-    for (int c = 0; c < NC; ++c) acc += jb[jidx(n, s, NC * r + c)] * xv[c];
+    for (int c = 0; c < NC; ++c) acc += jb[jidx<D>(n, s, NC * r + c)] * xv[c];
   }
-  if (r == 4) acc += pst_row<S>(g, k, n, i, j, xb);
+  if (r == PC) acc += pst_row<D, S>(g, k, n, i, j, kk, xb);
   const size_t o = ((size_t)bs * g.nn + n) * NC + r;
   S v = b ? b[o] - acc : acc;
   y[o] = Dsc ? (S)(Dsc[o] * (double)v) : v;
 }
 
-// ------------------------------------------------------------ transposes
+// ------------------------------------------------------------ transposes (2d adjoint)
 // Jt = J^T with the Dirichlet rows of Jt replaced by identity rows (the
 // transposed system of the free unknowns), and the row scaling of Jt.
 // (J^T)_{(i,r),(j,c)} = J_{(j,c),(i,r)}: node j = i + offset(s) stores it in the
@@ -85,27 +93,27 @@ __global__ void k_transpose_J(Geom g, double k, const S* __restrict__ J, S* __re
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= g.nn) return;
   const int i = n % (g.nx + 1), j = n / (g.nx + 1);
-  const S* jb = J + (size_t)bs * jslice(g.nn);
-  S* jt = Jt + (size_t)bs * jslice(g.nn);
+  const S* jb = J + (size_t)bs * jslice<2>(g.nn);
+  S* jt = Jt + (size_t)bs * jslice<2>(g.nn);
   const uint8_t m = g.dmask[n];
-  double rmax[NC] = {0, 0, 0, 0, 0};
-  for (int s = 0; s < NSLOT; ++s) {
+  double rmax[D2::NC] = {0, 0, 0, 0, 0};
+  for (int s = 0; s < D2::NSLOT; ++s) {
     const int dx = s % 3 - 1, dy = s / 3 - 1;
     const int ii = i + dx, jj = j + dy;
     const bool ok = ii >= 0 && jj >= 0 && ii <= g.nx && jj <= g.ny;
     const int nb = ok ? ii + (g.nx + 1) * jj : 0;
-    for (int r = 0; r < NC; ++r)
-      for (int c = 0; c < NC; ++c) {
-        double v = ok ? (double)jb[jidx(nb, slot_of(-dx, -dy), NC * c + r)] : 0.0;
+    for (int r = 0; r < D2::NC; ++r)
+      for (int c = 0; c < D2::NC; ++c) {
+        double v = ok ? (double)jb[jidx<2>(nb, slot_of<2>(-dx, -dy, 0), D2::NC * c + r)] : 0.0;
         if (m & (1u << r)) v = (s == 4 && c == r) ? 1.0 : 0.0;
-        jt[jidx(n, s, NC * r + c)] = (S)v;
+        jt[jidx<2>(n, s, D2::NC * r + c)] = (S)v;
         rmax[r] = fmax(rmax[r], fabs(v));
       }
   }
-  if (!(m & DM_P))
-    for (int q = 0; q < NPST; ++q) rmax[4] = fmax(rmax[4], fabs(k * g.pst[(size_t)q * g.nn + n]));
+  if (!(m & dm_p<2>()))
+    for (int q = 0; q < D2::NPST; ++q) rmax[4] = fmax(rmax[4], fabs(k * g.pst[(size_t)q * g.nn + n]));
   if (Dsc)
-    for (int r = 0; r < NC; ++r) Dsc[((size_t)bs * g.nn + n) * NC + r] = rmax[r] > 0.0 ? 1.0 / rmax[r] : 1.0;
+    for (int r = 0; r < D2::NC; ++r) Dsc[((size_t)bs * g.nn + n) * D2::NC + r] = rmax[r] > 0.0 ? 1.0 / rmax[r] : 1.0;
 }
 
 // y = J^T x for the stored block stencil (no Dirichlet modification) plus, when
@@ -117,31 +125,31 @@ __global__ void k_spmv_T(Geom g, double k, const S* __restrict__ J, const S* __r
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= g.nn) return;
   const int i = n % (g.nx + 1), j = n / (g.nx + 1);
-  const S* jb = J + (size_t)bs * jslice(g.nn);
-  const S* xb = x + (size_t)bs * g.nn * NC;
-  S acc[NC] = {0, 0, 0, 0, 0};
-  for (int s = 0; s < NSLOT; ++s) {
+  const S* jb = J + (size_t)bs * jslice<2>(g.nn);
+  const S* xb = x + (size_t)bs * g.nn * D2::NC;
+  S acc[D2::NC] = {0, 0, 0, 0, 0};
+  for (int s = 0; s < D2::NSLOT; ++s) {
     // row node m = n - offset(s) holds the entry in slot s
     const int dx = s % 3 - 1, dy = s / 3 - 1;
     const int ii = i - dx, jj = j - dy;
     if (ii < 0 || jj < 0 || ii > g.nx || jj > g.ny) continue;
     const int mr = ii + (g.nx + 1) * jj;
-    for (int r = 0; r < NC; ++r) {
-      const S xr = xb[(size_t)mr * NC + r];
-      for (int c = 0; c < NC; ++c) acc[c] += jb[jidx(mr, s, NC * r + c)] * xr;
+    for (int r = 0; r < D2::NC; ++r) {
+      const S xr = xb[(size_t)mr * D2::NC + r];
+      for (int c = 0; c < D2::NC; ++c) acc[c] += jb[jidx<2>(mr, s, D2::NC * r + c)] * xr;
     }
   }
-  if (with_pst && !(g.dmask[n] & DM_P)) {
+  if (with_pst && !(g.dmask[n] & dm_p<2>())) {
     S ap = 0;
-    for (int q = 0; q < NPST; ++q) {
+    for (int q = 0; q < D2::NPST; ++q) {
       const int dx = q % 5 - 2, dy = q / 5 - 2;
       const int ii = i + dx, jj = j + dy;
       if (ii < 0 || jj < 0 || ii > g.nx || jj > g.ny) continue;
-      ap += (S)g.pst[(size_t)q * g.nn + n] * xb[(size_t)(ii + (g.nx + 1) * jj) * NC + 4];
+      ap += (S)g.pst[(size_t)q * g.nn + n] * xb[(size_t)(ii + (g.nx + 1) * jj) * D2::NC + 4];
     }
     acc[4] += (S)k * ap;
   }
-  for (int c = 0; c < NC; ++c) y[((size_t)bs * g.nn + n) * NC + c] = acc[c];
+  for (int c = 0; c < D2::NC; ++c) y[((size_t)bs * g.nn + n) * D2::NC + c] = acc[c];
 }
 
 // Dirichlet unknowns of the adjoint: lam_D = rhs_D - (J^T lam)_D with lam_D = 0 in y.
@@ -150,8 +158,8 @@ __global__ void k_fix_dirichlet(Geom g, double* __restrict__ lam, const double* 
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= g.nn) return;
   const uint8_t m = g.dmask[n];
-  for (int c = 0; c < NC; ++c)
-    if (m & (1u << c)) lam[(size_t)n * NC + c] = rhs[(size_t)n * NC + c] - y[(size_t)n * NC + c];
+  for (int c = 0; c < D2::NC; ++c)
+    if (m & (1u << c)) lam[(size_t)n * D2::NC + c] = rhs[(size_t)n * D2::NC + c] - y[(size_t)n * D2::NC + c];
 }
 
 // y += a x (FP64)
@@ -165,40 +173,45 @@ __global__ void k_adjoint_rhs(Geom g, const double* __restrict__ rhs, double* __
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= g.nn) return;
   const uint8_t m = g.dmask[n];
-  for (int c = 0; c < NC; ++c) Res[(size_t)n * NC + c] = (m & (1u << c)) ? 0.0 : -rhs[(size_t)n * NC + c];
+  for (int c = 0; c < D2::NC; ++c) Res[(size_t)n * D2::NC + c] = (m & (1u << c)) ? 0.0 : -rhs[(size_t)n * D2::NC + c];
 }
 
 // ------------------------------------------------------- Vanka patch inverse
-// One 32-lane group inverts the 20x20 patch matrix of one cell (rows = local
-// unknowns 5a + c) by Gauss-Jordan with partial pivoting.  [A | I] lives in
-// LDS, lane r owning row r; per column the pivot row is found by a shuffle
-// reduction and every other row eliminates the column with the (unscaled)
-// pivot row.  Rows are scaled by their pivots at the end, which gives the
-// same inverse as scaling at each step.  Ainv is stored per colour:
-// Ainv[b][off_c*400 + e*nc_c + idx], e = 20 * row + column.
-constexpr int VF_LD = 2 * NE + 1;      // padded LDS row of [A | I]
-template <class S>
-__global__ void __launch_bounds__(VF_PATCHES * 32) k_vanka_factor(Geom g, double k, const S* __restrict__ J,
-                                                      S* __restrict__ Ainv, const int* __restrict__ active) {
-  __shared__ double M[VF_PATCHES][NE][VF_LD];
+// One lane group (vf_lanes lanes) inverts the NE x NE patch matrix of one cell
+// (rows = local unknowns NC a + c) by Gauss-Jordan with partial pivoting.
+// [A | I] lives in LDS, lane r owning row r; per column the pivot row is
+// found by a shuffle reduction and every other row eliminates the column with
+// the (unscaled) pivot row.  Rows are scaled by their pivots at the end, which
+// gives the same inverse as scaling at each step.  Ainv is stored per colour:
+// Ainv[b][off_c*NE*NE + e*nc_c + idx], e = NE * row + column.
+template <int D, class S>
+__global__ void __launch_bounds__(vf_lanes<D>() * vf_patches<D>()) k_vanka_factor(Geom g, double k,
+                                                                                  const S* __restrict__ J,
+                                                                                  S* __restrict__ Ainv,
+                                                                                  const int* __restrict__ active) {
+  FSI_DIM(D);
+  constexpr int GL = vf_lanes<D>(), NP = vf_patches<D>(), LD = 2 * NE + 1;
+  __shared__ double M[NP][NE][LD];
   const int bs = blockIdx.y;
   if (active && !active[bs]) return;   // uniform over the block
-  const int grp = threadIdx.x >> 5, lane = threadIdx.x & 31;
-  const int cell = blockIdx.x * VF_PATCHES + grp;
+  const int grp = threadIdx.x / GL, lane = threadIdx.x % GL;
+  const int cell = blockIdx.x * NP + grp;
   const bool live = cell < g.ncell;
-  const int ci = live ? cell % g.nx : 0, cj = live ? cell / g.nx : 0;
-  double(*Mp)[VF_LD] = M[grp];
+  int ci = 0, cj = 0, ck = 0;
+  if (live) cell_ijk<D>(g, cell, ci, cj, ck);
+  double(*Mp)[LD] = M[grp];
   if (lane < NE) {
     const int a = lane / NC, rc = lane % NC;
-    const int na = (ci + (a & 1)) + (g.nx + 1) * (cj + (a >> 1));
+    const int ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
+    const int na = node_at(g, ci + ax, cj + ay, ck + az);
     if (live) {
-      const S* jb = J + (size_t)bs * jslice(g.nn);
-      const bool pst_row = (rc == 4) && !(g.dmask[na] & DM_P);
+      const S* jb = J + (size_t)bs * jslice<D>(g.nn);
+      const bool pst_row = (rc == PC) && !(g.dmask[na] & dm_p<D>());
       for (int bb = 0; bb < NL; ++bb) {
-        const int dx = (bb & 1) - (a & 1), dy = (bb >> 1) - (a >> 1);
-        const int s = slot_of(dx, dy);
-        for (int c = 0; c < NC; ++c) Mp[lane][NC * bb + c] = (double)jb[jidx(na, s, NC * rc + c)];
-        if (pst_row) Mp[lane][NC * bb + 4] += k * g.pst[(size_t)pslot_of(dx, dy) * g.nn + na];
+        const int dx = (bb & 1) - ax, dy = ((bb >> 1) & 1) - ay, dz = ((bb >> 2) & 1) - az;
+        const int s = slot_of<D>(dx, dy, dz);
+        for (int c = 0; c < NC; ++c) Mp[lane][NC * bb + c] = (double)jb[jidx<D>(na, s, NC * rc + c)];
+        if (pst_row) Mp[lane][NC * bb + PC] += k * g.pst[(size_t)pslot_of<D>(dx, dy, dz) * g.nn + na];
       }
     } else {
       for (int c = 0; c < NE; ++c) Mp[lane][c] = (c == lane) ? 1.0 : 0.0;
@@ -213,9 +226,9 @@ __global__ void __launch_bounds__(VF_PATCHES * 32) k_vanka_factor(Geom g, double
     double cand = used ? -1.0 : fabs(v);
     int idx = lane;
 #pragma unroll
-    for (int off = 16; off > 0; off >>= 1) {
-      const double oc = __shfl_xor(cand, off, 32);
-      const int oi = __shfl_xor(idx, off, 32);
+    for (int off = GL / 2; off > 0; off >>= 1) {
+      const double oc = __shfl_xor(cand, off, GL);
+      const int oi = __shfl_xor(idx, off, GL);
       if (oc > cand || (oc == cand && oi < idx)) { cand = oc; idx = oi; }
     }
     double pv = Mp[idx][jc];
@@ -227,75 +240,82 @@ __global__ void __launch_bounds__(VF_PATCHES * 32) k_vanka_factor(Geom g, double
     __syncthreads();
   }
   if (live && lane < NE) {
-    const ColorInfo L = color_info(g.nx, g.ny, (ci & 1) + 2 * (cj & 1));
-    const int nc = L.nc;
-    const int idx = (ci >> 1) + L.ncx * (cj >> 1);
+    int col, idx;
+    ColorInfo L;
+    cell_colour<D>(g, ci, cj, ck, col, idx, L);
     const double d = Mp[lane][mycol] != 0.0 ? 1.0 / Mp[lane][mycol] : 1.0;
     S* out = Ainv + (size_t)bs * NE * NE * g.ncell + (size_t)L.off * NE * NE;
-    for (int c = 0; c < NE; ++c) out[(size_t)(NE * mycol + c) * nc + idx] = (S)(Mp[lane][NE + c] * d);
+    for (int c = 0; c < NE; ++c) out[(size_t)(NE * mycol + c) * L.nc + idx] = (S)(Mp[lane][NE + c] * d);
   }
 }
 
 // ------------------------------------------------------ colored Vanka pass
 // One multiplicative pass over the cells of one colour, residual and patch
 // update fused: every cell P of the colour forms r_P = b_P - (A x_old)_P on its
-// four nodes and writes x_new[P] = x_old[P] + omega Ainv_P r_P.  The cells of
-// one colour do not share nodes, so each node is written by at most one patch;
+// nodes and writes x_new[P] = x_old[P] + omega Ainv_P r_P.  The cells of one
+// colour do not share nodes, so each node is written by at most one patch;
 // the nodes no patch of the colour covers are copied.  x_old and x_new are
 // different buffers (other patches read x_old at the shared neighbours).
 // zero_in: x_old is taken as zero (first pass of a cycle): r_P = b_P and the
 // uncovered nodes get zero.
-// Thread mapping: a block of VC_CELLS consecutive cells of the colour has five
-// waves, wave r forming row r of every patch node; lanes 0-31 take the lower
-// node pair of the 16 cells, lanes 32-63 the upper pair, so within one cell
-// row a wave reads two runs of 32 consecutive nodes.  The 20 patch residuals
-// meet in LDS; the same thread then forms patch row 5a + r of Ainv_P r_P.
-// Extra blocks past the patch blocks copy the uncovered nodes.
-template <class S>
-__global__ void __launch_bounds__(VC_THREADS) k_vanka_color(Geom g, double k, int color, S omega, int zero_in,
-                                                            const S* __restrict__ J, const S* __restrict__ Ainv,
-                                                            const S* __restrict__ b, const S* __restrict__ xo,
-                                                            S* __restrict__ xn, const int* __restrict__ active) {
-  __shared__ S rs[NE][VC_CELLS];
+// Thread mapping: a block of vc_cells consecutive cells of the colour has NC
+// waves, wave r forming row r of every patch node.  In a wave, lane group
+// g = lane / (2 vc_cells) takes the local node pair (2g, 2g+1) of the block's
+// cells, so within one cell row a wave reads runs of 2 vc_cells consecutive
+// nodes.  The NE patch residuals meet in LDS; the same thread then forms patch
+// row NC a + r of Ainv_P r_P.  Extra blocks past the patch blocks copy the
+// uncovered nodes.
+template <int D, class S>
+__global__ void __launch_bounds__(Dm<D>::NC * 64) k_vanka_color(Geom g, double k, int color, S omega, int zero_in,
+                                                                const S* __restrict__ J, const S* __restrict__ Ainv,
+                                                                const S* __restrict__ b, const S* __restrict__ xo,
+                                                                S* __restrict__ xn, const int* __restrict__ active) {
+  FSI_DIM(D);
+  constexpr int VC = vc_cells<D>();
+  __shared__ S rs[NE][VC];
   const int bs = blockIdx.y;
   if (active && !active[bs]) return;   // uniform over the block
-  const ColorInfo L = color_info(g.nx, g.ny, color);
+  const ColorInfo L = color_info<D>(g, color);
   const int nc = L.nc;
-  const int npb = (nc + VC_CELLS - 1) / VC_CELLS;
+  const int npb = (nc + VC - 1) / VC;
   const S* xob = xo + (size_t)bs * g.nn * NC;
   S* xnb = xn + (size_t)bs * g.nn * NC;
+  const int cx = color & 1, cy = (color >> 1) & 1, cz = (color >> 2) & 1;
   if ((int)blockIdx.x >= npb) {
-    const int t = ((int)blockIdx.x - npb) * VC_THREADS + threadIdx.x;
+    const int t = ((int)blockIdx.x - npb) * (NC * 64) + threadIdx.x;
     if (t >= g.nn) return;
-    const int ni = t % (g.nx + 1), nj = t / (g.nx + 1);
-    const int cx = color & 1, cy = color >> 1;
-    const int ci = ni - ((ni - cx) & 1), cj = nj - ((nj - cy) & 1);
-    if (ci < 0 || cj < 0 || ci >= g.nx || cj >= g.ny)
+    int ni, nj, nk;
+    node_ijk<D>(g, t, ni, nj, nk);
+    const int ci = ni - ((ni - cx) & 1), cj = nj - ((nj - cy) & 1), ck = nk - ((nk - cz) & 1);
+    const bool covered = ci >= 0 && cj >= 0 && ci < g.nx && cj < g.ny && (D == 2 || (ck >= 0 && ck < g.nz));
+    if (!covered)
       for (int c = 0; c < NC; ++c) xnb[(size_t)t * NC + c] = zero_in ? (S)0 : xob[(size_t)t * NC + c];
     return;
   }
   const int r = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int a = ((lane >> 5) << 1) | (lane & 1);
-  const int jc = (lane & 31) >> 1;
-  const int idx = blockIdx.x * VC_CELLS + jc;
+  const int a = ((lane / (2 * VC)) << 1) | (lane & 1);
+  const int jc = (lane % (2 * VC)) >> 1;
+  const int idx = blockIdx.x * VC + jc;
   const bool live = idx < nc;
   int n = 0;
   if (live) {
-    const int ci = 2 * (idx % L.ncx) + (color & 1), cj = 2 * (idx / L.ncx) + (color >> 1);
-    n = ci + (a & 1) + (g.nx + 1) * (cj + (a >> 1));
+    const int ix = idx % L.ncx, rest = idx / L.ncx;
+    const int ci = 2 * ix + cx, cj = 2 * (rest % L.ncy) + cy, ck = D == 3 ? 2 * (rest / L.ncy) + cz : 0;
+    n = node_at(g, ci + (a & 1), cj + ((a >> 1) & 1), ck + ((a >> 2) & 1));
     S acc = 0;
     if (!zero_in) {
-      const int i = n % (g.nx + 1), j = n / (g.nx + 1);
-      const S* jb = J + (size_t)bs * jslice(g.nn);
+      int i, j, kk;
+      node_ijk<D>(g, n, i, j, kk);
+      const S* jb = J + (size_t)bs * jslice<D>(g.nn);
       int off[NSLOT];
-      slot_offsets(g, i, j, off);
+      slot_offsets<D>(g, i, j, kk, off);
 #pragma unroll
       for (int s = 0; s < NSLOT; ++s) {
         const S* xv = xob + (size_t)(n + off[s]) * NC;
 #pragma unroll
-        for (int c = 0; c < NC; ++c) acc += jb[jidx(n, s, NC * r + c)] * xv[c];
+        for (int c = 0; c < NC; ++c) acc += jb[jidx<D>(n, s, NC * r + c)] * xv[c];
       }
-      if (r == 4) acc += pst_row<S>(g, k, n, i, j, xob);
+      if (r == PC) acc += pst_row<D, S>(g, k, n, i, j, kk, xob);
     }
     rs[NC * a + r][jc] = b[((size_t)bs * g.nn + n) * NC + r] - acc;
   }
@@ -311,61 +331,73 @@ __global__ void __launch_bounds__(VC_THREADS) k_vanka_color(Geom g, double k, in
 }
 
 // --------------------------------------------------------- grid transfers
-// b_c = P^T r_f (bilinear weights), zero on coarse Dirichlet components and
-// ignoring fine Dirichlet components (P has zero rows there).
-template <class S>
+// b_c = P^T r_f ((bi/tri)linear weights), zero on coarse Dirichlet components
+// and ignoring fine Dirichlet components (P has zero rows there).
+template <int D, class S>
 __global__ void k_restrict(Geom gc, Geom gf, const S* __restrict__ rf, S* __restrict__ bc,
                            const int* __restrict__ active) {
+  FSI_DIM(D);
   const int bs = blockIdx.y;
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= gc.nn || (active && !active[bs])) return;
-  const int I = n % (gc.nx + 1), Jc = n / (gc.nx + 1);
+  int I, Jc, K;
+  node_ijk<D>(gc, n, I, Jc, K);
   const uint8_t mc = gc.dmask[n];
-  S acc[NC] = {0, 0, 0, 0, 0};
-  for (int dy = -1; dy <= 1; ++dy)
-    for (int dx = -1; dx <= 1; ++dx) {
-      const int fi = 2 * I + dx, fj = 2 * Jc + dy;
-      if (fi < 0 || fj < 0 || fi > gf.nx || fj > gf.ny) continue;
-      const S w = (S)((dx ? 0.5 : 1.0) * (dy ? 0.5 : 1.0));
-      const int nf = fi + (gf.nx + 1) * fj;
-      const uint8_t mf = gf.dmask[nf];
-      const S* rv = rf + ((size_t)bs * gf.nn + nf) * NC;
-      for (int c = 0; c < NC; ++c)
-        if (!(mf & (1u << c))) acc[c] += w * rv[c];
-    }
+  S acc[NC];
+  for (int c = 0; c < NC; ++c) acc[c] = 0;
+  for (int s = 0; s < NSLOT; ++s) {
+    const int dx = s % 3 - 1, dy = (s / 3) % 3 - 1, dz = D == 3 ? s / 9 - 1 : 0;
+    const int fi = 2 * I + dx, fj = 2 * Jc + dy, fk = 2 * K + dz;
+    if (fi < 0 || fj < 0 || fk < 0 || fi > gf.nx || fj > gf.ny || fk > gf.nz) continue;
+    const S w = (S)((dx ? 0.5 : 1.0) * (dy ? 0.5 : 1.0) * (dz ? 0.5 : 1.0));
+    const int nf = node_at(gf, fi, fj, fk);
+    const uint8_t mf = gf.dmask[nf];
+    const S* rv = rf + ((size_t)bs * gf.nn + nf) * NC;
+    for (int c = 0; c < NC; ++c)
+      if (!(mf & (1u << c))) acc[c] += w * rv[c];
+  }
   S* o = bc + ((size_t)bs * gc.nn + n) * NC;
   for (int c = 0; c < NC; ++c) o[c] = (mc & (1u << c)) ? (S)0 : acc[c];
 }
 
 // x_f += P x_c on non-Dirichlet fine components (coarse Dirichlet values are zero).
-template <class S>
+template <int D, class S>
 __global__ void k_prolong_add(Geom gf, Geom gc, const S* __restrict__ xc, S* __restrict__ xf,
                               const int* __restrict__ active) {
+  FSI_DIM(D);
   const int bs = blockIdx.y;
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= gf.nn || (active && !active[bs])) return;
-  const int fi = n % (gf.nx + 1), fj = n / (gf.nx + 1);
-  const int i0 = fi >> 1, j0 = fj >> 1;
-  const int i1 = (fi & 1) ? i0 + 1 : i0, j1 = (fj & 1) ? j0 + 1 : j0;
-  const S wx = (fi & 1) ? (S)0.5 : (S)1.0, wy = (fj & 1) ? (S)0.5 : (S)1.0;
+  int fi, fj, fk;
+  node_ijk<D>(gf, n, fi, fj, fk);
+  const int lo[3] = {fi >> 1, fj >> 1, fk >> 1};
+  const int odd[3] = {fi & 1, fj & 1, fk & 1};
   const uint8_t mf = gf.dmask[n];
-  S add[NC] = {0, 0, 0, 0, 0};
-  const int ci[2] = {i0, i1}, cj[2] = {j0, j1};
-  for (int q = 0; q < 4; ++q) {
-    const int ii = ci[q & 1], jj = cj[q >> 1];
-    if (((q & 1) && i1 == i0) || ((q >> 1) && j1 == j0)) continue;
-    const int nc = ii + (gc.nx + 1) * jj;
+  S add[NC];
+  for (int c = 0; c < NC; ++c) add[c] = 0;
+  for (int q = 0; q < NL; ++q) {
+    bool skip = false;
+    double w = 1.0;
+    int cc[3] = {lo[0], lo[1], lo[2]};
+    for (int ax = 0; ax < D; ++ax) {
+      const int bit = (q >> ax) & 1;
+      if (bit && !odd[ax]) skip = true;   // even fine index: one coarse node on this axis
+      if (odd[ax]) w *= 0.5;
+      cc[ax] += bit;
+    }
+    if (skip) continue;
+    const int nc = node_at(gc, cc[0], cc[1], D == 3 ? cc[2] : 0);
     const uint8_t mc = gc.dmask[nc];
     const S* xv = xc + ((size_t)bs * gc.nn + nc) * NC;
     for (int c = 0; c < NC; ++c)
-      if (!(mc & (1u << c))) add[c] += wx * wy * xv[c];
+      if (!(mc & (1u << c))) add[c] += (S)w * xv[c];
   }
   S* xo = xf + ((size_t)bs * gf.nn + n) * NC;
   for (int c = 0; c < NC; ++c)
     if (!(mf & (1u << c))) xo[c] += add[c];
 }
 
-// ------------------------------------------- coarsest level: direct solve
+// ------------------------------------------- coarsest level: direct solve (2d)
 // Unknowns ordered by super-columns of two x-node columns (bs = 2 (ny+1) 5);
 // the 3x3 block stencil plus the 5x5 pressure stencil make the matrix block
 // tridiagonal.  Factor: Delta_0 = D_0, Delta_K = D_K - L_K W_{K-1},
@@ -375,25 +407,25 @@ __global__ void k_prolong_add(Geom gf, Geom gc, const S* __restrict__ xc, S* __r
 template <class S>
 __device__ inline double coarse_entry(const Geom& g, double k, const S* jb, int K, int l, int K2, int l2) {
   // row: super-column K local l; column: super-column K2 local l2
-  const int r = l % NC, nl = l / NC, colx = nl / (g.ny + 1), jr = nl % (g.ny + 1);
-  const int c = l2 % NC, nl2 = l2 / NC, colx2 = nl2 / (g.ny + 1), jc = nl2 % (g.ny + 1);
+  const int r = l % D2::NC, nl = l / D2::NC, colx = nl / (g.ny + 1), jr = nl % (g.ny + 1);
+  const int c = l2 % D2::NC, nl2 = l2 / D2::NC, colx2 = nl2 / (g.ny + 1), jc = nl2 % (g.ny + 1);
   const int ir = 2 * K + colx, ic = 2 * K2 + colx2;
   if (ir > g.nx || ic > g.nx) return (K == K2 && l == l2) ? 1.0 : 0.0;   // padding: identity
   const int dx = ic - ir, dy = jc - jr;
   const int n = ir + (g.nx + 1) * jr;
   double v = 0.0;
-  if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1) v = (double)jb[jidx(n, slot_of(dx, dy), NC * r + c)];
-  if (r == 4 && c == 4 && dx >= -2 && dx <= 2 && dy >= -2 && dy <= 2 && !(g.dmask[n] & DM_P))
-    v += k * g.pst[(size_t)pslot_of(dx, dy) * g.nn + n];
+  if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1) v = (double)jb[jidx<2>(n, slot_of<2>(dx, dy, 0), D2::NC * r + c)];
+  if (r == 4 && c == 4 && dx >= -2 && dx <= 2 && dy >= -2 && dy <= 2 && !(g.dmask[n] & dm_p<2>()))
+    v += k * g.pst[(size_t)pslot_of<2>(dx, dy, 0) * g.nn + n];
   return v;
 }
 
 // global dof index of local unknown l of super-column K, or -1 for padding
 __device__ inline int coarse_gidx(const Geom& g, int K, int l) {
-  const int c = l % NC, nl = l / NC, colx = nl / (g.ny + 1), jn = nl % (g.ny + 1);
+  const int c = l % D2::NC, nl = l / D2::NC, colx = nl / (g.ny + 1), jn = nl % (g.ny + 1);
   const int i = 2 * K + colx;
   if (i > g.nx) return -1;
-  return (i + (g.nx + 1) * jn) * NC + c;
+  return (i + (g.nx + 1) * jn) * D2::NC + c;
 }
 
 // C = alpha A B for bs x bs row-major tiles in LDS (all threads of the block)
@@ -417,7 +449,7 @@ __global__ void __launch_bounds__(256) k_coarse_factor(Geom g, double k, const S
   const int bs = blockIdx.x;
   if (active && !active[bs]) return;
   const int tid = threadIdx.x, nt = blockDim.x;
-  const S* jb = J + (size_t)bs * jslice(g.nn);
+  const S* jb = J + (size_t)bs * jslice<2>(g.nn);
   const int w2 = 2 * bsz;
   const int B2i = bsz * bsz;
   double* M = lds;                  // bsz x 2bsz
@@ -518,7 +550,7 @@ __global__ void __launch_bounds__(256) k_coarse_inverse(Geom g, int bsz, int nsb
   const double* w = W + (size_t)bs * nsb * B2;
   const double* lb = Lb + (size_t)bs * nsb * B2;
   double* ys = Ysc + ((size_t)bs * nsb + Kc) * nsb * B2;
-  const int n0 = g.nn * NC;
+  const int n0 = g.nn * D2::NC;
   S* out = AinvS + (size_t)bs * n0 * n0;
   for (int e = tid; e < B2i; e += nt) { Y[e] = dinv[Kc * B2 + e]; ys[Kc * B2 + e] = Y[e]; }
   __syncthreads();
@@ -560,7 +592,7 @@ __global__ void __launch_bounds__(256) k_coarse_gemv(Geom g, const S* __restrict
                                                      S* __restrict__ xvec, const int* __restrict__ active) {
   const int bs = blockIdx.y;
   if (active && !active[bs]) return;
-  const int n0 = g.nn * NC;
+  const int n0 = g.nn * D2::NC;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int i = blockIdx.x * 64 + lane;
   __shared__ S part[4][64];
@@ -783,10 +815,11 @@ __global__ void k_trisolve(int R, const double* __restrict__ H, const double* __
 // ------------------------------------------------------------ Newton update
 // U[b] += dx[b] (on active slices), then per-slice maxima of |dx| and |U| per
 // field (v, u, p) into part[b][6][chunk].
-template <class S>
+template <int D, class S>
 __global__ void __launch_bounds__(RED_T) k_newton_update(int nn, double* __restrict__ U, const S* __restrict__ dx,
                                                          int chunk, double* __restrict__ part, int nchunk,
                                                          const int* __restrict__ active) {
+  FSI_DIM(D);
   __shared__ double sh[RED_T];
   const int b = blockIdx.y, ch = blockIdx.x;
   if (active && !active[b]) return;
@@ -799,7 +832,7 @@ __global__ void __launch_bounds__(RED_T) k_newton_update(int nn, double* __restr
       const double dv = (double)d[c];
       const double un = u[c] + dv;
       u[c] = un;
-      const int f = c < 2 ? 0 : (c < 4 ? 1 : 2);
+      const int f = c < D ? 0 : (c < 2 * D ? 1 : 2);
       m[f] = fmax(m[f], fabs(dv));
       m[3 + f] = fmax(m[3 + f], fabs(un));
       if (!isfinite(un)) m[f] = INFINITY;
@@ -838,9 +871,11 @@ __global__ void k_parareal_update(size_t n, const double* __restrict__ Cn, const
 
 // Per boundary b: sums of squares of (A - B) and of A for the velocity and the
 // displacement components -> part[b][4][chunk].
+template <int D>
 __global__ void __launch_bounds__(RED_T) k_change_norms(int nn, const double* __restrict__ A,
                                                         const double* __restrict__ Bv, int chunk,
                                                         double* __restrict__ part, int nchunk) {
+  FSI_DIM(D);
   __shared__ double sh[RED_T];
   const int b = blockIdx.y, ch = blockIdx.x;
   const int lo = ch * chunk, hi = min(nn, lo + chunk);
@@ -848,10 +883,11 @@ __global__ void __launch_bounds__(RED_T) k_change_norms(int nn, const double* __
   for (int n = lo + threadIdx.x; n < hi; n += blockDim.x) {
     const double* a = A + ((size_t)b * nn + n) * NC;
     const double* o = Bv + ((size_t)b * nn + n) * NC;
-    for (int c = 0; c < 4; ++c) {
+    for (int c = 0; c < 2 * D; ++c) {
       const double d = a[c] - o[c];
-      s[(c >> 1) * 2] += d * d;
-      s[(c >> 1) * 2 + 1] += a[c] * a[c];
+      const int f = c < D ? 0 : 1;
+      s[2 * f] += d * d;
+      s[2 * f + 1] += a[c] * a[c];
     }
   }
   for (int q = 0; q < 4; ++q) {
@@ -888,13 +924,18 @@ __global__ void k_convert(size_t n, const A* __restrict__ X, B2* __restrict__ Y)
 }
 
 // explicit instantiations
-#define INST(S)                                                                                                   \
-  template __global__ void k_spmv<S>(Geom, double, const S*, const S*, const S*, const double*, S*, const int*); \
-  template __global__ void k_vanka_factor<S>(Geom, double, const S*, S*, const int*);                            \
-  template __global__ void k_vanka_color<S>(Geom, double, int, S, int, const S*, const S*, const S*, const S*,   \
-                                            S*, const int*);                                                     \
-  template __global__ void k_restrict<S>(Geom, Geom, const S*, S*, const int*);                                  \
-  template __global__ void k_prolong_add<S>(Geom, Geom, const S*, S*, const int*);                               \
+#define FSI_INST_DS(D, S)                                                                                         \
+  template __global__ void k_spmv<D, S>(Geom, double, const S*, const S*, const S*, const double*, S*,           \
+                                        const int*);                                                             \
+  template __global__ void k_vanka_factor<D, S>(Geom, double, const S*, S*, const int*);                         \
+  template __global__ void k_vanka_color<D, S>(Geom, double, int, S, int, const S*, const S*, const S*,          \
+                                               const S*, S*, const int*);                                        \
+  template __global__ void k_restrict<D, S>(Geom, Geom, const S*, S*, const int*);                               \
+  template __global__ void k_prolong_add<D, S>(Geom, Geom, const S*, S*, const int*);                            \
+  template __global__ void k_newton_update<D, S>(int, double*, const S*, int, double*, int, const int*);
+#define FSI_INST_S(S)                                                                                             \
+  FSI_INST_DS(2, S)                                                                                               \
+  FSI_INST_DS(3, S)                                                                                               \
   template __global__ void k_coarse_factor<S>(Geom, double, const S*, int, int, double*, double*, double*,       \
                                               const int*);                                                       \
   template __global__ void k_coarse_inverse<S>(Geom, int, int, const double*, const double*, const double*,      \
@@ -907,13 +948,16 @@ __global__ void k_convert(size_t n, const A* __restrict__ X, B2* __restrict__ Y)
   template __global__ void k_scale<S>(int, const S*, size_t, S*, size_t, const double*, int, int, const int*);   \
   template __global__ void k_unscale<S>(int, const S*, size_t, const double*, S*, const int*);                   \
   template __global__ void k_scale_rhs<S>(int, const double*, const double*, S*, size_t, const int*);            \
-  template __global__ void k_newton_update<S>(int, double*, const S*, int, double*, int, const int*);            \
   template __global__ void k_fill<S>(size_t, S*, S);
-INST(double)
-INST(float)
+FSI_INST_S(double)
+FSI_INST_S(float)
+template __global__ void k_change_norms<2>(int, const double*, const double*, int, double*, int);
+template __global__ void k_change_norms<3>(int, const double*, const double*, int, double*, int);
 template __global__ void k_transpose_J<double>(Geom, double, const double*, double*, double*);
 template __global__ void k_spmv_T<double>(Geom, double, const double*, const double*, double*, int);
 template __global__ void k_convert<double, float>(size_t, const double*, float*);
 template __global__ void k_convert<float, double>(size_t, const float*, double*);
+template __global__ void k_convert<double, double>(size_t, const double*, double*);
+template __global__ void k_convert<float, float>(size_t, const float*, float*);
 
 }  // namespace fsi
