@@ -100,11 +100,18 @@ def _check(code, where):
 SOLVER_DEFAULTS = dict(cip_gamma=1e-4, gmres_restart=30, gmres_maxit=300, newton_maxit=30,
                        vanka_sweeps=2, vanka_omega=0.9, newton_rtol=1e-10, lin_rtol=1e-6,
                        vanka_sweeps_coarse=1, precond_lag=1, lin_rtol_first=1e-3)
+# 3d: the multiplicative 8-colour Vanka sweep is stable only with more damping
+# (a sweep with omega 0.9 amplifies errors at the 64x16x16 level), and the
+# level-0 gradient-jump penalty needs a larger weight for the coarse correction
+# to contract
+SOLVER_DEFAULTS_3D = dict(vanka_omega=0.6, cip_gamma=3e-4)
 
 
 def make_params(d: dict, precision=None, max_batch=None, **solver) -> Params:
     """fsi_params from a workload dict (geometry segments, physics, time grid keys)."""
     s = dict(SOLVER_DEFAULTS)
+    if d["dim"] == 3:
+        s.update(SOLVER_DEFAULTS_3D)
     s.update({k: v for k, v in d.items() if k in SOLVER_DEFAULTS})
     s.update(solver)
     p = Params()
