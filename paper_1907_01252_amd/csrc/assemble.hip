@@ -347,13 +347,21 @@ __global__ void k_elem_residual(Geom g, StepPar sp, const double* __restrict__ U
 }
 
 // Ke[b][NE*row + col][cell]: d Re_row / d U_col (new state) or / d Uo_col (old state).
+// A block takes jac_cells<D> consecutive cells (one per thread of a group) and
+// jac_waves<D> such groups; group w evaluates the dual-number residual for the
+// directions d = w, w + groups, ..., so the element matrices are written in
+// coalesced cell runs and in 2d the work of one cell is spread over 4 groups
+// (in 3d the register-heavy residual runs best with one group).
 template <int D, bool OLD>
-__global__ void __launch_bounds__(128) k_elem_jacobian(Geom g, StepPar sp, const double* __restrict__ U,
-                                                       const double* __restrict__ Uo, double* __restrict__ Ke,
-                                                       const int* __restrict__ active) {
+__global__ void __launch_bounds__(jac_cells<D>() * jac_waves<D>()) k_elem_jacobian(Geom g, StepPar sp,
+                                                                      const double* __restrict__ U,
+                                                                      const double* __restrict__ Uo,
+                                                                      double* __restrict__ Ke,
+                                                                      const int* __restrict__ active) {
   FSI_DIM(D);
   const int b = blockIdx.y;
-  const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+  const int cell = blockIdx.x * jac_cells<D>() + (int)threadIdx.x % jac_cells<D>();
+  const int w = (int)threadIdx.x / jac_cells<D>();
   if (cell >= g.ncell || (active && !active[b])) return;
   CellIn<D> ci = load_cell<D>(g, cell);
   const size_t so = (size_t)b * g.nn * NC;
@@ -364,7 +372,7 @@ __global__ void __launch_bounds__(128) k_elem_jacobian(Geom g, StepPar sp, const
       Uoe[NC * a + c] = Uo[so + (size_t)ci.nodes[a] * NC + c];
     }
   double* out = Ke + (size_t)b * NE * NE * g.ncell;
-  for (int d = 0; d < NE; ++d) {
+  for (int d = w; d < NE; d += jac_waves<D>()) {
     Dual R[NE];
     if (!OLD) {
       Dual Un[NE];

@@ -483,7 +483,8 @@ fsi_status assemble_levels(fsi_problem* pb, int B, const StepPar& sp, const int*
     }
     {
       ProfScope ps(pb, F_JAC, st, (double)B * (g.ncell * NE * NE * 8.0 + 2.0 * g.nn * NC * 8));
-      k_elem_jacobian<D, false><<<dim3((g.ncell + 127) / 128, B), 128, 0, st>>>(g, sp, U, Uo, pb->Ke, act);
+      k_elem_jacobian<D, false><<<dim3((g.ncell + jac_cells<D>() - 1) / jac_cells<D>(), B),
+                                  jac_cells<D>() * jac_waves<D>(), 0, st>>>(g, sp, U, Uo, pb->Ke, act);
     }
     k_gather_jacobian<D, S><<<grid1(g.nn, B), TPB, 0, st>>>(g, sp.k, pb->Ke, (S*)lv.J, lv.Dsc, act, 1);
     if (transpose) {
@@ -526,7 +527,7 @@ void smooth(fsi_problem* pb, int l, int B, double k, int sweeps, bool zero_first
   const Geom g = lv.geom();
   const S om = (S)pb->p.vanka_omega;
   const bool fine = l == pb->nlev - 1;
-  constexpr int NCOL = Dm<D>::NCOL, VC = vc_cells<D>();
+  constexpr int NCOL = Dm<D>::NCOL;
   // the passes alternate between x and the level's residual buffer; an even
   // number of colours per sweep leaves the result in x
   S* buf[2] = {x, (S*)lv.r_};
@@ -541,10 +542,18 @@ void smooth(fsi_problem* pb, int l, int B, double k, int sweeps, bool zero_first
                                             vec) +
                                    (double)NPST * g.nn * 8.0;
       ProfScope ps(pb, fine ? F_SMOOTH : F_COARSE_LEV, st, by);
-      const int npb = (nc + VC - 1) / VC, ncopy = (g.nn + NC * 64 - 1) / (NC * 64);
-      k_vanka_color<D, S><<<dim3(npb + ncopy, B), NC * 64, 0, st>>>(g, k, c, om, zero ? 1 : 0, (const S*)lv.J,
-                                                                     (const S*)lv.Ainv, b, buf[cur], buf[cur ^ 1],
-                                                                     act);
+      const int ncopy = (g.nn + NC * 64 - 1) / (NC * 64);
+      const S *J = (const S*)lv.J, *Ai = (const S*)lv.Ainv;
+      if constexpr (D == 2) {
+        k_vanka_color<D, S, 16><<<dim3((nc + 15) / 16 + ncopy, B), NC * 64, 0, st>>>(
+            g, k, c, om, zero ? 1 : 0, J, Ai, b, buf[cur], buf[cur ^ 1], act);
+      } else if ((size_t)nc * B >= 8192) {   // 3d: wide blocks where there are cells enough to fill the GPU
+        k_vanka_color<D, S, 32><<<dim3((nc + 31) / 32 + ncopy, B), NC * 64, 0, st>>>(
+            g, k, c, om, zero ? 1 : 0, J, Ai, b, buf[cur], buf[cur ^ 1], act);
+      } else {
+        k_vanka_color<D, S, 8><<<dim3((nc + 7) / 8 + ncopy, B), NC * 64, 0, st>>>(
+            g, k, c, om, zero ? 1 : 0, J, Ai, b, buf[cur], buf[cur ^ 1], act);
+      }
       cur ^= 1;
     }
 }
@@ -1016,8 +1025,9 @@ fsi_status adjoint_run(fsi_problem* pb, double T, int N, int m, const double* U0
     HIPCHK(hipMemsetAsync(pb->arhs, 0, nd * sizeof(double), st));
     k_drag_gradient<<<1, 1, 0, st>>>(g, rn, pb->faces, pb->nfaces, cur(s), -k, pb->arhs);
     if (s < S) {
-      k_elem_jacobian<2, true><<<dim3((g.ncell + 127) / 128, 1), 128, 0, st>>>(g, sp, cur(s + 1), prev(s + 1), pb->Ke,
-                                                                           nullptr);
+      k_elem_jacobian<2, true><<<dim3((g.ncell + jac_cells<2>() - 1) / jac_cells<2>(), 1),
+                                 jac_cells<2>() * jac_waves<2>(), 0, st>>>(
+          g, sp, cur(s + 1), prev(s + 1), pb->Ke, nullptr);
       k_gather_jacobian<2, double><<<grid1(g.nn, 1), TPB, 0, st>>>(g, k, pb->Ke, pb->Jold, nullptr, nullptr, 0);
       k_spmv_T<double><<<grid1(g.nn, 1), TPB, 0, st>>>(g, k, pb->Jold, pb->lamn, pb->ay, 0);
       k_daxpy<<<64, TPB, 0, st>>>(nd, -1.0, pb->ay, pb->arhs);

@@ -137,12 +137,16 @@ __host__ __device__ inline size_t jidx(int node, int s, int e) {
 // node (NC waves), the Vanka factor one lane group per patch row set.
 template <int D>
 __host__ __device__ constexpr int spmv_threads() { return Dm<D>::NC * 64; }
-template <int D>
-__host__ __device__ constexpr int vc_cells() { return 64 / Dm<D>::NL; }      // cells per fused-pass block
+
 template <int D>
 __host__ __device__ constexpr int vf_lanes() { return D == 2 ? 32 : 64; }    // lanes per patch (>= NE)
 template <int D>
 __host__ __device__ constexpr int vf_patches() { return D == 2 ? 8 : 1; }    // patches per factor block
+// element Jacobian: blocks of jac_cells cells, jac_waves threads per cell
+template <int D>
+__host__ __device__ constexpr int jac_cells() { return D == 2 ? 64 : 128; }
+template <int D>
+__host__ __device__ constexpr int jac_waves() { return D == 2 ? 4 : 1; }
 
 // ------------------------------------------------------------ colour helpers
 // Cells of colour c = (i mod 2) + 2 (j mod 2) + 4 (k mod 2): ncx per row, ncy

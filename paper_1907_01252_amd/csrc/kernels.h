@@ -41,7 +41,7 @@ __global__ void k_spmv(Geom g, double k, const S* J, const S* x, const S* b, con
                        const int* active);
 template <int D, class S>
 __global__ void k_vanka_factor(Geom g, double k, const S* J, S* Ainv, const int* active);
-template <int D, class S>
+template <int D, class S, int VC>
 __global__ void k_vanka_color(Geom g, double k, int color, S omega, int zero_in, const S* J, const S* Ainv,
                               const S* b, const S* xo, S* xn, const int* active);
 template <int D, class S>

@@ -258,20 +258,23 @@ __global__ void __launch_bounds__(vf_lanes<D>() * vf_patches<D>()) k_vanka_facto
 // different buffers (other patches read x_old at the shared neighbours).
 // zero_in: x_old is taken as zero (first pass of a cycle): r_P = b_P and the
 // uncovered nodes get zero.
-// Thread mapping: a block of vc_cells consecutive cells of the colour has NC
-// waves, wave r forming row r of every patch node.  In a wave, lane group
-// g = lane / (2 vc_cells) takes the local node pair (2g, 2g+1) of the block's
-// cells, so within one cell row a wave reads runs of 2 vc_cells consecutive
-// nodes.  The NE patch residuals meet in LDS; the same thread then forms patch
-// row NC a + r of Ainv_P r_P.  Extra blocks past the patch blocks copy the
+// Thread mapping: a block of VC consecutive cells of the colour has NC waves,
+// wave r forming row r of every patch node.  A lane group of 2 VC lanes takes
+// one node pair (a, a + 1) of the VC cells, so within one cell row a wave
+// reads runs of 2 VC consecutive nodes and the inverses in VC-cell runs.
+// 2d uses VC = 16 (two groups: pairs (0,1) and (2,3)).  3d uses VC = 32 on
+// large levels (one group; each thread loops over the four pairs) and VC = 8
+// on small ones (four groups, one pair each: more blocks for few cells).  The
+// NE patch residuals meet in LDS; the same thread then forms patch rows
+// NC a + r of Ainv_P r_P.  Extra blocks past the patch blocks copy the
 // uncovered nodes.
-template <int D, class S>
+template <int D, class S, int VC>
 __global__ void __launch_bounds__(Dm<D>::NC * 64) k_vanka_color(Geom g, double k, int color, S omega, int zero_in,
                                                                 const S* __restrict__ J, const S* __restrict__ Ainv,
                                                                 const S* __restrict__ b, const S* __restrict__ xo,
                                                                 S* __restrict__ xn, const int* __restrict__ active) {
   FSI_DIM(D);
-  constexpr int VC = vc_cells<D>();
+  static_assert(VC == 8 || VC == 16 || VC == 32, "cells per block");
   __shared__ S rs[NE][VC];
   const int bs = blockIdx.y;
   if (active && !active[bs]) return;   // uniform over the block
@@ -292,42 +295,58 @@ __global__ void __launch_bounds__(Dm<D>::NC * 64) k_vanka_color(Geom g, double k
       for (int c = 0; c < NC; ++c) xnb[(size_t)t * NC + c] = zero_in ? (S)0 : xob[(size_t)t * NC + c];
     return;
   }
+  // lane -> (cell jc of the block, node-pair group gp); the G = 64 / (2 VC)
+  // groups of a wave take the node pairs (2 gp, 2 gp + 1), and each thread
+  // loops over the NQ = NL / (2 G) pairs gp + G q
   const int r = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int a = ((lane / (2 * VC)) << 1) | (lane & 1);
+  constexpr int G = 64 / (2 * VC), NQ = NL / (2 * G), QS = 2 * G;
   const int jc = (lane % (2 * VC)) >> 1;
+  const int a0 = (lane & 1) + 2 * (lane / (2 * VC));
   const int idx = blockIdx.x * VC + jc;
   const bool live = idx < nc;
-  int n = 0;
+  int ci = 0, cj = 0, ck = 0;
   if (live) {
     const int ix = idx % L.ncx, rest = idx / L.ncx;
-    const int ci = 2 * ix + cx, cj = 2 * (rest % L.ncy) + cy, ck = D == 3 ? 2 * (rest / L.ncy) + cz : 0;
-    n = node_at(g, ci + (a & 1), cj + ((a >> 1) & 1), ck + ((a >> 2) & 1));
-    S acc = 0;
-    if (!zero_in) {
-      int i, j, kk;
-      node_ijk<D>(g, n, i, j, kk);
-      const S* jb = J + (size_t)bs * jslice<D>(g.nn);
-      int off[NSLOT];
-      slot_offsets<D>(g, i, j, kk, off);
+    ci = 2 * ix + cx;
+    cj = 2 * (rest % L.ncy) + cy;
+    ck = D == 3 ? 2 * (rest / L.ncy) + cz : 0;
+#pragma unroll 1
+    for (int q = 0; q < NQ; ++q) {
+      const int a = a0 + q * QS;
+      const int n = node_at(g, ci + (a & 1), cj + ((a >> 1) & 1), ck + ((a >> 2) & 1));
+      S acc = 0;
+      if (!zero_in) {
+        int i, j, kk;
+        node_ijk<D>(g, n, i, j, kk);
+        const S* jb = J + (size_t)bs * jslice<D>(g.nn);
+        int off[NSLOT];
+        slot_offsets<D>(g, i, j, kk, off);
 #pragma unroll
-      for (int s = 0; s < NSLOT; ++s) {
-        const S* xv = xob + (size_t)(n + off[s]) * NC;
+        for (int s = 0; s < NSLOT; ++s) {
+          const S* xv = xob + (size_t)(n + off[s]) * NC;
 #pragma unroll
-        for (int c = 0; c < NC; ++c) acc += jb[jidx<D>(n, s, NC * r + c)] * xv[c];
+          for (int c = 0; c < NC; ++c) acc += jb[jidx<D>(n, s, NC * r + c)] * xv[c];
+        }
+        if (r == PC) acc += pst_row<D, S>(g, k, n, i, j, kk, xob);
       }
-      if (r == PC) acc += pst_row<D, S>(g, k, n, i, j, kk, xob);
+      rs[NC * a + r][jc] = b[((size_t)bs * g.nn + n) * NC + r] - acc;
     }
-    rs[NC * a + r][jc] = b[((size_t)bs * g.nn + n) * NC + r] - acc;
   }
   __syncthreads();
   if (!live) return;
   const S* ai = Ainv + (size_t)bs * NE * NE * g.ncell + (size_t)L.off * NE * NE + idx;
-  const int row = NC * a + r;
-  S z = 0;
-#pragma unroll
-  for (int e = 0; e < NE; ++e) z += ai[(size_t)(NE * row + e) * nc] * rs[e][jc];
-  const size_t o = (size_t)n * NC + r;
-  xnb[o] = (zero_in ? (S)0 : xob[o]) + omega * z;
+#pragma unroll 1
+  for (int q = 0; q < NQ; ++q) {
+    const int a = a0 + q * QS;
+    const int row = NC * a + r;
+    S z = 0;
+    constexpr int EU = NQ == 1 ? NE : 8;   // looping threads: bounded loads in flight (registers)
+#pragma unroll EU
+    for (int e = 0; e < NE; ++e) z += ai[(size_t)(NE * row + e) * nc] * rs[e][jc];
+    const int n = node_at(g, ci + (a & 1), cj + ((a >> 1) & 1), ck + ((a >> 2) & 1));
+    const size_t o = (size_t)n * NC + r;
+    xnb[o] = (zero_in ? (S)0 : xob[o]) + omega * z;
+  }
 }
 
 // --------------------------------------------------------- grid transfers
@@ -928,8 +947,8 @@ __global__ void k_convert(size_t n, const A* __restrict__ X, B2* __restrict__ Y)
   template __global__ void k_spmv<D, S>(Geom, double, const S*, const S*, const S*, const double*, S*,           \
                                         const int*);                                                             \
   template __global__ void k_vanka_factor<D, S>(Geom, double, const S*, S*, const int*);                         \
-  template __global__ void k_vanka_color<D, S>(Geom, double, int, S, int, const S*, const S*, const S*,          \
-                                               const S*, S*, const int*);                                        \
+  template __global__ void k_vanka_color<D, S, (D == 2 ? 16 : 32)>(Geom, double, int, S, int, const S*,         \
+                                                                   const S*, const S*, const S*, S*, const int*); \
   template __global__ void k_restrict<D, S>(Geom, Geom, const S*, S*, const int*);                               \
   template __global__ void k_prolong_add<D, S>(Geom, Geom, const S*, S*, const int*);                            \
   template __global__ void k_newton_update<D, S>(int, double*, const S*, int, double*, int, const int*);
@@ -951,6 +970,10 @@ __global__ void k_convert(size_t n, const A* __restrict__ X, B2* __restrict__ Y)
   template __global__ void k_fill<S>(size_t, S*, S);
 FSI_INST_S(double)
 FSI_INST_S(float)
+template __global__ void k_vanka_color<3, double, 8>(Geom, double, int, double, int, const double*, const double*,
+                                                     const double*, const double*, double*, const int*);
+template __global__ void k_vanka_color<3, float, 8>(Geom, double, int, float, int, const float*, const float*,
+                                                    const float*, const float*, float*, const int*);
 template __global__ void k_change_norms<2>(int, const double*, const double*, int, double*, int);
 template __global__ void k_change_norms<3>(int, const double*, const double*, int, double*, int);
 template __global__ void k_transpose_J<double>(Geom, double, const double*, double*, double*);
