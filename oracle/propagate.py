@@ -128,8 +128,39 @@ def relative_change(Unew, Uold, dim):
     return r
 
 
-def parareal(disc, p, U0, tol=None, max_iter=None, rtol=1e-10, history=None):
-    """Parareal predictor-corrector of eq. (parareal:iteration).
+def theta_weight(F, C, dim, mode):
+    """Weight of the coarse terms in theta-Parareal (eq. (thetaparareal:iteration)).
+
+    The paper fits theta so that theta C(U^{i+1}_l) matches F(U^i_l): the least
+    squares value <F, C> / <C, C>, or the variant it uses, read here as the
+    cosine <F, C> / (|F| |C|) (<= 1 by Cauchy-Schwarz, which is what the paper
+    states for its choice; the printed denominator lacks the square roots).
+    Both are computed per solution component (the 2d velocity and displacement
+    components) and averaged; components with a zero norm are left out, and
+    with none left theta = 1 (plain Parareal).
+    """
+    if mode in (None, "plain"):
+        return 1.0
+    vals = []
+    for c in range(2 * dim):
+        f, g = F[:, c], C[:, c]
+        fg, gg, ff = float(f @ g), float(g @ g), float(f @ f)
+        if mode == "lsq":
+            if gg > 0.0:
+                vals.append(fg / gg)
+        elif mode == "cosine":
+            if gg > 0.0 and ff > 0.0:
+                vals.append(fg / np.sqrt(gg * ff))
+        else:
+            raise ValueError(mode)
+    return float(np.mean(vals)) if vals else 1.0
+
+
+def parareal(disc, p, U0, tol=None, max_iter=None, rtol=1e-10, history=None, theta=None, thetas=None):
+    """Parareal predictor-corrector of eq. (parareal:iteration); with theta =
+    "cosine" or "lsq" the weighted variant of eq. (thetaparareal:iteration),
+    U^{i+1}_{l+1} = th C(U^{i+1}_l) + F(U^i_l) - th C(U^i_l), th from
+    theta_weight(F(U^i_l), C(U^{i+1}_l)).
 
     U^0_0 = U0, U^0_{l+1} = C(U^0_l); iteration i computes F(U^i_l) for the
     slices l >= i (earlier slices are already exact), then sweeps
@@ -159,9 +190,13 @@ def parareal(disc, p, U0, tol=None, max_iter=None, rtol=1e-10, history=None):
             if l < i:
                 # slice l started from an exact state: its coarse value is unchanged
                 cn = Cold[l]
+                th = 1.0
             else:
                 cn = coarse_propagate(disc, p, Unew[l], l * dl, rtol=rtol)
-            Unew.append(cn + Fv[l] - Cold[l])
+                th = theta_weight(Fv[l], cn, disc.dim, theta)
+            if thetas is not None:
+                thetas.append((i, l, th))
+            Unew.append(th * cn + Fv[l] - th * Cold[l])
             Cold[l] = cn
         it = i + 1
         change = relative_change(np.stack(Unew), np.stack(U), disc.dim)

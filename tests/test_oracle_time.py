@@ -117,3 +117,57 @@ def test_parareal_finite_termination_and_K_equals_N():
     assert rel(hist[0][0][p["N"]][:, :4], seq[p["N"]][:, :4]) > 1e-8
     for l in range(p["N"] + 1):
         assert rel(Upar[l][:, :4], seq[l][:, :4]) <= 1e-12
+
+
+def test_theta_weight_definitions():
+    """Least squares weight minimises |F_c - th C_c| per component; the cosine weight is <= 1 and 1 for parallel fields."""
+    rng = np.random.default_rng(3)
+    F = rng.normal(size=(50, 5))
+    C = F + 0.3 * rng.normal(size=(50, 5))
+    lsq = [np.linalg.lstsq(C[:, [c]], F[:, c], rcond=None)[0][0] for c in range(4)]
+    assert abs(P.theta_weight(F, C, 2, "lsq") - np.mean(lsq)) <= 1e-14
+    cosv = [F[:, c] @ C[:, c] / (np.linalg.norm(F[:, c]) * np.linalg.norm(C[:, c])) for c in range(4)]
+    assert abs(P.theta_weight(F, C, 2, "cosine") - np.mean(cosv)) <= 1e-14
+    assert P.theta_weight(F, C, 2, "cosine") <= 1.0
+    assert abs(P.theta_weight(F, 2.5 * F, 2, "cosine") - 1.0) <= 1e-14
+    assert abs(P.theta_weight(F, 2.5 * F, 2, "lsq") - 0.4) <= 1e-14
+    # the pressure column does not enter; zero components are left out
+    G = C.copy()
+    G[:, 4] = 1e9
+    assert P.theta_weight(F, G, 2, "lsq") == P.theta_weight(F, C, 2, "lsq")
+    Z = np.zeros_like(F)
+    assert P.theta_weight(Z, C, 2, "cosine") == 1.0 and P.theta_weight(F, Z, 2, "lsq") == 1.0
+
+
+@pytest.mark.parametrize("mode", ["cosine", "lsq"])
+def test_theta_parareal_finite_termination(mode):
+    """Weighted Parareal keeps finite termination: slices 0..i exact after i iterations, K = N sequential."""
+    p = _small_parareal_problem()
+    D = Discretization(p)
+    U0 = np.zeros((D.mesh.n_nodes, 5))
+    seq = P.sequential(D, p, U0)
+    hist, th = [], []
+    Upar, it = P.parareal(D, p, U0, tol=0.0, history=hist, theta=mode, thetas=th)
+    assert it == p["N"]
+
+    def rel(a, b):
+        nb = np.linalg.norm(b)
+        return np.linalg.norm(a - b) / nb if nb > 0 else np.linalg.norm(a - b)
+
+    for i, (Ui, _) in enumerate(hist):
+        for l in range(0, i + 2):
+            assert rel(Ui[l][:, :4], seq[l][:, :4]) <= 1e-12, (i, l)
+    # the weights are genuinely different from 1 on the corrected slices
+    assert any(abs(t - 1.0) > 1e-6 for (i, l, t) in th if l >= i)
+    if mode == "cosine":
+        assert all(t <= 1.0 + 1e-15 for (_, _, t) in th)
+
+
+def test_plain_parareal_is_theta_one():
+    p = _small_parareal_problem()
+    D = Discretization(p)
+    U0 = np.zeros((D.mesh.n_nodes, 5))
+    a, ia = P.parareal(D, p, U0, tol=0.0, max_iter=2)
+    th = []
+    b, ib = P.parareal(D, p, U0, tol=0.0, max_iter=2, theta="plain", thetas=th)
+    assert ia == ib and np.array_equal(a, b) and all(t == 1.0 for (_, _, t) in th)
