@@ -86,6 +86,13 @@ typedef struct {
                                 Krylov operator is the exact Jacobian either way) */
   double lin_rtol_first;     /* FGMRES relative tolerance of the first Newton iteration of a step
                                 (0 < lin_rtol_first < 1) */
+  int32_t parareal_theta;    /* parareal_run correction (eq. (thetaparareal:iteration)):
+                                0 plain Parareal (theta = 1);
+                                1 theta = mean over the velocity and displacement components c of
+                                  <F_c, C_c> / (|F_c| |C_c|);
+                                2 theta = mean over c of <F_c, C_c> / <C_c, C_c>;
+                                F = F(U^i_l), C = C(U^{i+1}_l); components with a zero norm are
+                                left out, and with none left theta = 1 */
 } fsi_params;
 
 #define FSI_MAX_SLICES 1024
@@ -95,7 +102,7 @@ typedef struct {
   int32_t slice_status[FSI_MAX_SLICES]; /* fsi_status of the slice */
   double stage_ms[8];                   /* 0 residual, 1 Jacobian+smoother setup, 2 linear solve,
                                            3 update, 4 total, 5 coarse (Parareal), 6 fine (Parareal) */
-  int32_t parareal_iters;
+  int32_t parareal_iters;               /* completed Parareal iterations (also when a later one failed) */
   int32_t newton_total, krylov_total;   /* totals over all slices of the call */
 } fsi_stats;
 

@@ -1105,7 +1105,8 @@ fsi_status fsi_setup(const fsi_params* prm, fsi_problem** out) {
       p.gmres_restart < 1 || p.gmres_restart > 63 || p.newton_maxit < 1 || p.vanka_sweeps < 1 ||
       p.vanka_sweeps_coarse < 1 ||
       p.gmres_maxit < 1 || (p.precision != FSI_FP64 && p.precision != FSI_MIXED) ||
-      (p.precond_lag != 0 && p.precond_lag != 1) || !(p.lin_rtol_first > 0.0 && p.lin_rtol_first < 1.0))
+      (p.precond_lag != 0 && p.precond_lag != 1) || !(p.lin_rtol_first > 0.0 && p.lin_rtol_first < 1.0) ||
+      p.parareal_theta < 0 || p.parareal_theta > 2)
     return FSI_ERR_ARG;
   for (int a = 0; a < p.dim; ++a) {
     if (p.nseg[a] < 1 || p.nseg[a] > 4) return FSI_ERR_ARG;
@@ -1243,14 +1244,17 @@ fsi_status parareal_run(fsi_problem* pb, double T, int32_t N, int32_t m, int32_t
   Level& F = pb->lev[pb->nlev - 1];
   const size_t nd = (size_t)F.nn * (2 * pb->p.dim + 1);
   const double dl = T / N;
-  double *Cold = nullptr, *Fv = nullptr, *Up = nullptr, *Cn = nullptr, *part = nullptr;
+  double *Cold = nullptr, *Fv = nullptr, *Up = nullptr, *Cn = nullptr, *part = nullptr, *tpart = nullptr;
   const int chunk = 4096, nchunk = (F.nn + chunk - 1) / chunk;
+  std::vector<double> htp((size_t)18 * nchunk);
   auto cleanup = [&]() {
     (void)hipFree(Cold); (void)hipFree(Fv); (void)hipFree(Up); (void)hipFree(Cn); (void)hipFree(part);
+    (void)hipFree(tpart);
   };
   if (hipMalloc(&Cold, N * nd * sizeof(double)) != hipSuccess || hipMalloc(&Fv, N * nd * sizeof(double)) != hipSuccess ||
       hipMalloc(&Up, (N + 1) * nd * sizeof(double)) != hipSuccess || hipMalloc(&Cn, nd * sizeof(double)) != hipSuccess ||
-      hipMalloc(&part, (size_t)(N + 1) * 4 * nchunk * sizeof(double)) != hipSuccess) {
+      hipMalloc(&part, (size_t)(N + 1) * 4 * nchunk * sizeof(double)) != hipSuccess ||
+      hipMalloc(&tpart, (size_t)18 * nchunk * sizeof(double)) != hipSuccess) {
     cleanup();
     return FSI_ERR_OOM;
   }
@@ -1295,7 +1299,32 @@ fsi_status parareal_run(fsi_problem* pb, double T, int32_t N, int32_t m, int32_t
           coarse_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - c0).count();
           cn = Cn;
         }
-        k_parareal_update<<<256, TPB, 0, st>>>(nd, cn, Fv + l * nd, Cold + l * nd, Ub + (l + 1) * nd);
+        double th = 1.0;
+        if (l >= i && pb->p.parareal_theta != 0) {
+          // theta-Parareal weight from F(U^i_l) and C(U^{i+1}_l), per component, averaged
+          const int dim = pb->p.dim, nq = 3 * 2 * dim;
+          if (dim == 3)
+            k_theta_dots<3><<<nchunk, RED_T, 0, st>>>(F.nn, Fv + l * nd, Cn, chunk, tpart, nchunk);
+          else
+            k_theta_dots<2><<<nchunk, RED_T, 0, st>>>(F.nn, Fv + l * nd, Cn, chunk, tpart, nchunk);
+          if (hipMemcpyAsync(htp.data(), tpart, (size_t)nq * nchunk * sizeof(double), hipMemcpyDeviceToHost, st) !=
+                  hipSuccess ||
+              hipStreamSynchronize(st) != hipSuccess) { ret = FSI_ERR_HIP; goto done; }
+          double sum = 0.0;
+          int cnt = 0;
+          for (int c = 0; c < 2 * dim; ++c) {
+            double ff = 0.0, fg = 0.0, gg = 0.0;
+            for (int q = 0; q < nchunk; ++q) {
+              ff += htp[(size_t)(3 * c) * nchunk + q];
+              fg += htp[(size_t)(3 * c + 1) * nchunk + q];
+              gg += htp[(size_t)(3 * c + 2) * nchunk + q];
+            }
+            if (pb->p.parareal_theta == 1 && gg > 0.0 && ff > 0.0) { sum += fg / std::sqrt(gg * ff); ++cnt; }
+            if (pb->p.parareal_theta == 2 && gg > 0.0) { sum += fg / gg; ++cnt; }
+          }
+          th = cnt ? sum / cnt : 1.0;
+        }
+        k_parareal_update<<<256, TPB, 0, st>>>(nd, cn, Fv + l * nd, Cold + l * nd, Ub + (l + 1) * nd, th);
         if (cn != Cold + l * nd)
           if (hipMemcpyAsync(Cold + l * nd, Cn, nd * sizeof(double), hipMemcpyDeviceToDevice, st) != hipSuccess) { ret = FSI_ERR_HIP; goto done; }
       }
@@ -1318,6 +1347,7 @@ fsi_status parareal_run(fsi_problem* pb, double T, int32_t N, int32_t m, int32_t
           change = std::max(change, r);
         }
       it = i + 1;
+      sp->parareal_iters = it;   // completed iterations, also when a later one fails
       if (change < tol) break;
     }
     sp->parareal_iters = it;

@@ -87,7 +87,10 @@ __global__ void k_newton_update(int nn, double* U, const S* dx, int chunk, doubl
 __global__ void k_max_partials(int nchunk, const double* part, double* out, int B);
 __global__ void k_nonfinite(size_t n, const double* X, int* flag);
 __global__ void k_extrapolate(size_t n, double* U, const double* Uo, const double* Up, const int* active);
-__global__ void k_parareal_update(size_t n, const double* Cn, const double* Fv, const double* Cold, double* out);
+__global__ void k_parareal_update(size_t n, const double* Cn, const double* Fv, const double* Cold, double* out,
+                                  double th);
+template <int D>
+__global__ void k_theta_dots(int nn, const double* F, const double* Cv, int chunk, double* part, int nchunk);
 template <int D>
 __global__ void k_change_norms(int nn, const double* A, const double* Bv, int chunk, double* part, int nchunk);
 template <class S>

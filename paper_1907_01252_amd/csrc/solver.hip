@@ -881,11 +881,12 @@ __global__ void k_max_partials(int nchunk, const double* __restrict__ part, doub
   }
 }
 
-// Parareal correction of one boundary (eq. (parareal:iteration)): out = Cn + Fv - Cold, FP64.
+// Parareal correction of one boundary, FP64: out = th Cn + Fv - th Cold
+// (eq. (parareal:iteration) for th = 1, eq. (thetaparareal:iteration) otherwise).
 __global__ void k_parareal_update(size_t n, const double* __restrict__ Cn, const double* __restrict__ Fv,
-                                  const double* __restrict__ Cold, double* __restrict__ out) {
+                                  const double* __restrict__ Cold, double* __restrict__ out, double th) {
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
-    out[e] = Cn[e] + Fv[e] - Cold[e];
+    out[e] = th * Cn[e] + Fv[e] - th * Cold[e];
 }
 
 // Per boundary b: sums of squares of (A - B) and of A for the velocity and the
@@ -912,6 +913,31 @@ __global__ void __launch_bounds__(RED_T) k_change_norms(int nn, const double* __
   for (int q = 0; q < 4; ++q) {
     const double r = block_sum(s[q], sh);
     if (threadIdx.x == 0) part[((size_t)b * 4 + q) * nchunk + ch] = r;
+  }
+}
+
+// theta-Parareal inner products: per velocity/displacement component c, the
+// chunk sums of F_c F_c, F_c C_c and C_c C_c -> part[3 c + {0, 1, 2}][chunk].
+template <int D>
+__global__ void __launch_bounds__(RED_T) k_theta_dots(int nn, const double* __restrict__ F,
+                                                      const double* __restrict__ Cv, int chunk,
+                                                      double* __restrict__ part, int nchunk) {
+  FSI_DIM(D);
+  __shared__ double sh[RED_T];
+  const int ch = blockIdx.x;
+  const int lo = ch * chunk, hi = min(nn, lo + chunk);
+  double s[3 * 2 * D];
+  for (int q = 0; q < 3 * 2 * D; ++q) s[q] = 0.0;
+  for (int n = lo + threadIdx.x; n < hi; n += blockDim.x)
+    for (int c = 0; c < 2 * D; ++c) {
+      const double f = F[(size_t)n * NC + c], g = Cv[(size_t)n * NC + c];
+      s[3 * c] += f * f;
+      s[3 * c + 1] += f * g;
+      s[3 * c + 2] += g * g;
+    }
+  for (int q = 0; q < 3 * 2 * D; ++q) {
+    const double r = block_sum(s[q], sh);
+    if (threadIdx.x == 0) part[(size_t)q * nchunk + ch] = r;
   }
 }
 
@@ -976,6 +1002,8 @@ template __global__ void k_vanka_color<3, float, 8>(Geom, double, int, float, in
                                                     const float*, const float*, float*, const int*);
 template __global__ void k_change_norms<2>(int, const double*, const double*, int, double*, int);
 template __global__ void k_change_norms<3>(int, const double*, const double*, int, double*, int);
+template __global__ void k_theta_dots<2>(int, const double*, const double*, int, double*, int);
+template __global__ void k_theta_dots<3>(int, const double*, const double*, int, double*, int);
 template __global__ void k_transpose_J<double>(Geom, double, const double*, double*, double*);
 template __global__ void k_spmv_T<double>(Geom, double, const double*, const double*, double*, int);
 template __global__ void k_convert<double, float>(size_t, const double*, float*);

@@ -258,3 +258,22 @@ def test_drag_objective_autograd(fsi):
     assert abs(J.item() - Jo) <= 1e-10 * abs(Jo)
     for i in range(3):
         assert abs(q[i].grad.item() - go[i]) <= 1e-9 * abs(go[i])
+
+
+@pytest.mark.parametrize("mode,name", [(1, "cosine"), (2, "lsq")])
+def test_theta_parareal_parity(fsi, mode, name):
+    """Weighted Parareal (eq. (thetaparareal:iteration)) against the oracle, two iterations."""
+    p = synth.workload("c1", T=0.06, N=3, dt_fine=0.01, dt_coarse=0.02, seed=3)
+    _say("case: theta-parareal", name, "c1-small N=3 K=2")
+    prob = fsi.Problem(fsi.make_params(p, precision="fp64", max_batch=3, parareal_theta=mode))
+    D = Discretization(p)
+    U0 = np.zeros((D.mesh.n_nodes, 5))
+    ref, it = P.parareal(D, p, U0, tol=0.0, max_iter=2, theta=name)
+    Ub = torch.zeros(p["N"] + 1, prob.n_nodes, 5, dtype=torch.float64, device="cuda")
+    code, st = prob.parareal_run(p["T"], p["N"], p["m"], p["M"], 0.0, 2, _dev(U0), Ub, raise_on_error=False)
+    assert code in (fsi.FSI_OK, fsi.FSI_ERR_PARAREAL) and st.parareal_iters == 2
+    Ug = _host(Ub)
+    for l in range(1, p["N"] + 1):
+        err = field_rel(Ug[l], ref[l], norm="l2")
+        assert max(err["v"], err["u"]) <= 1e-10, (l, err)
+    prob.close()
