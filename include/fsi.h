@@ -93,6 +93,11 @@ typedef struct {
                                 2 theta = mean over c of <F_c, C_c> / <C_c, C_c>;
                                 F = F(U^i_l), C = C(U^{i+1}_l); components with a zero norm are
                                 left out, and with none left theta = 1 */
+  double theta_ref_k;        /* 0: every step of size k uses theta = 1/2 + theta0 k (Section 2.3).
+                                k_r > 0: theta = 1/2 + theta0 k_r^2 / k, the damping
+                                theta = 1/2 + alpha(k) k with equal dissipation per unit time
+                                for all step sizes (Section 4, fsi-3 discussion); steps of
+                                size k_r keep 1/2 + theta0 k_r */
 } fsi_params;
 
 #define FSI_MAX_SLICES 1024

@@ -124,9 +124,21 @@ class Discretization:
         self.S = _lps.lps_matrix(self) if m.level >= 1 else None
 
     def theta(self, k):
-        """theta = 1/2 + theta0 k (Section 2.3); a fixed theta may be forced."""
+        """theta = 1/2 + theta0 k (Section 2.3); a fixed theta may be forced.
+
+        With theta_ref_k = k_r > 0: the damping theta = 1/2 + alpha(k) k that the
+        paper proposes (Section 4, fsi-3 discussion) so that large and small
+        steps dissipate alike.  For y' = i w y the theta-scheme damps by
+        ln|R| = -(theta - 1/2) w^2 k^2 + O((w k)^4) per step, i.e. by
+        alpha(k) w^2 k^2 per unit time; equal damping per unit time for steps
+        k and k_r gives alpha(k) = theta0 (k_r / k)^2, so steps of size k_r keep
+        theta = 1/2 + theta0 k_r.
+        """
         if self.p.get("theta_fixed") is not None:
             return self.p["theta_fixed"]
+        kr = self.p.get("theta_ref_k") or 0.0
+        if kr > 0.0:
+            return 0.5 + self.p["theta0"] * kr * kr / k
         return 0.5 + self.p["theta0"] * k
 
     # ------------------------------------------------------------------ data

@@ -437,7 +437,10 @@ struct ProfScope {
 StepPar step_par(const fsi_problem* pb, double k) {
   StepPar sp;
   sp.k = k;
-  sp.theta = 0.5 + pb->p.theta0 * k;
+  // shifted Crank-Nicolson damping; with a reference step k_r the dissipation-matched
+  // theta = 1/2 + theta0 k_r^2 / k (equal damping per unit time for every step size)
+  const double kr = pb->p.theta_ref_k;
+  sp.theta = kr > 0.0 ? 0.5 + pb->p.theta0 * kr * kr / k : 0.5 + pb->p.theta0 * k;
   sp.rho_f = pb->p.rho_f; sp.nu_f = pb->p.nu_f; sp.rho_s = pb->p.rho_s;
   sp.mu_s = pb->p.mu_s; sp.lambda_s = pb->p.lambda_s;
   sp.peak = pb->p.inflow_peak; sp.ramp_time = pb->p.ramp_time;
@@ -1106,7 +1109,7 @@ fsi_status fsi_setup(const fsi_params* prm, fsi_problem** out) {
       p.vanka_sweeps_coarse < 1 ||
       p.gmres_maxit < 1 || (p.precision != FSI_FP64 && p.precision != FSI_MIXED) ||
       (p.precond_lag != 0 && p.precond_lag != 1) || !(p.lin_rtol_first > 0.0 && p.lin_rtol_first < 1.0) ||
-      p.parareal_theta < 0 || p.parareal_theta > 2)
+      p.parareal_theta < 0 || p.parareal_theta > 2 || !(p.theta_ref_k >= 0.0))
     return FSI_ERR_ARG;
   for (int a = 0; a < p.dim; ++a) {
     if (p.nseg[a] < 1 || p.nseg[a] > 4) return FSI_ERR_ARG;

@@ -277,3 +277,21 @@ def test_theta_parareal_parity(fsi, mode, name):
         err = field_rel(Ug[l], ref[l], norm="l2")
         assert max(err["v"], err["u"]) <= 1e-10, (l, err)
     prob.close()
+
+
+def test_dissipation_matched_coarse_step_parity(fsi):
+    """Coarse steps with theta = 1/2 + theta0 k_r^2 / K against the oracle with the same damping."""
+    p = synth.workload("c1", seed=4, theta_ref_k=0.0125)
+    _say("case: dissipation-matched coarse propagate c1 B=1 M=2")
+    prob = fsi.Problem(fsi.make_params(p, precision="fp64", max_batch=1, theta_ref_k=p["theta_ref_k"]))
+    D = Discretization(p)
+    U0 = np.zeros((D.mesh.n_nodes, 5))
+    Ua = P.propagate(D, U0, 0.0, 0.125, 2)
+    assert abs(D.theta(0.0625) - (0.5 + 0.0125 ** 2 / 0.0625)) < 1e-16
+    ref = P.propagate(D, Ua, 0.125, 0.125, 2)
+    Uin = _dev(Ua[None])
+    Uout = torch.zeros_like(Uin)
+    prob.coarse_propagate(1, [0.125], 0.125, 2, Uin, Uout)
+    err = field_rel(_host(Uout)[0], ref, norm="l2")
+    assert max(err.values()) <= 1e-10, err
+    prob.close()

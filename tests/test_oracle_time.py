@@ -171,3 +171,25 @@ def test_plain_parareal_is_theta_one():
     th = []
     b, ib = P.parareal(D, p, U0, tol=0.0, max_iter=2, theta="plain", thetas=th)
     assert ia == ib and np.array_equal(a, b) and all(t == 1.0 for (_, _, t) in th)
+
+
+def test_dissipation_matched_theta():
+    """theta(k) = 1/2 + theta0 k_r^2 / k damps an oscillation per unit time like steps of k_r (to leading order)."""
+    p = synth.workload("c2")
+    kr, K = 2.0 ** -9, 2.0 ** -6
+    D = Discretization(dict(p, theta_ref_k=kr))
+    D0 = Discretization(p)
+    assert D.theta(kr) == D0.theta(kr)
+
+    def rate(theta, k, w):
+        z = 1j * w * k
+        return np.log(abs((1 + (1 - theta) * z) / (1 - theta * z))) / k
+
+    for wK in (0.02, 0.05, 0.1):
+        w = wK / K
+        fine = rate(D0.theta(kr), kr, w)
+        matched = rate(D.theta(K), K, w)
+        default = rate(D0.theta(K), K, w)
+        assert fine < 0 and matched < 0
+        assert abs(matched / fine - 1.0) <= 2 * wK ** 2, (wK, matched / fine)
+        assert default / fine > 50.0        # the default large step damps ~ (K / k_r)^2 = 64 times more
