@@ -463,7 +463,7 @@ __global__ void k_gather_residual(Geom g, StepPar sp, const double* __restrict__
 // (Dirichlet rows become identity rows) and compute the row scaling
 // Dsc[b][node][c] = 1 / max_j |J_row,j| (including k S on pressure rows).
 // Slots whose neighbour lies outside the mesh are written as zeros.
-template <int D, class S>
+template <int D, class S, bool CJ>
 __global__ void k_gather_jacobian(Geom g, double k, const double* __restrict__ Ke, S* __restrict__ J,
                                   double* __restrict__ Dsc, const int* __restrict__ active, int dir_identity) {
   FSI_DIM(D);
@@ -473,7 +473,7 @@ __global__ void k_gather_jacobian(Geom g, double k, const double* __restrict__ K
   int i, j, kk;
   node_ijk<D>(g, n, i, j, kk);
   const double* ke = Ke + (size_t)b * NE * NE * g.ncell;
-  S* jb = J + (size_t)b * jslice<D>(g.nn);
+  S* jb = J + (size_t)b * jslice<D, CJ>(g.nn);
   const uint8_t m = g.dmask[n];
   double rmax[NC];
   for (int c = 0; c < NC; ++c) rmax[c] = 0.0;
@@ -502,7 +502,11 @@ __global__ void k_gather_jacobian(Geom g, double k, const double* __restrict__ K
         for (int c = 0; c < NC; ++c) blk[NC * r + c] = (dir_identity && centre && c == r) ? 1.0 : 0.0;
       for (int c = 0; c < NC; ++c) rmax[r] = fmax(rmax[r], fabs(blk[NC * r + c]));
     }
-    for (int e = 0; e < BLK; ++e) jb[jidx<D>(n, s, e)] = (S)blk[e];
+    for (int r = 0; r < NC; ++r)
+      for (int c = 0; c < NC; ++c) {
+        const int e = jentry<D, CJ>(r, c);   // compressed layout: structural zeros are not stored
+        if (e >= 0) jb[jidx<D, CJ>(n, s, e)] = (S)blk[NC * r + c];
+      }
   }
   if (!(m & dm_p<D>())) {
     double pm = 0.0;
@@ -685,13 +689,15 @@ __global__ void __launch_bounds__(256) k_param_sens(Geom g, StepPar sp, const do
   template __global__ void k_apply_dirichlet<D>(Geom, StepPar, double*, const double*, const int*);              \
   template __global__ void k_gather_residual<D>(Geom, StepPar, const double*, const double*, const double*,      \
                                                 double*, const int*);                                            \
-  template __global__ void k_gather_jacobian<D, double>(Geom, double, const double*, double*, double*,           \
-                                                        const int*, int);                                        \
-  template __global__ void k_gather_jacobian<D, float>(Geom, double, const double*, float*, double*, const int*, \
-                                                       int);                                                     \
+  template __global__ void k_gather_jacobian<D, double, true>(Geom, double, const double*, double*, double*,     \
+                                                              const int*, int);                                  \
+  template __global__ void k_gather_jacobian<D, float, true>(Geom, double, const double*, float*, double*,       \
+                                                             const int*, int);                                   \
   template __global__ void k_inject<D>(Geom, Geom, const double*, double*);
 FSI_INST_ASM(2)
 FSI_INST_ASM(3)
 template __global__ void k_elem_jacobian<2, true>(Geom, StepPar, const double*, const double*, double*, const int*);
+template __global__ void k_gather_jacobian<2, double, false>(Geom, double, const double*, double*, double*, const int*,
+                                                             int);
 
 }  // namespace fsi

@@ -90,6 +90,7 @@ struct fsi_problem {
   int vc_B = -1;
   double vc_k = -1.0;
   bool vc_mixed = false;
+  bool vc_cj = true;
   bool use_graphs = true;
   bool verbose = false;   // FSI_VERBOSE=1: Newton progress of slice 0 on stderr
   // library-owned stream for the propagators (capturable; ordered after the caller's stream)
@@ -395,7 +396,7 @@ fsi_status build_level(fsi_problem* pb, int l) {
   CHK(dalloc(pb, &L.U, (size_t)B * L.nn * NC));
   CHK(dalloc(pb, &L.Uo, (size_t)B * L.nn * NC));
   CHK(dalloc(pb, &L.Dsc, (size_t)B * L.nn * NC));
-  CHK(dalloc_bytes(pb, &L.J, (size_t)B * jslice<D>(L.nn) * ss));
+  CHK(dalloc_bytes(pb, &L.J, (size_t)B * jslice<D, false>(L.nn) * ss));
   // Vanka inverses: every smoothed level (in 3d level 0 is smoothed too)
   if (l >= 1 || D == 3) CHK(dalloc_bytes(pb, &L.Ainv, (size_t)B * NE * NE * L.ncell * ss));
   CHK(dalloc_bytes(pb, &L.x_, (size_t)B * L.nn * NC * ss));
@@ -466,11 +467,13 @@ fsi_status residual(fsi_problem* pb, int B, const StepPar& sp, const double* U, 
 // Jacobian of the finest level (always) and, when precond is set, the multigrid
 // hierarchy: injected coarse states, coarse-level Jacobians, Vanka inverses and
 // the coarsest-level solver (2d: explicit inverse; 3d: Vanka inverses, the
-// level is smoothed).
-template <int D, class S>
+// level is smoothed).  CJ selects the compressed block layout (the step
+// Jacobian) or the full one (the transposed adjoint operator).
+template <int D, class S, bool CJ>
 fsi_status assemble_levels(fsi_problem* pb, int B, const StepPar& sp, const int* act, hipStream_t st,
                            bool precond = true, bool transpose = false, double* save_fine = nullptr) {
   FSI_DIM(D);
+  if (CJ && transpose) return FSI_ERR_ARG;   // a transposed block needs the full layout
   const int L = pb->nlev - 1;
   for (int l = L; l >= (precond ? 0 : L); --l) {
     Level& lv = pb->lev[l];
@@ -489,22 +492,22 @@ fsi_status assemble_levels(fsi_problem* pb, int B, const StepPar& sp, const int*
       k_elem_jacobian<D, false><<<dim3((g.ncell + jac_cells<D>() - 1) / jac_cells<D>(), B),
                                   jac_cells<D>() * jac_waves<D>(), 0, st>>>(g, sp, U, Uo, pb->Ke, act);
     }
-    k_gather_jacobian<D, S><<<grid1(g.nn, B), TPB, 0, st>>>(g, sp.k, pb->Ke, (S*)lv.J, lv.Dsc, act, 1);
+    k_gather_jacobian<D, S, CJ><<<grid1(g.nn, B), TPB, 0, st>>>(g, sp.k, pb->Ke, (S*)lv.J, lv.Dsc, act, 1);
     if (transpose) {
       // adjoint (2d): the operator of every level becomes the transpose of the free block (B = 1)
-      const size_t bytes = jslice<D>(g.nn) * sizeof(S);
+      const size_t bytes = jslice<D, false>(g.nn) * sizeof(S);
       if (l == L && save_fine) HIPCHK(hipMemcpyAsync(save_fine, lv.J, bytes, hipMemcpyDeviceToDevice, st));
       HIPCHK(hipMemcpyAsync(pb->Jtmp, lv.J, bytes, hipMemcpyDeviceToDevice, st));
       k_transpose_J<double><<<grid1(g.nn, 1), TPB, 0, st>>>(g, sp.k, (const double*)pb->Jtmp, (double*)lv.J, lv.Dsc);
     }
     if (!precond) break;
     if (l >= 1 || D == 3) {
-      k_vanka_factor<D, S><<<dim3((g.ncell + vf_patches<D>() - 1) / vf_patches<D>(), B),
+      k_vanka_factor<D, S, CJ><<<dim3((g.ncell + vf_patches<D>() - 1) / vf_patches<D>(), B),
                              vf_lanes<D>() * vf_patches<D>(), 0, st>>>(g, sp.k, (const S*)lv.J, (S*)lv.Ainv, act);
     } else {
       const size_t lds_f = (size_t)5 * pb->cbs * pb->cbs * sizeof(double);
       const size_t lds_i = (size_t)3 * pb->cbs * pb->cbs * sizeof(double);
-      k_coarse_factor<S><<<B, TPB, lds_f, st>>>(g, sp.k, (const S*)lv.J, pb->cbs, pb->cnsb, pb->cDinv, pb->cW,
+      k_coarse_factor<S, CJ><<<B, TPB, lds_f, st>>>(g, sp.k, (const S*)lv.J, pb->cbs, pb->cnsb, pb->cDinv, pb->cW,
                                                 pb->cL, act);
       k_coarse_inverse<S><<<dim3(pb->cnsb, B), TPB, lds_i, st>>>(g, pb->cbs, pb->cnsb, pb->cDinv, pb->cW, pb->cL,
                                                                  pb->cY, (S*)pb->cAinv, act);
@@ -515,14 +518,14 @@ fsi_status assemble_levels(fsi_problem* pb, int B, const StepPar& sp, const int*
 }
 
 // y = D (b - A x) (or D A x)
-template <int D, class S>
+template <int D, class S, bool CJ>
 void spmv(const Geom& g, int B, double k, const S* J, const S* x, const S* b, const double* Dv, S* y, const int* act,
           hipStream_t st) {
-  k_spmv<D, S><<<dim3((g.nn + 63) / 64, B), spmv_threads<D>(), 0, st>>>(g, k, J, x, b, Dv, y, act);
+  k_spmv<D, S, CJ><<<dim3((g.nn + 63) / 64, B), spmv_threads<D>(), 0, st>>>(g, k, J, x, b, Dv, y, act);
 }
 
 // ------------------------------------------------------------ multigrid
-template <int D, class S>
+template <int D, class S, bool CJ>
 void smooth(fsi_problem* pb, int l, int B, double k, int sweeps, bool zero_first, S* x, const S* b, const int* act,
             hipStream_t st) {
   FSI_DIM(D);
@@ -541,20 +544,20 @@ void smooth(fsi_problem* pb, int l, int B, double k, int sweeps, bool zero_first
       const int nc = color_info<D>(g, c).nc;
       const double vec = 3.0 * g.nn * NC * sizeof(S);
       const double by = zero ? (double)B * ((double)NE * NE * nc * sizeof(S) + 2.0 * g.nn * NC * sizeof(S))
-                             : (double)B * ((double)NSLOT * BLK * g.nn * sizeof(S) + (double)NE * NE * nc * sizeof(S) +
+                             : (double)B * ((double)NSLOT * jblk<D, CJ>() * g.nn * sizeof(S) + (double)NE * NE * nc * sizeof(S) +
                                             vec) +
                                    (double)NPST * g.nn * 8.0;
       ProfScope ps(pb, fine ? F_SMOOTH : F_COARSE_LEV, st, by);
       const int ncopy = (g.nn + NC * 64 - 1) / (NC * 64);
       const S *J = (const S*)lv.J, *Ai = (const S*)lv.Ainv;
       if constexpr (D == 2) {
-        k_vanka_color<D, S, 16><<<dim3((nc + 15) / 16 + ncopy, B), NC * 64, 0, st>>>(
+        k_vanka_color<D, S, 16, CJ><<<dim3((nc + 15) / 16 + ncopy, B), NC * 64, 0, st>>>(
             g, k, c, om, zero ? 1 : 0, J, Ai, b, buf[cur], buf[cur ^ 1], act);
       } else if ((size_t)nc * B >= 8192) {   // 3d: wide blocks where there are cells enough to fill the GPU
-        k_vanka_color<D, S, 32><<<dim3((nc + 31) / 32 + ncopy, B), NC * 64, 0, st>>>(
+        k_vanka_color<D, S, 32, CJ><<<dim3((nc + 31) / 32 + ncopy, B), NC * 64, 0, st>>>(
             g, k, c, om, zero ? 1 : 0, J, Ai, b, buf[cur], buf[cur ^ 1], act);
       } else {
-        k_vanka_color<D, S, 8><<<dim3((nc + 7) / 8 + ncopy, B), NC * 64, 0, st>>>(
+        k_vanka_color<D, S, 8, CJ><<<dim3((nc + 7) / 8 + ncopy, B), NC * 64, 0, st>>>(
             g, k, c, om, zero ? 1 : 0, J, Ai, b, buf[cur], buf[cur ^ 1], act);
       }
       cur ^= 1;
@@ -565,7 +568,7 @@ void smooth(fsi_problem* pb, int l, int B, double k, int sweeps, bool zero_first
 // coarsest level (17 x 5 x 5 nodes at the workloads' level-0 mesh).
 constexpr int COARSEST_SWEEPS_3D = 4;
 
-template <int D, class S>
+template <int D, class S, bool CJ>
 void vcycle(fsi_problem* pb, int B, double k, const S* rhs, S* out, const int* act, hipStream_t st) {
   FSI_DIM(D);
   const int L = pb->nlev - 1;
@@ -575,13 +578,13 @@ void vcycle(fsi_problem* pb, int B, double k, const S* rhs, S* out, const int* a
     Level& lc = pb->lev[l - 1];
     const S* b = (l == L) ? rhs : (const S*)lv.b_;
     S* x = (l == L) ? out : (S*)lv.x_;
-    smooth<D, S>(pb, l, B, k, l == L ? pb->p.vanka_sweeps : pb->p.vanka_sweeps_coarse, true, x, b, act, st);
+    smooth<D, S, CJ>(pb, l, B, k, l == L ? pb->p.vanka_sweeps : pb->p.vanka_sweeps_coarse, true, x, b, act, st);
     const Geom g = lv.geom();
     {
-      const double by = (double)B * ((double)NSLOT * BLK * g.nn * sizeof(S) + 3.0 * g.nn * NC * sizeof(S)) +
+      const double by = (double)B * ((double)NSLOT * jblk<D, CJ>() * g.nn * sizeof(S) + 3.0 * g.nn * NC * sizeof(S)) +
                         (double)NPST * g.nn * 8.0;
       ProfScope ps(pb, l == L ? F_LEVEL_RES : F_COARSE_LEV, st, by);
-      spmv<D, S>(g, B, k, (const S*)lv.J, x, b, nullptr, (S*)lv.r_, act, st);
+      spmv<D, S, CJ>(g, B, k, (const S*)lv.J, x, b, nullptr, (S*)lv.r_, act, st);
     }
     k_restrict<D, S><<<grid1(lc.nn, B), TPB, 0, st>>>(lc.geom(), g, (const S*)lv.r_, (S*)lc.b_, act);
   }
@@ -590,10 +593,10 @@ void vcycle(fsi_problem* pb, int B, double k, const S* rhs, S* out, const int* a
     const int n0 = l0.nn * NC;
     if constexpr (D == 2) {
       ProfScope ps(pb, F_COARSE_SOLVE, st, (double)B * ((double)n0 * n0 + 2.0 * n0) * sizeof(S));
-      k_coarse_gemv<S><<<dim3((n0 + 63) / 64, B), TPB, 0, st>>>(l0.geom(), (const S*)pb->cAinv, (const S*)l0.b_,
-                                                                (S*)l0.x_, act);
+      k_coarse_gemv<S><<<dim3((n0 + 63) / 64, B), CG_THREADS, 0, st>>>(l0.geom(), (const S*)pb->cAinv,
+                                                                       (const S*)l0.b_, (S*)l0.x_, act);
     } else {
-      smooth<D, S>(pb, 0, B, k, COARSEST_SWEEPS_3D, true, (S*)l0.x_, (const S*)l0.b_, act, st);
+      smooth<D, S, CJ>(pb, 0, B, k, COARSEST_SWEEPS_3D, true, (S*)l0.x_, (const S*)l0.b_, act, st);
     }
   }
   for (int l = 1; l <= L; ++l) {
@@ -602,35 +605,36 @@ void vcycle(fsi_problem* pb, int B, double k, const S* rhs, S* out, const int* a
     const S* b = (l == L) ? rhs : (const S*)lv.b_;
     S* x = (l == L) ? out : (S*)lv.x_;
     k_prolong_add<D, S><<<grid1(lv.nn, B), TPB, 0, st>>>(lv.geom(), lc.geom(), (const S*)lc.x_, x, act);
-    smooth<D, S>(pb, l, B, k, l == L ? pb->p.vanka_sweeps : pb->p.vanka_sweeps_coarse, false, x, b, act, st);
+    smooth<D, S, CJ>(pb, l, B, k, l == L ? pb->p.vanka_sweeps : pb->p.vanka_sweeps_coarse, false, x, b, act, st);
   }
 }
 
 // One V-cycle on the finest-level buffers (rhs = pb->tmp, out = pb->w), replayed
 // from a captured graph when no per-kernel profiling is requested.  The graph
 // depends on the batch size and the step size; pointers are fixed per problem.
-template <int D, class S>
+template <int D, class S, bool CJ>
 fsi_status vcycle_run(fsi_problem* pb, int B, double k, hipStream_t st) {
   const bool mixed = sizeof(S) == 4;
   if (!pb->use_graphs || pb->prof.on) {
-    vcycle<D, S>(pb, B, k, (const S*)pb->tmp, (S*)pb->w, pb->gact, st);
+    vcycle<D, S, CJ>(pb, B, k, (const S*)pb->tmp, (S*)pb->w, pb->gact, st);
     HIPCHK(hipGetLastError());
     return FSI_OK;
   }
-  if (!pb->vc_exec || pb->vc_B != B || pb->vc_k != k || pb->vc_mixed != mixed) {
+  if (!pb->vc_exec || pb->vc_B != B || pb->vc_k != k || pb->vc_mixed != mixed || pb->vc_cj != CJ) {
     if (pb->vc_exec) {
       HIPCHK(hipGraphExecDestroy(pb->vc_exec));
       pb->vc_exec = nullptr;
     }
     hipGraph_t graph;
     HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-    vcycle<D, S>(pb, B, k, (const S*)pb->tmp, (S*)pb->w, pb->gact, st);
+    vcycle<D, S, CJ>(pb, B, k, (const S*)pb->tmp, (S*)pb->w, pb->gact, st);
     HIPCHK(hipStreamEndCapture(st, &graph));
     HIPCHK(hipGraphInstantiate(&pb->vc_exec, graph, nullptr, nullptr, 0));
     HIPCHK(hipGraphDestroy(graph));
     pb->vc_B = B;
     pb->vc_k = k;
     pb->vc_mixed = mixed;
+    pb->vc_cj = CJ;
   }
   HIPCHK(hipGraphLaunch(pb->vc_exec, st));
   return FSI_OK;
@@ -640,7 +644,7 @@ fsi_status vcycle_run(fsi_problem* pb, int B, double k, hipStream_t st) {
 // Solve J dx = -R for the slices with nact[b] = 1 (row-scaled system D J dx = -D R),
 // right-preconditioned FGMRES(R) with classical Gram-Schmidt applied twice; the
 // preconditioner is one multigrid V-cycle.  The solution (type S) goes to pb->xs.
-template <int D, class S>
+template <int D, class S, bool CJ>
 fsi_status fgmres(fsi_problem* pb, int B, double k, std::vector<int>& kits, hipStream_t st) {
   FSI_DIM(D);
   Level& F = pb->lev[pb->nlev - 1];
@@ -668,7 +672,7 @@ fsi_status fgmres(fsi_problem* pb, int B, double k, std::vector<int>& kits, hipS
       k_scale_rhs<S><<<grid1(n, B), TPB, 0, st>>>(n, pb->Res, F.Dsc, V, vb, pb->gact);
     } else {
       k_scale_rhs<S><<<grid1(n, B), TPB, 0, st>>>(n, pb->Res, nullptr, tmp, (size_t)n, pb->gact);
-      spmv<D, S>(g, B, k, (const S*)F.J, xs, tmp, F.Dsc, w, pb->gact, st);
+      spmv<D, S, CJ>(g, B, k, (const S*)F.J, xs, tmp, F.Dsc, w, pb->gact, st);
       k_scale<S><<<grid1(n, B), TPB, 0, st>>>(n, w, (size_t)n, V, vb, nullptr, 0, 2, pb->gact);
     }
     k_multidot<S><<<dim3(nchunk, B), RED_T, 0, st>>>(n, 1, V, vb, V, vb, 0, chunk, pb->partial, nchunk, pb->gact);
@@ -689,14 +693,14 @@ fsi_status fgmres(fsi_problem* pb, int B, double k, std::vector<int>& kits, hipS
       S* Zj = Z + (size_t)j * n;
       // Z_j = M^{-1} (V_j / D);  a = D J Z_j  (the new Arnoldi vector a lives in tmp)
       k_unscale<S><<<grid1(n, B), TPB, 0, st>>>(n, Vj, vb, F.Dsc, tmp, pb->gact);
-      CHK(vcycle_run<D, S>(pb, B, k, st));
+      CHK(vcycle_run<D, S, CJ>(pb, B, k, st));
       k_scale<S><<<grid1(n, B), TPB, 0, st>>>(n, w, (size_t)n, Zj, zb, nullptr, 0, 2, pb->gact);
       S* a = tmp;
       {
         ProfScope ps(pb, F_GMRES_SPMV, st,
-                     (double)B * ((double)NSLOT * BLK * F.nn * sizeof(S) + 2.0 * n * sizeof(S) + n * 8.0) +
+                     (double)B * ((double)NSLOT * jblk<D, CJ>() * F.nn * sizeof(S) + 2.0 * n * sizeof(S) + n * 8.0) +
                          (double)NPST * F.nn * 8.0);
-        spmv<D, S>(g, B, k, (const S*)F.J, w, nullptr, F.Dsc, a, pb->gact, st);
+        spmv<D, S, CJ>(g, B, k, (const S*)F.J, w, nullptr, F.Dsc, a, pb->gact, st);
       }
       // classical Gram-Schmidt, twice
       k_multidot<S><<<dim3(nchunk, B), RED_T, 0, st>>>(n, j + 1, a, (size_t)n, V, vb, (size_t)n, chunk, pb->partial,
@@ -767,8 +771,8 @@ fsi_status newton_solve_step(fsi_problem* pb, int B, const StepPar& sp, std::vec
     const int k0 = rs.krylov[0];
     HIPCHK(hipMemcpyAsync(pb->nact, nact.data(), B * sizeof(int), hipMemcpyHostToDevice, st));
     CHK(residual<D>(pb, B, sp, pb->U, pb->Uold, pb->Res, pb->nact, st));
-    CHK(assemble_levels<D, S>(pb, B, sp, pb->nact, st, it == 1 || pb->p.precond_lag == 0));
-    fsi_status ls = fgmres<D, S>(pb, B, sp.k, rs.krylov, st);
+    CHK(assemble_levels<D, S, true>(pb, B, sp, pb->nact, st, it == 1 || pb->p.precond_lag == 0));
+    fsi_status ls = fgmres<D, S, true>(pb, B, sp.k, rs.krylov, st);
     if (ls != FSI_OK && ls != FSI_ERR_LINEAR) return ls;
     k_newton_update<D, S><<<dim3(pb->nchunk_n, B), RED_T, 0, st>>>(nn, pb->U, (const S*)pb->xs, pb->chunk_n, pb->npart,
                                                                  pb->nchunk_n, pb->nact);
@@ -937,9 +941,9 @@ fsi_status adjoint_alloc(fsi_problem* pb, size_t nstates, int N) {
   Level& F = pb->lev[pb->nlev - 1];
   const size_t nd = (size_t)F.nn * NC;
   if (!pb->Jtmp) {
-    CHK(dalloc(pb, &pb->Jtmp, jslice<2>(F.nn)));
-    CHK(dalloc(pb, &pb->Jcopy, jslice<2>(F.nn)));
-    CHK(dalloc(pb, &pb->Jold, jslice<2>(F.nn)));
+    CHK(dalloc(pb, &pb->Jtmp, jslice<2, false>(F.nn)));
+    CHK(dalloc(pb, &pb->Jcopy, jslice<2, false>(F.nn)));
+    CHK(dalloc(pb, &pb->Jold, jslice<2, false>(F.nn)));
     CHK(dalloc(pb, &pb->lam, nd));
     CHK(dalloc(pb, &pb->lamn, nd));
     CHK(dalloc(pb, &pb->arhs, nd));
@@ -1031,18 +1035,18 @@ fsi_status adjoint_run(fsi_problem* pb, double T, int N, int m, const double* U0
       k_elem_jacobian<2, true><<<dim3((g.ncell + jac_cells<2>() - 1) / jac_cells<2>(), 1),
                                  jac_cells<2>() * jac_waves<2>(), 0, st>>>(
           g, sp, cur(s + 1), prev(s + 1), pb->Ke, nullptr);
-      k_gather_jacobian<2, double><<<grid1(g.nn, 1), TPB, 0, st>>>(g, k, pb->Ke, pb->Jold, nullptr, nullptr, 0);
+      k_gather_jacobian<2, double, false><<<grid1(g.nn, 1), TPB, 0, st>>>(g, k, pb->Ke, pb->Jold, nullptr, nullptr, 0);
       k_spmv_T<double><<<grid1(g.nn, 1), TPB, 0, st>>>(g, k, pb->Jold, pb->lamn, pb->ay, 0);
       k_daxpy<<<64, TPB, 0, st>>>(nd, -1.0, pb->ay, pb->arhs);
     }
     // transposed multigrid hierarchy at (U^s, U^{s-1})
     HIPCHK(hipMemcpyAsync(pb->U, cur(s), nd * sizeof(double), hipMemcpyDeviceToDevice, st));
     HIPCHK(hipMemcpyAsync(pb->Uold, prev(s), nd * sizeof(double), hipMemcpyDeviceToDevice, st));
-    CHK(assemble_levels<2, double>(pb, 1, sp, pb->nact, st, true, true, pb->Jcopy));
+    CHK(assemble_levels<2, double, false>(pb, 1, sp, pb->nact, st, true, true, pb->Jcopy));
     // free unknowns: Krylov solve with the Dirichlet entries of the right-hand side removed
     k_adjoint_rhs<<<grid1(g.nn, 1), TPB, 0, st>>>(g, pb->arhs, pb->Res);
     HIPCHK(hipGetLastError());
-    fsi_status ls = fgmres<2, double>(pb, 1, k, kits, st);
+    fsi_status ls = fgmres<2, double, false>(pb, 1, k, kits, st);
     if (ls != FSI_OK) { ret = ls; break; }
     HIPCHK(hipMemcpyAsync(pb->lam, pb->xs, nd * sizeof(double), hipMemcpyDeviceToDevice, st));
     // Dirichlet unknowns: lam_D = rhs_D - (J^T lam)_D
@@ -1190,9 +1194,11 @@ fsi_status fsi_setup(const fsi_params* prm, fsi_problem** out) {
   A_(dalloc(pb, &pb->npart, (size_t)B * 6 * pb->nchunk_n));
   A_(dalloc(pb, &pb->nmax, (size_t)B * 6));
 #undef A_
-  if (hipFuncSetAttribute((const void*)k_coarse_factor<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+  if (hipFuncSetAttribute((const void*)k_coarse_factor<double, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                           5 * pb->cbs * pb->cbs * sizeof(double)) != hipSuccess ||
-      hipFuncSetAttribute((const void*)k_coarse_factor<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+      hipFuncSetAttribute((const void*)k_coarse_factor<float, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          5 * pb->cbs * pb->cbs * sizeof(double)) != hipSuccess ||
+      hipFuncSetAttribute((const void*)k_coarse_factor<double, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                           5 * pb->cbs * pb->cbs * sizeof(double)) != hipSuccess) {
     fsi_destroy(pb);
     return FSI_ERR_HIP;
@@ -1401,12 +1407,12 @@ fsi_status debug_apply(fsi_problem* pb, int B, const double* U, const double* Uo
   HIPCHK(hipMemcpyAsync(pb->tdev, t, B * sizeof(double), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(pb->U, U, B * ndof * sizeof(double), hipMemcpyDeviceToDevice, st));
   HIPCHK(hipMemcpyAsync(pb->Uold, Uo, B * ndof * sizeof(double), hipMemcpyDeviceToDevice, st));
-  CHK(assemble_levels<D, S>(pb, B, sp, nullptr, st));
+  CHK(assemble_levels<D, S, true>(pb, B, sp, nullptr, st));
   k_convert<double, S><<<1024, TPB, 0, st>>>(B * ndof, X, (S*)pb->tmp);
   if (what == 0)
-    spmv<D, S>(F.geom(), B, k, (const S*)F.J, (const S*)pb->tmp, nullptr, nullptr, (S*)pb->w, nullptr, st);
+    spmv<D, S, true>(F.geom(), B, k, (const S*)F.J, (const S*)pb->tmp, nullptr, nullptr, (S*)pb->w, nullptr, st);
   else
-    vcycle<D, S>(pb, B, k, (const S*)pb->tmp, (S*)pb->w, nullptr, st);
+    vcycle<D, S, true>(pb, B, k, (const S*)pb->tmp, (S*)pb->w, nullptr, st);
   k_convert<S, double><<<1024, TPB, 0, st>>>(B * ndof, (const S*)pb->w, Y);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(st));

@@ -120,17 +120,44 @@ __host__ __device__ inline int pslot_of(int dx, int dy, int dz) {
 }
 
 // Jacobian storage: per slice, nodes are grouped in tiles of 64; a tile holds its
-// NSLOT x BLK block-stencil coefficients as runs of 64 consecutive values, so
-// one wave streams one contiguous array.
+// NSLOT x (stored entries per block) block-stencil coefficients as runs of 64
+// consecutive values, so one wave streams one contiguous array.
+//
+// Two block layouts (CJ):
+//  - full: all NC x NC entries, row-major (the transposed adjoint system);
+//  - compressed: the structural nonzeros of the step Jacobian only.  A
+//    displacement row (harmonic extension in the fluid, kinematic equation in
+//    the solid, identity when Dirichlet) depends on v_i and u_i of its own
+//    component i only, so it stores 2 entries (v_i, u_i); velocity and
+//    pressure rows store all NC.  2d: 19 of 25 entries, 3d: 34 of 49.
 constexpr int JT = 64;
 __host__ __device__ inline int nn_pad(int nn) { return (nn + JT - 1) / JT * JT; }
-template <int D>
-__host__ __device__ inline size_t jslice(int nn) {
-  return (size_t)Dm<D>::NSLOT * Dm<D>::BLK * nn_pad(nn);
+template <int D, bool CJ>
+__host__ __device__ constexpr int jblk() {
+  return CJ ? D * (2 * D + 1) + 2 * D + (2 * D + 1) : (2 * D + 1) * (2 * D + 1);
 }
-template <int D>
+// first stored entry of row r
+template <int D, bool CJ>
+__host__ __device__ constexpr int jrow_off(int r) {
+  return !CJ ? r * (2 * D + 1)
+             : (r < D ? r * (2 * D + 1) : (r < 2 * D ? D * (2 * D + 1) + 2 * (r - D) : D * (2 * D + 1) + 2 * D));
+}
+// stored index of entry (r, c) of a block, -1 for a structural zero of the compressed layout
+template <int D, bool CJ>
+__host__ __device__ inline int jentry(int r, int c) {
+  if (!CJ || r < D || r == 2 * D) return jrow_off<D, CJ>(r) + c;
+  if (c == r - D) return jrow_off<D, CJ>(r);
+  if (c == r) return jrow_off<D, CJ>(r) + 1;
+  return -1;
+}
+template <int D, bool CJ>
+__host__ __device__ inline size_t jslice(int nn) {
+  return (size_t)Dm<D>::NSLOT * jblk<D, CJ>() * nn_pad(nn);
+}
+template <int D, bool CJ>
 __host__ __device__ inline size_t jidx(int node, int s, int e) {
-  return (size_t)(node / JT) * (Dm<D>::NSLOT * Dm<D>::BLK * JT) + (size_t)(s * Dm<D>::BLK + e) * JT + (node % JT);
+  return (size_t)(node / JT) * (Dm<D>::NSLOT * jblk<D, CJ>() * JT) + (size_t)(s * jblk<D, CJ>() + e) * JT +
+         (node % JT);
 }
 
 // Launch shapes: the SpMV and the fused Vanka pass run one wave per row of a
@@ -142,6 +169,8 @@ template <int D>
 __host__ __device__ constexpr int vf_lanes() { return D == 2 ? 32 : 64; }    // lanes per patch (>= NE)
 template <int D>
 __host__ __device__ constexpr int vf_patches() { return D == 2 ? 8 : 1; }    // patches per factor block
+// coarsest-level dense product (2d): threads per block of 64 rows
+constexpr int CG_THREADS = 512;
 // element Jacobian: blocks of jac_cells cells, jac_waves threads per cell
 template <int D>
 __host__ __device__ constexpr int jac_cells() { return D == 2 ? 64 : 128; }

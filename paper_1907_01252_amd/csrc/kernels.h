@@ -1,6 +1,7 @@
 // Declarations of the HIP kernels (defined and instantiated in assemble.hip and
 // solver.hip) for the host driver.  D is the space dimension (2 or 3), S the
-// storage type of the linear solve.
+// storage type of the linear solve, CJ the Jacobian block layout (compressed
+// or full).
 #pragma once
 #include "fsi_internal.h"
 
@@ -15,7 +16,7 @@ __global__ void k_apply_dirichlet(Geom g, StepPar sp, double* U, const double* t
 template <int D>
 __global__ void k_gather_residual(Geom g, StepPar sp, const double* Re, const double* U, const double* t, double* R,
                                   const int* active);
-template <int D, class S>
+template <int D, class S, bool CJ>
 __global__ void k_gather_jacobian(Geom g, double k, const double* Ke, S* J, double* Dsc, const int* active,
                                   int dir_identity);
 template <int D>
@@ -36,12 +37,12 @@ __global__ void k_fix_dirichlet(Geom g, double* lam, const double* rhs, const do
 __global__ void k_adjoint_rhs(Geom g, const double* rhs, double* Res);
 __global__ void k_daxpy(size_t n, double a, const double* x, double* y);
 
-template <int D, class S>
+template <int D, class S, bool CJ>
 __global__ void k_spmv(Geom g, double k, const S* J, const S* x, const S* b, const double* Dsc, S* y,
                        const int* active);
-template <int D, class S>
+template <int D, class S, bool CJ>
 __global__ void k_vanka_factor(Geom g, double k, const S* J, S* Ainv, const int* active);
-template <int D, class S, int VC>
+template <int D, class S, int VC, bool CJ>
 __global__ void k_vanka_color(Geom g, double k, int color, S omega, int zero_in, const S* J, const S* Ainv,
                               const S* b, const S* xo, S* xn, const int* active);
 template <int D, class S>
@@ -49,7 +50,7 @@ __global__ void k_restrict(Geom gc, Geom gf, const S* rf, S* bc, const int* acti
 template <int D, class S>
 __global__ void k_prolong_add(Geom gf, Geom gc, const S* xc, S* xf, const int* active);
 // 2d coarsest level
-template <class S>
+template <class S, bool CJ>
 __global__ void k_coarse_factor(Geom g, double k, const S* J, int bsz, int nsb, double* Dinv, double* W, double* Lb,
                                 const int* active);
 template <class S>

@@ -10,19 +10,28 @@ namespace fsi {
 
 using D2 = Dm<2>;
 
-// Neighbour node offsets of the 3^D block stencil of node (i, j, k), without
-// branches: an out-of-mesh neighbour maps onto the node itself.  The Jacobian
-// stores zeros in those slots (and the pressure stencil for such pairs), so
-// the product adds exactly nothing and every load of a row can be in flight
-// at once.
+// Neighbour node offsets of the 3^D block stencil of node (i, j, k), per axis
+// (offset index 0, 1, 2 for -1, 0, +1), without branches: an out-of-mesh
+// neighbour maps onto the node itself.  The Jacobian stores zeros in those
+// slots (and the pressure stencil for such pairs), so the product adds exactly
+// nothing and every load of a row can be in flight at once.
+struct Nbr {
+  int ox[3], oy[3], oz[3];
+};
 template <int D>
-__device__ inline void slot_offsets(const Geom& g, int i, int j, int k, int (&off)[Dm<D>::NSLOT]) {
+__device__ inline Nbr nbr_offsets(const Geom& g, int i, int j, int k) {
   const int W = g.nx + 1, P = W * (g.ny + 1);
-  const int o[3][3] = {{i > 0 ? -1 : 0, 0, i < g.nx ? 1 : 0},
-                       {j > 0 ? -W : 0, 0, j < g.ny ? W : 0},
-                       {k > 0 ? -P : 0, 0, k < g.nz ? P : 0}};
-#pragma unroll
-  for (int s = 0; s < Dm<D>::NSLOT; ++s) off[s] = o[0][s % 3] + o[1][(s / 3) % 3] + (D == 3 ? o[2][s / 9] : 0);
+  Nbr o;
+  o.ox[0] = i > 0 ? -1 : 0;
+  o.ox[1] = 0;
+  o.ox[2] = i < g.nx ? 1 : 0;
+  o.oy[0] = j > 0 ? -W : 0;
+  o.oy[1] = 0;
+  o.oy[2] = j < g.ny ? W : 0;
+  o.oz[0] = D == 3 && k > 0 ? -P : 0;
+  o.oz[1] = 0;
+  o.oz[2] = D == 3 && k < g.nz ? P : 0;
+  return o;
 }
 
 // k * sum_q pst[q][n] x_p(neighbour q) over the 5^D pressure stencil (clamped
@@ -44,6 +53,38 @@ __device__ inline S pst_row(const Geom& g, double k, int n, int i, int j, int kk
   return (S)k * ap;
 }
 
+// Row r of the block stencil at node n times x: the sum over the slots of the
+// stored entries of row r.  In the compressed layout a displacement row holds
+// (v_i, u_i) only.  In 3d the planes of the stencil are taken one at a time, so
+// that the loads of a plane are in flight together within the register budget.
+template <int D, class S, bool CJ>
+__device__ inline S stencil_row(const S* __restrict__ jb, const S* __restrict__ xb, int n, int r, const Nbr& nb) {
+  FSI_DIM(D);
+  S acc = 0;
+  const int e0 = jrow_off<D, CJ>(r);
+  const bool urow = CJ && r >= D && r < 2 * D;
+  constexpr int NZ = D == 3 ? 3 : 1;
+#pragma unroll 1
+  for (int sz = 0; sz < NZ; ++sz) {
+    const int oz = sz == 0 ? nb.oz[0] : (sz == 1 ? 0 : nb.oz[2]);
+#pragma unroll
+    for (int sy = 0; sy < 3; ++sy)
+#pragma unroll
+      for (int sx = 0; sx < 3; ++sx) {
+        const int s = sx + 3 * sy + 9 * sz;
+        const S* xv = xb + (size_t)(n + nb.ox[sx] + nb.oy[sy] + oz) * NC;
+        if (urow) {
+          acc += jb[jidx<D, CJ>(n, s, e0)] * xv[r - D];
+          acc += jb[jidx<D, CJ>(n, s, e0 + 1)] * xv[r];
+        } else {
+#pragma unroll
+          for (int c = 0; c < NC; ++c) acc += jb[jidx<D, CJ>(n, s, e0 + c)] * xv[c];
+        }
+      }
+  }
+  return acc;
+}
+
 // ------------------------------------------------------------------ SpMV
 // y = D (A x)            (b == nullptr)
 // y = D (b - A x)        (b != nullptr)
@@ -53,7 +94,7 @@ __device__ inline S pst_row(const Geom& g, double k, int n, int i, int j, int kk
 // wave r forming row r, so the rows of a node read its neighbours' x through
 // the same CU's cache, and a wave streams 64 consecutive values of each
 // coefficient run of the tiled layout.
-template <int D, class S>
+template <int D, class S, bool CJ>
 __global__ void __launch_bounds__(Dm<D>::NC * 64) k_spmv(Geom g, double k, const S* __restrict__ J,
                                                          const S* __restrict__ x, const S* __restrict__ b,
                                                          const double* __restrict__ Dsc, S* __restrict__ y,
@@ -65,17 +106,9 @@ __global__ void __launch_bounds__(Dm<D>::NC * 64) k_spmv(Geom g, double k, const
   if (n >= g.nn || (active && !active[bs])) return;
   int i, j, kk;
   node_ijk<D>(g, n, i, j, kk);
-  const S* jb = J + (size_t)bs * jslice<D>(g.nn);
+  const S* jb = J + (size_t)bs * jslice<D, CJ>(g.nn);
   const S* xb = x + (size_t)bs * g.nn * NC;
-  int off[NSLOT];
-  slot_offsets<D>(g, i, j, kk, off);
-  S acc = 0;
-#pragma unroll
-  for (int s = 0; s < NSLOT; ++s) {
-    const S* xv = xb + (size_t)(n + off[s]) * NC;
-#pragma unroll
-    for (int c = 0; c < NC; ++c) acc += jb[jidx<D>(n, s, NC * r + c)] * xv[c];
-  }
+  S acc = stencil_row<D, S, CJ>(jb, xb, n, r, nbr_offsets<D>(g, i, j, kk));
   if (r == PC) acc += pst_row<D, S>(g, k, n, i, j, kk, xb);
   const size_t o = ((size_t)bs * g.nn + n) * NC + r;
   S v = b ? b[o] - acc : acc;
@@ -93,8 +126,8 @@ __global__ void k_transpose_J(Geom g, double k, const S* __restrict__ J, S* __re
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= g.nn) return;
   const int i = n % (g.nx + 1), j = n / (g.nx + 1);
-  const S* jb = J + (size_t)bs * jslice<2>(g.nn);
-  S* jt = Jt + (size_t)bs * jslice<2>(g.nn);
+  const S* jb = J + (size_t)bs * jslice<2, false>(g.nn);
+  S* jt = Jt + (size_t)bs * jslice<2, false>(g.nn);
   const uint8_t m = g.dmask[n];
   double rmax[D2::NC] = {0, 0, 0, 0, 0};
   for (int s = 0; s < D2::NSLOT; ++s) {
@@ -104,9 +137,9 @@ __global__ void k_transpose_J(Geom g, double k, const S* __restrict__ J, S* __re
     const int nb = ok ? ii + (g.nx + 1) * jj : 0;
     for (int r = 0; r < D2::NC; ++r)
       for (int c = 0; c < D2::NC; ++c) {
-        double v = ok ? (double)jb[jidx<2>(nb, slot_of<2>(-dx, -dy, 0), D2::NC * c + r)] : 0.0;
+        double v = ok ? (double)jb[jidx<2, false>(nb, slot_of<2>(-dx, -dy, 0), D2::NC * c + r)] : 0.0;
         if (m & (1u << r)) v = (s == 4 && c == r) ? 1.0 : 0.0;
-        jt[jidx<2>(n, s, D2::NC * r + c)] = (S)v;
+        jt[jidx<2, false>(n, s, D2::NC * r + c)] = (S)v;
         rmax[r] = fmax(rmax[r], fabs(v));
       }
   }
@@ -125,7 +158,7 @@ __global__ void k_spmv_T(Geom g, double k, const S* __restrict__ J, const S* __r
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= g.nn) return;
   const int i = n % (g.nx + 1), j = n / (g.nx + 1);
-  const S* jb = J + (size_t)bs * jslice<2>(g.nn);
+  const S* jb = J + (size_t)bs * jslice<2, false>(g.nn);
   const S* xb = x + (size_t)bs * g.nn * D2::NC;
   S acc[D2::NC] = {0, 0, 0, 0, 0};
   for (int s = 0; s < D2::NSLOT; ++s) {
@@ -136,7 +169,7 @@ __global__ void k_spmv_T(Geom g, double k, const S* __restrict__ J, const S* __r
     const int mr = ii + (g.nx + 1) * jj;
     for (int r = 0; r < D2::NC; ++r) {
       const S xr = xb[(size_t)mr * D2::NC + r];
-      for (int c = 0; c < D2::NC; ++c) acc[c] += jb[jidx<2>(mr, s, D2::NC * r + c)] * xr;
+      for (int c = 0; c < D2::NC; ++c) acc[c] += jb[jidx<2, false>(mr, s, D2::NC * r + c)] * xr;
     }
   }
   if (with_pst && !(g.dmask[n] & dm_p<2>())) {
@@ -184,7 +217,7 @@ __global__ void k_adjoint_rhs(Geom g, const double* __restrict__ rhs, double* __
 // the (unscaled) pivot row.  Rows are scaled by their pivots at the end, which
 // gives the same inverse as scaling at each step.  Ainv is stored per colour:
 // Ainv[b][off_c*NE*NE + e*nc_c + idx], e = NE * row + column.
-template <int D, class S>
+template <int D, class S, bool CJ>
 __global__ void __launch_bounds__(vf_lanes<D>() * vf_patches<D>()) k_vanka_factor(Geom g, double k,
                                                                                   const S* __restrict__ J,
                                                                                   S* __restrict__ Ainv,
@@ -205,12 +238,15 @@ __global__ void __launch_bounds__(vf_lanes<D>() * vf_patches<D>()) k_vanka_facto
     const int ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
     const int na = node_at(g, ci + ax, cj + ay, ck + az);
     if (live) {
-      const S* jb = J + (size_t)bs * jslice<D>(g.nn);
+      const S* jb = J + (size_t)bs * jslice<D, CJ>(g.nn);
       const bool pst_row = (rc == PC) && !(g.dmask[na] & dm_p<D>());
       for (int bb = 0; bb < NL; ++bb) {
         const int dx = (bb & 1) - ax, dy = ((bb >> 1) & 1) - ay, dz = ((bb >> 2) & 1) - az;
         const int s = slot_of<D>(dx, dy, dz);
-        for (int c = 0; c < NC; ++c) Mp[lane][NC * bb + c] = (double)jb[jidx<D>(na, s, NC * rc + c)];
+        for (int c = 0; c < NC; ++c) {
+          const int e = jentry<D, CJ>(rc, c);
+          Mp[lane][NC * bb + c] = e >= 0 ? (double)jb[jidx<D, CJ>(na, s, e)] : 0.0;
+        }
         if (pst_row) Mp[lane][NC * bb + PC] += k * g.pst[(size_t)pslot_of<D>(dx, dy, dz) * g.nn + na];
       }
     } else {
@@ -268,7 +304,7 @@ __global__ void __launch_bounds__(vf_lanes<D>() * vf_patches<D>()) k_vanka_facto
 // NE patch residuals meet in LDS; the same thread then forms patch rows
 // NC a + r of Ainv_P r_P.  Extra blocks past the patch blocks copy the
 // uncovered nodes.
-template <int D, class S, int VC>
+template <int D, class S, int VC, bool CJ>
 __global__ void __launch_bounds__(Dm<D>::NC * 64) k_vanka_color(Geom g, double k, int color, S omega, int zero_in,
                                                                 const S* __restrict__ J, const S* __restrict__ Ainv,
                                                                 const S* __restrict__ b, const S* __restrict__ xo,
@@ -318,15 +354,8 @@ __global__ void __launch_bounds__(Dm<D>::NC * 64) k_vanka_color(Geom g, double k
       if (!zero_in) {
         int i, j, kk;
         node_ijk<D>(g, n, i, j, kk);
-        const S* jb = J + (size_t)bs * jslice<D>(g.nn);
-        int off[NSLOT];
-        slot_offsets<D>(g, i, j, kk, off);
-#pragma unroll
-        for (int s = 0; s < NSLOT; ++s) {
-          const S* xv = xob + (size_t)(n + off[s]) * NC;
-#pragma unroll
-          for (int c = 0; c < NC; ++c) acc += jb[jidx<D>(n, s, NC * r + c)] * xv[c];
-        }
+        const S* jb = J + (size_t)bs * jslice<D, CJ>(g.nn);
+        acc = stencil_row<D, S, CJ>(jb, xob, n, r, nbr_offsets<D>(g, i, j, kk));
         if (r == PC) acc += pst_row<D, S>(g, k, n, i, j, kk, xob);
       }
       rs[NC * a + r][jc] = b[((size_t)bs * g.nn + n) * NC + r] - acc;
@@ -423,7 +452,7 @@ __global__ void k_prolong_add(Geom gf, Geom gc, const S* __restrict__ xc, S* __r
 // W_K = Delta_K^{-1} U_K.  Stored per slice: Dinv_K, W_K, L_K (bs x bs each).
 // From the factors the explicit inverse is formed once per factorisation, so
 // each coarse solve of a V-cycle is one dense matrix-vector product.
-template <class S>
+template <class S, bool CJ>
 __device__ inline double coarse_entry(const Geom& g, double k, const S* jb, int K, int l, int K2, int l2) {
   // row: super-column K local l; column: super-column K2 local l2
   const int r = l % D2::NC, nl = l / D2::NC, colx = nl / (g.ny + 1), jr = nl % (g.ny + 1);
@@ -433,7 +462,8 @@ __device__ inline double coarse_entry(const Geom& g, double k, const S* jb, int 
   const int dx = ic - ir, dy = jc - jr;
   const int n = ir + (g.nx + 1) * jr;
   double v = 0.0;
-  if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1) v = (double)jb[jidx<2>(n, slot_of<2>(dx, dy, 0), D2::NC * r + c)];
+  const int e = jentry<2, CJ>(r, c);
+  if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && e >= 0) v = (double)jb[jidx<2, CJ>(n, slot_of<2>(dx, dy, 0), e)];
   if (r == 4 && c == 4 && dx >= -2 && dx <= 2 && dy >= -2 && dy <= 2 && !(g.dmask[n] & dm_p<2>()))
     v += k * g.pst[(size_t)pslot_of<2>(dx, dy, 0) * g.nn + n];
   return v;
@@ -460,7 +490,7 @@ __device__ inline void tile_gemm(int bsz, const double* A, const double* Bm, dou
 // One workgroup per slice.  LDS: [Delta | I] (bs x 2bs), L_K, U_K and W_{K-1}
 // (bs x bs each).  Gauss-Jordan with partial pivoting: wave 0 finds the pivot and
 // the row factors, then every thread owns columns of [Delta | I] for the update.
-template <class S>
+template <class S, bool CJ>
 __global__ void __launch_bounds__(256) k_coarse_factor(Geom g, double k, const S* __restrict__ J, int bsz, int nsb,
                                                        double* __restrict__ Dinv, double* __restrict__ W,
                                                        double* __restrict__ Lb, const int* __restrict__ active) {
@@ -468,7 +498,7 @@ __global__ void __launch_bounds__(256) k_coarse_factor(Geom g, double k, const S
   const int bs = blockIdx.x;
   if (active && !active[bs]) return;
   const int tid = threadIdx.x, nt = blockDim.x;
-  const S* jb = J + (size_t)bs * jslice<2>(g.nn);
+  const S* jb = J + (size_t)bs * jslice<2, CJ>(g.nn);
   const int w2 = 2 * bsz;
   const int B2i = bsz * bsz;
   double* M = lds;                  // bsz x 2bsz
@@ -487,10 +517,10 @@ __global__ void __launch_bounds__(256) k_coarse_factor(Geom g, double k, const S
   for (int K = 0; K < nsb; ++K) {
     for (int e = tid; e < B2i; e += nt) {
       const int r = e / bsz, c = e % bsz;
-      M[r * w2 + c] = coarse_entry<S>(g, k, jb, K, r, K, c);
+      M[r * w2 + c] = coarse_entry<S, CJ>(g, k, jb, K, r, K, c);
       M[r * w2 + bsz + c] = (r == c) ? 1.0 : 0.0;
-      if (K > 0) Lt[e] = coarse_entry<S>(g, k, jb, K, r, K - 1, c);
-      if (K < nsb - 1) Ut[e] = coarse_entry<S>(g, k, jb, K, r, K + 1, c);
+      if (K > 0) Lt[e] = coarse_entry<S, CJ>(g, k, jb, K, r, K - 1, c);
+      if (K < nsb - 1) Ut[e] = coarse_entry<S, CJ>(g, k, jb, K, r, K + 1, c);
     }
     for (int e = tid; e < bsz; e += nt) usedf[e] = 0;
     __syncthreads();
@@ -604,25 +634,42 @@ __global__ void __launch_bounds__(256) k_coarse_inverse(Geom g, int bsz, int nsb
   }
 }
 
-// x = A^{-1} b on the coarsest level: a block owns 64 rows; its 4 waves split
+// x = A^{-1} b on the coarsest level: a block owns 64 rows; its waves split
 // the columns (coalesced column-major reads) and reduce through LDS.
 template <class S>
-__global__ void __launch_bounds__(256) k_coarse_gemv(Geom g, const S* __restrict__ AinvS, const S* __restrict__ bvec,
-                                                     S* __restrict__ xvec, const int* __restrict__ active) {
+__global__ void __launch_bounds__(CG_THREADS) k_coarse_gemv(Geom g, const S* __restrict__ AinvS,
+                                                            const S* __restrict__ bvec, S* __restrict__ xvec,
+                                                            const int* __restrict__ active) {
+  // 64 rows per block; wave w takes the columns j = w (mod CG_WAVES) with four
+  // independent partial sums, so each lane keeps four loads in flight
+  constexpr int W = CG_THREADS / 64;
   const int bs = blockIdx.y;
   if (active && !active[bs]) return;
   const int n0 = g.nn * D2::NC;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int i = blockIdx.x * 64 + lane;
-  __shared__ S part[4][64];
+  __shared__ S part[W][64];
   const S* bb = bvec + (size_t)bs * n0;
   const S* A = AinvS + (size_t)bs * n0 * n0;
-  S acc = 0;
-  if (i < n0)
-    for (int j = wv; j < n0; j += 4) acc += A[(size_t)j * n0 + i] * bb[j];
-  part[wv][lane] = acc;
+  S a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+  if (i < n0) {
+    int j = wv;
+    for (; j + 3 * W < n0; j += 4 * W) {
+      a0 += A[(size_t)j * n0 + i] * bb[j];
+      a1 += A[(size_t)(j + W) * n0 + i] * bb[j + W];
+      a2 += A[(size_t)(j + 2 * W) * n0 + i] * bb[j + 2 * W];
+      a3 += A[(size_t)(j + 3 * W) * n0 + i] * bb[j + 3 * W];
+    }
+    for (; j < n0; j += W) a0 += A[(size_t)j * n0 + i] * bb[j];
+  }
+  part[wv][lane] = (a0 + a1) + (a2 + a3);
   __syncthreads();
-  if (wv == 0 && i < n0) xvec[(size_t)bs * n0 + i] = part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane];
+  if (wv == 0 && i < n0) {
+    S x = part[0][lane];
+#pragma unroll
+    for (int w = 1; w < W; ++w) x += part[w][lane];
+    xvec[(size_t)bs * n0 + i] = x;
+  }
 }
 
 // ------------------------------------------------------------ FGMRES pieces
@@ -970,19 +1017,20 @@ __global__ void k_convert(size_t n, const A* __restrict__ X, B2* __restrict__ Y)
 
 // explicit instantiations
 #define FSI_INST_DS(D, S)                                                                                         \
-  template __global__ void k_spmv<D, S>(Geom, double, const S*, const S*, const S*, const double*, S*,           \
-                                        const int*);                                                             \
-  template __global__ void k_vanka_factor<D, S>(Geom, double, const S*, S*, const int*);                         \
-  template __global__ void k_vanka_color<D, S, (D == 2 ? 16 : 32)>(Geom, double, int, S, int, const S*,         \
-                                                                   const S*, const S*, const S*, S*, const int*); \
+  template __global__ void k_spmv<D, S, true>(Geom, double, const S*, const S*, const S*, const double*, S*,     \
+                                              const int*);                                                       \
+  template __global__ void k_vanka_factor<D, S, true>(Geom, double, const S*, S*, const int*);                   \
+  template __global__ void k_vanka_color<D, S, (D == 2 ? 16 : 32), true>(Geom, double, int, S, int, const S*,   \
+                                                                         const S*, const S*, const S*, S*,      \
+                                                                         const int*);                            \
   template __global__ void k_restrict<D, S>(Geom, Geom, const S*, S*, const int*);                               \
   template __global__ void k_prolong_add<D, S>(Geom, Geom, const S*, S*, const int*);                            \
   template __global__ void k_newton_update<D, S>(int, double*, const S*, int, double*, int, const int*);
 #define FSI_INST_S(S)                                                                                             \
   FSI_INST_DS(2, S)                                                                                               \
   FSI_INST_DS(3, S)                                                                                               \
-  template __global__ void k_coarse_factor<S>(Geom, double, const S*, int, int, double*, double*, double*,       \
-                                              const int*);                                                       \
+  template __global__ void k_coarse_factor<S, true>(Geom, double, const S*, int, int, double*, double*, double*, \
+                                                    const int*);                                                 \
   template __global__ void k_coarse_inverse<S>(Geom, int, int, const double*, const double*, const double*,      \
                                                double*, S*, const int*);                                          \
   template __global__ void k_coarse_gemv<S>(Geom, const S*, const S*, S*, const int*);                           \
@@ -996,10 +1044,20 @@ __global__ void k_convert(size_t n, const A* __restrict__ X, B2* __restrict__ Y)
   template __global__ void k_fill<S>(size_t, S*, S);
 FSI_INST_S(double)
 FSI_INST_S(float)
-template __global__ void k_vanka_color<3, double, 8>(Geom, double, int, double, int, const double*, const double*,
-                                                     const double*, const double*, double*, const int*);
-template __global__ void k_vanka_color<3, float, 8>(Geom, double, int, float, int, const float*, const float*,
-                                                    const float*, const float*, float*, const int*);
+template __global__ void k_vanka_color<3, double, 8, true>(Geom, double, int, double, int, const double*,
+                                                           const double*, const double*, const double*, double*,
+                                                           const int*);
+template __global__ void k_vanka_color<3, float, 8, true>(Geom, double, int, float, int, const float*, const float*,
+                                                          const float*, const float*, float*, const int*);
+// full-layout operators of the (2d, FP64) transposed adjoint system
+template __global__ void k_spmv<2, double, false>(Geom, double, const double*, const double*, const double*,
+                                                  const double*, double*, const int*);
+template __global__ void k_vanka_factor<2, double, false>(Geom, double, const double*, double*, const int*);
+template __global__ void k_vanka_color<2, double, 16, false>(Geom, double, int, double, int, const double*,
+                                                             const double*, const double*, const double*, double*,
+                                                             const int*);
+template __global__ void k_coarse_factor<double, false>(Geom, double, const double*, int, int, double*, double*,
+                                                        double*, const int*);
 template __global__ void k_change_norms<2>(int, const double*, const double*, int, double*, int);
 template __global__ void k_change_norms<3>(int, const double*, const double*, int, double*, int);
 template __global__ void k_theta_dots<2>(int, const double*, const double*, int, double*, int);
