@@ -398,7 +398,7 @@ fsi_status build_level(fsi_problem* pb, int l) {
   CHK(dalloc(pb, &L.Dsc, (size_t)B * L.nn * NC));
   CHK(dalloc_bytes(pb, &L.J, (size_t)B * jslice<D, false>(L.nn) * ss));
   // Vanka inverses: every smoothed level (in 3d level 0 is smoothed too)
-  if (l >= 1 || D == 3) CHK(dalloc_bytes(pb, &L.Ainv, (size_t)B * NE * NE * L.ncell * ss));
+  if (l >= 1 || D == 3) CHK(dalloc_bytes(pb, &L.Ainv, (size_t)B * ainv_slice<D>(L.ncell) * ss));
   CHK(dalloc_bytes(pb, &L.x_, (size_t)B * L.nn * NC * ss));
   CHK(dalloc_bytes(pb, &L.b_, (size_t)B * L.nn * NC * ss));
   CHK(dalloc_bytes(pb, &L.r_, (size_t)B * L.nn * NC * ss));
@@ -464,6 +464,15 @@ fsi_status residual(fsi_problem* pb, int B, const StepPar& sp, const double* U, 
   return FSI_OK;
 }
 
+// Cells per block of the fused Vanka pass on a level (and the block width of its
+// Vanka inverse storage): 16 in 2d; in 3d 32 where a colour has cells enough
+// over the batch to fill the GPU with wide blocks, else 8.
+template <int D>
+int vanka_vc(const Geom& g, int B) {
+  if (D == 2) return 16;
+  return (size_t)(g.ncell / Dm<D>::NCOL) * B >= 8192 ? 32 : 8;
+}
+
 // Jacobian of the finest level (always) and, when precond is set, the multigrid
 // hierarchy: injected coarse states, coarse-level Jacobians, Vanka inverses and
 // the coarsest-level solver (2d: explicit inverse; 3d: Vanka inverses, the
@@ -503,7 +512,8 @@ fsi_status assemble_levels(fsi_problem* pb, int B, const StepPar& sp, const int*
     if (!precond) break;
     if (l >= 1 || D == 3) {
       k_vanka_factor<D, S, CJ><<<dim3((g.ncell + vf_patches<D>() - 1) / vf_patches<D>(), B),
-                             vf_lanes<D>() * vf_patches<D>(), 0, st>>>(g, sp.k, (const S*)lv.J, (S*)lv.Ainv, act);
+                                 vf_lanes<D>() * vf_patches<D>(), 0, st>>>(g, sp.k, (const S*)lv.J, (S*)lv.Ainv,
+                                                                          vanka_vc<D>(g, B), act);
     } else {
       const size_t lds_f = (size_t)5 * pb->cbs * pb->cbs * sizeof(double);
       const size_t lds_i = (size_t)3 * pb->cbs * pb->cbs * sizeof(double);
@@ -541,7 +551,8 @@ void smooth(fsi_problem* pb, int l, int B, double k, int sweeps, bool zero_first
   for (int s = 0; s < sweeps; ++s)
     for (int c = 0; c < NCOL; ++c) {
       const bool zero = zero_first && s == 0 && c == 0;
-      const int nc = color_info<D>(g, c).nc;
+      const int vc = vanka_vc<D>(g, B);
+      const int nc = color_info<D>(g, c, vc).nc;
       const double vec = 3.0 * g.nn * NC * sizeof(S);
       const double by = zero ? (double)B * ((double)NE * NE * nc * sizeof(S) + 2.0 * g.nn * NC * sizeof(S))
                              : (double)B * ((double)NSLOT * jblk<D, CJ>() * g.nn * sizeof(S) + (double)NE * NE * nc * sizeof(S) +
@@ -553,7 +564,7 @@ void smooth(fsi_problem* pb, int l, int B, double k, int sweeps, bool zero_first
       if constexpr (D == 2) {
         k_vanka_color<D, S, 16, CJ><<<dim3((nc + 15) / 16 + ncopy, B), NC * 64, 0, st>>>(
             g, k, c, om, zero ? 1 : 0, J, Ai, b, buf[cur], buf[cur ^ 1], act);
-      } else if ((size_t)nc * B >= 8192) {   // 3d: wide blocks where there are cells enough to fill the GPU
+      } else if (vc == 32) {
         k_vanka_color<D, S, 32, CJ><<<dim3((nc + 31) / 32 + ncopy, B), NC * 64, 0, st>>>(
             g, k, c, om, zero ? 1 : 0, J, Ai, b, buf[cur], buf[cur ^ 1], act);
       } else {

@@ -179,21 +179,23 @@ __host__ __device__ constexpr int jac_waves() { return D == 2 ? 4 : 1; }
 
 // ------------------------------------------------------------ colour helpers
 // Cells of colour c = (i mod 2) + 2 (j mod 2) + 4 (k mod 2): ncx per row, ncy
-// rows per plane, nc in total, and the offset of the colour's block in the
-// per-colour Vanka inverse storage (colours stored in order).  Computed
-// without arrays, so a colour only known at run time costs no private memory.
+// rows per plane, nc in total.  The fused Vanka pass takes the cells of a
+// colour in blocks of vc consecutive ones; off is the first cell slot of the
+// colour in the Vanka inverse storage, where every colour is padded to a
+// multiple of vc cells (colours stored in order).  Computed without arrays, so
+// a colour only known at run time costs no private memory.
 struct ColorInfo {
   int ncx, ncy, nc, off;
 };
 template <int D>
-__host__ __device__ inline ColorInfo color_info(const Geom& g, int c) {
+__host__ __device__ inline ColorInfo color_info(const Geom& g, int c, int vc) {
   ColorInfo ci;
   ci.off = 0;
 #pragma unroll
   for (int q = 0; q < Dm<D>::NCOL; ++q) {
     const int nq = ((g.nx - (q & 1) + 1) / 2) * ((g.ny - ((q >> 1) & 1) + 1) / 2) *
                    (D == 3 ? (g.nz - ((q >> 2) & 1) + 1) / 2 : 1);
-    if (q < c) ci.off += nq;
+    if (q < c) ci.off += (nq + vc - 1) / vc * vc;
   }
   ci.ncx = (g.nx - (c & 1) + 1) / 2;
   ci.ncy = (g.ny - ((c >> 1) & 1) + 1) / 2;
@@ -202,10 +204,21 @@ __host__ __device__ inline ColorInfo color_info(const Geom& g, int c) {
 }
 // Colour and index within the colour of cell (i, j, k).
 template <int D>
-__host__ __device__ inline void cell_colour(const Geom& g, int i, int j, int k, int& col, int& idx, ColorInfo& L) {
+__host__ __device__ inline void cell_colour(const Geom& g, int i, int j, int k, int vc, int& col, int& idx,
+                                            ColorInfo& L) {
   col = (i & 1) + 2 * (j & 1) + (D == 3 ? 4 * (k & 1) : 0);
-  L = color_info<D>(g, col);
+  L = color_info<D>(g, col, vc);
   idx = (i >> 1) + L.ncx * ((j >> 1) + L.ncy * (k >> 1));
+}
+
+// Vanka inverses: per slice, the NE x NE inverse of every cell patch, stored by
+// colour and, within a colour, by block of vc cells: entry (r, e) of cell
+// idx = vc q + t sits at ((off + vc q) NE^2 + (NE r + e) vc + t).  A block of the
+// fused pass so reads one contiguous region.  VC_MAX bounds vc (padding).
+constexpr int VC_MAX = 32;
+template <int D>
+__host__ __device__ inline size_t ainv_slice(int ncell) {
+  return ((size_t)ncell + (size_t)Dm<D>::NCOL * VC_MAX) * Dm<D>::NE * Dm<D>::NE;
 }
 
 // A bar face shared with a fluid cell (2d): fluid cell index, face axis (0: x,

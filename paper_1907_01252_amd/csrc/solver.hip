@@ -220,7 +220,7 @@ __global__ void k_adjoint_rhs(Geom g, const double* __restrict__ rhs, double* __
 template <int D, class S, bool CJ>
 __global__ void __launch_bounds__(vf_lanes<D>() * vf_patches<D>()) k_vanka_factor(Geom g, double k,
                                                                                   const S* __restrict__ J,
-                                                                                  S* __restrict__ Ainv,
+                                                                                  S* __restrict__ Ainv, int vc,
                                                                                   const int* __restrict__ active) {
   FSI_DIM(D);
   constexpr int GL = vf_lanes<D>(), NP = vf_patches<D>(), LD = 2 * NE + 1;
@@ -278,10 +278,11 @@ __global__ void __launch_bounds__(vf_lanes<D>() * vf_patches<D>()) k_vanka_facto
   if (live && lane < NE) {
     int col, idx;
     ColorInfo L;
-    cell_colour<D>(g, ci, cj, ck, col, idx, L);
+    cell_colour<D>(g, ci, cj, ck, vc, col, idx, L);
     const double d = Mp[lane][mycol] != 0.0 ? 1.0 / Mp[lane][mycol] : 1.0;
-    S* out = Ainv + (size_t)bs * NE * NE * g.ncell + (size_t)L.off * NE * NE;
-    for (int c = 0; c < NE; ++c) out[(size_t)(NE * mycol + c) * L.nc + idx] = (S)(Mp[lane][NE + c] * d);
+    const int q = idx / vc, t = idx - q * vc;
+    S* out = Ainv + (size_t)bs * ainv_slice<D>(g.ncell) + ((size_t)L.off + (size_t)q * vc) * NE * NE + t;
+    for (int c = 0; c < NE; ++c) out[(size_t)(NE * mycol + c) * vc] = (S)(Mp[lane][NE + c] * d);
   }
 }
 
@@ -314,7 +315,7 @@ __global__ void __launch_bounds__(Dm<D>::NC * 64) k_vanka_color(Geom g, double k
   __shared__ S rs[NE][VC];
   const int bs = blockIdx.y;
   if (active && !active[bs]) return;   // uniform over the block
-  const ColorInfo L = color_info<D>(g, color);
+  const ColorInfo L = color_info<D>(g, color, VC);
   const int nc = L.nc;
   const int npb = (nc + VC - 1) / VC;
   const S* xob = xo + (size_t)bs * g.nn * NC;
@@ -363,7 +364,8 @@ __global__ void __launch_bounds__(Dm<D>::NC * 64) k_vanka_color(Geom g, double k
   }
   __syncthreads();
   if (!live) return;
-  const S* ai = Ainv + (size_t)bs * NE * NE * g.ncell + (size_t)L.off * NE * NE + idx;
+  const S* ai =
+      Ainv + (size_t)bs * ainv_slice<D>(g.ncell) + ((size_t)L.off + (size_t)blockIdx.x * VC) * NE * NE + jc;
 #pragma unroll 1
   for (int q = 0; q < NQ; ++q) {
     const int a = a0 + q * QS;
@@ -371,7 +373,7 @@ __global__ void __launch_bounds__(Dm<D>::NC * 64) k_vanka_color(Geom g, double k
     S z = 0;
     constexpr int EU = NQ == 1 ? NE : 8;   // looping threads: bounded loads in flight (registers)
 #pragma unroll EU
-    for (int e = 0; e < NE; ++e) z += ai[(size_t)(NE * row + e) * nc] * rs[e][jc];
+    for (int e = 0; e < NE; ++e) z += ai[(NE * row + e) * VC] * rs[e][jc];
     const int n = node_at(g, ci + (a & 1), cj + ((a >> 1) & 1), ck + ((a >> 2) & 1));
     const size_t o = (size_t)n * NC + r;
     xnb[o] = (zero_in ? (S)0 : xob[o]) + omega * z;
@@ -1019,7 +1021,7 @@ __global__ void k_convert(size_t n, const A* __restrict__ X, B2* __restrict__ Y)
 #define FSI_INST_DS(D, S)                                                                                         \
   template __global__ void k_spmv<D, S, true>(Geom, double, const S*, const S*, const S*, const double*, S*,     \
                                               const int*);                                                       \
-  template __global__ void k_vanka_factor<D, S, true>(Geom, double, const S*, S*, const int*);                   \
+  template __global__ void k_vanka_factor<D, S, true>(Geom, double, const S*, S*, int, const int*);              \
   template __global__ void k_vanka_color<D, S, (D == 2 ? 16 : 32), true>(Geom, double, int, S, int, const S*,   \
                                                                          const S*, const S*, const S*, S*,      \
                                                                          const int*);                            \
@@ -1052,7 +1054,7 @@ template __global__ void k_vanka_color<3, float, 8, true>(Geom, double, int, flo
 // full-layout operators of the (2d, FP64) transposed adjoint system
 template __global__ void k_spmv<2, double, false>(Geom, double, const double*, const double*, const double*,
                                                   const double*, double*, const int*);
-template __global__ void k_vanka_factor<2, double, false>(Geom, double, const double*, double*, const int*);
+template __global__ void k_vanka_factor<2, double, false>(Geom, double, const double*, double*, int, const int*);
 template __global__ void k_vanka_color<2, double, 16, false>(Geom, double, int, double, int, const double*,
                                                              const double*, const double*, const double*, double*,
                                                              const int*);
