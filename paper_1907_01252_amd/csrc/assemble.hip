@@ -473,7 +473,10 @@ __global__ void k_gather_jacobian(Geom g, double k, const double* __restrict__ K
   int i, j, kk;
   node_ijk<D>(g, n, i, j, kk);
   const double* ke = Ke + (size_t)b * NE * NE * g.ncell;
-  S* jb = J + (size_t)b * jslice<D, CJ>(g.nn);
+  S* jb = J + (size_t)b * jslice<D, CJ>(g);
+  const int row = n / (g.nx + 1);
+  S* j0 = jb + jnode<D, CJ>(g, i, row, 0);   // every copy of the tiled storage
+  S* j1 = jb + jnode<D, CJ>(g, i, row, jcopies<D>() - 1);
   const uint8_t m = g.dmask[n];
   double rmax[NC];
   for (int c = 0; c < NC; ++c) rmax[c] = 0.0;
@@ -505,7 +508,10 @@ __global__ void k_gather_jacobian(Geom g, double k, const double* __restrict__ K
     for (int r = 0; r < NC; ++r)
       for (int c = 0; c < NC; ++c) {
         const int e = jentry<D, CJ>(r, c);   // compressed layout: structural zeros are not stored
-        if (e >= 0) jb[jidx<D, CJ>(n, s, e)] = (S)blk[NC * r + c];
+        if (e >= 0) {
+          j0[jent<D, CJ>(s, e)] = (S)blk[NC * r + c];
+          if (jcopies<D>() == 2) j1[jent<D, CJ>(s, e)] = (S)blk[NC * r + c];
+        }
       }
   }
   if (!(m & dm_p<D>())) {

@@ -54,33 +54,44 @@ __device__ inline S pst_row(const Geom& g, double k, int n, int i, int j, int kk
 }
 
 // Row r of the block stencil at node n times x: the sum over the slots of the
-// stored entries of row r.  In the compressed layout a displacement row holds
-// (v_i, u_i) only.  In 3d the planes of the stencil are taken one at a time, so
-// that the loads of a plane are in flight together within the register budget.
+// stored entries of row r (jn: the node's position in the tiled Jacobian).  In
+// the compressed layout a displacement row holds (v_i, u_i) only; the row kind
+// is uniform over a wave and tested once, outside the slot loops, so that the
+// loads of all slots (3d: of one plane of slots) are in flight together.
 template <int D, class S, bool CJ>
-__device__ inline S stencil_row(const S* __restrict__ jb, const S* __restrict__ xb, int n, int r, const Nbr& nb) {
+__device__ inline S stencil_row(const S* __restrict__ jn, const S* __restrict__ xb, int n, int r, const Nbr& nb) {
   FSI_DIM(D);
   S acc = 0;
   const int e0 = jrow_off<D, CJ>(r);
-  const bool urow = CJ && r >= D && r < 2 * D;
   constexpr int NZ = D == 3 ? 3 : 1;
+  if (CJ && r >= D && r < 2 * D) {
 #pragma unroll 1
-  for (int sz = 0; sz < NZ; ++sz) {
-    const int oz = sz == 0 ? nb.oz[0] : (sz == 1 ? 0 : nb.oz[2]);
+    for (int sz = 0; sz < NZ; ++sz) {
+      const int oz = sz == 0 ? nb.oz[0] : (sz == 1 ? 0 : nb.oz[2]);
 #pragma unroll
-    for (int sy = 0; sy < 3; ++sy)
+      for (int sy = 0; sy < 3; ++sy)
 #pragma unroll
-      for (int sx = 0; sx < 3; ++sx) {
-        const int s = sx + 3 * sy + 9 * sz;
-        const S* xv = xb + (size_t)(n + nb.ox[sx] + nb.oy[sy] + oz) * NC;
-        if (urow) {
-          acc += jb[jidx<D, CJ>(n, s, e0)] * xv[r - D];
-          acc += jb[jidx<D, CJ>(n, s, e0 + 1)] * xv[r];
-        } else {
-#pragma unroll
-          for (int c = 0; c < NC; ++c) acc += jb[jidx<D, CJ>(n, s, e0 + c)] * xv[c];
+        for (int sx = 0; sx < 3; ++sx) {
+          const int s = sx + 3 * sy + 9 * sz;
+          const S* xv = xb + (size_t)(n + nb.ox[sx] + nb.oy[sy] + oz) * NC;
+          acc += jn[jent<D, CJ>(s, e0)] * xv[r - D];
+          acc += jn[jent<D, CJ>(s, e0 + 1)] * xv[r];
         }
-      }
+    }
+  } else {
+#pragma unroll 1
+    for (int sz = 0; sz < NZ; ++sz) {
+      const int oz = sz == 0 ? nb.oz[0] : (sz == 1 ? 0 : nb.oz[2]);
+#pragma unroll
+      for (int sy = 0; sy < 3; ++sy)
+#pragma unroll
+        for (int sx = 0; sx < 3; ++sx) {
+          const int s = sx + 3 * sy + 9 * sz;
+          const S* xv = xb + (size_t)(n + nb.ox[sx] + nb.oy[sy] + oz) * NC;
+#pragma unroll
+          for (int c = 0; c < NC; ++c) acc += jn[jent<D, CJ>(s, e0 + c)] * xv[c];
+        }
+    }
   }
   return acc;
 }
@@ -90,10 +101,10 @@ __device__ inline S stencil_row(const S* __restrict__ jb, const S* __restrict__ 
 // y = D (b - A x)        (b != nullptr)
 // with A = J (3^D block stencil of NC x NC blocks) + k * S_p (pressure stencil).
 // D = Dsc (row scaling) when given, else identity.
-// One thread per (node, row): a block of NC waves takes 64 consecutive nodes,
-// wave r forming row r, so the rows of a node read its neighbours' x through
-// the same CU's cache, and a wave streams 64 consecutive values of each
-// coefficient run of the tiled layout.
+// One thread per (node, row): a block of NC waves takes 64 lanes of nodes of
+// the Jacobian storage (one tile in 2d, two tiles of copy 0 in 3d), wave r
+// forming row r, so the rows of a node read its neighbours' x through the same
+// CU's cache, and a wave streams whole runs of each coefficient.
 template <int D, class S, bool CJ>
 __global__ void __launch_bounds__(Dm<D>::NC * 64) k_spmv(Geom g, double k, const S* __restrict__ J,
                                                          const S* __restrict__ x, const S* __restrict__ b,
@@ -101,14 +112,27 @@ __global__ void __launch_bounds__(Dm<D>::NC * 64) k_spmv(Geom g, double k, const
                                                          const int* __restrict__ active) {
   FSI_DIM(D);
   const int bs = blockIdx.y;
-  const int r = threadIdx.x >> 6;
-  const int n = blockIdx.x * 64 + (threadIdx.x & 63);
-  if (n >= g.nn || (active && !active[bs])) return;
-  int i, j, kk;
-  node_ijk<D>(g, n, i, j, kk);
-  const S* jb = J + (size_t)bs * jslice<D, CJ>(g.nn);
+  const int r = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  int n, i, row;
+  if (D == 2) {
+    n = blockIdx.x * 64 + lane;
+    row = n / (g.nx + 1);
+    i = n - row * (g.nx + 1);
+    if (n >= g.nn) return;
+  } else {
+    constexpr int TX = jtx<D>();
+    const int ntx = jntx<D>(g, 0);
+    const int t = blockIdx.x * (64 / TX) + lane / TX;
+    row = t / ntx;
+    i = (t - row * ntx) * TX + lane % TX;
+    if (row >= jrows<D>(g) || i > g.nx) return;
+    n = i + (g.nx + 1) * row;
+  }
+  if (active && !active[bs]) return;
+  const int j = row % (g.ny + 1), kk = row / (g.ny + 1);
+  const S* jn = J + (size_t)bs * jslice<D, CJ>(g) + jnode<D, CJ>(g, i, row, 0);
   const S* xb = x + (size_t)bs * g.nn * NC;
-  S acc = stencil_row<D, S, CJ>(jb, xb, n, r, nbr_offsets<D>(g, i, j, kk));
+  S acc = stencil_row<D, S, CJ>(jn, xb, n, r, nbr_offsets<D>(g, i, j, kk));
   if (r == PC) acc += pst_row<D, S>(g, k, n, i, j, kk, xb);
   const size_t o = ((size_t)bs * g.nn + n) * NC + r;
   S v = b ? b[o] - acc : acc;
@@ -126,20 +150,22 @@ __global__ void k_transpose_J(Geom g, double k, const S* __restrict__ J, S* __re
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= g.nn) return;
   const int i = n % (g.nx + 1), j = n / (g.nx + 1);
-  const S* jb = J + (size_t)bs * jslice<2, false>(g.nn);
-  S* jt = Jt + (size_t)bs * jslice<2, false>(g.nn);
+  const S* jb = J + (size_t)bs * jslice<2, false>(g);
+  S* jt = Jt + (size_t)bs * jslice<2, false>(g);
+  S* jt0 = jt + jnode<2, false>(g, i, j, 0);
   const uint8_t m = g.dmask[n];
   double rmax[D2::NC] = {0, 0, 0, 0, 0};
   for (int s = 0; s < D2::NSLOT; ++s) {
     const int dx = s % 3 - 1, dy = s / 3 - 1;
     const int ii = i + dx, jj = j + dy;
     const bool ok = ii >= 0 && jj >= 0 && ii <= g.nx && jj <= g.ny;
-    const int nb = ok ? ii + (g.nx + 1) * jj : 0;
+    const S* jnb = jb + (ok ? jnode<2, false>(g, ii, jj, 0) : 0);
+    const int so = slot_of<2>(-dx, -dy, 0);
     for (int r = 0; r < D2::NC; ++r)
       for (int c = 0; c < D2::NC; ++c) {
-        double v = ok ? (double)jb[jidx<2, false>(nb, slot_of<2>(-dx, -dy, 0), D2::NC * c + r)] : 0.0;
+        double v = ok ? (double)jnb[jent<2, false>(so, D2::NC * c + r)] : 0.0;
         if (m & (1u << r)) v = (s == 4 && c == r) ? 1.0 : 0.0;
-        jt[jidx<2, false>(n, s, D2::NC * r + c)] = (S)v;
+        jt0[jent<2, false>(s, D2::NC * r + c)] = (S)v;
         rmax[r] = fmax(rmax[r], fabs(v));
       }
   }
@@ -158,7 +184,7 @@ __global__ void k_spmv_T(Geom g, double k, const S* __restrict__ J, const S* __r
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= g.nn) return;
   const int i = n % (g.nx + 1), j = n / (g.nx + 1);
-  const S* jb = J + (size_t)bs * jslice<2, false>(g.nn);
+  const S* jb = J + (size_t)bs * jslice<2, false>(g);
   const S* xb = x + (size_t)bs * g.nn * D2::NC;
   S acc[D2::NC] = {0, 0, 0, 0, 0};
   for (int s = 0; s < D2::NSLOT; ++s) {
@@ -169,7 +195,8 @@ __global__ void k_spmv_T(Geom g, double k, const S* __restrict__ J, const S* __r
     const int mr = ii + (g.nx + 1) * jj;
     for (int r = 0; r < D2::NC; ++r) {
       const S xr = xb[(size_t)mr * D2::NC + r];
-      for (int c = 0; c < D2::NC; ++c) acc[c] += jb[jidx<2, false>(mr, s, D2::NC * r + c)] * xr;
+      const S* jm = jb + jnode<2, false>(g, ii, jj, 0);
+      for (int c = 0; c < D2::NC; ++c) acc[c] += jm[jent<2, false>(s, D2::NC * r + c)] * xr;
     }
   }
   if (with_pst && !(g.dmask[n] & dm_p<2>())) {
@@ -238,14 +265,14 @@ __global__ void __launch_bounds__(vf_lanes<D>() * vf_patches<D>()) k_vanka_facto
     const int ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
     const int na = node_at(g, ci + ax, cj + ay, ck + az);
     if (live) {
-      const S* jb = J + (size_t)bs * jslice<D, CJ>(g.nn);
+      const S* jn = J + (size_t)bs * jslice<D, CJ>(g) + jnode_n<D, CJ>(g, na, 0);
       const bool pst_row = (rc == PC) && !(g.dmask[na] & dm_p<D>());
       for (int bb = 0; bb < NL; ++bb) {
         const int dx = (bb & 1) - ax, dy = ((bb >> 1) & 1) - ay, dz = ((bb >> 2) & 1) - az;
         const int s = slot_of<D>(dx, dy, dz);
         for (int c = 0; c < NC; ++c) {
           const int e = jentry<D, CJ>(rc, c);
-          Mp[lane][NC * bb + c] = e >= 0 ? (double)jb[jidx<D, CJ>(na, s, e)] : 0.0;
+          Mp[lane][NC * bb + c] = e >= 0 ? (double)jn[jent<D, CJ>(s, e)] : 0.0;
         }
         if (pst_row) Mp[lane][NC * bb + PC] += k * g.pst[(size_t)pslot_of<D>(dx, dy, dz) * g.nn + na];
       }
@@ -305,8 +332,14 @@ __global__ void __launch_bounds__(vf_lanes<D>() * vf_patches<D>()) k_vanka_facto
 // NE patch residuals meet in LDS; the same thread then forms patch rows
 // NC a + r of Ainv_P r_P.  Extra blocks past the patch blocks copy the
 // uncovered nodes.
+// Minimum waves per SIMD requested for the fused pass: in 2d FP32 the register
+// budget of 6 waves (85 VGPRs) keeps enough waves resident to hide latency.
+template <int D, class S>
+constexpr int vanka_waves_per_simd() {
+  return (D == 2 && sizeof(S) == 4) ? 6 : 1;
+}
 template <int D, class S, int VC, bool CJ>
-__global__ void __launch_bounds__(Dm<D>::NC * 64) k_vanka_color(Geom g, double k, int color, S omega, int zero_in,
+__global__ void __launch_bounds__(Dm<D>::NC * 64, (vanka_waves_per_simd<D, S>())) k_vanka_color(Geom g, double k, int color, S omega, int zero_in,
                                                                 const S* __restrict__ J, const S* __restrict__ Ainv,
                                                                 const S* __restrict__ b, const S* __restrict__ xo,
                                                                 S* __restrict__ xn, const int* __restrict__ active) {
@@ -355,8 +388,9 @@ __global__ void __launch_bounds__(Dm<D>::NC * 64) k_vanka_color(Geom g, double k
       if (!zero_in) {
         int i, j, kk;
         node_ijk<D>(g, n, i, j, kk);
-        const S* jb = J + (size_t)bs * jslice<D, CJ>(g.nn);
-        acc = stencil_row<D, S, CJ>(jb, xob, n, r, nbr_offsets<D>(g, i, j, kk));
+        // (3d: the copy whose tiles start where this colour's node runs start)
+        const S* jn = J + (size_t)bs * jslice<D, CJ>(g) + jnode<D, CJ>(g, i, j + (g.ny + 1) * kk, cx);
+        acc = stencil_row<D, S, CJ>(jn, xob, n, r, nbr_offsets<D>(g, i, j, kk));
         if (r == PC) acc += pst_row<D, S>(g, k, n, i, j, kk, xob);
       }
       rs[NC * a + r][jc] = b[((size_t)bs * g.nn + n) * NC + r] - acc;
@@ -465,7 +499,8 @@ __device__ inline double coarse_entry(const Geom& g, double k, const S* jb, int 
   const int n = ir + (g.nx + 1) * jr;
   double v = 0.0;
   const int e = jentry<2, CJ>(r, c);
-  if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && e >= 0) v = (double)jb[jidx<2, CJ>(n, slot_of<2>(dx, dy, 0), e)];
+  if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && e >= 0)
+    v = (double)jb[jnode<2, CJ>(g, ir, jr, 0) + jent<2, CJ>(slot_of<2>(dx, dy, 0), e)];
   if (r == 4 && c == 4 && dx >= -2 && dx <= 2 && dy >= -2 && dy <= 2 && !(g.dmask[n] & dm_p<2>()))
     v += k * g.pst[(size_t)pslot_of<2>(dx, dy, 0) * g.nn + n];
   return v;
@@ -500,7 +535,7 @@ __global__ void __launch_bounds__(256) k_coarse_factor(Geom g, double k, const S
   const int bs = blockIdx.x;
   if (active && !active[bs]) return;
   const int tid = threadIdx.x, nt = blockDim.x;
-  const S* jb = J + (size_t)bs * jslice<2, CJ>(g.nn);
+  const S* jb = J + (size_t)bs * jslice<2, CJ>(g);
   const int w2 = 2 * bsz;
   const int B2i = bsz * bsz;
   double* M = lds;                  // bsz x 2bsz
