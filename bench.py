@@ -89,6 +89,8 @@ def main():
     ap.add_argument("--no-profile-sweep", action="store_true")
     ap.add_argument("--set", action="append", default=[], metavar="KEY=VALUE",
                     help="solver parameter override (fsi_params field), e.g. vanka_sweeps_coarse=1")
+    ap.add_argument("--parareal", action="store_true",
+                    help="time parareal_run on the c1 workload, plain and pipelined schedules")
     ap.add_argument("--adjoint", action="store_true",
                     help="time one adjoint_gradient call of the c4 workload instead of the fine sweep")
     args = ap.parse_args()
@@ -104,6 +106,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.adjoint:
         return adjoint_bench(args)
+    if args.parareal:
+        return parareal_bench(args)
     p = synth.workload(args.workload, seed=0)
     prec = args.precision or p["precision"]
     N, m, M, dl = p["N"], p["m"], p["M"], p["slice_len"]
@@ -273,6 +277,53 @@ def adjoint_bench(args):
         "J": J, "grad": {"inflow_peak": g[0], "mu_s": g[1], "lambda_s": g[2]},
         "newton_forward": st.newton_total, "krylov_total": st.krylov_total,
         "krylov_backward": st.krylov_its[0], "steps": steps, "ms_per_backward_step": None,
+    }))
+
+
+def parareal_bench(args):
+    """parareal_run on c1 (8 slices, tolerance 1e-8): the plain schedule (batched fine sweep, then the
+    sequential correction sweep) against the pipelined one (fine chunks of G slices on a second stream,
+    overlapped with the correction sweep), same iterates."""
+    import torch
+    import synth
+    from paper_1907_01252_amd import fsi
+    name = "c1" if args.workload == "c2" else args.workload
+    p = synth.workload(name, seed=0)
+    N = p["N"]
+    rows = {}
+    ref = None
+    for G in [0, 1, 2, 4]:
+        prob = fsi.Problem(fsi.make_params(p, max_batch=N, parareal_pipeline=G))
+        nd = prob.n_dofs // prob.n_nodes
+        U0 = torch.zeros(prob.n_nodes, nd, dtype=torch.float64, device="cuda")
+        prob.initial_state(U0)
+        Ub = torch.zeros(N + 1, prob.n_nodes, nd, dtype=torch.float64, device="cuda")
+        best = None
+        for rep in range(1 + args.steps):   # the first call also builds the worker workspace
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            code, st = prob.parareal_run(p["T"], N, p["m"], p["M"], 1e-8, N, U0, Ub, raise_on_error=False)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            if rep > 0:
+                best = wall if best is None else min(best, wall)
+        U = Ub.cpu()
+        if ref is None:
+            ref = U
+        rows[f"G{G}" if G else "plain"] = {
+            "seconds": best, "iterations": st.parareal_iters, "status": int(code),
+            "coarse_ms": st.stage_ms[5], "fine_ms": st.stage_ms[6],
+            "max_rel_diff_vs_plain": float((U - ref).abs().max() / ref.abs().max()),
+        }
+        prob.close()
+    plain = rows["plain"]["seconds"]
+    bestG = min((k for k in rows if k != "plain"), key=lambda k: rows[k]["seconds"])
+    print(json.dumps({
+        "metric": "parareal_run wall time to tolerance 1e-8, plain vs pipelined schedule",
+        "value": rows[bestG]["seconds"], "unit": "s", "higher_is_better": False, "n_gpus": 1, "dtype": "f64",
+        "data": "synthetic", "config": {"workload": f"{name}: 2d ALE-FSI, {N} slices x {p['m']} fine / {p['M']} "
+                                                   f"coarse steps, T={p['T']}"},
+        "speedup_vs_plain": plain / rows[bestG]["seconds"], "best": bestG, "schedules": rows,
     }))
 
 

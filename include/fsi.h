@@ -53,7 +53,7 @@ typedef struct fsi_problem fsi_problem;
 
 /* Problem description.  SI units as in Table "parameters" of Section 4. */
 typedef struct {
-  int32_t dim;               /* 2 (the only dimension built) */
+  int32_t dim;               /* 2 (quadrilaterals, 5 unknowns per node) or 3 (hexahedra, 7) */
   int32_t level;             /* refinement level l >= 1 of the level-0 mesh */
   /* level-0 tensor mesh: per axis nseg segments, breakpoints seg_pts[a][0..nseg],
      seg_cells[a][s] level-0 cells in segment s; the bar faces must be breakpoints */
@@ -98,6 +98,15 @@ typedef struct {
                                 theta = 1/2 + alpha(k) k with equal dissipation per unit time
                                 for all step sizes (Section 4, fsi-3 discussion); steps of
                                 size k_r keep 1/2 + theta0 k_r */
+  int32_t parareal_pipeline; /* parareal_run schedule (Section 3, task-based implementation):
+                                0: each iteration runs one batched fine sweep, then the
+                                sequential correction sweep;
+                                G in [1, max_batch]: the fine propagations run in chunks of G
+                                consecutive slices on a second workspace and stream, each
+                                starting as soon as the correction sweep has written its
+                                inputs, overlapped with the rest of the sweep.  Same iterates
+                                as 0.  The second workspace (max_batch G) is created on the
+                                first such call and kept with the problem. */
 } fsi_params;
 
 #define FSI_MAX_SLICES 1024

@@ -4,10 +4,14 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <deque>
+#include <mutex>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "kernels.h"
@@ -123,6 +127,8 @@ struct fsi_problem {
   int nchunk_n = 1, chunk_n = 1;
   Prof prof;
   std::vector<void*> allocs;
+  // pipelined Parareal: workspace of the fine-sweep worker (created on first use)
+  fsi_problem* pipe = nullptr;
 };
 
 namespace {
@@ -1106,6 +1112,7 @@ const char* fsi_status_string(fsi_status s) {
 
 void fsi_destroy(fsi_problem* pb) {
   if (!pb) return;
+  if (pb->pipe) fsi_destroy(pb->pipe);
   if (pb->vc_exec) (void)hipGraphExecDestroy(pb->vc_exec);
   if (pb->ist) (void)hipStreamSynchronize(pb->ist);
   if (pb->ist) (void)hipStreamDestroy(pb->ist);
@@ -1125,7 +1132,8 @@ fsi_status fsi_setup(const fsi_params* prm, fsi_problem** out) {
       p.vanka_sweeps_coarse < 1 ||
       p.gmres_maxit < 1 || (p.precision != FSI_FP64 && p.precision != FSI_MIXED) ||
       (p.precond_lag != 0 && p.precond_lag != 1) || !(p.lin_rtol_first > 0.0 && p.lin_rtol_first < 1.0) ||
-      p.parareal_theta < 0 || p.parareal_theta > 2 || !(p.theta_ref_k >= 0.0))
+      p.parareal_theta < 0 || p.parareal_theta > 2 || !(p.theta_ref_k >= 0.0) || p.parareal_pipeline < 0 ||
+      p.parareal_pipeline > p.max_batch)
     return FSI_ERR_ARG;
   for (int a = 0; a < p.dim; ++a) {
     if (p.nseg[a] < 1 || p.nseg[a] > 4) return FSI_ERR_ARG;
@@ -1258,129 +1266,357 @@ fsi_status coarse_propagate(fsi_problem* pb, int32_t B, const double* t0, double
   return run_propagate(pb, B, t0, slice_len, M, U_in, U_out, stats, st);
 }
 
+namespace {
+
+// Device scratch of a Parareal run and the host copies of its partial sums.
+struct PararealBufs {
+  double *Cold = nullptr, *Fv = nullptr, *Up = nullptr, *Cn = nullptr, *part = nullptr, *tpart = nullptr;
+  int chunk = 4096, nchunk = 1;
+  std::vector<double> htp, hp;
+  ~PararealBufs() {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(Cold); (void)hipFree(Fv); (void)hipFree(Up); (void)hipFree(Cn); (void)hipFree(part);
+    (void)hipFree(tpart);
+  }
+  // nfv: number of fine-result buffers of N slices each
+  fsi_status alloc(int nn, size_t nd, int N, int nfv) {
+    nchunk = (nn + chunk - 1) / chunk;
+    htp.resize((size_t)18 * nchunk);
+    hp.resize((size_t)(N + 1) * 4 * nchunk);
+    if (hipMalloc(&Cold, N * nd * sizeof(double)) != hipSuccess ||
+        hipMalloc(&Fv, (size_t)nfv * N * nd * sizeof(double)) != hipSuccess ||
+        hipMalloc(&Up, (N + 1) * nd * sizeof(double)) != hipSuccess || hipMalloc(&Cn, nd * sizeof(double)) != hipSuccess ||
+        hipMalloc(&part, (size_t)(N + 1) * 4 * nchunk * sizeof(double)) != hipSuccess ||
+        hipMalloc(&tpart, (size_t)18 * nchunk * sizeof(double)) != hipSuccess)
+      return FSI_ERR_OOM;
+    return FSI_OK;
+  }
+};
+
+// theta-Parareal weight from F = F(U^i_l) and C = C(U^{i+1}_l), per velocity /
+// displacement component, averaged (host-synchronous on st).
+fsi_status theta_weight(fsi_problem* pb, PararealBufs& w, const double* Fl, const double* Cl, double& th,
+                        hipStream_t st) {
+  const int dim = pb->p.dim, nq = 3 * 2 * dim;
+  const int nn = pb->lev[pb->nlev - 1].nn;
+  th = 1.0;
+  if (pb->p.parareal_theta == 0) return FSI_OK;
+  if (dim == 3)
+    k_theta_dots<3><<<w.nchunk, RED_T, 0, st>>>(nn, Fl, Cl, w.chunk, w.tpart, w.nchunk);
+  else
+    k_theta_dots<2><<<w.nchunk, RED_T, 0, st>>>(nn, Fl, Cl, w.chunk, w.tpart, w.nchunk);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(w.htp.data(), w.tpart, (size_t)nq * w.nchunk * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  double sum = 0.0;
+  int cnt = 0;
+  for (int c = 0; c < 2 * dim; ++c) {
+    double ff = 0.0, fg = 0.0, gg = 0.0;
+    for (int q = 0; q < w.nchunk; ++q) {
+      ff += w.htp[(size_t)(3 * c) * w.nchunk + q];
+      fg += w.htp[(size_t)(3 * c + 1) * w.nchunk + q];
+      gg += w.htp[(size_t)(3 * c + 2) * w.nchunk + q];
+    }
+    if (pb->p.parareal_theta == 1 && gg > 0.0 && ff > 0.0) { sum += fg / std::sqrt(gg * ff); ++cnt; }
+    if (pb->p.parareal_theta == 2 && gg > 0.0) { sum += fg / gg; ++cnt; }
+  }
+  th = cnt ? sum / cnt : 1.0;
+  return FSI_OK;
+}
+
+// Largest relative change of v and of u over the N + 1 slice boundaries.
+fsi_status boundary_change(fsi_problem* pb, PararealBufs& w, int N, const double* Ub, double& change,
+                           hipStream_t st) {
+  const int nn = pb->lev[pb->nlev - 1].nn;
+  if (pb->p.dim == 3)
+    k_change_norms<3><<<dim3(w.nchunk, N + 1), RED_T, 0, st>>>(nn, Ub, w.Up, w.chunk, w.part, w.nchunk);
+  else
+    k_change_norms<2><<<dim3(w.nchunk, N + 1), RED_T, 0, st>>>(nn, Ub, w.Up, w.chunk, w.part, w.nchunk);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(w.hp.data(), w.part, w.hp.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  change = 0.0;
+  for (int l = 0; l <= N; ++l)
+    for (int f = 0; f < 2; ++f) {
+      double dd = 0.0, nn2 = 0.0;
+      for (int c = 0; c < w.nchunk; ++c) {
+        dd += w.hp[((size_t)l * 4 + 2 * f) * w.nchunk + c];
+        nn2 += w.hp[((size_t)l * 4 + 2 * f + 1) * w.nchunk + c];
+      }
+      const double r = nn2 > 0.0 ? std::sqrt(dd / nn2) : std::sqrt(dd);
+      change = std::max(change, r);
+    }
+  return FSI_OK;
+}
+
+double ms_since(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// Plain schedule: each iteration is one batched fine sweep over the slices that
+// are not yet exact, then the sequential coarse / correction sweep.
+fsi_status parareal_plain(fsi_problem* pb, double T, int N, int m, int M, double tol, int max_iter,
+                          const double* U0, double* Ub, fsi_stats* sp, double& coarse_ms, double& fine_ms,
+                          hipStream_t st) {
+  const size_t nd = (size_t)pb->lev[pb->nlev - 1].nn * (2 * pb->p.dim + 1);
+  const double dl = T / N;
+  PararealBufs w;
+  CHK(w.alloc(pb->lev[pb->nlev - 1].nn, nd, N, 1));
+  fsi_stats tmp;
+  HIPCHK(hipMemcpyAsync(Ub, U0, nd * sizeof(double), hipMemcpyDeviceToDevice, st));
+  // initial coarse sweep U^0_{l+1} = C(U^0_l)
+  for (int l = 0; l < N; ++l) {
+    const double t0 = l * dl;
+    auto c0 = std::chrono::steady_clock::now();
+    CHK(run_propagate(pb, 1, &t0, dl, M, Ub + l * nd, Ub + (l + 1) * nd, &tmp, st));
+    coarse_ms += ms_since(c0);
+    HIPCHK(hipMemcpyAsync(w.Cold + l * nd, Ub + (l + 1) * nd, nd * sizeof(double), hipMemcpyDeviceToDevice, st));
+  }
+  int it = 0;
+  double change = 1e300;
+  std::vector<double> t0s(N);
+  for (int i = 0; i < max_iter; ++i) {
+    // fine sweep over the slices that are not yet exact, batched in one call
+    const int Bf = N - i;
+    for (int l = i; l < N; ++l) t0s[l - i] = l * dl;
+    auto f0 = std::chrono::steady_clock::now();
+    CHK(run_propagate(pb, Bf, t0s.data(), dl, m, Ub + i * nd, w.Fv + i * nd, &tmp, st));
+    fine_ms += ms_since(f0);
+    sp->newton_total += tmp.newton_total;
+    sp->krylov_total += tmp.krylov_total;
+    HIPCHK(hipMemcpyAsync(w.Up, Ub, (N + 1) * nd * sizeof(double), hipMemcpyDeviceToDevice, st));
+    // sequential correction sweep
+    for (int l = 0; l < N; ++l) {
+      const double* cn = w.Cold + l * nd;
+      double th = 1.0;
+      if (l >= i) {
+        const double t0 = l * dl;
+        auto c0 = std::chrono::steady_clock::now();
+        CHK(run_propagate(pb, 1, &t0, dl, M, Ub + l * nd, w.Cn, &tmp, st));
+        coarse_ms += ms_since(c0);
+        cn = w.Cn;
+        CHK(theta_weight(pb, w, w.Fv + l * nd, w.Cn, th, st));
+      }
+      k_parareal_update<<<256, TPB, 0, st>>>(nd, cn, w.Fv + l * nd, w.Cold + l * nd, Ub + (l + 1) * nd, th);
+      if (cn != w.Cold + l * nd)
+        HIPCHK(hipMemcpyAsync(w.Cold + l * nd, w.Cn, nd * sizeof(double), hipMemcpyDeviceToDevice, st));
+    }
+    CHK(boundary_change(pb, w, N, Ub, change, st));
+    it = i + 1;
+    sp->parareal_iters = it;   // completed iterations, also when a later one fails
+    if (change < tol) break;
+  }
+  return (!(change < tol) && it < N) ? FSI_ERR_PARAREAL : FSI_OK;
+}
+
+// Pipelined schedule (the task view of the iteration): the fine propagation of
+// a chunk of G consecutive slices in iteration i + 1 depends only on the
+// corrected states of those slices, which the correction sweep of iteration i
+// produces one after another.  A worker host thread with its own workspace and
+// stream runs the fine chunks in order as soon as their inputs are written,
+// while this thread runs the sequential coarse / correction sweep; a sweep step
+// waits only for the chunks it reads.  Chunks of an iteration that turns out
+// not to be needed are discarded.  The iterates are those of the plain
+// schedule: every slice sees the same inputs and the same arithmetic.
+struct FineTask {
+  int iter, l0, cnt;
+  hipEvent_t ready;
+};
+
+fsi_status parareal_pipelined(fsi_problem* pb, double T, int N, int m, int M, double tol, int max_iter,
+                              const double* U0, double* Ub, fsi_stats* sp, double& coarse_ms, double& fine_ms,
+                              hipStream_t st) {
+  const int G = pb->p.parareal_pipeline;
+  const size_t nd = (size_t)pb->lev[pb->nlev - 1].nn * (2 * pb->p.dim + 1);
+  const double dl = T / N;
+  if (!pb->pipe) {
+    fsi_params q = pb->p;
+    q.max_batch = G;
+    q.parareal_pipeline = 0;
+    CHK(fsi_setup(&q, &pb->pipe));
+  }
+  fsi_problem* wp = pb->pipe;
+  if (wp->Bmax < G) return FSI_ERR_ARG;
+  PararealBufs w;
+  CHK(w.alloc(pb->lev[pb->nlev - 1].nn, nd, N, 2));   // fine results double-buffered by iteration parity
+  auto fbuf = [&](int iter) { return w.Fv + (size_t)(iter & 1) * N * nd; };
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  hipStream_t ws = nullptr;
+  HIPCHK(hipStreamCreateWithFlags(&ws, hipStreamNonBlocking));
+
+  const int ng = (N + G - 1) / G;
+  std::vector<FineTask> tasks;
+  std::vector<int> tid((size_t)max_iter * ng, -1);
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<int> queue;
+  int done = 0;
+  bool stop = false;
+  fsi_status werr = FSI_OK;
+  double wfine_ms = 0.0;
+  int wnewton = 0, wkrylov = 0;
+  tasks.reserve((size_t)max_iter * ng);
+
+  std::thread worker([&]() {
+    (void)hipSetDevice(dev);
+    std::vector<double> t0s(G);
+    for (;;) {
+      FineTask t;
+      {
+        std::unique_lock<std::mutex> lk(mu);
+        cv.wait(lk, [&] { return stop || !queue.empty(); });
+        if (stop) return;
+        t = tasks[queue.front()];
+        queue.pop_front();
+      }
+      fsi_status s = hipStreamWaitEvent(ws, t.ready, 0) == hipSuccess ? FSI_OK : FSI_ERR_HIP;
+      for (int k = 0; k < t.cnt; ++k) t0s[k] = (t.l0 + k) * dl;
+      fsi_stats tmp{};
+      auto f0 = std::chrono::steady_clock::now();
+      if (s == FSI_OK)
+        s = run_propagate(wp, t.cnt, t0s.data(), dl, m, Ub + t.l0 * nd, fbuf(t.iter) + t.l0 * nd, &tmp, ws);
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        wfine_ms += ms_since(f0);
+        wnewton += tmp.newton_total;
+        wkrylov += tmp.krylov_total;
+        if (s != FSI_OK && werr == FSI_OK) werr = s;
+        ++done;
+      }
+      cv.notify_all();
+      if (s != FSI_OK) return;
+    }
+  });
+
+  // chunk g of iteration it: slices [max(gG, it), min((g+1)G, N))
+  auto enqueue = [&](int it, int g) -> fsi_status {
+    const int l0 = std::max(g * G, it), l1 = std::min((g + 1) * G, N);
+    if (l1 <= l0) return FSI_OK;
+    hipEvent_t ev;
+    HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    if (hipEventRecord(ev, st) != hipSuccess) {
+      (void)hipEventDestroy(ev);
+      return FSI_ERR_HIP;
+    }
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      tasks.push_back({it, l0, l1 - l0, ev});
+      tid[(size_t)it * ng + g] = (int)tasks.size() - 1;
+      queue.push_back((int)tasks.size() - 1);
+    }
+    cv.notify_all();
+    return FSI_OK;
+  };
+  // the input state of slice j for iteration it has just been written on st
+  auto input_ready = [&](int it, int j) -> fsi_status {
+    if (it >= max_iter || j >= N || j < it) return FSI_OK;
+    const int g = j / G;
+    return j == std::min((g + 1) * G, N) - 1 ? enqueue(it, g) : FSI_OK;
+  };
+  // wait until the chunk of iteration it holding slice j has finished (no-op if it has no work)
+  auto wait_chunk = [&](int it, int j) -> fsi_status {
+    const int t = tid[(size_t)it * ng + j / G];
+    if (t < 0) return FSI_OK;
+    std::unique_lock<std::mutex> lk(mu);
+    cv.wait(lk, [&] { return done > t || werr != FSI_OK; });
+    return done > t ? FSI_OK : werr;
+  };
+
+  fsi_status ret = FSI_OK;
+  int it = 0;
+  double change = 1e300;
+  fsi_stats tmp;
+#define PP_(x) do { fsi_status s_ = (x); if (s_ != FSI_OK) { ret = s_; goto finish; } } while (0)
+  if (hipMemcpyAsync(Ub, U0, nd * sizeof(double), hipMemcpyDeviceToDevice, st) != hipSuccess) {
+    ret = FSI_ERR_HIP;
+    goto finish;
+  }
+  PP_(input_ready(0, 0));
+  for (int l = 0; l < N; ++l) {
+    const double t0 = l * dl;
+    auto c0 = std::chrono::steady_clock::now();
+    PP_(run_propagate(pb, 1, &t0, dl, M, Ub + l * nd, Ub + (l + 1) * nd, &tmp, st));
+    coarse_ms += ms_since(c0);
+    if (hipMemcpyAsync(w.Cold + l * nd, Ub + (l + 1) * nd, nd * sizeof(double), hipMemcpyDeviceToDevice, st) !=
+        hipSuccess) {
+      ret = FSI_ERR_HIP;
+      goto finish;
+    }
+    PP_(input_ready(0, l + 1));
+  }
+  for (int i = 0; i < max_iter; ++i) {
+    if (hipMemcpyAsync(w.Up, Ub, (N + 1) * nd * sizeof(double), hipMemcpyDeviceToDevice, st) != hipSuccess) {
+      ret = FSI_ERR_HIP;
+      goto finish;
+    }
+    for (int l = 0; l < N; ++l) {
+      // Ub[l + 1] may still be an input of a running chunk of this iteration, and
+      // F(U^i_l) must be there: chunks finish in order, so wait for the later one
+      if (l + 1 < N && l + 1 >= i) PP_(wait_chunk(i, l + 1));
+      if (l >= i) PP_(wait_chunk(i, l));
+      // a slice l < i is exact; its fine result was last computed in iteration l
+      const double* fl = (l >= i ? fbuf(i) : fbuf(l)) + l * nd;
+      const double* cn = w.Cold + l * nd;
+      double th = 1.0;
+      if (l >= i) {
+        const double t0 = l * dl;
+        auto c0 = std::chrono::steady_clock::now();
+        PP_(run_propagate(pb, 1, &t0, dl, M, Ub + l * nd, w.Cn, &tmp, st));
+        coarse_ms += ms_since(c0);
+        cn = w.Cn;
+        PP_(theta_weight(pb, w, fl, w.Cn, th, st));
+      }
+      k_parareal_update<<<256, TPB, 0, st>>>(nd, cn, fl, w.Cold + l * nd, Ub + (l + 1) * nd, th);
+      if (cn != w.Cold + l * nd &&
+          hipMemcpyAsync(w.Cold + l * nd, w.Cn, nd * sizeof(double), hipMemcpyDeviceToDevice, st) != hipSuccess) {
+        ret = FSI_ERR_HIP;
+        goto finish;
+      }
+      if (l >= i) PP_(input_ready(i + 1, l + 1));
+    }
+    PP_(boundary_change(pb, w, N, Ub, change, st));
+    it = i + 1;
+    sp->parareal_iters = it;
+    if (change < tol) break;
+  }
+  if (!(change < tol) && it < N) ret = FSI_ERR_PARAREAL;
+finish:
+#undef PP_
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    stop = true;   // queued chunks that are not needed any more are dropped
+  }
+  cv.notify_all();
+  worker.join();   // a chunk already running finishes first
+  (void)hipStreamSynchronize(ws);
+  (void)hipStreamDestroy(ws);
+  for (FineTask& t : tasks) (void)hipEventDestroy(t.ready);
+  fine_ms += wfine_ms;
+  sp->newton_total += wnewton;
+  sp->krylov_total += wkrylov;
+  return ret;
+}
+
+}  // namespace
+
 fsi_status parareal_run(fsi_problem* pb, double T, int32_t N, int32_t m, int32_t M, double tol, int32_t max_iter,
                         const double* U0, double* Ub, fsi_stats* stats, hipStream_t st) {
   if (!pb || !U0 || !Ub || N < 1 || N > pb->Bmax || m < 1 || M < 1 || !(T > 0.0) || max_iter < 1) return FSI_ERR_ARG;
   if (max_iter > N) max_iter = N;
-  Level& F = pb->lev[pb->nlev - 1];
-  const size_t nd = (size_t)F.nn * (2 * pb->p.dim + 1);
-  const double dl = T / N;
-  double *Cold = nullptr, *Fv = nullptr, *Up = nullptr, *Cn = nullptr, *part = nullptr, *tpart = nullptr;
-  const int chunk = 4096, nchunk = (F.nn + chunk - 1) / chunk;
-  std::vector<double> htp((size_t)18 * nchunk);
-  auto cleanup = [&]() {
-    (void)hipFree(Cold); (void)hipFree(Fv); (void)hipFree(Up); (void)hipFree(Cn); (void)hipFree(part);
-    (void)hipFree(tpart);
-  };
-  if (hipMalloc(&Cold, N * nd * sizeof(double)) != hipSuccess || hipMalloc(&Fv, N * nd * sizeof(double)) != hipSuccess ||
-      hipMalloc(&Up, (N + 1) * nd * sizeof(double)) != hipSuccess || hipMalloc(&Cn, nd * sizeof(double)) != hipSuccess ||
-      hipMalloc(&part, (size_t)(N + 1) * 4 * nchunk * sizeof(double)) != hipSuccess ||
-      hipMalloc(&tpart, (size_t)18 * nchunk * sizeof(double)) != hipSuccess) {
-    cleanup();
-    return FSI_ERR_OOM;
-  }
   fsi_stats local;
   fsi_stats* sp = stats ? stats : &local;
   std::memset(sp, 0, sizeof(fsi_stats));
-  fsi_stats tmp;
   auto t_start = std::chrono::steady_clock::now();
   double coarse_ms = 0.0, fine_ms = 0.0;
-  fsi_status ret = FSI_OK;
-#define PR_(x) do { fsi_status s_ = (x); if (s_ != FSI_OK) { ret = s_; goto done; } } while (0)
-  {
-    if (hipMemcpyAsync(Ub, U0, nd * sizeof(double), hipMemcpyDeviceToDevice, st) != hipSuccess) { ret = FSI_ERR_HIP; goto done; }
-    // initial coarse sweep U^0_{l+1} = C(U^0_l)
-    for (int l = 0; l < N; ++l) {
-      const double t0 = l * dl;
-      auto c0 = std::chrono::steady_clock::now();
-      PR_(run_propagate(pb, 1, &t0, dl, M, Ub + l * nd, Ub + (l + 1) * nd, &tmp, st));
-      coarse_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - c0).count();
-      if (hipMemcpyAsync(Cold + l * nd, Ub + (l + 1) * nd, nd * sizeof(double), hipMemcpyDeviceToDevice, st) != hipSuccess) { ret = FSI_ERR_HIP; goto done; }
-    }
-    int it = 0;
-    double change = 1e300;
-    std::vector<double> t0s(N), hp((size_t)(N + 1) * 4 * nchunk);
-    for (int i = 0; i < max_iter; ++i) {
-      // fine sweep over the slices that are not yet exact, batched in one call
-      const int Bf = N - i;
-      for (int l = i; l < N; ++l) t0s[l - i] = l * dl;
-      auto f0 = std::chrono::steady_clock::now();
-      PR_(run_propagate(pb, Bf, t0s.data(), dl, m, Ub + i * nd, Fv + i * nd, &tmp, st));
-      fine_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - f0).count();
-      sp->newton_total += tmp.newton_total;
-      sp->krylov_total += tmp.krylov_total;
-      if (hipMemcpyAsync(Up, Ub, (N + 1) * nd * sizeof(double), hipMemcpyDeviceToDevice, st) != hipSuccess) { ret = FSI_ERR_HIP; goto done; }
-      // sequential correction sweep
-      for (int l = 0; l < N; ++l) {
-        const double* cn = Cold + l * nd;
-        if (l >= i) {
-          const double t0 = l * dl;
-          auto c0 = std::chrono::steady_clock::now();
-          PR_(run_propagate(pb, 1, &t0, dl, M, Ub + l * nd, Cn, &tmp, st));
-          coarse_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - c0).count();
-          cn = Cn;
-        }
-        double th = 1.0;
-        if (l >= i && pb->p.parareal_theta != 0) {
-          // theta-Parareal weight from F(U^i_l) and C(U^{i+1}_l), per component, averaged
-          const int dim = pb->p.dim, nq = 3 * 2 * dim;
-          if (dim == 3)
-            k_theta_dots<3><<<nchunk, RED_T, 0, st>>>(F.nn, Fv + l * nd, Cn, chunk, tpart, nchunk);
-          else
-            k_theta_dots<2><<<nchunk, RED_T, 0, st>>>(F.nn, Fv + l * nd, Cn, chunk, tpart, nchunk);
-          if (hipMemcpyAsync(htp.data(), tpart, (size_t)nq * nchunk * sizeof(double), hipMemcpyDeviceToHost, st) !=
-                  hipSuccess ||
-              hipStreamSynchronize(st) != hipSuccess) { ret = FSI_ERR_HIP; goto done; }
-          double sum = 0.0;
-          int cnt = 0;
-          for (int c = 0; c < 2 * dim; ++c) {
-            double ff = 0.0, fg = 0.0, gg = 0.0;
-            for (int q = 0; q < nchunk; ++q) {
-              ff += htp[(size_t)(3 * c) * nchunk + q];
-              fg += htp[(size_t)(3 * c + 1) * nchunk + q];
-              gg += htp[(size_t)(3 * c + 2) * nchunk + q];
-            }
-            if (pb->p.parareal_theta == 1 && gg > 0.0 && ff > 0.0) { sum += fg / std::sqrt(gg * ff); ++cnt; }
-            if (pb->p.parareal_theta == 2 && gg > 0.0) { sum += fg / gg; ++cnt; }
-          }
-          th = cnt ? sum / cnt : 1.0;
-        }
-        k_parareal_update<<<256, TPB, 0, st>>>(nd, cn, Fv + l * nd, Cold + l * nd, Ub + (l + 1) * nd, th);
-        if (cn != Cold + l * nd)
-          if (hipMemcpyAsync(Cold + l * nd, Cn, nd * sizeof(double), hipMemcpyDeviceToDevice, st) != hipSuccess) { ret = FSI_ERR_HIP; goto done; }
-      }
-      if (pb->p.dim == 3)
-        k_change_norms<3><<<dim3(nchunk, N + 1), RED_T, 0, st>>>(F.nn, Ub, Up, chunk, part, nchunk);
-      else
-        k_change_norms<2><<<dim3(nchunk, N + 1), RED_T, 0, st>>>(F.nn, Ub, Up, chunk, part, nchunk);
-      if (hipGetLastError() != hipSuccess) { ret = FSI_ERR_HIP; goto done; }
-      if (hipMemcpyAsync(hp.data(), part, hp.size() * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
-          hipStreamSynchronize(st) != hipSuccess) { ret = FSI_ERR_HIP; goto done; }
-      change = 0.0;
-      for (int l = 0; l <= N; ++l)
-        for (int f = 0; f < 2; ++f) {
-          double dd = 0.0, nn2 = 0.0;
-          for (int c = 0; c < nchunk; ++c) {
-            dd += hp[((size_t)l * 4 + 2 * f) * nchunk + c];
-            nn2 += hp[((size_t)l * 4 + 2 * f + 1) * nchunk + c];
-          }
-          const double r = nn2 > 0.0 ? std::sqrt(dd / nn2) : std::sqrt(dd);
-          change = std::max(change, r);
-        }
-      it = i + 1;
-      sp->parareal_iters = it;   // completed iterations, also when a later one fails
-      if (change < tol) break;
-    }
-    sp->parareal_iters = it;
-    if (!(change < tol) && it < N) ret = FSI_ERR_PARAREAL;
-  }
-done:
-#undef PR_
+  const fsi_status ret =
+      pb->p.parareal_pipeline > 0
+          ? parareal_pipelined(pb, T, N, m, M, tol, max_iter, U0, Ub, sp, coarse_ms, fine_ms, st)
+          : parareal_plain(pb, T, N, m, M, tol, max_iter, U0, Ub, sp, coarse_ms, fine_ms, st);
   (void)hipStreamSynchronize(st);
-  cleanup();
   sp->stage_ms[5] = coarse_ms;
   sp->stage_ms[6] = fine_ms;
-  sp->stage_ms[4] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+  sp->stage_ms[4] = ms_since(t_start);
   return ret;
 }
 

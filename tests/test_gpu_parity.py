@@ -211,11 +211,13 @@ def test_fine_propagate_parity_mixed(fsi):
         assert max(err.values()) <= 1e-6, (b, err)
 
 
-def test_parareal_K_equals_N(fsi):
-    """Parareal with N iterations reproduces the sequential fine solution (Section 4.1 statement)."""
+@pytest.mark.parametrize("pipeline", [0, 2])
+def test_parareal_K_equals_N(fsi, pipeline):
+    """Parareal with N iterations reproduces the sequential fine solution (Section 4.1 statement),
+    with the plain and the pipelined schedule."""
     p = synth.workload("c1", T=0.06, N=3, dt_fine=0.01, dt_coarse=0.02, seed=3)
-    _say("case: parareal K=N c1-small N=3")
-    prob = fsi.Problem(fsi.make_params(p, precision="fp64", max_batch=3))
+    _say("case: parareal K=N c1-small N=3 pipeline", pipeline)
+    prob = fsi.Problem(fsi.make_params(p, precision="fp64", max_batch=3, parareal_pipeline=pipeline))
     D = Discretization(p)
     U0 = np.zeros((D.mesh.n_nodes, 5))
     seq = P.sequential(D, p, U0)
@@ -295,3 +297,35 @@ def test_dissipation_matched_coarse_step_parity(fsi):
     err = field_rel(_host(Uout)[0], ref, norm="l2")
     assert max(err.values()) <= 1e-10, err
     prob.close()
+
+
+def _parareal_gpu(fsi, p, tol, max_iter, **solver):
+    prob = fsi.Problem(fsi.make_params(p, precision="fp64", max_batch=p["N"], **solver))
+    U0 = torch.zeros(prob.n_nodes, 5, dtype=torch.float64, device="cuda")
+    prob.initial_state(U0)
+    Ub = torch.zeros(p["N"] + 1, prob.n_nodes, 5, dtype=torch.float64, device="cuda")
+    code, st = prob.parareal_run(p["T"], p["N"], p["m"], p["M"], tol, max_iter, U0, Ub, raise_on_error=False)
+    out = _host(Ub)
+    prob.close()
+    return code, st, out
+
+
+@pytest.mark.parametrize("G,theta", [(1, 0), (2, 0), (3, 1)])
+def test_pipelined_parareal_equals_plain(fsi, G, theta):
+    """The pipelined schedule (fine chunks of G slices overlapped with the correction sweep)
+    computes the iterates of the plain schedule: same boundary states, same iteration count,
+    for chunk sizes that do and do not divide N, with and without the theta weight."""
+    p = synth.workload("c1", T=0.1, N=5, dt_fine=0.01, dt_coarse=0.02, seed=2)
+    _say("case: pipelined parareal c1-small N=5 G", G, "theta", theta)
+    c0, s0, U0 = _parareal_gpu(fsi, p, 0.0, 3, parareal_theta=theta)
+    c1, s1, U1 = _parareal_gpu(fsi, p, 0.0, 3, parareal_theta=theta, parareal_pipeline=G)
+    assert c0 == c1 and s0.parareal_iters == s1.parareal_iters == 3
+    assert s0.newton_total == s1.newton_total, (s0.newton_total, s1.newton_total)
+    scale = np.abs(U0).max()
+    assert np.abs(U1 - U0).max() <= 1e-13 * scale, np.abs(U1 - U0).max() / scale
+    # with a tolerance both schedules stop after the same iteration
+    c0, s0, U0 = _parareal_gpu(fsi, p, 1e-6, 5, parareal_theta=theta)
+    c1, s1, U1 = _parareal_gpu(fsi, p, 1e-6, 5, parareal_theta=theta, parareal_pipeline=G)
+    _say("iterations", s0.parareal_iters, s1.parareal_iters, "ms plain", s0.stage_ms[4], "pipelined", s1.stage_ms[4])
+    assert c0 == c1 and s0.parareal_iters == s1.parareal_iters
+    assert np.abs(U1 - U0).max() <= 1e-13 * np.abs(U0).max()
