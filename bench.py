@@ -60,12 +60,13 @@ def counter_traffic(kernel_family, prec):
 
 
 def kernel_source_hash(fn):
-    """Hash of the solver kernels' source (solver.hip, which holds the kernel and its
-    device helpers, and the shared layout header), tagged with the kernel name: any
-    edit there invalidates counter figures taken before it."""
+    """Hash of the dominant kernel's source (vanka.hip, which holds the kernel and the
+    factor kernel that writes its inverses, stencil.h with its device helpers, and the
+    shared layout header), tagged with the kernel name: any edit there invalidates
+    counter figures taken before it."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_1907_01252_amd", "csrc")
-    src = open(os.path.join(csrc, "solver.hip")).read() + open(os.path.join(csrc, "fsi_internal.h")).read()
+    src = "".join(open(os.path.join(csrc, f)).read() for f in ("vanka.hip", "stencil.h", "fsi_internal.h"))
     assert f" {fn}(" in src, fn
     return hashlib.sha256((fn + src).encode()).hexdigest()[:16]
 

@@ -1,100 +1,15 @@
-// Batched linear-solver kernels: block-stencil SpMV, Vanka patch inverses and
-// colored multiplicative Vanka sweeps, multigrid transfers, the coarsest-level
-// block-tridiagonal direct solve (2d) and the FGMRES building blocks.  Every
+// Batched linear-solver kernels: block-stencil SpMV, transposed products of the
+// adjoint, multigrid transfers, the coarsest-level block-tridiagonal direct
+// solve (2d) and the FGMRES building blocks (the Vanka kernels are in
+// vanka.hip).  Every
 // kernel takes the slice index from blockIdx.y and skips slices whose active
 // flag is 0.  S is the storage and arithmetic type of the linear solve
 // (double, or float in the mixed-precision path); D the space dimension.
-#include "fsi_internal.h"
+#include "stencil.h"
 
 namespace fsi {
 
 using D2 = Dm<2>;
-
-// Neighbour node offsets of the 3^D block stencil of node (i, j, k), per axis
-// (offset index 0, 1, 2 for -1, 0, +1), without branches: an out-of-mesh
-// neighbour maps onto the node itself.  The Jacobian stores zeros in those
-// slots (and the pressure stencil for such pairs), so the product adds exactly
-// nothing and every load of a row can be in flight at once.
-struct Nbr {
-  int ox[3], oy[3], oz[3];
-};
-template <int D>
-__device__ inline Nbr nbr_offsets(const Geom& g, int i, int j, int k) {
-  const int W = g.nx + 1, P = W * (g.ny + 1);
-  Nbr o;
-  o.ox[0] = i > 0 ? -1 : 0;
-  o.ox[1] = 0;
-  o.ox[2] = i < g.nx ? 1 : 0;
-  o.oy[0] = j > 0 ? -W : 0;
-  o.oy[1] = 0;
-  o.oy[2] = j < g.ny ? W : 0;
-  o.oz[0] = D == 3 && k > 0 ? -P : 0;
-  o.oz[1] = 0;
-  o.oz[2] = D == 3 && k < g.nz ? P : 0;
-  return o;
-}
-
-// k * sum_q pst[q][n] x_p(neighbour q) over the 5^D pressure stencil (clamped
-// neighbours, zero coefficients outside the mesh and on Dirichlet pressure rows).
-template <int D, class S>
-__device__ inline S pst_row(const Geom& g, double k, int n, int i, int j, int kk, const S* __restrict__ xb) {
-  FSI_DIM(D);
-  int cx[5], cy[5], cz[5];
-#pragma unroll
-  for (int d = 0; d < 5; ++d) {
-    cx[d] = min(max(i + d - 2, 0), g.nx);
-    cy[d] = (g.nx + 1) * min(max(j + d - 2, 0), g.ny);
-    cz[d] = D == 3 ? (g.nx + 1) * (g.ny + 1) * min(max(kk + d - 2, 0), g.nz) : 0;
-  }
-  S ap = 0;
-#pragma unroll
-  for (int q = 0; q < NPST; ++q)
-    ap += (S)g.pst[(size_t)q * g.nn + n] * xb[(size_t)(cx[q % 5] + cy[(q / 5) % 5] + cz[q / 25]) * NC + PC];
-  return (S)k * ap;
-}
-
-// Row r of the block stencil at node n times x: the sum over the slots of the
-// stored entries of row r (jn: the node's position in the tiled Jacobian).  In
-// the compressed layout a displacement row holds (v_i, u_i) only; the row kind
-// is uniform over a wave and tested once, outside the slot loops, so that the
-// loads of all slots (3d: of one plane of slots) are in flight together.
-template <int D, class S, bool CJ>
-__device__ inline S stencil_row(const S* __restrict__ jn, const S* __restrict__ xb, int n, int r, const Nbr& nb) {
-  FSI_DIM(D);
-  S acc = 0;
-  const int e0 = jrow_off<D, CJ>(r);
-  constexpr int NZ = D == 3 ? 3 : 1;
-  if (CJ && r >= D && r < 2 * D) {
-#pragma unroll 1
-    for (int sz = 0; sz < NZ; ++sz) {
-      const int oz = sz == 0 ? nb.oz[0] : (sz == 1 ? 0 : nb.oz[2]);
-#pragma unroll
-      for (int sy = 0; sy < 3; ++sy)
-#pragma unroll
-        for (int sx = 0; sx < 3; ++sx) {
-          const int s = sx + 3 * sy + 9 * sz;
-          const S* xv = xb + (size_t)(n + nb.ox[sx] + nb.oy[sy] + oz) * NC;
-          acc += jn[jent<D, CJ>(s, e0)] * xv[r - D];
-          acc += jn[jent<D, CJ>(s, e0 + 1)] * xv[r];
-        }
-    }
-  } else {
-#pragma unroll 1
-    for (int sz = 0; sz < NZ; ++sz) {
-      const int oz = sz == 0 ? nb.oz[0] : (sz == 1 ? 0 : nb.oz[2]);
-#pragma unroll
-      for (int sy = 0; sy < 3; ++sy)
-#pragma unroll
-        for (int sx = 0; sx < 3; ++sx) {
-          const int s = sx + 3 * sy + 9 * sz;
-          const S* xv = xb + (size_t)(n + nb.ox[sx] + nb.oy[sy] + oz) * NC;
-#pragma unroll
-          for (int c = 0; c < NC; ++c) acc += jn[jent<D, CJ>(s, e0 + c)] * xv[c];
-        }
-    }
-  }
-  return acc;
-}
 
 // ------------------------------------------------------------------ SpMV
 // y = D (A x)            (b == nullptr)
@@ -234,184 +149,6 @@ __global__ void k_adjoint_rhs(Geom g, const double* __restrict__ rhs, double* __
   if (n >= g.nn) return;
   const uint8_t m = g.dmask[n];
   for (int c = 0; c < D2::NC; ++c) Res[(size_t)n * D2::NC + c] = (m & (1u << c)) ? 0.0 : -rhs[(size_t)n * D2::NC + c];
-}
-
-// ------------------------------------------------------- Vanka patch inverse
-// One lane group (vf_lanes lanes) inverts the NE x NE patch matrix of one cell
-// (rows = local unknowns NC a + c) by Gauss-Jordan with partial pivoting.
-// [A | I] lives in LDS, lane r owning row r; per column the pivot row is
-// found by a shuffle reduction and every other row eliminates the column with
-// the (unscaled) pivot row.  Rows are scaled by their pivots at the end, which
-// gives the same inverse as scaling at each step.  Ainv is stored per colour:
-// Ainv[b][off_c*NE*NE + e*nc_c + idx], e = NE * row + column.
-template <int D, class S, bool CJ>
-__global__ void __launch_bounds__(vf_lanes<D>() * vf_patches<D>()) k_vanka_factor(Geom g, double k,
-                                                                                  const S* __restrict__ J,
-                                                                                  S* __restrict__ Ainv, int vc,
-                                                                                  const int* __restrict__ active) {
-  FSI_DIM(D);
-  constexpr int GL = vf_lanes<D>(), NP = vf_patches<D>(), LD = 2 * NE + 1;
-  __shared__ double M[NP][NE][LD];
-  const int bs = blockIdx.y;
-  if (active && !active[bs]) return;   // uniform over the block
-  const int grp = threadIdx.x / GL, lane = threadIdx.x % GL;
-  const int cell = blockIdx.x * NP + grp;
-  const bool live = cell < g.ncell;
-  int ci = 0, cj = 0, ck = 0;
-  if (live) cell_ijk<D>(g, cell, ci, cj, ck);
-  double(*Mp)[LD] = M[grp];
-  if (lane < NE) {
-    const int a = lane / NC, rc = lane % NC;
-    const int ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
-    const int na = node_at(g, ci + ax, cj + ay, ck + az);
-    if (live) {
-      const S* jn = J + (size_t)bs * jslice<D, CJ>(g) + jnode_n<D, CJ>(g, na, 0);
-      const bool pst_row = (rc == PC) && !(g.dmask[na] & dm_p<D>());
-      for (int bb = 0; bb < NL; ++bb) {
-        const int dx = (bb & 1) - ax, dy = ((bb >> 1) & 1) - ay, dz = ((bb >> 2) & 1) - az;
-        const int s = slot_of<D>(dx, dy, dz);
-        for (int c = 0; c < NC; ++c) {
-          const int e = jentry<D, CJ>(rc, c);
-          Mp[lane][NC * bb + c] = e >= 0 ? (double)jn[jent<D, CJ>(s, e)] : 0.0;
-        }
-        if (pst_row) Mp[lane][NC * bb + PC] += k * g.pst[(size_t)pslot_of<D>(dx, dy, dz) * g.nn + na];
-      }
-    } else {
-      for (int c = 0; c < NE; ++c) Mp[lane][c] = (c == lane) ? 1.0 : 0.0;
-    }
-    for (int c = 0; c < NE; ++c) Mp[lane][NE + c] = (c == lane) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  bool used = lane >= NE;
-  int mycol = 0;
-  for (int jc = 0; jc < NE; ++jc) {
-    const double v = lane < NE ? Mp[lane][jc] : 0.0;
-    double cand = used ? -1.0 : fabs(v);
-    int idx = lane;
-#pragma unroll
-    for (int off = GL / 2; off > 0; off >>= 1) {
-      const double oc = __shfl_xor(cand, off, GL);
-      const int oi = __shfl_xor(idx, off, GL);
-      if (oc > cand || (oc == cand && oi < idx)) { cand = oc; idx = oi; }
-    }
-    double pv = Mp[idx][jc];
-    if (pv == 0.0) pv = 1.0;   // singular patch: leave the column alone
-    if (lane == idx) { used = true; mycol = jc; }
-    const double f = (lane < NE && lane != idx) ? v / pv : 0.0;
-    if (f != 0.0)
-      for (int c = jc; c < 2 * NE; ++c) Mp[lane][c] -= f * Mp[idx][c];
-    __syncthreads();
-  }
-  if (live && lane < NE) {
-    int col, idx;
-    ColorInfo L;
-    cell_colour<D>(g, ci, cj, ck, vc, col, idx, L);
-    const double d = Mp[lane][mycol] != 0.0 ? 1.0 / Mp[lane][mycol] : 1.0;
-    const int q = idx / vc, t = idx - q * vc;
-    S* out = Ainv + (size_t)bs * ainv_slice<D>(g.ncell) + ((size_t)L.off + (size_t)q * vc) * NE * NE + t;
-    for (int c = 0; c < NE; ++c) out[(size_t)(NE * mycol + c) * vc] = (S)(Mp[lane][NE + c] * d);
-  }
-}
-
-// ------------------------------------------------------ colored Vanka pass
-// One multiplicative pass over the cells of one colour, residual and patch
-// update fused: every cell P of the colour forms r_P = b_P - (A x_old)_P on its
-// nodes and writes x_new[P] = x_old[P] + omega Ainv_P r_P.  The cells of one
-// colour do not share nodes, so each node is written by at most one patch;
-// the nodes no patch of the colour covers are copied.  x_old and x_new are
-// different buffers (other patches read x_old at the shared neighbours).
-// zero_in: x_old is taken as zero (first pass of a cycle): r_P = b_P and the
-// uncovered nodes get zero.
-// Thread mapping: a block of VC consecutive cells of the colour has NC waves,
-// wave r forming row r of every patch node.  A lane group of 2 VC lanes takes
-// one node pair (a, a + 1) of the VC cells, so within one cell row a wave
-// reads runs of 2 VC consecutive nodes and the inverses in VC-cell runs.
-// 2d uses VC = 16 (two groups: pairs (0,1) and (2,3)).  3d uses VC = 32 on
-// large levels (one group; each thread loops over the four pairs) and VC = 8
-// on small ones (four groups, one pair each: more blocks for few cells).  The
-// NE patch residuals meet in LDS; the same thread then forms patch rows
-// NC a + r of Ainv_P r_P.  Extra blocks past the patch blocks copy the
-// uncovered nodes.
-// Minimum waves per SIMD requested for the fused pass: in 2d FP32 the register
-// budget of 6 waves (85 VGPRs) keeps enough waves resident to hide latency.
-template <int D, class S>
-constexpr int vanka_waves_per_simd() {
-  return (D == 2 && sizeof(S) == 4) ? 6 : 1;
-}
-template <int D, class S, int VC, bool CJ>
-__global__ void __launch_bounds__(Dm<D>::NC * 64, (vanka_waves_per_simd<D, S>())) k_vanka_color(Geom g, double k, int color, S omega, int zero_in,
-                                                                const S* __restrict__ J, const S* __restrict__ Ainv,
-                                                                const S* __restrict__ b, const S* __restrict__ xo,
-                                                                S* __restrict__ xn, const int* __restrict__ active) {
-  FSI_DIM(D);
-  static_assert(VC == 8 || VC == 16 || VC == 32, "cells per block");
-  __shared__ S rs[NE][VC];
-  const int bs = blockIdx.y;
-  if (active && !active[bs]) return;   // uniform over the block
-  const ColorInfo L = color_info<D>(g, color, VC);
-  const int nc = L.nc;
-  const int npb = (nc + VC - 1) / VC;
-  const S* xob = xo + (size_t)bs * g.nn * NC;
-  S* xnb = xn + (size_t)bs * g.nn * NC;
-  const int cx = color & 1, cy = (color >> 1) & 1, cz = (color >> 2) & 1;
-  if ((int)blockIdx.x >= npb) {
-    const int t = ((int)blockIdx.x - npb) * (NC * 64) + threadIdx.x;
-    if (t >= g.nn) return;
-    int ni, nj, nk;
-    node_ijk<D>(g, t, ni, nj, nk);
-    const int ci = ni - ((ni - cx) & 1), cj = nj - ((nj - cy) & 1), ck = nk - ((nk - cz) & 1);
-    const bool covered = ci >= 0 && cj >= 0 && ci < g.nx && cj < g.ny && (D == 2 || (ck >= 0 && ck < g.nz));
-    if (!covered)
-      for (int c = 0; c < NC; ++c) xnb[(size_t)t * NC + c] = zero_in ? (S)0 : xob[(size_t)t * NC + c];
-    return;
-  }
-  // lane -> (cell jc of the block, node-pair group gp); the G = 64 / (2 VC)
-  // groups of a wave take the node pairs (2 gp, 2 gp + 1), and each thread
-  // loops over the NQ = NL / (2 G) pairs gp + G q
-  const int r = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  constexpr int G = 64 / (2 * VC), NQ = NL / (2 * G), QS = 2 * G;
-  const int jc = (lane % (2 * VC)) >> 1;
-  const int a0 = (lane & 1) + 2 * (lane / (2 * VC));
-  const int idx = blockIdx.x * VC + jc;
-  const bool live = idx < nc;
-  int ci = 0, cj = 0, ck = 0;
-  if (live) {
-    const int ix = idx % L.ncx, rest = idx / L.ncx;
-    ci = 2 * ix + cx;
-    cj = 2 * (rest % L.ncy) + cy;
-    ck = D == 3 ? 2 * (rest / L.ncy) + cz : 0;
-#pragma unroll 1
-    for (int q = 0; q < NQ; ++q) {
-      const int a = a0 + q * QS;
-      const int n = node_at(g, ci + (a & 1), cj + ((a >> 1) & 1), ck + ((a >> 2) & 1));
-      S acc = 0;
-      if (!zero_in) {
-        int i, j, kk;
-        node_ijk<D>(g, n, i, j, kk);
-        // (3d: the copy whose tiles start where this colour's node runs start)
-        const S* jn = J + (size_t)bs * jslice<D, CJ>(g) + jnode<D, CJ>(g, i, j + (g.ny + 1) * kk, cx);
-        acc = stencil_row<D, S, CJ>(jn, xob, n, r, nbr_offsets<D>(g, i, j, kk));
-        if (r == PC) acc += pst_row<D, S>(g, k, n, i, j, kk, xob);
-      }
-      rs[NC * a + r][jc] = b[((size_t)bs * g.nn + n) * NC + r] - acc;
-    }
-  }
-  __syncthreads();
-  if (!live) return;
-  const S* ai =
-      Ainv + (size_t)bs * ainv_slice<D>(g.ncell) + ((size_t)L.off + (size_t)blockIdx.x * VC) * NE * NE + jc;
-#pragma unroll 1
-  for (int q = 0; q < NQ; ++q) {
-    const int a = a0 + q * QS;
-    const int row = NC * a + r;
-    S z = 0;
-    constexpr int EU = NQ == 1 ? NE : 8;   // looping threads: bounded loads in flight (registers)
-#pragma unroll EU
-    for (int e = 0; e < NE; ++e) z += ai[(NE * row + e) * VC] * rs[e][jc];
-    const int n = node_at(g, ci + (a & 1), cj + ((a >> 1) & 1), ck + ((a >> 2) & 1));
-    const size_t o = (size_t)n * NC + r;
-    xnb[o] = (zero_in ? (S)0 : xob[o]) + omega * z;
-  }
 }
 
 // --------------------------------------------------------- grid transfers
@@ -1056,10 +793,6 @@ __global__ void k_convert(size_t n, const A* __restrict__ X, B2* __restrict__ Y)
 #define FSI_INST_DS(D, S)                                                                                         \
   template __global__ void k_spmv<D, S, true>(Geom, double, const S*, const S*, const S*, const double*, S*,     \
                                               const int*);                                                       \
-  template __global__ void k_vanka_factor<D, S, true>(Geom, double, const S*, S*, int, const int*);              \
-  template __global__ void k_vanka_color<D, S, (D == 2 ? 16 : 32), true>(Geom, double, int, S, int, const S*,   \
-                                                                         const S*, const S*, const S*, S*,      \
-                                                                         const int*);                            \
   template __global__ void k_restrict<D, S>(Geom, Geom, const S*, S*, const int*);                               \
   template __global__ void k_prolong_add<D, S>(Geom, Geom, const S*, S*, const int*);                            \
   template __global__ void k_newton_update<D, S>(int, double*, const S*, int, double*, int, const int*);
@@ -1081,18 +814,9 @@ __global__ void k_convert(size_t n, const A* __restrict__ X, B2* __restrict__ Y)
   template __global__ void k_fill<S>(size_t, S*, S);
 FSI_INST_S(double)
 FSI_INST_S(float)
-template __global__ void k_vanka_color<3, double, 8, true>(Geom, double, int, double, int, const double*,
-                                                           const double*, const double*, const double*, double*,
-                                                           const int*);
-template __global__ void k_vanka_color<3, float, 8, true>(Geom, double, int, float, int, const float*, const float*,
-                                                          const float*, const float*, float*, const int*);
 // full-layout operators of the (2d, FP64) transposed adjoint system
 template __global__ void k_spmv<2, double, false>(Geom, double, const double*, const double*, const double*,
                                                   const double*, double*, const int*);
-template __global__ void k_vanka_factor<2, double, false>(Geom, double, const double*, double*, int, const int*);
-template __global__ void k_vanka_color<2, double, 16, false>(Geom, double, int, double, int, const double*,
-                                                             const double*, const double*, const double*, double*,
-                                                             const int*);
 template __global__ void k_coarse_factor<double, false>(Geom, double, const double*, int, int, double*, double*,
                                                         double*, const int*);
 template __global__ void k_change_norms<2>(int, const double*, const double*, int, double*, int);

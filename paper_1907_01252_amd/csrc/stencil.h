@@ -1,0 +1,95 @@
+// Device helpers of the block-stencil operator, shared by the SpMV and the
+// fused Vanka pass: neighbour offsets, the pressure-stabilisation row and one
+// row of the block stencil times a vector.
+#pragma once
+#include "fsi_internal.h"
+
+namespace fsi {
+
+// Neighbour node offsets of the 3^D block stencil of node (i, j, k), per axis
+// (offset index 0, 1, 2 for -1, 0, +1), without branches: an out-of-mesh
+// neighbour maps onto the node itself.  The Jacobian stores zeros in those
+// slots (and the pressure stencil for such pairs), so the product adds exactly
+// nothing and every load of a row can be in flight at once.
+struct Nbr {
+  int ox[3], oy[3], oz[3];
+};
+template <int D>
+__device__ inline Nbr nbr_offsets(const Geom& g, int i, int j, int k) {
+  const int W = g.nx + 1, P = W * (g.ny + 1);
+  Nbr o;
+  o.ox[0] = i > 0 ? -1 : 0;
+  o.ox[1] = 0;
+  o.ox[2] = i < g.nx ? 1 : 0;
+  o.oy[0] = j > 0 ? -W : 0;
+  o.oy[1] = 0;
+  o.oy[2] = j < g.ny ? W : 0;
+  o.oz[0] = D == 3 && k > 0 ? -P : 0;
+  o.oz[1] = 0;
+  o.oz[2] = D == 3 && k < g.nz ? P : 0;
+  return o;
+}
+
+// k * sum_q pst[q][n] x_p(neighbour q) over the 5^D pressure stencil (clamped
+// neighbours, zero coefficients outside the mesh and on Dirichlet pressure rows).
+template <int D, class S>
+__device__ inline S pst_row(const Geom& g, double k, int n, int i, int j, int kk, const S* __restrict__ xb) {
+  FSI_DIM(D);
+  int cx[5], cy[5], cz[5];
+#pragma unroll
+  for (int d = 0; d < 5; ++d) {
+    cx[d] = min(max(i + d - 2, 0), g.nx);
+    cy[d] = (g.nx + 1) * min(max(j + d - 2, 0), g.ny);
+    cz[d] = D == 3 ? (g.nx + 1) * (g.ny + 1) * min(max(kk + d - 2, 0), g.nz) : 0;
+  }
+  S ap = 0;
+#pragma unroll
+  for (int q = 0; q < NPST; ++q)
+    ap += (S)g.pst[(size_t)q * g.nn + n] * xb[(size_t)(cx[q % 5] + cy[(q / 5) % 5] + cz[q / 25]) * NC + PC];
+  return (S)k * ap;
+}
+
+// Row r of the block stencil at node n times x: the sum over the slots of the
+// stored entries of row r (jn: the node's position in the tiled Jacobian).  In
+// the compressed layout a displacement row holds (v_i, u_i) only; the row kind
+// is uniform over a wave and tested once, outside the slot loops, so that the
+// loads of all slots (3d: of one plane of slots) are in flight together.
+template <int D, class S, bool CJ>
+__device__ inline S stencil_row(const S* __restrict__ jn, const S* __restrict__ xb, int n, int r, const Nbr& nb) {
+  FSI_DIM(D);
+  S acc = 0;
+  const int e0 = jrow_off<D, CJ>(r);
+  constexpr int NZ = D == 3 ? 3 : 1;
+  if (CJ && r >= D && r < 2 * D) {
+#pragma unroll 1
+    for (int sz = 0; sz < NZ; ++sz) {
+      const int oz = sz == 0 ? nb.oz[0] : (sz == 1 ? 0 : nb.oz[2]);
+#pragma unroll
+      for (int sy = 0; sy < 3; ++sy)
+#pragma unroll
+        for (int sx = 0; sx < 3; ++sx) {
+          const int s = sx + 3 * sy + 9 * sz;
+          const S* xv = xb + (size_t)(n + nb.ox[sx] + nb.oy[sy] + oz) * NC;
+          acc += jn[jent<D, CJ>(s, e0)] * xv[r - D];
+          acc += jn[jent<D, CJ>(s, e0 + 1)] * xv[r];
+        }
+    }
+  } else {
+#pragma unroll 1
+    for (int sz = 0; sz < NZ; ++sz) {
+      const int oz = sz == 0 ? nb.oz[0] : (sz == 1 ? 0 : nb.oz[2]);
+#pragma unroll
+      for (int sy = 0; sy < 3; ++sy)
+#pragma unroll
+        for (int sx = 0; sx < 3; ++sx) {
+          const int s = sx + 3 * sy + 9 * sz;
+          const S* xv = xb + (size_t)(n + nb.ox[sx] + nb.oy[sy] + oz) * NC;
+#pragma unroll
+          for (int c = 0; c < NC; ++c) acc += jn[jent<D, CJ>(s, e0 + c)] * xv[c];
+        }
+    }
+  }
+  return acc;
+}
+
+}  // namespace fsi
