@@ -135,15 +135,219 @@ __device__ inline void mat_mul(const T (&A)[D][D], const U2 (&B)[D][D], T (&C)[D
     }
 }
 
+// Pointwise coefficients of the element residual at one quadrature point: the
+// residual of local row (a, i) is the quadrature sum of w times
+//   momentum row i:      am[i] N_a + sum_r bm[i][r] d_r N_a
+//   pressure row:        ap N_a
+//   displacement row i:  au[i] N_a + sum_r bu[i][r] d_r N_a  (bu only on rows owned by the cell)
+// (the outflow face adds its own term).  Fluid cells: ALE momentum, divergence
+// and harmonic extension; solid cells: St. Venant-Kirchhoff momentum and the
+// kinematic equation.
+template <int D, class T>
+struct Flux {
+  T am[D], bm[D][D], ap, au[D], bu[D][D];
+};
+
+// f, o: new and old state at the point (scalar types TU, TO); TR the common type.
+template <int D, class TU, class TO, class TR>
+__device__ void point_flux(const Cell<D>& c, const StepPar& sp, const Pt<D, TU>& f, const Pt<D, TO>& o,
+                           Flux<D, TR>& fl) {
+  const double k = sp.k, th = sp.theta;
+  const double kth = k * th, k1th = k * (1.0 - th);
+  const double rf = sp.rho_f, rn = sp.rho_f * sp.nu_f;
+  TU F[D][D], J, Fi[D][D];
+  TO Fo[D][D], Jo, Foi[D][D];
+  def_grad<D, TU>(f.gu, F, J, Fi);
+  def_grad<D, TO>(o.gu, Fo, Jo, Foi);
+  if (!c.solid) {
+    // ALE time derivative with the means of the step
+    TR gub[D][D], Fb[D][D], Jbd, Fbi[D][D], gvb[D][D];
+    for (int i = 0; i < D; ++i)
+      for (int r = 0; r < D; ++r) {
+        gub[i][r] = 0.5 * (f.gu[i][r] + o.gu[i][r]);
+        gvb[i][r] = 0.5 * (f.gv[i][r] + o.gv[i][r]);
+      }
+    def_grad<D, TR>(gub, Fb, Jbd, Fbi);
+    const TR Jb = 0.5 * (J + Jo);
+    TR A[D][D];
+    mat_mul<D, TR, TR>(gvb, Fbi, A);
+    for (int i = 0; i < D; ++i) {
+      TR adv = A[i][0] * (f.u[0] - o.u[0]);
+      for (int r = 1; r < D; ++r) adv += A[i][r] * (f.u[r] - o.u[r]);
+      fl.am[i] = rf * Jb * ((f.v[i] - o.v[i]) - adv);
+    }
+    // convection, new and old
+    TU C[D][D];
+    TO Co[D][D];
+    mat_mul<D, TU, TU>(f.gv, Fi, C);
+    mat_mul<D, TO, TO>(o.gv, Foi, Co);
+    for (int i = 0; i < D; ++i) {
+      TU cn = C[i][0] * f.v[0];
+      TO co = Co[i][0] * o.v[0];
+      for (int r = 1; r < D; ++r) { cn += C[i][r] * f.v[r]; co += Co[i][r] * o.v[r]; }
+      fl.am[i] += kth * rf * J * cn;
+      fl.am[i] += k1th * rf * Jo * co;
+    }
+    // Piola-transformed Cauchy stress J sigma F^{-T}; the pressure is the new one in both parts
+    for (int i = 0; i < D; ++i)
+      for (int r = 0; r < D; ++r) {
+        TU pn = TU(0.0);
+        TR po = TR(0.0);
+        for (int cc = 0; cc < D; ++cc) {
+          const TU s = rn * (C[i][cc] + C[cc][i]) - (i == cc ? f.p : TU(0.0));
+          const TR so = rn * (Co[i][cc] + Co[cc][i]) - (i == cc ? f.p : TU(0.0));
+          pn += s * Fi[r][cc];
+          po += so * Foi[r][cc];
+        }
+        fl.bm[i][r] = kth * (J * pn) + k1th * (Jo * po);
+      }
+    TU trc = C[0][0];
+    for (int i = 1; i < D; ++i) trc += C[i][i];
+    fl.ap = k * J * trc;
+    for (int i = 0; i < D; ++i) {
+      fl.au[i] = TR(0.0);
+      for (int r = 0; r < D; ++r) fl.bu[i][r] = k * (th * f.gu[i][r] + (1.0 - th) * o.gu[i][r]);
+    }
+  } else {
+    // St. Venant-Kirchhoff first Piola stress F Sigma(E), E = (F^T F - I)/2
+    const double mu = sp.mu_s, lam = sp.lambda_s;
+    TU E[D][D], S[D][D];
+    TO Eo[D][D], So[D][D];
+    for (int r = 0; r < D; ++r)
+      for (int s = 0; s < D; ++s) {
+        TU e = F[0][r] * F[0][s];
+        TO eo = Fo[0][r] * Fo[0][s];
+        for (int i = 1; i < D; ++i) { e += F[i][r] * F[i][s]; eo += Fo[i][r] * Fo[i][s]; }
+        E[r][s] = 0.5 * (e - (r == s ? 1.0 : 0.0));
+        Eo[r][s] = 0.5 * (eo - (r == s ? 1.0 : 0.0));
+      }
+    TU trE = E[0][0];
+    TO trEo = Eo[0][0];
+    for (int r = 1; r < D; ++r) { trE += E[r][r]; trEo += Eo[r][r]; }
+    for (int r = 0; r < D; ++r)
+      for (int s = 0; s < D; ++s) {
+        S[r][s] = 2.0 * mu * E[r][s] + (r == s ? lam * trE : TU(0.0));
+        So[r][s] = 2.0 * mu * Eo[r][s] + (r == s ? lam * trEo : TO(0.0));
+      }
+    for (int i = 0; i < D; ++i)
+      for (int r = 0; r < D; ++r) {
+        TU pn = F[i][0] * S[0][r];
+        TO po = Fo[i][0] * So[0][r];
+        for (int s = 1; s < D; ++s) { pn += F[i][s] * S[s][r]; po += Fo[i][s] * So[s][r]; }
+        fl.bm[i][r] = kth * pn + k1th * po;
+      }
+    fl.ap = TR(0.0);
+    for (int i = 0; i < D; ++i) {
+      fl.am[i] = sp.rho_s * (f.v[i] - o.v[i]);
+      fl.au[i] = (f.u[i] - o.u[i]) - k * (th * f.v[i] + (1.0 - th) * o.v[i]);
+      for (int r = 0; r < D; ++r) fl.bu[i][r] = TR(0.0);
+    }
+  }
+}
+
+// R[NC a + c] += w (coefficients of fl against the test functions of local node a)
+template <int D, class T>
+__device__ inline void add_flux(const Cell<D>& c, const Flux<D, T>& fl, const double (&N)[Dm<D>::NL],
+                                const double (&G)[Dm<D>::NL][D], double w, T (&R)[Dm<D>::NE]) {
+  FSI_DIM(D);
+  for (int a = 0; a < NL; ++a) {
+    for (int i = 0; i < D; ++i) {
+      T s = fl.am[i] * N[a];
+      for (int r = 0; r < D; ++r) s += fl.bm[i][r] * G[a][r];
+      R[NC * a + i] += w * s;
+    }
+    R[NC * a + PC] += w * fl.ap * N[a];
+    for (int i = 0; i < D; ++i) {
+      T s = fl.au[i] * N[a];
+      if (c.urow[a])
+        for (int r = 0; r < D; ++r) s += fl.bu[i][r] * G[a][r];
+      R[NC * a + D + i] += w * s;
+    }
+  }
+}
+
+// Outflow (do-nothing) correction at a point of the face x = L, outward normal
+// e_x: bt[i] = k theta rho nu J (F^{-T} grad v^T F^{-T} n)_i + the old-state part;
+// momentum row (a, i) gets - w bt[i] N_a.
+template <int D, class TU, class TO, class TR>
+__device__ void face_flux(const StepPar& sp, const Pt<D, TU>& f, const Pt<D, TO>& o, TR (&bt)[D]) {
+  const double k = sp.k, th = sp.theta;
+  const double kth = k * th, k1th = k * (1.0 - th);
+  const double rn = sp.rho_f * sp.nu_f;
+  TU F[D][D], J, Fi[D][D];
+  TO Fo[D][D], Jo, Foi[D][D];
+  def_grad<D, TU>(f.gu, F, J, Fi);
+  def_grad<D, TO>(o.gu, Fo, Jo, Foi);
+  TU t2[D];
+  TO t2o[D];
+  for (int i = 0; i < D; ++i) {
+    t2[i] = f.gv[0][i] * Fi[0][0];
+    t2o[i] = o.gv[0][i] * Foi[0][0];
+    for (int j = 1; j < D; ++j) { t2[i] += f.gv[j][i] * Fi[0][j]; t2o[i] += o.gv[j][i] * Foi[0][j]; }
+  }
+  for (int i = 0; i < D; ++i) {
+    TU t3 = Fi[0][i] * t2[0];
+    TO t3o = Foi[0][i] * t2o[0];
+    for (int j = 1; j < D; ++j) { t3 += Fi[j][i] * t2[j]; t3o += Foi[j][i] * t2o[j]; }
+    bt[i] = kth * rn * J * t3 + k1th * rn * Jo * t3o;
+  }
+}
+
+// State at a point in FP64 (value) with the derivative in the direction of
+// local unknown (node bn, component cc): N_bn on that component's value, grad
+// N_bn on its gradient, zero elsewhere.
+template <int D>
+__device__ inline void seed_point(const double (&U)[Dm<D>::NE], const double (&N)[Dm<D>::NL],
+                                  const double (&G)[Dm<D>::NL][D], int bn, int cc, Pt<D, Dual>& f) {
+  FSI_DIM(D);
+  Pt<D, double> v;
+  eval_point<D, double>(U, N, G, v);
+  double Nb = 0.0, Gb[D];
+  for (int r = 0; r < D; ++r) Gb[r] = 0.0;
+#pragma unroll
+  for (int a = 0; a < NL; ++a)
+    if (a == bn) {
+      Nb = N[a];
+      for (int r = 0; r < D; ++r) Gb[r] = G[a][r];
+    }
+  for (int i = 0; i < D; ++i) {
+    f.v[i] = Dual(v.v[i], cc == i ? Nb : 0.0);
+    f.u[i] = Dual(v.u[i], cc == D + i ? Nb : 0.0);
+    for (int r = 0; r < D; ++r) {
+      f.gv[i][r] = Dual(v.gv[i][r], cc == i ? Gb[r] : 0.0);
+      f.gu[i][r] = Dual(v.gu[i][r], cc == D + i ? Gb[r] : 0.0);
+    }
+  }
+  f.p = Dual(v.p, cc == PC ? Nb : 0.0);
+}
+
+// K[NC a + c] += w (derivatives of the coefficients fl against the test functions)
+template <int D>
+__device__ inline void add_flux_tangent(const Cell<D>& c, const Flux<D, Dual>& fl, const double (&N)[Dm<D>::NL],
+                                        const double (&G)[Dm<D>::NL][D], double w, double (&K)[Dm<D>::NE]) {
+  FSI_DIM(D);
+  for (int a = 0; a < NL; ++a) {
+    for (int i = 0; i < D; ++i) {
+      double s = fl.am[i].d * N[a];
+      for (int r = 0; r < D; ++r) s += fl.bm[i][r].d * G[a][r];
+      K[NC * a + i] += w * s;
+    }
+    K[NC * a + PC] += w * fl.ap.d * N[a];
+    for (int i = 0; i < D; ++i) {
+      double s = fl.au[i].d * N[a];
+      if (c.urow[a])
+        for (int r = 0; r < D; ++r) s += fl.bu[i][r].d * G[a][r];
+      K[NC * a + D + i] += w * s;
+    }
+  }
+}
+
 // Element residual R[NC a + c] of one step (Dirichlet rows are replaced later).
 // TU, TO: scalar types of the new and the old state; R has the common type.
 template <int D, class TU, class TO, class TR>
 __device__ void elem_residual(const Cell<D>& c, const StepPar& sp, const TU (&U)[Dm<D>::NE],
                               const TO (&Uo)[Dm<D>::NE], TR (&R)[Dm<D>::NE]) {
   FSI_DIM(D);
-  const double k = sp.k, th = sp.theta;
-  const double kth = k * th, k1th = k * (1.0 - th);
-  const double rf = sp.rho_f, rn = sp.rho_f * sp.nu_f;
   for (int e = 0; e < NE; ++e) R[e] = TR(0.0);
   double w = 1.0;
   for (int r = 0; r < D; ++r) w *= 0.5 * c.h[r];
@@ -157,112 +361,9 @@ __device__ void elem_residual(const Cell<D>& c, const StepPar& sp, const TU (&U)
     Pt<D, TO> o;
     eval_point<D, TU>(U, N, G, f);
     eval_point<D, TO>(Uo, N, G, o);
-    TU F[D][D], J, Fi[D][D];
-    TO Fo[D][D], Jo, Foi[D][D];
-    def_grad<D, TU>(f.gu, F, J, Fi);
-    def_grad<D, TO>(o.gu, Fo, Jo, Foi);
-    if (!c.solid) {
-      // ALE time derivative with the means of the step
-      TR gub[D][D], Fb[D][D], Jbd, Fbi[D][D], gvb[D][D];
-      for (int i = 0; i < D; ++i)
-        for (int r = 0; r < D; ++r) {
-          gub[i][r] = 0.5 * (f.gu[i][r] + o.gu[i][r]);
-          gvb[i][r] = 0.5 * (f.gv[i][r] + o.gv[i][r]);
-        }
-      def_grad<D, TR>(gub, Fb, Jbd, Fbi);
-      const TR Jb = 0.5 * (J + Jo);
-      TR A[D][D];
-      mat_mul<D, TR, TR>(gvb, Fbi, A);
-      TR m[D];
-      for (int i = 0; i < D; ++i) {
-        TR adv = A[i][0] * (f.u[0] - o.u[0]);
-        for (int r = 1; r < D; ++r) adv += A[i][r] * (f.u[r] - o.u[r]);
-        m[i] = rf * Jb * ((f.v[i] - o.v[i]) - adv);
-      }
-      // convection, new and old
-      TU C[D][D];
-      TO Co[D][D];
-      mat_mul<D, TU, TU>(f.gv, Fi, C);
-      mat_mul<D, TO, TO>(o.gv, Foi, Co);
-      for (int i = 0; i < D; ++i) {
-        TU cn = C[i][0] * f.v[0];
-        TO co = Co[i][0] * o.v[0];
-        for (int r = 1; r < D; ++r) { cn += C[i][r] * f.v[r]; co += Co[i][r] * o.v[r]; }
-        m[i] += kth * rf * J * cn;
-        m[i] += k1th * rf * Jo * co;
-      }
-      // Piola-transformed Cauchy stress J sigma F^{-T}; the pressure is the new one in both parts
-      TR P[D][D];
-      for (int i = 0; i < D; ++i)
-        for (int r = 0; r < D; ++r) {
-          TU pn = TU(0.0);
-          TR po = TR(0.0);
-          for (int cc = 0; cc < D; ++cc) {
-            const TU s = rn * (C[i][cc] + C[cc][i]) - (i == cc ? f.p : TU(0.0));
-            const TR so = rn * (Co[i][cc] + Co[cc][i]) - (i == cc ? f.p : TU(0.0));
-            pn += s * Fi[r][cc];
-            po += so * Foi[r][cc];
-          }
-          P[i][r] = kth * (J * pn) + k1th * (Jo * po);
-        }
-      TU trc = C[0][0];
-      for (int i = 1; i < D; ++i) trc += C[i][i];
-      const TU div = k * J * trc;
-      TR ug[D][D];
-      for (int i = 0; i < D; ++i)
-        for (int r = 0; r < D; ++r) ug[i][r] = k * (th * f.gu[i][r] + (1.0 - th) * o.gu[i][r]);
-      for (int a = 0; a < NL; ++a) {
-        for (int i = 0; i < D; ++i) {
-          TR s = m[i] * N[a];
-          for (int r = 0; r < D; ++r) s += P[i][r] * G[a][r];
-          R[NC * a + i] += w * s;
-        }
-        R[NC * a + PC] += w * div * N[a];
-        if (c.urow[a])
-          for (int i = 0; i < D; ++i) {
-            TR s = ug[i][0] * G[a][0];
-            for (int r = 1; r < D; ++r) s += ug[i][r] * G[a][r];
-            R[NC * a + D + i] += w * s;
-          }
-      }
-    } else {
-      // St. Venant-Kirchhoff first Piola stress F Sigma(E), E = (F^T F - I)/2
-      const double mu = sp.mu_s, lam = sp.lambda_s;
-      TU E[D][D], S[D][D];
-      TO Eo[D][D], So[D][D];
-      for (int r = 0; r < D; ++r)
-        for (int s = 0; s < D; ++s) {
-          TU e = F[0][r] * F[0][s];
-          TO eo = Fo[0][r] * Fo[0][s];
-          for (int i = 1; i < D; ++i) { e += F[i][r] * F[i][s]; eo += Fo[i][r] * Fo[i][s]; }
-          E[r][s] = 0.5 * (e - (r == s ? 1.0 : 0.0));
-          Eo[r][s] = 0.5 * (eo - (r == s ? 1.0 : 0.0));
-        }
-      TU trE = E[0][0];
-      TO trEo = Eo[0][0];
-      for (int r = 1; r < D; ++r) { trE += E[r][r]; trEo += Eo[r][r]; }
-      for (int r = 0; r < D; ++r)
-        for (int s = 0; s < D; ++s) {
-          S[r][s] = 2.0 * mu * E[r][s] + (r == s ? lam * trE : TU(0.0));
-          So[r][s] = 2.0 * mu * Eo[r][s] + (r == s ? lam * trEo : TO(0.0));
-        }
-      TR Ps[D][D];
-      for (int i = 0; i < D; ++i)
-        for (int r = 0; r < D; ++r) {
-          TU pn = F[i][0] * S[0][r];
-          TO po = Fo[i][0] * So[0][r];
-          for (int s = 1; s < D; ++s) { pn += F[i][s] * S[s][r]; po += Fo[i][s] * So[s][r]; }
-          Ps[i][r] = kth * pn + k1th * po;
-        }
-      for (int a = 0; a < NL; ++a)
-        for (int i = 0; i < D; ++i) {
-          TR s = sp.rho_s * (f.v[i] - o.v[i]) * N[a];
-          for (int r = 0; r < D; ++r) s += Ps[i][r] * G[a][r];
-          R[NC * a + i] += w * s;
-          const TR kin = (f.u[i] - o.u[i]) - k * (th * f.v[i] + (1.0 - th) * o.v[i]);
-          R[NC * a + D + i] += w * kin * N[a];
-        }
-    }
+    Flux<D, TR> fl;
+    point_flux<D, TU, TO, TR>(c, sp, f, o, fl);
+    add_flux<D, TR>(c, fl, N, G, w, R);
   }
   if (c.outflow) {
     // do-nothing correction on the face x = L (outward normal e_x), points (1, eta[, zeta])
@@ -278,25 +379,10 @@ __device__ void elem_residual(const Cell<D>& c, const StepPar& sp, const TU (&U)
       Pt<D, TO> o;
       eval_point<D, TU>(U, N, G, f);
       eval_point<D, TO>(Uo, N, G, o);
-      TU F[D][D], J, Fi[D][D];
-      TO Fo[D][D], Jo, Foi[D][D];
-      def_grad<D, TU>(f.gu, F, J, Fi);
-      def_grad<D, TO>(o.gu, Fo, Jo, Foi);
-      // F^{-T} grad v^T F^{-T} n with n = e_x
-      TU t2[D];
-      TO t2o[D];
-      for (int i = 0; i < D; ++i) {
-        t2[i] = f.gv[0][i] * Fi[0][0];
-        t2o[i] = o.gv[0][i] * Foi[0][0];
-        for (int j = 1; j < D; ++j) { t2[i] += f.gv[j][i] * Fi[0][j]; t2o[i] += o.gv[j][i] * Foi[0][j]; }
-      }
-      for (int i = 0; i < D; ++i) {
-        TU t3 = Fi[0][i] * t2[0];
-        TO t3o = Foi[0][i] * t2o[0];
-        for (int j = 1; j < D; ++j) { t3 += Fi[j][i] * t2[j]; t3o += Foi[j][i] * t2o[j]; }
-        const TR b = kth * rn * J * t3 + k1th * rn * Jo * t3o;
-        for (int a = 0; a < NL; ++a) R[NC * a + i] -= wf * b * N[a];
-      }
+      TR bt[D];
+      face_flux<D, TU, TO, TR>(sp, f, o, bt);
+      for (int i = 0; i < D; ++i)
+        for (int a = 0; a < NL; ++a) R[NC * a + i] -= wf * bt[i] * N[a];
     }
   }
 }
@@ -372,18 +458,61 @@ __global__ void __launch_bounds__(jac_cells<D>() * jac_waves<D>()) k_elem_jacobi
       Uoe[NC * a + c] = Uo[so + (size_t)ci.nodes[a] * NC + c];
     }
   double* out = Ke + (size_t)b * NE * NE * g.ncell;
-  for (int d = w; d < NE; d += jac_waves<D>()) {
-    Dual R[NE];
-    if (!OLD) {
-      Dual Un[NE];
-      for (int e = 0; e < NE; ++e) Un[e] = Dual(Ue[e], e == d ? 1.0 : 0.0);
-      elem_residual<D, Dual, double, Dual>(ci.c, sp, Un, Uoe, R);
-    } else {
+  if constexpr (OLD) {
+    for (int d = w; d < NE; d += jac_waves<D>()) {
+      Dual R[NE];
       Dual Uold[NE];
       for (int e = 0; e < NE; ++e) Uold[e] = Dual(Uoe[e], e == d ? 1.0 : 0.0);
       elem_residual<D, double, Dual, Dual>(ci.c, sp, Ue, Uold, R);
+      for (int e = 0; e < NE; ++e) out[(size_t)(NE * e + d) * g.ncell + cell] = R[e].d;
     }
-    for (int e = 0; e < NE; ++e) out[(size_t)(NE * e + d) * g.ncell + cell] = R[e].d;
+  } else {
+    // column d = (node bn, component cc): at each quadrature point the state is
+    // interpolated in FP64 and only its derivative in direction d is seeded
+    // (N_bn on the value, grad N_bn on the gradient of component cc); the
+    // pointwise coefficients are differentiated in dual numbers and only their
+    // derivatives are integrated against the test functions
+    const double gq[2] = {GA, GB};
+    double wq = 1.0;
+    for (int r = 0; r < D; ++r) wq *= 0.5 * ci.c.h[r];
+    for (int d = w; d < NE; d += jac_waves<D>()) {
+      const int bn = d / NC, cc = d % NC;
+      double K[NE];
+      for (int e = 0; e < NE; ++e) K[e] = 0.0;
+      for (int q = 0; q < (1 << D); ++q) {
+        double xi[D];
+        for (int r = 0; r < D; ++r) xi[r] = gq[(q >> r) & 1];
+        double N[NL], G[NL][D];
+        q1_at<D>(xi, ci.c.h, N, G);
+        Pt<D, Dual> f;
+        Pt<D, double> o;
+        seed_point<D>(Ue, N, G, bn, cc, f);
+        eval_point<D, double>(Uoe, N, G, o);
+        Flux<D, Dual> fl;
+        point_flux<D, Dual, double, Dual>(ci.c, sp, f, o, fl);
+        add_flux_tangent<D>(ci.c, fl, N, G, wq, K);
+      }
+      if (ci.c.outflow) {
+        double wf = 1.0;
+        for (int r = 1; r < D; ++r) wf *= 0.5 * ci.c.h[r];
+        for (int q = 0; q < (1 << (D - 1)); ++q) {
+          double xi[D];
+          xi[0] = 1.0;
+          for (int r = 1; r < D; ++r) xi[r] = gq[(q >> (r - 1)) & 1];
+          double N[NL], G[NL][D];
+          q1_at<D>(xi, ci.c.h, N, G);
+          Pt<D, Dual> f;
+          Pt<D, double> o;
+          seed_point<D>(Ue, N, G, bn, cc, f);
+          eval_point<D, double>(Uoe, N, G, o);
+          Dual bt[D];
+          face_flux<D, Dual, double, Dual>(sp, f, o, bt);
+          for (int i = 0; i < D; ++i)
+            for (int a = 0; a < NL; ++a) K[NC * a + i] -= wf * bt[i].d * N[a];
+        }
+      }
+      for (int e = 0; e < NE; ++e) out[(size_t)(NE * e + d) * g.ncell + cell] = K[e];
+    }
   }
 }
 

@@ -280,6 +280,7 @@ __global__ void __launch_bounds__(256) k_coarse_factor(Geom g, double k, const S
   double* Ut = Lt + B2i;
   double* Wp = Ut + B2i;
   __shared__ double fac[64];
+  __shared__ double prow[128];
   __shared__ int colmap[64];
   __shared__ int usedf[64];
   __shared__ int piv_row;
@@ -326,10 +327,16 @@ __global__ void __launch_bounds__(256) k_coarse_factor(Geom g, double k, const S
       __syncthreads();
       const int pr = piv_row;
       const double pv = piv_val;
-      for (int c = tid; c < w2; c += nt) {
-        const double pc = M[pr * w2 + c];
-        for (int r = 0; r < bsz; ++r) M[r * w2 + c] -= fac[r] * pc;
-        M[pr * w2 + c] = pc / pv;
+      // the pivot row, then every (row, column) pair in parallel: columns left of
+      // jc are already eliminated in all rows but their pivot rows, so only
+      // columns >= jc change (and the identity half)
+      for (int c = tid; c < w2; c += nt) prow[c] = M[pr * w2 + c];
+      __syncthreads();
+      const int wc = w2 - jc;
+      for (int e = tid; e < bsz * wc; e += nt) {
+        const int r = e / wc, c = jc + (e - r * wc);
+        const double pc = prow[c];
+        M[r * w2 + c] = r == pr ? pc / pv : M[r * w2 + c] - fac[r] * pc;
       }
       __syncthreads();
     }
