@@ -602,10 +602,10 @@ __global__ void k_gather_jacobian(Geom g, double k, const double* __restrict__ K
   int i, j, kk;
   node_ijk<D>(g, n, i, j, kk);
   const double* ke = Ke + (size_t)b * NE * NE * g.ncell;
-  S* jb = J + (size_t)b * jslice<D, CJ>(g);
+  S* jb = J + (size_t)b * jslice<D, S, CJ>(g);
   const int row = n / (g.nx + 1);
-  S* j0 = jb + jnode<D, CJ>(g, i, row, 0);   // every copy of the tiled storage
-  S* j1 = jb + jnode<D, CJ>(g, i, row, jcopies<D>() - 1);
+  S* j0 = jb + jnode<D, S, CJ>(g, i, row, 0);   // every copy of the tiled storage
+  S* j1 = jb + jnode<D, S, CJ>(g, i, row, jcopies<D, S>() - 1);
   const uint8_t m = g.dmask[n];
   double rmax[NC];
   for (int c = 0; c < NC; ++c) rmax[c] = 0.0;
@@ -638,8 +638,8 @@ __global__ void k_gather_jacobian(Geom g, double k, const double* __restrict__ K
       for (int c = 0; c < NC; ++c) {
         const int e = jentry<D, CJ>(r, c);   // compressed layout: structural zeros are not stored
         if (e >= 0) {
-          j0[jent<D, CJ>(s, e)] = (S)blk[NC * r + c];
-          if (jcopies<D>() == 2) j1[jent<D, CJ>(s, e)] = (S)blk[NC * r + c];
+          j0[jent<D, S, CJ>(s, e)] = (S)blk[NC * r + c];
+          if (jcopies<D, S>() == 2) j1[jent<D, S, CJ>(s, e)] = (S)blk[NC * r + c];
         }
       }
   }

@@ -402,7 +402,8 @@ fsi_status build_level(fsi_problem* pb, int l) {
   CHK(dalloc(pb, &L.U, (size_t)B * L.nn * NC));
   CHK(dalloc(pb, &L.Uo, (size_t)B * L.nn * NC));
   CHK(dalloc(pb, &L.Dsc, (size_t)B * L.nn * NC));
-  CHK(dalloc_bytes(pb, &L.J, (size_t)B * jslice<D, false>(L.geom()) * ss));
+  const size_t jvals = std::max(jslice<D, double, false>(L.geom()), jslice<D, float, false>(L.geom()));
+  CHK(dalloc_bytes(pb, &L.J, (size_t)B * jvals * ss));
   // Vanka inverses: every smoothed level (in 3d level 0 is smoothed too)
   if (l >= 1 || D == 3) CHK(dalloc_bytes(pb, &L.Ainv, (size_t)B * ainv_slice<D>(L.ncell) * ss));
   CHK(dalloc_bytes(pb, &L.x_, (size_t)B * L.nn * NC * ss));
@@ -510,7 +511,7 @@ fsi_status assemble_levels(fsi_problem* pb, int B, const StepPar& sp, const int*
     k_gather_jacobian<D, S, CJ><<<grid1(g.nn, B), TPB, 0, st>>>(g, sp.k, pb->Ke, (S*)lv.J, lv.Dsc, act, 1);
     if (transpose) {
       // adjoint (2d): the operator of every level becomes the transpose of the free block (B = 1)
-      const size_t bytes = jslice<D, false>(g) * sizeof(S);
+      const size_t bytes = jslice<D, S, false>(g) * sizeof(S);
       if (l == L && save_fine) HIPCHK(hipMemcpyAsync(save_fine, lv.J, bytes, hipMemcpyDeviceToDevice, st));
       HIPCHK(hipMemcpyAsync(pb->Jtmp, lv.J, bytes, hipMemcpyDeviceToDevice, st));
       k_transpose_J<double><<<grid1(g.nn, 1), TPB, 0, st>>>(g, sp.k, (const double*)pb->Jtmp, (double*)lv.J, lv.Dsc);
@@ -537,7 +538,8 @@ fsi_status assemble_levels(fsi_problem* pb, int B, const StepPar& sp, const int*
 template <int D, class S, bool CJ>
 void spmv(const Geom& g, int B, double k, const S* J, const S* x, const S* b, const double* Dv, S* y, const int* act,
           hipStream_t st) {
-  const int nb = D == 2 ? (g.nn + 63) / 64 : (jntx<D>(g, 0) * jrows<D>(g) * jtx<D>() + 63) / 64;
+  const int nb =
+      !jrowtiles<D, S>() ? (g.nn + 63) / 64 : (jntx<D, S>(g, 0) * jrows<D>(g) * jtx<D, S>() + 63) / 64;
   k_spmv<D, S, CJ><<<dim3(nb, B), spmv_threads<D>(), 0, st>>>(g, k, J, x, b, Dv, y, act);
 }
 
@@ -959,9 +961,9 @@ fsi_status adjoint_alloc(fsi_problem* pb, size_t nstates, int N) {
   Level& F = pb->lev[pb->nlev - 1];
   const size_t nd = (size_t)F.nn * NC;
   if (!pb->Jtmp) {
-    CHK(dalloc(pb, &pb->Jtmp, jslice<2, false>(F.geom())));
-    CHK(dalloc(pb, &pb->Jcopy, jslice<2, false>(F.geom())));
-    CHK(dalloc(pb, &pb->Jold, jslice<2, false>(F.geom())));
+    CHK(dalloc(pb, &pb->Jtmp, jslice<2, double, false>(F.geom())));
+    CHK(dalloc(pb, &pb->Jcopy, jslice<2, double, false>(F.geom())));
+    CHK(dalloc(pb, &pb->Jold, jslice<2, double, false>(F.geom())));
     CHK(dalloc(pb, &pb->lam, nd));
     CHK(dalloc(pb, &pb->lamn, nd));
     CHK(dalloc(pb, &pb->arhs, nd));

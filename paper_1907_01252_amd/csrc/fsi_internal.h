@@ -120,18 +120,19 @@ __host__ __device__ inline int pslot_of(int dx, int dy, int dz) {
 }
 
 // Jacobian storage (block-stencil coefficients of the NSLOT neighbours of each
-// node), per slice, as runs of jtx<D>() values of one coefficient over
-// consecutive nodes, so that a wave reads whole runs.
-//  - 2d: tiles of 64 consecutive node indices (row-major node order), one copy.
-//    The working set of the finest level over the slice batch is a few hundred
-//    MB, and compact storage keeps a large part of the repeated passes inside
-//    the GPU's last-level cache.
-//  - 3d: tiles of 32 consecutive x-positions within one mesh row (fixed j, k),
-//    rows padded to whole tiles (the padding is never read), in two copies,
-//    with tile origins at x = 0 (copy 0) and x = 1 (copy 1): a block of the
-//    fused Vanka pass takes the cells of one colour, whose nodes start at x = 0
-//    or x = 1 (by the colour's x-parity), and reads the copy whose runs it
-//    covers exactly.
+// node), per slice, as runs of jtx() values of one coefficient over
+// consecutive nodes, so that a wave reads whole runs.  Two tilings, chosen by
+// dimension and storage type S:
+//  - compact (2d FP64): tiles of 64 consecutive node indices (row-major node
+//    order), one copy.  The working set of the finest level over the slice
+//    batch is a few hundred MB, and compact storage keeps a large part of the
+//    repeated passes inside the GPU's last-level cache.
+//  - row tiles (3d, and 2d FP32): tiles of 32 consecutive x-positions within
+//    one mesh row (fixed j, k), rows padded to whole tiles (the padding is
+//    never read), in two copies, with tile origins at x = 0 (copy 0) and x = 1
+//    (copy 1): a block of the fused Vanka pass takes the cells of one colour,
+//    whose nodes start at x = 0 or x = 1 (by the colour's x-parity), and reads
+//    the copy whose runs it covers exactly, in whole 128-byte lines.
 //
 // Two block layouts (CJ):
 //  - full: all NC x NC entries, row-major (the transposed adjoint system);
@@ -140,13 +141,17 @@ __host__ __device__ inline int pslot_of(int dx, int dy, int dz) {
 //    the solid, identity when Dirichlet) depends on v_i and u_i of its own
 //    component i only, so it stores 2 entries (v_i, u_i); velocity and
 //    pressure rows store all NC.  2d: 19 of 25 entries, 3d: 34 of 49.
-template <int D>
-__host__ __device__ constexpr int jtx() {
-  return D == 2 ? 64 : 32;
+template <int D, class S>
+__host__ __device__ constexpr bool jrowtiles() {
+  return D == 3 || sizeof(S) == 4;
 }
-template <int D>
+template <int D, class S>
+__host__ __device__ constexpr int jtx() {
+  return jrowtiles<D, S>() ? 32 : 64;
+}
+template <int D, class S>
 __host__ __device__ constexpr int jcopies() {
-  return D == 2 ? 1 : 2;
+  return jrowtiles<D, S>() ? 2 : 1;
 }
 template <int D, bool CJ>
 __host__ __device__ constexpr int jblk() {
@@ -166,49 +171,51 @@ __host__ __device__ inline int jentry(int r, int c) {
   if (c == r) return jrow_off<D, CJ>(r) + 1;
   return -1;
 }
-// mesh rows (j, k), and tiles per row of copy sh (3d)
+// mesh rows (j, k), and tiles per row of copy sh (row tiles)
 template <int D>
 __host__ __device__ inline int jrows(const Geom& g) {
   return (g.ny + 1) * (D == 3 ? g.nz + 1 : 1);
 }
-template <int D>
+template <int D, class S>
 __host__ __device__ inline int jntx(const Geom& g, int sh) {
-  return (g.nx + 1 + sh * (jtx<D>() - 1) + jtx<D>() - 1) / jtx<D>();
+  return (g.nx + 1 + sh * (jtx<D, S>() - 1) + jtx<D, S>() - 1) / jtx<D, S>();
 }
-template <int D, bool CJ>
+template <int D, class S, bool CJ>
 __host__ __device__ constexpr int jtile() {
-  return Dm<D>::NSLOT * jblk<D, CJ>() * jtx<D>();
+  return Dm<D>::NSLOT * jblk<D, CJ>() * jtx<D, S>();
 }
 // tiles per slice
-template <int D>
+template <int D, class S>
 __host__ __device__ inline size_t jtiles(const Geom& g) {
-  if (D == 2) return (size_t)(g.nn + jtx<D>() - 1) / jtx<D>();
-  return (size_t)(jntx<D>(g, 0) + jntx<D>(g, 1)) * jrows<D>(g);
+  if (!jrowtiles<D, S>()) return (size_t)(g.nn + jtx<D, S>() - 1) / jtx<D, S>();
+  return (size_t)(jntx<D, S>(g, 0) + jntx<D, S>(g, 1)) * jrows<D>(g);
 }
 // values per slice
-template <int D, bool CJ>
+template <int D, class S, bool CJ>
 __host__ __device__ inline size_t jslice(const Geom& g) {
-  return jtiles<D>(g) * jtile<D, CJ>();
+  return jtiles<D, S>(g) * jtile<D, S, CJ>();
 }
-// position of node (x, row) (in copy sh, 3d); entry e of slot s sits jent(s, e) further
-template <int D, bool CJ>
+// position of node (x, row) (in copy sh of the row tiles); entry e of slot s
+// sits jent(s, e) further
+template <int D, class S, bool CJ>
 __host__ __device__ inline size_t jnode(const Geom& g, int x, int row, int sh) {
-  if (D == 2) {
+  constexpr int TX = jtx<D, S>();
+  if (!jrowtiles<D, S>()) {
     const int n = x + (g.nx + 1) * row;
-    return (size_t)(n / jtx<D>()) * jtile<D, CJ>() + n % jtx<D>();
+    return (size_t)(n / TX) * jtile<D, S, CJ>() + n % TX;
   }
-  const int p = x + sh * (jtx<D>() - 1);
-  const size_t t = (sh ? (size_t)jntx<D>(g, 0) * jrows<D>(g) : 0) + (size_t)row * jntx<D>(g, sh) + p / jtx<D>();
-  return t * jtile<D, CJ>() + p % jtx<D>();
+  const int p = x + sh * (TX - 1);
+  const size_t t = (sh ? (size_t)jntx<D, S>(g, 0) * jrows<D>(g) : 0) + (size_t)row * jntx<D, S>(g, sh) + p / TX;
+  return t * jtile<D, S, CJ>() + p % TX;
 }
-template <int D, bool CJ>
+template <int D, class S, bool CJ>
 __host__ __device__ constexpr int jent(int s, int e) {
-  return (s * jblk<D, CJ>() + e) * jtx<D>();
+  return (s * jblk<D, CJ>() + e) * jtx<D, S>();
 }
-// position of node n (in copy sh, 3d)
-template <int D, bool CJ>
+// position of node n (in copy sh of the row tiles)
+template <int D, class S, bool CJ>
 __host__ __device__ inline size_t jnode_n(const Geom& g, int n, int sh) {
-  return jnode<D, CJ>(g, n % (g.nx + 1), n / (g.nx + 1), sh);
+  return jnode<D, S, CJ>(g, n % (g.nx + 1), n / (g.nx + 1), sh);
 }
 
 // Launch shapes: the SpMV and the fused Vanka pass run one wave per row of a

@@ -29,14 +29,14 @@ __global__ void __launch_bounds__(Dm<D>::NC * 64) k_spmv(Geom g, double k, const
   const int bs = blockIdx.y;
   const int r = threadIdx.x >> 6, lane = threadIdx.x & 63;
   int n, i, row;
-  if (D == 2) {
+  if (!jrowtiles<D, S>()) {
     n = blockIdx.x * 64 + lane;
     row = n / (g.nx + 1);
     i = n - row * (g.nx + 1);
     if (n >= g.nn) return;
   } else {
-    constexpr int TX = jtx<D>();
-    const int ntx = jntx<D>(g, 0);
+    constexpr int TX = jtx<D, S>();
+    const int ntx = jntx<D, S>(g, 0);
     const int t = blockIdx.x * (64 / TX) + lane / TX;
     row = t / ntx;
     i = (t - row * ntx) * TX + lane % TX;
@@ -45,7 +45,7 @@ __global__ void __launch_bounds__(Dm<D>::NC * 64) k_spmv(Geom g, double k, const
   }
   if (active && !active[bs]) return;
   const int j = row % (g.ny + 1), kk = row / (g.ny + 1);
-  const S* jn = J + (size_t)bs * jslice<D, CJ>(g) + jnode<D, CJ>(g, i, row, 0);
+  const S* jn = J + (size_t)bs * jslice<D, S, CJ>(g) + jnode<D, S, CJ>(g, i, row, 0);
   const S* xb = x + (size_t)bs * g.nn * NC;
   S acc = stencil_row<D, S, CJ>(jn, xb, n, r, nbr_offsets<D>(g, i, j, kk));
   if (r == PC) acc += pst_row<D, S>(g, k, n, i, j, kk, xb);
@@ -65,22 +65,22 @@ __global__ void k_transpose_J(Geom g, double k, const S* __restrict__ J, S* __re
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= g.nn) return;
   const int i = n % (g.nx + 1), j = n / (g.nx + 1);
-  const S* jb = J + (size_t)bs * jslice<2, false>(g);
-  S* jt = Jt + (size_t)bs * jslice<2, false>(g);
-  S* jt0 = jt + jnode<2, false>(g, i, j, 0);
+  const S* jb = J + (size_t)bs * jslice<2, S, false>(g);
+  S* jt = Jt + (size_t)bs * jslice<2, S, false>(g);
+  S* jt0 = jt + jnode<2, S, false>(g, i, j, 0);
   const uint8_t m = g.dmask[n];
   double rmax[D2::NC] = {0, 0, 0, 0, 0};
   for (int s = 0; s < D2::NSLOT; ++s) {
     const int dx = s % 3 - 1, dy = s / 3 - 1;
     const int ii = i + dx, jj = j + dy;
     const bool ok = ii >= 0 && jj >= 0 && ii <= g.nx && jj <= g.ny;
-    const S* jnb = jb + (ok ? jnode<2, false>(g, ii, jj, 0) : 0);
+    const S* jnb = jb + (ok ? jnode<2, S, false>(g, ii, jj, 0) : 0);
     const int so = slot_of<2>(-dx, -dy, 0);
     for (int r = 0; r < D2::NC; ++r)
       for (int c = 0; c < D2::NC; ++c) {
-        double v = ok ? (double)jnb[jent<2, false>(so, D2::NC * c + r)] : 0.0;
+        double v = ok ? (double)jnb[jent<2, S, false>(so, D2::NC * c + r)] : 0.0;
         if (m & (1u << r)) v = (s == 4 && c == r) ? 1.0 : 0.0;
-        jt0[jent<2, false>(s, D2::NC * r + c)] = (S)v;
+        jt0[jent<2, S, false>(s, D2::NC * r + c)] = (S)v;
         rmax[r] = fmax(rmax[r], fabs(v));
       }
   }
@@ -99,7 +99,7 @@ __global__ void k_spmv_T(Geom g, double k, const S* __restrict__ J, const S* __r
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= g.nn) return;
   const int i = n % (g.nx + 1), j = n / (g.nx + 1);
-  const S* jb = J + (size_t)bs * jslice<2, false>(g);
+  const S* jb = J + (size_t)bs * jslice<2, S, false>(g);
   const S* xb = x + (size_t)bs * g.nn * D2::NC;
   S acc[D2::NC] = {0, 0, 0, 0, 0};
   for (int s = 0; s < D2::NSLOT; ++s) {
@@ -110,8 +110,8 @@ __global__ void k_spmv_T(Geom g, double k, const S* __restrict__ J, const S* __r
     const int mr = ii + (g.nx + 1) * jj;
     for (int r = 0; r < D2::NC; ++r) {
       const S xr = xb[(size_t)mr * D2::NC + r];
-      const S* jm = jb + jnode<2, false>(g, ii, jj, 0);
-      for (int c = 0; c < D2::NC; ++c) acc[c] += jm[jent<2, false>(s, D2::NC * r + c)] * xr;
+      const S* jm = jb + jnode<2, S, false>(g, ii, jj, 0);
+      for (int c = 0; c < D2::NC; ++c) acc[c] += jm[jent<2, S, false>(s, D2::NC * r + c)] * xr;
     }
   }
   if (with_pst && !(g.dmask[n] & dm_p<2>())) {
@@ -237,7 +237,7 @@ __device__ inline double coarse_entry(const Geom& g, double k, const S* jb, int 
   double v = 0.0;
   const int e = jentry<2, CJ>(r, c);
   if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && e >= 0)
-    v = (double)jb[jnode<2, CJ>(g, ir, jr, 0) + jent<2, CJ>(slot_of<2>(dx, dy, 0), e)];
+    v = (double)jb[jnode<2, S, CJ>(g, ir, jr, 0) + jent<2, S, CJ>(slot_of<2>(dx, dy, 0), e)];
   if (r == 4 && c == 4 && dx >= -2 && dx <= 2 && dy >= -2 && dy <= 2 && !(g.dmask[n] & dm_p<2>()))
     v += k * g.pst[(size_t)pslot_of<2>(dx, dy, 0) * g.nn + n];
   return v;
@@ -272,7 +272,7 @@ __global__ void __launch_bounds__(256) k_coarse_factor(Geom g, double k, const S
   const int bs = blockIdx.x;
   if (active && !active[bs]) return;
   const int tid = threadIdx.x, nt = blockDim.x;
-  const S* jb = J + (size_t)bs * jslice<2, CJ>(g);
+  const S* jb = J + (size_t)bs * jslice<2, S, CJ>(g);
   const int w2 = 2 * bsz;
   const int B2i = bsz * bsz;
   double* M = lds;                  // bsz x 2bsz

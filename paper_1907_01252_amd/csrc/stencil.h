@@ -70,8 +70,8 @@ __device__ inline S stencil_row(const S* __restrict__ jn, const S* __restrict__ 
         for (int sx = 0; sx < 3; ++sx) {
           const int s = sx + 3 * sy + 9 * sz;
           const S* xv = xb + (size_t)(n + nb.ox[sx] + nb.oy[sy] + oz) * NC;
-          acc += jn[jent<D, CJ>(s, e0)] * xv[r - D];
-          acc += jn[jent<D, CJ>(s, e0 + 1)] * xv[r];
+          acc += jn[jent<D, S, CJ>(s, e0)] * xv[r - D];
+          acc += jn[jent<D, S, CJ>(s, e0 + 1)] * xv[r];
         }
     }
   } else {
@@ -85,7 +85,7 @@ __device__ inline S stencil_row(const S* __restrict__ jn, const S* __restrict__ 
           const int s = sx + 3 * sy + 9 * sz;
           const S* xv = xb + (size_t)(n + nb.ox[sx] + nb.oy[sy] + oz) * NC;
 #pragma unroll
-          for (int c = 0; c < NC; ++c) acc += jn[jent<D, CJ>(s, e0 + c)] * xv[c];
+          for (int c = 0; c < NC; ++c) acc += jn[jent<D, S, CJ>(s, e0 + c)] * xv[c];
         }
     }
   }

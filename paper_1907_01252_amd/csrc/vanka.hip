@@ -36,14 +36,14 @@ __global__ void __launch_bounds__(vf_lanes<D>() * vf_patches<D>()) k_vanka_facto
     const int ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
     const int na = node_at(g, ci + ax, cj + ay, ck + az);
     if (live) {
-      const S* jn = J + (size_t)bs * jslice<D, CJ>(g) + jnode_n<D, CJ>(g, na, 0);
+      const S* jn = J + (size_t)bs * jslice<D, S, CJ>(g) + jnode_n<D, S, CJ>(g, na, 0);
       const bool pst_row = (rc == PC) && !(g.dmask[na] & dm_p<D>());
       for (int bb = 0; bb < NL; ++bb) {
         const int dx = (bb & 1) - ax, dy = ((bb >> 1) & 1) - ay, dz = ((bb >> 2) & 1) - az;
         const int s = slot_of<D>(dx, dy, dz);
         for (int c = 0; c < NC; ++c) {
           const int e = jentry<D, CJ>(rc, c);
-          Mp[lane][NC * bb + c] = e >= 0 ? (double)jn[jent<D, CJ>(s, e)] : 0.0;
+          Mp[lane][NC * bb + c] = e >= 0 ? (double)jn[jent<D, S, CJ>(s, e)] : 0.0;
         }
         if (pst_row) Mp[lane][NC * bb + PC] += k * g.pst[(size_t)pslot_of<D>(dx, dy, dz) * g.nn + na];
       }
@@ -162,7 +162,7 @@ __global__ void __launch_bounds__(Dm<D>::NC * 64, (vanka_waves_per_simd<D, S>())
         int i, j, kk;
         node_ijk<D>(g, n, i, j, kk);
         // (3d: the copy whose tiles start where this colour's node runs start)
-        const S* jn = J + (size_t)bs * jslice<D, CJ>(g) + jnode<D, CJ>(g, i, j + (g.ny + 1) * kk, cx);
+        const S* jn = J + (size_t)bs * jslice<D, S, CJ>(g) + jnode<D, S, CJ>(g, i, j + (g.ny + 1) * kk, cx);
         acc = stencil_row<D, S, CJ>(jn, xob, n, r, nbr_offsets<D>(g, i, j, kk));
         if (r == PC) acc += pst_row<D, S>(g, k, n, i, j, kk, xob);
       }
