@@ -182,3 +182,21 @@ def random_state(p: dict, seed: int, grad_u_max: float = 0.1) -> np.ndarray:
     U[:, d:2 * d] = u
     U[:, 2 * d] = rng.normal(0.0, 10.0, size=nn)
     return U
+
+
+def smooth_state(p: dict, seed: int, v_scale: float = 0.5, grad_u_max: float = 0.02) -> np.ndarray:
+    """A smooth random nodal state [nodes, comp] (float64) for whole propagator
+    steps at full size: velocity and displacement are smooth random fields (the
+    low Fourier modes of random_state), |v| up to v_scale * peak, the largest
+    nodal difference quotient of u below grad_u_max, pressure zero (it only
+    seeds Newton).  Dirichlet data is not applied here.
+    """
+    d = p["dim"]
+    a = random_state(p, seed, grad_u_max=grad_u_max)
+    b = random_state(p, seed + 100000, grad_u_max=1.0)
+    U = np.zeros_like(a)
+    U[:, d:2 * d] = a[:, d:2 * d]
+    vb = b[:, d:2 * d]
+    U[:, :d] = vb * (v_scale * p["inflow_peak"] / max(np.abs(vb).max(), 1e-300))
+    return U
+
