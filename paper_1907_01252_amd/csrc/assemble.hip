@@ -73,11 +73,19 @@ __device__ inline void q1_at(const double (&xi)[D], const double (&h)[D], double
   }
 }
 
-// Field values and gradients at one point: v, grad v (gv[i][r] = d_r v_i), u, grad u, p.
-template <int D, class T>
+// Field values and gradients at one point: v, grad v (gv[i][r] = d_r v_i), u,
+// grad u, p, with scalar types per field (velocity TV, displacement TD,
+// pressure TP; one type T for all by default).
+template <int D, class TV, class TD = TV, class TP = TV>
 struct Pt {
-  T v[D], gv[D][D], u[D], gu[D][D], p;
+  TV v[D], gv[D][D];
+  TD u[D], gu[D][D];
+  TP p;
 };
+
+// Scalar type of a product of the given types (Dual if any is Dual).
+template <class... T>
+using Pr = decltype((T() * ...));
 
 template <int D, class T>
 __device__ inline void eval_point(const T (&U)[Dm<D>::NE], const double (&N)[Dm<D>::NL],
@@ -125,11 +133,11 @@ __device__ inline void def_grad(const T (&gu)[D][D], T (&F)[D][D], T& J, T (&Fi)
 }
 
 // C = A B
-template <int D, class T, class U2>
-__device__ inline void mat_mul(const T (&A)[D][D], const U2 (&B)[D][D], T (&C)[D][D]) {
+template <int D, class TA, class TB, class TC>
+__device__ inline void mat_mul(const TA (&A)[D][D], const TB (&B)[D][D], TC (&C)[D][D]) {
   for (int i = 0; i < D; ++i)
     for (int j = 0; j < D; ++j) {
-      T s = A[i][0] * B[0][j];
+      TC s = A[i][0] * B[0][j];
       for (int r = 1; r < D; ++r) s += A[i][r] * B[r][j];
       C[i][j] = s;
     }
@@ -148,41 +156,50 @@ struct Flux {
   T am[D], bm[D][D], ap, au[D], bu[D][D];
 };
 
-// f, o: new and old state at the point (scalar types TU, TO); TR the common type.
-template <int D, class TU, class TO, class TR>
-__device__ void point_flux(const Cell<D>& c, const StepPar& sp, const Pt<D, TU>& f, const Pt<D, TO>& o,
+// f, o: new state (field types TV, TD, TP) and old state (TO) at the point; TR
+// the result type.  Every intermediate carries only the types it depends on,
+// so a derivative in one field's direction skips the parts that do not see it.
+template <int D, class TV, class TD, class TP, class TO, class TR>
+__device__ void point_flux(const Cell<D>& c, const StepPar& sp, const Pt<D, TV, TD, TP>& f, const Pt<D, TO>& o,
                            Flux<D, TR>& fl) {
+  using TVo = Pr<TV, TO>;
+  using TDo = Pr<TD, TO>;
+  using TVD = Pr<TV, TD>;
+  using TA = Pr<TV, TD, TO>;
+  using TS = Pr<TV, TD, TP>;
+  using TPo = Pr<TP, TO>;
   const double k = sp.k, th = sp.theta;
   const double kth = k * th, k1th = k * (1.0 - th);
   const double rf = sp.rho_f, rn = sp.rho_f * sp.nu_f;
-  TU F[D][D], J, Fi[D][D];
+  TD F[D][D], J, Fi[D][D];
   TO Fo[D][D], Jo, Foi[D][D];
-  def_grad<D, TU>(f.gu, F, J, Fi);
+  def_grad<D, TD>(f.gu, F, J, Fi);
   def_grad<D, TO>(o.gu, Fo, Jo, Foi);
   if (!c.solid) {
     // ALE time derivative with the means of the step
-    TR gub[D][D], Fb[D][D], Jbd, Fbi[D][D], gvb[D][D];
+    TDo gub[D][D], Fb[D][D], Jbd, Fbi[D][D];
+    TVo gvb[D][D];
     for (int i = 0; i < D; ++i)
       for (int r = 0; r < D; ++r) {
         gub[i][r] = 0.5 * (f.gu[i][r] + o.gu[i][r]);
         gvb[i][r] = 0.5 * (f.gv[i][r] + o.gv[i][r]);
       }
-    def_grad<D, TR>(gub, Fb, Jbd, Fbi);
-    const TR Jb = 0.5 * (J + Jo);
-    TR A[D][D];
-    mat_mul<D, TR, TR>(gvb, Fbi, A);
+    def_grad<D, TDo>(gub, Fb, Jbd, Fbi);
+    const TDo Jb = 0.5 * (J + Jo);
+    TA A[D][D];
+    mat_mul<D, TVo, TDo, TA>(gvb, Fbi, A);
     for (int i = 0; i < D; ++i) {
-      TR adv = A[i][0] * (f.u[0] - o.u[0]);
+      TA adv = A[i][0] * (f.u[0] - o.u[0]);
       for (int r = 1; r < D; ++r) adv += A[i][r] * (f.u[r] - o.u[r]);
       fl.am[i] = rf * Jb * ((f.v[i] - o.v[i]) - adv);
     }
     // convection, new and old
-    TU C[D][D];
+    TVD C[D][D];
     TO Co[D][D];
-    mat_mul<D, TU, TU>(f.gv, Fi, C);
-    mat_mul<D, TO, TO>(o.gv, Foi, Co);
+    mat_mul<D, TV, TD, TVD>(f.gv, Fi, C);
+    mat_mul<D, TO, TO, TO>(o.gv, Foi, Co);
     for (int i = 0; i < D; ++i) {
-      TU cn = C[i][0] * f.v[0];
+      TVD cn = C[i][0] * f.v[0];
       TO co = Co[i][0] * o.v[0];
       for (int r = 1; r < D; ++r) { cn += C[i][r] * f.v[r]; co += Co[i][r] * o.v[r]; }
       fl.am[i] += kth * rf * J * cn;
@@ -191,17 +208,17 @@ __device__ void point_flux(const Cell<D>& c, const StepPar& sp, const Pt<D, TU>&
     // Piola-transformed Cauchy stress J sigma F^{-T}; the pressure is the new one in both parts
     for (int i = 0; i < D; ++i)
       for (int r = 0; r < D; ++r) {
-        TU pn = TU(0.0);
-        TR po = TR(0.0);
+        TS pn = TS(0.0);
+        TPo po = TPo(0.0);
         for (int cc = 0; cc < D; ++cc) {
-          const TU s = rn * (C[i][cc] + C[cc][i]) - (i == cc ? f.p : TU(0.0));
-          const TR so = rn * (Co[i][cc] + Co[cc][i]) - (i == cc ? f.p : TU(0.0));
+          const TS s = rn * (C[i][cc] + C[cc][i]) - (i == cc ? f.p : TP(0.0));
+          const TPo so = rn * (Co[i][cc] + Co[cc][i]) - (i == cc ? f.p : TP(0.0));
           pn += s * Fi[r][cc];
           po += so * Foi[r][cc];
         }
         fl.bm[i][r] = kth * (J * pn) + k1th * (Jo * po);
       }
-    TU trc = C[0][0];
+    TVD trc = C[0][0];
     for (int i = 1; i < D; ++i) trc += C[i][i];
     fl.ap = k * J * trc;
     for (int i = 0; i < D; ++i) {
@@ -211,27 +228,27 @@ __device__ void point_flux(const Cell<D>& c, const StepPar& sp, const Pt<D, TU>&
   } else {
     // St. Venant-Kirchhoff first Piola stress F Sigma(E), E = (F^T F - I)/2
     const double mu = sp.mu_s, lam = sp.lambda_s;
-    TU E[D][D], S[D][D];
+    TD E[D][D], S[D][D];
     TO Eo[D][D], So[D][D];
     for (int r = 0; r < D; ++r)
       for (int s = 0; s < D; ++s) {
-        TU e = F[0][r] * F[0][s];
+        TD e = F[0][r] * F[0][s];
         TO eo = Fo[0][r] * Fo[0][s];
         for (int i = 1; i < D; ++i) { e += F[i][r] * F[i][s]; eo += Fo[i][r] * Fo[i][s]; }
         E[r][s] = 0.5 * (e - (r == s ? 1.0 : 0.0));
         Eo[r][s] = 0.5 * (eo - (r == s ? 1.0 : 0.0));
       }
-    TU trE = E[0][0];
+    TD trE = E[0][0];
     TO trEo = Eo[0][0];
     for (int r = 1; r < D; ++r) { trE += E[r][r]; trEo += Eo[r][r]; }
     for (int r = 0; r < D; ++r)
       for (int s = 0; s < D; ++s) {
-        S[r][s] = 2.0 * mu * E[r][s] + (r == s ? lam * trE : TU(0.0));
+        S[r][s] = 2.0 * mu * E[r][s] + (r == s ? lam * trE : TD(0.0));
         So[r][s] = 2.0 * mu * Eo[r][s] + (r == s ? lam * trEo : TO(0.0));
       }
     for (int i = 0; i < D; ++i)
       for (int r = 0; r < D; ++r) {
-        TU pn = F[i][0] * S[0][r];
+        TD pn = F[i][0] * S[0][r];
         TO po = Fo[i][0] * So[0][r];
         for (int s = 1; s < D; ++s) { pn += F[i][s] * S[s][r]; po += Fo[i][s] * So[s][r]; }
         fl.bm[i][r] = kth * pn + k1th * po;
@@ -269,16 +286,17 @@ __device__ inline void add_flux(const Cell<D>& c, const Flux<D, T>& fl, const do
 // Outflow (do-nothing) correction at a point of the face x = L, outward normal
 // e_x: bt[i] = k theta rho nu J (F^{-T} grad v^T F^{-T} n)_i + the old-state part;
 // momentum row (a, i) gets - w bt[i] N_a.
-template <int D, class TU, class TO, class TR>
-__device__ void face_flux(const StepPar& sp, const Pt<D, TU>& f, const Pt<D, TO>& o, TR (&bt)[D]) {
+template <int D, class TV, class TD, class TP, class TO, class TR>
+__device__ void face_flux(const StepPar& sp, const Pt<D, TV, TD, TP>& f, const Pt<D, TO>& o, TR (&bt)[D]) {
+  using TVD = Pr<TV, TD>;
   const double k = sp.k, th = sp.theta;
   const double kth = k * th, k1th = k * (1.0 - th);
   const double rn = sp.rho_f * sp.nu_f;
-  TU F[D][D], J, Fi[D][D];
+  TD F[D][D], J, Fi[D][D];
   TO Fo[D][D], Jo, Foi[D][D];
-  def_grad<D, TU>(f.gu, F, J, Fi);
+  def_grad<D, TD>(f.gu, F, J, Fi);
   def_grad<D, TO>(o.gu, Fo, Jo, Foi);
-  TU t2[D];
+  TVD t2[D];
   TO t2o[D];
   for (int i = 0; i < D; ++i) {
     t2[i] = f.gv[0][i] * Fi[0][0];
@@ -286,19 +304,27 @@ __device__ void face_flux(const StepPar& sp, const Pt<D, TU>& f, const Pt<D, TO>
     for (int j = 1; j < D; ++j) { t2[i] += f.gv[j][i] * Fi[0][j]; t2o[i] += o.gv[j][i] * Foi[0][j]; }
   }
   for (int i = 0; i < D; ++i) {
-    TU t3 = Fi[0][i] * t2[0];
+    TVD t3 = Fi[0][i] * t2[0];
     TO t3o = Foi[0][i] * t2o[0];
     for (int j = 1; j < D; ++j) { t3 += Fi[j][i] * t2[j]; t3o += Foi[j][i] * t2o[j]; }
     bt[i] = kth * rn * J * t3 + k1th * rn * Jo * t3o;
   }
 }
 
+// A value of scalar type T with derivative der (dropped for double).
+template <class T>
+__device__ inline T seeded(double val, double der);
+template <>
+__device__ inline double seeded<double>(double val, double) { return val; }
+template <>
+__device__ inline Dual seeded<Dual>(double val, double der) { return Dual(val, der); }
+
 // State at a point in FP64 (value) with the derivative in the direction of
 // local unknown (node bn, component cc): N_bn on that component's value, grad
-// N_bn on its gradient, zero elsewhere.
-template <int D>
+// N_bn on its gradient, zero elsewhere.  Only the field of cc is dual-typed.
+template <int D, class TV, class TD, class TP>
 __device__ inline void seed_point(const double (&U)[Dm<D>::NE], const double (&N)[Dm<D>::NL],
-                                  const double (&G)[Dm<D>::NL][D], int bn, int cc, Pt<D, Dual>& f) {
+                                  const double (&G)[Dm<D>::NL][D], int bn, int cc, Pt<D, TV, TD, TP>& f) {
   FSI_DIM(D);
   Pt<D, double> v;
   eval_point<D, double>(U, N, G, v);
@@ -311,14 +337,14 @@ __device__ inline void seed_point(const double (&U)[Dm<D>::NE], const double (&N
       for (int r = 0; r < D; ++r) Gb[r] = G[a][r];
     }
   for (int i = 0; i < D; ++i) {
-    f.v[i] = Dual(v.v[i], cc == i ? Nb : 0.0);
-    f.u[i] = Dual(v.u[i], cc == D + i ? Nb : 0.0);
+    f.v[i] = seeded<TV>(v.v[i], cc == i ? Nb : 0.0);
+    f.u[i] = seeded<TD>(v.u[i], cc == D + i ? Nb : 0.0);
     for (int r = 0; r < D; ++r) {
-      f.gv[i][r] = Dual(v.gv[i][r], cc == i ? Gb[r] : 0.0);
-      f.gu[i][r] = Dual(v.gu[i][r], cc == D + i ? Gb[r] : 0.0);
+      f.gv[i][r] = seeded<TV>(v.gv[i][r], cc == i ? Gb[r] : 0.0);
+      f.gu[i][r] = seeded<TD>(v.gu[i][r], cc == D + i ? Gb[r] : 0.0);
     }
   }
-  f.p = Dual(v.p, cc == PC ? Nb : 0.0);
+  f.p = seeded<TP>(v.p, cc == PC ? Nb : 0.0);
 }
 
 // K[NC a + c] += w (derivatives of the coefficients fl against the test functions)
@@ -342,6 +368,59 @@ __device__ inline void add_flux_tangent(const Cell<D>& c, const Flux<D, Dual>& f
   }
 }
 
+// Column (bn, cc) of the element Jacobian dR/dU^n: K[e] = dR_e / dU_{NC bn + cc}.
+// TV, TD, TP: Dual for the field of cc (or all Dual), double for the others.
+template <int D, class TV, class TD, class TP>
+__device__ inline void jac_column(const Cell<D>& c, const StepPar& sp, const double (&Ue)[Dm<D>::NE],
+                                  const double (&Uoe)[Dm<D>::NE], int bn, int cc, double (&K)[Dm<D>::NE]) {
+  FSI_DIM(D);
+  const double gq[2] = {GA, GB};
+  double wq = 1.0;
+  for (int r = 0; r < D; ++r) wq *= 0.5 * c.h[r];
+  for (int e = 0; e < NE; ++e) K[e] = 0.0;
+  for (int q = 0; q < (1 << D); ++q) {
+    double xi[D];
+    for (int r = 0; r < D; ++r) xi[r] = gq[(q >> r) & 1];
+    double N[NL], G[NL][D];
+    q1_at<D>(xi, c.h, N, G);
+    Pt<D, TV, TD, TP> f;
+    Pt<D, double> o;
+    seed_point<D, TV, TD, TP>(Ue, N, G, bn, cc, f);
+    eval_point<D, double>(Uoe, N, G, o);
+    Flux<D, Dual> fl;
+    point_flux<D, TV, TD, TP, double, Dual>(c, sp, f, o, fl);
+    add_flux_tangent<D>(c, fl, N, G, wq, K);
+  }
+  if (c.outflow) {
+    double wf = 1.0;
+    for (int r = 1; r < D; ++r) wf *= 0.5 * c.h[r];
+    for (int q = 0; q < (1 << (D - 1)); ++q) {
+      double xi[D];
+      xi[0] = 1.0;
+      for (int r = 1; r < D; ++r) xi[r] = gq[(q >> (r - 1)) & 1];
+      double N[NL], G[NL][D];
+      q1_at<D>(xi, c.h, N, G);
+      Pt<D, TV, TD, TP> f;
+      Pt<D, double> o;
+      seed_point<D, TV, TD, TP>(Ue, N, G, bn, cc, f);
+      eval_point<D, double>(Uoe, N, G, o);
+      Dual bt[D];
+      face_flux<D, TV, TD, TP, double, Dual>(sp, f, o, bt);
+      for (int i = 0; i < D; ++i)
+        for (int a = 0; a < NL; ++a) K[NC * a + i] -= wf * bt[i].d * N[a];
+    }
+  }
+}
+
+// The same as a called function: the three field-typed variants of a 3d
+// element then share one stack frame instead of three inlined ones.
+template <int D, class TV, class TD, class TP>
+__device__ __noinline__ void jac_column_call(const Cell<D>& c, const StepPar& sp, const double (&Ue)[Dm<D>::NE],
+                                             const double (&Uoe)[Dm<D>::NE], int bn, int cc,
+                                             double (&K)[Dm<D>::NE]) {
+  jac_column<D, TV, TD, TP>(c, sp, Ue, Uoe, bn, cc, K);
+}
+
 // Element residual R[NC a + c] of one step (Dirichlet rows are replaced later).
 // TU, TO: scalar types of the new and the old state; R has the common type.
 template <int D, class TU, class TO, class TR>
@@ -362,7 +441,7 @@ __device__ void elem_residual(const Cell<D>& c, const StepPar& sp, const TU (&U)
     eval_point<D, TU>(U, N, G, f);
     eval_point<D, TO>(Uo, N, G, o);
     Flux<D, TR> fl;
-    point_flux<D, TU, TO, TR>(c, sp, f, o, fl);
+    point_flux<D, TU, TU, TU, TO, TR>(c, sp, f, o, fl);
     add_flux<D, TR>(c, fl, N, G, w, R);
   }
   if (c.outflow) {
@@ -380,7 +459,7 @@ __device__ void elem_residual(const Cell<D>& c, const StepPar& sp, const TU (&U)
       eval_point<D, TU>(U, N, G, f);
       eval_point<D, TO>(Uo, N, G, o);
       TR bt[D];
-      face_flux<D, TU, TO, TR>(sp, f, o, bt);
+      face_flux<D, TU, TU, TU, TO, TR>(sp, f, o, bt);
       for (int i = 0; i < D; ++i)
         for (int a = 0; a < NL; ++a) R[NC * a + i] -= wf * bt[i] * N[a];
     }
@@ -470,46 +549,23 @@ __global__ void __launch_bounds__(jac_cells<D>() * jac_waves<D>()) k_elem_jacobi
     // column d = (node bn, component cc): at each quadrature point the state is
     // interpolated in FP64 and only its derivative in direction d is seeded
     // (N_bn on the value, grad N_bn on the gradient of component cc); the
-    // pointwise coefficients are differentiated in dual numbers and only their
-    // derivatives are integrated against the test functions
-    const double gq[2] = {GA, GB};
-    double wq = 1.0;
-    for (int r = 0; r < D; ++r) wq *= 0.5 * ci.c.h[r];
+    // pointwise coefficients are differentiated in dual numbers, with only the
+    // field of cc dual-typed, and only their derivatives are integrated
     for (int d = w; d < NE; d += jac_waves<D>()) {
       const int bn = d / NC, cc = d % NC;
       double K[NE];
-      for (int e = 0; e < NE; ++e) K[e] = 0.0;
-      for (int q = 0; q < (1 << D); ++q) {
-        double xi[D];
-        for (int r = 0; r < D; ++r) xi[r] = gq[(q >> r) & 1];
-        double N[NL], G[NL][D];
-        q1_at<D>(xi, ci.c.h, N, G);
-        Pt<D, Dual> f;
-        Pt<D, double> o;
-        seed_point<D>(Ue, N, G, bn, cc, f);
-        eval_point<D, double>(Uoe, N, G, o);
-        Flux<D, Dual> fl;
-        point_flux<D, Dual, double, Dual>(ci.c, sp, f, o, fl);
-        add_flux_tangent<D>(ci.c, fl, N, G, wq, K);
-      }
-      if (ci.c.outflow) {
-        double wf = 1.0;
-        for (int r = 1; r < D; ++r) wf *= 0.5 * ci.c.h[r];
-        for (int q = 0; q < (1 << (D - 1)); ++q) {
-          double xi[D];
-          xi[0] = 1.0;
-          for (int r = 1; r < D; ++r) xi[r] = gq[(q >> (r - 1)) & 1];
-          double N[NL], G[NL][D];
-          q1_at<D>(xi, ci.c.h, N, G);
-          Pt<D, Dual> f;
-          Pt<D, double> o;
-          seed_point<D>(Ue, N, G, bn, cc, f);
-          eval_point<D, double>(Uoe, N, G, o);
-          Dual bt[D];
-          face_flux<D, Dual, double, Dual>(sp, f, o, bt);
-          for (int i = 0; i < D; ++i)
-            for (int a = 0; a < NL; ++a) K[NC * a + i] -= wf * bt[i].d * N[a];
-        }
+      if constexpr (D == 2) {
+        // 2d: one all-dual variant, inlined (it fits the registers; the typed,
+        // called variants measured slower here)
+        jac_column<D, Dual, Dual, Dual>(ci.c, sp, Ue, Uoe, bn, cc, K);
+      } else {
+        // 3d: only the field of cc is dual-typed (half the time of the all-dual form)
+        if (cc < D)
+          jac_column_call<D, Dual, double, double>(ci.c, sp, Ue, Uoe, bn, cc, K);
+        else if (cc < 2 * D)
+          jac_column_call<D, double, Dual, double>(ci.c, sp, Ue, Uoe, bn, cc, K);
+        else
+          jac_column_call<D, double, double, Dual>(ci.c, sp, Ue, Uoe, bn, cc, K);
       }
       for (int e = 0; e < NE; ++e) out[(size_t)(NE * e + d) * g.ncell + cell] = K[e];
     }
