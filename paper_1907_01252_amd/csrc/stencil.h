@@ -49,6 +49,29 @@ __device__ inline S pst_row(const Geom& g, double k, int n, int i, int j, int kk
   return (S)k * ap;
 }
 
+// Part of the pressure-stabilisation row: k * sum of pst[q][n] x_p(neighbour q)
+// over the stencil rows [r0, r1) (a row is one (dy, dz) offset, its five dx
+// offsets unrolled).  The fused Vanka pass spreads the rows over the waves of
+// the displacement rows, which have the fewest block-stencil loads.
+template <int D, class S>
+__device__ inline S pst_rows(const Geom& g, double k, int n, int i, int j, int kk, const S* __restrict__ xb, int r0,
+                             int r1) {
+  FSI_DIM(D);
+  int cx[5];
+#pragma unroll
+  for (int d = 0; d < 5; ++d) cx[d] = min(max(i + d - 2, 0), g.nx);
+  S ap = 0;
+  for (int rr = r0; rr < r1; ++rr) {
+    const int dy = rr % 5, dz = rr / 5;
+    const int oy = (g.nx + 1) * min(max(j + dy - 2, 0), g.ny);
+    const int oz = D == 3 ? (g.nx + 1) * (g.ny + 1) * min(max(kk + dz - 2, 0), g.nz) : 0;
+#pragma unroll
+    for (int dx = 0; dx < 5; ++dx)
+      ap += (S)g.pst[(size_t)(5 * rr + dx) * g.nn + n] * xb[(size_t)(cx[dx] + oy + oz) * NC + PC];
+  }
+  return (S)k * ap;
+}
+
 // Row r of the block stencil at node n times x: the sum over the slots of the
 // stored entries of row r (jn: the node's position in the tiled Jacobian).  In
 // the compressed layout a displacement row holds (v_i, u_i) only; the row kind

@@ -118,7 +118,12 @@ __global__ void __launch_bounds__(Dm<D>::NC * 64, (vanka_waves_per_simd<D, S>())
                                                                 S* __restrict__ xn, const int* __restrict__ active) {
   FSI_DIM(D);
   static_assert(VC == 8 || VC == 16 || VC == 32, "cells per block");
+  // the pressure-stabilisation row of a node is spread over the D
+  // displacement-row waves, which have the fewest block-stencil loads (in 2d
+  // FP64 the pressure wave keeps it: measured as fast, and one barrier fewer)
+  constexpr bool SPLIT = !(D == 2 && sizeof(S) == 8);
   __shared__ S rs[NE][VC];
+  __shared__ S pp[SPLIT ? NL : 1][D][VC];   // parts of the pressure rows' stabilisation terms
   const int bs = blockIdx.y;
   if (active && !active[bs]) return;   // uniform over the block
   const ColorInfo L = color_info<D>(g, color, VC);
@@ -164,12 +169,29 @@ __global__ void __launch_bounds__(Dm<D>::NC * 64, (vanka_waves_per_simd<D, S>())
         // (3d: the copy whose tiles start where this colour's node runs start)
         const S* jn = J + (size_t)bs * jslice<D, S, CJ>(g) + jnode<D, S, CJ>(g, i, j + (g.ny + 1) * kk, cx);
         acc = stencil_row<D, S, CJ>(jn, xob, n, r, nbr_offsets<D>(g, i, j, kk));
-        if (r == PC) acc += pst_row<D, S>(g, k, n, i, j, kk, xob);
+        if (!SPLIT && r == PC) acc += pst_row<D, S>(g, k, n, i, j, kk, xob);
+        if (SPLIT && r >= D && r < 2 * D) {
+          constexpr int NROW = D == 3 ? 25 : 5;
+          const int part = r - D;
+          pp[a][part][jc] = pst_rows<D, S>(g, k, n, i, j, kk, xob, part * NROW / D, (part + 1) * NROW / D);
+        }
       }
       rs[NC * a + r][jc] = b[((size_t)bs * g.nn + n) * NC + r] - acc;
     }
   }
   __syncthreads();
+  if (SPLIT && !zero_in) {   // uniform over the block: every thread meets the barrier
+    if (live && r == PC) {
+#pragma unroll 1
+      for (int q = 0; q < NQ; ++q) {
+        const int a = a0 + q * QS;
+        S s = pp[a][0][jc];
+        for (int part = 1; part < D; ++part) s += pp[a][part][jc];
+        rs[NC * a + PC][jc] -= s;
+      }
+    }
+    __syncthreads();
+  }
   if (!live) return;
   const S* ai =
       Ainv + (size_t)bs * ainv_slice<D>(g.ncell) + ((size_t)L.off + (size_t)blockIdx.x * VC) * NE * NE + jc;
