@@ -14,9 +14,10 @@ namespace fsi {
 struct Nbr {
   int ox[3], oy[3], oz[3];
 };
+// W, P: the strides of y and z in the indexing of x (the mesh's own, or those of
+// a block's staged copy of its neighbourhood)
 template <int D>
-__device__ inline Nbr nbr_offsets(const Geom& g, int i, int j, int k) {
-  const int W = g.nx + 1, P = W * (g.ny + 1);
+__device__ inline Nbr nbr_offsets(const Geom& g, int i, int j, int k, int W, int P) {
   Nbr o;
   o.ox[0] = i > 0 ? -1 : 0;
   o.ox[1] = 0;
@@ -28,6 +29,10 @@ __device__ inline Nbr nbr_offsets(const Geom& g, int i, int j, int k) {
   o.oz[1] = 0;
   o.oz[2] = D == 3 && k < g.nz ? P : 0;
   return o;
+}
+template <int D>
+__device__ inline Nbr nbr_offsets(const Geom& g, int i, int j, int k) {
+  return nbr_offsets<D>(g, i, j, k, g.nx + 1, (g.nx + 1) * (g.ny + 1));
 }
 
 // k * sum_q pst[q][n] x_p(neighbour q) over the 5^D pressure stencil (clamped
@@ -68,6 +73,26 @@ __device__ inline S pst_rows(const Geom& g, double k, int n, int i, int j, int k
 #pragma unroll
     for (int dx = 0; dx < 5; ++dx)
       ap += (S)g.pst[(size_t)(5 * rr + dx) * g.nn + n] * xb[(size_t)(cx[dx] + oy + oz) * NC + PC];
+  }
+  return (S)k * ap;
+}
+
+// The same from a staged copy of the pressure values of a box of nodes: xp
+// holds p at (x, y, z) = (X0 + lx, Y0 + ly, Z0 + lz) at lx + RX (ly + RY lz);
+// the box contains every clamped stencil neighbour of node (i, j, kk).
+template <int D, class S>
+__device__ inline S pst_rows_staged(const Geom& g, double k, int n, int i, int j, int kk, const S* xp, int X0,
+                                    int Y0, int Z0, int RX, int RY, int r0, int r1) {
+  int cx[5];
+#pragma unroll
+  for (int d = 0; d < 5; ++d) cx[d] = min(max(i + d - 2, 0), g.nx) - X0;
+  S ap = 0;
+  for (int rr = r0; rr < r1; ++rr) {
+    const int dy = rr % 5, dz = rr / 5;
+    const int oy = RX * (min(max(j + dy - 2, 0), g.ny) - Y0);
+    const int oz = D == 3 ? RX * RY * (min(max(kk + dz - 2, 0), g.nz) - Z0) : 0;
+#pragma unroll
+    for (int dx = 0; dx < 5; ++dx) ap += (S)g.pst[(size_t)(5 * rr + dx) * g.nn + n] * xp[cx[dx] + oy + oz];
   }
   return (S)k * ap;
 }

@@ -124,6 +124,12 @@ __global__ void __launch_bounds__(Dm<D>::NC * 64, (vanka_waves_per_simd<D, S>())
   constexpr bool SPLIT = !(D == 2 && sizeof(S) == 8);
   __shared__ S rs[NE][VC];
   __shared__ S pp[SPLIT ? NL : 1][D][VC];   // parts of the pressure rows' stabilisation terms
+  // staged x around the block's nodes: all components within one node (box
+  // RX1 x RY1 x RZ1), the pressure within two (box RX2 x RY2 x RZ2)
+  constexpr int RX1 = 2 * VC + 2, RY1 = 4, RZ1 = D == 3 ? 4 : 1;
+  constexpr int RX2 = 2 * VC + 4, RY2 = 6, RZ2 = D == 3 ? 6 : 1;
+  __shared__ S xr[RX1 * RY1 * RZ1 * NC];
+  __shared__ S pr[RX2 * RY2 * RZ2];
   const int bs = blockIdx.y;
   if (active && !active[bs]) return;   // uniform over the block
   const ColorInfo L = color_info<D>(g, color, VC);
@@ -152,6 +158,30 @@ __global__ void __launch_bounds__(Dm<D>::NC * 64, (vanka_waves_per_simd<D, S>())
   const int a0 = (lane & 1) + 2 * (lane / (2 * VC));
   const int idx = blockIdx.x * VC + jc;
   const bool live = idx < nc;
+  // The block's cells lie in one cell row when the colour's rows hold whole
+  // blocks: then the x values its stencils read are staged in LDS once
+  // (block-uniform), instead of every wave loading every neighbour's vector.
+  const bool stage = !zero_in && L.ncx % VC == 0;
+  int X1 = 0, Y1 = 0, Z1 = 0;
+  if (stage) {
+    const int idx0 = blockIdx.x * VC, rest0 = idx0 / L.ncx;
+    X1 = 2 * (idx0 % L.ncx) + cx - 1;
+    Y1 = 2 * (rest0 % L.ncy) + cy - 1;
+    Z1 = D == 3 ? 2 * (rest0 / L.ncy) + cz - 1 : 0;
+    const int W = g.nx + 1, P = W * (g.ny + 1);
+    for (int e = threadIdx.x; e < RX1 * RY1 * RZ1 * NC; e += NC * 64) {
+      const int c = e % NC, t = e / NC;
+      const int gx = min(max(X1 + t % RX1, 0), g.nx), gy = min(max(Y1 + (t / RX1) % RY1, 0), g.ny);
+      const int gz = D == 3 ? min(max(Z1 + t / (RX1 * RY1), 0), g.nz) : 0;
+      xr[e] = xob[(size_t)(gx + W * gy + P * gz) * NC + c];
+    }
+    for (int e = threadIdx.x; e < RX2 * RY2 * RZ2; e += NC * 64) {
+      const int gx = min(max(X1 - 1 + e % RX2, 0), g.nx), gy = min(max(Y1 - 1 + (e / RX2) % RY2, 0), g.ny);
+      const int gz = D == 3 ? min(max(Z1 - 1 + e / (RX2 * RY2), 0), g.nz) : 0;
+      pr[e] = xob[(size_t)(gx + W * gy + P * gz) * NC + PC];
+    }
+    __syncthreads();
+  }
   int ci = 0, cj = 0, ck = 0;
   if (live) {
     const int ix = idx % L.ncx, rest = idx / L.ncx;
@@ -168,12 +198,19 @@ __global__ void __launch_bounds__(Dm<D>::NC * 64, (vanka_waves_per_simd<D, S>())
         node_ijk<D>(g, n, i, j, kk);
         // (3d: the copy whose tiles start where this colour's node runs start)
         const S* jn = J + (size_t)bs * jslice<D, S, CJ>(g) + jnode<D, S, CJ>(g, i, j + (g.ny + 1) * kk, cx);
-        acc = stencil_row<D, S, CJ>(jn, xob, n, r, nbr_offsets<D>(g, i, j, kk));
-        if (!SPLIT && r == PC) acc += pst_row<D, S>(g, k, n, i, j, kk, xob);
-        if (SPLIT && r >= D && r < 2 * D) {
-          constexpr int NROW = D == 3 ? 25 : 5;
-          const int part = r - D;
-          pp[a][part][jc] = pst_rows<D, S>(g, k, n, i, j, kk, xob, part * NROW / D, (part + 1) * NROW / D);
+        constexpr int NROW = D == 3 ? 25 : 5;
+        const int part = r - D, p0 = part * NROW / D, p1 = (part + 1) * NROW / D;
+        if (stage) {
+          const int ln = (i - X1) + RX1 * ((j - Y1) + RY1 * (kk - Z1));
+          acc = stencil_row<D, S, CJ>(jn, xr, ln, r, nbr_offsets<D>(g, i, j, kk, RX1, RX1 * RY1));
+          if (!SPLIT && r == PC)
+            acc += pst_rows_staged<D, S>(g, k, n, i, j, kk, pr, X1 - 1, Y1 - 1, Z1 - 1, RX2, RY2, 0, NROW);
+          if (SPLIT && r >= D && r < 2 * D)
+            pp[a][part][jc] = pst_rows_staged<D, S>(g, k, n, i, j, kk, pr, X1 - 1, Y1 - 1, Z1 - 1, RX2, RY2, p0, p1);
+        } else {
+          acc = stencil_row<D, S, CJ>(jn, xob, n, r, nbr_offsets<D>(g, i, j, kk));
+          if (!SPLIT && r == PC) acc += pst_row<D, S>(g, k, n, i, j, kk, xob);
+          if (SPLIT && r >= D && r < 2 * D) pp[a][part][jc] = pst_rows<D, S>(g, k, n, i, j, kk, xob, p0, p1);
         }
       }
       rs[NC * a + r][jc] = b[((size_t)bs * g.nn + n) * NC + r] - acc;
