@@ -38,6 +38,11 @@ namespace {
 constexpr int TPB = 256;
 constexpr int MAXLEV = 8;
 constexpr int NCHUNK_MAX = 1024;
+// elements per block of the Krylov dot products (one partial sum per block and
+// vector): at least KDOT_CHUNK, and about KDOT_BLOCKS blocks per slice, so a
+// slice batch fills the GPU and the partial sums stay few
+constexpr int KDOT_CHUNK = 512;
+constexpr int KDOT_BLOCKS = 48;
 
 struct Level {
   int nx = 0, ny = 0, nz = 0, nn = 0, ncell = 0;   // nz = 0 in 2d
@@ -678,7 +683,7 @@ fsi_status fgmres(fsi_problem* pb, int B, double k, std::vector<int>& kits, hipS
   S* w = (S*)pb->w;
   S* xs = (S*)pb->xs;
   S* tmp = (S*)pb->tmp;
-  const int chunk = 2048;
+  const int chunk = std::max(KDOT_CHUNK, (n + KDOT_BLOCKS * 256 - 1) / (KDOT_BLOCKS * 256) * 256);
   const int nchunk = (n + chunk - 1) / chunk;
   const dim3 gb((B + 63) / 64), tb(64);
   std::vector<int> hstate(B);
@@ -1203,7 +1208,7 @@ fsi_status fsi_setup(const fsi_params* prm, fsi_problem** out) {
   A_(dalloc(pb, &pb->beta0, B));
   A_(dalloc(pb, &pb->beta, B));
   A_(dalloc(pb, &pb->ycoef, (size_t)B * 64));
-  A_(dalloc(pb, &pb->partial, (size_t)B * 64 * ((ndof + 2047) / 2048 + 1)));
+  A_(dalloc(pb, &pb->partial, (size_t)B * 64 * ((ndof + KDOT_CHUNK - 1) / KDOT_CHUNK + 1)));
   A_(dalloc(pb, &pb->gstate, B));
   A_(dalloc(pb, &pb->ncol, B));
   A_(dalloc(pb, &pb->ltol, B));
