@@ -529,10 +529,10 @@ fsi_status assemble_levels(fsi_problem* pb, int B, const StepPar& sp, const int*
     } else {
       const size_t lds_f = (size_t)5 * pb->cbs * pb->cbs * sizeof(double);
       const size_t lds_i = (size_t)3 * pb->cbs * pb->cbs * sizeof(double);
-      k_coarse_factor<S, CJ><<<B, TPB, lds_f, st>>>(g, sp.k, (const S*)lv.J, pb->cbs, pb->cnsb, pb->cDinv, pb->cW,
-                                                pb->cL, act);
-      k_coarse_inverse<S><<<dim3(pb->cnsb, B), TPB, lds_i, st>>>(g, pb->cbs, pb->cnsb, pb->cDinv, pb->cW, pb->cL,
-                                                                 pb->cY, (S*)pb->cAinv, act);
+      k_coarse_factor<S, CJ><<<B, CF_THREADS, lds_f, st>>>(g, sp.k, (const S*)lv.J, pb->cbs, pb->cnsb, pb->cDinv,
+                                                           pb->cW, pb->cL, act);
+      k_coarse_inverse<S><<<dim3(pb->cnsb, B), CF_THREADS, lds_i, st>>>(g, pb->cbs, pb->cnsb, pb->cDinv, pb->cW,
+                                                                        pb->cL, pb->cY, (S*)pb->cAinv, act);
     }
     HIPCHK(hipGetLastError());
   }

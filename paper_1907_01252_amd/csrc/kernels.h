@@ -7,6 +7,11 @@
 
 namespace fsi {
 
+// threads of the coarsest-level factorisation and inverse kernels (one block per
+// slice, or per slice and super-column): the dense block work of a slice is
+// spread over all of them
+constexpr int CF_THREADS = 1024;
+
 template <int D>
 __global__ void k_elem_residual(Geom g, StepPar sp, const double* U, const double* Uo, double* Re, const int* active);
 template <int D, bool OLD>

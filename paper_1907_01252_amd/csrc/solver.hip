@@ -6,6 +6,7 @@
 // flag is 0.  S is the storage and arithmetic type of the linear solve
 // (double, or float in the mixed-precision path); D the space dimension.
 #include "stencil.h"
+#include "kernels.h"
 
 namespace fsi {
 
@@ -265,7 +266,7 @@ __device__ inline void tile_gemm(int bsz, const double* A, const double* Bm, dou
 // (bs x bs each).  Gauss-Jordan with partial pivoting: wave 0 finds the pivot and
 // the row factors, then every thread owns columns of [Delta | I] for the update.
 template <class S, bool CJ>
-__global__ void __launch_bounds__(256) k_coarse_factor(Geom g, double k, const S* __restrict__ J, int bsz, int nsb,
+__global__ void __launch_bounds__(CF_THREADS) k_coarse_factor(Geom g, double k, const S* __restrict__ J, int bsz, int nsb,
                                                        double* __restrict__ Dinv, double* __restrict__ W,
                                                        double* __restrict__ Lb, const int* __restrict__ active) {
   extern __shared__ double lds[];
@@ -363,7 +364,7 @@ __global__ void __launch_bounds__(256) k_coarse_factor(Geom g, double k, const S
 // Block products run on LDS tiles; Y blocks go through a global scratch.
 // The result is written in dof order, column-major: AinvS[b][j][i].
 template <class S>
-__global__ void __launch_bounds__(256) k_coarse_inverse(Geom g, int bsz, int nsb, const double* __restrict__ Dinv,
+__global__ void __launch_bounds__(CF_THREADS) k_coarse_inverse(Geom g, int bsz, int nsb, const double* __restrict__ Dinv,
                                                         const double* __restrict__ W, const double* __restrict__ Lb,
                                                         double* __restrict__ Ysc, S* __restrict__ AinvS,
                                                         const int* __restrict__ active) {
