@@ -60,10 +60,10 @@ def counter_traffic(kernel_family, prec):
 
 
 def kernel_source_hash(fn):
-    """Hash of the dominant kernel's source (vanka.hip, which holds the kernel and the
-    factor kernel that writes its inverses, stencil.h with its device helpers, and the
-    shared layout header), tagged with the kernel name: any edit there invalidates
-    counter figures taken before it."""
+    """Hash of the dominant kernel's source (vanka.hip, which holds the kernel, stencil.h
+    with its device helpers, and the shared layout header with the storage of the
+    Jacobian and of the inverses it reads), tagged with the kernel name: any edit there
+    invalidates counter figures taken before it."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_1907_01252_amd", "csrc")
     src = "".join(open(os.path.join(csrc, f)).read() for f in ("vanka.hip", "stencil.h", "fsi_internal.h"))

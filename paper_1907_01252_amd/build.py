@@ -15,7 +15,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfsi.so")
-SOURCES = ["assemble.hip", "solver.hip", "vanka.hip", "driver.hip"]
+SOURCES = ["assemble.hip", "solver.hip", "vanka.hip", "vanka_factor.hip", "driver.hip"]
 ARCH = os.environ.get("FSI_OFFLOAD_ARCH", "gfx950")
 FLAGS = [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
          # packed FP32 instructions are kept out of the generated code

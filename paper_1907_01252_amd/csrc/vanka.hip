@@ -1,88 +1,11 @@
-// Vanka smoother kernels: the cell-patch inverses (Gauss-Jordan in LDS) and
-// the fused colored multiplicative pass (patch residuals from the block stencil
-// and the patch update in one kernel).  Every kernel takes the slice index from
+// The fused colored multiplicative Vanka pass: patch residuals from the block
+// stencil and the patch update in one kernel (the patch inverses it applies
+// are formed in vanka_factor.hip).  Every kernel takes the slice index from
 // blockIdx.y and skips slices whose active flag is 0; S is the storage type of
 // the linear solve, D the space dimension, CJ the Jacobian block layout.
 #include "stencil.h"
 
 namespace fsi {
-
-// ------------------------------------------------------- Vanka patch inverse
-// One lane group (vf_lanes lanes) inverts the NE x NE patch matrix of one cell
-// (rows = local unknowns NC a + c) by Gauss-Jordan with partial pivoting.
-// [A | I] lives in LDS, lane r owning row r; per column the pivot row is
-// found by a shuffle reduction and every other row eliminates the column with
-// the (unscaled) pivot row.  Rows are scaled by their pivots at the end, which
-// gives the same inverse as scaling at each step.  Ainv is stored by colour and
-// block of vc cells of the fused pass (ainv_slice in fsi_internal.h).
-template <int D, class S, bool CJ>
-__global__ void __launch_bounds__(vf_lanes<D>() * vf_patches<D>()) k_vanka_factor(Geom g, double k,
-                                                                                  const S* __restrict__ J,
-                                                                                  S* __restrict__ Ainv, int vc,
-                                                                                  const int* __restrict__ active) {
-  FSI_DIM(D);
-  constexpr int GL = vf_lanes<D>(), NP = vf_patches<D>(), LD = 2 * NE + 1;
-  __shared__ double M[NP][NE][LD];
-  const int bs = blockIdx.y;
-  if (active && !active[bs]) return;   // uniform over the block
-  const int grp = threadIdx.x / GL, lane = threadIdx.x % GL;
-  const int cell = blockIdx.x * NP + grp;
-  const bool live = cell < g.ncell;
-  int ci = 0, cj = 0, ck = 0;
-  if (live) cell_ijk<D>(g, cell, ci, cj, ck);
-  double(*Mp)[LD] = M[grp];
-  if (lane < NE) {
-    const int a = lane / NC, rc = lane % NC;
-    const int ax = a & 1, ay = (a >> 1) & 1, az = (a >> 2) & 1;
-    const int na = node_at(g, ci + ax, cj + ay, ck + az);
-    if (live) {
-      const S* jn = J + (size_t)bs * jslice<D, S, CJ>(g) + jnode_n<D, S, CJ>(g, na, 0);
-      const bool pst_row = (rc == PC) && !(g.dmask[na] & dm_p<D>());
-      for (int bb = 0; bb < NL; ++bb) {
-        const int dx = (bb & 1) - ax, dy = ((bb >> 1) & 1) - ay, dz = ((bb >> 2) & 1) - az;
-        const int s = slot_of<D>(dx, dy, dz);
-        for (int c = 0; c < NC; ++c) {
-          const int e = jentry<D, CJ>(rc, c);
-          Mp[lane][NC * bb + c] = e >= 0 ? (double)jn[jent<D, S, CJ>(s, e)] : 0.0;
-        }
-        if (pst_row) Mp[lane][NC * bb + PC] += k * g.pst[(size_t)pslot_of<D>(dx, dy, dz) * g.nn + na];
-      }
-    } else {
-      for (int c = 0; c < NE; ++c) Mp[lane][c] = (c == lane) ? 1.0 : 0.0;
-    }
-    for (int c = 0; c < NE; ++c) Mp[lane][NE + c] = (c == lane) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  bool used = lane >= NE;
-  int mycol = 0;
-  for (int jc = 0; jc < NE; ++jc) {
-    const double v = lane < NE ? Mp[lane][jc] : 0.0;
-    double cand = used ? -1.0 : fabs(v);
-    int idx = lane;
-#pragma unroll
-    for (int off = GL / 2; off > 0; off >>= 1) {
-      const double oc = __shfl_xor(cand, off, GL);
-      const int oi = __shfl_xor(idx, off, GL);
-      if (oc > cand || (oc == cand && oi < idx)) { cand = oc; idx = oi; }
-    }
-    double pv = Mp[idx][jc];
-    if (pv == 0.0) pv = 1.0;   // singular patch: leave the column alone
-    if (lane == idx) { used = true; mycol = jc; }
-    const double f = (lane < NE && lane != idx) ? v / pv : 0.0;
-    if (f != 0.0)
-      for (int c = jc; c < 2 * NE; ++c) Mp[lane][c] -= f * Mp[idx][c];
-    __syncthreads();
-  }
-  if (live && lane < NE) {
-    int col, idx;
-    ColorInfo L;
-    cell_colour<D>(g, ci, cj, ck, vc, col, idx, L);
-    const double d = Mp[lane][mycol] != 0.0 ? 1.0 / Mp[lane][mycol] : 1.0;
-    const int q = idx / vc, t = idx - q * vc;
-    S* out = Ainv + (size_t)bs * ainv_slice<D>(g.ncell) + ((size_t)L.off + (size_t)q * vc) * NE * NE + t;
-    for (int c = 0; c < NE; ++c) out[(size_t)(NE * mycol + c) * vc] = (S)(Mp[lane][NE + c] * d);
-  }
-}
 
 // ------------------------------------------------------ colored Vanka pass
 // One multiplicative pass over the cells of one colour, residual and patch
@@ -247,7 +170,6 @@ __global__ void __launch_bounds__(Dm<D>::NC * 64, (vanka_waves_per_simd<D, S>())
 }
 
 #define FSI_INST_VANKA(D, S)                                                                                      \
-  template __global__ void k_vanka_factor<D, S, true>(Geom, double, const S*, S*, int, const int*);              \
   template __global__ void k_vanka_color<D, S, (D == 2 ? 16 : 32), true>(Geom, double, int, S, int, const S*,   \
                                                                          const S*, const S*, const S*, S*,      \
                                                                          const int*);
@@ -261,7 +183,6 @@ template __global__ void k_vanka_color<3, double, 8, true>(Geom, double, int, do
 template __global__ void k_vanka_color<3, float, 8, true>(Geom, double, int, float, int, const float*, const float*,
                                                           const float*, const float*, float*, const int*);
 // full-layout operators of the (2d, FP64) transposed adjoint system
-template __global__ void k_vanka_factor<2, double, false>(Geom, double, const double*, double*, int, const int*);
 template __global__ void k_vanka_color<2, double, 16, false>(Geom, double, int, double, int, const double*,
                                                              const double*, const double*, const double*, double*,
                                                              const int*);
