@@ -122,7 +122,11 @@ typedef struct {
 
 /* Build the mesh hierarchy, node classes, constant stabilisation operators and
    device workspace for params->max_batch slices.  *out receives the handle.
-   Errors: FSI_ERR_ARG (bad params), FSI_ERR_OOM, FSI_ERR_HIP. */
+   Errors: FSI_ERR_ARG (bad params: a size or count out of range, a non-finite
+   constant, rho_f, nu_f, rho_s, mu_s or ramp_time not positive, lambda_s,
+   theta0, lps_alpha0 or cip_gamma negative, vanka_omega outside (0, 2),
+   newton_rtol not positive, lin_rtol or lin_rtol_first outside (0, 1)),
+   FSI_ERR_OOM, FSI_ERR_HIP. */
 fsi_status fsi_setup(const fsi_params* params, fsi_problem** out);
 
 /* Number of mesh nodes and of unknowns (5 per node in 2d) on the finest level. */
@@ -135,8 +139,10 @@ fsi_status fsi_initial_state(fsi_problem* pb, double* U0_dev, hipStream_t stream
    size k = slice_len / m from t0_host[b] (host array), starting from
    U_in_dev[b] and writing the final state to U_out_dev[b] (both [B][n_dofs],
    may alias).  The pressure of U_in only seeds Newton.  Per-slice status and
-   iteration counts go to stats (host, may be NULL).  Non-finite input gives
-   FSI_ERR_NONFINITE before any work; a slice that fails keeps its last iterate. */
+   iteration counts go to stats (host, may be NULL).  FSI_ERR_ARG if B is not
+   in [1, max_batch], m < 1, slice_len is not positive or a pointer is NULL;
+   non-finite input gives FSI_ERR_NONFINITE before any work (U_out is then not
+   written); a slice that fails keeps its last iterate. */
 fsi_status fine_propagate(fsi_problem* pb, int32_t B, const double* t0_host, double slice_len,
                           int32_t m, const double* U_in_dev, double* U_out_dev,
                           fsi_stats* stats, hipStream_t stream);

@@ -1148,6 +1148,14 @@ fsi_status fsi_setup(const fsi_params* prm, fsi_problem** out) {
       if (p.seg_cells[a][s] < 1 || !(p.seg_pts[a][s + 1] > p.seg_pts[a][s])) return FSI_ERR_ARG;
   }
   if (!(p.rho_f > 0 && p.nu_f > 0 && p.rho_s > 0 && p.ramp_time > 0)) return FSI_ERR_ARG;
+  // the remaining physical and solver constants: finite, and in the range where
+  // the scheme and the solver are defined
+  for (double v : {p.rho_f, p.nu_f, p.rho_s, p.mu_s, p.lambda_s, p.inflow_peak, p.ramp_time, p.theta0, p.lps_alpha0,
+                   p.cip_gamma, p.vanka_omega, p.newton_rtol, p.lin_rtol})
+    if (!std::isfinite(v)) return FSI_ERR_ARG;
+  if (!(p.mu_s > 0) || p.lambda_s < 0 || p.theta0 < 0 || p.lps_alpha0 < 0 || p.cip_gamma < 0 ||
+      !(p.vanka_omega > 0 && p.vanka_omega < 2) || !(p.newton_rtol > 0) || !(p.lin_rtol > 0 && p.lin_rtol < 1))
+    return FSI_ERR_ARG;
   fsi_problem* pb = new (std::nothrow) fsi_problem();
   if (!pb) return FSI_ERR_OOM;
   pb->p = p;
