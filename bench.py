@@ -154,7 +154,9 @@ def main():
     t_b = time.perf_counter()
     wall = (t_b - t_a) / args.steps
     # one more sweep of the same workload with HIP events around every launch of the
-    # profiled kernel families (kernels launched directly, not replayed from graphs)
+    # profiled kernel families (kernels launched directly, not replayed from graphs; the
+    # library runs it as one batch of all slices, so that no other group's kernels share
+    # the GPU with a timed launch)
     prof_wall = 0.0
     fams = {name: (0, 0.0, 0.0) for name in FAMILIES}
     if not args.no_profile_sweep:
@@ -240,7 +242,7 @@ def main():
                                f"{p['level']}-level-refined {'x'.join(str(c) for c in synth.mesh_shape(p))} Q1, "
                                f"{nd} unknowns, {N} slices x {m} steps of {p['k_fine']:.6g}",
                    "slices": N, "steps_per_slice": m, "unknowns": nd, "precision": prec,
-                   "solver_overrides": overrides},
+                   "batch_split": int(prob.params.batch_split), "solver_overrides": overrides},
         "newton_per_sweep": stats[-1][0], "krylov_per_sweep": stats[-1][1],
         "sequential": seq,
         "speedup_batched_vs_sequential": (value / seq["value"]) if seq else None,
@@ -248,7 +250,8 @@ def main():
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
                      "traffic": counter_traffic(dom, prec) if args.workload == "c2" else None,
                      "kernel": KERNEL_NAMES.get(dom, dom), "launches": dn,
-                     "mean_launch_us": 1e3 * dms / max(dn, 1), "bytes_per_launch": dby / max(dn, 1)},
+                     "mean_launch_us": 1e3 * dms / max(dn, 1), "bytes_per_launch": dby / max(dn, 1),
+                     "measured_on": "profiled sweep: all slices in one batch, HIP events around every launch"},
         "profiled_sweep_ms": 1e3 * prof_wall,
         "kernels": {f: {"launches": v[0], "ms_per_sweep": v[1],
                         "GBs": (v[2] / (v[1] * 1e-3) / 1e9) if v[1] > 0 else None} for f, v in fams.items()},

@@ -107,6 +107,19 @@ typedef struct {
                                 inputs, overlapped with the rest of the sweep.  Same iterates
                                 as 0.  The second workspace (max_batch G) is created on the
                                 first such call and kept with the problem. */
+  int32_t batch_split;       /* fine_propagate / coarse_propagate with B >= 2 slices:
+                                0 or 1: one batch on the library stream;
+                                S in [2, 4] (and <= max_batch): the slices are cut into S
+                                consecutive groups of (nearly) equal size, each run by its
+                                own host thread on its own workspace and stream, so that
+                                one group's latency-bound phases (coarse levels, Krylov
+                                scalars, host synchronisation) overlap another group's
+                                bandwidth-bound passes on the same GPU.  Every slice's
+                                arithmetic is that of the single batch (same results, bit
+                                for bit).  The S - 1 extra workspaces (max_batch
+                                ceil(max_batch / S) each) are created by fsi_setup.  Calls
+                                made while per-kernel timing is enabled, and the adjoint's
+                                recompute, run as one batch. */
 } fsi_params;
 
 #define FSI_MAX_SLICES 1024
@@ -125,7 +138,8 @@ typedef struct {
    Errors: FSI_ERR_ARG (bad params: a size or count out of range, a non-finite
    constant, rho_f, nu_f, rho_s, mu_s or ramp_time not positive, lambda_s,
    theta0, lps_alpha0 or cip_gamma negative, vanka_omega outside (0, 2),
-   newton_rtol not positive, lin_rtol or lin_rtol_first outside (0, 1)),
+   newton_rtol not positive, lin_rtol or lin_rtol_first outside (0, 1),
+   batch_split outside [0, 4] or above max_batch),
    FSI_ERR_OOM, FSI_ERR_HIP. */
 fsi_status fsi_setup(const fsi_params* params, fsi_problem** out);
 

@@ -134,6 +134,8 @@ struct fsi_problem {
   std::vector<void*> allocs;
   // pipelined Parareal: workspace of the fine-sweep worker (created on first use)
   fsi_problem* pipe = nullptr;
+  // concurrent slice groups of a propagator call: workspaces of groups 1 .. S-1
+  std::vector<fsi_problem*> sub;
 };
 
 namespace {
@@ -850,17 +852,10 @@ fsi_status newton_solve_step(fsi_problem* pb, int B, const StepPar& sp, std::vec
   return FSI_OK;
 }
 
-template <int D, class S>
-fsi_status propagate(fsi_problem* pb, int B, const double* t0, double slice_len, int nsteps, const double* U_in,
-                     double* U_out, fsi_stats* stats, hipStream_t st) {
-  FSI_DIM(D);
-  Level& F = pb->lev[pb->nlev - 1];
-  const Geom g = F.geom();
-  const size_t ndof = (size_t)F.nn * NC;
-  const double k = slice_len / nsteps;
-  const StepPar sp = step_par(pb, k);
-  auto t_start = std::chrono::steady_clock::now();
-  // non-finite input check
+// FSI_ERR_NONFINITE (with the status of every slice) if any of the B input
+// states holds a value that is not finite
+fsi_status check_finite(fsi_problem* pb, int B, const double* U_in, fsi_stats* stats, hipStream_t st) {
+  const size_t ndof = (size_t)pb->lev[pb->nlev - 1].nn * (2 * pb->p.dim + 1);
   HIPCHK(hipMemsetAsync(pb->flag, 0, B * sizeof(int), st));
   k_nonfinite<<<dim3(64, B), TPB, 0, st>>>(ndof, U_in, pb->flag);
   std::vector<int> hflag(B);
@@ -869,9 +864,23 @@ fsi_status propagate(fsi_problem* pb, int B, const double* t0, double slice_len,
   for (int b = 0; b < B; ++b)
     if (hflag[b]) {
       if (stats)
-        for (int q = 0; q < B; ++q) stats->slice_status[q] = hflag[q] ? FSI_ERR_NONFINITE : FSI_OK;
+        for (int q = 0; q < B && q < FSI_MAX_SLICES; ++q) stats->slice_status[q] = hflag[q] ? FSI_ERR_NONFINITE : FSI_OK;
       return FSI_ERR_NONFINITE;
     }
+  return FSI_OK;
+}
+
+template <int D, class S>
+fsi_status propagate(fsi_problem* pb, int B, const double* t0, double slice_len, int nsteps, const double* U_in,
+                     double* U_out, fsi_stats* stats, hipStream_t st, bool check_input) {
+  FSI_DIM(D);
+  Level& F = pb->lev[pb->nlev - 1];
+  const Geom g = F.geom();
+  const size_t ndof = (size_t)F.nn * NC;
+  const double k = slice_len / nsteps;
+  const StepPar sp = step_par(pb, k);
+  auto t_start = std::chrono::steady_clock::now();
+  if (check_input) CHK(check_finite(pb, B, U_in, stats, st));
   HIPCHK(hipMemcpyAsync(pb->U, U_in, (size_t)B * ndof * sizeof(double), hipMemcpyDeviceToDevice, st));
   RunStats rs;
   rs.newton.assign(B, 0);
@@ -920,6 +929,17 @@ fsi_status propagate(fsi_problem* pb, int B, const double* t0, double slice_len,
   return ret;
 }
 
+// One batch of B slices on pb's workspace and stream (which already waits for the caller's work).
+fsi_status propagate_batch(fsi_problem* pb, int B, const double* t0, double slice_len, int nsteps,
+                           const double* U_in, double* U_out, fsi_stats* stats, bool check_input) {
+  hipStream_t st = pb->ist;
+  if (pb->p.dim == 3)
+    return pb->mixed ? propagate<3, float>(pb, B, t0, slice_len, nsteps, U_in, U_out, stats, st, check_input)
+                     : propagate<3, double>(pb, B, t0, slice_len, nsteps, U_in, U_out, stats, st, check_input);
+  return pb->mixed ? propagate<2, float>(pb, B, t0, slice_len, nsteps, U_in, U_out, stats, st, check_input)
+                   : propagate<2, double>(pb, B, t0, slice_len, nsteps, U_in, U_out, stats, st, check_input);
+}
+
 fsi_status run_propagate(fsi_problem* pb, int B, const double* t0, double slice_len, int nsteps, const double* U_in,
                          double* U_out, fsi_stats* stats, hipStream_t caller) {
   if (!pb || !t0 || !U_in || !U_out || B <= 0 || B > pb->Bmax || nsteps <= 0 || !(slice_len > 0.0))
@@ -929,12 +949,49 @@ fsi_status run_propagate(fsi_problem* pb, int B, const double* t0, double slice_
   // the call returns after completion, so the caller's later work sees the results
   HIPCHK(hipEventRecord(pb->iev, caller));
   HIPCHK(hipStreamWaitEvent(pb->ist, pb->iev, 0));
-  hipStream_t st = pb->ist;
-  if (pb->p.dim == 3)
-    return pb->mixed ? propagate<3, float>(pb, B, t0, slice_len, nsteps, U_in, U_out, stats, st)
-                     : propagate<3, double>(pb, B, t0, slice_len, nsteps, U_in, U_out, stats, st);
-  return pb->mixed ? propagate<2, float>(pb, B, t0, slice_len, nsteps, U_in, U_out, stats, st)
-                   : propagate<2, double>(pb, B, t0, slice_len, nsteps, U_in, U_out, stats, st);
+  const int S = std::min((int)pb->sub.size() + 1, B);
+  if (S <= 1 || pb->prof.on || pb->traj_out)
+    return propagate_batch(pb, B, t0, slice_len, nsteps, U_in, U_out, stats, true);
+  // concurrent slice groups: the whole batch's input is checked first, so that a
+  // bad slice stops the call before any group writes U_out
+  CHK(check_finite(pb, B, U_in, stats, pb->ist));
+  const size_t ndof = (size_t)pb->lev[pb->nlev - 1].nn * (2 * pb->p.dim + 1);
+  std::vector<int> g0(S + 1);
+  for (int g = 0; g <= S; ++g) g0[g] = (int)((long long)B * g / S);
+  std::vector<fsi_stats> gst(S);
+  std::vector<fsi_status> gret(S, FSI_OK);
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  auto group = [&](int g) {
+    fsi_problem* q = g == 0 ? pb : pb->sub[g - 1];
+    std::memset(&gst[g], 0, sizeof(fsi_stats));
+    if (g > 0 && (hipSetDevice(dev) != hipSuccess || hipEventRecord(q->iev, caller) != hipSuccess ||
+                  hipStreamWaitEvent(q->ist, q->iev, 0) != hipSuccess)) {
+      gret[g] = FSI_ERR_HIP;
+      return;
+    }
+    const int b0 = g0[g], nb = g0[g + 1] - g0[g];
+    gret[g] = propagate_batch(q, nb, t0 + b0, slice_len, nsteps, U_in + b0 * ndof, U_out + b0 * ndof, &gst[g], false);
+  };
+  std::vector<std::thread> th;
+  th.reserve(S - 1);
+  for (int g = 1; g < S; ++g) th.emplace_back(group, g);
+  group(0);
+  for (std::thread& t : th) t.join();
+  fsi_status ret = FSI_OK;
+  for (int g = 0; g < S; ++g) {
+    if (gret[g] != FSI_OK && ret == FSI_OK) ret = gret[g];
+    if (!stats) continue;
+    for (int b = g0[g]; b < g0[g + 1] && b < FSI_MAX_SLICES; ++b) {
+      stats->newton_its[b] = gst[g].newton_its[b - g0[g]];
+      stats->krylov_its[b] = gst[g].krylov_its[b - g0[g]];
+      stats->slice_status[b] = gst[g].slice_status[b - g0[g]];
+    }
+    stats->newton_total += gst[g].newton_total;
+    stats->krylov_total += gst[g].krylov_total;
+    for (int i = 0; i < 8; ++i) stats->stage_ms[i] = std::max(stats->stage_ms[i], gst[g].stage_ms[i]);
+  }
+  return ret;
 }
 
 // ------------------------------------------------------------ adjoint
@@ -1120,6 +1177,7 @@ const char* fsi_status_string(fsi_status s) {
 void fsi_destroy(fsi_problem* pb) {
   if (!pb) return;
   if (pb->pipe) fsi_destroy(pb->pipe);
+  for (fsi_problem* q : pb->sub) fsi_destroy(q);
   if (pb->vc_exec) (void)hipGraphExecDestroy(pb->vc_exec);
   if (pb->ist) (void)hipStreamSynchronize(pb->ist);
   if (pb->ist) (void)hipStreamDestroy(pb->ist);
@@ -1140,7 +1198,7 @@ fsi_status fsi_setup(const fsi_params* prm, fsi_problem** out) {
       p.gmres_maxit < 1 || (p.precision != FSI_FP64 && p.precision != FSI_MIXED) ||
       (p.precond_lag != 0 && p.precond_lag != 1) || !(p.lin_rtol_first > 0.0 && p.lin_rtol_first < 1.0) ||
       p.parareal_theta < 0 || p.parareal_theta > 2 || !(p.theta_ref_k >= 0.0) || p.parareal_pipeline < 0 ||
-      p.parareal_pipeline > p.max_batch)
+      p.parareal_pipeline > p.max_batch || p.batch_split < 0 || p.batch_split > 4 || p.batch_split > p.max_batch)
     return FSI_ERR_ARG;
   for (int a = 0; a < p.dim; ++a) {
     if (p.nseg[a] < 1 || p.nseg[a] > 4) return FSI_ERR_ARG;
@@ -1242,6 +1300,21 @@ fsi_status fsi_setup(const fsi_params* prm, fsi_problem** out) {
       hipEventCreateWithFlags(&pb->iev, hipEventDisableTiming) != hipSuccess) {
     fsi_destroy(pb);
     return FSI_ERR_HIP;
+  }
+  if (p.batch_split > 1) {
+    fsi_params q = p;
+    q.max_batch = (p.max_batch + p.batch_split - 1) / p.batch_split;
+    q.batch_split = 0;
+    q.parareal_pipeline = 0;
+    for (int g = 1; g < p.batch_split; ++g) {
+      fsi_problem* w = nullptr;
+      const fsi_status e = fsi_setup(&q, &w);
+      if (e != FSI_OK) {
+        fsi_destroy(pb);
+        return e;
+      }
+      pb->sub.push_back(w);
+    }
   }
   *out = pb;
   return FSI_OK;
@@ -1448,6 +1521,7 @@ fsi_status parareal_pipelined(fsi_problem* pb, double T, int N, int m, int M, do
     fsi_params q = pb->p;
     q.max_batch = G;
     q.parareal_pipeline = 0;
+    q.batch_split = 0;
     CHK(fsi_setup(&q, &pb->pipe));
   }
   fsi_problem* wp = pb->pipe;

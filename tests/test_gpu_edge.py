@@ -15,6 +15,10 @@
   zero norm.
 - A batch that is not full (B = 2 of max_batch 4, with different start times)
   gives the results of the full batch's first two slices.
+- Concurrent slice groups (batch_split 2 and 3, B = 5 of max_batch 5, so the
+  groups are uneven) give the single batch's states bit for bit and the same
+  per-slice Newton and Krylov counts; an infinite value in the last group's input stops
+  the call before any group writes U_out.
 """
 import sys
 
@@ -137,3 +141,30 @@ def test_partial_batch_equals_full_batch(fsi):
     err = np.abs(a - b).max() / np.abs(b).max()
     assert err <= 1e-12, err
     prob.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_concurrent_groups_equal_one_batch(fsi, precision):
+    p = synth.workload("c1", seed=5)
+    _say("case: c1 B=5, batch_split 0 vs 2 vs 3,", precision)
+    D = Discretization(p)
+    dl = p["slice_len"]
+    t0 = [l * dl for l in range(5)]
+    U = np.stack([D.apply_dirichlet(synth.smooth_state(p, 100 + l), t0[l]) for l in range(5)])
+    res = {}
+    for split in (0, 2, 3):
+        prob = fsi.Problem(fsi.make_params(p, precision=precision, max_batch=5, batch_split=split))
+        out = torch.zeros(5, prob.n_nodes, 5, dtype=torch.float64, device="cuda")
+        code, st = prob.fine_propagate(5, t0, dl, 3, _dev(U), out)
+        res[split] = (_host(out), list(st.newton_its[:5]), list(st.krylov_its[:5]), st.newton_total, st.krylov_total)
+        if split == 3:
+            bad = U.copy()
+            bad[4, 3, 0] = np.inf
+            sentinel = torch.full_like(out, 7.0)
+            code, st = prob.fine_propagate(5, t0, dl, 3, _dev(bad), sentinel, raise_on_error=False)
+            assert code == fsi.FSI_ERR_NONFINITE and list(st.slice_status[:5]) == [0, 0, 0, 0, fsi.FSI_ERR_NONFINITE]
+            assert bool((_host(sentinel) == 7.0).all())
+        prob.close()
+    for split in (2, 3):
+        assert np.array_equal(res[split][0], res[0][0]), (split, np.abs(res[split][0] - res[0][0]).max())
+        assert res[split][1:] == res[0][1:], (split, res[split][1:], res[0][1:])
