@@ -98,10 +98,13 @@ def _check(code, where):
         raise FsiError(code, where)
 
 
+# batch_split = 3: three concurrent slice groups measured fastest on one MI355X for
+# c2, c3 and c5 (four groups are slower: with the caller's stream they need more
+# hardware queues than a process gets by default)
 SOLVER_DEFAULTS = dict(cip_gamma=1e-4, gmres_restart=30, gmres_maxit=300, newton_maxit=30,
                        vanka_sweeps=2, vanka_omega=0.9, newton_rtol=1e-10, lin_rtol=1e-6,
                        vanka_sweeps_coarse=1, precond_lag=1, lin_rtol_first=1e-3, parareal_theta=0,
-                       theta_ref_k=0.0, parareal_pipeline=0, batch_split=2)
+                       theta_ref_k=0.0, parareal_pipeline=0, batch_split=3)
 # 3d: the multiplicative 8-colour Vanka sweep is stable only with more damping
 # (a sweep with omega 0.9 amplifies errors at the 64x16x16 level), and the
 # level-0 gradient-jump penalty needs a larger weight for the coarse correction
@@ -135,7 +138,7 @@ def make_params(d: dict, precision=None, max_batch=None, **solver) -> Params:
     p.precision = FSI_MIXED if prec in ("mixed", FSI_MIXED) else FSI_FP64
     p.max_batch = int(max_batch if max_batch is not None else d.get("N", 1))
     if "batch_split" not in solver and p.max_batch < s["batch_split"]:
-        s["batch_split"] = 0   # too few slices to split: one batch
+        s["batch_split"] = p.max_batch if p.max_batch >= 2 else 0   # no more groups than slices
     for key, v in s.items():
         setattr(p, key, type(getattr(p, key))(v))
     return p
