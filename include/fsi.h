@@ -117,9 +117,12 @@ typedef struct {
                                 bandwidth-bound passes on the same GPU.  Every slice's
                                 arithmetic is that of the single batch (same results, bit
                                 for bit).  The S - 1 extra workspaces (max_batch
-                                ceil(max_batch / S) each) are created by fsi_setup.  Calls
-                                made while per-kernel timing is enabled, and the adjoint's
-                                recompute, run as one batch. */
+                                ceil(max_batch / S) each) are created on the first call
+                                that splits (FSI_ERR_OOM from that call if they do not
+                                fit) and kept with the problem.  Calls made while
+                                per-kernel timing is enabled, and the adjoint's recompute,
+                                run as one batch.  Each group's stream takes a hardware
+                                queue: S = 3 leaves one for the caller's stream. */
 } fsi_params;
 
 #define FSI_MAX_SLICES 1024

@@ -949,9 +949,28 @@ fsi_status run_propagate(fsi_problem* pb, int B, const double* t0, double slice_
   // the call returns after completion, so the caller's later work sees the results
   HIPCHK(hipEventRecord(pb->iev, caller));
   HIPCHK(hipStreamWaitEvent(pb->ist, pb->iev, 0));
-  const int S = std::min((int)pb->sub.size() + 1, B);
+  const int S = std::min(std::max(pb->p.batch_split, 1), B);
   if (S <= 1 || pb->prof.on || pb->traj_out)
     return propagate_batch(pb, B, t0, slice_len, nsteps, U_in, U_out, stats, true);
+  // the groups' workspaces are made on the first call that splits (their streams then
+  // exist only in a process that uses them: each stream takes a hardware queue)
+  if (pb->sub.empty()) {
+    fsi_params q = pb->p;
+    q.max_batch = (pb->p.max_batch + pb->p.batch_split - 1) / pb->p.batch_split;
+    q.batch_split = 0;
+    q.parareal_pipeline = 0;
+    std::vector<fsi_problem*> ws;
+    for (int g = 1; g < pb->p.batch_split; ++g) {
+      fsi_problem* w = nullptr;
+      const fsi_status e = fsi_setup(&q, &w);
+      if (e != FSI_OK) {
+        for (fsi_problem* x : ws) fsi_destroy(x);
+        return e;
+      }
+      ws.push_back(w);
+    }
+    pb->sub = std::move(ws);
+  }
   // concurrent slice groups: the whole batch's input is checked first, so that a
   // bad slice stops the call before any group writes U_out
   CHK(check_finite(pb, B, U_in, stats, pb->ist));
@@ -1300,21 +1319,6 @@ fsi_status fsi_setup(const fsi_params* prm, fsi_problem** out) {
       hipEventCreateWithFlags(&pb->iev, hipEventDisableTiming) != hipSuccess) {
     fsi_destroy(pb);
     return FSI_ERR_HIP;
-  }
-  if (p.batch_split > 1) {
-    fsi_params q = p;
-    q.max_batch = (p.max_batch + p.batch_split - 1) / p.batch_split;
-    q.batch_split = 0;
-    q.parareal_pipeline = 0;
-    for (int g = 1; g < p.batch_split; ++g) {
-      fsi_problem* w = nullptr;
-      const fsi_status e = fsi_setup(&q, &w);
-      if (e != FSI_OK) {
-        fsi_destroy(pb);
-        return e;
-      }
-      pb->sub.push_back(w);
-    }
   }
   *out = pb;
   return FSI_OK;
