@@ -141,6 +141,19 @@ struct fsi_problem {
 namespace {
 
 // ------------------------------------------------------------------ helpers
+// Runs an entry point's body; a C++ exception (host allocation, thread start)
+// becomes a status instead of crossing the C ABI.
+template <class F>
+fsi_status guarded(F&& f) noexcept {
+  try {
+    return f();
+  } catch (const std::bad_alloc&) {
+    return FSI_ERR_OOM;
+  } catch (...) {
+    return FSI_ERR_HIP;
+  }
+}
+
 template <class T>
 fsi_status dalloc(fsi_problem* pb, T** p, size_t n) {
   void* q = nullptr;
@@ -990,12 +1003,22 @@ fsi_status run_propagate(fsi_problem* pb, int B, const double* t0, double slice_
       return;
     }
     const int b0 = g0[g], nb = g0[g + 1] - g0[g];
-    gret[g] = propagate_batch(q, nb, t0 + b0, slice_len, nsteps, U_in + b0 * ndof, U_out + b0 * ndof, &gst[g], false);
+    gret[g] = guarded([&] {
+      return propagate_batch(q, nb, t0 + b0, slice_len, nsteps, U_in + b0 * ndof, U_out + b0 * ndof, &gst[g], false);
+    });
   };
   std::vector<std::thread> th;
   th.reserve(S - 1);
-  for (int g = 1; g < S; ++g) th.emplace_back(group, g);
+  int started = 1;   // groups 1 .. started-1 have a thread; a group whose thread did not start runs here
+  try {
+    for (int g = 1; g < S; ++g) {
+      th.emplace_back(group, g);
+      started = g + 1;
+    }
+  } catch (...) {
+  }
   group(0);
+  for (int g = started; g < S; ++g) group(g);
   for (std::thread& t : th) t.join();
   fsi_status ret = FSI_OK;
   for (int g = 0; g < S; ++g) {
@@ -1206,7 +1229,13 @@ void fsi_destroy(fsi_problem* pb) {
   delete pb;
 }
 
+static fsi_status setup_impl(const fsi_params* prm, fsi_problem** out);
+
 fsi_status fsi_setup(const fsi_params* prm, fsi_problem** out) {
+  return guarded([&] { return setup_impl(prm, out); });
+}
+
+static fsi_status setup_impl(const fsi_params* prm, fsi_problem** out) {
   if (!prm || !out) return FSI_ERR_ARG;
   *out = nullptr;
   const fsi_params& p = *prm;
@@ -1350,13 +1379,15 @@ fsi_status fsi_initial_state(fsi_problem* pb, double* U0, hipStream_t st) {
 
 fsi_status fine_propagate(fsi_problem* pb, int32_t B, const double* t0, double slice_len, int32_t m,
                           const double* U_in, double* U_out, fsi_stats* stats, hipStream_t st) {
-  return run_propagate(pb, B, t0, slice_len, m, U_in, U_out, stats, st);
+  return guarded([&] { return run_propagate(pb, B, t0, slice_len, m, U_in, U_out, stats, st); });
 }
 
 fsi_status coarse_propagate(fsi_problem* pb, int32_t B, const double* t0, double slice_len, int32_t M,
                             const double* U_in, double* U_out, fsi_stats* stats, hipStream_t st) {
-  return run_propagate(pb, B, t0, slice_len, M, U_in, U_out, stats, st);
+  return guarded([&] { return run_propagate(pb, B, t0, slice_len, M, U_in, U_out, stats, st); });
 }
+
+}  // extern "C"
 
 namespace {
 
@@ -1693,6 +1724,8 @@ finish:
 
 }  // namespace
 
+extern "C" {
+
 fsi_status parareal_run(fsi_problem* pb, double T, int32_t N, int32_t m, int32_t M, double tol, int32_t max_iter,
                         const double* U0, double* Ub, fsi_stats* stats, hipStream_t st) {
   if (!pb || !U0 || !Ub || N < 1 || N > pb->Bmax || m < 1 || M < 1 || !(T > 0.0) || max_iter < 1) return FSI_ERR_ARG;
@@ -1702,10 +1735,11 @@ fsi_status parareal_run(fsi_problem* pb, double T, int32_t N, int32_t m, int32_t
   std::memset(sp, 0, sizeof(fsi_stats));
   auto t_start = std::chrono::steady_clock::now();
   double coarse_ms = 0.0, fine_ms = 0.0;
-  const fsi_status ret =
-      pb->p.parareal_pipeline > 0
-          ? parareal_pipelined(pb, T, N, m, M, tol, max_iter, U0, Ub, sp, coarse_ms, fine_ms, st)
-          : parareal_plain(pb, T, N, m, M, tol, max_iter, U0, Ub, sp, coarse_ms, fine_ms, st);
+  const fsi_status ret = guarded([&] {
+    return pb->p.parareal_pipeline > 0
+               ? parareal_pipelined(pb, T, N, m, M, tol, max_iter, U0, Ub, sp, coarse_ms, fine_ms, st)
+               : parareal_plain(pb, T, N, m, M, tol, max_iter, U0, Ub, sp, coarse_ms, fine_ms, st);
+  });
   (void)hipStreamSynchronize(st);
   sp->stage_ms[5] = coarse_ms;
   sp->stage_ms[6] = fine_ms;
@@ -1717,7 +1751,7 @@ fsi_status adjoint_gradient(fsi_problem* pb, double T, int32_t N, int32_t m, con
                             double* grad_out, fsi_stats* stats, hipStream_t st) {
   if (!pb || !U0 || !J_out || !grad_out || N < 1 || N > pb->Bmax || m < 1 || !(T > 0.0)) return FSI_ERR_ARG;
   if (pb->mixed || pb->p.dim != 2) return FSI_ERR_ARG;   // the adjoint runs in the 2d FP64 path
-  return adjoint_run(pb, T, N, m, U0, J_out, grad_out, stats, st);
+  return guarded([&] { return adjoint_run(pb, T, N, m, U0, J_out, grad_out, stats, st); });
 }
 
 fsi_status fsi_debug_residual(fsi_problem* pb, int32_t B, const double* U, const double* Uo, const double* t,
@@ -1776,12 +1810,12 @@ extern "C" {
 
 fsi_status fsi_debug_jacobian_apply(fsi_problem* pb, int32_t B, const double* U, const double* Uo, const double* t,
                                     double k, const double* X, double* Y, hipStream_t st) {
-  return debug_dispatch(pb, B, U, Uo, t, k, X, Y, 0, st);
+  return guarded([&] { return debug_dispatch(pb, B, U, Uo, t, k, X, Y, 0, st); });
 }
 
 fsi_status fsi_debug_vcycle(fsi_problem* pb, int32_t B, const double* U, const double* Uo, const double* t, double k,
                             const double* X, double* Y, hipStream_t st) {
-  return debug_dispatch(pb, B, U, Uo, t, k, X, Y, 1, st);
+  return guarded([&] { return debug_dispatch(pb, B, U, Uo, t, k, X, Y, 1, st); });
 }
 
 fsi_status fsi_profile_enable(fsi_problem* pb, int32_t on) {

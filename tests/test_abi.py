@@ -37,6 +37,19 @@ def test_every_declared_symbol_is_exported(lib):
         assert hasattr(lib, n), n
 
 
+def test_no_undeclared_c_symbol_is_exported(lib):
+    """The library's unmangled (C linkage) dynamic symbols are exactly the header's functions."""
+    import shutil
+    import subprocess
+    nm = shutil.which("nm")
+    if nm is None:
+        pytest.skip("nm not available")
+    out = subprocess.run([nm, "-D", "--defined-only", lib._name], capture_output=True, text=True, check=True).stdout
+    c_syms = {ln.split()[-1] for ln in out.splitlines()
+              if len(ln.split()) == 3 and ln.split()[1] == "T" and not ln.split()[-1].startswith("_")}
+    assert c_syms == set(declared_functions()), c_syms ^ set(declared_functions())
+
+
 def test_binding_matches_header():
     from paper_1907_01252_amd import fsi
     assert set(fsi.EXPORTS) == set(declared_functions())
