@@ -584,8 +584,7 @@ void smooth(fsi_problem* pb, int l, int B, double k, int sweeps, bool zero_first
       const int nc = color_info<D>(g, c, vc).nc;
       const double vec = 3.0 * g.nn * NC * sizeof(S);
       const double by = zero ? (double)B * ((double)NE * NE * nc * sizeof(S) + 2.0 * g.nn * NC * sizeof(S))
-                             : (double)B * ((double)NSLOT * jblk<D, CJ>() * g.nn * sizeof(S) + (double)NE * NE * nc * sizeof(S) +
-                                            vec) +
+                             : jbytes_launch<D, S, CJ>(g, B) + (double)B * ((double)NE * NE * nc * sizeof(S) + vec) +
                                    (double)NPST * g.nn * 8.0;
       ProfScope ps(pb, fine ? F_SMOOTH : F_COARSE_LEV, st, by);
       const int ncopy = (g.nn + NC * 64 - 1) / (NC * 64);
@@ -621,8 +620,7 @@ void vcycle(fsi_problem* pb, int B, double k, const S* rhs, S* out, const int* a
     smooth<D, S, CJ>(pb, l, B, k, l == L ? pb->p.vanka_sweeps : pb->p.vanka_sweeps_coarse, true, x, b, act, st);
     const Geom g = lv.geom();
     {
-      const double by = (double)B * ((double)NSLOT * jblk<D, CJ>() * g.nn * sizeof(S) + 3.0 * g.nn * NC * sizeof(S)) +
-                        (double)NPST * g.nn * 8.0;
+      const double by = jbytes_launch<D, S, CJ>(g, B) + (double)B * 3.0 * g.nn * NC * sizeof(S) + (double)NPST * g.nn * 8.0;
       ProfScope ps(pb, l == L ? F_LEVEL_RES : F_COARSE_LEV, st, by);
       spmv<D, S, CJ>(g, B, k, (const S*)lv.J, x, b, nullptr, (S*)lv.r_, act, st);
     }
@@ -738,8 +736,7 @@ fsi_status fgmres(fsi_problem* pb, int B, double k, std::vector<int>& kits, hipS
       S* a = tmp;
       {
         ProfScope ps(pb, F_GMRES_SPMV, st,
-                     (double)B * ((double)NSLOT * jblk<D, CJ>() * F.nn * sizeof(S) + 2.0 * n * sizeof(S) + n * 8.0) +
-                         (double)NPST * F.nn * 8.0);
+                     jbytes_launch<D, S, CJ>(g, B) + (double)B * (2.0 * n * sizeof(S) + n * 8.0) + (double)NPST * F.nn * 8.0);
         spmv<D, S, CJ>(g, B, k, (const S*)F.J, w, nullptr, F.Dsc, a, pb->gact, st);
       }
       // classical Gram-Schmidt, twice

@@ -212,6 +212,27 @@ template <int D, class S, bool CJ>
 __host__ __device__ constexpr int jent(int s, int e) {
   return (s * jblk<D, CJ>() + e) * jtx<D, S>();
 }
+// Offset of the slice whose Jacobian values row r of slice bs reads in the
+// SpMV and the fused Vanka pass.  The displacement rows of the step Jacobian
+// (harmonic extension, kinematic equation, Dirichlet identity) are linear in
+// (v, u) with coefficients fixed by the mesh, k and theta, so every slice of a
+// call assembles the same values (bit for bit) for them; in the compressed
+// layout all slices read them from slice 0, which every call assembles at its
+// first Newton iteration, and that one copy stays in cache.
+template <int D, class S, bool CJ>
+__host__ __device__ inline size_t jslice_row(const Geom& g, int bs, int r) {
+  return (CJ && r >= D && r < 2 * D) ? 0 : (size_t)bs * jslice<D, S, CJ>(g);
+}
+// stored entries of a block that all slices read from slice 0 (the displacement rows)
+template <int D, bool CJ>
+__host__ __device__ constexpr int jblk_shared() {
+  return CJ ? 2 * D : 0;
+}
+// Jacobian bytes one SpMV or fused-pass launch over B slices reads from memory
+template <int D, class S, bool CJ>
+inline double jbytes_launch(const Geom& g, int B) {
+  return ((double)B * (jblk<D, CJ>() - jblk_shared<D, CJ>()) + jblk_shared<D, CJ>()) * Dm<D>::NSLOT * g.nn * sizeof(S);
+}
 // position of node n (in copy sh of the row tiles)
 template <int D, class S, bool CJ>
 __host__ __device__ inline size_t jnode_n(const Geom& g, int n, int sh) {

@@ -46,7 +46,7 @@ __global__ void __launch_bounds__(Dm<D>::NC * 64) k_spmv(Geom g, double k, const
   }
   if (active && !active[bs]) return;
   const int j = row % (g.ny + 1), kk = row / (g.ny + 1);
-  const S* jn = J + (size_t)bs * jslice<D, S, CJ>(g) + jnode<D, S, CJ>(g, i, row, 0);
+  const S* jn = J + jslice_row<D, S, CJ>(g, bs, r) + jnode<D, S, CJ>(g, i, row, 0);
   const S* xb = x + (size_t)bs * g.nn * NC;
   S acc = stencil_row<D, S, CJ>(jn, xb, n, r, nbr_offsets<D>(g, i, j, kk));
   if (r == PC) acc += pst_row<D, S>(g, k, n, i, j, kk, xb);

@@ -120,7 +120,7 @@ __global__ void __launch_bounds__(Dm<D>::NC * 64, (vanka_waves_per_simd<D, S>())
         int i, j, kk;
         node_ijk<D>(g, n, i, j, kk);
         // (3d: the copy whose tiles start where this colour's node runs start)
-        const S* jn = J + (size_t)bs * jslice<D, S, CJ>(g) + jnode<D, S, CJ>(g, i, j + (g.ny + 1) * kk, cx);
+        const S* jn = J + jslice_row<D, S, CJ>(g, bs, r) + jnode<D, S, CJ>(g, i, j + (g.ny + 1) * kk, cx);
         constexpr int NROW = D == 3 ? 25 : 5;
         const int part = r - D, p0 = part * NROW / D, p1 = (part + 1) * NROW / D;
         if (stage) {
