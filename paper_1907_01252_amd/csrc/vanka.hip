@@ -1,8 +1,10 @@
 // The fused colored multiplicative Vanka pass: patch residuals from the block
 // stencil and the patch update in one kernel (the patch inverses it applies
-// are formed in vanka_factor.hip).  Every kernel takes the slice index from
-// blockIdx.y and skips slices whose active flag is 0; S is the storage type of
-// the linear solve, D the space dimension, CJ the Jacobian block layout.
+// are formed in vanka_factor.hip).  The kernel takes the slice index from
+// blockIdx.y (blockIdx.x when slice_fast is set, the slices then being the
+// fast grid dimension) and skips slices whose active flag is 0; S is the
+// storage type of the linear solve, D the space dimension, CJ the Jacobian
+// block layout.
 #include "stencil.h"
 
 namespace fsi {
@@ -38,7 +40,8 @@ __global__ void __launch_bounds__(Dm<D>::NC * 64, (vanka_waves_per_simd<D, S>())
     k_vanka_color(Geom g, double k, int color, S omega, int zero_in,
                                                                 const S* __restrict__ J, const S* __restrict__ Ainv,
                                                                 const S* __restrict__ b, const S* __restrict__ xo,
-                                                                S* __restrict__ xn, const int* __restrict__ active) {
+                                                                S* __restrict__ xn, const int* __restrict__ active,
+                                                                int slice_fast) {
   FSI_DIM(D);
   static_assert(VC == 8 || VC == 16 || VC == 32, "cells per block");
   // the pressure-stabilisation row of a node is spread over the D
@@ -53,7 +56,8 @@ __global__ void __launch_bounds__(Dm<D>::NC * 64, (vanka_waves_per_simd<D, S>())
   constexpr int RX2 = 2 * VC + 4, RY2 = 6, RZ2 = D == 3 ? 6 : 1;
   __shared__ S xr[RX1 * RY1 * RZ1 * NC];
   __shared__ S pr[RX2 * RY2 * RZ2];
-  const int bs = blockIdx.y;
+  const int bs = slice_fast ? blockIdx.x : blockIdx.y;
+  const int bx = slice_fast ? blockIdx.y : blockIdx.x;
   if (active && !active[bs]) return;   // uniform over the block
   const ColorInfo L = color_info<D>(g, color, VC);
   const int nc = L.nc;
@@ -61,8 +65,8 @@ __global__ void __launch_bounds__(Dm<D>::NC * 64, (vanka_waves_per_simd<D, S>())
   const S* xob = xo + (size_t)bs * g.nn * NC;
   S* xnb = xn + (size_t)bs * g.nn * NC;
   const int cx = color & 1, cy = (color >> 1) & 1, cz = (color >> 2) & 1;
-  if ((int)blockIdx.x >= npb) {
-    const int t = ((int)blockIdx.x - npb) * (NC * 64) + threadIdx.x;
+  if (bx >= npb) {
+    const int t = (bx - npb) * (NC * 64) + threadIdx.x;
     if (t >= g.nn) return;
     int ni, nj, nk;
     node_ijk<D>(g, t, ni, nj, nk);
@@ -79,7 +83,7 @@ __global__ void __launch_bounds__(Dm<D>::NC * 64, (vanka_waves_per_simd<D, S>())
   constexpr int G = 64 / (2 * VC), NQ = NL / (2 * G), QS = 2 * G;
   const int jc = (lane % (2 * VC)) >> 1;
   const int a0 = (lane & 1) + 2 * (lane / (2 * VC));
-  const int idx = blockIdx.x * VC + jc;
+  const int idx = bx * VC + jc;
   const bool live = idx < nc;
   // The block's cells lie in one cell row when the colour's rows hold whole
   // blocks: then the x values its stencils read are staged in LDS once
@@ -87,7 +91,7 @@ __global__ void __launch_bounds__(Dm<D>::NC * 64, (vanka_waves_per_simd<D, S>())
   const bool stage = !zero_in && L.ncx % VC == 0;
   int X1 = 0, Y1 = 0, Z1 = 0;
   if (stage) {
-    const int idx0 = blockIdx.x * VC, rest0 = idx0 / L.ncx;
+    const int idx0 = bx * VC, rest0 = idx0 / L.ncx;
     X1 = 2 * (idx0 % L.ncx) + cx - 1;
     Y1 = 2 * (rest0 % L.ncy) + cy - 1;
     Z1 = D == 3 ? 2 * (rest0 / L.ncy) + cz - 1 : 0;
@@ -154,7 +158,7 @@ __global__ void __launch_bounds__(Dm<D>::NC * 64, (vanka_waves_per_simd<D, S>())
   }
   if (!live) return;
   const S* ai =
-      Ainv + (size_t)bs * ainv_slice<D>(g.ncell) + ((size_t)L.off + (size_t)blockIdx.x * VC) * NE * NE + jc;
+      Ainv + (size_t)bs * ainv_slice<D>(g.ncell) + ((size_t)L.off + (size_t)bx * VC) * NE * NE + jc;
 #pragma unroll 1
   for (int q = 0; q < NQ; ++q) {
     const int a = a0 + q * QS;
@@ -172,19 +176,19 @@ __global__ void __launch_bounds__(Dm<D>::NC * 64, (vanka_waves_per_simd<D, S>())
 #define FSI_INST_VANKA(D, S)                                                                                      \
   template __global__ void k_vanka_color<D, S, (D == 2 ? 16 : 32), true>(Geom, double, int, S, int, const S*,   \
                                                                          const S*, const S*, const S*, S*,      \
-                                                                         const int*);
+                                                                         const int*, int);
 FSI_INST_VANKA(2, double)
 FSI_INST_VANKA(2, float)
 FSI_INST_VANKA(3, double)
 FSI_INST_VANKA(3, float)
 template __global__ void k_vanka_color<3, double, 8, true>(Geom, double, int, double, int, const double*,
                                                            const double*, const double*, const double*, double*,
-                                                           const int*);
+                                                           const int*, int);
 template __global__ void k_vanka_color<3, float, 8, true>(Geom, double, int, float, int, const float*, const float*,
-                                                          const float*, const float*, float*, const int*);
+                                                          const float*, const float*, float*, const int*, int);
 // full-layout operators of the (2d, FP64) transposed adjoint system
 template __global__ void k_vanka_color<2, double, 16, false>(Geom, double, int, double, int, const double*,
                                                              const double*, const double*, const double*, double*,
-                                                             const int*);
+                                                             const int*, int);
 
 }  // namespace fsi
