@@ -219,3 +219,32 @@ def test_solid_stress_is_strain_energy_gradient():
         w = rng.normal(size=(m.n_nodes, 2))
         dpsi = energy(U[:, 2:4] + 1e-30j * w).imag / 1e-30
         assert abs(np.sum(R[:, 0:2] * w) - k * dpsi) <= 1e-12 * abs(k * dpsi)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_displacement_rows_do_not_depend_on_the_state(dim):
+    """The displacement rows of the step Jacobian (harmonic extension, kinematic
+    equation, Dirichlet identity) are linear in (v, u) with coefficients fixed by
+    the mesh, k and theta: two unrelated states give the same rows, and the rows
+    touch only v_i and u_i of their own component i.  The GPU path stores these
+    rows once for all slices of a call and relies on exactly this."""
+    if dim == 2:
+        p = synth.workload("c1")
+    else:
+        p = synth.workload("c5", level=0)
+    D = Discretization(p)
+    nc = 2 * dim + 1
+    k = p["k_fine"]
+    A1 = D.jacobian(synth.random_state(p, 31), synth.random_state(p, 32), 0.05, k).tocsr()
+    A2 = D.jacobian(synth.random_state(p, 33), synth.random_state(p, 34), 0.11, k).tocsr()
+    n = A1.shape[0]
+    rows = np.array([r for r in range(n) if dim <= r % nc < 2 * dim])
+    R1, R2 = A1[rows], A2[rows]
+    diff = abs(R1 - R2).max()
+    assert diff <= 1e-14 * abs(R1).max(), diff
+    # structure: row of component i (u_i) couples only to v_i and u_i
+    R1 = R1.tocoo()
+    comp_row = (rows[R1.row] % nc) - dim
+    comp_col = R1.col % nc
+    nz = R1.data != 0
+    assert np.all((comp_col[nz] == comp_row[nz]) | (comp_col[nz] == comp_row[nz] + dim))
