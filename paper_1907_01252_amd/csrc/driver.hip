@@ -560,7 +560,9 @@ void spmv(const Geom& g, int B, double k, const S* J, const S* x, const S* b, co
           hipStream_t st) {
   const int nb =
       !jrowtiles<D, S>() ? (g.nn + 63) / 64 : (jntx<D, S>(g, 0) * jrows<D>(g) * jtx<D, S>() + 63) / 64;
-  k_spmv<D, S, CJ><<<dim3(nb, B), spmv_threads<D>(), 0, st>>>(g, k, J, x, b, Dv, y, act);
+  // slices as the fast grid dimension in 2d FP64 (c2 SpMV 4% faster; the 3d one was 8% slower)
+  const int sf = (D == 2 && sizeof(S) == 8) && nb <= 65535 ? 1 : 0;
+  k_spmv<D, S, CJ><<<sf ? dim3(B, nb) : dim3(nb, B), spmv_threads<D>(), 0, st>>>(g, k, J, x, b, Dv, y, act, sf);
 }
 
 // ------------------------------------------------------------ multigrid

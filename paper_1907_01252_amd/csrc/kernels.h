@@ -44,7 +44,7 @@ __global__ void k_daxpy(size_t n, double a, const double* x, double* y);
 
 template <int D, class S, bool CJ>
 __global__ void k_spmv(Geom g, double k, const S* J, const S* x, const S* b, const double* Dsc, S* y,
-                       const int* active);
+                       const int* active, int slice_fast);
 template <int D, class S, bool CJ>
 __global__ void k_vanka_factor(Geom g, double k, const S* J, S* Ainv, int vc, const int* active);
 template <int D, class S, int VC, bool CJ>

@@ -20,25 +20,28 @@ using D2 = Dm<2>;
 // One thread per (node, row): a block of NC waves takes 64 lanes of nodes of
 // the Jacobian storage (one tile in 2d, two tiles of copy 0 in 3d), wave r
 // forming row r, so the rows of a node read its neighbours' x through the same
-// CU's cache, and a wave streams whole runs of each coefficient.
+// CU's cache, and a wave streams whole runs of each coefficient.  The slice is
+// blockIdx.y, or blockIdx.x when slice_fast is set (slices as the fast grid
+// dimension, so the blocks of one tile in all slices run together).
 template <int D, class S, bool CJ>
 __global__ void __launch_bounds__(Dm<D>::NC * 64) k_spmv(Geom g, double k, const S* __restrict__ J,
                                                          const S* __restrict__ x, const S* __restrict__ b,
                                                          const double* __restrict__ Dsc, S* __restrict__ y,
-                                                         const int* __restrict__ active) {
+                                                         const int* __restrict__ active, int slice_fast) {
   FSI_DIM(D);
-  const int bs = blockIdx.y;
+  const int bs = slice_fast ? blockIdx.x : blockIdx.y;
+  const int bx = slice_fast ? blockIdx.y : blockIdx.x;
   const int r = threadIdx.x >> 6, lane = threadIdx.x & 63;
   int n, i, row;
   if (!jrowtiles<D, S>()) {
-    n = blockIdx.x * 64 + lane;
+    n = bx * 64 + lane;
     row = n / (g.nx + 1);
     i = n - row * (g.nx + 1);
     if (n >= g.nn) return;
   } else {
     constexpr int TX = jtx<D, S>();
     const int ntx = jntx<D, S>(g, 0);
-    const int t = blockIdx.x * (64 / TX) + lane / TX;
+    const int t = bx * (64 / TX) + lane / TX;
     row = t / ntx;
     i = (t - row * ntx) * TX + lane % TX;
     if (row >= jrows<D>(g) || i > g.nx) return;
@@ -800,7 +803,7 @@ __global__ void k_convert(size_t n, const A* __restrict__ X, B2* __restrict__ Y)
 // explicit instantiations
 #define FSI_INST_DS(D, S)                                                                                         \
   template __global__ void k_spmv<D, S, true>(Geom, double, const S*, const S*, const S*, const double*, S*,     \
-                                              const int*);                                                       \
+                                              const int*, int);                                                  \
   template __global__ void k_restrict<D, S>(Geom, Geom, const S*, S*, const int*);                               \
   template __global__ void k_prolong_add<D, S>(Geom, Geom, const S*, S*, const int*);                            \
   template __global__ void k_newton_update<D, S>(int, double*, const S*, int, double*, int, const int*);
@@ -824,7 +827,7 @@ FSI_INST_S(double)
 FSI_INST_S(float)
 // full-layout operators of the (2d, FP64) transposed adjoint system
 template __global__ void k_spmv<2, double, false>(Geom, double, const double*, const double*, const double*,
-                                                  const double*, double*, const int*);
+                                                  const double*, double*, const int*, int);
 template __global__ void k_coarse_factor<double, false>(Geom, double, const double*, int, int, double*, double*,
                                                         double*, const int*);
 template __global__ void k_change_norms<2>(int, const double*, const double*, int, double*, int);
