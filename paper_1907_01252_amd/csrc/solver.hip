@@ -1,10 +1,11 @@
 // Batched linear-solver kernels: block-stencil SpMV, transposed products of the
 // adjoint, multigrid transfers, the coarsest-level block-tridiagonal direct
 // solve (2d) and the FGMRES building blocks (the Vanka kernels are in
-// vanka.hip).  Every
-// kernel takes the slice index from blockIdx.y and skips slices whose active
-// flag is 0.  S is the storage and arithmetic type of the linear solve
-// (double, or float in the mixed-precision path); D the space dimension.
+// vanka.hip and vanka_factor.hip).  Every kernel takes the slice index from
+// blockIdx.y (the SpMV from blockIdx.x when its slices are the fast grid
+// dimension) and skips slices whose active flag is 0.  S is the storage and
+// arithmetic type of the linear solve (double, or float in the mixed-precision
+// path); D the space dimension.
 #include "stencil.h"
 #include "kernels.h"
 
