@@ -52,7 +52,7 @@ struct Level {
   uint8_t *d_solid = nullptr, *d_cls = nullptr, *d_dmask = nullptr;
   // batch workspace
   double *U = nullptr, *Uo = nullptr, *Dsc = nullptr;
-  void *J = nullptr, *Ainv = nullptr, *x_ = nullptr, *b_ = nullptr, *r_ = nullptr, *t_ = nullptr;
+  void *J = nullptr, *Ainv = nullptr, *Yu = nullptr, *x_ = nullptr, *b_ = nullptr, *r_ = nullptr, *t_ = nullptr;
   Geom geom() const {
     Geom g;
     g.nx = nx; g.ny = ny; g.nz = nz; g.nn = nn; g.ncell = ncell;
@@ -425,7 +425,10 @@ fsi_status build_level(fsi_problem* pb, int l) {
   const size_t jvals = std::max(jslice<D, double, false>(L.geom()), jslice<D, float, false>(L.geom()));
   CHK(dalloc_bytes(pb, &L.J, (size_t)B * jvals * ss));
   // Vanka inverses: every smoothed level (in 3d level 0 is smoothed too)
-  if (l >= 1 || D == 3) CHK(dalloc_bytes(pb, &L.Ainv, (size_t)B * ainv_slice<D>(L.ncell) * ss));
+  if (l >= 1 || D == 3) {
+    CHK(dalloc_bytes(pb, &L.Ainv, (size_t)B * ainv_slice<D>(L.ncell) * ss));
+    CHK(dalloc_bytes(pb, &L.Yu, yu_level<D>(L.ncell) * ss));   // shared by the slices
+  }
   CHK(dalloc_bytes(pb, &L.x_, (size_t)B * L.nn * NC * ss));
   CHK(dalloc_bytes(pb, &L.b_, (size_t)B * L.nn * NC * ss));
   CHK(dalloc_bytes(pb, &L.r_, (size_t)B * L.nn * NC * ss));
@@ -540,7 +543,7 @@ fsi_status assemble_levels(fsi_problem* pb, int B, const StepPar& sp, const int*
     if (l >= 1 || D == 3) {
       k_vanka_factor<D, S, CJ><<<dim3((g.ncell + vf_patches<D>() - 1) / vf_patches<D>(), B),
                                  vf_lanes<D>() * vf_patches<D>(), 0, st>>>(g, sp.k, (const S*)lv.J, (S*)lv.Ainv,
-                                                                          vanka_vc<D>(g, B), act);
+                                                                          (S*)lv.Yu, vanka_vc<D>(g, B), act);
     } else {
       const size_t lds_f = (size_t)5 * pb->cbs * pb->cbs * sizeof(double);
       const size_t lds_i = (size_t)3 * pb->cbs * pb->cbs * sizeof(double);
@@ -585,12 +588,15 @@ void smooth(fsi_problem* pb, int l, int B, double k, int sweeps, bool zero_first
       const int vc = vanka_vc<D>(g, B);
       const int nc = color_info<D>(g, c, vc).nc;
       const double vec = 3.0 * g.nn * NC * sizeof(S);
-      const double by = zero ? (double)B * ((double)NE * NE * nc * sizeof(S) + 2.0 * g.nn * NC * sizeof(S))
-                             : jbytes_launch<D, S, CJ>(g, B) + (double)B * ((double)NE * NE * nc * sizeof(S) + vec) +
-                                   (double)NPST * g.nn * 8.0;
+      // inverse rows per slice; in the split patch solve Y1, Y2 once per launch
+      constexpr bool SP = patch_split<S, CJ>();
+      const double inv = (double)ainv_rows<D, SP>() * NE * nc * sizeof(S);
+      const double ysh = SP ? (double)yu_cell<D>() * nc * sizeof(S) : 0.0;
+      const double by = zero ? (double)B * (inv + 2.0 * g.nn * NC * sizeof(S)) + ysh
+                             : jbytes_launch<D, S, CJ>(g, B) + (double)B * (inv + vec) + ysh + (double)NPST * g.nn * 8.0;
       ProfScope ps(pb, fine ? F_SMOOTH : F_COARSE_LEV, st, by);
       const int ncopy = (g.nn + NC * 64 - 1) / (NC * 64);
-      const S *J = (const S*)lv.J, *Ai = (const S*)lv.Ainv;
+      const S *J = (const S*)lv.J, *Ai = (const S*)lv.Ainv, *Yu = (const S*)lv.Yu;
       // blocks of the colour (vc cells each) and of the copy of the other nodes, per slice.
       // Slices as the fast grid dimension: the blocks of one tile in all slices are dispatched
       // together, so the values every slice shares (displacement rows of slice 0, the
@@ -600,13 +606,13 @@ void smooth(fsi_problem* pb, int l, int B, double k, int sweeps, bool zero_first
       const int sf = (D == 3 || sizeof(S) == 8) && nbx <= 65535 ? 1 : 0;
       const dim3 grid = sf ? dim3(B, nbx) : dim3(nbx, B);
       if constexpr (D == 2) {
-        k_vanka_color<D, S, 16, CJ><<<grid, NC * 64, 0, st>>>(g, k, c, om, zero ? 1 : 0, J, Ai, b, buf[cur],
+        k_vanka_color<D, S, 16, CJ><<<grid, NC * 64, 0, st>>>(g, k, c, om, zero ? 1 : 0, J, Ai, Yu, b, buf[cur],
                                                               buf[cur ^ 1], act, sf);
       } else if (vc == 32) {
-        k_vanka_color<D, S, 32, CJ><<<grid, NC * 64, 0, st>>>(g, k, c, om, zero ? 1 : 0, J, Ai, b, buf[cur],
+        k_vanka_color<D, S, 32, CJ><<<grid, NC * 64, 0, st>>>(g, k, c, om, zero ? 1 : 0, J, Ai, Yu, b, buf[cur],
                                                               buf[cur ^ 1], act, sf);
       } else {
-        k_vanka_color<D, S, 8, CJ><<<grid, NC * 64, 0, st>>>(g, k, c, om, zero ? 1 : 0, J, Ai, b, buf[cur],
+        k_vanka_color<D, S, 8, CJ><<<grid, NC * 64, 0, st>>>(g, k, c, om, zero ? 1 : 0, J, Ai, Yu, b, buf[cur],
                                                              buf[cur ^ 1], act, sf);
       }
       cur ^= 1;

@@ -299,6 +299,38 @@ template <int D>
 __host__ __device__ inline size_t ainv_slice(int ncell) {
   return ((size_t)ncell + (size_t)Dm<D>::NCOL * VC_MAX) * Dm<D>::NE * Dm<D>::NE;
 }
+// Patch solves with the compressed Jacobian (CJ) split the patch unknowns into
+// the displacements u (D NL of them) and the rest w = (v, p) (NW).  The patch
+// matrix's displacement rows touch only v_i and u_i of their own component i
+// and do not depend on the state, so with Y1_i = A_uu,i^{-1} and
+// Y2_i = Y1_i A_uv,i (NL x NL per component, the same in every slice) the
+// patch update is delta_w = (A^{-1} r)_w from the NW rows of the inverse that
+// belong to w (stored per slice), then delta_u,i = Y1_i r_u,i - Y2_i delta_v,i.
+// Rows of the full layout (the transposed adjoint system) are all stored.
+// the split patch solve is used with the compressed layout in FP64 (in FP32 the
+// 3d c5-level-1 mixed step no longer converged with it)
+template <class S, bool CJ>
+__host__ __device__ constexpr bool patch_split() {
+  return CJ && sizeof(S) == 8;
+}
+template <int D, bool CJ>
+__host__ __device__ constexpr int ainv_rows() {
+  return CJ ? (D + 1) * Dm<D>::NL : Dm<D>::NE;
+}
+// stored row of local unknown NC a + c (c not a displacement in CJ)
+template <int D, bool CJ>
+__host__ __device__ constexpr int ainv_row(int a, int c) {
+  return CJ ? (D + 1) * a + (c < D ? c : D) : Dm<D>::NC * a + c;
+}
+// values of Y1 and Y2 per cell, and per level (slot layout as the inverses)
+template <int D>
+__host__ __device__ constexpr int yu_cell() {
+  return 2 * D * Dm<D>::NL * Dm<D>::NL;
+}
+template <int D>
+__host__ __device__ inline size_t yu_level(int ncell) {
+  return ((size_t)ncell + (size_t)Dm<D>::NCOL * VC_MAX) * yu_cell<D>();
+}
 
 // A bar face shared with a fluid cell (2d): fluid cell index, face axis (0: x,
 // 1: y), side of the face in the fluid cell (0: low, 1: high) and the sign of

@@ -46,10 +46,10 @@ template <int D, class S, bool CJ>
 __global__ void k_spmv(Geom g, double k, const S* J, const S* x, const S* b, const double* Dsc, S* y,
                        const int* active, int slice_fast);
 template <int D, class S, bool CJ>
-__global__ void k_vanka_factor(Geom g, double k, const S* J, S* Ainv, int vc, const int* active);
+__global__ void k_vanka_factor(Geom g, double k, const S* J, S* Ainv, S* Yu, int vc, const int* active);
 template <int D, class S, int VC, bool CJ>
 __global__ void k_vanka_color(Geom g, double k, int color, S omega, int zero_in, const S* J, const S* Ainv,
-                              const S* b, const S* xo, S* xn, const int* active, int slice_fast);
+                              const S* Yu, const S* b, const S* xo, S* xn, const int* active, int slice_fast);
 template <int D, class S>
 __global__ void k_restrict(Geom gc, Geom gf, const S* rf, S* bc, const int* active);
 template <int D, class S>

@@ -39,6 +39,7 @@ template <int D, class S, int VC, bool CJ>
 __global__ void __launch_bounds__(Dm<D>::NC * 64, (vanka_waves_per_simd<D, S>()))
     k_vanka_color(Geom g, double k, int color, S omega, int zero_in,
                                                                 const S* __restrict__ J, const S* __restrict__ Ainv,
+                                                                const S* __restrict__ Yu,
                                                                 const S* __restrict__ b, const S* __restrict__ xo,
                                                                 S* __restrict__ xn, const int* __restrict__ active,
                                                                 int slice_fast) {
@@ -56,6 +57,8 @@ __global__ void __launch_bounds__(Dm<D>::NC * 64, (vanka_waves_per_simd<D, S>())
   constexpr int RX2 = 2 * VC + 4, RY2 = 6, RZ2 = D == 3 ? 6 : 1;
   __shared__ S xr[RX1 * RY1 * RZ1 * NC];
   __shared__ S pr[RX2 * RY2 * RZ2];
+  constexpr bool SP = patch_split<S, CJ>();   // split patch solve (see ainv_rows)
+  __shared__ S dv[SP ? NL * D : 1][VC];        // velocity part of the patch update
   const int bs = slice_fast ? blockIdx.x : blockIdx.y;
   const int bx = slice_fast ? blockIdx.y : blockIdx.x;
   if (active && !active[bs]) return;   // uniform over the block
@@ -156,39 +159,65 @@ __global__ void __launch_bounds__(Dm<D>::NC * 64, (vanka_waves_per_simd<D, S>())
     }
     __syncthreads();
   }
-  if (!live) return;
-  const S* ai =
-      Ainv + (size_t)bs * ainv_slice<D>(g.ncell) + ((size_t)L.off + (size_t)bx * VC) * NE * NE + jc;
+  // patch update: rows of the stored inverse first (in the split solve the
+  // non-displacement unknowns), then the displacements from Y1, Y2 and the
+  // velocity update
+  const bool urow = SP && r >= D && r < 2 * D;
+  constexpr int NR = ainv_rows<D, SP>();
+  if (live && !urow) {
+    const S* ai = Ainv + (size_t)bs * ainv_slice<D>(g.ncell) + ((size_t)L.off + (size_t)bx * VC) * NR * NE + jc;
 #pragma unroll 1
-  for (int q = 0; q < NQ; ++q) {
-    const int a = a0 + q * QS;
-    const int row = NC * a + r;
-    S z = 0;
-    constexpr int EU = NQ == 1 ? NE : 8;   // looping threads: bounded loads in flight (registers)
+    for (int q = 0; q < NQ; ++q) {
+      const int a = a0 + q * QS;
+      const int wr = ainv_row<D, SP>(a, r);
+      S z = 0;
+      constexpr int EU = NQ == 1 ? NE : 8;   // looping threads: bounded loads in flight (registers)
 #pragma unroll EU
-    for (int e = 0; e < NE; ++e) z += ai[(NE * row + e) * VC] * rs[e][jc];
-    const int n = node_at(g, ci + (a & 1), cj + ((a >> 1) & 1), ck + ((a >> 2) & 1));
-    const size_t o = (size_t)n * NC + r;
-    xnb[o] = (zero_in ? (S)0 : xob[o]) + omega * z;
+      for (int e = 0; e < NE; ++e) z += ai[(NE * wr + e) * VC] * rs[e][jc];
+      if (SP && r < D) dv[D * a + r][jc] = z;
+      const int n = node_at(g, ci + (a & 1), cj + ((a >> 1) & 1), ck + ((a >> 2) & 1));
+      const size_t o = (size_t)n * NC + r;
+      xnb[o] = (zero_in ? (S)0 : xob[o]) + omega * z;
+    }
+  }
+  if constexpr (SP) {
+    __syncthreads();   // every thread of the block: dv is complete
+    if (live && urow) {
+      const int i = r - D;
+      const S* y1 = Yu + ((size_t)L.off + (size_t)bx * VC) * yu_cell<D>() + jc + (size_t)(2 * i) * NL * NL * VC;
+      const S* y2 = y1 + (size_t)NL * NL * VC;
+#pragma unroll 1
+      for (int q = 0; q < NQ; ++q) {
+        const int a = a0 + q * QS;
+        S z = 0;
+#pragma unroll
+        for (int bb = 0; bb < NL; ++bb)
+          z += y1[(NL * a + bb) * VC] * rs[NC * bb + r][jc] - y2[(NL * a + bb) * VC] * dv[D * bb + i][jc];
+        const int n = node_at(g, ci + (a & 1), cj + ((a >> 1) & 1), ck + ((a >> 2) & 1));
+        const size_t o = (size_t)n * NC + r;
+        xnb[o] = (zero_in ? (S)0 : xob[o]) + omega * z;
+      }
+    }
   }
 }
 
 #define FSI_INST_VANKA(D, S)                                                                                      \
   template __global__ void k_vanka_color<D, S, (D == 2 ? 16 : 32), true>(Geom, double, int, S, int, const S*,   \
-                                                                         const S*, const S*, const S*, S*,      \
-                                                                         const int*, int);
+                                                                         const S*, const S*, const S*, const S*,  \
+                                                                         S*, const int*, int);
 FSI_INST_VANKA(2, double)
 FSI_INST_VANKA(2, float)
 FSI_INST_VANKA(3, double)
 FSI_INST_VANKA(3, float)
 template __global__ void k_vanka_color<3, double, 8, true>(Geom, double, int, double, int, const double*,
-                                                           const double*, const double*, const double*, double*,
-                                                           const int*, int);
+                                                           const double*, const double*, const double*,
+                                                           const double*, double*, const int*, int);
 template __global__ void k_vanka_color<3, float, 8, true>(Geom, double, int, float, int, const float*, const float*,
-                                                          const float*, const float*, float*, const int*, int);
+                                                          const float*, const float*, const float*, float*,
+                                                          const int*, int);
 // full-layout operators of the (2d, FP64) transposed adjoint system
 template __global__ void k_vanka_color<2, double, 16, false>(Geom, double, int, double, int, const double*,
-                                                             const double*, const double*, const double*, double*,
-                                                             const int*, int);
+                                                             const double*, const double*, const double*,
+                                                             const double*, double*, const int*, int);
 
 }  // namespace fsi

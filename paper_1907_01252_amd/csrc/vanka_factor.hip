@@ -21,12 +21,16 @@ namespace fsi {
 template <int D, class S, bool CJ>
 __global__ void __launch_bounds__(vf_lanes<D>() * vf_patches<D>()) k_vanka_factor(Geom g, double k,
                                                                                   const S* __restrict__ J,
-                                                                                  S* __restrict__ Ainv, int vc,
+                                                                                  S* __restrict__ Ainv,
+                                                                                  S* __restrict__ Yu, int vc,
                                                                                   const int* __restrict__ active) {
   FSI_DIM(D);
   constexpr int GL = vf_lanes<D>(), NP = vf_patches<D>();
   __shared__ double Q[2][NP][NE];   // published pivot row, one buffer per step parity
   __shared__ int colmap[NP][NE];    // pivot row of each column
+  // [A_uu,i | A_uv,i | I] of every displacement component i (slice 0 only)
+  constexpr bool SP = patch_split<S, CJ>();
+  __shared__ double Mu[SP ? NP : 1][SP ? D : 1][SP ? NL : 1][SP ? 3 * NL : 1];
   const int bs = blockIdx.y;
   if (active && !active[bs]) return;   // uniform over the block
   const int grp = threadIdx.x / GL, lane = threadIdx.x % GL;
@@ -53,6 +57,59 @@ __global__ void __launch_bounds__(vf_lanes<D>() * vf_patches<D>()) k_vanka_facto
         row[NC * bb + c] = e >= 0 ? (double)jn[jent<D, S, CJ>(s, e)] : 0.0;
       }
       if (pst_row) row[NC * bb + PC] += k * g.pst[(size_t)pslot_of<D>(dx, dy, dz) * g.nn + na];
+    }
+  }
+  if constexpr (SP) {
+    // Y1_i = A_uu,i^{-1} and Y2_i = Y1_i A_uv,i of the patch, the same in every
+    // slice: slice 0 writes them (block-uniform branch)
+    if (bs == 0) {
+      const int rc = lane % NC, a = lane / NC;
+      if (lane < NE && rc >= D && rc < 2 * D) {
+        const int i = rc - D;
+#pragma unroll
+        for (int c = 0; c < NE; ++c) {
+          const int cb = c / NC, cc = c % NC;
+          if (cc == D + i) Mu[grp][i][a][cb] = row[c];
+          else if (cc == i) Mu[grp][i][a][NL + cb] = row[c];
+        }
+        for (int b = 0; b < NL; ++b) Mu[grp][i][a][2 * NL + b] = a == b ? 1.0 : 0.0;
+      }
+      __syncthreads();
+      if (lane < D) {
+        // Gauss-Jordan with partial pivoting on the NL x 3 NL system of component lane
+        double(*m)[3 * NL] = Mu[grp][lane];
+        for (int pc = 0; pc < NL; ++pc) {
+          int pr = pc;
+          for (int rr = pc + 1; rr < NL; ++rr)
+            if (fabs(m[rr][pc]) > fabs(m[pr][pc])) pr = rr;
+          if (pr != pc)
+            for (int c = 0; c < 3 * NL; ++c) {
+              const double t = m[pc][c];
+              m[pc][c] = m[pr][c];
+              m[pr][c] = t;
+            }
+          const double inv = m[pc][pc] == 0.0 ? 1.0 : 1.0 / m[pc][pc];
+          for (int c = 0; c < 3 * NL; ++c) m[pc][c] *= inv;
+          for (int rr = 0; rr < NL; ++rr) {
+            if (rr == pc) continue;
+            const double f = m[rr][pc];
+            if (f != 0.0)
+              for (int c = 0; c < 3 * NL; ++c) m[rr][c] -= f * m[pc][c];
+          }
+        }
+        if (live) {
+          int col, idx;
+          ColorInfo L;
+          cell_colour<D>(g, ci, cj, ck, vc, col, idx, L);
+          const int q = idx / vc, t = idx - q * vc;
+          S* y = Yu + ((size_t)L.off + (size_t)q * vc) * yu_cell<D>() + t;
+          for (int a2 = 0; a2 < NL; ++a2)
+            for (int b = 0; b < NL; ++b) {
+              y[(size_t)((2 * lane) * NL * NL + a2 * NL + b) * vc] = (S)m[a2][2 * NL + b];       // Y1
+              y[(size_t)((2 * lane + 1) * NL * NL + a2 * NL + b) * vc] = (S)m[a2][NL + b];      // Y2
+            }
+        }
+      }
     }
   }
   bool used = lane >= NE;
@@ -86,22 +143,26 @@ __global__ void __launch_bounds__(vf_lanes<D>() * vf_patches<D>()) k_vanka_facto
     for (int c = 0; c + 1 < NE; ++c) row[c] = fma(-v, q[c], row[c + 1]);
     row[NE - 1] = -v * q[NE - 1];
   }
-  if (live && lane < NE) {
+  const int mrc = mycol % NC;
+  if (live && lane < NE && !(SP && mrc >= D && mrc < 2 * D)) {
     // row mycol of the inverse: entry (mycol, pivot row of j) is held in entry j
+    // (in the split patch solve only the rows of the non-displacement unknowns are stored)
     int col, idx;
     ColorInfo L;
     cell_colour<D>(g, ci, cj, ck, vc, col, idx, L);
     const int q = idx / vc, t = idx - q * vc;
-    S* out = Ainv + (size_t)bs * ainv_slice<D>(g.ncell) + ((size_t)L.off + (size_t)q * vc) * NE * NE + t;
+    constexpr int NR = ainv_rows<D, SP>();
+    const int wr = ainv_row<D, SP>(mycol / NC, mrc);
+    S* out = Ainv + (size_t)bs * ainv_slice<D>(g.ncell) + ((size_t)L.off + (size_t)q * vc) * NR * NE + t;
 #pragma unroll
-    for (int j = 0; j < NE; ++j) out[(size_t)(NE * mycol + colmap[grp][j]) * vc] = (S)row[j];
+    for (int j = 0; j < NE; ++j) out[(size_t)(NE * wr + colmap[grp][j]) * vc] = (S)row[j];
   }
 }
 
-template __global__ void k_vanka_factor<2, double, true>(Geom, double, const double*, double*, int, const int*);
-template __global__ void k_vanka_factor<2, float, true>(Geom, double, const float*, float*, int, const int*);
-template __global__ void k_vanka_factor<3, double, true>(Geom, double, const double*, double*, int, const int*);
-template __global__ void k_vanka_factor<3, float, true>(Geom, double, const float*, float*, int, const int*);
-template __global__ void k_vanka_factor<2, double, false>(Geom, double, const double*, double*, int, const int*);
+template __global__ void k_vanka_factor<2, double, true>(Geom, double, const double*, double*, double*, int, const int*);
+template __global__ void k_vanka_factor<2, float, true>(Geom, double, const float*, float*, float*, int, const int*);
+template __global__ void k_vanka_factor<3, double, true>(Geom, double, const double*, double*, double*, int, const int*);
+template __global__ void k_vanka_factor<3, float, true>(Geom, double, const float*, float*, float*, int, const int*);
+template __global__ void k_vanka_factor<2, double, false>(Geom, double, const double*, double*, double*, int, const int*);
 
 }  // namespace fsi
