@@ -78,22 +78,28 @@ __global__ void __launch_bounds__(vf_lanes<D>() * vf_patches<D>()) k_vanka_facto
       if (lane < D) {
         // Gauss-Jordan with partial pivoting on the NL x 3 NL system of component lane
         double(*m)[3 * NL] = Mu[grp][lane];
+#pragma unroll 1
         for (int pc = 0; pc < NL; ++pc) {
           int pr = pc;
+#pragma unroll 1
           for (int rr = pc + 1; rr < NL; ++rr)
             if (fabs(m[rr][pc]) > fabs(m[pr][pc])) pr = rr;
           if (pr != pc)
+#pragma unroll 1
             for (int c = 0; c < 3 * NL; ++c) {
               const double t = m[pc][c];
               m[pc][c] = m[pr][c];
               m[pr][c] = t;
             }
           const double inv = m[pc][pc] == 0.0 ? 1.0 : 1.0 / m[pc][pc];
+#pragma unroll 1
           for (int c = 0; c < 3 * NL; ++c) m[pc][c] *= inv;
+#pragma unroll 1
           for (int rr = 0; rr < NL; ++rr) {
             if (rr == pc) continue;
             const double f = m[rr][pc];
             if (f != 0.0)
+#pragma unroll 1
               for (int c = 0; c < 3 * NL; ++c) m[rr][c] -= f * m[pc][c];
           }
         }
@@ -103,7 +109,9 @@ __global__ void __launch_bounds__(vf_lanes<D>() * vf_patches<D>()) k_vanka_facto
           cell_colour<D>(g, ci, cj, ck, vc, col, idx, L);
           const int q = idx / vc, t = idx - q * vc;
           S* y = Yu + ((size_t)L.off + (size_t)q * vc) * yu_cell<D>() + t;
+#pragma unroll 1
           for (int a2 = 0; a2 < NL; ++a2)
+#pragma unroll 1
             for (int b = 0; b < NL; ++b) {
               y[(size_t)((2 * lane) * NL * NL + a2 * NL + b) * vc] = (S)m[a2][2 * NL + b];       // Y1
               y[(size_t)((2 * lane + 1) * NL * NL + a2 * NL + b) * vc] = (S)m[a2][NL + b];      // Y2
