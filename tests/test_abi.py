@@ -106,3 +106,15 @@ def test_argument_errors_without_gpu(lib):
     assert lib.coarse_propagate(None, 1, t0, 0.1, 2, None, None, None, None) == fsi.FSI_ERR_ARG
     assert lib.parareal_run(None, 1.0, 2, 2, 1, 1e-8, 2, None, None, None, None) == fsi.FSI_ERR_ARG
     lib.fsi_destroy(None)
+
+
+def test_batch_split_defaults():
+    """Three concurrent slice groups by default, never more groups than slices; an explicit value is kept."""
+    from paper_1907_01252_amd import fsi
+    import synth
+    w = synth.workload("c1")
+    assert fsi.make_params(w, max_batch=8).batch_split == 3
+    assert fsi.make_params(w, max_batch=2).batch_split == 2
+    assert fsi.make_params(w, max_batch=1).batch_split == 0
+    assert fsi.make_params(w, max_batch=8, batch_split=0).batch_split == 0
+    assert fsi.make_params(w, max_batch=8, batch_split=4).batch_split == 4
