@@ -563,7 +563,8 @@ void spmv(const Geom& g, int B, double k, const S* J, const S* x, const S* b, co
           hipStream_t st) {
   const int nb =
       !jrowtiles<D, S>() ? (g.nn + 63) / 64 : (jntx<D, S>(g, 0) * jrows<D>(g) * jtx<D, S>() + 63) / 64;
-  // slices as the fast grid dimension in 2d FP64 (c2 SpMV 4% faster; the 3d one was 8% slower)
+  // slices as the fast grid dimension in 2d FP64 (the 128x32-cell, 32-slice SpMV 4% faster;
+  // the 3d 64x16x16 one was 8% slower)
   const int sf = (D == 2 && sizeof(S) == 8) && nb <= 65535 ? 1 : 0;
   k_spmv<D, S, CJ><<<sf ? dim3(B, nb) : dim3(nb, B), spmv_threads<D>(), 0, st>>>(g, k, J, x, b, Dv, y, act, sf);
 }
@@ -600,8 +601,9 @@ void smooth(fsi_problem* pb, int l, int B, double k, int sweeps, bool zero_first
       // blocks of the colour (vc cells each) and of the copy of the other nodes, per slice.
       // Slices as the fast grid dimension: the blocks of one tile in all slices are dispatched
       // together, so the values every slice shares (displacement rows of slice 0, the
-      // stabilisation stencil) are fetched once per XCD cache and reused (c2 pass 4% faster,
-      // c5 13%); the 2d FP32 pass (row tiles, six waves per SIMD) was 6% slower that way.
+      // stabilisation stencil) are fetched once per XCD cache and reused (the 2d FP64 pass on
+      // 128x32 cells and 32 slices 4% faster, the 3d one on 64x16x16 cells and 16 slices 13%);
+      // the 2d FP32 pass (row tiles, six waves per SIMD) was 6% slower that way.
       const int nbx = (nc + vc - 1) / vc + ncopy;
       const int sf = (D == 3 || sizeof(S) == 8) && nbx <= 65535 ? 1 : 0;
       const dim3 grid = sf ? dim3(B, nbx) : dim3(nbx, B);

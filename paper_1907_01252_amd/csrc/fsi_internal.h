@@ -308,7 +308,7 @@ __host__ __device__ inline size_t ainv_slice(int ncell) {
 // belong to w (stored per slice), then delta_u,i = Y1_i r_u,i - Y2_i delta_v,i.
 // Rows of the full layout (the transposed adjoint system) are all stored.
 // the split patch solve is used with the compressed layout in FP64 (in FP32 the
-// 3d c5-level-1 mixed step no longer converged with it)
+// 3d mixed-precision step on 32x8x8 cells no longer converged with it)
 template <class S, bool CJ>
 __host__ __device__ constexpr bool patch_split() {
   return CJ && sizeof(S) == 8;

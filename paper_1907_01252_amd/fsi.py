@@ -99,8 +99,9 @@ def _check(code, where):
 
 
 # batch_split = 3: three concurrent slice groups measured fastest on one MI355X for
-# c2, c3 and c5 (four groups are slower: with the caller's stream they need more
-# hardware queues than a process gets by default)
+# the 2d FP64 (128x32 cells, 32 slices), 2d mixed (256x64, 64 slices) and 3d mixed
+# (64x16x16, 16 slices) sweeps (four groups are slower: with the caller's stream
+# they need more hardware queues than a process gets by default)
 SOLVER_DEFAULTS = dict(cip_gamma=1e-4, gmres_restart=30, gmres_maxit=300, newton_maxit=30,
                        vanka_sweeps=2, vanka_omega=0.9, newton_rtol=1e-10, lin_rtol=1e-6,
                        vanka_sweeps_coarse=1, precond_lag=1, lin_rtol_first=1e-3, parareal_theta=0,
