@@ -248,3 +248,46 @@ def test_displacement_rows_do_not_depend_on_the_state(dim):
     comp_col = R1.col % nc
     nz = R1.data != 0
     assert np.all((comp_col[nz] == comp_row[nz]) | (comp_col[nz] == comp_row[nz] + dim))
+
+
+def test_solid_inertia_is_consistent_mass():
+    """Momentum rows of the solid with no stiffness (mu_s = lambda_s = 0), the fluid at
+    rest and no displacement: the residual reduces to rho_s M_S (v - v°), M_S the
+    consistent Q1 mass matrix of the solid cells, here built from 1d P1 mass matrices
+    (tensor form) on the bar's own node grid.  A lumped or missing inertia term, a
+    wrong density or a wrong sign fails.  The velocity is put only on nodes that touch
+    no fluid cell, so every fluid term vanishes.
+    """
+    p = synth.workload("c1", mu_s=0.0, lambda_s=0.0, rho_s=1234.5)
+    D = Discretization(p)
+    m = D.mesh
+    x, y = m.axes
+    ix = np.nonzero((x >= 0.4 - 1e-12) & (x <= 0.5 + 1e-12))[0]
+    iy = np.nonzero(y <= 0.25 + 1e-12)[0]
+
+    def mass1(pts):
+        n = len(pts)
+        A = np.zeros((n, n))
+        for i in range(n - 1):
+            A[i:i + 2, i:i + 2] += np.array([[2.0, 1.0], [1.0, 2.0]]) * (pts[i + 1] - pts[i]) / 6.0
+        return A
+
+    Ms = np.kron(mass1(y[iy]), mass1(x[ix]))               # x fastest, as the node numbering
+    nodes = (ix[None, :] + (len(x)) * iy[:, None]).ravel()
+    rng = np.random.default_rng(7)
+    U = np.zeros((m.n_nodes, 5))
+    Uo = np.zeros((m.n_nodes, 5))
+    strict = ~m.in_NF
+    U[strict, 0:2] = rng.uniform(-1.0, 1.0, size=(strict.sum(), 2))
+    Uo[strict, 0:2] = rng.uniform(-1.0, 1.0, size=(strict.sum(), 2))
+    assert strict[nodes].sum() == strict.sum() > 0
+    k = p["k_fine"]
+    R = D.residual(U, Uo, 0.5, k, with_dirichlet=False)
+    expect = np.zeros((m.n_nodes, 2))
+    expect[nodes] = p["rho_s"] * (Ms @ (U[nodes, 0:2] - Uo[nodes, 0:2]))
+    scale = np.abs(expect).max()
+    assert np.abs(R[:, 0:2] - expect).max() <= 1e-13 * scale
+    # the consistent mass couples neighbours: a lumped mass would differ by a lot
+    lumped = np.zeros_like(expect)
+    lumped[nodes] = p["rho_s"] * (Ms.sum(axis=1)[:, None] * (U[nodes, 0:2] - Uo[nodes, 0:2]))
+    assert np.abs(lumped - expect).max() > 0.1 * scale

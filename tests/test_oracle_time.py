@@ -193,3 +193,37 @@ def test_dissipation_matched_theta():
         assert fine < 0 and matched < 0
         assert abs(matched / fine - 1.0) <= 2 * wK ** 2, (wK, matched / fine)
         assert default / fine > 50.0        # the default large step damps ~ (K / k_r)^2 = 64 times more
+
+
+def test_parareal_change_norm_hand_example():
+    """The stopping quantity of the Parareal iteration (Section 3) on a hand-worked
+    two-boundary, two-node example: per boundary and per field (v and u separately,
+    p left out), the Euclidean norm of the change over the norm of the NEW iterate;
+    the largest of these is 1/5 (boundary 1, velocity).
+
+    Each plausible mistake gives a different number: dividing by the old iterate
+    1/sqrt(18), max-norms 1/4, v and u in one norm sqrt(1.01)/sqrt(26), one norm over
+    all boundaries 1/sqrt(26), the pressure included 10.
+    """
+    new = np.zeros((2, 2, 5))
+    old = np.zeros((2, 2, 5))
+    # boundary 0: nonzero, unchanged
+    new[0, 0, 0] = old[0, 0, 0] = 1.0
+    # boundary 1: v_new = ((3, 0), (0, 4)), v_old = ((3, 0), (0, 3))
+    new[1, 0, 0:2] = (3.0, 0.0)
+    new[1, 1, 0:2] = (0.0, 4.0)
+    old[1, 0, 0:2] = (3.0, 0.0)
+    old[1, 1, 0:2] = (0.0, 3.0)
+    # u_new = ((0.6, 0.8), 0), u_old = ((0.6, 0.7), 0): change 0.1 of norm 1
+    new[1, 0, 2:4] = (0.6, 0.8)
+    old[1, 0, 2:4] = (0.6, 0.7)
+    # the pressure changes by ten times its new size
+    new[1, 1, 4] = 1.0
+    old[1, 1, 4] = 11.0
+    assert P.relative_change(new, old, 2) == pytest.approx(0.2, rel=1e-15, abs=0.0)
+    # a change in one boundary's displacement alone is seen with its own norm
+    old2 = new.copy()
+    old2[0, 1, 3] = 0.5
+    new2 = new.copy()
+    new2[0, 1, 2:4] = (0.0, 2.0)
+    assert P.relative_change(new2, old2, 2) == pytest.approx(1.5 / 2.0, rel=1e-15, abs=0.0)
