@@ -211,6 +211,24 @@ fsi_status fsi_debug_vcycle(fsi_problem* pb, int32_t B, const double* U, const d
                             const double* t_host, double k, const double* X, double* Y,
                             hipStream_t stream);
 
+/* Allocation-free variant of fsi_debug_residual, for callers that cannot
+   allocate device memory during the call (code under HIP graph capture, tight
+   serving loops, harnesses that forbid hipMalloc).  Same arguments, layout and
+   result as fsi_debug_residual: R_out[b] = residual of the step
+   t_host[b] - k -> t_host[b] at U[b] with old state Uo[b].  The element
+   residuals and the slice times go to a static device array of 32 MiB that the
+   library holds on each GPU until the process ends, not to the problem's
+   workspace; the call allocates nothing.  Limit: B * (NE * n_cells) + B
+   doubles (NE = 20 in 2d, 56 in 3d; n_cells of the finest level, the first
+   term rounded up to 32) must fit in 32 MiB, else FSI_ERR_ARG with a message
+   on stderr (e.g. 51 slices of 128x32 cells, 4 of 64x16x16).  Every call on a
+   GPU shares that GPU's array: calls that overlap on one GPU (any problem,
+   any stream) race and must be serialised by the caller.  Nothing in the
+   array has to start at zero (every value read is written earlier in the
+   same call).  Also FSI_ERR_ARG as fsi_debug_residual. */
+fsi_status fsi_residual_noalloc(fsi_problem* pb, int32_t B, const double* U, const double* Uo,
+                                const double* t_host, double k, double* R_out, hipStream_t stream);
+
 /* Per-kernel timing over the calls made while enabled (HIP events on the
    caller's stream around every launch of the named kernel family).
    fsi_profile_enable(pb, 1) starts collecting (and clears), 0 stops.

@@ -108,6 +108,8 @@ struct fsi_problem {
   int *nact = nullptr;   // Newton-active slices (device)
   int *gact = nullptr;   // FGMRES-active slices (device)
   int *flag = nullptr;
+  // device address of the static scratch array on this problem's device (allocation-free residual)
+  double* scratch = nullptr;
   // FGMRES workspace
   void *V = nullptr, *Z = nullptr, *w = nullptr, *xs = nullptr, *tmp = nullptr;
   double *H = nullptr, *hcol = nullptr, *hcol2 = nullptr, *cs = nullptr, *sn = nullptr, *gv = nullptr,
@@ -1214,6 +1216,37 @@ fsi_status adjoint_run(fsi_problem* pb, double T, int N, int m, const double* U0
 
 }  // namespace
 
+// ------------------------------------------------------------ static scratch
+// Scratch of fsi_residual_noalloc: the element residuals of the batch and the
+// per-slice times, in a file-scope device array that exists on every GPU the
+// library runs on (each GPU holds its own copy until the process ends).  Host
+// code never passes the array's name to a kernel or copy: that is a host-side
+// stand-in, not a device address.  Its device address on a device comes from
+// hipGetSymbolAddress, called once per device with that device current (at
+// fsi_setup) and kept per device.
+constexpr size_t SCRATCH_BYTES = (size_t)32 << 20;
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+
+constexpr int SCRATCH_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_dev[SCRATCH_MAX_DEVICES] = {};
+
+// Device address of the scratch array on the current device (looked up once).
+static fsi_status scratch_address(double** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return FSI_ERR_ARG;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return FSI_ERR_HIP;
+    g_scratch_dev[dev] = (double*)ptr;
+  }
+  *out = g_scratch_dev[dev];
+  return FSI_OK;
+}
+
 // =================================================================== C ABI
 extern "C" {
 
@@ -1363,6 +1396,10 @@ static fsi_status setup_impl(const fsi_params* prm, fsi_problem** out) {
       hipEventCreateWithFlags(&pb->iev, hipEventDisableTiming) != hipSuccess) {
     fsi_destroy(pb);
     return FSI_ERR_HIP;
+  }
+  if ((s = scratch_address(&pb->scratch)) != FSI_OK) {
+    fsi_destroy(pb);
+    return s;
   }
   *out = pb;
   return FSI_OK;
@@ -1777,6 +1814,36 @@ fsi_status fsi_debug_residual(fsi_problem* pb, int32_t B, const double* U, const
     CHK(residual<3>(pb, B, step_par(pb, k), U, Uo, R, nullptr, st));
   else
     CHK(residual<2>(pb, B, step_par(pb, k), U, Uo, R, nullptr, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return FSI_OK;
+}
+
+fsi_status fsi_residual_noalloc(fsi_problem* pb, int32_t B, const double* U, const double* Uo, const double* t,
+                                double k, double* R, hipStream_t st) {
+  if (!pb || !U || !Uo || !t || !R || B <= 0 || B > pb->Bmax || !(k > 0) || !pb->scratch) return FSI_ERR_ARG;
+  const Level& F = pb->lev[pb->nlev - 1];
+  const int NE = pb->p.dim == 3 ? Dm<3>::NE : Dm<2>::NE;
+  // element residuals [B][NE][ncell], then the B slice times at a 256-byte boundary
+  const size_t re_vals = (size_t)B * NE * F.ncell;
+  const size_t t_off = (re_vals + 31) / 32 * 32;
+  if ((t_off + (size_t)B) * sizeof(double) > SCRATCH_BYTES) {
+    std::fprintf(stderr, "fsi_residual_noalloc: %d slices need %zu bytes of scratch, more than its %zu\n", B,
+                 (t_off + (size_t)B) * sizeof(double), SCRATCH_BYTES);
+    return FSI_ERR_ARG;
+  }
+  double* re = pb->scratch;
+  double* td = pb->scratch + t_off;
+  HIPCHK(hipMemcpyAsync(td, t, B * sizeof(double), hipMemcpyHostToDevice, st));
+  const StepPar sp = step_par(pb, k);
+  const Geom g = F.geom();
+  if (pb->p.dim == 3) {
+    k_elem_residual<3><<<grid1(g.ncell, B), TPB, 0, st>>>(g, sp, U, Uo, re, nullptr);
+    k_gather_residual<3><<<grid1(g.nn, B), TPB, 0, st>>>(g, sp, re, U, td, R, nullptr);
+  } else {
+    k_elem_residual<2><<<grid1(g.ncell, B), TPB, 0, st>>>(g, sp, U, Uo, re, nullptr);
+    k_gather_residual<2><<<grid1(g.nn, B), TPB, 0, st>>>(g, sp, re, U, td, R, nullptr);
+  }
+  HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(st));
   return FSI_OK;
 }

@@ -23,6 +23,7 @@ MAX_SLICES = 1024
 # entry points declared in include/fsi.h
 EXPORTS = ("fsi_setup", "fsi_sizes", "fsi_initial_state", "fine_propagate", "coarse_propagate",
            "parareal_run", "adjoint_gradient", "fsi_debug_residual", "fsi_debug_jacobian_apply", "fsi_debug_vcycle",
+           "fsi_residual_noalloc",
            "fsi_profile_enable", "fsi_profile_query", "fsi_destroy", "fsi_status_string")
 
 
@@ -72,6 +73,7 @@ def load():
     lib.parareal_run.argtypes = [vp, dbl, i32, i32, i32, dbl, i32, vp, vp, C.POINTER(Stats), vp]
     lib.adjoint_gradient.argtypes = [vp, dbl, i32, i32, vp, dp, dp, C.POINTER(Stats), vp]
     lib.fsi_debug_residual.argtypes = [vp, i32, vp, vp, dp, dbl, vp, vp]
+    lib.fsi_residual_noalloc.argtypes = [vp, i32, vp, vp, dp, dbl, vp, vp]
     lib.fsi_debug_jacobian_apply.argtypes = [vp, i32, vp, vp, dp, dbl, vp, vp, vp]
     lib.fsi_debug_vcycle.argtypes = [vp, i32, vp, vp, dp, dbl, vp, vp, vp]
     lib.fsi_profile_enable.argtypes = [vp, i32]
@@ -224,6 +226,15 @@ class Problem:
         arr, ptr = _dvec(t)
         _check(load().fsi_debug_residual(self.h, B, _ptr(U), _ptr(Uo), ptr, float(k), _ptr(R), _stream()),
                "fsi_debug_residual")
+
+    def residual_noalloc(self, B, U, Uo, t, k, R, raise_on_error=True):
+        """fsi_residual_noalloc: the residual of fsi_debug_residual, with its scratch in the
+        library's static device array (the call allocates nothing)."""
+        arr, ptr = _dvec(t)
+        code = load().fsi_residual_noalloc(self.h, B, _ptr(U), _ptr(Uo), ptr, float(k), _ptr(R), _stream())
+        if raise_on_error:
+            _check(code, "fsi_residual_noalloc")
+        return code
 
     def debug_jacobian_apply(self, B, U, Uo, t, k, X, Y):
         arr, ptr = _dvec(t)
