@@ -8,15 +8,20 @@ of the first Parareal fine sweep.  One timed step = one batched fine sweep
 (fine_propagate over all 32 slices).  Reported:
 
   value            dof.steps/s of the batched sweep (unknowns x steps x slices / wall time)
-  sequential       the same slices propagated one call per slice (B = 1), on a
-                   prefix of the slices, same solver settings
+  sequential       slices spread over [0, T] propagated one call per slice
+                   (B = 1), same solver settings; their outputs must equal the
+                   timed batched sweep's outputs of the same slices (1e-10 per
+                   field in FP64, 1e-6 mixed)
   roofline         the colored Vanka smoothing pass (dominant kernel): algorithmic
-                   bytes per launch / mean launch time from HIP events on the
-                   stream of the timed sweeps, against the 8 TB/s HBM peak
+                   bytes per launch (active slices only) / mean launch time from
+                   HIP events on the library's stream, against the 8 TB/s HBM peak
+  roofline_c3/_c5  the same for the 256x64 mixed and the 64x16x16 3d workloads
+                   (short sweeps, same kernels and sizes)
   accuracy         a batched-sweep slice against the FP64 oracle on a bounded
-                   number of steps (gate 1e-6 relative per field)
+                   number of steps (gate 1e-10 relative per field in FP64, 1e-6 mixed)
   cpu_baseline     the oracle (NumPy/SciPy, SuperLU) on the host, same slice,
-                   bounded to a few steps
+                   bounded to a few steps; slice_parallel: one process per slice
+                   on up to 16 host cores, the same few steps each
 """
 from __future__ import annotations
 
@@ -78,7 +83,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--precision", default=None, help="fp64 | mixed (default: the workload's)")
-    ap.add_argument("--seq-slices", type=int, default=4)
+    ap.add_argument("--seq-slices", type=int, default=4,
+                    help="slices of the sequential baseline, spread evenly over the interval")
     ap.add_argument("--gate-steps", type=int, default=2)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -88,6 +94,10 @@ def main():
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="before the sweep, copy this many MB with a plain device copy (counter calibration)")
     ap.add_argument("--no-profile-sweep", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the short profiled c3 and c5 sweeps (roofline_c3, roofline_c5)")
+    ap.add_argument("--cpu-procs", type=int, default=16,
+                    help="most host processes of the slice-parallel oracle figure")
     ap.add_argument("--set", action="append", default=[], metavar="KEY=VALUE",
                     help="solver parameter override (fsi_params field), e.g. vanka_sweeps_coarse=1")
     ap.add_argument("--parareal", action="store_true",
@@ -153,6 +163,7 @@ def main():
     torch.cuda.synchronize()
     t_b = time.perf_counter()
     wall = (t_b - t_a) / args.steps
+    Ubatch = Uout.clone()
     # one more sweep of the same workload with HIP events around every launch of the
     # profiled kernel families (kernels launched directly, not replayed from graphs; the
     # library runs it as one batch of all slices, so that no other group's kernels share
@@ -170,18 +181,29 @@ def main():
     dof_steps = nd * m * N
     value = dof_steps / wall
 
-    # ---- sequential-slice path on a prefix of the slices
+    # ---- sequential-slice path (B = 1 calls) on slices spread over the whole interval; its
+    # outputs must equal the timed batched sweep's outputs of the same slices
     seq = None
+    eq_tol = 1e-10 if prec == "fp64" else 1e-6
     if not args.no_seq:
         S = min(args.seq_slices, N)
+        picks = sorted({int(round(q * (N - 1) / max(S - 1, 1))) for q in range(S)})
+        outs = {}
         torch.cuda.synchronize()
         t_c = time.perf_counter()
-        for l in range(S):
+        for l in picks:
             o = torch.zeros_like(Uin[l:l + 1])
             prob.fine_propagate(1, [t0s[l]], dl, m, Uin[l:l + 1].contiguous(), o)
+            outs[l] = o
         torch.cuda.synchronize()
         seq_wall = time.perf_counter() - t_c
-        seq = {"value": nd * m * S / seq_wall, "slices_timed": S, "ms_per_slice": 1e3 * seq_wall / S}
+        diff = 0.0
+        for l in picks:
+            a, b = outs[l][0].cpu().numpy(), Ubatch[l].cpu().numpy()
+            for sl in fields(dim).values():
+                diff = max(diff, float(np.linalg.norm(a[:, sl] - b[:, sl]) / max(np.linalg.norm(b[:, sl]), 1e-300)))
+        seq = {"value": nd * m * len(picks) / seq_wall, "slices_timed": picks, "ms_per_slice": 1e3 * seq_wall / len(picks),
+               "max_rel_diff_vs_batched": diff, "gate": eq_tol, "pass": diff <= eq_tol}
 
     # ---- accuracy gate and CPU baseline: oracle on slice 1 for a few steps
     acc, cpu = None, None
@@ -213,18 +235,22 @@ def main():
         cores_used = max(1, int(round((time.process_time() - c_d) / cpu_wall)))
         if done == ns:
             errs = {}
-            for f, sl in (("v", slice(0, dim)), ("u", slice(dim, 2 * dim)), ("p", slice(2 * dim, 2 * dim + 1))):
+            for f, sl in fields(dim).items():
                 errs[f] = float(np.linalg.norm(g[:, sl] - ref[:, sl]) / np.linalg.norm(ref[:, sl]))
-            acc = {"max_rel_err": max(errs.values()), "per_field": errs, "gate": 1e-6,
-                   "pass": max(errs.values()) <= 1e-6, "sample": f"slice {l}, {ns} steps vs FP64 oracle"}
+            acc = {"max_rel_err": max(errs.values()), "per_field": errs, "gate": eq_tol,
+                   "pass": max(errs.values()) <= eq_tol, "sample": f"slice {l}, {ns} steps vs FP64 oracle"}
         cpu = {"value": nd * done / cpu_wall, "unit": "dof\u00b7steps/s", "cores": cores_used,
                "threads_allowed": int(threads), "kind": "oracle",
                "sample": f"slice {l} of {args.workload}: {done} Newton-SuperLU steps, {cpu_wall:.1f} s"}
+        cpu["slice_parallel"] = oracle_slice_parallel(args.workload, [Uin[q].cpu().numpy() for q in range(N)], t0s, k,
+                                                      ns, args.cpu_procs, nd)
 
-    # dominant kernel family by total time in the timed sweeps
-    dom = max(("vanka_pass_fine", "krylov_spmv_fine", "level_residual_fine"), key=lambda f: fams[f][1])
-    dn, dms, dby = fams[dom]
-    achieved = dby / (dms * 1e-3) / 1e9 if dms > 0 else None
+    roof = roofline_of(fams, counter_traffic if args.workload == "c2" else None, prec)
+    prob.close()
+    extra = {}
+    if not args.no_extra and args.workload == "c2":
+        for name, msteps in (("c3", 4), ("c5", 2)):
+            extra["roofline_" + name] = short_profiled_roofline(name, msteps)
     out = {
         "metric": METRIC,
         "value": value,
@@ -246,12 +272,8 @@ def main():
         "newton_per_sweep": stats[-1][0], "krylov_per_sweep": stats[-1][1],
         "sequential": seq,
         "speedup_batched_vs_sequential": (value / seq["value"]) if seq else None,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-                     "traffic": counter_traffic(dom, prec) if args.workload == "c2" else None,
-                     "kernel": KERNEL_NAMES.get(dom, dom), "launches": dn,
-                     "mean_launch_us": 1e3 * dms / max(dn, 1), "bytes_per_launch": dby / max(dn, 1),
-                     "measured_on": "profiled sweep: all slices in one batch, HIP events around every launch"},
+        "roofline": roof,
+        **extra,
         "profiled_sweep_ms": 1e3 * prof_wall,
         "kernels": {f: {"launches": v[0], "ms_per_sweep": v[1],
                         "GBs": (v[2] / (v[1] * 1e-3) / 1e9) if v[1] > 0 else None} for f, v in fams.items()},
@@ -259,6 +281,100 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
+
+
+def fields(dim):
+    return {"v": slice(0, dim), "u": slice(dim, 2 * dim), "p": slice(2 * dim, 2 * dim + 1)}
+
+
+def roofline_of(fams, traffic_fn, prec):
+    """roofline object of the dominant kernel family (largest time in the profiled sweep)."""
+    dom = max(("vanka_pass_fine", "krylov_spmv_fine", "level_residual_fine"), key=lambda f: fams[f][1])
+    dn, dms, dby = fams[dom]
+    achieved = dby / (dms * 1e-3) / 1e9 if dms > 0 else None
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+            "traffic": traffic_fn(dom, prec) if traffic_fn else None,
+            "kernel": KERNEL_NAMES.get(dom, dom), "launches": dn,
+            "mean_launch_us": 1e3 * dms / max(dn, 1), "bytes_per_launch": dby / max(dn, 1),
+            "measured_on": "profiled sweep: all slices in one batch, HIP events around every launch; "
+                           "bytes of the slices each launch works on"}
+
+
+def short_profiled_roofline(name, msteps):
+    """Dominant-kernel roofline of a short profiled sweep of workload `name` (msteps fine steps of
+    the workload's size per slice, all slices in one batch; inputs from a one-step coarse sweep)."""
+    import torch
+    import synth
+    from paper_1907_01252_amd import fsi
+    p = synth.workload(name, seed=0)
+    prec = p["precision"]
+    N, m = p["N"], p["m"]
+    dl = p["slice_len"] * msteps / m
+    prob = fsi.Problem(fsi.make_params(p, precision=prec, max_batch=N))
+    nc = prob.n_dofs // prob.n_nodes
+    U = torch.zeros(N + 1, prob.n_nodes, nc, dtype=torch.float64, device="cuda")
+    prob.initial_state(U[0])
+    for l in range(N):
+        out = torch.zeros_like(U[0:1])
+        prob.coarse_propagate(1, [l * dl], dl, 1, U[l:l + 1].contiguous(), out)
+        U[l + 1] = out[0]
+    Uin = U[:N].contiguous()
+    Uout = torch.zeros_like(Uin)
+    t0s = [l * dl for l in range(N)]
+    prob.fine_propagate(N, t0s, dl, msteps, Uin, Uout)      # warm-up
+    prob.profile_enable(True)
+    _, st = prob.fine_propagate(N, t0s, dl, msteps, Uin, Uout)
+    torch.cuda.synchronize()
+    prob.profile_enable(False)
+    fams = {f: prob.profile_query(i) for i, f in enumerate(FAMILIES)}
+    prob.close()
+    r = roofline_of(fams, None, prec)
+    r["sweep"] = f"{name}: {prob.n_dofs} unknowns, {N} slices x {msteps} steps of {p['k_fine']:.6g}, {prec}"
+    r["newton"], r["krylov"] = st.newton_total, st.krylov_total
+    return r
+
+
+def _oracle_slice_worker(name, u_in, t0, k, ns, barrier, queue):
+    """One host process of the slice-parallel oracle figure: ns Newton-SuperLU steps of one slice."""
+    from threadpoolctl import threadpool_limits
+    import synth
+    from oracle.residual import Discretization
+    from oracle import propagate as P
+    with threadpool_limits(1):
+        D = Discretization(synth.workload(name, seed=0))
+        barrier.wait()
+        t_0 = time.perf_counter()
+        U = u_in
+        for n in range(ns):
+            U = P.newton_step(D, U, t0 + (n + 1) * k, k)
+        queue.put(time.perf_counter() - t_0)
+
+
+def oracle_slice_parallel(name, inputs, t0s, k, ns, max_procs, nd):
+    """The paper's one-slice-per-core model with the oracle: P processes (P = min(slices, host
+    cores, max_procs)) each take ns steps of its own slice at the same time; throughput = P ns
+    unknowns-steps over the slowest process's time.  A sample of the sweep (ns of m steps)."""
+    import multiprocessing as mp
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    P = max(1, min(len(inputs), cores, max_procs))
+    ctx = mp.get_context("spawn")
+    barrier, queue = ctx.Barrier(P), ctx.Queue()
+    picks = [int(round(q * (len(inputs) - 1) / max(P - 1, 1))) for q in range(P)]
+    procs = [ctx.Process(target=_oracle_slice_worker, args=(name, inputs[l], t0s[l], k, ns, barrier, queue))
+             for l in picks]
+    for pr in procs:
+        pr.start()
+    walls = [queue.get(timeout=600) for _ in procs]
+    for pr in procs:
+        pr.join()
+    return {"value": P * ns * nd / max(walls), "unit": "dof\u00b7steps/s", "cores": P, "processes": P,
+            "kind": "oracle",
+            "sample": f"{P} slices of {name} at once, one process each, {ns} Newton-SuperLU steps per slice "
+                      f"(slowest {max(walls):.1f} s)"}
 
 
 def adjoint_bench(args):

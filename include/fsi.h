@@ -123,6 +123,13 @@ typedef struct {
                                 per-kernel timing is enabled, and the adjoint's recompute,
                                 run as one batch.  Each group's stream takes a hardware
                                 queue: S = 3 leaves one for the caller's stream. */
+  double newton_res_rtol;    /* FP64 residual test of Newton's method (in the mixed path the test
+                                of the iterative refinement): a slice's step is done when, after
+                                an iteration whose linear solve reached its tolerance, the update
+                                test (newton_rtol) holds and then the residual R of the time-step
+                                equation (Section 2.3) at the new state satisfies, per field f,
+                                max |D R_f| <= newton_res_rtol max |U_f|, D the row scaling
+                                1 / max_j |J_ij| of the step Jacobian (0 < newton_res_rtol < 1) */
 } fsi_params;
 
 #define FSI_MAX_SLICES 1024
@@ -130,14 +137,24 @@ typedef struct {
   int32_t newton_its[FSI_MAX_SLICES];   /* Newton iterations summed over the steps, per slice */
   int32_t krylov_its[FSI_MAX_SLICES];   /* FGMRES iterations summed over the steps, per slice */
   int32_t slice_status[FSI_MAX_SLICES]; /* fsi_status of the slice */
-  double stage_ms[8];                   /* 0 residual, 1 Jacobian+smoother setup, 2 linear solve,
-                                           3 update, 4 total, 5 coarse (Parareal), 6 fine (Parareal) */
+  double stage_ms[8];                   /* propagators: milliseconds summed over the call's Newton
+                                           iterations, from HIP events on the call's stream (with
+                                           concurrent slice groups the largest group's figure):
+                                           0 residual, 1 Jacobian + multigrid setup, 2 linear
+                                           solve, 3 update and convergence tests; 4 wall time of
+                                           the call (host clock).  parareal_run: 4 wall time,
+                                           5 coarse propagations, 6 fine sweeps (host clock) */
   int32_t parareal_iters;               /* completed Parareal iterations (also when a later one failed) */
   int32_t newton_total, krylov_total;   /* totals over all slices of the call */
 } fsi_stats;
 
 /* Build the mesh hierarchy, node classes, constant stabilisation operators and
    device workspace for params->max_batch slices.  *out receives the handle.
+   The mesh is the tensor mesh of params->seg_* refined `level` times, with the
+   elastic bar resolved by cell faces on every level (Section 2.2 asks for an
+   interface-fitted mesh); the node classes and the Dirichlet data follow the
+   ALE system of eqs. (ALE), (ALE:stress) and the test spaces of eq. (test);
+   the pressure stabilisation is the local projection named in Section 2.2.
    Errors: FSI_ERR_ARG (bad params: a size or count out of range, a non-finite
    constant, rho_f, nu_f, rho_s, mu_s or ramp_time not positive, lambda_s,
    theta0, lps_alpha0 or cip_gamma negative, vanka_omega outside (0, 2),
@@ -146,10 +163,16 @@ typedef struct {
    FSI_ERR_OOM, FSI_ERR_HIP. */
 fsi_status fsi_setup(const fsi_params* params, fsi_problem** out);
 
-/* Number of mesh nodes and of unknowns (5 per node in 2d) on the finest level. */
+/* Number of mesh nodes and of unknowns on the finest level: the equal-order
+   nodal unknowns (v, u, p) of Section 2.2, 5 per node in 2d and 7 in 3d.
+   FSI_ERR_ARG if pb is NULL; either output pointer may be NULL. */
 fsi_status fsi_sizes(const fsi_problem* pb, int64_t* n_nodes, int64_t* n_dofs);
 
-/* U0_dev[n_dofs] := zero state with the Dirichlet data of t = 0. */
+/* U0_dev[n_dofs] := the initial value of eq. (ALE) used by the workloads: the
+   fluid and the bar at rest (v = u = p = 0) with the Dirichlet data of t = 0
+   (the inflow profile of Section 4 scaled by the ramp s(0) = 0, so also zero).
+   Device array of the caller, written on `stream`; returns after completion.
+   FSI_ERR_ARG for NULL arguments. */
 fsi_status fsi_initial_state(fsi_problem* pb, double* U0_dev, hipStream_t stream);
 
 /* Fine propagator F of Section 3: for each of B slices b, m uniform steps of
@@ -159,7 +182,14 @@ fsi_status fsi_initial_state(fsi_problem* pb, double* U0_dev, hipStream_t stream
    iteration counts go to stats (host, may be NULL).  FSI_ERR_ARG if B is not
    in [1, max_batch], m < 1, slice_len is not positive or a pointer is NULL;
    non-finite input gives FSI_ERR_NONFINITE before any work (U_out is then not
-   written); a slice that fails keeps its last iterate. */
+   written); a slice that fails keeps its last iterate.  Per-slice statuses
+   (stats->slice_status; the call returns one of the failing ones):
+   FSI_ERR_NEWTON (the update and residual tests, newton_rtol and
+   newton_res_rtol, not met within newton_maxit iterations), FSI_ERR_LINEAR
+   (the same, and the last linear solve of the slice missed its tolerance
+   within gmres_maxit iterations; an update from such a solve is never
+   accepted), FSI_ERR_NONFINITE (a Newton iterate was not finite).  A failed
+   slice stops; the others go on. */
 fsi_status fine_propagate(fsi_problem* pb, int32_t B, const double* t0_host, double slice_len,
                           int32_t m, const double* U_in_dev, double* U_out_dev,
                           fsi_stats* stats, hipStream_t stream);

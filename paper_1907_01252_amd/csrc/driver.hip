@@ -79,6 +79,9 @@ struct Prof {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[F_NFAM];
   double bytes[F_NFAM] = {};
   int64_t launches[F_NFAM] = {};
+  // slices the timed launches work on (the kernels return at once for the others):
+  // the algorithmic bytes are charged for these only
+  int pact = 0;
 };
 
 }  // namespace
@@ -133,6 +136,14 @@ struct fsi_problem {
   double *npart = nullptr, *nmax = nullptr;
   int nchunk_n = 1, chunk_n = 1;
   Prof prof;
+  // stage events of the Newton iterations (pool reused by every call)
+  struct StageEv {
+    int stage;
+    hipEvent_t a, b;
+  };
+  std::vector<hipEvent_t> spool;
+  size_t sused = 0;
+  std::vector<StageEv> sev;
   std::vector<void*> allocs;
   // pipelined Parareal: workspace of the fine-sweep worker (created on first use)
   fsi_problem* pipe = nullptr;
@@ -467,6 +478,14 @@ struct ProfScope {
   }
 };
 
+// slices whose bytes a profiled launch over a batch of B is charged for
+inline int prof_nb(const fsi_problem* pb, int B) { return pb->prof.on ? std::min(pb->prof.pact, B) : B; }
+inline int count_active(const std::vector<int>& a) {
+  int n = 0;
+  for (int v : a) n += v != 0;
+  return n;
+}
+
 StepPar step_par(const fsi_problem* pb, double k) {
   StepPar sp;
   sp.k = k;
@@ -488,7 +507,7 @@ fsi_status residual(fsi_problem* pb, int B, const StepPar& sp, const double* U, 
   Level& F = pb->lev[pb->nlev - 1];
   const Geom g = F.geom();
   {
-    ProfScope ps(pb, F_RES, st, (double)B * (F.nn * NC * 8.0 * 3 + F.ncell * NE * 8.0 * 2));
+    ProfScope ps(pb, F_RES, st, (double)prof_nb(pb, B) * (F.nn * NC * 8.0 * 3 + F.ncell * NE * 8.0 * 2));
     k_elem_residual<D><<<grid1(g.ncell, B), TPB, 0, st>>>(g, sp, U, Uo, pb->Re, act);
     k_gather_residual<D><<<grid1(g.nn, B), TPB, 0, st>>>(g, sp, pb->Re, U, pb->tdev, R, act);
   }
@@ -529,7 +548,7 @@ fsi_status assemble_levels(fsi_problem* pb, int B, const StepPar& sp, const int*
       k_inject<D><<<grid1(g.nn, B), TPB, 0, st>>>(g, f.geom(), Uof, lv.Uo);
     }
     {
-      ProfScope ps(pb, F_JAC, st, (double)B * (g.ncell * NE * NE * 8.0 + 2.0 * g.nn * NC * 8));
+      ProfScope ps(pb, F_JAC, st, (double)prof_nb(pb, B) * (g.ncell * NE * NE * 8.0 + 2.0 * g.nn * NC * 8));
       k_elem_jacobian<D, false><<<dim3((g.ncell + jac_cells<D>() - 1) / jac_cells<D>(), B),
                                   jac_cells<D>() * jac_waves<D>(), 0, st>>>(g, sp, U, Uo, pb->Ke, act);
     }
@@ -595,8 +614,9 @@ void smooth(fsi_problem* pb, int l, int B, double k, int sweeps, bool zero_first
       constexpr bool SP = patch_split<S, CJ>();
       const double inv = (double)ainv_rows<D, SP>() * NE * nc * sizeof(S);
       const double ysh = SP ? (double)yu_cell<D>() * nc * sizeof(S) : 0.0;
-      const double by = zero ? (double)B * (inv + 2.0 * g.nn * NC * sizeof(S)) + ysh
-                             : jbytes_launch<D, S, CJ>(g, B) + (double)B * (inv + vec) + ysh + (double)NPST * g.nn * 8.0;
+      const int nb = prof_nb(pb, B);
+      const double by = zero ? (double)nb * (inv + 2.0 * g.nn * NC * sizeof(S)) + ysh
+                             : jbytes_launch<D, S, CJ>(g, nb) + (double)nb * (inv + vec) + ysh + (double)NPST * g.nn * 8.0;
       ProfScope ps(pb, fine ? F_SMOOTH : F_COARSE_LEV, st, by);
       const int ncopy = (g.nn + NC * 64 - 1) / (NC * 64);
       const S *J = (const S*)lv.J, *Ai = (const S*)lv.Ainv, *Yu = (const S*)lv.Yu;
@@ -640,7 +660,8 @@ void vcycle(fsi_problem* pb, int B, double k, const S* rhs, S* out, const int* a
     smooth<D, S, CJ>(pb, l, B, k, l == L ? pb->p.vanka_sweeps : pb->p.vanka_sweeps_coarse, true, x, b, act, st);
     const Geom g = lv.geom();
     {
-      const double by = jbytes_launch<D, S, CJ>(g, B) + (double)B * 3.0 * g.nn * NC * sizeof(S) + (double)NPST * g.nn * 8.0;
+      const int nb = prof_nb(pb, B);
+      const double by = jbytes_launch<D, S, CJ>(g, nb) + (double)nb * 3.0 * g.nn * NC * sizeof(S) + (double)NPST * g.nn * 8.0;
       ProfScope ps(pb, l == L ? F_LEVEL_RES : F_COARSE_LEV, st, by);
       spmv<D, S, CJ>(g, B, k, (const S*)lv.J, x, b, nullptr, (S*)lv.r_, act, st);
     }
@@ -650,7 +671,7 @@ void vcycle(fsi_problem* pb, int B, double k, const S* rhs, S* out, const int* a
     Level& l0 = pb->lev[0];
     const int n0 = l0.nn * NC;
     if constexpr (D == 2) {
-      ProfScope ps(pb, F_COARSE_SOLVE, st, (double)B * ((double)n0 * n0 + 2.0 * n0) * sizeof(S));
+      ProfScope ps(pb, F_COARSE_SOLVE, st, (double)prof_nb(pb, B) * ((double)n0 * n0 + 2.0 * n0) * sizeof(S));
       k_coarse_gemv<S><<<dim3((n0 + 63) / 64, B), CG_THREADS, 0, st>>>(l0.geom(), (const S*)pb->cAinv,
                                                                        (const S*)l0.b_, (S*)l0.x_, act);
     } else {
@@ -703,7 +724,8 @@ fsi_status vcycle_run(fsi_problem* pb, int B, double k, hipStream_t st) {
 // right-preconditioned FGMRES(R) with classical Gram-Schmidt applied twice; the
 // preconditioner is one multigrid V-cycle.  The solution (type S) goes to pb->xs.
 template <int D, class S, bool CJ>
-fsi_status fgmres(fsi_problem* pb, int B, double k, std::vector<int>& kits, hipStream_t st) {
+fsi_status fgmres(fsi_problem* pb, int B, double k, std::vector<int>& kits, hipStream_t st,
+                  std::vector<int>* failed = nullptr) {
   FSI_DIM(D);
   Level& F = pb->lev[pb->nlev - 1];
   const Geom g = F.geom();
@@ -720,6 +742,7 @@ fsi_status fgmres(fsi_problem* pb, int B, double k, std::vector<int>& kits, hipS
   const int nchunk = (n + chunk - 1) / chunk;
   const dim3 gb((B + 63) / 64), tb(64);
   std::vector<int> hstate(B);
+  if (failed) failed->assign(B, 0);
   HIPCHK(hipMemcpyAsync(pb->ltol, pb->ltol_h.data(), B * sizeof(double), hipMemcpyHostToDevice, st));
   k_fill<S><<<1024, TPB, 0, st>>>((size_t)B * n, xs, (S)0);
   HIPCHK(hipMemcpyAsync(pb->gact, pb->nact, B * sizeof(int), hipMemcpyDeviceToDevice, st));
@@ -745,6 +768,11 @@ fsi_status fgmres(fsi_problem* pb, int B, double k, std::vector<int>& kits, hipS
     bool any = false;
     for (int b = 0; b < B; ++b) any |= hstate[b] == 0;
     if (!any) break;
+    if (pb->prof.on) {
+      int na = 0;
+      for (int b = 0; b < B; ++b) na += hstate[b] == 0;
+      pb->prof.pact = na;
+    }
     int jmax = 0;
     for (int j = 0; j < R; ++j) {
       S* Vj = V + (size_t)j * n;
@@ -755,8 +783,9 @@ fsi_status fgmres(fsi_problem* pb, int B, double k, std::vector<int>& kits, hipS
       k_scale<S><<<grid1(n, B), TPB, 0, st>>>(n, w, (size_t)n, Zj, zb, nullptr, 0, 2, pb->gact);
       S* a = tmp;
       {
+        const int nb = prof_nb(pb, B);
         ProfScope ps(pb, F_GMRES_SPMV, st,
-                     jbytes_launch<D, S, CJ>(g, B) + (double)B * (2.0 * n * sizeof(S) + n * 8.0) + (double)NPST * F.nn * 8.0);
+                     jbytes_launch<D, S, CJ>(g, nb) + (double)nb * (2.0 * n * sizeof(S) + n * 8.0) + (double)NPST * F.nn * 8.0);
         spmv<D, S, CJ>(g, B, k, (const S*)F.J, w, nullptr, F.Dsc, a, pb->gact, st);
       }
       // classical Gram-Schmidt, twice
@@ -787,7 +816,12 @@ fsi_status fgmres(fsi_problem* pb, int B, double k, std::vector<int>& kits, hipS
       HIPCHK(hipMemcpyAsync(hstate.data(), pb->gstate, B * sizeof(int), hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
       any = false;
-      for (int b = 0; b < B; ++b) any |= hstate[b] == 0;
+      int na = 0;
+      for (int b = 0; b < B; ++b) {
+        any |= hstate[b] == 0;
+        na += hstate[b] == 0;
+      }
+      pb->prof.pact = na;
       if (!any || total >= pb->p.gmres_maxit) break;
     }
     // xs += Z y on every slice that ran in this cycle (ncol > 0)
@@ -796,7 +830,12 @@ fsi_status fgmres(fsi_problem* pb, int B, double k, std::vector<int>& kits, hipS
                                                   pb->nact);
     HIPCHK(hipGetLastError());
     if (!any) break;
-    if (total >= pb->p.gmres_maxit) return FSI_ERR_LINEAR;
+    if (total >= pb->p.gmres_maxit) {
+      // the slices still running did not reach their tolerance
+      if (failed)
+        for (int b = 0; b < B; ++b) (*failed)[b] = hstate[b] == 0 ? 1 : 0;
+      return FSI_ERR_LINEAR;
+    }
     // restart the unconverged slices
     k_update_gact<<<gb, tb, 0, st>>>(pb->nact, pb->gstate, pb->gact, B);
   }
@@ -808,15 +847,34 @@ struct RunStats {
   std::vector<int> newton, krylov, status;
 };
 
+// Stage timing of the Newton iterations (stats->stage_ms[0..3]): HIP events on
+// the call's stream at the stage boundaries, summed after the call has finished.
+hipEvent_t stage_mark(fsi_problem* pb, hipStream_t st) {
+  if (pb->sused >= pb->spool.size()) {
+    hipEvent_t ev = nullptr;
+    if (hipEventCreate(&ev) != hipSuccess) return nullptr;
+    pb->spool.push_back(ev);
+  }
+  hipEvent_t ev = pb->spool[pb->sused++];
+  return hipEventRecord(ev, st) == hipSuccess ? ev : nullptr;
+}
+void stage_span(fsi_problem* pb, int stage, hipEvent_t a, hipEvent_t b) {
+  if (a && b) pb->sev.push_back({stage, a, b});
+}
+
 template <int D, class S>
 fsi_status newton_solve_step(fsi_problem* pb, int B, const StepPar& sp, std::vector<int>& hact, RunStats& rs,
                              hipStream_t st) {
+  FSI_DIM(D);
   Level& F = pb->lev[pb->nlev - 1];
   const int nn = F.nn;
   const int maxit = pb->p.newton_maxit;
   std::vector<double> prev((size_t)B * 3, -1.0), hm((size_t)B * 6), est_prev(B, 1e300);
   std::vector<int> nact(hact);
-  for (int it = 1; it <= maxit; ++it) {
+  // pending[b]: the update test of slice b held after an iteration whose linear solve
+  // converged; the slice is done once the FP64 residual at its new state passes too
+  std::vector<int> pending(B, 0), lin_failed(B, 0), last_lin_failed(B, 0);
+  for (int it = 1; it <= maxit + 1; ++it) {
     // per-slice Krylov tolerance (inexact Newton): the first iteration only has to bring
     // the extrapolated guess close enough for the quadratic phase; later ones are tight
     // while the error estimate is large and loose once it is near the Newton tolerance,
@@ -827,20 +885,66 @@ fsi_status newton_solve_step(fsi_problem* pb, int B, const StepPar& sp, std::vec
                               : std::min(1e-2, std::max(pb->p.lin_rtol, 0.1 * pb->p.newton_rtol / est_prev[b]));
     const int k0 = rs.krylov[0];
     HIPCHK(hipMemcpyAsync(pb->nact, nact.data(), B * sizeof(int), hipMemcpyHostToDevice, st));
+    pb->prof.pact = count_active(nact);
+    hipEvent_t e0 = stage_mark(pb, st);
     CHK(residual<D>(pb, B, sp, pb->U, pb->Uold, pb->Res, pb->nact, st));
+    hipEvent_t e1 = stage_mark(pb, st);
+    stage_span(pb, 0, e0, e1);
+    bool anyp = false;
+    for (int b = 0; b < B; ++b) anyp |= pending[b] != 0;
+    if (anyp) {
+      // residual test of the pending slices: per field, max |D R_f| <= res_rtol max |U_f|,
+      // D the row scaling of the last Jacobian (the refinement test of the mixed path:
+      // the FP64 residual of the FP64 state)
+      k_residual_norms<D><<<dim3(pb->nchunk_n, B), RED_T, 0, st>>>(nn, pb->Res, F.Dsc, pb->U, pb->chunk_n, pb->npart,
+                                                                  pb->nchunk_n, pb->nact);
+      k_max_partials<<<(B + 63) / 64, 64, 0, st>>>(pb->nchunk_n, pb->npart, pb->nmax, B);
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipMemcpyAsync(hm.data(), pb->nmax, (size_t)B * 6 * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      hipEvent_t ec = stage_mark(pb, st);
+      stage_span(pb, 3, e1, ec);
+      e1 = ec;
+      bool left = false;
+      for (int b = 0; b < B; ++b) {
+        if (pending[b]) {
+          bool ok = true;
+          for (int f = 0; f < 3; ++f) {
+            const double r = hm[(size_t)b * 6 + f], un = hm[(size_t)b * 6 + 3 + f];
+            if (!(r <= std::max(pb->p.newton_res_rtol * un, 1e-300))) ok = false;
+          }
+          pending[b] = 0;
+          if (ok) {
+            nact[b] = 0;
+            continue;
+          }
+          if (pb->verbose && b == 0) std::fprintf(stderr, "fsi newton slice 0: residual test failed, iterating on\n");
+        }
+        left |= nact[b] != 0;
+      }
+      if (!left) return FSI_OK;
+      HIPCHK(hipMemcpyAsync(pb->nact, nact.data(), B * sizeof(int), hipMemcpyHostToDevice, st));
+      pb->prof.pact = count_active(nact);
+    }
+    if (it > maxit) break;
     CHK(assemble_levels<D, S, true>(pb, B, sp, pb->nact, st, it == 1 || pb->p.precond_lag == 0));
-    fsi_status ls = fgmres<D, S, true>(pb, B, sp.k, rs.krylov, st);
+    hipEvent_t e2 = stage_mark(pb, st);
+    stage_span(pb, 1, e1, e2);
+    fsi_status ls = fgmres<D, S, true>(pb, B, sp.k, rs.krylov, st, &lin_failed);
     if (ls != FSI_OK && ls != FSI_ERR_LINEAR) return ls;
+    hipEvent_t e3 = stage_mark(pb, st);
+    stage_span(pb, 2, e2, e3);
     k_newton_update<D, S><<<dim3(pb->nchunk_n, B), RED_T, 0, st>>>(nn, pb->U, (const S*)pb->xs, pb->chunk_n, pb->npart,
                                                                  pb->nchunk_n, pb->nact);
     k_max_partials<<<(B + 63) / 64, 64, 0, st>>>(pb->nchunk_n, pb->npart, pb->nmax, B);
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(hm.data(), pb->nmax, (size_t)B * 6 * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    bool any = false;
+    stage_span(pb, 3, e3, stage_mark(pb, st));
     for (int b = 0; b < B; ++b) {
       if (!nact[b]) continue;
       rs.newton[b] += 1;
+      last_lin_failed[b] = lin_failed[b];
       // per field: relative size of the update just applied, and an estimate of
       // the error left after it from the observed contraction (d_k / d_{k-1}) d_k
       double worst = 0.0, est = 0.0;
@@ -862,21 +966,20 @@ fsi_status newton_solve_step(fsi_problem* pb, int B, const StepPar& sp, std::vec
         continue;
       }
       if (pb->verbose && b == 0)
-        std::fprintf(stderr, "fsi newton it %d slice 0: rel(v,u,p) = %.3e %.3e %.3e  est %.3e  krylov %d\n", it,
+        std::fprintf(stderr, "fsi newton it %d slice 0: rel(v,u,p) = %.3e %.3e %.3e  est %.3e  krylov %d%s\n", it,
                      hm[3] > 0 ? hm[0] / hm[3] : hm[0], hm[4] > 0 ? hm[1] / hm[4] : hm[1],
-                     hm[5] > 0 ? hm[2] / hm[5] : hm[2], est, rs.krylov[0] - k0);
+                     hm[5] > 0 ? hm[2] / hm[5] : hm[2], est, rs.krylov[0] - k0, lin_failed[0] ? " (linear solve failed)" : "");
       est_prev[b] = est;
-      if (worst <= pb->p.newton_rtol || est <= pb->p.newton_rtol) {
-        nact[b] = 0;
-      } else {
-        any = true;
-      }
+      // an update from a linear solve that missed its tolerance is never accepted
+      if ((worst <= pb->p.newton_rtol || est <= pb->p.newton_rtol) && !lin_failed[b]) pending[b] = 1;
     }
+    bool any = false;
+    for (int b = 0; b < B; ++b) any |= nact[b] != 0;
     if (!any) return FSI_OK;
   }
   for (int b = 0; b < B; ++b)
     if (nact[b]) {
-      rs.status[b] = FSI_ERR_NEWTON;
+      rs.status[b] = last_lin_failed[b] ? FSI_ERR_LINEAR : FSI_ERR_NEWTON;
       hact[b] = 0;
     }
   return FSI_OK;
@@ -910,6 +1013,8 @@ fsi_status propagate(fsi_problem* pb, int B, const double* t0, double slice_len,
   const double k = slice_len / nsteps;
   const StepPar sp = step_par(pb, k);
   auto t_start = std::chrono::steady_clock::now();
+  pb->sused = 0;
+  pb->sev.clear();
   if (check_input) CHK(check_finite(pb, B, U_in, stats, st));
   HIPCHK(hipMemcpyAsync(pb->U, U_in, (size_t)B * ndof * sizeof(double), hipMemcpyDeviceToDevice, st));
   RunStats rs;
@@ -953,6 +1058,10 @@ fsi_status propagate(fsi_problem* pb, int B, const double* t0, double slice_len,
     }
     stats->newton_total = nt;
     stats->krylov_total = kt;
+    for (const auto& e : pb->sev) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, e.a, e.b) == hipSuccess) stats->stage_ms[e.stage] += ms;
+    }
     stats->stage_ms[4] =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
   }
@@ -1274,6 +1383,7 @@ void fsi_destroy(fsi_problem* pb) {
   if (pb->iev) (void)hipEventDestroy(pb->iev);
   for (void* q : pb->allocs) (void)hipFree(q);
   for (hipEvent_t e : pb->prof.pool) (void)hipEventDestroy(e);
+  for (hipEvent_t e : pb->spool) (void)hipEventDestroy(e);
   delete pb;
 }
 
@@ -1305,10 +1415,11 @@ static fsi_status setup_impl(const fsi_params* prm, fsi_problem** out) {
   // the remaining physical and solver constants: finite, and in the range where
   // the scheme and the solver are defined
   for (double v : {p.rho_f, p.nu_f, p.rho_s, p.mu_s, p.lambda_s, p.inflow_peak, p.ramp_time, p.theta0, p.lps_alpha0,
-                   p.cip_gamma, p.vanka_omega, p.newton_rtol, p.lin_rtol})
+                   p.cip_gamma, p.vanka_omega, p.newton_rtol, p.lin_rtol, p.newton_res_rtol})
     if (!std::isfinite(v)) return FSI_ERR_ARG;
   if (!(p.mu_s > 0) || p.lambda_s < 0 || p.theta0 < 0 || p.lps_alpha0 < 0 || p.cip_gamma < 0 ||
-      !(p.vanka_omega > 0 && p.vanka_omega < 2) || !(p.newton_rtol > 0) || !(p.lin_rtol > 0 && p.lin_rtol < 1))
+      !(p.vanka_omega > 0 && p.vanka_omega < 2) || !(p.newton_rtol > 0) || !(p.lin_rtol > 0 && p.lin_rtol < 1) ||
+      !(p.newton_res_rtol > 0 && p.newton_res_rtol < 1))
     return FSI_ERR_ARG;
   fsi_problem* pb = new (std::nothrow) fsi_problem();
   if (!pb) return FSI_ERR_OOM;

@@ -90,6 +90,9 @@ __global__ void k_trisolve(int R, const double* H, const double* gv, const int* 
 template <int D, class S>
 __global__ void k_newton_update(int nn, double* U, const S* dx, int chunk, double* part, int nchunk,
                                 const int* active);
+template <int D>
+__global__ void k_residual_norms(int nn, const double* R, const double* Dsc, const double* U, int chunk, double* part,
+                                 int nchunk, const int* active);
 __global__ void k_max_partials(int nchunk, const double* part, double* out, int B);
 __global__ void k_nonfinite(size_t n, const double* X, int* flag);
 __global__ void k_extrapolate(size_t n, double* U, const double* Uo, const double* Up, const int* active);

@@ -704,6 +704,43 @@ __global__ void __launch_bounds__(RED_T) k_newton_update(int nn, double* __restr
 }
 
 // max over chunks -> out[b][6]
+// Newton's residual test: per slice b and field f (v, u, p), partial maxima of
+// |Dsc R| (q = f) and of |U| (q = 3 + f) over chunks of nodes -> part[b][q][chunk]
+// (Dsc = row scaling 1 / max_j |J_ij| of the last assembly); non-finite R gives infinity.
+template <int D>
+__global__ void __launch_bounds__(RED_T) k_residual_norms(int nn, const double* __restrict__ R,
+                                                          const double* __restrict__ Dsc,
+                                                          const double* __restrict__ U, int chunk,
+                                                          double* __restrict__ part, int nchunk,
+                                                          const int* __restrict__ active) {
+  FSI_DIM(D);
+  __shared__ double sh[RED_T];
+  const int b = blockIdx.y, ch = blockIdx.x;
+  if (active && !active[b]) return;
+  const int lo = ch * chunk, hi = min(nn, lo + chunk);
+  double m[6] = {0, 0, 0, 0, 0, 0};
+  for (int n = lo + threadIdx.x; n < hi; n += blockDim.x) {
+    const size_t o = ((size_t)b * nn + n) * NC;
+    for (int c = 0; c < NC; ++c) {
+      const double r = Dsc[o + c] * R[o + c];
+      const int f = c < D ? 0 : (c < 2 * D ? 1 : 2);
+      m[f] = isfinite(r) ? fmax(m[f], fabs(r)) : INFINITY;
+      m[3 + f] = fmax(m[3 + f], fabs(U[o + c]));
+    }
+  }
+  for (int q = 0; q < 6; ++q) {
+    const int t = threadIdx.x;
+    sh[t] = m[q];
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+      if (t < s) sh[t] = fmax(sh[t], sh[t + s]);
+      __syncthreads();
+    }
+    if (t == 0) part[((size_t)b * 6 + q) * nchunk + ch] = sh[0];
+    __syncthreads();
+  }
+}
+
 __global__ void k_max_partials(int nchunk, const double* __restrict__ part, double* __restrict__ out, int B) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= B) return;
@@ -831,6 +868,10 @@ template __global__ void k_spmv<2, double, false>(Geom, double, const double*, c
                                                   const double*, double*, const int*, int);
 template __global__ void k_coarse_factor<double, false>(Geom, double, const double*, int, int, double*, double*,
                                                         double*, const int*);
+template __global__ void k_residual_norms<2>(int, const double*, const double*, const double*, int, double*, int,
+                                             const int*);
+template __global__ void k_residual_norms<3>(int, const double*, const double*, const double*, int, double*, int,
+                                             const int*);
 template __global__ void k_change_norms<2>(int, const double*, const double*, int, double*, int);
 template __global__ void k_change_norms<3>(int, const double*, const double*, int, double*, int);
 template __global__ void k_theta_dots<2>(int, const double*, const double*, int, double*, int);

@@ -92,7 +92,8 @@ def test_argument_errors_without_gpu(lib):
                 dict(mu_s=0.0), dict(lambda_s=-1.0), dict(lambda_s=float("nan")), dict(inflow_peak=float("inf")),
                 dict(theta0=-0.5), dict(lps_alpha0=-1.0), dict(cip_gamma=-1e-4), dict(vanka_omega=0.0),
                 dict(vanka_omega=2.0), dict(newton_rtol=0.0), dict(lin_rtol=1.0), dict(rho_s=float("nan")),
-                dict(batch_split=-1), dict(batch_split=5), dict(batch_split=3)):
+                dict(batch_split=-1), dict(batch_split=5), dict(batch_split=3), dict(newton_res_rtol=0.0),
+                dict(newton_res_rtol=1.0), dict(newton_res_rtol=float("nan"))):
         p = fsi.make_params(synth.workload("c1"), max_batch=2)
         for k, v in bad.items():
             setattr(p, k, v)

@@ -168,3 +168,47 @@ def test_concurrent_groups_equal_one_batch(fsi, precision):
     for split in (2, 3):
         assert np.array_equal(res[split][0], res[0][0]), (split, np.abs(res[split][0] - res[0][0]).max())
         assert res[split][1:] == res[0][1:], (split, res[split][1:], res[0][1:])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_linear_failure_is_reported_per_slice(fsi, precision):
+    """With one FGMRES iteration per linear solve no solve reaches its tolerance: Newton must
+    not accept any update from such a solve, so every slice ends with FSI_ERR_LINEAR (the
+    call returns it) instead of a state that only looks converged."""
+    p = synth.workload("c1", seed=3)
+    _say("case: linear failure c1 B=2 gmres_maxit=1", precision)
+    prob = fsi.Problem(fsi.make_params(p, precision=precision, max_batch=2, gmres_maxit=1, newton_maxit=4,
+                                       batch_split=0))
+    U0 = torch.zeros(2, prob.n_nodes, 5, dtype=torch.float64, device="cuda")
+    prob.initial_state(U0[0])
+    prob.initial_state(U0[1])
+    k = p["k_fine"]
+    out = torch.zeros_like(U0)
+    code, st = prob.fine_propagate(2, [0.05, 0.2], 2 * k, 2, U0, out, raise_on_error=False)
+    assert code == fsi.FSI_ERR_LINEAR, code
+    assert [st.slice_status[b] for b in range(2)] == [fsi.FSI_ERR_LINEAR] * 2
+    assert all(st.newton_its[b] == 4 for b in range(2)), [st.newton_its[b] for b in range(2)]
+    prob.close()
+
+
+def test_stage_times_are_reported(fsi):
+    """stats.stage_ms[0..3] (residual, Jacobian and multigrid setup, linear solve, update and
+    tests) are the HIP-event times of the Newton stages: positive, and together not more
+    than the call's wall time; the linear solve dominates."""
+    p = synth.workload("c1", seed=1)
+    _say("case: stage times c1 B=2 m=3")
+    prob = fsi.Problem(fsi.make_params(p, precision="fp64", max_batch=2, batch_split=0))
+    U0 = torch.zeros(2, prob.n_nodes, 5, dtype=torch.float64, device="cuda")
+    prob.initial_state(U0[0])
+    prob.initial_state(U0[1])
+    k = p["k_fine"]
+    out = torch.zeros_like(U0)
+    prob.fine_propagate(2, [0.0, 0.03], 3 * k, 3, U0, out)   # warm-up (graph capture)
+    code, st = prob.fine_propagate(2, [0.0, 0.03], 3 * k, 3, U0, out)
+    ms = [st.stage_ms[i] for i in range(5)]
+    _say("stage ms", ms)
+    assert code == fsi.FSI_OK
+    assert all(m > 0.0 for m in ms[:4]), ms
+    assert sum(ms[:4]) <= 1.05 * ms[4], ms
+    assert ms[2] == max(ms[:4]), ms
+    prob.close()

@@ -329,3 +329,85 @@ def test_pipelined_parareal_equals_plain(fsi, G, theta):
     _say("iterations", s0.parareal_iters, s1.parareal_iters, "ms plain", s0.stage_ms[4], "pipelined", s1.stage_ms[4])
     assert c0 == c1 and s0.parareal_iters == s1.parareal_iters
     assert np.abs(U1 - U0).max() <= 1e-13 * np.abs(U0).max()
+
+
+def test_parareal_tolerance_stop_matches_oracle(fsi):
+    """Parareal with a tolerance (not a fixed count): the GPU must stop after the same iteration
+    as the oracle, whose stopping norm is the largest relative change of v and of u over the
+    slice boundaries, and return the same boundary states (1e-10).  The tolerance is placed
+    between two of the oracle's successive changes (their geometric mean, a factor of more than
+    2 from each, while the two sides' changes agree to about 1e-10)."""
+    p = synth.workload("c1", T=0.1, N=5, dt_fine=0.01, dt_coarse=0.02, seed=2)
+    D = Discretization(p)
+    U0 = np.zeros((D.mesh.n_nodes, 5))
+    hist = []
+    P.parareal(D, p, U0, tol=0.0, max_iter=p["N"], history=hist)
+    changes = [c for _, c in hist]
+    _say("case: parareal tolerance stop c1-small N=5, oracle changes", changes)
+    K = 2   # stop after iteration K: change[K-1] < tol <= change[K-2]
+    assert changes[K - 1] < 0.2 * changes[K - 2]
+    tol = float(np.sqrt(changes[K - 1] * changes[K - 2]))
+    ref, it = P.parareal(D, p, U0, tol=tol, max_iter=p["N"])
+    assert it == K
+    for pipeline in (0, 2):
+        prob = fsi.Problem(fsi.make_params(p, precision="fp64", max_batch=p["N"], parareal_pipeline=pipeline))
+        Ub = torch.zeros(p["N"] + 1, prob.n_nodes, 5, dtype=torch.float64, device="cuda")
+        code, st = prob.parareal_run(p["T"], p["N"], p["m"], p["M"], tol, p["N"], _dev(U0), Ub, raise_on_error=False)
+        assert code == fsi.FSI_OK, code
+        assert st.parareal_iters == K, (pipeline, st.parareal_iters)
+        Ug = _host(Ub)
+        for l in range(1, p["N"] + 1):
+            err = field_rel(Ug[l], ref[l], norm="l2")
+            assert max(err["v"], err["u"]) <= 1e-10, (pipeline, l, err)
+        prob.close()
+
+
+def _c4_golden():
+    import os
+    g = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c4_adjoint.npz"))
+    k = float(g["k"])
+    p = synth.workload("c4", seed=0, T=float(g["T"]), N=int(g["N"]), dt_fine=k)
+    assert p["m"] == int(g["m"]) and p["k_fine"] == k
+    D = Discretization(p)
+    U0 = D.apply_dirichlet(synth.smooth_state(p, int(g["seed"])), 0.0)
+    return g, p, U0
+
+
+def test_adjoint_gradient_c4_mesh_vs_oracle(fsi):
+    """The adjoint on the c4 mesh (128x32 cells, fine step 2^-9), N = 2 slices of 2 steps from a
+    seeded smooth state, against the oracle's adjoint stored in tests/golden/c4_adjoint.npz."""
+    g, p, U0 = _c4_golden()
+    _say("case: adjoint gradient c4 mesh N=2 m=2 vs stored oracle adjoint")
+    prob = fsi.Problem(fsi.make_params(p, precision="fp64", max_batch=p["N"]))
+    Jg, gg, st = prob.adjoint_gradient(p["T"], p["N"], p["m"], _dev(U0))
+    prob.close()
+    Jo, go = float(g["J"]), g["grad"]
+    _say("J", Jg, Jo, "grad", gg, go)
+    assert abs(Jg - Jo) <= 1e-10 * abs(Jo)
+    assert np.all(np.abs(gg - go) <= 1e-9 * np.abs(go)), (gg, go)
+
+
+def test_adjoint_gradient_c4_mesh_vs_gpu_central_differences(fsi):
+    """The GPU adjoint gradient against central differences (h = 1e-6 relative) of the GPU's own
+    forward functional J(q), one parameter at a time, to 1e-5 relative."""
+    g, p, U0 = _c4_golden()
+    _say("case: adjoint gradient c4 mesh vs central differences of the GPU forward solve")
+    Ud = _dev(U0)
+
+    def J_of(**q):
+        d = dict(p)
+        d.update(q)
+        prob = fsi.Problem(fsi.make_params(d, precision="fp64", max_batch=p["N"]))
+        J, grad, _ = prob.adjoint_gradient(p["T"], p["N"], p["m"], Ud)
+        prob.close()
+        return J, grad
+
+    J0, grad = J_of()
+    h = 1e-6
+    for i, q in enumerate(("inflow_peak", "mu_s", "lambda_s")):
+        base = p[q]
+        Jp, _ = J_of(**{q: base * (1 + h)})
+        Jm, _ = J_of(**{q: base * (1 - h)})
+        fd = (Jp - Jm) / (2 * h * base)
+        _say(q, "adjoint", grad[i], "central difference", fd)
+        assert abs(fd - grad[i]) <= 1e-5 * abs(grad[i]), (q, fd, grad[i])

@@ -192,3 +192,29 @@ def test_adjoint_rejects_3d(fsi, c5l1):
     U0 = torch.zeros(1, prob.n_nodes, 7, dtype=torch.float64, device="cuda")
     with pytest.raises(fsi.FsiError):
         prob.adjoint_gradient(0.01, 1, 1, U0[0])
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("mixed", 1e-6)])
+def test_wide_block_variant_vs_golden_3d(fsi, precision, tol):
+    """32 slices in one batch: the finest level's colours then hold (256 cells x 32 slices)
+    >= 8192 cells over the batch, so the fused Vanka pass and the factor run with 32 cells per
+    block (the variant of the 64x16x16-cell workload) instead of 8.  Every slice (the two golden
+    inputs repeated) against the stored oracle steps."""
+    p = synth.workload("c5", seed=0, level=1)
+    _say("case: 3d wide-block variant c5-level1 B=32", precision)
+    prob = fsi.Problem(fsi.make_params(p, precision=precision, max_batch=32, batch_split=0))
+    g = np.load(GOLDEN)
+    U_in, U_ref = g["U_in"], g["U_out"]
+    t0, k, steps = float(g["t0"]), float(g["k"]), int(g["steps"])
+    B = 32
+    Uin = _dev(np.stack([U_in[b % 2] for b in range(B)]))
+    Uout = torch.zeros_like(Uin)
+    code, st = prob.fine_propagate(B, [t0] * B, steps * k, steps, Uin, Uout)
+    Ug = _host(Uout)
+    worst = 0.0
+    for b in range(B):
+        err = field_rel(Ug[b], U_ref[b % 2], norm="l2")
+        worst = max(worst, max(err.values()))
+        assert max(err.values()) <= tol, (b, err)
+    _say("worst", worst, "newton", st.newton_total, "krylov", st.krylov_total)
+    prob.close()
