@@ -96,6 +96,8 @@ def main():
     ap.add_argument("--no-profile-sweep", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the short profiled c3 and c5 sweeps (roofline_c3, roofline_c5)")
+    ap.add_argument("--progress", action="store_true",
+                    help="print a line to stderr after each fine sweep (long profiler runs)")
     ap.add_argument("--cpu-procs", type=int, default=16,
                     help="most host processes of the slice-parallel oracle figure")
     ap.add_argument("--set", action="append", default=[], metavar="KEY=VALUE",
@@ -152,14 +154,21 @@ def main():
         del src, dst
 
     # ---- warmup + timed batched sweeps
-    for _ in range(args.warmup):
+    def say(msg):
+        if args.progress:
+            print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+    say(f"inputs ready ({args.workload}, {N} slices x {m} steps)")
+    for w in range(args.warmup):
         prob.fine_propagate(N, t0s, dl, m, Uin, Uout)
+        say(f"warm-up sweep {w + 1} done")
     torch.cuda.synchronize()
     t_a = time.perf_counter()
     stats = []
-    for _ in range(args.steps):
+    for q in range(args.steps):
         _, st = prob.fine_propagate(N, t0s, dl, m, Uin, Uout)
         stats.append((st.newton_total, st.krylov_total))
+        say(f"timed sweep {q + 1} done")
     torch.cuda.synchronize()
     t_b = time.perf_counter()
     wall = (t_b - t_a) / args.steps

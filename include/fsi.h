@@ -130,6 +130,14 @@ typedef struct {
                                 equation (Section 2.3) at the new state satisfies, per field f,
                                 max |D R_f| <= newton_res_rtol max |U_f|, D the row scaling
                                 1 / max_j |J_ij| of the step Jacobian (0 < newton_res_rtol < 1) */
+  /* launch choices (results do not depend on them; the binding takes them from its
+     autotuner table): */
+  int32_t spmv_slice_fast;   /* SpMV grid with the slices as the fast dimension: 1 yes, 0 no,
+                                -1 the built-in default (yes for 2d FP64) */
+  int32_t vanka_slice_fast;  /* the same for the fused Vanka pass (-1: yes for 3d and 2d FP64) */
+  int32_t vanka_wide_cells;  /* 3d: a level whose colours hold at least this many cells over
+                                the batch runs the fused Vanka pass with 32 cells per block,
+                                others with 8 (0: 8192) */
 } fsi_params;
 
 #define FSI_MAX_SLICES 1024

@@ -113,6 +113,20 @@ struct fsi_problem {
   int *flag = nullptr;
   // device address of the static scratch array on this problem's device (allocation-free residual)
   double* scratch = nullptr;
+  // FGMRES: Arnoldi step j replayed from a captured graph (V-cycle included) per (B, k, type,
+  // layout); a few configurations are kept.  Each step writes the slices' Krylov states to
+  // pinned host memory (one buffer per step parity) and records an event.
+  struct StepGraphs {
+    int B;
+    double k;
+    bool mixed, cj;
+    std::vector<hipGraphExec_t> ex;
+    uint64_t used;
+  };
+  std::vector<StepGraphs> sg;
+  uint64_t sg_clock = 0;
+  int* hst_pin = nullptr;   // [2][Bmax], hipHostMalloc
+  hipEvent_t step_ev[2] = {nullptr, nullptr};
   // FGMRES workspace
   void *V = nullptr, *Z = nullptr, *w = nullptr, *xs = nullptr, *tmp = nullptr;
   double *H = nullptr, *hcol = nullptr, *hcol2 = nullptr, *cs = nullptr, *sn = nullptr, *gv = nullptr,
@@ -517,11 +531,30 @@ fsi_status residual(fsi_problem* pb, int B, const StepPar& sp, const double* U, 
 
 // Cells per block of the fused Vanka pass on a level (and the block width of its
 // Vanka inverse storage): 16 in 2d; in 3d 32 where a colour has cells enough
-// over the batch to fill the GPU with wide blocks, else 8.
+// over the batch to fill the GPU with wide blocks (fsi_params.vanka_wide_cells,
+// 8192 by default), else 8.
 template <int D>
-int vanka_vc(const Geom& g, int B) {
+int vanka_vc(const fsi_problem* pb, const Geom& g, int B) {
   if (D == 2) return 16;
-  return (size_t)(g.ncell / Dm<D>::NCOL) * B >= 8192 ? 32 : 8;
+  const long long th = pb->p.vanka_wide_cells > 0 ? pb->p.vanka_wide_cells : 8192;
+  return (long long)(g.ncell / Dm<D>::NCOL) * B >= th ? 32 : 8;
+}
+
+// Launch order of the SpMV and of the fused Vanka pass: slices as the fast grid
+// dimension (1) or the slow one (0).  fsi_params.spmv_slice_fast /
+// vanka_slice_fast choose; -1 keeps the measured defaults: slices fast for the
+// 2d FP64 SpMV (the 128x32-cell, 32-slice one 4% faster; the 3d 64x16x16 one was
+// 8% slower) and for the 3d and 2d FP64 Vanka passes (the 2d FP32 pass was 6%
+// slower that way).
+template <int D, class S>
+int spmv_slice_fast(const fsi_problem* pb) {
+  const int f = pb->p.spmv_slice_fast;
+  return f >= 0 ? f : ((D == 2 && sizeof(S) == 8) ? 1 : 0);
+}
+template <int D, class S>
+int vanka_slice_fast(const fsi_problem* pb) {
+  const int f = pb->p.vanka_slice_fast;
+  return f >= 0 ? f : ((D == 3 || sizeof(S) == 8) ? 1 : 0);
 }
 
 // Jacobian of the finest level (always) and, when precond is set, the multigrid
@@ -564,7 +597,7 @@ fsi_status assemble_levels(fsi_problem* pb, int B, const StepPar& sp, const int*
     if (l >= 1 || D == 3) {
       k_vanka_factor<D, S, CJ><<<dim3((g.ncell + vf_patches<D>() - 1) / vf_patches<D>(), B),
                                  vf_lanes<D>() * vf_patches<D>(), 0, st>>>(g, sp.k, (const S*)lv.J, (S*)lv.Ainv,
-                                                                          (S*)lv.Yu, vanka_vc<D>(g, B), act);
+                                                                          (S*)lv.Yu, vanka_vc<D>(pb, g, B), act);
     } else {
       const size_t lds_f = (size_t)5 * pb->cbs * pb->cbs * sizeof(double);
       const size_t lds_i = (size_t)3 * pb->cbs * pb->cbs * sizeof(double);
@@ -580,13 +613,11 @@ fsi_status assemble_levels(fsi_problem* pb, int B, const StepPar& sp, const int*
 
 // y = D (b - A x) (or D A x)
 template <int D, class S, bool CJ>
-void spmv(const Geom& g, int B, double k, const S* J, const S* x, const S* b, const double* Dv, S* y, const int* act,
-          hipStream_t st) {
+void spmv(const fsi_problem* pb, const Geom& g, int B, double k, const S* J, const S* x, const S* b, const double* Dv,
+          S* y, const int* act, hipStream_t st) {
   const int nb =
       !jrowtiles<D, S>() ? (g.nn + 63) / 64 : (jntx<D, S>(g, 0) * jrows<D>(g) * jtx<D, S>() + 63) / 64;
-  // slices as the fast grid dimension in 2d FP64 (the 128x32-cell, 32-slice SpMV 4% faster;
-  // the 3d 64x16x16 one was 8% slower)
-  const int sf = (D == 2 && sizeof(S) == 8) && nb <= 65535 ? 1 : 0;
+  const int sf = spmv_slice_fast<D, S>(pb) && nb <= 65535 ? 1 : 0;
   k_spmv<D, S, CJ><<<sf ? dim3(B, nb) : dim3(nb, B), spmv_threads<D>(), 0, st>>>(g, k, J, x, b, Dv, y, act, sf);
 }
 
@@ -607,7 +638,7 @@ void smooth(fsi_problem* pb, int l, int B, double k, int sweeps, bool zero_first
   for (int s = 0; s < sweeps; ++s)
     for (int c = 0; c < NCOL; ++c) {
       const bool zero = zero_first && s == 0 && c == 0;
-      const int vc = vanka_vc<D>(g, B);
+      const int vc = vanka_vc<D>(pb, g, B);
       const int nc = color_info<D>(g, c, vc).nc;
       const double vec = 3.0 * g.nn * NC * sizeof(S);
       // inverse rows per slice; in the split patch solve Y1, Y2 once per launch
@@ -627,7 +658,7 @@ void smooth(fsi_problem* pb, int l, int B, double k, int sweeps, bool zero_first
       // 128x32 cells and 32 slices 4% faster, the 3d one on 64x16x16 cells and 16 slices 13%);
       // the 2d FP32 pass (row tiles, six waves per SIMD) was 6% slower that way.
       const int nbx = (nc + vc - 1) / vc + ncopy;
-      const int sf = (D == 3 || sizeof(S) == 8) && nbx <= 65535 ? 1 : 0;
+      const int sf = vanka_slice_fast<D, S>(pb) && nbx <= 65535 ? 1 : 0;
       const dim3 grid = sf ? dim3(B, nbx) : dim3(nbx, B);
       if constexpr (D == 2) {
         k_vanka_color<D, S, 16, CJ><<<grid, NC * 64, 0, st>>>(g, k, c, om, zero ? 1 : 0, J, Ai, Yu, b, buf[cur],
@@ -663,7 +694,7 @@ void vcycle(fsi_problem* pb, int B, double k, const S* rhs, S* out, const int* a
       const int nb = prof_nb(pb, B);
       const double by = jbytes_launch<D, S, CJ>(g, nb) + (double)nb * 3.0 * g.nn * NC * sizeof(S) + (double)NPST * g.nn * 8.0;
       ProfScope ps(pb, l == L ? F_LEVEL_RES : F_COARSE_LEV, st, by);
-      spmv<D, S, CJ>(g, B, k, (const S*)lv.J, x, b, nullptr, (S*)lv.r_, act, st);
+      spmv<D, S, CJ>(pb, g, B, k, (const S*)lv.J, x, b, nullptr, (S*)lv.r_, act, st);
     }
     k_restrict<D, S><<<grid1(lc.nn, B), TPB, 0, st>>>(lc.geom(), g, (const S*)lv.r_, (S*)lc.b_, act);
   }
@@ -720,6 +751,95 @@ fsi_status vcycle_run(fsi_problem* pb, int B, double k, hipStream_t st) {
 }
 
 // ------------------------------------------------------------ FGMRES
+// Classical Gram-Schmidt twice against V_0..V_j for the new Arnoldi vector a (in
+// pb->tmp), its norm, V_{j+1} = a / |a|, and the Givens update of column j.
+template <int D, class S>
+void arnoldi_tail(fsi_problem* pb, int B, int j, int n, hipStream_t st) {
+  Level& F = pb->lev[pb->nlev - 1];
+  (void)F;
+  const int R = pb->R;
+  const size_t vb = (size_t)(R + 1) * n;
+  S* V = (S*)pb->V;
+  S* a = (S*)pb->tmp;
+  const int chunk = std::max(KDOT_CHUNK, (n + KDOT_BLOCKS * 256 - 1) / (KDOT_BLOCKS * 256) * 256);
+  const int nchunk = (n + chunk - 1) / chunk;
+  const dim3 gb((B + 63) / 64), tb(64);
+  k_multidot<S><<<dim3(nchunk, B), RED_T, 0, st>>>(n, j + 1, a, (size_t)n, V, vb, (size_t)n, chunk, pb->partial,
+                                                     nchunk, pb->gact);
+  k_reduce_partials<<<B, 64, 0, st>>>(j + 1, nchunk, pb->partial, pb->hcol, 64, pb->gact);
+  k_multiaxpy<S><<<grid1(n, B), TPB, 0, st>>>(n, j + 1, a, (size_t)n, V, vb, (size_t)n, pb->hcol, 64, -1.0, pb->gact);
+  k_multidot<S><<<dim3(nchunk, B), RED_T, 0, st>>>(n, j + 1, a, (size_t)n, V, vb, (size_t)n, chunk, pb->partial,
+                                                     nchunk, pb->gact);
+  k_reduce_partials<<<B, 64, 0, st>>>(j + 1, nchunk, pb->partial, pb->hcol2, 64, pb->gact);
+  k_multiaxpy<S><<<grid1(n, B), TPB, 0, st>>>(n, j + 1, a, (size_t)n, V, vb, (size_t)n, pb->hcol2, 64, -1.0, pb->gact);
+  k_multidot<S><<<dim3(nchunk, B), RED_T, 0, st>>>(n, 1, a, (size_t)n, a, (size_t)n, 0, chunk, pb->partial, nchunk,
+                                                     pb->gact);
+  k_reduce_partials<<<B, 64, 0, st>>>(1, nchunk, pb->partial, pb->res, 1, pb->gact);
+  k_cgs_combine<<<gb, tb, 0, st>>>(j, pb->hcol, pb->hcol2, pb->res, pb->gact, B);
+  k_scale<S><<<grid1(n, B), TPB, 0, st>>>(n, a, (size_t)n, V + (size_t)(j + 1) * n, vb, pb->res, 1, 1, pb->gact);
+  k_givens<<<gb, tb, 0, st>>>(j, R, pb->H, pb->hcol, pb->cs, pb->sn, pb->gv, pb->res, pb->beta0, pb->ltol, pb->gstate,
+                              pb->ncol, pb->gact, B);
+}
+
+// Capture Arnoldi step j (Z_j = M^{-1} (V_j / D) with the V-cycle, the product
+// a = D J Z_j, orthogonalisation, Givens update, the slices' new masks, and their
+// states copied to pinned host memory) into one graph.
+template <int D, class S, bool CJ>
+fsi_status capture_step(fsi_problem* pb, int B, double k, int j, hipGraphExec_t* out, hipStream_t st) {
+  FSI_DIM(D);
+  Level& F = pb->lev[pb->nlev - 1];
+  const Geom g = F.geom();
+  const int n = F.nn * NC;
+  const int R = pb->R;
+  const size_t vb = (size_t)(R + 1) * n, zb = (size_t)R * n;
+  S* Vj = (S*)pb->V + (size_t)j * n;
+  S* Zj = (S*)pb->Z + (size_t)j * n;
+  S* w = (S*)pb->w;
+  S* a = (S*)pb->tmp;
+  hipGraph_t graph;
+  HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  k_unscale<S><<<grid1(n, B), TPB, 0, st>>>(n, Vj, vb, F.Dsc, a, pb->gact);
+  vcycle<D, S, CJ>(pb, B, k, (const S*)a, w, pb->gact, st);
+  k_scale<S><<<grid1(n, B), TPB, 0, st>>>(n, w, (size_t)n, Zj, zb, nullptr, 0, 2, pb->gact);
+  spmv<D, S, CJ>(pb, g, B, k, (const S*)F.J, w, nullptr, F.Dsc, a, pb->gact, st);
+  arnoldi_tail<D, S>(pb, B, j, n, st);
+  k_update_gact<<<(B + 63) / 64, 64, 0, st>>>(pb->nact, pb->gstate, pb->gact, B,
+                                              pb->hst_pin + (size_t)(j & 1) * pb->Bmax);
+  const hipError_t e0 = hipGetLastError();
+  const hipError_t e1 = hipStreamEndCapture(st, &graph);
+  if (e0 != hipSuccess || e1 != hipSuccess) return FSI_ERR_HIP;
+  const hipError_t e2 = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  return e2 == hipSuccess ? FSI_OK : FSI_ERR_HIP;
+}
+
+// The step graphs of (B, k, S, CJ): found in the cache, or a new empty entry (graphs
+// are captured when first needed); the least recently used entry makes room.
+template <int D, class S, bool CJ>
+fsi_status step_graphs(fsi_problem* pb, int B, double k, std::vector<hipGraphExec_t>*& ex, hipStream_t st) {
+  constexpr int KEEP = 4;
+  const bool mixed = sizeof(S) == 4;
+  for (auto& e : pb->sg)
+    if (e.B == B && e.k == k && e.mixed == mixed && e.cj == CJ) {
+      e.used = ++pb->sg_clock;
+      ex = &e.ex;
+      return FSI_OK;
+    }
+  if ((int)pb->sg.size() >= KEEP) {
+    auto old = std::min_element(pb->sg.begin(), pb->sg.end(),
+                                [](const fsi_problem::StepGraphs& a, const fsi_problem::StepGraphs& b) {
+                                  return a.used < b.used;
+                                });
+    HIPCHK(hipStreamSynchronize(st));
+    for (hipGraphExec_t x : old->ex)
+      if (x) HIPCHK(hipGraphExecDestroy(x));
+    pb->sg.erase(old);
+  }
+  pb->sg.push_back({B, k, mixed, CJ, std::vector<hipGraphExec_t>(pb->R, nullptr), ++pb->sg_clock});
+  ex = &pb->sg.back().ex;
+  return FSI_OK;
+}
+
 // Solve J dx = -R for the slices with nact[b] = 1 (row-scaled system D J dx = -D R),
 // right-preconditioned FGMRES(R) with classical Gram-Schmidt applied twice; the
 // preconditioner is one multigrid V-cycle.  The solution (type S) goes to pb->xs.
@@ -753,7 +873,7 @@ fsi_status fgmres(fsi_problem* pb, int B, double k, std::vector<int>& kits, hipS
       k_scale_rhs<S><<<grid1(n, B), TPB, 0, st>>>(n, pb->Res, F.Dsc, V, vb, pb->gact);
     } else {
       k_scale_rhs<S><<<grid1(n, B), TPB, 0, st>>>(n, pb->Res, nullptr, tmp, (size_t)n, pb->gact);
-      spmv<D, S, CJ>(g, B, k, (const S*)F.J, xs, tmp, F.Dsc, w, pb->gact, st);
+      spmv<D, S, CJ>(pb, g, B, k, (const S*)F.J, xs, tmp, F.Dsc, w, pb->gact, st);
       k_scale<S><<<grid1(n, B), TPB, 0, st>>>(n, w, (size_t)n, V, vb, nullptr, 0, 2, pb->gact);
     }
     k_multidot<S><<<dim3(nchunk, B), RED_T, 0, st>>>(n, 1, V, vb, V, vb, 0, chunk, pb->partial, nchunk, pb->gact);
@@ -774,6 +894,36 @@ fsi_status fgmres(fsi_problem* pb, int B, double k, std::vector<int>& kits, hipS
       pb->prof.pact = na;
     }
     int jmax = 0;
+    if (pb->use_graphs && !pb->prof.on && pb->hst_pin) {
+      // Arnoldi steps from graphs, one step ahead: step j + 1 is queued before the host
+      // reads the states step j wrote, so the GPU does not wait for the host between
+      // steps.  A step queued after the last slice has converged finds every slice
+      // masked out and changes nothing.
+      std::vector<hipGraphExec_t>* ex = nullptr;
+      CHK(step_graphs<D, S, CJ>(pb, B, k, ex, st));
+      auto launch = [&](int j) -> fsi_status {
+        if (!(*ex)[j]) CHK(capture_step<D, S, CJ>(pb, B, k, j, &(*ex)[j], st));
+        HIPCHK(hipGraphLaunch((*ex)[j], st));
+        HIPCHK(hipEventRecord(pb->step_ev[j & 1], st));
+        return FSI_OK;
+      };
+      CHK(launch(0));
+      for (int j = 0; j < R; ++j) {
+        if (j + 1 < R && total + 1 < pb->p.gmres_maxit) CHK(launch(j + 1));
+        HIPCHK(hipEventSynchronize(pb->step_ev[j & 1]));
+        const int* hs = pb->hst_pin + (size_t)(j & 1) * pb->Bmax;
+        any = false;
+        for (int b = 0; b < B; ++b) {
+          if (hstate[b] == 0) kits[b] += 1;
+          hstate[b] = hs[b];
+          any |= hstate[b] == 0;
+        }
+        ++total;
+        jmax = j + 1;
+        if (!any || total >= pb->p.gmres_maxit) break;
+      }
+      // the look-ahead step (if queued) has run before anything later on the stream
+    } else {
     for (int j = 0; j < R; ++j) {
       S* Vj = V + (size_t)j * n;
       S* Zj = Z + (size_t)j * n;
@@ -786,27 +936,9 @@ fsi_status fgmres(fsi_problem* pb, int B, double k, std::vector<int>& kits, hipS
         const int nb = prof_nb(pb, B);
         ProfScope ps(pb, F_GMRES_SPMV, st,
                      jbytes_launch<D, S, CJ>(g, nb) + (double)nb * (2.0 * n * sizeof(S) + n * 8.0) + (double)NPST * F.nn * 8.0);
-        spmv<D, S, CJ>(g, B, k, (const S*)F.J, w, nullptr, F.Dsc, a, pb->gact, st);
+        spmv<D, S, CJ>(pb, g, B, k, (const S*)F.J, w, nullptr, F.Dsc, a, pb->gact, st);
       }
-      // classical Gram-Schmidt, twice
-      k_multidot<S><<<dim3(nchunk, B), RED_T, 0, st>>>(n, j + 1, a, (size_t)n, V, vb, (size_t)n, chunk, pb->partial,
-                                                         nchunk, pb->gact);
-      k_reduce_partials<<<B, 64, 0, st>>>(j + 1, nchunk, pb->partial, pb->hcol, 64, pb->gact);
-      k_multiaxpy<S><<<grid1(n, B), TPB, 0, st>>>(n, j + 1, a, (size_t)n, V, vb, (size_t)n, pb->hcol, 64, -1.0,
-                                                    pb->gact);
-      k_multidot<S><<<dim3(nchunk, B), RED_T, 0, st>>>(n, j + 1, a, (size_t)n, V, vb, (size_t)n, chunk, pb->partial,
-                                                         nchunk, pb->gact);
-      k_reduce_partials<<<B, 64, 0, st>>>(j + 1, nchunk, pb->partial, pb->hcol2, 64, pb->gact);
-      k_multiaxpy<S><<<grid1(n, B), TPB, 0, st>>>(n, j + 1, a, (size_t)n, V, vb, (size_t)n, pb->hcol2, 64, -1.0,
-                                                    pb->gact);
-      k_multidot<S><<<dim3(nchunk, B), RED_T, 0, st>>>(n, 1, a, (size_t)n, a, (size_t)n, 0, chunk, pb->partial,
-                                                         nchunk, pb->gact);
-      k_reduce_partials<<<B, 64, 0, st>>>(1, nchunk, pb->partial, pb->res, 1, pb->gact);
-      k_cgs_combine<<<gb, tb, 0, st>>>(j, pb->hcol, pb->hcol2, pb->res, pb->gact, B);
-      // V_{j+1} = w / ||w||
-      k_scale<S><<<grid1(n, B), TPB, 0, st>>>(n, a, (size_t)n, V + (size_t)(j + 1) * n, vb, pb->res, 1, 1, pb->gact);
-      k_givens<<<gb, tb, 0, st>>>(j, R, pb->H, pb->hcol, pb->cs, pb->sn, pb->gv, pb->res, pb->beta0, pb->ltol,
-                                  pb->gstate, pb->ncol, pb->gact, B);
+      arnoldi_tail<D, S>(pb, B, j, n, st);
       HIPCHK(hipGetLastError());
       for (int b = 0; b < B; ++b)
         if (hstate[b] == 0) kits[b] += 1;
@@ -823,6 +955,7 @@ fsi_status fgmres(fsi_problem* pb, int B, double k, std::vector<int>& kits, hipS
       }
       pb->prof.pact = na;
       if (!any || total >= pb->p.gmres_maxit) break;
+    }
     }
     // xs += Z y on every slice that ran in this cycle (ncol > 0)
     k_trisolve<<<gb, tb, 0, st>>>(R, pb->H, pb->gv, pb->ncol, pb->ycoef, pb->nact, B);
@@ -1379,6 +1512,13 @@ void fsi_destroy(fsi_problem* pb) {
   for (fsi_problem* q : pb->sub) fsi_destroy(q);
   if (pb->vc_exec) (void)hipGraphExecDestroy(pb->vc_exec);
   if (pb->ist) (void)hipStreamSynchronize(pb->ist);
+  for (auto& e : pb->sg)
+    for (hipGraphExec_t x : e.ex)
+      if (x) (void)hipGraphExecDestroy(x);
+  if (pb->hst_pin) (void)hipHostFree(pb->hst_pin);
+  for (hipEvent_t e : pb->step_ev)
+    if (e) (void)hipEventDestroy(e);
+  if (pb->ist) (void)hipStreamSynchronize(pb->ist);
   if (pb->ist) (void)hipStreamDestroy(pb->ist);
   if (pb->iev) (void)hipEventDestroy(pb->iev);
   for (void* q : pb->allocs) (void)hipFree(q);
@@ -1419,7 +1559,8 @@ static fsi_status setup_impl(const fsi_params* prm, fsi_problem** out) {
     if (!std::isfinite(v)) return FSI_ERR_ARG;
   if (!(p.mu_s > 0) || p.lambda_s < 0 || p.theta0 < 0 || p.lps_alpha0 < 0 || p.cip_gamma < 0 ||
       !(p.vanka_omega > 0 && p.vanka_omega < 2) || !(p.newton_rtol > 0) || !(p.lin_rtol > 0 && p.lin_rtol < 1) ||
-      !(p.newton_res_rtol > 0 && p.newton_res_rtol < 1))
+      !(p.newton_res_rtol > 0 && p.newton_res_rtol < 1) || p.spmv_slice_fast < -1 || p.spmv_slice_fast > 1 ||
+      p.vanka_slice_fast < -1 || p.vanka_slice_fast > 1 || p.vanka_wide_cells < 0)
     return FSI_ERR_ARG;
   fsi_problem* pb = new (std::nothrow) fsi_problem();
   if (!pb) return FSI_ERR_OOM;
@@ -1505,6 +1646,17 @@ static fsi_status setup_impl(const fsi_params* prm, fsi_problem** out) {
   }
   if (hipStreamCreateWithFlags(&pb->ist, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&pb->iev, hipEventDisableTiming) != hipSuccess) {
+    fsi_destroy(pb);
+    return FSI_ERR_HIP;
+  }
+  if (hipHostMalloc((void**)&pb->hst_pin, 2 * (size_t)B * sizeof(int), hipHostMallocCoherent) != hipSuccess) {
+    pb->hst_pin = nullptr;
+    fsi_destroy(pb);
+    return FSI_ERR_OOM;
+  }
+  std::memset(pb->hst_pin, 0, 2 * (size_t)B * sizeof(int));
+  if (hipEventCreateWithFlags(&pb->step_ev[0], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&pb->step_ev[1], hipEventDisableTiming) != hipSuccess) {
     fsi_destroy(pb);
     return FSI_ERR_HIP;
   }
@@ -1978,7 +2130,7 @@ fsi_status debug_apply(fsi_problem* pb, int B, const double* U, const double* Uo
   CHK(assemble_levels<D, S, true>(pb, B, sp, nullptr, st));
   k_convert<double, S><<<1024, TPB, 0, st>>>(B * ndof, X, (S*)pb->tmp);
   if (what == 0)
-    spmv<D, S, true>(F.geom(), B, k, (const S*)F.J, (const S*)pb->tmp, nullptr, nullptr, (S*)pb->w, nullptr, st);
+    spmv<D, S, true>(pb, F.geom(), B, k, (const S*)F.J, (const S*)pb->tmp, nullptr, nullptr, (S*)pb->w, nullptr, st);
   else
     vcycle<D, S, true>(pb, B, k, (const S*)pb->tmp, (S*)pb->w, nullptr, st);
   k_convert<S, double><<<1024, TPB, 0, st>>>(B * ndof, (const S*)pb->w, Y);

@@ -599,12 +599,16 @@ __global__ void k_cgs_combine(int j, double* __restrict__ hcol, const double* __
   hcol[(size_t)b * 64 + j + 1] = hn2[b];
 }
 
-// gact[b] = nact[b] && state[b] == 0
+// gact[b] = nact[b] && state[b] == 0; with hout (pinned host memory) set, also
+// hout[b] = state[b], so the host reads the states once the launch has finished
+// without a separate copy
 __global__ void k_update_gact(const int* __restrict__ nact, const int* __restrict__ state, int* __restrict__ gact,
-                              int B) {
+                              int B, int* hout) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= B) return;
-  gact[b] = (nact[b] && state[b] == 0) ? 1 : 0;
+  const int s = state[b];
+  gact[b] = (nact[b] && s == 0) ? 1 : 0;
+  if (hout) hout[b] = s;
 }
 
 // Arnoldi bookkeeping for column j of every active slice: Hcol = h (j+2 entries,

@@ -41,6 +41,7 @@ class Params(C.Structure):
         ("vanka_sweeps_coarse", C.c_int32), ("precond_lag", C.c_int32),
         ("lin_rtol_first", C.c_double), ("parareal_theta", C.c_int32), ("theta_ref_k", C.c_double),
         ("parareal_pipeline", C.c_int32), ("batch_split", C.c_int32), ("newton_res_rtol", C.c_double),
+        ("spmv_slice_fast", C.c_int32), ("vanka_slice_fast", C.c_int32), ("vanka_wide_cells", C.c_int32),
     ]
 
 
@@ -107,7 +108,8 @@ def _check(code, where):
 SOLVER_DEFAULTS = dict(cip_gamma=1e-4, gmres_restart=30, gmres_maxit=300, newton_maxit=30,
                        vanka_sweeps=2, vanka_omega=0.9, newton_rtol=1e-10, lin_rtol=1e-6,
                        vanka_sweeps_coarse=1, precond_lag=1, lin_rtol_first=1e-3, parareal_theta=0,
-                       theta_ref_k=0.0, parareal_pipeline=0, batch_split=3, newton_res_rtol=1e-10)
+                       theta_ref_k=0.0, parareal_pipeline=0, batch_split=3, newton_res_rtol=1e-10,
+                       spmv_slice_fast=-1, vanka_slice_fast=-1, vanka_wide_cells=0)
 # 3d: the multiplicative 8-colour Vanka sweep is stable only with more damping
 # (a sweep with omega 0.9 amplifies errors at the 64x16x16 level), and the
 # level-0 gradient-jump penalty needs a larger weight for the coarse correction
