@@ -277,7 +277,10 @@ def main():
                                f"{p['level']}-level-refined {'x'.join(str(c) for c in synth.mesh_shape(p))} Q1, "
                                f"{nd} unknowns, {N} slices x {m} steps of {p['k_fine']:.6g}",
                    "slices": N, "steps_per_slice": m, "unknowns": nd, "precision": prec,
-                   "batch_split": int(prob.params.batch_split), "solver_overrides": overrides},
+                   "batch_split": int(prob.params.batch_split),
+                   "launch": {k: int(getattr(prob.params, k)) for k in ("spmv_slice_fast", "vanka_slice_fast",
+                                                                         "vanka_wide_cells")},
+                   "solver_overrides": overrides},
         "newton_per_sweep": stats[-1][0], "krylov_per_sweep": stats[-1][1],
         "sequential": seq,
         "speedup_batched_vs_sequential": (value / seq["value"]) if seq else None,

@@ -117,12 +117,28 @@ SOLVER_DEFAULTS = dict(cip_gamma=1e-4, gmres_restart=30, gmres_maxit=300, newton
 SOLVER_DEFAULTS_3D = dict(vanka_omega=0.6, cip_gamma=3e-4)
 
 
-def make_params(d: dict, precision=None, max_batch=None, **solver) -> Params:
-    """fsi_params from a workload dict (geometry segments, physics, time grid keys)."""
+def tuned_choice(dim, level, precision, max_batch):
+    """Launch choices the autotuner stored for this problem size (autotune.py), or {}."""
+    from . import autotune
+    e = autotune.load_table().get(autotune.table_key(dim, level, precision, max_batch))
+    return dict(e["choice"]) if e else {}
+
+
+def make_params(d: dict, precision=None, max_batch=None, tuned=True, **solver) -> Params:
+    """fsi_params from a workload dict (geometry segments, physics, time grid keys).
+
+    With tuned=True the launch choices the autotuner stored for a problem of this
+    dimension, level, precision and batch size are applied, except those the
+    caller sets explicitly."""
     s = dict(SOLVER_DEFAULTS)
     if d["dim"] == 3:
         s.update(SOLVER_DEFAULTS_3D)
     s.update({k: v for k, v in d.items() if k in SOLVER_DEFAULTS})
+    if tuned:
+        prec_name = "mixed" if (precision if precision is not None else d.get("precision", "fp64")) in \
+            ("mixed", FSI_MIXED) else "fp64"
+        mb = int(max_batch if max_batch is not None else d.get("N", 1))
+        s.update({k: v for k, v in tuned_choice(d["dim"], d["level"], prec_name, mb).items() if k not in solver})
     s.update(solver)
     p = Params()
     p.dim = d["dim"]

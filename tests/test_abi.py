@@ -119,3 +119,24 @@ def test_batch_split_defaults():
     assert fsi.make_params(w, max_batch=1).batch_split == 0
     assert fsi.make_params(w, max_batch=8, batch_split=0).batch_split == 0
     assert fsi.make_params(w, max_batch=8, batch_split=4).batch_split == 4
+
+
+def test_tuned_choices_are_applied(tmp_path, monkeypatch):
+    """make_params applies the autotuner's stored choices for the problem's key, unless the caller
+    sets a choice itself or asks for tuned=False."""
+    import json
+    import synth
+    from paper_1907_01252_amd import autotune, fsi
+    w = synth.workload("c1")
+    key = autotune.table_key(2, w["level"], "fp64", 8)
+    path = tmp_path / "tuned.json"
+    path.write_text(json.dumps({key: {"choice": {"batch_split": 2, "spmv_slice_fast": 0, "vanka_slice_fast": 1}}}))
+    monkeypatch.setattr(autotune, "TABLE", str(path))
+    p = fsi.make_params(w, max_batch=8)
+    assert (p.batch_split, p.spmv_slice_fast, p.vanka_slice_fast) == (2, 0, 1)
+    p = fsi.make_params(w, max_batch=8, spmv_slice_fast=1)
+    assert (p.batch_split, p.spmv_slice_fast) == (2, 1)
+    p = fsi.make_params(w, max_batch=8, tuned=False)
+    assert (p.batch_split, p.spmv_slice_fast, p.vanka_slice_fast) == (3, -1, -1)
+    p = fsi.make_params(w, max_batch=4)   # another key: the table does not apply
+    assert (p.batch_split, p.spmv_slice_fast) == (3, -1)

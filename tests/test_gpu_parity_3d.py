@@ -218,3 +218,24 @@ def test_wide_block_variant_vs_golden_3d(fsi, precision, tol):
         assert max(err.values()) <= tol, (b, err)
     _say("worst", worst, "newton", st.newton_total, "krylov", st.krylov_total)
     prob.close()
+
+
+def test_block_width_choice_does_not_change_results_3d(fsi):
+    """The autotuner's 3d block-width threshold only changes how the fused Vanka pass is launched
+    (8 or 32 cells per block, with the matching inverse storage): the same 32-slice call with
+    both widths gives the same states."""
+    p = synth.workload("c5", seed=0, level=1)
+    _say("case: 3d block width 8 vs 32, c5-level1 B=32 mixed")
+    g = np.load(GOLDEN)
+    t0, k = float(g["t0"]), float(g["k"])
+    Uin = _dev(np.stack([g["U_in"][b % 2] for b in range(32)]))
+    outs = []
+    for wide in (8192, 1 << 30):
+        prob = fsi.Problem(fsi.make_params(p, precision="mixed", max_batch=32, batch_split=0, vanka_wide_cells=wide))
+        o = torch.zeros_like(Uin)
+        prob.fine_propagate(32, [t0] * 32, k, 1, Uin, o)
+        outs.append(_host(o))
+        prob.close()
+    d = np.abs(outs[0] - outs[1]).max() / np.abs(outs[1]).max()
+    _say("max rel diff", d)
+    assert d <= 1e-12, d
