@@ -66,3 +66,45 @@ def lps_matrix(disc) -> sp.csr_matrix:
     S = sp.csr_matrix((SK.ravel(), (rows, cols)), shape=(m.n_nodes, m.n_nodes))
     S.sum_duplicates()
     return S
+
+
+def lps_matrix_q2(disc) -> sp.csr_matrix:
+    """One-level local projection for the Q2 pair (2d):
+
+        s_h(p, xi) = sum over fluid cells K of alpha_K (grad(p - i_h p), grad(xi - i_h xi))_K,
+
+    i_h the bilinear (Q1) interpolation on K from its four vertex values: the Q2
+    functions of a cell against the Q1 ones of the same cell play the part that the
+    Q1 functions of a patch of four cells play against the parent cell's in the Q1
+    case (a Q2 cell carries the nine nodes of such a patch).  alpha_K as there,
+    alpha_K = alpha0 h_K^2 / (rho_f nu_f) with h_K = |K|^(1/2); the 3-point Gauss rule
+    integrates the Q2 Laplace stiffness exactly.  Constant, symmetric, positive
+    semi-definite, zero on the functions that are Q1 on every fluid cell."""
+    m = disc.mesh
+    d = m.dim
+    p = disc.p
+    nloc = m.nloc
+    K = np.einsum("cq,cqar,cqbr->cab", disc.W, disc.G, disc.G)         # Q2 Laplace stiffness [cells, a, b]
+    hK = np.prod(m.h, axis=1) ** (1.0 / d)
+    alpha = p["lps_alpha0"] * hK ** 2 / (p["rho_f"] * p["nu_f"])
+    # kappa = I - i_h on the local nodes: node a at position o/2 gets the bilinear
+    # combination of the four vertex values (vertex = all offsets 0 or 2)
+    kappa = np.eye(nloc)
+    for a in range(nloc):
+        s_ = [((a // 3 ** r) % 3) / 2.0 for r in range(d)]
+        for b in range(nloc):
+            ob = [(b // 3 ** r) % 3 for r in range(d)]
+            if any(o == 1 for o in ob):
+                continue
+            w = 1.0
+            for r in range(d):
+                w *= s_[r] if ob[r] == 2 else 1.0 - s_[r]
+            kappa[a, b] -= w
+    flu = np.nonzero(m.fluid)[0]
+    SK = alpha[flu, None, None] * np.einsum("ap,cab,bq->cpq", kappa, K[flu], kappa)
+    nodes = m.conn[flu]
+    rows = np.broadcast_to(nodes[:, :, None], SK.shape).ravel()
+    cols = np.broadcast_to(nodes[:, None, :], SK.shape).ravel()
+    S = sp.csr_matrix((SK.ravel(), (rows, cols)), shape=(m.n_nodes, m.n_nodes))
+    S.sum_duplicates()
+    return S

@@ -19,9 +19,16 @@ import numpy as np
 
 
 class Mesh:
-    def __init__(self, p: dict, level: int | None = None):
+    """degree 1: Q1 cells with 2^d vertex nodes; degree 2 (Section 2.2's Q2): the same
+    cells with (3)^d nodes each, the vertices plus the edge, face and cell midpoints, so
+    that the nodes of a level-l Q2 mesh are the vertices of the level-(l + 1) mesh.
+    Local node a of a cell sits at offset (digit r of a in base degree + 1) / degree on
+    axis r."""
+
+    def __init__(self, p: dict, level: int | None = None, degree: int = 1):
         self.dim = d = p["dim"]
         self.level = p["level"] if level is None else level
+        self.degree = degree
         axes = []
         for ax in p["segments"][:d]:
             pts = []
@@ -30,15 +37,25 @@ class Mesh:
                 pts.extend(lo + (hi - lo) * np.arange(nl) / nl)
             pts.append(ax[-1][1])
             axes.append(np.asarray(pts, dtype=np.float64))
-        self.axes = axes
+        self.axes = axes                                       # cell vertices per axis
         self.shape = tuple(len(a) - 1 for a in axes)          # cells per axis
-        self.nshape = tuple(n + 1 for n in self.shape)         # nodes per axis
+        if degree == 2:
+            naxes = []
+            for a in axes:
+                na = np.empty(2 * a.size - 1)
+                na[0::2] = a
+                na[1::2] = 0.5 * (a[:-1] + a[1:])
+                naxes.append(na)
+        else:
+            naxes = axes
+        self.naxes = naxes                                     # node coordinates per axis
+        self.nshape = tuple(len(a) for a in naxes)             # nodes per axis
         self.n_nodes = int(np.prod(self.nshape))
         self.n_cells = int(np.prod(self.shape))
-        self.nloc = 2 ** d
+        self.nloc = (degree + 1) ** d
 
         # node coordinates [n_nodes, d]
-        grids = np.meshgrid(*axes, indexing="ij")
+        grids = np.meshgrid(*naxes, indexing="ij")
         self.X = np.stack([g.ravel(order="F") for g in grids], axis=1)
         # node multi-index
         nidx = np.meshgrid(*[np.arange(n) for n in self.nshape], indexing="ij")
@@ -49,8 +66,8 @@ class Mesh:
         self.cell_ijk = np.stack([g.ravel(order="F") for g in cidx], axis=1)
         self.conn = np.zeros((self.n_cells, self.nloc), dtype=np.int64)
         for a in range(self.nloc):
-            off = [(a >> q) & 1 for q in range(d)]
-            self.conn[:, a] = self.node_index(self.cell_ijk + np.asarray(off))
+            off = [(a // (degree + 1) ** q) % (degree + 1) for q in range(d)]
+            self.conn[:, a] = self.node_index(degree * self.cell_ijk + np.asarray(off))
         self.h = np.stack([np.diff(axes[q])[self.cell_ijk[:, q]] for q in range(d)], axis=1)
         self.x0 = np.stack([axes[q][self.cell_ijk[:, q]] for q in range(d)], axis=1)
 

@@ -7,8 +7,9 @@ theta0 k, F = I + grad u, J = det F, the same with ° for the old state, and
 the mean values F̄ = I + (grad u + grad u°)/2, J̄ = (J + J°)/2,
 grad v̄ = (grad v + grad v°)/2 on the step.  (grad v)_{ij} = d_j v_i.
 
-Residual rows, each integrated with the 2-point Gauss rule per direction
-(Section 2.3 time-step equation with the forms of eq. (semiforms)):
+Residual rows, each integrated with the 2-point Gauss rule per direction for
+Q1 cells and the 3-point rule for Q2 cells (Section 2.3 time-step equation
+with the forms of eq. (semiforms)):
 
   momentum, fluid cells   rho_f J̄ ((v - v°) - grad v̄ F̄^{-1} (u - u°)) . phi
                           + k theta     [rho_f J  (grad v  F^{-1}  v ) . phi + J  sigma(v , p; F ) F^{-T}  : grad phi]
@@ -48,7 +49,7 @@ from __future__ import annotations
 import numpy as np
 import scipy.sparse as sp
 
-from .fe import gauss_rule, q1_basis
+from .fe import gauss_rule, q1_basis, q2_basis
 from .mesh import Mesh
 from . import lps as _lps
 
@@ -87,24 +88,33 @@ def ramp(t: float, ramp_time: float) -> float:
 
 
 class Discretization:
-    """Mesh, quadrature, masks and the constant stabilisation of one level."""
+    """Mesh, quadrature, masks and the constant stabilisation of one level.
 
-    def __init__(self, p: dict, level: int | None = None):
+    degree (default p.get("degree", 1)): 1 for Q1 cells (2-point Gauss rule), 2 for
+    the Q2 cells of Section 2.2 (3-point rule, exact for the products of Q2 functions
+    and their gradients on the affine cells), 2d."""
+
+    def __init__(self, p: dict, level: int | None = None, degree: int | None = None):
         self.p = p
-        self.mesh = m = Mesh(p, level)
+        self.degree = deg = p.get("degree", 1) if degree is None else degree
+        if deg not in (1, 2) or (deg == 2 and p["dim"] != 2):
+            raise ValueError("degree 1 (2d, 3d) or 2 (2d)")
+        self.mesh = m = Mesh(p, level, deg)
         self.dim = d = m.dim
         self.nc = 2 * d + 1
-        self.nloc = 2 ** d
-        xq, wq = gauss_rule(d)
-        self.Nq, self.dNq = q1_basis(d, xq)                  # [nq, a], [nq, a, r]
+        self.nloc = m.nloc
+        npts = deg + 1
+        basis = q1_basis if deg == 1 else q2_basis
+        xq, wq = gauss_rule(d, npts)
+        self.Nq, self.dNq = basis(d, xq)                      # [nq, a], [nq, a, r]
         self.wq = wq
         # physical gradients and weights per cell: G [cells, nq, a, r], W [cells, nq]
         self.G = self.dNq[None, :, :, :] / m.h[:, None, None, :]
         self.W = np.prod(m.h, axis=1)[:, None] * wq[None, :]
         # outflow face quadrature: reference points (1, eta[, zeta])
-        xf, wf = gauss_rule(d - 1)
+        xf, wf = gauss_rule(d - 1, npts)
         xf_full = np.concatenate([np.ones((xf.shape[0], 1)), xf], axis=1)
-        self.Nf, dNf = q1_basis(d, xf_full)
+        self.Nf, dNf = basis(d, xf_full)
         oc = m.outflow_cells
         self.Gf = dNf[None, :, :, :] / m.h[oc][:, None, None, :]
         self.Wf = np.prod(m.h[oc][:, 1:], axis=1)[:, None] * wf[None, :]
@@ -121,7 +131,10 @@ class Discretization:
         rows = (m.conn[:, :, None] * self.nc + np.arange(self.nc)[None, None, :]).ravel()
         self.scatter = sp.csr_matrix((np.ones(ne), (rows, np.arange(ne))),
                                      shape=(m.n_nodes * self.nc, ne))
-        self.S = _lps.lps_matrix(self) if m.level >= 1 else None
+        if deg == 2:
+            self.S = _lps.lps_matrix_q2(self)
+        else:
+            self.S = _lps.lps_matrix(self) if m.level >= 1 else None
 
     def theta(self, k):
         """theta = 1/2 + theta0 k (Section 2.3); a fixed theta may be forced.

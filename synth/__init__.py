@@ -120,8 +120,14 @@ def mesh_shape(p: dict) -> tuple[int, ...]:
     return tuple(sum(s[2] for s in ax) * 2 ** p["level"] for ax in p["segments"])
 
 
+def node_level(p: dict) -> int:
+    """Refinement level of the node grid: the cells' level for Q1, one more for Q2
+    (a Q2 cell carries the 3^d nodes of 2^d cells of the next level)."""
+    return p["level"] + (p.get("degree", 1) - 1)
+
+
 def n_nodes(p: dict) -> int:
-    return int(np.prod([n + 1 for n in mesh_shape(p)]))
+    return int(np.prod([sum(s[2] for s in ax) * 2 ** node_level(p) + 1 for ax in p["segments"]]))
 
 
 def n_comp(p: dict) -> int:
@@ -139,12 +145,13 @@ def random_state(p: dict, seed: int, grad_u_max: float = 0.1) -> np.ndarray:
     from numpy import pi
     rng = np.random.default_rng(seed)
     d = p["dim"]
-    shape = mesh_shape(p)
+    lv = node_level(p)
+    shape = tuple(sum(s[2] for s in ax) * 2 ** lv for ax in p["segments"])
     axes = []
     for ax in p["segments"][:d]:
         pts = []
         for (lo, hi, n) in ax:
-            nl = n * 2 ** p["level"]
+            nl = n * 2 ** lv
             pts.extend(lo + (hi - lo) * np.arange(nl) / nl)
         pts.append(ax[-1][1])
         axes.append(np.asarray(pts))
