@@ -138,6 +138,12 @@ typedef struct {
   int32_t vanka_wide_cells;  /* 3d: a level whose colours hold at least this many cells over
                                 the batch runs the fused Vanka pass with 32 cells per block,
                                 others with 8 (0: 8192) */
+  int32_t degree;            /* polynomial degree of the equal-order elements (Section 2.2):
+                                1 (Q1, every mode) or 2 (Q2, the paper's choice; 2d FP64, no
+                                adjoint).  With degree 2 the cells are those of `level` (which
+                                may then be 0) and the nodes those of level + 1 (9 per cell);
+                                the Krylov operator is the Q2 step Jacobian and the
+                                preconditioner the Q1 multigrid V-cycle on the same nodes */
 } fsi_params;
 
 #define FSI_MAX_SLICES 1024

@@ -44,11 +44,11 @@ __device__ inline Dual& operator-=(Dual& a, Dual b) { a.v -= b.v; a.d -= b.d; re
 constexpr double GA = 0.21132486540518711775;  // 1/2 - 1/(2 sqrt 3)
 constexpr double GB = 0.78867513459481288225;  // 1/2 + 1/(2 sqrt 3)
 
-template <int D>
+template <int D, int NLoc = Dm<D>::NL>
 struct Cell {
   double h[D];
   bool solid, outflow;
-  bool urow[Dm<D>::NL];   // fluid cell: harmonic-extension row of local node a is owned here
+  bool urow[NLoc];   // fluid cell: harmonic-extension row of local node a is owned here
 };
 
 // Q1 shape functions and their physical gradients at reference point xi of a
@@ -87,16 +87,16 @@ struct Pt {
 template <class... T>
 using Pr = decltype((T() * ...));
 
-template <int D, class T>
-__device__ inline void eval_point(const T (&U)[Dm<D>::NE], const double (&N)[Dm<D>::NL],
-                                  const double (&G)[Dm<D>::NL][D], Pt<D, T>& f) {
+template <int D, class T, int NLoc = Dm<D>::NL>
+__device__ inline void eval_point(const T (&U)[NLoc * (2 * D + 1)], const double (&N)[NLoc],
+                                  const double (&G)[NLoc][D], Pt<D, T>& f) {
   FSI_DIM(D);
   for (int i = 0; i < D; ++i) {
     f.v[i] = T(0.0); f.u[i] = T(0.0);
     for (int r = 0; r < D; ++r) { f.gv[i][r] = T(0.0); f.gu[i][r] = T(0.0); }
   }
   f.p = T(0.0);
-  for (int a = 0; a < NL; ++a) {
+  for (int a = 0; a < NLoc; ++a) {
     for (int i = 0; i < D; ++i) {
       const T va = U[NC * a + i], ua = U[NC * a + D + i];
       f.v[i] += N[a] * va;
@@ -159,9 +159,9 @@ struct Flux {
 // f, o: new state (field types TV, TD, TP) and old state (TO) at the point; TR
 // the result type.  Every intermediate carries only the types it depends on,
 // so a derivative in one field's direction skips the parts that do not see it.
-template <int D, class TV, class TD, class TP, class TO, class TR>
-__device__ void point_flux(const Cell<D>& c, const StepPar& sp, const Pt<D, TV, TD, TP>& f, const Pt<D, TO>& o,
-                           Flux<D, TR>& fl) {
+template <int D, class TV, class TD, class TP, class TO, class TR, int NLoc>
+__device__ void point_flux(const Cell<D, NLoc>& c, const StepPar& sp, const Pt<D, TV, TD, TP>& f,
+                           const Pt<D, TO>& o, Flux<D, TR>& fl) {
   using TVo = Pr<TV, TO>;
   using TDo = Pr<TD, TO>;
   using TVD = Pr<TV, TD>;
@@ -263,11 +263,11 @@ __device__ void point_flux(const Cell<D>& c, const StepPar& sp, const Pt<D, TV, 
 }
 
 // R[NC a + c] += w (coefficients of fl against the test functions of local node a)
-template <int D, class T>
-__device__ inline void add_flux(const Cell<D>& c, const Flux<D, T>& fl, const double (&N)[Dm<D>::NL],
-                                const double (&G)[Dm<D>::NL][D], double w, T (&R)[Dm<D>::NE]) {
+template <int D, class T, int NLoc>
+__device__ inline void add_flux(const Cell<D, NLoc>& c, const Flux<D, T>& fl, const double (&N)[NLoc],
+                                const double (&G)[NLoc][D], double w, T (&R)[NLoc * (2 * D + 1)]) {
   FSI_DIM(D);
-  for (int a = 0; a < NL; ++a) {
+  for (int a = 0; a < NLoc; ++a) {
     for (int i = 0; i < D; ++i) {
       T s = fl.am[i] * N[a];
       for (int r = 0; r < D; ++r) s += fl.bm[i][r] * G[a][r];
@@ -322,16 +322,16 @@ __device__ inline Dual seeded<Dual>(double val, double der) { return Dual(val, d
 // State at a point in FP64 (value) with the derivative in the direction of
 // local unknown (node bn, component cc): N_bn on that component's value, grad
 // N_bn on its gradient, zero elsewhere.  Only the field of cc is dual-typed.
-template <int D, class TV, class TD, class TP>
-__device__ inline void seed_point(const double (&U)[Dm<D>::NE], const double (&N)[Dm<D>::NL],
-                                  const double (&G)[Dm<D>::NL][D], int bn, int cc, Pt<D, TV, TD, TP>& f) {
+template <int D, class TV, class TD, class TP, int NLoc>
+__device__ inline void seed_point(const double (&U)[NLoc * (2 * D + 1)], const double (&N)[NLoc],
+                                  const double (&G)[NLoc][D], int bn, int cc, Pt<D, TV, TD, TP>& f) {
   FSI_DIM(D);
   Pt<D, double> v;
-  eval_point<D, double>(U, N, G, v);
+  eval_point<D, double, NLoc>(U, N, G, v);
   double Nb = 0.0, Gb[D];
   for (int r = 0; r < D; ++r) Gb[r] = 0.0;
 #pragma unroll
-  for (int a = 0; a < NL; ++a)
+  for (int a = 0; a < NLoc; ++a)
     if (a == bn) {
       Nb = N[a];
       for (int r = 0; r < D; ++r) Gb[r] = G[a][r];
@@ -348,11 +348,11 @@ __device__ inline void seed_point(const double (&U)[Dm<D>::NE], const double (&N
 }
 
 // K[NC a + c] += w (derivatives of the coefficients fl against the test functions)
-template <int D>
-__device__ inline void add_flux_tangent(const Cell<D>& c, const Flux<D, Dual>& fl, const double (&N)[Dm<D>::NL],
-                                        const double (&G)[Dm<D>::NL][D], double w, double (&K)[Dm<D>::NE]) {
+template <int D, int NLoc>
+__device__ inline void add_flux_tangent(const Cell<D, NLoc>& c, const Flux<D, Dual>& fl, const double (&N)[NLoc],
+                                        const double (&G)[NLoc][D], double w, double (&K)[NLoc * (2 * D + 1)]) {
   FSI_DIM(D);
-  for (int a = 0; a < NL; ++a) {
+  for (int a = 0; a < NLoc; ++a) {
     for (int i = 0; i < D; ++i) {
       double s = fl.am[i].d * N[a];
       for (int r = 0; r < D; ++r) s += fl.bm[i][r].d * G[a][r];
@@ -871,6 +871,315 @@ __global__ void __launch_bounds__(256) k_param_sens(Geom g, StepPar sp, const do
   }
   if (threadIdx.x == 0)
     for (int q = 0; q < 3; ++q) out[q] += sh[q][0];
+}
+
+
+// ================================================================ Q2 cells (2d)
+// Biquadratic equal-order elements (Section 2.2, the paper's V_h^(2)): the cells
+// of one level (geometry gc) carry the nine nodes of the next level's node grid
+// (geometry gn): local node a = ox + 3 oy sits at node (2 i + ox, 2 j + oy) of cell
+// (i, j).  The pointwise coefficients are those of the Q1 element (point_flux);
+// basis and quadrature change: Lagrange polynomials on 0, 1/2, 1 per axis and the
+// 3-point Gauss rule per direction (exact for the products of Q2 functions and
+// gradients on these affine cells).
+constexpr int Q2NL = 9, Q2NE = 45;
+constexpr double G3X[3] = {0.11270166537925831148, 0.5, 0.88729833462074168852};   // 1/2 -+ sqrt(15)/10
+constexpr double G3W[3] = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
+
+// Q2 shape functions and physical gradients at reference point xi of a box cell
+__device__ inline void q2_at(const double (&xi)[2], const double (&h)[2], double (&N)[Q2NL], double (&G)[Q2NL][2]) {
+  double L[2][3], dL[2][3];
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const double x = xi[r];
+    L[r][0] = (2.0 * x - 1.0) * (x - 1.0);
+    L[r][1] = 4.0 * x * (1.0 - x);
+    L[r][2] = x * (2.0 * x - 1.0);
+    dL[r][0] = (4.0 * x - 3.0) / h[r];
+    dL[r][1] = (4.0 - 8.0 * x) / h[r];
+    dL[r][2] = (4.0 * x - 1.0) / h[r];
+  }
+#pragma unroll
+  for (int a = 0; a < Q2NL; ++a) {
+    const int ox = a % 3, oy = a / 3;
+    N[a] = L[0][ox] * L[1][oy];
+    G[a][0] = dL[0][ox] * L[1][oy];
+    G[a][1] = L[0][ox] * dL[1][oy];
+  }
+}
+
+struct CellInQ2 {
+  Cell<2, Q2NL> c;
+  int nodes[Q2NL];
+};
+
+__device__ inline CellInQ2 load_cell_q2(const Geom& gc, const Geom& gn, int cell) {
+  CellInQ2 ci;
+  const int i = cell % gc.nx, j = cell / gc.nx;
+  ci.c.h[0] = gc.x[i + 1] - gc.x[i];
+  ci.c.h[1] = gc.y[j + 1] - gc.y[j];
+  ci.c.solid = gc.solid[cell] != 0;
+  ci.c.outflow = (i == gc.nx - 1) && !ci.c.solid;
+  for (int a = 0; a < Q2NL; ++a) {
+    ci.nodes[a] = (2 * i + a % 3) + (gn.nx + 1) * (2 * j + a / 3);
+    ci.c.urow[a] = !(gn.cls[ci.nodes[a]] & CL_NS);
+  }
+  return ci;
+}
+
+// Element residual of one Q2 cell (Dirichlet rows are replaced in the gather).
+template <class TU, class TO, class TR>
+__device__ void elem_residual_q2(const Cell<2, Q2NL>& c, const StepPar& sp, const TU (&U)[Q2NE],
+                                 const TO (&Uo)[Q2NE], TR (&R)[Q2NE]) {
+  constexpr int NC = 5;
+  for (int e = 0; e < Q2NE; ++e) R[e] = TR(0.0);
+  for (int q = 0; q < 9; ++q) {
+    const double xi[2] = {G3X[q % 3], G3X[q / 3]};
+    const double w = G3W[q % 3] * G3W[q / 3] * c.h[0] * c.h[1];
+    double N[Q2NL], G[Q2NL][2];
+    q2_at(xi, c.h, N, G);
+    Pt<2, TU> f;
+    Pt<2, TO> o;
+    eval_point<2, TU, Q2NL>(U, N, G, f);
+    eval_point<2, TO, Q2NL>(Uo, N, G, o);
+    Flux<2, TR> fl;
+    point_flux<2, TU, TU, TU, TO, TR>(c, sp, f, o, fl);
+    add_flux<2, TR>(c, fl, N, G, w, R);
+  }
+  if (c.outflow) {
+    for (int q = 0; q < 3; ++q) {
+      const double xi[2] = {1.0, G3X[q]};
+      const double wf = G3W[q] * c.h[1];
+      double N[Q2NL], G[Q2NL][2];
+      q2_at(xi, c.h, N, G);
+      Pt<2, TU> f;
+      Pt<2, TO> o;
+      eval_point<2, TU, Q2NL>(U, N, G, f);
+      eval_point<2, TO, Q2NL>(Uo, N, G, o);
+      TR bt[2];
+      face_flux<2, TU, TU, TU, TO, TR>(sp, f, o, bt);
+      for (int i = 0; i < 2; ++i)
+        for (int a = 0; a < Q2NL; ++a) R[NC * a + i] -= wf * bt[i] * N[a];
+    }
+  }
+}
+
+// Column (bn, cc) of the Q2 element Jacobian dR/dU^n (all fields dual-typed).
+__device__ inline void jac_column_q2(const Cell<2, Q2NL>& c, const StepPar& sp, const double (&Ue)[Q2NE],
+                                     const double (&Uoe)[Q2NE], int bn, int cc, double (&K)[Q2NE]) {
+  constexpr int NC = 5;
+  for (int e = 0; e < Q2NE; ++e) K[e] = 0.0;
+  for (int q = 0; q < 9; ++q) {
+    const double xi[2] = {G3X[q % 3], G3X[q / 3]};
+    const double w = G3W[q % 3] * G3W[q / 3] * c.h[0] * c.h[1];
+    double N[Q2NL], G[Q2NL][2];
+    q2_at(xi, c.h, N, G);
+    Pt<2, Dual> f;
+    Pt<2, double> o;
+    seed_point<2, Dual, Dual, Dual, Q2NL>(Ue, N, G, bn, cc, f);
+    eval_point<2, double, Q2NL>(Uoe, N, G, o);
+    Flux<2, Dual> fl;
+    point_flux<2, Dual, Dual, Dual, double, Dual>(c, sp, f, o, fl);
+    add_flux_tangent<2, Q2NL>(c, fl, N, G, w, K);
+  }
+  if (c.outflow) {
+    for (int q = 0; q < 3; ++q) {
+      const double xi[2] = {1.0, G3X[q]};
+      const double wf = G3W[q] * c.h[1];
+      double N[Q2NL], G[Q2NL][2];
+      q2_at(xi, c.h, N, G);
+      Pt<2, Dual> f;
+      Pt<2, double> o;
+      seed_point<2, Dual, Dual, Dual, Q2NL>(Ue, N, G, bn, cc, f);
+      eval_point<2, double, Q2NL>(Uoe, N, G, o);
+      Dual bt[2];
+      face_flux<2, Dual, Dual, Dual, double, Dual>(sp, f, o, bt);
+      for (int i = 0; i < 2; ++i)
+        for (int a = 0; a < Q2NL; ++a) K[NC * a + i] -= wf * bt[i].d * N[a];
+    }
+  }
+}
+
+// Re[b][e][cell] of every Q2 cell
+__global__ void k_elem_residual_q2(Geom gc, Geom gn, StepPar sp, const double* __restrict__ U,
+                                   const double* __restrict__ Uo, double* __restrict__ Re,
+                                   const int* __restrict__ active) {
+  constexpr int NC = 5;
+  const int b = blockIdx.y;
+  const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= gc.ncell || (active && !active[b])) return;
+  const CellInQ2 ci = load_cell_q2(gc, gn, cell);
+  const size_t so = (size_t)b * gn.nn * NC;
+  double Ue[Q2NE], Uoe[Q2NE], R[Q2NE];
+  for (int a = 0; a < Q2NL; ++a)
+    for (int c = 0; c < NC; ++c) {
+      Ue[NC * a + c] = U[so + (size_t)ci.nodes[a] * NC + c];
+      Uoe[NC * a + c] = Uo[so + (size_t)ci.nodes[a] * NC + c];
+    }
+  elem_residual_q2<double, double, double>(ci.c, sp, Ue, Uoe, R);
+  double* out = Re + (size_t)b * Q2NE * gc.ncell;
+  for (int e = 0; e < Q2NE; ++e) out[(size_t)e * gc.ncell + cell] = R[e];
+}
+
+// Ke[b][45 row + col][cell]: a block takes Q2_JC cells and Q2_JW groups of them;
+// group w forms the columns w, w + Q2_JW, ...
+constexpr int Q2_JC = 64, Q2_JW = 4;
+__global__ void __launch_bounds__(Q2_JC * Q2_JW) k_elem_jacobian_q2(Geom gc, Geom gn, StepPar sp,
+                                                                   const double* __restrict__ U,
+                                                                   const double* __restrict__ Uo,
+                                                                   double* __restrict__ Ke,
+                                                                   const int* __restrict__ active) {
+  constexpr int NC = 5;
+  const int b = blockIdx.y;
+  const int cell = blockIdx.x * Q2_JC + (int)threadIdx.x % Q2_JC;
+  const int w = (int)threadIdx.x / Q2_JC;
+  if (cell >= gc.ncell || (active && !active[b])) return;
+  const CellInQ2 ci = load_cell_q2(gc, gn, cell);
+  const size_t so = (size_t)b * gn.nn * NC;
+  double Ue[Q2NE], Uoe[Q2NE];
+  for (int a = 0; a < Q2NL; ++a)
+    for (int c = 0; c < NC; ++c) {
+      Ue[NC * a + c] = U[so + (size_t)ci.nodes[a] * NC + c];
+      Uoe[NC * a + c] = Uo[so + (size_t)ci.nodes[a] * NC + c];
+    }
+  double* out = Ke + (size_t)b * Q2NE * Q2NE * gc.ncell;
+  for (int d = w; d < Q2NE; d += Q2_JW) {
+    double K[Q2NE];
+    jac_column_q2(ci.c, sp, Ue, Uoe, d / NC, d % NC, K);
+    for (int e = 0; e < Q2NE; ++e) out[(size_t)(Q2NE * e + d) * gc.ncell + cell] = K[e];
+  }
+}
+
+// The Q2 cells containing node coordinate I of an axis with nc cells: cell index and
+// local offset (0, 1, 2) of the node in it; returns their number (1 or 2).
+__device__ inline int q2_cells_of(int I, int nc, int (&cell)[2], int (&off)[2]) {
+  if (I & 1) {
+    cell[0] = I >> 1;
+    off[0] = 1;
+    return 1;
+  }
+  int n = 0;
+  if (I / 2 - 1 >= 0) { cell[n] = I / 2 - 1; off[n] = 2; ++n; }
+  if (I / 2 < nc) { cell[n] = I / 2; off[n] = 0; ++n; }
+  return n;
+}
+
+// Sum the Q2 element residuals of the cells around each node, add k S2 p (the Q2
+// pressure stabilisation, 5 x 5 node stencil pst2), replace the Dirichlet rows by U - g(t).
+__global__ void k_gather_residual_q2(Geom gc, Geom gn, StepPar sp, const double* __restrict__ pst2,
+                                     const double* __restrict__ Re, const double* __restrict__ U,
+                                     const double* __restrict__ t, double* __restrict__ R,
+                                     const int* __restrict__ active) {
+  constexpr int NC = 5;
+  const int b = blockIdx.y;
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= gn.nn || (active && !active[b])) return;
+  const int I = n % (gn.nx + 1), Jn = n / (gn.nx + 1);
+  int cxs[2], oxs[2], cys[2], oys[2];
+  const int ncx = q2_cells_of(I, gc.nx, cxs, oxs), ncy = q2_cells_of(Jn, gc.ny, cys, oys);
+  const double* re = Re + (size_t)b * Q2NE * gc.ncell;
+  double r[NC] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int qy = 0; qy < ncy; ++qy)
+    for (int qx = 0; qx < ncx; ++qx) {
+      const int cell = cxs[qx] + gc.nx * cys[qy], a = oxs[qx] + 3 * oys[qy];
+      for (int c = 0; c < NC; ++c) r[c] += re[(size_t)(NC * a + c) * gc.ncell + cell];
+    }
+  const double* u = U + (size_t)b * gn.nn * NC;
+  double sp_ = 0.0;
+  for (int q = 0; q < 25; ++q) {
+    const int ii = I + q % 5 - 2, jj = Jn + q / 5 - 2;
+    if (ii < 0 || jj < 0 || ii > gn.nx || jj > gn.ny) continue;
+    sp_ += pst2[(size_t)q * gn.nn + n] * u[(size_t)(ii + (gn.nx + 1) * jj) * NC + 4];
+  }
+  r[4] += sp.k * sp_;
+  const uint8_t m = gn.dmask[n];
+  double* out = R + ((size_t)b * gn.nn + n) * NC;
+  for (int c = 0; c < NC; ++c)
+    out[c] = (m & (1u << c)) ? u[(size_t)n * NC + c] - dirichlet_value<2>(gn, sp, n, c, t[b]) : r[c];
+}
+
+// Gather the Q2 element matrices into the 5 x 5 node stencil of full 5 x 5 blocks,
+// J2[b][25 slot + 5 r + c][node] (slot (dx + 2) + 5 (dy + 2)); Dirichlet rows become
+// identity rows; Dsc[b][node][r] = 1 / max_j |J_rj| (with k S2 on pressure rows).
+__global__ void k_gather_jacobian_q2(Geom gc, Geom gn, double k, const double* __restrict__ pst2,
+                                     const double* __restrict__ Ke, double* __restrict__ J2,
+                                     double* __restrict__ Dsc, const int* __restrict__ active) {
+  constexpr int NC = 5;
+  const int b = blockIdx.y;
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= gn.nn || (active && !active[b])) return;
+  const int I = n % (gn.nx + 1), Jn = n / (gn.nx + 1);
+  int cxs[2], oxs[2], cys[2], oys[2];
+  const int ncx = q2_cells_of(I, gc.nx, cxs, oxs), ncy = q2_cells_of(Jn, gc.ny, cys, oys);
+  const double* ke = Ke + (size_t)b * Q2NE * Q2NE * gc.ncell;
+  double* jb = J2 + (size_t)b * 625 * gn.nn + n;
+  const uint8_t m = gn.dmask[n];
+  double rmax[NC] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int s = 0; s < 25; ++s) {
+    const int dx = s % 5 - 2, dy = s / 5 - 2;
+    double blk[25];
+    for (int e = 0; e < 25; ++e) blk[e] = 0.0;
+    for (int qy = 0; qy < ncy; ++qy) {
+      const int by = oys[qy] + dy;
+      if (by < 0 || by > 2) continue;
+      for (int qx = 0; qx < ncx; ++qx) {
+        const int bx = oxs[qx] + dx;
+        if (bx < 0 || bx > 2) continue;
+        const int cell = cxs[qx] + gc.nx * cys[qy], a = oxs[qx] + 3 * oys[qy], bl = bx + 3 * by;
+        for (int r = 0; r < NC; ++r)
+          for (int c = 0; c < NC; ++c)
+            blk[NC * r + c] += ke[(size_t)(Q2NE * (NC * a + r) + NC * bl + c) * gc.ncell + cell];
+      }
+    }
+    for (int r = 0; r < NC; ++r) {
+      if (m & (1u << r))
+        for (int c = 0; c < NC; ++c) blk[NC * r + c] = (s == 12 && c == r) ? 1.0 : 0.0;
+      for (int c = 0; c < NC; ++c) rmax[r] = fmax(rmax[r], fabs(blk[NC * r + c]));
+    }
+    for (int e = 0; e < 25; ++e) jb[(size_t)(25 * s + e) * gn.nn] = blk[e];
+  }
+  if (!(m & dm_p<2>())) {
+    double pm = 0.0;
+    for (int q = 0; q < 25; ++q) pm = fmax(pm, fabs(k * pst2[(size_t)q * gn.nn + n]));
+    rmax[4] = fmax(rmax[4], pm);
+  }
+  if (!Dsc) return;
+  double* d = Dsc + ((size_t)b * gn.nn + n) * NC;
+  for (int r = 0; r < NC; ++r) d[r] = rmax[r] > 0.0 ? 1.0 / rmax[r] : 1.0;
+}
+
+// Product with the Q2 Jacobian, y = D (bv - J2 x) (or D J2 x without bv; D = 1 without
+// Dsc), the stabilisation k S2 included on the pressure rows.  One thread per node;
+// a neighbour slot outside the mesh reads the node itself (J2 and pst2 hold zeros there).
+__global__ void k_spmv_q2(Geom gn, double k, const double* __restrict__ pst2, const double* __restrict__ J2,
+                          const double* __restrict__ x, const double* __restrict__ bv,
+                          const double* __restrict__ Dsc, double* __restrict__ y,
+                          const int* __restrict__ active) {
+  constexpr int NC = 5;
+  const int b = blockIdx.y;
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= gn.nn || (active && !active[b])) return;
+  const int I = n % (gn.nx + 1), Jn = n / (gn.nx + 1);
+  const double* jb = J2 + (size_t)b * 625 * gn.nn + n;
+  const double* xb = x + (size_t)b * gn.nn * NC;
+  double acc[NC] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int s = 0; s < 25; ++s) {
+    const int ii = I + s % 5 - 2, jj = Jn + s / 5 - 2;
+    const int nb = (ii < 0 || jj < 0 || ii > gn.nx || jj > gn.ny) ? n : ii + (gn.nx + 1) * jj;
+    double xn[NC];
+    for (int c = 0; c < NC; ++c) xn[c] = xb[(size_t)nb * NC + c];
+    for (int r = 0; r < NC; ++r) {
+      double a = acc[r];
+      for (int c = 0; c < NC; ++c) a = fma(jb[(size_t)(25 * s + NC * r + c) * gn.nn], xn[c], a);
+      acc[r] = a;
+    }
+    acc[4] = fma(k * pst2[(size_t)s * gn.nn + n], xn[4], acc[4]);
+  }
+  const size_t o = ((size_t)b * gn.nn + n) * NC;
+  for (int r = 0; r < NC; ++r) {
+    const double v = bv ? bv[o + r] - acc[r] : acc[r];
+    y[o + r] = Dsc ? Dsc[o + r] * v : v;
+  }
 }
 
 #define FSI_INST_ASM(D)                                                                                           \

@@ -113,6 +113,10 @@ struct fsi_problem {
   int *flag = nullptr;
   // device address of the static scratch array on this problem's device (allocation-free residual)
   double* scratch = nullptr;
+  // Q2 cells (degree 2, 2d FP64): the cells are those of level nlev - 2, the nodes those of
+  // the finest level; the Q1 hierarchy on the same nodes is the preconditioner
+  int deg = 1;
+  double *pst2 = nullptr, *J2 = nullptr, *Ke2 = nullptr, *Re2 = nullptr;
   // FGMRES: Arnoldi step j replayed from a captured graph (V-cycle included) per (B, k, type,
   // layout); a few configurations are kept.  Each step writes the slices' Krylov states to
   // pinned host memory (one buffer per step parity) and records an event.
@@ -463,6 +467,58 @@ fsi_status build_level(fsi_problem* pb, int l) {
   return FSI_OK;
 }
 
+// Pressure stabilisation of Q2 cells (one-level local projection): over every fluid
+// Q2 cell K, alpha_K (grad(p - i_h p), grad(q - i_h q))_K with i_h the bilinear
+// interpolation on K from its vertices, alpha_K = alpha0 |K| / (rho_f nu_f); the Q2
+// Laplace stiffness of the box cell is the tensor form of the 1d quadratic element
+// matrices (mass h/30 [4 2 -1; 2 16 2; -1 2 4], stiffness 1/(3h) [7 -8 1; -8 16 -8;
+// 1 -8 7]).  Returned as the 5 x 5 node stencil [25][nn] of the node grid N (the cells'
+// nodes: local node a = ox + 3 oy of cell (i, j) is node (2 i + ox, 2 j + oy)).
+std::vector<double> q2_lps_stencil(const Level& C, const Level& N, const fsi_params& p) {
+  std::vector<double> pst((size_t)25 * N.nn, 0.0);
+  const int W = N.nx + 1;
+  for (int j = 0; j < C.ny; ++j)
+    for (int i = 0; i < C.nx; ++i) {
+      if (C.solid[i + C.nx * j]) continue;
+      const double hx = C.x[i + 1] - C.x[i], hy = C.y[j + 1] - C.y[j];
+      double M[2][3][3], Ks[2][3][3];
+      const double Mr[3][3] = {{4, 2, -1}, {2, 16, 2}, {-1, 2, 4}}, Kr[3][3] = {{7, -8, 1}, {-8, 16, -8}, {1, -8, 7}};
+      const double hh[2] = {hx, hy};
+      for (int r = 0; r < 2; ++r)
+        for (int a = 0; a < 3; ++a)
+          for (int b = 0; b < 3; ++b) {
+            M[r][a][b] = Mr[a][b] * hh[r] / 30.0;
+            Ks[r][a][b] = Kr[a][b] / (3.0 * hh[r]);
+          }
+      double K[9][9], kap[9][9];
+      for (int a = 0; a < 9; ++a)
+        for (int b = 0; b < 9; ++b)
+          K[a][b] = Ks[0][a % 3][b % 3] * M[1][a / 3][b / 3] + M[0][a % 3][b % 3] * Ks[1][a / 3][b / 3];
+      // kap = I - i_h: node a at (ox/2, oy/2) minus the bilinear combination of the vertex values
+      for (int a = 0; a < 9; ++a) {
+        const double sx = (a % 3) * 0.5, sy = (a / 3) * 0.5;
+        for (int b = 0; b < 9; ++b) {
+          double v = a == b ? 1.0 : 0.0;
+          const int bx = b % 3, by = b / 3;
+          if (bx != 1 && by != 1) v -= (bx == 2 ? sx : 1.0 - sx) * (by == 2 ? sy : 1.0 - sy);
+          kap[a][b] = v;
+        }
+      }
+      const double alpha = p.lps_alpha0 * hx * hy / (p.rho_f * p.nu_f);
+      for (int q = 0; q < 9; ++q)
+        for (int r = 0; r < 9; ++r) {
+          double v = 0.0;
+          for (int a = 0; a < 9; ++a)
+            for (int b = 0; b < 9; ++b) v += kap[a][q] * K[a][b] * kap[b][r];
+          if (v == 0.0) continue;
+          const int nq = (2 * i + q % 3) + W * (2 * j + q / 3);
+          const int slot = (r % 3 - q % 3 + 2) + 5 * (r / 3 - q / 3 + 2);
+          pst[(size_t)slot * N.nn + nq] += alpha * v;
+        }
+    }
+  return pst;
+}
+
 // ------------------------------------------------------------ profiling
 void prof_rec(fsi_problem* pb, hipEvent_t* e, hipStream_t st) {
   Prof& P = pb->prof;
@@ -520,6 +576,16 @@ fsi_status residual(fsi_problem* pb, int B, const StepPar& sp, const double* U, 
   FSI_DIM(D);
   Level& F = pb->lev[pb->nlev - 1];
   const Geom g = F.geom();
+  if constexpr (D == 2) {
+    if (pb->deg == 2) {
+      const Geom gc = pb->lev[pb->nlev - 2].geom();
+      ProfScope ps(pb, F_RES, st, (double)prof_nb(pb, B) * (F.nn * NC * 8.0 * 3 + gc.ncell * 45 * 8.0 * 2));
+      k_elem_residual_q2<<<grid1(gc.ncell, B), TPB, 0, st>>>(gc, g, sp, U, Uo, pb->Re2, act);
+      k_gather_residual_q2<<<grid1(g.nn, B), TPB, 0, st>>>(gc, g, sp, pb->pst2, pb->Re2, U, pb->tdev, R, act);
+      HIPCHK(hipGetLastError());
+      return FSI_OK;
+    }
+  }
   {
     ProfScope ps(pb, F_RES, st, (double)prof_nb(pb, B) * (F.nn * NC * 8.0 * 3 + F.ncell * NE * 8.0 * 2));
     k_elem_residual<D><<<grid1(g.ncell, B), TPB, 0, st>>>(g, sp, U, Uo, pb->Re, act);
@@ -568,7 +634,9 @@ fsi_status assemble_levels(fsi_problem* pb, int B, const StepPar& sp, const int*
   FSI_DIM(D);
   if (CJ && transpose) return FSI_ERR_ARG;   // a transposed block needs the full layout
   const int L = pb->nlev - 1;
-  for (int l = L; l >= (precond ? 0 : L); --l) {
+  // Q2: the Q1 hierarchy is only the preconditioner, so without precond nothing of it is rebuilt
+  const int lstop = precond ? 0 : (pb->deg == 2 ? L + 1 : L);
+  for (int l = L; l >= lstop; --l) {
     Level& lv = pb->lev[l];
     const Geom g = lv.geom();
     const double* U = (l == L) ? pb->U : lv.U;
@@ -608,6 +676,20 @@ fsi_status assemble_levels(fsi_problem* pb, int B, const StepPar& sp, const int*
     }
     HIPCHK(hipGetLastError());
   }
+  if constexpr (D == 2) {
+    if (pb->deg == 2) {
+      // the Krylov operator: the exact Jacobian of the Q2 step (and its row scaling)
+      const Level& F = pb->lev[L];
+      const Geom gc = pb->lev[L - 1].geom(), gn = F.geom();
+      {
+        ProfScope ps(pb, F_JAC, st, (double)prof_nb(pb, B) * (gc.ncell * 45.0 * 45.0 * 8.0 + 2.0 * gn.nn * NC * 8));
+        k_elem_jacobian_q2<<<dim3((gc.ncell + Q2_JAC_CELLS - 1) / Q2_JAC_CELLS, B), Q2_JAC_THREADS, 0, st>>>(
+            gc, gn, sp, pb->U, pb->Uold, pb->Ke2, act);
+      }
+      k_gather_jacobian_q2<<<grid1(gn.nn, B), TPB, 0, st>>>(gc, gn, sp.k, pb->pst2, pb->Ke2, pb->J2, F.Dsc, act);
+      HIPCHK(hipGetLastError());
+    }
+  }
   return FSI_OK;
 }
 
@@ -619,6 +701,22 @@ void spmv(const fsi_problem* pb, const Geom& g, int B, double k, const S* J, con
       !jrowtiles<D, S>() ? (g.nn + 63) / 64 : (jntx<D, S>(g, 0) * jrows<D>(g) * jtx<D, S>() + 63) / 64;
   const int sf = spmv_slice_fast<D, S>(pb) && nb <= 65535 ? 1 : 0;
   k_spmv<D, S, CJ><<<sf ? dim3(B, nb) : dim3(nb, B), spmv_threads<D>(), 0, st>>>(g, k, J, x, b, Dv, y, act, sf);
+}
+
+// The Krylov operator's product y = D (b - J x) (or D J x): the Q1 step Jacobian of the
+// finest level, or with Q2 cells their Jacobian (FP64).
+template <int D, class S, bool CJ>
+void krylov_spmv(const fsi_problem* pb, int B, double k, const S* x, const S* b, const double* Dv, S* y,
+                 const int* act, hipStream_t st) {
+  const Level& F = pb->lev[pb->nlev - 1];
+  if constexpr (D == 2 && sizeof(S) == 8 && CJ) {
+    if (pb->deg == 2) {
+      k_spmv_q2<<<grid1(F.nn, B), TPB, 0, st>>>(F.geom(), k, pb->pst2, pb->J2, (const double*)x, (const double*)b, Dv,
+                                               (double*)y, act);
+      return;
+    }
+  }
+  spmv<D, S, CJ>(pb, F.geom(), B, k, (const S*)F.J, x, b, Dv, y, act, st);
 }
 
 // ------------------------------------------------------------ multigrid
@@ -801,7 +899,7 @@ fsi_status capture_step(fsi_problem* pb, int B, double k, int j, hipGraphExec_t*
   k_unscale<S><<<grid1(n, B), TPB, 0, st>>>(n, Vj, vb, F.Dsc, a, pb->gact);
   vcycle<D, S, CJ>(pb, B, k, (const S*)a, w, pb->gact, st);
   k_scale<S><<<grid1(n, B), TPB, 0, st>>>(n, w, (size_t)n, Zj, zb, nullptr, 0, 2, pb->gact);
-  spmv<D, S, CJ>(pb, g, B, k, (const S*)F.J, w, nullptr, F.Dsc, a, pb->gact, st);
+  krylov_spmv<D, S, CJ>(pb, B, k, w, nullptr, F.Dsc, a, pb->gact, st);
   arnoldi_tail<D, S>(pb, B, j, n, st);
   k_update_gact<<<(B + 63) / 64, 64, 0, st>>>(pb->nact, pb->gstate, pb->gact, B,
                                               pb->hst_pin + (size_t)(j & 1) * pb->Bmax);
@@ -873,7 +971,7 @@ fsi_status fgmres(fsi_problem* pb, int B, double k, std::vector<int>& kits, hipS
       k_scale_rhs<S><<<grid1(n, B), TPB, 0, st>>>(n, pb->Res, F.Dsc, V, vb, pb->gact);
     } else {
       k_scale_rhs<S><<<grid1(n, B), TPB, 0, st>>>(n, pb->Res, nullptr, tmp, (size_t)n, pb->gact);
-      spmv<D, S, CJ>(pb, g, B, k, (const S*)F.J, xs, tmp, F.Dsc, w, pb->gact, st);
+      krylov_spmv<D, S, CJ>(pb, B, k, xs, tmp, F.Dsc, w, pb->gact, st);
       k_scale<S><<<grid1(n, B), TPB, 0, st>>>(n, w, (size_t)n, V, vb, nullptr, 0, 2, pb->gact);
     }
     k_multidot<S><<<dim3(nchunk, B), RED_T, 0, st>>>(n, 1, V, vb, V, vb, 0, chunk, pb->partial, nchunk, pb->gact);
@@ -934,9 +1032,9 @@ fsi_status fgmres(fsi_problem* pb, int B, double k, std::vector<int>& kits, hipS
       S* a = tmp;
       {
         const int nb = prof_nb(pb, B);
-        ProfScope ps(pb, F_GMRES_SPMV, st,
-                     jbytes_launch<D, S, CJ>(g, nb) + (double)nb * (2.0 * n * sizeof(S) + n * 8.0) + (double)NPST * F.nn * 8.0);
-        spmv<D, S, CJ>(pb, g, B, k, (const S*)F.J, w, nullptr, F.Dsc, a, pb->gact, st);
+        const double jb = pb->deg == 2 ? (double)nb * 625.0 * F.nn * 8.0 + 25.0 * F.nn * 8.0 : jbytes_launch<D, S, CJ>(g, nb);
+        ProfScope ps(pb, F_GMRES_SPMV, st, jb + (double)nb * (2.0 * n * sizeof(S) + n * 8.0) + (double)NPST * F.nn * 8.0);
+        krylov_spmv<D, S, CJ>(pb, B, k, w, nullptr, F.Dsc, a, pb->gact, st);
       }
       arnoldi_tail<D, S>(pb, B, j, n, st);
       HIPCHK(hipGetLastError());
@@ -1537,7 +1635,7 @@ static fsi_status setup_impl(const fsi_params* prm, fsi_problem** out) {
   if (!prm || !out) return FSI_ERR_ARG;
   *out = nullptr;
   const fsi_params& p = *prm;
-  if ((p.dim != 2 && p.dim != 3) || p.level < 1 || p.level > MAXLEV - 2 || p.max_batch < 1 ||
+  if ((p.dim != 2 && p.dim != 3) || p.level < (p.degree == 2 ? 0 : 1) || p.level > MAXLEV - 2 || p.max_batch < 1 ||
       p.max_batch > FSI_MAX_SLICES ||
       p.gmres_restart < 1 || p.gmres_restart > 63 || p.newton_maxit < 1 || p.vanka_sweeps < 1 ||
       p.vanka_sweeps_coarse < 1 ||
@@ -1560,7 +1658,9 @@ static fsi_status setup_impl(const fsi_params* prm, fsi_problem** out) {
   if (!(p.mu_s > 0) || p.lambda_s < 0 || p.theta0 < 0 || p.lps_alpha0 < 0 || p.cip_gamma < 0 ||
       !(p.vanka_omega > 0 && p.vanka_omega < 2) || !(p.newton_rtol > 0) || !(p.lin_rtol > 0 && p.lin_rtol < 1) ||
       !(p.newton_res_rtol > 0 && p.newton_res_rtol < 1) || p.spmv_slice_fast < -1 || p.spmv_slice_fast > 1 ||
-      p.vanka_slice_fast < -1 || p.vanka_slice_fast > 1 || p.vanka_wide_cells < 0)
+      p.vanka_slice_fast < -1 || p.vanka_slice_fast > 1 || p.vanka_wide_cells < 0 ||
+      (p.degree != 1 && p.degree != 2) ||
+      (p.degree == 2 && (p.dim != 2 || p.precision != FSI_FP64 || p.level + 2 > MAXLEV - 1)))
     return FSI_ERR_ARG;
   fsi_problem* pb = new (std::nothrow) fsi_problem();
   if (!pb) return FSI_ERR_OOM;
@@ -1569,7 +1669,8 @@ static fsi_status setup_impl(const fsi_params* prm, fsi_problem** out) {
   pb->mixed = p.precision == FSI_MIXED;
   pb->ssz = pb->mixed ? sizeof(float) : sizeof(double);
   pb->R = p.gmres_restart;
-  pb->nlev = p.level + 1;
+  pb->deg = p.degree;
+  pb->nlev = p.level + 1 + (p.degree - 1);   // Q2: the Q1 hierarchy reaches the Q2 node grid
   {
     // FSI_GRAPHS=0 replays nothing from graphs (every kernel launched directly)
     const char* e = std::getenv("FSI_GRAPHS");
@@ -1634,6 +1735,13 @@ static fsi_status setup_impl(const fsi_params* prm, fsi_problem** out) {
   A_(dalloc_bytes(pb, &pb->cAinv, direct ? (size_t)B * C.nn * NC * C.nn * NC * ss : 1));
   A_(dalloc(pb, &pb->npart, (size_t)B * 6 * pb->nchunk_n));
   A_(dalloc(pb, &pb->nmax, (size_t)B * 6));
+  if (pb->deg == 2) {
+    const Level& Cq = pb->lev[pb->nlev - 2];   // the Q2 cells
+    A_(upload(pb, &pb->pst2, q2_lps_stencil(Cq, F, p)));
+    A_(dalloc(pb, &pb->J2, (size_t)B * 625 * F.nn));
+    A_(dalloc(pb, &pb->Ke2, (size_t)B * 45 * 45 * Cq.ncell));
+    A_(dalloc(pb, &pb->Re2, (size_t)B * 45 * Cq.ncell));
+  }
 #undef A_
   if (hipFuncSetAttribute((const void*)k_coarse_factor<double, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                           5 * pb->cbs * pb->cbs * sizeof(double)) != hipSuccess ||
@@ -2065,7 +2173,7 @@ fsi_status parareal_run(fsi_problem* pb, double T, int32_t N, int32_t m, int32_t
 fsi_status adjoint_gradient(fsi_problem* pb, double T, int32_t N, int32_t m, const double* U0, double* J_out,
                             double* grad_out, fsi_stats* stats, hipStream_t st) {
   if (!pb || !U0 || !J_out || !grad_out || N < 1 || N > pb->Bmax || m < 1 || !(T > 0.0)) return FSI_ERR_ARG;
-  if (pb->mixed || pb->p.dim != 2) return FSI_ERR_ARG;   // the adjoint runs in the 2d FP64 path
+  if (pb->mixed || pb->p.dim != 2 || pb->deg != 1) return FSI_ERR_ARG;   // the adjoint runs in the 2d Q1 FP64 path
   return guarded([&] { return adjoint_run(pb, T, N, m, U0, J_out, grad_out, stats, st); });
 }
 
@@ -2085,9 +2193,10 @@ fsi_status fsi_residual_noalloc(fsi_problem* pb, int32_t B, const double* U, con
                                 double k, double* R, hipStream_t st) {
   if (!pb || !U || !Uo || !t || !R || B <= 0 || B > pb->Bmax || !(k > 0) || !pb->scratch) return FSI_ERR_ARG;
   const Level& F = pb->lev[pb->nlev - 1];
-  const int NE = pb->p.dim == 3 ? Dm<3>::NE : Dm<2>::NE;
+  const Level& Cq = pb->lev[pb->nlev - (pb->deg == 2 ? 2 : 1)];   // the cells of the element kernels
+  const int NE = pb->deg == 2 ? 45 : (pb->p.dim == 3 ? Dm<3>::NE : Dm<2>::NE);
   // element residuals [B][NE][ncell], then the B slice times at a 256-byte boundary
-  const size_t re_vals = (size_t)B * NE * F.ncell;
+  const size_t re_vals = (size_t)B * NE * Cq.ncell;
   const size_t t_off = (re_vals + 31) / 32 * 32;
   if ((t_off + (size_t)B) * sizeof(double) > SCRATCH_BYTES) {
     std::fprintf(stderr, "fsi_residual_noalloc: %d slices need %zu bytes of scratch, more than its %zu\n", B,
@@ -2099,7 +2208,11 @@ fsi_status fsi_residual_noalloc(fsi_problem* pb, int32_t B, const double* U, con
   HIPCHK(hipMemcpyAsync(td, t, B * sizeof(double), hipMemcpyHostToDevice, st));
   const StepPar sp = step_par(pb, k);
   const Geom g = F.geom();
-  if (pb->p.dim == 3) {
+  if (pb->deg == 2) {
+    const Geom gc = Cq.geom();
+    k_elem_residual_q2<<<grid1(gc.ncell, B), TPB, 0, st>>>(gc, g, sp, U, Uo, re, nullptr);
+    k_gather_residual_q2<<<grid1(g.nn, B), TPB, 0, st>>>(gc, g, sp, pb->pst2, re, U, td, R, nullptr);
+  } else if (pb->p.dim == 3) {
     k_elem_residual<3><<<grid1(g.ncell, B), TPB, 0, st>>>(g, sp, U, Uo, re, nullptr);
     k_gather_residual<3><<<grid1(g.nn, B), TPB, 0, st>>>(g, sp, re, U, td, R, nullptr);
   } else {
@@ -2130,7 +2243,7 @@ fsi_status debug_apply(fsi_problem* pb, int B, const double* U, const double* Uo
   CHK(assemble_levels<D, S, true>(pb, B, sp, nullptr, st));
   k_convert<double, S><<<1024, TPB, 0, st>>>(B * ndof, X, (S*)pb->tmp);
   if (what == 0)
-    spmv<D, S, true>(pb, F.geom(), B, k, (const S*)F.J, (const S*)pb->tmp, nullptr, nullptr, (S*)pb->w, nullptr, st);
+    krylov_spmv<D, S, true>(pb, B, k, (const S*)pb->tmp, nullptr, nullptr, (S*)pb->w, nullptr, st);
   else
     vcycle<D, S, true>(pb, B, k, (const S*)pb->tmp, (S*)pb->w, nullptr, st);
   k_convert<S, double><<<1024, TPB, 0, st>>>(B * ndof, (const S*)pb->w, Y);

@@ -27,6 +27,19 @@ __global__ void k_gather_jacobian(Geom g, double k, const double* Ke, S* J, doub
 template <int D>
 __global__ void k_inject(Geom gc, Geom gf, const double* Uf, double* Uc);
 
+// Q2 cells (2d): gc the cells' level, gn the node grid (the next level)
+__global__ void k_elem_residual_q2(Geom gc, Geom gn, StepPar sp, const double* U, const double* Uo, double* Re,
+                                   const int* active);
+__global__ void k_elem_jacobian_q2(Geom gc, Geom gn, StepPar sp, const double* U, const double* Uo, double* Ke,
+                                   const int* active);
+__global__ void k_gather_residual_q2(Geom gc, Geom gn, StepPar sp, const double* pst2, const double* Re,
+                                     const double* U, const double* t, double* R, const int* active);
+__global__ void k_gather_jacobian_q2(Geom gc, Geom gn, double k, const double* pst2, const double* Ke, double* J2,
+                                     double* Dsc, const int* active);
+__global__ void k_spmv_q2(Geom gn, double k, const double* pst2, const double* J2, const double* x, const double* bv,
+                          const double* Dsc, double* y, const int* active);
+constexpr int Q2_JAC_CELLS = 64, Q2_JAC_THREADS = 256;   // k_elem_jacobian_q2 launch shape
+
 // 2d adjoint
 __global__ void k_drag_values(Geom g, double rn, const DragFace* faces, int nf, const double* U, size_t stride,
                               int nstates, double* vals);

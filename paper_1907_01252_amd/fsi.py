@@ -42,6 +42,7 @@ class Params(C.Structure):
         ("lin_rtol_first", C.c_double), ("parareal_theta", C.c_int32), ("theta_ref_k", C.c_double),
         ("parareal_pipeline", C.c_int32), ("batch_split", C.c_int32), ("newton_res_rtol", C.c_double),
         ("spmv_slice_fast", C.c_int32), ("vanka_slice_fast", C.c_int32), ("vanka_wide_cells", C.c_int32),
+        ("degree", C.c_int32),
     ]
 
 
@@ -134,7 +135,7 @@ def make_params(d: dict, precision=None, max_batch=None, tuned=True, **solver) -
     if d["dim"] == 3:
         s.update(SOLVER_DEFAULTS_3D)
     s.update({k: v for k, v in d.items() if k in SOLVER_DEFAULTS})
-    if tuned:
+    if tuned and int(d.get("degree", 1)) == 1:
         prec_name = "mixed" if (precision if precision is not None else d.get("precision", "fp64")) in \
             ("mixed", FSI_MIXED) else "fp64"
         mb = int(max_batch if max_batch is not None else d.get("N", 1))
@@ -143,6 +144,7 @@ def make_params(d: dict, precision=None, max_batch=None, tuned=True, **solver) -
     p = Params()
     p.dim = d["dim"]
     p.level = d["level"]
+    p.degree = int(d.get("degree", 1))
     for a, ax in enumerate(d["segments"]):
         p.nseg[a] = len(ax)
         for q, (lo, hi, n) in enumerate(ax):

@@ -84,6 +84,11 @@ _WORKLOADS = {
     # 2d adjoint workload, 128x32 cells, 32 slices on [0,1]
     "c4": dict(dim=2, level=3, T=1.0, N=32, dt_fine=0.002, dt_coarse=0.02,
                precision="fp64", parareal_tol=1e-8, mu_s=5e5),
+    # Q2 cells (the paper's element) on the nodes of c1 and of c2: 16x4 and 64x16 cells
+    "c1q2": dict(dim=2, level=0, degree=2, T=1.0, N=8, dt_fine=0.01, dt_coarse=0.1,
+                 precision="fp64", parareal_tol=1e-8, mu_s=5e5),
+    "c2q2": dict(dim=2, level=2, degree=2, T=2.0, N=32, dt_fine=0.002, dt_coarse=0.02,
+                 precision="fp64", parareal_tol=1e-8, mu_s=2e6),
     # 3d, 64x16x16 hexahedra, 16 slices on [0,0.8]
     "c5": dict(dim=3, level=2, T=0.8, N=16, dt_fine=0.005, dt_coarse=0.05,
                precision="mixed", parareal_tol=1e-8, mu_s=1e6),
@@ -93,7 +98,7 @@ _WORKLOADS = {
 def workload(name: str, seed: int = 0, **overrides) -> dict:
     """Return the full parameter dict of a named workload for one seed.
 
-    The seed perturbs the inflow peak: c1, c2, c4 draw peak = 0.3 (1 + u),
+    The seed perturbs the inflow peak: c1, c2, c4 (and c1q2, c2q2) draw peak = 0.3 (1 + u),
     u ~ U(-0.05, 0.05); c3 draws peak ~ U(0.2, 1.0); c5 keeps 0.3.
     """
     w = copy.deepcopy(_WORKLOADS[name])
@@ -101,7 +106,7 @@ def workload(name: str, seed: int = 0, **overrides) -> dict:
     p.update(w)
     p["lambda_s"] = lame_lambda(p["mu_s"], p["nu_s"])
     rng = np.random.default_rng(seed)
-    if name in ("c1", "c2", "c4"):
+    if name in ("c1", "c2", "c4", "c1q2", "c2q2"):
         p["inflow_peak"] = 0.3 * (1.0 + rng.uniform(-0.05, 0.05))
     elif name == "c3":
         p["inflow_peak"] = float(rng.uniform(0.2, 1.0))

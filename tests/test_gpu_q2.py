@@ -1,0 +1,169 @@
+"""GPU parity of the biquadratic (Q2) cells of Section 2.2 through the C ABI.
+
+The Q2 problem on level l has the nodes of the Q1 level l + 1 and nine per
+cell; the library solves each Newton step with FGMRES on the exact Q2 Jacobian,
+preconditioned by the Q1 multigrid V-cycle on the same nodes.  Compared with the
+FP64 oracle's Q2 discretisation (oracle.residual with degree 2): the residual
+and Jacobian products to 1e-12, fine propagation to 1e-10 (c1q2: 16x4 cells,
+the 297 nodes of c1), batched against single-slice calls, and one step of a
+sampled slice of the 32-slice c2q2 batch (64x16 cells, the 21,285 unknowns of
+c2) in the launch configuration of a full sweep.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle.residual import Discretization
+from oracle import propagate as P
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+FIELDS = {"v": slice(0, 2), "u": slice(2, 4), "p": slice(4, 5)}
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def field_rel(a, b, norm="max"):
+    out = {}
+    for k, sl in FIELDS.items():
+        x, y = a[..., sl], b[..., sl]
+        if norm == "max":
+            out[k] = np.abs(x - y).max() / max(np.abs(y).max(), 1e-300)
+        else:
+            out[k] = np.linalg.norm(x - y) / max(np.linalg.norm(y), 1e-300)
+    return out
+
+
+@pytest.fixture(scope="module")
+def fsi():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1907_01252_amd import fsi as f
+    f.load()
+    return f
+
+
+@pytest.fixture(scope="module")
+def c1q2(fsi):
+    p = synth.workload("c1q2", seed=1)
+    prob = fsi.Problem(fsi.make_params(p, precision="fp64", max_batch=4, batch_split=0))
+    return p, prob, Discretization(p)
+
+
+def test_sizes_q2(fsi, c1q2):
+    p, prob, D = c1q2
+    assert prob.n_nodes == D.mesh.n_nodes == 33 * 9
+
+
+def test_residual_parity_q2(fsi, c1q2):
+    p, prob, D = c1q2
+    _say("case: Q2 residual parity c1q2 B=3")
+    B = 3
+    U = np.stack([synth.random_state(p, 100 + b) for b in range(B)])
+    Uo = np.stack([synth.random_state(p, 200 + b) for b in range(B)])
+    t = [0.05, 0.3, 0.0731]
+    k = p["k_fine"]
+    R = torch.zeros(B, prob.n_nodes, 5, dtype=torch.float64, device="cuda")
+    prob.debug_residual(B, _dev(U), _dev(Uo), t, k, R)
+    Rg = _host(R)
+    for b in range(B):
+        err = field_rel(Rg[b], D.residual(U[b], Uo[b], t[b], k))
+        assert max(err.values()) <= 1e-12, (b, err)
+
+
+def test_jacobian_parity_q2(fsi, c1q2):
+    p, prob, D = c1q2
+    _say("case: Q2 jacobian parity c1q2 B=2")
+    B = 2
+    U = np.stack([synth.random_state(p, 300 + b) for b in range(B)])
+    Uo = np.stack([synth.random_state(p, 400 + b) for b in range(B)])
+    X = np.stack([synth.random_state(p, 500 + b) for b in range(B)])
+    t = [0.02, 0.5]
+    k = p["k_fine"]
+    Y = torch.zeros(B, prob.n_nodes, 5, dtype=torch.float64, device="cuda")
+    prob.debug_jacobian_apply(B, _dev(U), _dev(Uo), t, k, _dev(X), Y)
+    Yg = _host(Y)
+    for b in range(B):
+        Yo = (D.jacobian(U[b], Uo[b], t[b], k) @ X[b].ravel()).reshape(-1, 5)
+        err = field_rel(Yg[b], Yo)
+        assert max(err.values()) <= 1e-12, (b, err)
+
+
+def test_fine_propagate_parity_q2(fsi, c1q2):
+    p, prob, D = c1q2
+    _say("case: Q2 fine_propagate fp64 c1q2 B=2 m=3")
+    k = p["k_fine"]
+    m = 3
+    dl = m * k
+    U0 = np.zeros((D.mesh.n_nodes, 5))
+    Ua = P.propagate(D, U0, 0.0, 2 * dl, 6)
+    inputs, t0 = [U0, Ua], [0.0, 2 * dl]
+    ref = [P.propagate(D, inputs[b], t0[b], dl, m) for b in range(2)]
+    Uin = _dev(np.stack(inputs))
+    Uout = torch.zeros_like(Uin)
+    code, st = prob.fine_propagate(2, t0, dl, m, Uin, Uout)
+    Ug = _host(Uout)
+    for b in range(2):
+        err = field_rel(Ug[b], ref[b], norm="l2")
+        _say("slice", b, "newton", st.newton_its[b], "krylov", st.krylov_its[b], "err", err)
+        assert max(err.values()) <= 1e-10, (b, err)
+
+
+def test_batched_equals_sequential_q2(fsi, c1q2):
+    p, prob, D = c1q2
+    _say("case: Q2 batched vs sequential c1q2 B=3")
+    k = p["k_fine"]
+    dl = 2 * k
+    ins = np.stack([synth.random_state(p, 600 + q, grad_u_max=0.02) * [0.3, 0.3, 1, 1, 0] for q in range(3)])
+    t0 = [0.1 + q * dl for q in range(3)]
+    for q in range(3):
+        ins[q] = D.apply_dirichlet(ins[q], t0[q])
+    Uin = _dev(ins)
+    Ub = torch.zeros_like(Uin)
+    prob.fine_propagate(3, t0, dl, 2, Uin, Ub)
+    Us = torch.zeros_like(Uin)
+    for q in range(3):
+        out = torch.zeros_like(Uin[q:q + 1])
+        prob.fine_propagate(1, [t0[q]], dl, 2, Uin[q:q + 1].contiguous(), out)
+        Us[q] = out[0]
+    err = field_rel(_host(Ub), _host(Us), norm="l2")
+    assert max(err.values()) <= 1e-10, err
+
+
+def test_c2q2_fullsize_sampled_slice(fsi):
+    """32 slices of c2q2 (64x16 Q2 cells, 21,285 unknowns) in one call, one fine step; slice 13
+    against the oracle (about half a minute on the host)."""
+    p = synth.workload("c2q2", seed=0)
+    _say("case: c2q2 full size, 32 slices in one call, one step; slice 13 vs oracle")
+    D = Discretization(p)
+    N, dl = p["N"], p["slice_len"]
+    t0s = [l * dl for l in range(N)]
+    U_in = np.stack([D.apply_dirichlet(synth.smooth_state(p, 200 + l), t0s[l]) for l in range(N)])
+    prob = fsi.Problem(fsi.make_params(p, precision="fp64", max_batch=N))
+    Uin = _dev(U_in)
+    Uout = torch.zeros_like(Uin)
+    code, st = prob.fine_propagate(N, t0s, p["k_fine"], 1, Uin, Uout)
+    Ug = _host(Uout)
+    prob.close()
+    assert code == fsi.FSI_OK
+    l = 13
+    ref = P.propagate(D, U_in[l], t0s[l], p["k_fine"], 1)
+    err = field_rel(Ug[l], ref, norm="l2")
+    _say("slice", l, "newton", st.newton_its[l], "krylov", st.krylov_its[l], err)
+    assert max(err.values()) <= 1e-10, err

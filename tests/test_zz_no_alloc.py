@@ -44,7 +44,7 @@ def _pair(fsi, prob, B, U, Uo, t, k):
     return code, Ra.cpu().numpy(), Rb.cpu().numpy()
 
 
-@pytest.mark.parametrize("name,level,Bs", [("c1", 1, (3, 2)), ("c5", 1, (2, 1))])
+@pytest.mark.parametrize("name,level,Bs", [("c1", 1, (3, 2)), ("c5", 1, (2, 1)), ("c1q2", 0, (3, 2))])
 def test_noalloc_residual_equals_workspace_residual(fsi, name, level, Bs):
     p = synth.workload(name, seed=5, level=level)
     _say("case: residual_noalloc vs debug_residual", name, "level", level, "B", Bs)
