@@ -274,7 +274,8 @@ def main():
         "dtype": "f64" if prec == "fp64" else "f32-inner/f64-newton",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {dim}d ALE-FSI {'channel+bar' if dim == 2 else 'duct+block'}, "
-                               f"{p['level']}-level-refined {'x'.join(str(c) for c in synth.mesh_shape(p))} Q1, "
+                               f"{p['level']}-level-refined {'x'.join(str(c) for c in synth.mesh_shape(p))} "
+                               f"Q{p.get('degree', 1)}, "
                                f"{nd} unknowns, {N} slices x {m} steps of {p['k_fine']:.6g}",
                    "slices": N, "steps_per_slice": m, "unknowns": nd, "precision": prec,
                    "batch_split": int(prob.params.batch_split),

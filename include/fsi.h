@@ -144,6 +144,10 @@ typedef struct {
                                 may then be 0) and the nodes those of level + 1 (9 per cell);
                                 the Krylov operator is the Q2 step Jacobian and the
                                 preconditioner the Q1 multigrid V-cycle on the same nodes */
+  double newton_res_accept;  /* 0: off.  > 0: a slice whose residual at the top of a Newton
+                                iteration (after at least one update) meets the residual test
+                                with this tolerance ends its step there, without a further
+                                linear solve (round-off level, below newton_res_rtol) */
 } fsi_params;
 
 #define FSI_MAX_SLICES 1024

@@ -1123,7 +1123,10 @@ fsi_status newton_solve_step(fsi_problem* pb, int B, const StepPar& sp, std::vec
     stage_span(pb, 0, e0, e1);
     bool anyp = false;
     for (int b = 0; b < B; ++b) anyp |= pending[b] != 0;
-    if (anyp) {
+    // with newton_res_accept > 0 every slice updated at least once is also tested: a residual
+    // at that (round-off) level ends its step without another solve
+    const bool early = pb->p.newton_res_accept > 0.0 && it >= 2;
+    if (anyp || early) {
       // residual test of the pending slices: per field, max |D R_f| <= res_rtol max |U_f|,
       // D the row scaling of the last Jacobian (the refinement test of the mixed path:
       // the FP64 residual of the FP64 state)
@@ -1138,18 +1141,21 @@ fsi_status newton_solve_step(fsi_problem* pb, int B, const StepPar& sp, std::vec
       e1 = ec;
       bool left = false;
       for (int b = 0; b < B; ++b) {
-        if (pending[b]) {
+        if (pending[b] || (early && nact[b])) {
+          const double tol = pending[b] ? pb->p.newton_res_rtol : pb->p.newton_res_accept;
           bool ok = true;
           for (int f = 0; f < 3; ++f) {
             const double r = hm[(size_t)b * 6 + f], un = hm[(size_t)b * 6 + 3 + f];
-            if (!(r <= std::max(pb->p.newton_res_rtol * un, 1e-300))) ok = false;
+            if (!(r <= std::max(tol * un, 1e-300))) ok = false;
           }
+          const bool was_pending = pending[b] != 0;
           pending[b] = 0;
           if (ok) {
             nact[b] = 0;
             continue;
           }
-          if (pb->verbose && b == 0) std::fprintf(stderr, "fsi newton slice 0: residual test failed, iterating on\n");
+          if (pb->verbose && b == 0 && was_pending)
+            std::fprintf(stderr, "fsi newton slice 0: residual test failed, iterating on\n");
         }
         left |= nact[b] != 0;
       }
@@ -1657,7 +1663,7 @@ static fsi_status setup_impl(const fsi_params* prm, fsi_problem** out) {
     if (!std::isfinite(v)) return FSI_ERR_ARG;
   if (!(p.mu_s > 0) || p.lambda_s < 0 || p.theta0 < 0 || p.lps_alpha0 < 0 || p.cip_gamma < 0 ||
       !(p.vanka_omega > 0 && p.vanka_omega < 2) || !(p.newton_rtol > 0) || !(p.lin_rtol > 0 && p.lin_rtol < 1) ||
-      !(p.newton_res_rtol > 0 && p.newton_res_rtol < 1) || p.spmv_slice_fast < -1 || p.spmv_slice_fast > 1 ||
+      !(p.newton_res_rtol > 0 && p.newton_res_rtol < 1) || !(p.newton_res_accept >= 0 && p.newton_res_accept < 1) || p.spmv_slice_fast < -1 || p.spmv_slice_fast > 1 ||
       p.vanka_slice_fast < -1 || p.vanka_slice_fast > 1 || p.vanka_wide_cells < 0 ||
       (p.degree != 1 && p.degree != 2) ||
       (p.degree == 2 && (p.dim != 2 || p.precision != FSI_FP64 || p.level + 2 > MAXLEV - 1)))
