@@ -30,13 +30,15 @@ namespace fsi {
 // uncovered nodes.
 //
 // Minimum waves per SIMD requested for the fused pass: in 2d FP32 the register
-// budget of 6 waves (85 VGPRs) keeps enough waves resident to hide latency.
-template <int D, class S>
+// budget of 6 waves (85 VGPRs) keeps enough waves resident to hide latency; in 2d
+// FP64 4 waves with the compressed Jacobian (128 VGPRs: three blocks of five waves per CU;
+// the full-layout variant of the transposed adjoint operator keeps the compiler's choice).
+template <int D, class S, bool CJ>
 constexpr int vanka_waves_per_simd() {
-  return (D == 2 && sizeof(S) == 4) ? 6 : 1;
+  return D == 2 ? (sizeof(S) == 4 ? 6 : (CJ ? 4 : 1)) : 1;
 }
 template <int D, class S, int VC, bool CJ>
-__global__ void __launch_bounds__(Dm<D>::NC * 64, (vanka_waves_per_simd<D, S>()))
+__global__ void __launch_bounds__(Dm<D>::NC * 64, (vanka_waves_per_simd<D, S, CJ>()))
     k_vanka_color(Geom g, double k, int color, S omega, int zero_in,
                                                                 const S* __restrict__ J, const S* __restrict__ Ainv,
                                                                 const S* __restrict__ Yu,
@@ -59,6 +61,12 @@ __global__ void __launch_bounds__(Dm<D>::NC * 64, (vanka_waves_per_simd<D, S>())
   __shared__ S pr[RX2 * RY2 * RZ2];
   constexpr bool SP = patch_split<S, CJ>();   // split patch solve (see ainv_rows)
   __shared__ S dv[SP ? NL * D : 1][VC];        // velocity part of the patch update
+  // 2d split solve: the displacement-row waves, which have the fewest stencil loads, copy
+  // the block's inverse rows (one contiguous region) to LDS while the other waves load
+  // the Jacobian, so the inverse is not fetched only after the residual barrier
+  constexpr bool AL = D == 2 && SP;
+  constexpr int NR = ainv_rows<D, SP>();
+  __shared__ S ainvL[AL ? NR * NE * VC : 1];
   const int bs = slice_fast ? blockIdx.x : blockIdx.y;
   const int bx = slice_fast ? blockIdx.y : blockIdx.x;
   if (active && !active[bs]) return;   // uniform over the block
@@ -112,6 +120,25 @@ __global__ void __launch_bounds__(Dm<D>::NC * 64, (vanka_waves_per_simd<D, S>())
     }
     __syncthreads();
   }
+  if constexpr (AL) {
+    if (r >= D && r < 2 * D) {
+      // whole region of the block (colours are padded to whole blocks, so it is allocated)
+      const S* src = Ainv + (size_t)bs * ainv_slice<D>(g.ncell) + ((size_t)L.off + (size_t)bx * VC) * NR * NE;
+      constexpr int NT = D * 64, NV = NR * NE * VC / NT;
+      static_assert(NR * NE * VC % NT == 0, "inverse region per copying thread");
+      const int t0 = (r - D) * 64 + lane;
+      constexpr int CH = 10;   // loads in flight per chunk (registers)
+      static_assert(NV % CH == 0, "chunks");
+#pragma unroll 1
+      for (int q0 = 0; q0 < NV; q0 += CH) {
+        S tmp[CH];
+#pragma unroll
+        for (int q = 0; q < CH; ++q) tmp[q] = src[t0 + (q0 + q) * NT];
+#pragma unroll
+        for (int q = 0; q < CH; ++q) ainvL[t0 + (q0 + q) * NT] = tmp[q];
+      }
+    }
+  }
   int ci = 0, cj = 0, ck = 0;
   if (live) {
     const int ix = idx % L.ncx, rest = idx / L.ncx;
@@ -163,9 +190,9 @@ __global__ void __launch_bounds__(Dm<D>::NC * 64, (vanka_waves_per_simd<D, S>())
   // non-displacement unknowns), then the displacements from Y1, Y2 and the
   // velocity update
   const bool urow = SP && r >= D && r < 2 * D;
-  constexpr int NR = ainv_rows<D, SP>();
   if (live && !urow) {
-    const S* ai = Ainv + (size_t)bs * ainv_slice<D>(g.ncell) + ((size_t)L.off + (size_t)bx * VC) * NR * NE + jc;
+    const S* ai = AL ? ainvL + jc
+                     : Ainv + (size_t)bs * ainv_slice<D>(g.ncell) + ((size_t)L.off + (size_t)bx * VC) * NR * NE + jc;
 #pragma unroll 1
     for (int q = 0; q < NQ; ++q) {
       const int a = a0 + q * QS;
