@@ -61,9 +61,11 @@ __global__ void __launch_bounds__(Dm<D>::NC * 64, (vanka_waves_per_simd<D, S, CJ
   __shared__ S pr[RX2 * RY2 * RZ2];
   constexpr bool SP = patch_split<S, CJ>();   // split patch solve (see ainv_rows)
   __shared__ S dv[SP ? NL * D : 1][VC];        // velocity part of the patch update
-  // 2d split solve: the displacement-row waves, which have the fewest stencil loads, copy
-  // the block's inverse rows (one contiguous region) to LDS while the other waves load
-  // the Jacobian, so the inverse is not fetched only after the residual barrier
+  // 2d FP64 split solve: the displacement-row waves, which have the fewest stencil loads,
+  // copy the block's inverse rows (one contiguous region) to LDS while the other waves
+  // load the Jacobian, so the inverse is not fetched only after the residual barrier
+  // (in 2d FP32 those waves also form the pressure stabilisation, and the copy made
+  // the 256x64-cell pass 1.6 times slower)
   constexpr bool AL = D == 2 && SP;
   constexpr int NR = ainv_rows<D, SP>();
   __shared__ S ainvL[AL ? NR * NE * VC : 1];
