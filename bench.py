@@ -46,22 +46,24 @@ KERNEL_NAMES = {"vanka_pass_fine": "k_vanka_color (fused residual + patch update
                 "level_residual_fine": "k_spmv (residual before restriction, finest level)"}
 
 
-def counter_traffic(kernel_family, prec):
+def counter_traffic(workload, kernel_family, prec):
     """HBM bytes per launch of the dominant kernel from the committed counter runs, or None.
 
-    profiles/traffic.json records the kernel family, FETCH_SIZE/WRITE_SIZE means
-    (calibrated with a copy kernel) and a hash of the kernel's source at the
-    time of the runs; another family, precision or a changed kernel gives None.
+    profiles/traffic.json records, per workload, the FETCH_SIZE/WRITE_SIZE means of
+    the kernel's launches over the whole batch (calibrated with a copy kernel), and a
+    hash of the kernel's source at the time of the runs; another family, precision or
+    a changed kernel gives None.
     """
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     tr = json.load(open(path))
-    if tr.get("family") != kernel_family or tr.get("precision") != prec:
+    w = tr.get("workloads", {}).get(workload)
+    if w is None or tr.get("family") != kernel_family or w.get("precision") != prec:
         return None
     if kernel_source_hash(tr["kernel_function"]) != tr["source_hash"]:
         return None
-    return tr["traffic_bytes_per_launch"]
+    return w["traffic_bytes_per_launch"]
 
 
 def kernel_source_hash(fn):
@@ -254,7 +256,7 @@ def main():
         cpu["slice_parallel"] = oracle_slice_parallel(args.workload, [Uin[q].cpu().numpy() for q in range(N)], t0s, k,
                                                       ns, args.cpu_procs, nd)
 
-    roof = roofline_of(fams, counter_traffic if args.workload == "c2" else None, prec)
+    roof = roofline_of(fams, lambda fam, pr: counter_traffic(args.workload, fam, pr), prec)
     prob.close()
     extra = {}
     if not args.no_extra and args.workload == "c2":
@@ -342,7 +344,7 @@ def short_profiled_roofline(name, msteps):
     prob.profile_enable(False)
     fams = {f: prob.profile_query(i) for i, f in enumerate(FAMILIES)}
     prob.close()
-    r = roofline_of(fams, None, prec)
+    r = roofline_of(fams, lambda fam, pr: counter_traffic(name, fam, pr), prec)
     r["sweep"] = f"{name}: {prob.n_dofs} unknowns, {N} slices x {msteps} steps of {p['k_fine']:.6g}, {prec}"
     r["newton"], r["krylov"] = st.newton_total, st.krylov_total
     return r
