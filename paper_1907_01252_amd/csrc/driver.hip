@@ -110,6 +110,7 @@ struct fsi_problem {
   hipEvent_t iev = nullptr;
   int *nact = nullptr;   // Newton-active slices (device)
   int *gact = nullptr;   // FGMRES-active slices (device)
+  int *gord = nullptr;   // the FGMRES-active slices in order, then -1 (device; k_update_gact)
   int *flag = nullptr;
   // device address of the static scratch array on this problem's device (allocation-free residual)
   double* scratch = nullptr;
@@ -693,13 +694,25 @@ fsi_status assemble_levels(fsi_problem* pb, int B, const StepPar& sp, const int*
   return FSI_OK;
 }
 
+// Grid mode of a launch with the slices as the fast grid dimension: under the
+// FGMRES mask the kernel takes its slice from the ordered list of the working
+// slices (mode 2, act replaced by that list), else from its column (mode 1,
+// act the per-slice flags or null).
+inline int slice_mode(const fsi_problem* pb, int sf, const int*& act) {
+  if (sf && act && act == pb->gact) {
+    act = pb->gord;
+    return 2;
+  }
+  return sf;
+}
+
 // y = D (b - A x) (or D A x)
 template <int D, class S, bool CJ>
 void spmv(const fsi_problem* pb, const Geom& g, int B, double k, const S* J, const S* x, const S* b, const double* Dv,
           S* y, const int* act, hipStream_t st) {
   const int nb =
       !jrowtiles<D, S>() ? (g.nn + 63) / 64 : (jntx<D, S>(g, 0) * jrows<D>(g) * jtx<D, S>() + 63) / 64;
-  const int sf = spmv_slice_fast<D, S>(pb) && nb <= 65535 ? 1 : 0;
+  const int sf = slice_mode(pb, spmv_slice_fast<D, S>(pb) && nb <= 65535 ? 1 : 0, act);
   k_spmv<D, S, CJ><<<sf ? dim3(B, nb) : dim3(nb, B), spmv_threads<D>(), 0, st>>>(g, k, J, x, b, Dv, y, act, sf);
 }
 
@@ -756,17 +769,18 @@ void smooth(fsi_problem* pb, int l, int B, double k, int sweeps, bool zero_first
       // 128x32 cells and 32 slices 4% faster, the 3d one on 64x16x16 cells and 16 slices 13%);
       // the 2d FP32 pass (row tiles, six waves per SIMD) was 6% slower that way.
       const int nbx = (nc + vc - 1) / vc + ncopy;
-      const int sf = vanka_slice_fast<D, S>(pb) && nbx <= 65535 ? 1 : 0;
+      const int* sel = act;
+      const int sf = slice_mode(pb, vanka_slice_fast<D, S>(pb) && nbx <= 65535 ? 1 : 0, sel);
       const dim3 grid = sf ? dim3(B, nbx) : dim3(nbx, B);
       if constexpr (D == 2) {
         k_vanka_color<D, S, 16, CJ><<<grid, NC * 64, 0, st>>>(g, k, c, om, zero ? 1 : 0, J, Ai, Yu, b, buf[cur],
-                                                              buf[cur ^ 1], act, sf);
+                                                              buf[cur ^ 1], sel, sf);
       } else if (vc == 32) {
         k_vanka_color<D, S, 32, CJ><<<grid, NC * 64, 0, st>>>(g, k, c, om, zero ? 1 : 0, J, Ai, Yu, b, buf[cur],
-                                                              buf[cur ^ 1], act, sf);
+                                                              buf[cur ^ 1], sel, sf);
       } else {
         k_vanka_color<D, S, 8, CJ><<<grid, NC * 64, 0, st>>>(g, k, c, om, zero ? 1 : 0, J, Ai, Yu, b, buf[cur],
-                                                             buf[cur ^ 1], act, sf);
+                                                             buf[cur ^ 1], sel, sf);
       }
       cur ^= 1;
     }
@@ -901,8 +915,8 @@ fsi_status capture_step(fsi_problem* pb, int B, double k, int j, hipGraphExec_t*
   k_scale<S><<<grid1(n, B), TPB, 0, st>>>(n, w, (size_t)n, Zj, zb, nullptr, 0, 2, pb->gact);
   krylov_spmv<D, S, CJ>(pb, B, k, w, nullptr, F.Dsc, a, pb->gact, st);
   arnoldi_tail<D, S>(pb, B, j, n, st);
-  k_update_gact<<<(B + 63) / 64, 64, 0, st>>>(pb->nact, pb->gstate, pb->gact, B,
-                                              pb->hst_pin + (size_t)(j & 1) * pb->Bmax);
+  k_update_gact<<<1, 64, 0, st>>>(pb->nact, pb->gstate, pb->gact, pb->gord, B,
+                                  pb->hst_pin + (size_t)(j & 1) * pb->Bmax);
   const hipError_t e0 = hipGetLastError();
   const hipError_t e1 = hipStreamEndCapture(st, &graph);
   if (e0 != hipSuccess || e1 != hipSuccess) return FSI_ERR_HIP;
@@ -963,7 +977,7 @@ fsi_status fgmres(fsi_problem* pb, int B, double k, std::vector<int>& kits, hipS
   if (failed) failed->assign(B, 0);
   HIPCHK(hipMemcpyAsync(pb->ltol, pb->ltol_h.data(), B * sizeof(double), hipMemcpyHostToDevice, st));
   k_fill<S><<<1024, TPB, 0, st>>>((size_t)B * n, xs, (S)0);
-  HIPCHK(hipMemcpyAsync(pb->gact, pb->nact, B * sizeof(int), hipMemcpyDeviceToDevice, st));
+  k_update_gact<<<1, 64, 0, st>>>(pb->nact, nullptr, pb->gact, pb->gord, B);   // gact = nact
   int total = 0;
   for (int cycle = 0;; ++cycle) {
     // V0 = D (b - J xs), b = -R
@@ -978,7 +992,7 @@ fsi_status fgmres(fsi_problem* pb, int B, double k, std::vector<int>& kits, hipS
     k_reduce_partials<<<B, 64, 0, st>>>(1, nchunk, pb->partial, pb->beta, 1, pb->gact);
     k_init_cycle<<<gb, tb, 0, st>>>(R, cycle, pb->beta, pb->beta0, pb->gv, pb->gstate, pb->ncol, pb->ltol, pb->gact,
                                     B);
-    k_update_gact<<<gb, tb, 0, st>>>(pb->nact, pb->gstate, pb->gact, B);
+    k_update_gact<<<1, 64, 0, st>>>(pb->nact, pb->gstate, pb->gact, pb->gord, B);
     k_scale<S><<<grid1(n, B), TPB, 0, st>>>(n, V, vb, V, vb, pb->beta, 1, 1, pb->gact);
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(hstate.data(), pb->gstate, B * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -1042,7 +1056,7 @@ fsi_status fgmres(fsi_problem* pb, int B, double k, std::vector<int>& kits, hipS
         if (hstate[b] == 0) kits[b] += 1;
       ++total;
       jmax = j + 1;
-      k_update_gact<<<gb, tb, 0, st>>>(pb->nact, pb->gstate, pb->gact, B);
+      k_update_gact<<<1, 64, 0, st>>>(pb->nact, pb->gstate, pb->gact, pb->gord, B);
       HIPCHK(hipMemcpyAsync(hstate.data(), pb->gstate, B * sizeof(int), hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
       any = false;
@@ -1068,7 +1082,7 @@ fsi_status fgmres(fsi_problem* pb, int B, double k, std::vector<int>& kits, hipS
       return FSI_ERR_LINEAR;
     }
     // restart the unconverged slices
-    k_update_gact<<<gb, tb, 0, st>>>(pb->nact, pb->gstate, pb->gact, B);
+    k_update_gact<<<1, 64, 0, st>>>(pb->nact, pb->gstate, pb->gact, pb->gord, B);
   }
   return FSI_OK;
 }
@@ -1713,6 +1727,7 @@ static fsi_status setup_impl(const fsi_params* prm, fsi_problem** out) {
   A_(dalloc(pb, &pb->tdev, B));
   A_(dalloc(pb, &pb->nact, B));
   A_(dalloc(pb, &pb->gact, B));
+  A_(dalloc(pb, &pb->gord, B));
   A_(dalloc(pb, &pb->flag, B));
   A_(dalloc_bytes(pb, &pb->V, (size_t)B * (R + 1) * ndof * ss));
   A_(dalloc_bytes(pb, &pb->Z, (size_t)B * R * ndof * ss));

@@ -97,7 +97,7 @@ __global__ void k_givens(int j, int R, double* H, const double* hcol, double* cs
 __global__ void k_init_cycle(int R, int cycle, const double* beta2, double* beta0, double* gv, int* state, int* ncol,
                              const double* tolv, const int* gact, int B);
 __global__ void k_cgs_combine(int j, double* hcol, const double* hcol2, const double* hn2, const int* active, int B);
-__global__ void k_update_gact(const int* nact, const int* state, int* gact, int B, int* hout = nullptr);
+__global__ void k_update_gact(const int* nact, const int* state, int* gact, int* ord, int B, int* hout = nullptr);
 __global__ void k_trisolve(int R, const double* H, const double* gv, const int* ncol, double* y, const int* active,
                            int B);
 template <int D, class S>

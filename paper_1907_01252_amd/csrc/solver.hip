@@ -30,7 +30,8 @@ __global__ void __launch_bounds__(Dm<D>::NC * 64) k_spmv(Geom g, double k, const
                                                          const double* __restrict__ Dsc, S* __restrict__ y,
                                                          const int* __restrict__ active, int slice_fast) {
   FSI_DIM(D);
-  const int bs = slice_fast ? blockIdx.x : blockIdx.y;
+  // slice_fast = 2: active is the ordered list of working slices (k_update_gact)
+  const int bs = slice_fast == 2 ? active[blockIdx.x] : (slice_fast ? blockIdx.x : blockIdx.y);
   const int bx = slice_fast ? blockIdx.y : blockIdx.x;
   const int r = threadIdx.x >> 6, lane = threadIdx.x & 63;
   int n, i, row;
@@ -48,7 +49,7 @@ __global__ void __launch_bounds__(Dm<D>::NC * 64) k_spmv(Geom g, double k, const
     if (row >= jrows<D>(g) || i > g.nx) return;
     n = i + (g.nx + 1) * row;
   }
-  if (active && !active[bs]) return;
+  if (slice_fast == 2 ? bs < 0 : (active && !active[bs])) return;
   const int j = row % (g.ny + 1), kk = row / (g.ny + 1);
   const S* jn = J + jslice_row<D, S, CJ>(g, bs, r) + jnode<D, S, CJ>(g, i, row, 0);
   const S* xb = x + (size_t)bs * g.nn * NC;
@@ -599,16 +600,33 @@ __global__ void k_cgs_combine(int j, double* __restrict__ hcol, const double* __
   hcol[(size_t)b * 64 + j + 1] = hn2[b];
 }
 
-// gact[b] = nact[b] && state[b] == 0; with hout (pinned host memory) set, also
-// hout[b] = state[b], so the host reads the states once the launch has finished
-// without a separate copy
+// gact[b] = nact[b] && state[b] == 0 (gact = nact without state), and the working
+// slices in order: ord[q] = index of the q-th slice with gact set, -1 from their
+// count on.  Launches with the slices as the fast grid dimension take their slice
+// from ord (slice_fast = 2), so the working slices fill the first grid columns and
+// their blocks spread evenly over the XCDs (consecutive blocks go to consecutive
+// XCDs); with the flags, converged slices leave their XCDs' share of the launch
+// idle while the others still hold whole slices.  With hout (pinned host memory)
+// set, also hout[b] = state[b], so the host reads the states once the launch has
+// finished without a separate copy.  One wave.
 __global__ void k_update_gact(const int* __restrict__ nact, const int* __restrict__ state, int* __restrict__ gact,
-                              int B, int* hout) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= B) return;
-  const int s = state[b];
-  gact[b] = (nact[b] && s == 0) ? 1 : 0;
-  if (hout) hout[b] = s;
+                              int* __restrict__ ord, int B, int* hout) {
+  const int lane = threadIdx.x;
+  int base = 0;
+  for (int b0 = 0; b0 < B; b0 += 64) {
+    const int b = b0 + lane;
+    int f = 0;
+    if (b < B) {
+      const int s = state ? state[b] : 0;
+      f = (nact[b] && s == 0) ? 1 : 0;
+      gact[b] = f;
+      if (hout) hout[b] = s;
+    }
+    const unsigned long long m = __ballot(f);
+    if (f) ord[base + __popcll(m & ((1ull << lane) - 1ull))] = b;
+    base += __popcll(m);
+  }
+  for (int q = base + lane; q < B; q += 64) ord[q] = -1;
 }
 
 // Arnoldi bookkeeping for column j of every active slice: Hcol = h (j+2 entries,

@@ -2,7 +2,9 @@
 // stencil and the patch update in one kernel (the patch inverses it applies
 // are formed in vanka_factor.hip).  The kernel takes the slice index from
 // blockIdx.y (blockIdx.x when slice_fast is set, the slices then being the
-// fast grid dimension) and skips slices whose active flag is 0; S is the
+// fast grid dimension) and skips slices whose active flag is 0; with
+// slice_fast = 2 active lists the working slices in order and blockIdx.x
+// indexes that list (-1: nothing to do).  S is the
 // storage type of the linear solve, D the space dimension, CJ the Jacobian
 // block layout.
 #include "stencil.h"
@@ -69,9 +71,10 @@ __global__ void __launch_bounds__(Dm<D>::NC * 64, (vanka_waves_per_simd<D, S, CJ
   constexpr bool AL = D == 2 && SP;
   constexpr int NR = ainv_rows<D, SP>();
   __shared__ S ainvL[AL ? NR * NE * VC : 1];
-  const int bs = slice_fast ? blockIdx.x : blockIdx.y;
+  // slice_fast = 2: active is the ordered list of working slices (k_update_gact)
+  const int bs = slice_fast == 2 ? active[blockIdx.x] : (slice_fast ? blockIdx.x : blockIdx.y);
   const int bx = slice_fast ? blockIdx.y : blockIdx.x;
-  if (active && !active[bs]) return;   // uniform over the block
+  if (slice_fast == 2 ? bs < 0 : (active && !active[bs])) return;   // uniform over the block
   const ColorInfo L = color_info<D>(g, color, VC);
   const int nc = L.nc;
   const int npb = (nc + VC - 1) / VC;
