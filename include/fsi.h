@@ -109,7 +109,7 @@ typedef struct {
                                 first such call and kept with the problem. */
   int32_t batch_split;       /* fine_propagate / coarse_propagate with B >= 2 slices:
                                 0 or 1: one batch on the library stream;
-                                S in [2, 4] (and <= max_batch): the slices are cut into S
+                                S in [2, 8] (and <= max_batch): the slices are cut into S
                                 consecutive groups of (nearly) equal size, each run by its
                                 own host thread on its own workspace and stream, so that
                                 one group's latency-bound phases (coarse levels, Krylov
@@ -177,7 +177,7 @@ typedef struct {
    constant, rho_f, nu_f, rho_s, mu_s or ramp_time not positive, lambda_s,
    theta0, lps_alpha0 or cip_gamma negative, vanka_omega outside (0, 2),
    newton_rtol not positive, lin_rtol or lin_rtol_first outside (0, 1),
-   batch_split outside [0, 4] or above max_batch),
+   batch_split outside [0, 8] or above max_batch),
    FSI_ERR_OOM, FSI_ERR_HIP. */
 fsi_status fsi_setup(const fsi_params* params, fsi_problem** out);
 

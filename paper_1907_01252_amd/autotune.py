@@ -10,8 +10,9 @@ fine_propagate call, `steps_per_slice` steps of the workload's step size, the
 inputs from a one-step coarse sweep) under candidate settings of the choices
 that change how the work is launched but not what is computed:
 
-  batch_split       concurrent slice groups (1, 2 or 3; 4 needs more hardware
-                    queues than a process gets by default)
+  batch_split       concurrent slice groups (1, 2 or 3; also 4 when the process
+                    has at least 8 hardware queues, GPU_MAX_HW_QUEUES: each group's
+                    stream needs one of its own, and HIP's default is 4)
   spmv_slice_fast   SpMV grid with the slices as the fast dimension (0 or 1)
   vanka_slice_fast  the same for the fused Vanka pass (0 or 1)
   vanka_wide_cells  3d only: colour size over the batch from which the fused
@@ -25,9 +26,11 @@ largest relative difference is recorded (the choices reorder launches, so it
 is zero unless a choice changes the arithmetic).
 
 The result goes to tuned.json next to this file, keyed by the problem's
-dimension, refinement level, precision and batch size, which make_params()
-applies to a problem of that key unless the caller sets a choice itself; the
-timings of every candidate go to profiles/autotune_<workload>.md.
+dimension, refinement level, precision and batch size and by the process's
+hardware queue count (no suffix for HIP's default of 4, -q<N> otherwise), which
+make_params() applies to a problem of that key unless the caller sets a choice
+itself; the timings of every candidate go to profiles/autotune_<workload>.md
+(autotune_<workload>_q<N>.md).
 """
 from __future__ import annotations
 
@@ -47,15 +50,25 @@ TABLE = os.path.join(HERE, "tuned.json")
 CHOICES = ("batch_split", "spmv_slice_fast", "vanka_slice_fast", "vanka_wide_cells")
 
 
-def candidates(dim: int) -> dict:
-    c = {"batch_split": [1, 2, 3], "spmv_slice_fast": [0, 1], "vanka_slice_fast": [0, 1]}
+def hw_queues() -> int:
+    """Hardware queues HIP gives this process (GPU_MAX_HW_QUEUES, default 4)."""
+    try:
+        return max(1, int(os.environ.get("GPU_MAX_HW_QUEUES", "4")))
+    except ValueError:
+        return 4
+
+
+def candidates(dim: int, queues: int = 4) -> dict:
+    # five or more groups measured about twice as slow as four, with 8 or 16 queues
+    c = {"batch_split": [1, 2, 3] + ([4] if queues >= 8 else []), "spmv_slice_fast": [0, 1],
+         "vanka_slice_fast": [0, 1]}
     if dim == 3:
         c["vanka_wide_cells"] = [4096, 8192, 16384, 1 << 30]
     return c
 
 
-def table_key(dim: int, level: int, precision: str, max_batch: int) -> str:
-    return f"d{dim}-l{level}-{precision}-b{max_batch}"
+def table_key(dim: int, level: int, precision: str, max_batch: int, queues: int = 4) -> str:
+    return f"d{dim}-l{level}-{precision}-b{max_batch}" + ("" if queues == 4 else f"-q{queues}")
 
 
 def load_table() -> dict:
@@ -128,8 +141,9 @@ def tune(name: str, steps_per_slice: int = 4, reps: int = 2, log=print) -> dict:
     trials = []
     best_t, diff, counts = sw.time(cur, reps)
     trials.append({"choice": dict(cur), "seconds": best_t, "max_rel_diff": diff, "newton_krylov": counts})
-    log(f"autotune {name}: start {cur} {best_t:.4f} s")
-    for key, values in candidates(dim).items():
+    q = hw_queues()
+    log(f"autotune {name}: start {cur} {best_t:.4f} s ({q} hardware queues)")
+    for key, values in candidates(dim, q).items():
         for v in values:
             if v == cur[key]:
                 continue
@@ -141,22 +155,27 @@ def tune(name: str, steps_per_slice: int = 4, reps: int = 2, log=print) -> dict:
             if t < 0.99 * best_t:
                 cur, best_t = trial, t
     p = sw.p
-    return {"workload": name, "key": table_key(dim, p["level"], sw.prec, sw.N), "choice": cur, "seconds": best_t,
+    return {"workload": name, "key": table_key(dim, p["level"], sw.prec, sw.N, q), "queues": q,
+            "choice": cur, "seconds": best_t,
             "sweep": f"{name}: {sw.N} slices x {steps_per_slice} steps of {p['k_fine']:.6g}, {sw.prec}",
             "reps": reps, "trials": trials,
             "date": datetime.datetime.now(datetime.timezone.utc).strftime("%Y-%m-%d %H:%M UTC")}
+
+
+def _evidence(r: dict) -> str:
+    return f"autotune_{r['workload']}" + ("" if r["queues"] == 4 else f"_q{r['queues']}") + ".md"
 
 
 def write(results: list, table_path: str = TABLE, profiles: str | None = None, command: str = ""):
     table = load_table() if table_path == TABLE else {}
     for r in results:
         table[r["key"]] = {"workload": r["workload"], "choice": r["choice"], "seconds": r["seconds"],
-                           "sweep": r["sweep"], "evidence": f"profiles/autotune_{r['workload']}.md"}
+                           "sweep": r["sweep"], "hw_queues": r["queues"], "evidence": f"profiles/{_evidence(r)}"}
     with open(table_path, "w") as f:
         json.dump(table, f, indent=1, sort_keys=True)
     if profiles:
         for r in results:
-            lines = [f"# Autotuner: {r['sweep']}", "",
+            lines = [f"# Autotuner: {r['sweep']}, {r['queues']} hardware queues", "",
                      "Command (repository root, one MI355X):", "", f"    {command}", "",
                      f"Measured {r['date']}; each row is the best of {r['reps']} sweeps after a warm-up sweep on a "
                      "fresh problem. Coordinate descent from the built-in defaults (first row); a candidate is kept "
@@ -168,7 +187,7 @@ def write(results: list, table_path: str = TABLE, profiles: str | None = None, c
             for t in r["trials"]:
                 lines.append(f"| `{json.dumps(t['choice'])}` | {t['seconds'] * 1e3:.1f} | "
                              f"{t['newton_krylov'][0]}, {t['newton_krylov'][1]} | {t['max_rel_diff']:.1e} |")
-            with open(os.path.join(profiles, f"autotune_{r['workload']}.md"), "w") as f:
+            with open(os.path.join(profiles, _evidence(r)), "w") as f:
                 f.write("\n".join(lines) + "\n")
 
 
@@ -183,7 +202,9 @@ def main():
     a = ap.parse_args()
     sys.path.insert(0, ROOT)
     # the command as run with the default outputs (this package's tuned.json, profiles/)
-    cmd = f"python -m paper_1907_01252_amd.autotune {' '.join(a.workloads)} --reps {a.reps}"
+    q = hw_queues()
+    cmd = (f"GPU_MAX_HW_QUEUES={q} " if q != 4 else "") + \
+        f"python -m paper_1907_01252_amd.autotune {' '.join(a.workloads)} --reps {a.reps}"
     res = []
     for spec in a.workloads:
         name, _, steps = spec.partition(":")

@@ -1662,7 +1662,7 @@ static fsi_status setup_impl(const fsi_params* prm, fsi_problem** out) {
       p.gmres_maxit < 1 || (p.precision != FSI_FP64 && p.precision != FSI_MIXED) ||
       (p.precond_lag != 0 && p.precond_lag != 1) || !(p.lin_rtol_first > 0.0 && p.lin_rtol_first < 1.0) ||
       p.parareal_theta < 0 || p.parareal_theta > 2 || !(p.theta_ref_k >= 0.0) || p.parareal_pipeline < 0 ||
-      p.parareal_pipeline > p.max_batch || p.batch_split < 0 || p.batch_split > 4 || p.batch_split > p.max_batch)
+      p.parareal_pipeline > p.max_batch || p.batch_split < 0 || p.batch_split > 8 || p.batch_split > p.max_batch)
     return FSI_ERR_ARG;
   for (int a = 0; a < p.dim; ++a) {
     if (p.nseg[a] < 1 || p.nseg[a] > 4) return FSI_ERR_ARG;
@@ -2258,6 +2258,7 @@ fsi_status debug_apply(fsi_problem* pb, int B, const double* U, const double* Uo
   Level& F = pb->lev[pb->nlev - 1];
   const size_t ndof = (size_t)F.nn * NC;
   const StepPar sp = step_par(pb, k);
+  pb->prof.pact = B;   // every slice works (profiled bytes)
   HIPCHK(hipMemcpyAsync(pb->tdev, t, B * sizeof(double), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(pb->U, U, B * ndof * sizeof(double), hipMemcpyDeviceToDevice, st));
   HIPCHK(hipMemcpyAsync(pb->Uold, Uo, B * ndof * sizeof(double), hipMemcpyDeviceToDevice, st));

@@ -252,9 +252,9 @@ __host__ __device__ constexpr int vf_patches() { return D == 2 ? 8 : 1; }    // 
 constexpr int CG_THREADS = 512;
 // element Jacobian: blocks of jac_cells cells, jac_waves threads per cell
 template <int D>
-__host__ __device__ constexpr int jac_cells() { return D == 2 ? 64 : 128; }
+__host__ __device__ constexpr int jac_cells() { return 64; }
 template <int D>
-__host__ __device__ constexpr int jac_waves() { return D == 2 ? 4 : 1; }
+__host__ __device__ constexpr int jac_waves() { return D == 2 ? 4 : 2; }
 
 // ------------------------------------------------------------ colour helpers
 // Cells of colour c = (i mod 2) + 2 (j mod 2) + 4 (k mod 2): ncx per row, ncy

@@ -124,9 +124,12 @@ SOLVER_DEFAULTS_3D = dict(vanka_omega=0.6, cip_gamma=3e-4, newton_res_accept=1e-
 
 
 def tuned_choice(dim, level, precision, max_batch):
-    """Launch choices the autotuner stored for this problem size (autotune.py), or {}."""
+    """Launch choices the autotuner stored for this problem size (autotune.py) and this process's
+    hardware queue count, else those of the default count (4), else {}."""
     from . import autotune
-    e = autotune.load_table().get(autotune.table_key(dim, level, precision, max_batch))
+    table = autotune.load_table()
+    e = table.get(autotune.table_key(dim, level, precision, max_batch, autotune.hw_queues())) or \
+        table.get(autotune.table_key(dim, level, precision, max_batch))
     return dict(e["choice"]) if e else {}
 
 

@@ -92,7 +92,7 @@ def test_argument_errors_without_gpu(lib):
                 dict(mu_s=0.0), dict(lambda_s=-1.0), dict(lambda_s=float("nan")), dict(inflow_peak=float("inf")),
                 dict(theta0=-0.5), dict(lps_alpha0=-1.0), dict(cip_gamma=-1e-4), dict(vanka_omega=0.0),
                 dict(vanka_omega=2.0), dict(newton_rtol=0.0), dict(lin_rtol=1.0), dict(rho_s=float("nan")),
-                dict(batch_split=-1), dict(batch_split=5), dict(batch_split=3), dict(newton_res_rtol=0.0),
+                dict(batch_split=-1), dict(batch_split=9), dict(batch_split=3), dict(newton_res_rtol=0.0),
                 dict(newton_res_rtol=1.0), dict(newton_res_rtol=float("nan"))):
         p = fsi.make_params(synth.workload("c1"), max_batch=2)
         for k, v in bad.items():
@@ -140,3 +140,25 @@ def test_tuned_choices_are_applied(tmp_path, monkeypatch):
     assert (p.batch_split, p.spmv_slice_fast, p.vanka_slice_fast) == (3, -1, -1)
     p = fsi.make_params(w, max_batch=4)   # another key: the table does not apply
     assert (p.batch_split, p.spmv_slice_fast) == (3, -1)
+
+
+def test_tuned_choices_follow_the_hardware_queues(tmp_path, monkeypatch):
+    """An entry tuned with more hardware queues applies only to a process that has them; the
+    default-queue entry serves every other count."""
+    import json
+    import synth
+    from paper_1907_01252_amd import autotune, fsi
+    w = synth.workload("c1")
+    k4 = autotune.table_key(2, w["level"], "fp64", 8)
+    k8 = autotune.table_key(2, w["level"], "fp64", 8, 8)
+    assert k8 == k4 + "-q8"
+    path = tmp_path / "tuned.json"
+    path.write_text(json.dumps({k4: {"choice": {"batch_split": 2}}, k8: {"choice": {"batch_split": 4}}}))
+    monkeypatch.setattr(autotune, "TABLE", str(path))
+    monkeypatch.delenv("GPU_MAX_HW_QUEUES", raising=False)
+    assert fsi.make_params(w, max_batch=8).batch_split == 2
+    monkeypatch.setenv("GPU_MAX_HW_QUEUES", "8")
+    assert fsi.make_params(w, max_batch=8).batch_split == 4
+    monkeypatch.setenv("GPU_MAX_HW_QUEUES", "16")   # no entry of its own: the default one
+    assert fsi.make_params(w, max_batch=8).batch_split == 2
+    assert 4 in autotune.candidates(2, 8)["batch_split"] and 4 not in autotune.candidates(2, 4)["batch_split"]
