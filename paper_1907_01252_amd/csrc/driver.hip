@@ -694,6 +694,13 @@ fsi_status assemble_levels(fsi_problem* pb, int B, const StepPar& sp, const int*
   return FSI_OK;
 }
 
+// Blocks per slice of a launch with the slices as the slow grid dimension, rounded up
+// to a multiple of the 8 XCDs: consecutive blocks go to consecutive XCDs, so block x
+// of every slice then runs on XCD x mod 8, and the values every slice shares (the
+// displacement rows of slice 0, the stabilisation stencil) are fetched by one XCD and
+// reused from its cache by the following slices.  The extra blocks return at once.
+inline int xcd_pad(int nb) { return (nb + 7) / 8 * 8; }
+
 // Grid mode of a launch with the slices as the fast grid dimension: under the
 // FGMRES mask the kernel takes its slice from the ordered list of the working
 // slices (mode 2, act replaced by that list), else from its column (mode 1,
@@ -713,7 +720,8 @@ void spmv(const fsi_problem* pb, const Geom& g, int B, double k, const S* J, con
   const int nb =
       !jrowtiles<D, S>() ? (g.nn + 63) / 64 : (jntx<D, S>(g, 0) * jrows<D>(g) * jtx<D, S>() + 63) / 64;
   const int sf = slice_mode(pb, spmv_slice_fast<D, S>(pb) && nb <= 65535 ? 1 : 0, act);
-  k_spmv<D, S, CJ><<<sf ? dim3(B, nb) : dim3(nb, B), spmv_threads<D>(), 0, st>>>(g, k, J, x, b, Dv, y, act, sf);
+  k_spmv<D, S, CJ><<<sf ? dim3(B, nb) : dim3(xcd_pad(nb), B), spmv_threads<D>(), 0, st>>>(g, k, J, x, b, Dv, y, act,
+                                                                                      sf);
 }
 
 // The Krylov operator's product y = D (b - J x) (or D J x): the Q1 step Jacobian of the
@@ -771,7 +779,7 @@ void smooth(fsi_problem* pb, int l, int B, double k, int sweeps, bool zero_first
       const int nbx = (nc + vc - 1) / vc + ncopy;
       const int* sel = act;
       const int sf = slice_mode(pb, vanka_slice_fast<D, S>(pb) && nbx <= 65535 ? 1 : 0, sel);
-      const dim3 grid = sf ? dim3(B, nbx) : dim3(nbx, B);
+      const dim3 grid = sf ? dim3(B, nbx) : dim3(xcd_pad(nbx), B);
       if constexpr (D == 2) {
         k_vanka_color<D, S, 16, CJ><<<grid, NC * 64, 0, st>>>(g, k, c, om, zero ? 1 : 0, J, Ai, Yu, b, buf[cur],
                                                               buf[cur ^ 1], sel, sf);
