@@ -148,6 +148,11 @@ typedef struct {
                                 iteration (after at least one update) meets the residual test
                                 with this tolerance ends its step there, without a further
                                 linear solve (round-off level, below newton_res_rtol) */
+  int32_t newton_guess;      /* Newton's starting point at step n: 0: U^{n-1}; q in [1, 3]:
+                                the polynomial of degree q through the last q + 1 states of
+                                the slice, evaluated at t_n (degree min(q, n - 1) at the
+                                first steps; the Dirichlet values of t_n replace it on the
+                                boundary).  The converged step does not depend on it */
 } fsi_params;
 
 #define FSI_MAX_SLICES 1024
@@ -177,7 +182,7 @@ typedef struct {
    constant, rho_f, nu_f, rho_s, mu_s or ramp_time not positive, lambda_s,
    theta0, lps_alpha0 or cip_gamma negative, vanka_omega outside (0, 2),
    newton_rtol not positive, lin_rtol or lin_rtol_first outside (0, 1),
-   batch_split outside [0, 8] or above max_batch),
+   batch_split outside [0, 8] or above max_batch, newton_guess outside [0, 3]),
    FSI_ERR_OOM, FSI_ERR_HIP. */
 fsi_status fsi_setup(const fsi_params* params, fsi_problem** out);
 

@@ -95,6 +95,7 @@ struct fsi_problem {
   size_t ssz = 8;        // sizeof(S)
   int R = 30;
   // finest-level Newton data (double)
+  double *Uprev2 = nullptr, *Uprev3 = nullptr;   // U^{n-3}, U^{n-4} (higher-degree Newton guesses)
   double *U = nullptr, *Uold = nullptr, *Uprev = nullptr, *Res = nullptr, *Re = nullptr, *Ke = nullptr,
          *tdev = nullptr;
   // V-cycle replay graph (captured per batch size and step size)
@@ -1286,11 +1287,16 @@ fsi_status propagate(fsi_problem* pb, int B, const double* t0, double slice_len,
     for (int b = 0; b < B; ++b) th[b] = t0[b] + n * k;
     HIPCHK(hipMemcpyAsync(pb->tdev, th.data(), B * sizeof(double), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(pb->nact, hact.data(), B * sizeof(int), hipMemcpyHostToDevice, st));
-    if (n >= 2)
-      HIPCHK(hipMemcpyAsync(pb->Uprev, pb->Uold, (size_t)B * ndof * sizeof(double), hipMemcpyDeviceToDevice, st));
-    HIPCHK(hipMemcpyAsync(pb->Uold, pb->U, (size_t)B * ndof * sizeof(double), hipMemcpyDeviceToDevice, st));
-    // Newton guess: the old state (first step) or the linear extrapolation of the last two
-    if (n >= 2) k_extrapolate<<<dim3(64, B), TPB, 0, st>>>(ndof, pb->U, pb->Uold, pb->Uprev, pb->nact);
+    // history U^{n-1} .. U^{n-1-q} of the Newton guess (older states first)
+    const int q = std::min(pb->p.newton_guess, n - 1);
+    const size_t sb = (size_t)B * ndof * sizeof(double);
+    if (n >= 4 && pb->p.newton_guess >= 3) HIPCHK(hipMemcpyAsync(pb->Uprev3, pb->Uprev2, sb, hipMemcpyDeviceToDevice, st));
+    if (n >= 3 && pb->p.newton_guess >= 2) HIPCHK(hipMemcpyAsync(pb->Uprev2, pb->Uprev, sb, hipMemcpyDeviceToDevice, st));
+    if (n >= 2) HIPCHK(hipMemcpyAsync(pb->Uprev, pb->Uold, sb, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(pb->Uold, pb->U, sb, hipMemcpyDeviceToDevice, st));
+    // Newton guess: the old state, or the extrapolation of degree q of the last q + 1 states
+    if (q >= 1)
+      k_extrapolate<<<dim3(64, B), TPB, 0, st>>>(ndof, q, pb->U, pb->Uold, pb->Uprev, pb->Uprev2, pb->Uprev3, pb->nact);
     k_apply_dirichlet<D><<<grid1(F.nn, B), TPB, 0, st>>>(g, sp, pb->U, pb->tdev, pb->nact);
     HIPCHK(hipGetLastError());
     CHK(newton_solve_step<D, S>(pb, B, sp, hact, rs, st));
@@ -1670,7 +1676,7 @@ static fsi_status setup_impl(const fsi_params* prm, fsi_problem** out) {
       p.gmres_maxit < 1 || (p.precision != FSI_FP64 && p.precision != FSI_MIXED) ||
       (p.precond_lag != 0 && p.precond_lag != 1) || !(p.lin_rtol_first > 0.0 && p.lin_rtol_first < 1.0) ||
       p.parareal_theta < 0 || p.parareal_theta > 2 || !(p.theta_ref_k >= 0.0) || p.parareal_pipeline < 0 ||
-      p.parareal_pipeline > p.max_batch || p.batch_split < 0 || p.batch_split > 8 || p.batch_split > p.max_batch)
+      p.parareal_pipeline > p.max_batch || p.batch_split < 0 || p.batch_split > 8 || p.newton_guess < 0 || p.newton_guess > 3 || p.batch_split > p.max_batch)
     return FSI_ERR_ARG;
   for (int a = 0; a < p.dim; ++a) {
     if (p.nseg[a] < 1 || p.nseg[a] > 4) return FSI_ERR_ARG;
@@ -1729,6 +1735,8 @@ static fsi_status setup_impl(const fsi_params* prm, fsi_problem** out) {
   A_(dalloc(pb, &pb->U, B * ndof));
   A_(dalloc(pb, &pb->Uold, B * ndof));
   A_(dalloc(pb, &pb->Uprev, B * ndof));
+  if (p.newton_guess >= 2) A_(dalloc(pb, &pb->Uprev2, B * ndof));
+  if (p.newton_guess >= 3) A_(dalloc(pb, &pb->Uprev3, B * ndof));
   A_(dalloc(pb, &pb->Res, B * ndof));
   A_(dalloc(pb, &pb->Re, (size_t)B * NE * F.ncell));
   A_(dalloc(pb, &pb->Ke, (size_t)B * NE * NE * F.ncell));

@@ -108,7 +108,8 @@ __global__ void k_residual_norms(int nn, const double* R, const double* Dsc, con
                                  int nchunk, const int* active);
 __global__ void k_max_partials(int nchunk, const double* part, double* out, int B);
 __global__ void k_nonfinite(size_t n, const double* X, int* flag);
-__global__ void k_extrapolate(size_t n, double* U, const double* Uo, const double* Up, const int* active);
+__global__ void k_extrapolate(size_t n, int q, double* U, const double* U1, const double* U2, const double* U3,
+                              const double* U4, const int* active);
 __global__ void k_parareal_update(size_t n, const double* Cn, const double* Fv, const double* Cold, double* out,
                                   double th);
 template <int D>

@@ -833,13 +833,27 @@ __global__ void __launch_bounds__(RED_T) k_theta_dots(int nn, const double* __re
   }
 }
 
-// Newton initial guess of step n >= 2: linear extrapolation U = 2 U^{n-1} - U^{n-2}.
-__global__ void k_extrapolate(size_t n, double* __restrict__ U, const double* __restrict__ Uo,
-                              const double* __restrict__ Up, const int* __restrict__ active) {
+// Newton initial guess of step n: the polynomial of degree q (1 to 3) through the
+// states at t_{n-1}, ..., t_{n-1-q} (equal steps) evaluated at t_n, i.e. the
+// binomial weights U = sum_j (-1)^j C(q+1, j+1) U^{n-1-j}:
+//   q = 1: 2 U^{n-1} - U^{n-2};  q = 2: 3 U^{n-1} - 3 U^{n-2} + U^{n-3};
+//   q = 3: 4 U^{n-1} - 6 U^{n-2} + 4 U^{n-3} - U^{n-4}.
+__global__ void k_extrapolate(size_t n, int q, double* __restrict__ U, const double* __restrict__ U1,
+                              const double* __restrict__ U2, const double* __restrict__ U3,
+                              const double* __restrict__ U4, const int* __restrict__ active) {
   const int b = blockIdx.y;
   if (active && !active[b]) return;
-  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
-    U[(size_t)b * n + e] = 2.0 * Uo[(size_t)b * n + e] - Up[(size_t)b * n + e];
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+    const size_t o = (size_t)b * n + e;
+    double u;
+    if (q == 1)
+      u = 2.0 * U1[o] - U2[o];
+    else if (q == 2)
+      u = 3.0 * (U1[o] - U2[o]) + U3[o];
+    else
+      u = 4.0 * (U1[o] + U3[o]) - 6.0 * U2[o] - U4[o];
+    U[o] = u;
+  }
 }
 
 // flag[b] = 1 if any entry of X[b] is not finite

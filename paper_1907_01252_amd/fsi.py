@@ -42,7 +42,7 @@ class Params(C.Structure):
         ("lin_rtol_first", C.c_double), ("parareal_theta", C.c_int32), ("theta_ref_k", C.c_double),
         ("parareal_pipeline", C.c_int32), ("batch_split", C.c_int32), ("newton_res_rtol", C.c_double),
         ("spmv_slice_fast", C.c_int32), ("vanka_slice_fast", C.c_int32), ("vanka_wide_cells", C.c_int32),
-        ("degree", C.c_int32), ("newton_res_accept", C.c_double),
+        ("degree", C.c_int32), ("newton_res_accept", C.c_double), ("newton_guess", C.c_int32),
     ]
 
 
@@ -106,6 +106,10 @@ def _check(code, where):
 # the 2d FP64 (128x32 cells, 32 slices), 2d mixed (256x64, 64 slices) and 3d mixed
 # (64x16x16, 16 slices) sweeps (four groups are slower: with the caller's stream
 # they need more hardware queues than a process gets by default)
+# newton_guess = 3: Newton starts from the cubic extrapolation of the last four states
+# (against the linear one: 2d mixed 256x64 cells 13% fewer Krylov iterations and 13% faster,
+# 2d FP64 128x32 cells 6% faster; the 3d 64x16x16 sweep is equal within 0.6% for degrees
+# 1-3 and keeps the linear guess)
 # newton_res_accept = 1e-12: a step whose scaled FP64 residual is already at 1e-12 of the
 # state at the top of a Newton iteration ends there (2d c2: 30% fewer Newton and 25% fewer
 # Krylov iterations, 1.84e7 instead of 1.46e7 dof*steps/s; oracle parity still 1e-12)
@@ -113,14 +117,15 @@ SOLVER_DEFAULTS = dict(cip_gamma=1e-4, gmres_restart=30, gmres_maxit=300, newton
                        vanka_sweeps=2, vanka_omega=0.9, newton_rtol=1e-10, lin_rtol=1e-6,
                        vanka_sweeps_coarse=1, precond_lag=1, lin_rtol_first=1e-3, parareal_theta=0,
                        theta_ref_k=0.0, parareal_pipeline=0, batch_split=3, newton_res_rtol=1e-10,
-                       spmv_slice_fast=-1, vanka_slice_fast=-1, vanka_wide_cells=0, newton_res_accept=1e-12)
+                       spmv_slice_fast=-1, vanka_slice_fast=-1, vanka_wide_cells=0, newton_res_accept=1e-12,
+                       newton_guess=3)
 # 3d: the multiplicative 8-colour Vanka sweep is stable only with more damping
 # (a sweep with omega 0.9 amplifies errors at the 64x16x16 level), and the
 # level-0 gradient-jump penalty needs a larger weight for the coarse correction
 # to contract; a Newton step ends early only at a residual 1e-13 of the state
 # (at 1e-12 the FP64 32x8x8-cell steps kept 5e-11 of the oracle's, at 1e-13
 # no faster in 3d)
-SOLVER_DEFAULTS_3D = dict(vanka_omega=0.6, cip_gamma=3e-4, newton_res_accept=1e-13)
+SOLVER_DEFAULTS_3D = dict(vanka_omega=0.6, cip_gamma=3e-4, newton_res_accept=1e-13, newton_guess=1)
 
 
 def tuned_choice(dim, level, precision, max_batch):

@@ -147,6 +147,40 @@ def test_fine_propagate_parity_fp64(fsi, c1):
         assert max(err.values()) <= 1e-10, (b, err)
 
 
+@pytest.fixture(scope="module")
+def c1_six_steps(c1):
+    """Two c1 slices of six fine steps (from rest at t = 0 and from the state at t = 6 k) and
+    the oracle's end states."""
+    p, _, D = c1
+    k = p["k_fine"]
+    m = 6
+    U0 = np.zeros((D.mesh.n_nodes, 5))
+    inputs = [U0, P.propagate(D, U0, 0.0, m * k, m)]
+    t0 = [0.0, m * k]
+    return inputs, t0, m, [P.propagate(D, inputs[b], t0[b], m * k, m) for b in range(2)]
+
+
+@pytest.mark.parametrize("guess", [0, 1, 2, 3])
+def test_newton_guess_does_not_change_the_steps(fsi, c1, c1_six_steps, guess):
+    """Newton's starting point (the old state, or the extrapolation of degree 1-3 of the last
+    states; the binding's default is 3 in 2d) changes the iteration counts, not the converged steps:
+    six steps of two c1 slices against the oracle to 1e-10."""
+    p, _, D = c1
+    inputs, t0, m, ref = c1_six_steps
+    _say(f"case: fine_propagate fp64 c1 B=2 m={m} newton_guess={guess}")
+    prob = fsi.Problem(fsi.make_params(p, precision="fp64", max_batch=2, batch_split=0, newton_guess=guess))
+    Uin = _dev(np.stack(inputs))
+    Uout = torch.zeros_like(Uin)
+    code, st = prob.fine_propagate(2, t0, m * p["k_fine"], m, Uin, Uout)
+    Ug = _host(Uout)
+    prob.close()
+    assert code == fsi.FSI_OK
+    for b in range(2):
+        err = field_rel(Ug[b], ref[b], norm="l2")
+        _say("slice", b, "newton", st.newton_its[b], "krylov", st.krylov_its[b], "err", err)
+        assert max(err.values()) <= 1e-10, (b, err)
+
+
 def test_batched_equals_sequential(fsi, c1):
     p, prob, D = c1
     _say("case: batched vs sequential c1 B=3")
