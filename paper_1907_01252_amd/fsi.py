@@ -106,6 +106,14 @@ def _check(code, where):
 # the 2d FP64 (128x32 cells, 32 slices), 2d mixed (256x64, 64 slices) and 3d mixed
 # (64x16x16, 16 slices) sweeps (four groups are slower: with the caller's stream
 # they need more hardware queues than a process gets by default)
+# lin_rtol: floor of the relative tolerance of every linear solve after a step's first (the
+# forcing term min(1e-2, max(lin_rtol, 0.1 newton_rtol / update size))).  With the
+# extrapolated guesses, solving each Newton correction to fewer digits is faster (more Newton
+# iterations, fewer Krylov ones), but the steps' error against the oracle follows the last
+# correction's accuracy (2d 32x8 cells, six steps: 3e-12 at 1e-6 and 1e-5, 5e-11 to
+# 8e-11 at 1e-4, 1e-9 at 1e-3, whatever the residual test): FP64 1e-5 (128x32 cells 4%
+# faster than 1e-6); mixed precision, whose tolerance is 1e-6, 1e-3 in 2d (256x64 cells 28%
+# faster) and 1e-4 in 3d (64x16x16 cells 13% faster)
 # newton_guess = 3: Newton starts from the cubic extrapolation of the last four states
 # (against the linear one: 2d mixed 256x64 cells 13% fewer Krylov iterations and 13% faster,
 # 2d FP64 128x32 cells 6% faster; the 3d 64x16x16 sweep is equal within 0.6% for degrees
@@ -114,7 +122,7 @@ def _check(code, where):
 # state at the top of a Newton iteration ends there (2d c2: 30% fewer Newton and 25% fewer
 # Krylov iterations, 1.84e7 instead of 1.46e7 dof*steps/s; oracle parity still 1e-12)
 SOLVER_DEFAULTS = dict(cip_gamma=1e-4, gmres_restart=30, gmres_maxit=300, newton_maxit=30,
-                       vanka_sweeps=2, vanka_omega=0.9, newton_rtol=1e-10, lin_rtol=1e-6,
+                       vanka_sweeps=2, vanka_omega=0.9, newton_rtol=1e-10, lin_rtol=1e-5,
                        vanka_sweeps_coarse=1, precond_lag=1, lin_rtol_first=1e-3, parareal_theta=0,
                        theta_ref_k=0.0, parareal_pipeline=0, batch_split=3, newton_res_rtol=1e-10,
                        spmv_slice_fast=-1, vanka_slice_fast=-1, vanka_wide_cells=0, newton_res_accept=1e-12,
@@ -126,6 +134,8 @@ SOLVER_DEFAULTS = dict(cip_gamma=1e-4, gmres_restart=30, gmres_maxit=300, newton
 # (at 1e-12 the FP64 32x8x8-cell steps kept 5e-11 of the oracle's, at 1e-13
 # no faster in 3d)
 SOLVER_DEFAULTS_3D = dict(vanka_omega=0.6, cip_gamma=3e-4, newton_res_accept=1e-13, newton_guess=1)
+# mixed precision (the FP32 inner solve; tolerance 1e-6 after the FP64 refinement): lin_rtol by dimension
+LIN_RTOL_MIXED = {2: 1e-3, 3: 1e-4}
 
 
 def tuned_choice(dim, level, precision, max_batch):
@@ -172,6 +182,8 @@ def make_params(d: dict, precision=None, max_batch=None, tuned=True, **solver) -
         setattr(p, key, float(d[key]))
     prec = precision if precision is not None else d.get("precision", "fp64")
     p.precision = FSI_MIXED if prec in ("mixed", FSI_MIXED) else FSI_FP64
+    if p.precision == FSI_MIXED and "lin_rtol" not in solver and "lin_rtol" not in d:
+        s["lin_rtol"] = LIN_RTOL_MIXED[d["dim"]]
     p.max_batch = int(max_batch if max_batch is not None else d.get("N", 1))
     if "batch_split" not in solver and p.max_batch < s["batch_split"]:
         s["batch_split"] = p.max_batch if p.max_batch >= 2 else 0   # no more groups than slices
