@@ -762,7 +762,7 @@ void smooth(fsi_problem* pb, int l, int B, double k, int sweeps, bool zero_first
       const int nc = color_info<D>(g, c, vc).nc;
       const double vec = 3.0 * g.nn * NC * sizeof(S);
       // inverse rows per slice; in the split patch solve Y1, Y2 once per launch
-      constexpr bool SP = patch_split<S, CJ>();
+      constexpr bool SP = patch_split<D, S, CJ>();
       const double inv = (double)ainv_rows<D, SP>() * NE * nc * sizeof(S);
       const double ysh = SP ? (double)yu_cell<D>() * nc * sizeof(S) : 0.0;
       const int nb = prof_nb(pb, B);

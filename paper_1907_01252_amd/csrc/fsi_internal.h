@@ -307,11 +307,12 @@ __host__ __device__ inline size_t ainv_slice(int ncell) {
 // patch update is delta_w = (A^{-1} r)_w from the NW rows of the inverse that
 // belong to w (stored per slice), then delta_u,i = Y1_i r_u,i - Y2_i delta_v,i.
 // Rows of the full layout (the transposed adjoint system) are all stored.
-// the split patch solve is used with the compressed layout in FP64 (in FP32 the
-// 3d mixed-precision step on 32x8x8 cells no longer converged with it)
-template <class S, bool CJ>
+// the split patch solve is used with the compressed layout in FP64 and in 2d FP32
+// (in 3d FP32 one slice of the mixed-precision step on 32x8x8 cells no longer
+// converged with it)
+template <int D, class S, bool CJ>
 __host__ __device__ constexpr bool patch_split() {
-  return CJ && sizeof(S) == 8;
+  return CJ && (sizeof(S) == 8 || D == 2);
 }
 template <int D, bool CJ>
 __host__ __device__ constexpr int ainv_rows() {

@@ -61,14 +61,14 @@ __global__ void __launch_bounds__(Dm<D>::NC * 64, (vanka_waves_per_simd<D, S, CJ
   constexpr int RX2 = 2 * VC + 4, RY2 = 6, RZ2 = D == 3 ? 6 : 1;
   __shared__ S xr[RX1 * RY1 * RZ1 * NC];
   __shared__ S pr[RX2 * RY2 * RZ2];
-  constexpr bool SP = patch_split<S, CJ>();   // split patch solve (see ainv_rows)
+  constexpr bool SP = patch_split<D, S, CJ>();   // split patch solve (see ainv_rows)
   __shared__ S dv[SP ? NL * D : 1][VC];        // velocity part of the patch update
   // 2d FP64 split solve: the displacement-row waves, which have the fewest stencil loads,
   // copy the block's inverse rows (one contiguous region) to LDS while the other waves
   // load the Jacobian, so the inverse is not fetched only after the residual barrier
   // (in 2d FP32 those waves also form the pressure stabilisation, and the copy made
   // the 256x64-cell pass 1.6 times slower)
-  constexpr bool AL = D == 2 && SP;
+  constexpr bool AL = D == 2 && SP && sizeof(S) == 8;
   constexpr int NR = ainv_rows<D, SP>();
   __shared__ S ainvL[AL ? NR * NE * VC : 1];
   // slice_fast = 2: active is the ordered list of working slices (k_update_gact)

@@ -29,7 +29,7 @@ __global__ void __launch_bounds__(vf_lanes<D>() * vf_patches<D>()) k_vanka_facto
   __shared__ double Q[2][NP][NE];   // published pivot row, one buffer per step parity
   __shared__ int colmap[NP][NE];    // pivot row of each column
   // [A_uu,i | A_uv,i | I] of every displacement component i (slice 0 only)
-  constexpr bool SP = patch_split<S, CJ>();
+  constexpr bool SP = patch_split<D, S, CJ>();
   __shared__ double Mu[SP ? NP : 1][SP ? D : 1][SP ? NL : 1][SP ? 3 * NL : 1];
   const int bs = blockIdx.y;
   if (active && !active[bs]) return;   // uniform over the block
