@@ -522,11 +522,13 @@ std::vector<double> q2_lps_stencil(const Level& C, const Level& N, const fsi_par
 }
 
 // ------------------------------------------------------------ profiling
+// The timing events carry no system-scope fence: they only measure, and a fence at
+// every event would write back and invalidate the caches between the timed launches.
 void prof_rec(fsi_problem* pb, hipEvent_t* e, hipStream_t st) {
   Prof& P = pb->prof;
   if (P.used >= P.pool.size()) {
     hipEvent_t ev;
-    (void)hipEventCreate(&ev);
+    (void)hipEventCreateWithFlags(&ev, hipEventDisableSystemFence);
     P.pool.push_back(ev);
   }
   *e = P.pool[P.used++];
