@@ -167,3 +167,64 @@ def test_c2q2_fullsize_sampled_slice(fsi):
     err = field_rel(Ug[l], ref, norm="l2")
     _say("slice", l, "newton", st.newton_its[l], "krylov", st.krylov_its[l], err)
     assert max(err.values()) <= 1e-10, err
+
+
+# ---- edge cases of the Q2 path (as for Q1 in test_gpu_edge.py)
+
+def test_q2_rest_state_is_a_fixed_point(fsi):
+    """Zero inflow from rest: every step's residual is zero at the guess, so no linear solve runs
+    and the state stays exactly zero (fine and coarse propagator)."""
+    p = synth.workload("c1q2", seed=0, inflow_peak=0.0)
+    m = 3
+    _say("case: Q2 zero inflow, zero state, c1q2 B=2")
+    prob = fsi.Problem(fsi.make_params(p, precision="fp64", max_batch=2))
+    U = torch.zeros(2, prob.n_nodes, 5, dtype=torch.float64, device="cuda")
+    out = torch.full_like(U, 7.0)
+    code, st = prob.fine_propagate(2, [0.0, p["slice_len"]], p["slice_len"], m, U, out)
+    assert code == fsi.FSI_OK
+    assert not bool(out.any()), _host(out).max()
+    assert list(st.krylov_its[:2]) == [0, 0], list(st.krylov_its[:2])
+    code, st = prob.coarse_propagate(2, [0.0, p["slice_len"]], p["slice_len"], 1, U, out)
+    assert code == fsi.FSI_OK and not bool(out.any())
+    prob.close()
+
+
+def test_q2_nonfinite_input_is_refused(fsi):
+    p = synth.workload("c1q2", seed=2)
+    _say("case: Q2 NaN in slice 1 of a c1q2 batch of 2")
+    D = Discretization(p)
+    prob = fsi.Problem(fsi.make_params(p, precision="fp64", max_batch=2))
+    U = np.stack([D.apply_dirichlet(synth.smooth_state(p, 40 + l), 0.0) for l in range(2)])
+    U[1, 17, 4] = np.nan
+    out = torch.full((2, prob.n_nodes, 5), 7.0, dtype=torch.float64, device="cuda")
+    code, st = prob.fine_propagate(2, [0.0, 0.0], p["slice_len"], 2, _dev(U), out, raise_on_error=False)
+    assert code == fsi.FSI_ERR_NONFINITE
+    assert list(st.slice_status[:2]) == [fsi.FSI_OK, fsi.FSI_ERR_NONFINITE]
+    assert bool((_host(out) == 7.0).all())
+    prob.close()
+
+
+def test_q2_groups_and_aliasing_equal_one_batch(fsi):
+    """Concurrent slice groups (batch_split 2 and 3) and an aliased U_in/U_out give the single
+    batch's outputs and iteration counts bit for bit (c1q2, B = 5)."""
+    p = synth.workload("c1q2", seed=5)
+    _say("case: Q2 c1q2 B=5, batch_split 0 vs 2 vs 3, and in place")
+    D = Discretization(p)
+    dl = p["slice_len"]
+    t0 = [l * dl for l in range(5)]
+    U = np.stack([D.apply_dirichlet(synth.smooth_state(p, 100 + l), t0[l]) for l in range(5)])
+    res = {}
+    for split in (0, 2, 3):
+        prob = fsi.Problem(fsi.make_params(p, precision="fp64", max_batch=5, batch_split=split))
+        out = torch.zeros(5, prob.n_nodes, 5, dtype=torch.float64, device="cuda")
+        code, st = prob.fine_propagate(5, t0, dl, 2, _dev(U), out)
+        assert code == fsi.FSI_OK
+        res[split] = (_host(out), list(st.newton_its[:5]), list(st.krylov_its[:5]))
+        if split == 0:
+            inplace = _dev(U)
+            prob.fine_propagate(5, t0, dl, 2, inplace, inplace)
+            assert np.array_equal(_host(inplace), res[0][0])
+        prob.close()
+    for split in (2, 3):
+        assert np.array_equal(res[split][0], res[0][0]), (split, np.abs(res[split][0] - res[0][0]).max())
+        assert res[split][1:] == res[0][1:], (split, res[split][1:], res[0][1:])
