@@ -139,10 +139,11 @@ typedef struct {
                                 the batch runs the fused Vanka pass with 32 cells per block,
                                 others with 8 (0: 8192) */
   int32_t degree;            /* polynomial degree of the equal-order elements (Section 2.2):
-                                1 (Q1, every mode) or 2 (Q2, the paper's choice; 2d FP64, no
-                                adjoint).  With degree 2 the cells are those of `level` (which
-                                may then be 0) and the nodes those of level + 1 (9 per cell);
-                                the Krylov operator is the Q2 step Jacobian and the
+                                1 (Q1, every mode) or 2 (Q2, the paper's choice; 2d, FP64 or
+                                mixed precision, no adjoint).  With degree 2 the cells are
+                                those of `level` (which may then be 0) and the nodes those of
+                                level + 1 (9 per cell); the Krylov operator is the Q2 step
+                                Jacobian (stored in the linear solve's type) and the
                                 preconditioner the Q1 multigrid V-cycle on the same nodes */
   double newton_res_accept;  /* 0: off.  > 0: a slice whose residual at the top of a Newton
                                 iteration (after at least one update) meets the residual test

@@ -1101,10 +1101,12 @@ __global__ void k_gather_residual_q2(Geom gc, Geom gn, StepPar sp, const double*
 }
 
 // Gather the Q2 element matrices into the 5 x 5 node stencil of full 5 x 5 blocks,
-// J2[b][25 slot + 5 r + c][node] (slot (dx + 2) + 5 (dy + 2)); Dirichlet rows become
-// identity rows; Dsc[b][node][r] = 1 / max_j |J_rj| (with k S2 on pressure rows).
+// J2[b][25 slot + 5 r + c][node] (slot (dx + 2) + 5 (dy + 2)), stored in the linear
+// solve's type S (summed in FP64); Dirichlet rows become identity rows;
+// Dsc[b][node][r] = 1 / max_j |J_rj| (with k S2 on pressure rows).
+template <class S>
 __global__ void k_gather_jacobian_q2(Geom gc, Geom gn, double k, const double* __restrict__ pst2,
-                                     const double* __restrict__ Ke, double* __restrict__ J2,
+                                     const double* __restrict__ Ke, S* __restrict__ J2,
                                      double* __restrict__ Dsc, const int* __restrict__ active) {
   constexpr int NC = 5;
   const int b = blockIdx.y;
@@ -1114,7 +1116,7 @@ __global__ void k_gather_jacobian_q2(Geom gc, Geom gn, double k, const double* _
   int cxs[2], oxs[2], cys[2], oys[2];
   const int ncx = q2_cells_of(I, gc.nx, cxs, oxs), ncy = q2_cells_of(Jn, gc.ny, cys, oys);
   const double* ke = Ke + (size_t)b * Q2NE * Q2NE * gc.ncell;
-  double* jb = J2 + (size_t)b * 625 * gn.nn + n;
+  S* jb = J2 + (size_t)b * 625 * gn.nn + n;
   const uint8_t m = gn.dmask[n];
   double rmax[NC] = {0.0, 0.0, 0.0, 0.0, 0.0};
   for (int s = 0; s < 25; ++s) {
@@ -1138,7 +1140,7 @@ __global__ void k_gather_jacobian_q2(Geom gc, Geom gn, double k, const double* _
         for (int c = 0; c < NC; ++c) blk[NC * r + c] = (s == 12 && c == r) ? 1.0 : 0.0;
       for (int c = 0; c < NC; ++c) rmax[r] = fmax(rmax[r], fabs(blk[NC * r + c]));
     }
-    for (int e = 0; e < 25; ++e) jb[(size_t)(25 * s + e) * gn.nn] = blk[e];
+    for (int e = 0; e < 25; ++e) jb[(size_t)(25 * s + e) * gn.nn] = (S)blk[e];
   }
   if (!(m & dm_p<2>())) {
     double pm = 0.0;
@@ -1151,38 +1153,48 @@ __global__ void k_gather_jacobian_q2(Geom gc, Geom gn, double k, const double* _
 }
 
 // Product with the Q2 Jacobian, y = D (bv - J2 x) (or D J2 x without bv; D = 1 without
-// Dsc), the stabilisation k S2 included on the pressure rows.  One thread per node;
-// a neighbour slot outside the mesh reads the node itself (J2 and pst2 hold zeros there).
-__global__ void k_spmv_q2(Geom gn, double k, const double* __restrict__ pst2, const double* __restrict__ J2,
-                          const double* __restrict__ x, const double* __restrict__ bv,
-                          const double* __restrict__ Dsc, double* __restrict__ y,
+// Dsc), the stabilisation k S2 included on the pressure rows, in the linear solve's
+// type S (FP32 accumulation in the mixed-precision path).  One thread per node; a
+// neighbour slot outside the mesh reads the node itself (J2 and pst2 hold zeros there).
+template <class S>
+__global__ void k_spmv_q2(Geom gn, double k, const double* __restrict__ pst2, const S* __restrict__ J2,
+                          const S* __restrict__ x, const S* __restrict__ bv,
+                          const double* __restrict__ Dsc, S* __restrict__ y,
                           const int* __restrict__ active) {
   constexpr int NC = 5;
   const int b = blockIdx.y;
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= gn.nn || (active && !active[b])) return;
   const int I = n % (gn.nx + 1), Jn = n / (gn.nx + 1);
-  const double* jb = J2 + (size_t)b * 625 * gn.nn + n;
-  const double* xb = x + (size_t)b * gn.nn * NC;
-  double acc[NC] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  const S* jb = J2 + (size_t)b * 625 * gn.nn + n;
+  const S* xb = x + (size_t)b * gn.nn * NC;
+  S acc[NC] = {0, 0, 0, 0, 0};
   for (int s = 0; s < 25; ++s) {
     const int ii = I + s % 5 - 2, jj = Jn + s / 5 - 2;
     const int nb = (ii < 0 || jj < 0 || ii > gn.nx || jj > gn.ny) ? n : ii + (gn.nx + 1) * jj;
-    double xn[NC];
+    S xn[NC];
     for (int c = 0; c < NC; ++c) xn[c] = xb[(size_t)nb * NC + c];
     for (int r = 0; r < NC; ++r) {
-      double a = acc[r];
+      S a = acc[r];
       for (int c = 0; c < NC; ++c) a = fma(jb[(size_t)(25 * s + NC * r + c) * gn.nn], xn[c], a);
       acc[r] = a;
     }
-    acc[4] = fma(k * pst2[(size_t)s * gn.nn + n], xn[4], acc[4]);
+    acc[4] = fma((S)(k * pst2[(size_t)s * gn.nn + n]), xn[4], acc[4]);
   }
   const size_t o = ((size_t)b * gn.nn + n) * NC;
   for (int r = 0; r < NC; ++r) {
-    const double v = bv ? bv[o + r] - acc[r] : acc[r];
-    y[o + r] = Dsc ? Dsc[o + r] * v : v;
+    const S v = bv ? bv[o + r] - acc[r] : acc[r];
+    y[o + r] = Dsc ? (S)(Dsc[o + r] * v) : v;
   }
 }
+template __global__ void k_gather_jacobian_q2<double>(Geom, Geom, double, const double*, const double*, double*,
+                                                      double*, const int*);
+template __global__ void k_gather_jacobian_q2<float>(Geom, Geom, double, const double*, const double*, float*,
+                                                     double*, const int*);
+template __global__ void k_spmv_q2<double>(Geom, double, const double*, const double*, const double*, const double*,
+                                           const double*, double*, const int*);
+template __global__ void k_spmv_q2<float>(Geom, double, const double*, const float*, const float*, const float*,
+                                          const double*, float*, const int*);
 
 #define FSI_INST_ASM(D)                                                                                           \
   template __global__ void k_elem_residual<D>(Geom, StepPar, const double*, const double*, double*, const int*); \

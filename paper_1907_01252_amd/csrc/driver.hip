@@ -118,7 +118,8 @@ struct fsi_problem {
   // Q2 cells (degree 2, 2d FP64): the cells are those of level nlev - 2, the nodes those of
   // the finest level; the Q1 hierarchy on the same nodes is the preconditioner
   int deg = 1;
-  double *pst2 = nullptr, *J2 = nullptr, *Ke2 = nullptr, *Re2 = nullptr;
+  double *pst2 = nullptr, *Ke2 = nullptr, *Re2 = nullptr;
+  void *J2 = nullptr;   // Q2 step Jacobian in the linear solve's type
   // FGMRES: Arnoldi step j replayed from a captured graph (V-cycle included) per (B, k, type,
   // layout); a few configurations are kept.  Each step writes the slices' Krylov states to
   // pinned host memory (one buffer per step parity) and records an event.
@@ -690,7 +691,8 @@ fsi_status assemble_levels(fsi_problem* pb, int B, const StepPar& sp, const int*
         k_elem_jacobian_q2<<<dim3((gc.ncell + Q2_JAC_CELLS - 1) / Q2_JAC_CELLS, B), Q2_JAC_THREADS, 0, st>>>(
             gc, gn, sp, pb->U, pb->Uold, pb->Ke2, act);
       }
-      k_gather_jacobian_q2<<<grid1(gn.nn, B), TPB, 0, st>>>(gc, gn, sp.k, pb->pst2, pb->Ke2, pb->J2, F.Dsc, act);
+      k_gather_jacobian_q2<S><<<grid1(gn.nn, B), TPB, 0, st>>>(gc, gn, sp.k, pb->pst2, pb->Ke2, (S*)pb->J2, F.Dsc,
+                                                                act);
       HIPCHK(hipGetLastError());
     }
   }
@@ -728,15 +730,14 @@ void spmv(const fsi_problem* pb, const Geom& g, int B, double k, const S* J, con
 }
 
 // The Krylov operator's product y = D (b - J x) (or D J x): the Q1 step Jacobian of the
-// finest level, or with Q2 cells their Jacobian (FP64).
+// finest level, or with Q2 cells their Jacobian (in the linear solve's type).
 template <int D, class S, bool CJ>
 void krylov_spmv(const fsi_problem* pb, int B, double k, const S* x, const S* b, const double* Dv, S* y,
                  const int* act, hipStream_t st) {
   const Level& F = pb->lev[pb->nlev - 1];
-  if constexpr (D == 2 && sizeof(S) == 8 && CJ) {
+  if constexpr (D == 2 && CJ) {
     if (pb->deg == 2) {
-      k_spmv_q2<<<grid1(F.nn, B), TPB, 0, st>>>(F.geom(), k, pb->pst2, pb->J2, (const double*)x, (const double*)b, Dv,
-                                               (double*)y, act);
+      k_spmv_q2<S><<<grid1(F.nn, B), TPB, 0, st>>>(F.geom(), k, pb->pst2, (const S*)pb->J2, x, b, Dv, y, act);
       return;
     }
   }
@@ -1057,7 +1058,7 @@ fsi_status fgmres(fsi_problem* pb, int B, double k, std::vector<int>& kits, hipS
       S* a = tmp;
       {
         const int nb = prof_nb(pb, B);
-        const double jb = pb->deg == 2 ? (double)nb * 625.0 * F.nn * 8.0 + 25.0 * F.nn * 8.0 : jbytes_launch<D, S, CJ>(g, nb);
+        const double jb = pb->deg == 2 ? (double)nb * 625.0 * F.nn * sizeof(S) + 25.0 * F.nn * 8.0 : jbytes_launch<D, S, CJ>(g, nb);
         ProfScope ps(pb, F_GMRES_SPMV, st, jb + (double)nb * (2.0 * n * sizeof(S) + n * 8.0) + (double)NPST * F.nn * 8.0);
         krylov_spmv<D, S, CJ>(pb, B, k, w, nullptr, F.Dsc, a, pb->gact, st);
       }
@@ -1696,7 +1697,7 @@ static fsi_status setup_impl(const fsi_params* prm, fsi_problem** out) {
       !(p.newton_res_rtol > 0 && p.newton_res_rtol < 1) || !(p.newton_res_accept >= 0 && p.newton_res_accept < 1) || p.spmv_slice_fast < -1 || p.spmv_slice_fast > 1 ||
       p.vanka_slice_fast < -1 || p.vanka_slice_fast > 1 || p.vanka_wide_cells < 0 ||
       (p.degree != 1 && p.degree != 2) ||
-      (p.degree == 2 && (p.dim != 2 || p.precision != FSI_FP64 || p.level + 2 > MAXLEV - 1)))
+      (p.degree == 2 && (p.dim != 2 || p.level + 2 > MAXLEV - 1)))
     return FSI_ERR_ARG;
   fsi_problem* pb = new (std::nothrow) fsi_problem();
   if (!pb) return FSI_ERR_OOM;
@@ -1777,7 +1778,7 @@ static fsi_status setup_impl(const fsi_params* prm, fsi_problem** out) {
   if (pb->deg == 2) {
     const Level& Cq = pb->lev[pb->nlev - 2];   // the Q2 cells
     A_(upload(pb, &pb->pst2, q2_lps_stencil(Cq, F, p)));
-    A_(dalloc(pb, &pb->J2, (size_t)B * 625 * F.nn));
+    A_(dalloc_bytes(pb, &pb->J2, (size_t)B * 625 * F.nn * ss));
     A_(dalloc(pb, &pb->Ke2, (size_t)B * 45 * 45 * Cq.ncell));
     A_(dalloc(pb, &pb->Re2, (size_t)B * 45 * Cq.ncell));
   }

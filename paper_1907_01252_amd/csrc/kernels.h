@@ -34,10 +34,12 @@ __global__ void k_elem_jacobian_q2(Geom gc, Geom gn, StepPar sp, const double* U
                                    const int* active);
 __global__ void k_gather_residual_q2(Geom gc, Geom gn, StepPar sp, const double* pst2, const double* Re,
                                      const double* U, const double* t, double* R, const int* active);
-__global__ void k_gather_jacobian_q2(Geom gc, Geom gn, double k, const double* pst2, const double* Ke, double* J2,
+template <class S>
+__global__ void k_gather_jacobian_q2(Geom gc, Geom gn, double k, const double* pst2, const double* Ke, S* J2,
                                      double* Dsc, const int* active);
-__global__ void k_spmv_q2(Geom gn, double k, const double* pst2, const double* J2, const double* x, const double* bv,
-                          const double* Dsc, double* y, const int* active);
+template <class S>
+__global__ void k_spmv_q2(Geom gn, double k, const double* pst2, const S* J2, const S* x, const S* bv,
+                          const double* Dsc, S* y, const int* active);
 constexpr int Q2_JAC_CELLS = 64, Q2_JAC_THREADS = 256;   // k_elem_jacobian_q2 launch shape
 
 // 2d adjoint

@@ -89,6 +89,9 @@ _WORKLOADS = {
                  precision="fp64", parareal_tol=1e-8, mu_s=5e5),
     "c2q2": dict(dim=2, level=2, degree=2, T=2.0, N=32, dt_fine=0.002, dt_coarse=0.02,
                  precision="fp64", parareal_tol=1e-8, mu_s=2e6),
+    # Q2 cells on the nodes of c3 (128x32 cells), mixed precision
+    "c3q2": dict(dim=2, level=3, degree=2, T=2.0, N=64, dt_fine=0.001, dt_coarse=0.01,
+                 precision="mixed", parareal_tol=1e-8, mu_s=5e5),
     # 3d, 64x16x16 hexahedra, 16 slices on [0,0.8]
     "c5": dict(dim=3, level=2, T=0.8, N=16, dt_fine=0.005, dt_coarse=0.05,
                precision="mixed", parareal_tol=1e-8, mu_s=1e6),
@@ -99,7 +102,7 @@ def workload(name: str, seed: int = 0, **overrides) -> dict:
     """Return the full parameter dict of a named workload for one seed.
 
     The seed perturbs the inflow peak: c1, c2, c4 (and c1q2, c2q2) draw peak = 0.3 (1 + u),
-    u ~ U(-0.05, 0.05); c3 draws peak ~ U(0.2, 1.0); c5 keeps 0.3.
+    u ~ U(-0.05, 0.05); c3 (and c3q2) draws peak ~ U(0.2, 1.0); c5 keeps 0.3.
     """
     w = copy.deepcopy(_WORKLOADS[name])
     p = base_params(w["dim"])
@@ -108,7 +111,7 @@ def workload(name: str, seed: int = 0, **overrides) -> dict:
     rng = np.random.default_rng(seed)
     if name in ("c1", "c2", "c4", "c1q2", "c2q2"):
         p["inflow_peak"] = 0.3 * (1.0 + rng.uniform(-0.05, 0.05))
-    elif name == "c3":
+    elif name in ("c3", "c3q2"):
         p["inflow_peak"] = float(rng.uniform(0.2, 1.0))
     p.update(overrides)
     p["name"] = name

@@ -1,4 +1,5 @@
-"""GPU parity of the biquadratic (Q2) cells of Section 2.2 through the C ABI.
+"""GPU parity of the biquadratic (Q2) cells of Section 2.2 through the C ABI (FP64 and
+mixed precision).
 
 The Q2 problem on level l has the nodes of the Q1 level l + 1 and nine per
 cell; the library solves each Newton step with FGMRES on the exact Q2 Jacobian,
@@ -7,7 +8,10 @@ FP64 oracle's Q2 discretisation (oracle.residual with degree 2): the residual
 and Jacobian products to 1e-12, fine propagation to 1e-10 (c1q2: 16x4 cells,
 the 297 nodes of c1), batched against single-slice calls, and one step of a
 sampled slice of the 32-slice c2q2 batch (64x16 cells, the 21,285 unknowns of
-c2) in the launch configuration of a full sweep.
+c2) in the launch configuration of a full sweep.  Mixed precision (FP32 Q2 product
+and V-cycle inside the FP64 Newton loop): c1q2 against the oracle to 1e-6, and the
+64-slice c3q2 batch (128x32 cells, the 83,525 unknowns of c3) against the FP64 Q2
+path to 1e-6.
 """
 import sys
 
@@ -228,3 +232,55 @@ def test_q2_groups_and_aliasing_equal_one_batch(fsi):
     for split in (2, 3):
         assert np.array_equal(res[split][0], res[0][0]), (split, np.abs(res[split][0] - res[0][0]).max())
         assert res[split][1:] == res[0][1:], (split, res[split][1:], res[0][1:])
+
+
+# ---- Q2 cells in the mixed-precision path (FP32 Krylov/multigrid, FP64 Newton)
+
+def test_fine_propagate_parity_q2_mixed(fsi, c1q2):
+    """c1q2, two slices of three steps, with the FP32 inner solve: the FP64 Newton refinement
+    brings the steps to the FP64 oracle within 1e-6."""
+    p, _, D = c1q2
+    _say("case: Q2 fine_propagate mixed c1q2 B=2 m=3")
+    k = p["k_fine"]
+    m = 3
+    dl = m * k
+    U0 = np.zeros((D.mesh.n_nodes, 5))
+    Ua = P.propagate(D, U0, 0.0, 2 * dl, 6)
+    inputs, t0 = [U0, Ua], [0.0, 2 * dl]
+    ref = [P.propagate(D, inputs[b], t0[b], dl, m) for b in range(2)]
+    prob = fsi.Problem(fsi.make_params(p, precision="mixed", max_batch=2, batch_split=0))
+    Uin = _dev(np.stack(inputs))
+    Uout = torch.zeros_like(Uin)
+    code, st = prob.fine_propagate(2, t0, dl, m, Uin, Uout)
+    Ug = _host(Uout)
+    prob.close()
+    assert code == fsi.FSI_OK
+    for b in range(2):
+        err = field_rel(Ug[b], ref[b], norm="l2")
+        _say("slice", b, "newton", st.newton_its[b], "krylov", st.krylov_its[b], "err", err)
+        assert max(err.values()) <= 1e-6, (b, err)
+
+
+def test_c3q2_fullsize_mixed_equals_fp64(fsi):
+    """64 slices of c3q2 (128x32 Q2 cells on the 16,705 nodes of c3) in one call, one step, in
+    mixed precision and in FP64: the refined steps agree within 1e-6 per field on every slice
+    (the FP64 Q2 path is compared with the oracle at the c2q2 size above)."""
+    p = synth.workload("c3q2", seed=0)
+    _say("case: c3q2 full size, 64 slices in one call, one step, mixed vs FP64")
+    D = Discretization(p)
+    N, dl = p["N"], p["slice_len"]
+    t0s = [l * dl for l in range(N)]
+    U_in = np.stack([D.apply_dirichlet(synth.smooth_state(p, 300 + l), t0s[l]) for l in range(N)])
+    Uin = _dev(U_in)
+    out = {}
+    for prec in ("fp64", "mixed"):
+        prob = fsi.Problem(fsi.make_params(p, precision=prec, max_batch=N))
+        o = torch.zeros_like(Uin)
+        code, st = prob.fine_propagate(N, t0s, p["k_fine"], 1, Uin, o)
+        assert code == fsi.FSI_OK, prec
+        out[prec] = _host(o)
+        _say(prec, "newton", st.newton_total, "krylov", st.krylov_total)
+        prob.close()
+    worst = max(max(field_rel(out["mixed"][l], out["fp64"][l], norm="l2").values()) for l in range(N))
+    _say("worst slice difference", worst)
+    assert worst <= 1e-6, worst
