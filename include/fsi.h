@@ -154,6 +154,10 @@ typedef struct {
                                 the slice, evaluated at t_n (degree min(q, n - 1) at the
                                 first steps; the Dirichlet values of t_n replace it on the
                                 boundary).  The converged step does not depend on it */
+  double precond_lps_scale;  /* degree 2 only: factor on the local-projection constant of the
+                                Q1 levels that precondition the Q2 system (0: 1, the Q1
+                                discretisation's own; > 0: the factor).  Only the
+                                preconditioner changes, not the Q2 step */
 } fsi_params;
 
 #define FSI_MAX_SLICES 1024

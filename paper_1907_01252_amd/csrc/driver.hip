@@ -286,6 +286,8 @@ void cell_h(const Level& L, int i, int j, int k, double (&h)[D]) {
 template <int D>
 void build_lps(Level& L, const fsi_params& p) {
   FSI_DIM(D);
+  // with Q2 cells these levels only precondition the Q2 system: their constant may differ
+  const double lps_scale = (p.degree == 2 && p.precond_lps_scale > 0.0) ? p.precond_lps_scale : 1.0;
   constexpr int NP = D == 2 ? 9 : 27;   // nodes of the parent patch
   const Geom g = host_geom(L);
   for (int cell = 0; cell < L.ncell; ++cell) {
@@ -296,7 +298,7 @@ void build_lps(Level& L, const fsi_params& p) {
     cell_h<D>(L, i, j, k, h);
     double vol = 1.0;
     for (int r = 0; r < D; ++r) vol *= h[r];
-    const double alpha = p.lps_alpha0 * std::pow(vol, 2.0 / D) / (p.rho_f * p.nu_f);
+    const double alpha = lps_scale * p.lps_alpha0 * std::pow(vol, 2.0 / D) / (p.rho_f * p.nu_f);
     double K[NL][NL];
     q1_stiffness<D>(h, K);
     const int org[3] = {i - (i & 1), j - (j & 1), k - (k & 1)};   // parent patch origin node
@@ -1679,7 +1681,8 @@ static fsi_status setup_impl(const fsi_params* prm, fsi_problem** out) {
       p.gmres_maxit < 1 || (p.precision != FSI_FP64 && p.precision != FSI_MIXED) ||
       (p.precond_lag != 0 && p.precond_lag != 1) || !(p.lin_rtol_first > 0.0 && p.lin_rtol_first < 1.0) ||
       p.parareal_theta < 0 || p.parareal_theta > 2 || !(p.theta_ref_k >= 0.0) || p.parareal_pipeline < 0 ||
-      p.parareal_pipeline > p.max_batch || p.batch_split < 0 || p.batch_split > 8 || p.newton_guess < 0 || p.newton_guess > 3 || p.batch_split > p.max_batch)
+      p.parareal_pipeline > p.max_batch || p.batch_split < 0 || p.batch_split > 8 || p.newton_guess < 0 || p.newton_guess > 3 ||
+      !(p.precond_lps_scale >= 0 && p.precond_lps_scale < 1e6) || p.batch_split > p.max_batch)
     return FSI_ERR_ARG;
   for (int a = 0; a < p.dim; ++a) {
     if (p.nseg[a] < 1 || p.nseg[a] > 4) return FSI_ERR_ARG;

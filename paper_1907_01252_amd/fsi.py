@@ -43,6 +43,7 @@ class Params(C.Structure):
         ("parareal_pipeline", C.c_int32), ("batch_split", C.c_int32), ("newton_res_rtol", C.c_double),
         ("spmv_slice_fast", C.c_int32), ("vanka_slice_fast", C.c_int32), ("vanka_wide_cells", C.c_int32),
         ("degree", C.c_int32), ("newton_res_accept", C.c_double), ("newton_guess", C.c_int32),
+        ("precond_lps_scale", C.c_double),
     ]
 
 
@@ -114,6 +115,9 @@ def _check(code, where):
 # 8e-11 at 1e-4, 1e-9 at 1e-3, whatever the residual test): FP64 1e-5 (128x32 cells 4%
 # faster than 1e-6); mixed precision, whose tolerance is 1e-6, 1e-3 in 2d (256x64 cells 28%
 # faster) and 1e-4 in 3d (64x16x16 cells 13% faster)
+# precond_lps_scale = 2: with Q2 cells the Q1 preconditioner's stabilisation constant is
+# doubled (Krylov iterations per sweep: 64x16 Q2 cells 77,364 -> 70,793, 128x32 mixed
+# 145,728 -> 133,036; 8-9% faster; 2.5 within 1%, 4 and 0.5 slower)
 # newton_guess = 3: Newton starts from the cubic extrapolation of the last four states
 # (against the linear one: 2d mixed 256x64 cells 13% fewer Krylov iterations and 13% faster,
 # 2d FP64 128x32 cells 6% faster; the 3d 64x16x16 sweep is equal within 0.6% for degrees
@@ -126,7 +130,7 @@ SOLVER_DEFAULTS = dict(cip_gamma=1e-4, gmres_restart=30, gmres_maxit=300, newton
                        vanka_sweeps_coarse=1, precond_lag=1, lin_rtol_first=1e-3, parareal_theta=0,
                        theta_ref_k=0.0, parareal_pipeline=0, batch_split=3, newton_res_rtol=1e-10,
                        spmv_slice_fast=-1, vanka_slice_fast=-1, vanka_wide_cells=0, newton_res_accept=1e-12,
-                       newton_guess=3)
+                       newton_guess=3, precond_lps_scale=2.0)
 # 3d: the multiplicative 8-colour Vanka sweep is stable only with more damping
 # (a sweep with omega 0.9 amplifies errors at the 64x16x16 level), and the
 # level-0 gradient-jump penalty needs a larger weight for the coarse correction

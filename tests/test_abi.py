@@ -94,7 +94,8 @@ def test_argument_errors_without_gpu(lib):
                 dict(vanka_omega=2.0), dict(newton_rtol=0.0), dict(lin_rtol=1.0), dict(rho_s=float("nan")),
                 dict(batch_split=-1), dict(batch_split=9), dict(batch_split=3), dict(newton_res_rtol=0.0),
                 dict(newton_res_rtol=1.0), dict(newton_res_rtol=float("nan")), dict(newton_guess=-1),
-                dict(newton_guess=4)):
+                dict(newton_guess=4), dict(precond_lps_scale=-1.0),
+                dict(precond_lps_scale=float("nan"))):
         p = fsi.make_params(synth.workload("c1"), max_batch=2)
         for k, v in bad.items():
             setattr(p, k, v)
