@@ -138,6 +138,9 @@ SOLVER_DEFAULTS = dict(cip_gamma=1e-4, gmres_restart=30, gmres_maxit=300, newton
 # (at 1e-12 the FP64 32x8x8-cell steps kept 5e-11 of the oracle's, at 1e-13
 # no faster in 3d)
 SOLVER_DEFAULTS_3D = dict(vanka_omega=0.6, cip_gamma=3e-4, newton_res_accept=1e-13, newton_guess=1)
+# Q2 cells: one smoothing sweep on the finest Q1 level of the preconditioner (the Q2 nodes), where
+# Q1 takes two (64x16 Q2 cells 10% faster, 128x32 mixed 22%: more Krylov iterations, cheaper cycles)
+SOLVER_DEFAULTS_Q2 = dict(vanka_sweeps=1)
 # mixed precision (the FP32 inner solve; tolerance 1e-6 after the FP64 refinement): lin_rtol by dimension
 LIN_RTOL_MIXED = {2: 1e-3, 3: 1e-4}
 
@@ -161,6 +164,8 @@ def make_params(d: dict, precision=None, max_batch=None, tuned=True, **solver) -
     s = dict(SOLVER_DEFAULTS)
     if d["dim"] == 3:
         s.update(SOLVER_DEFAULTS_3D)
+    if int(d.get("degree", 1)) == 2:
+        s.update(SOLVER_DEFAULTS_Q2)
     s.update({k: v for k, v in d.items() if k in SOLVER_DEFAULTS})
     if tuned and int(d.get("degree", 1)) == 1:
         prec_name = "mixed" if (precision if precision is not None else d.get("precision", "fp64")) in \
