@@ -164,3 +164,29 @@ def test_tuned_choices_follow_the_hardware_queues(tmp_path, monkeypatch):
     monkeypatch.setenv("GPU_MAX_HW_QUEUES", "16")   # no entry of its own: the default one
     assert fsi.make_params(w, max_batch=8).batch_split == 2
     assert 4 in autotune.candidates(2, 8)["batch_split"] and 4 not in autotune.candidates(2, 4)["batch_split"]
+
+
+def test_solver_defaults_by_precision_and_degree():
+    """make_params: the measured solver defaults per dimension, precision and element degree, and
+    the caller's settings over them."""
+    import synth
+    from paper_1907_01252_amd import fsi
+
+    def mp(name, **kw):
+        return fsi.make_params(synth.workload(name), **kw)
+    p = mp("c2")                                    # 2d FP64
+    assert (p.lin_rtol, p.vanka_sweeps, p.vanka_sweeps_coarse, p.newton_guess) == (1e-5, 2, 1, 3)
+    assert abs(p.vanka_omega - 0.9) < 1e-15
+    p = mp("c3")                                    # 2d mixed
+    assert (p.lin_rtol, p.vanka_sweeps, p.vanka_sweeps_coarse, p.newton_guess) == (1e-3, 1, 2, 3)
+    p = mp("c5")                                    # 3d mixed
+    assert (p.lin_rtol, p.vanka_sweeps, p.vanka_sweeps_coarse, p.newton_guess) == (1e-4, 1, 1, 1)
+    assert abs(p.vanka_omega - 0.6) < 1e-15
+    p = mp("c5", precision="fp64")                  # 3d FP64
+    assert (p.lin_rtol, p.vanka_sweeps) == (1e-5, 2)
+    p = mp("c2q2")                                  # Q2 FP64
+    assert (p.degree, p.vanka_sweeps, p.precond_lps_scale, p.lin_rtol) == (2, 1, 2.0, 1e-5)
+    p = mp("c3q2")                                  # Q2 mixed
+    assert (p.degree, p.vanka_sweeps, p.vanka_sweeps_coarse, p.lin_rtol) == (2, 1, 2, 1e-3)
+    p = mp("c3", lin_rtol=1e-6, vanka_sweeps=2)     # the caller's settings win
+    assert (p.lin_rtol, p.vanka_sweeps, p.vanka_sweeps_coarse) == (1e-6, 2, 2)
