@@ -265,6 +265,31 @@ def test_parareal_K_equals_N(fsi, pipeline):
         assert max(err["v"], err["u"]) <= 1e-10, (l, err)
 
 
+@pytest.mark.parametrize("pipeline", [0, 4])
+def test_parareal_full_c1_K_equals_N_vs_golden(fsi, pipeline):
+    """The full c1 workload (8 slices of 13 fine and 2 coarse steps on [0, 1], 32x8 cells): Parareal
+    with K = N reproduces the oracle's sequential fine solution (stored by
+    tests/golden/make_c1_sequential.py) at every slice boundary, 1e-10 in v and u, with the plain and
+    the pipelined schedule (chunks of 4 slices)."""
+    import os
+    g = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c1_sequential.npz"))
+    p = synth.workload("c1", seed=int(g["seed"]))
+    assert (p["N"], p["m"], p["M"]) == (int(g["N"]), int(g["m"]), int(g["M"]))
+    seq = g["states"]
+    _say("case: parareal K=N full c1 N=8 m=13 M=2 pipeline", pipeline)
+    prob = fsi.Problem(fsi.make_params(p, precision="fp64", max_batch=p["N"], parareal_pipeline=pipeline))
+    U0 = np.zeros_like(seq[0])
+    Ub = torch.zeros(p["N"] + 1, prob.n_nodes, 5, dtype=torch.float64, device="cuda")
+    code, st = prob.parareal_run(p["T"], p["N"], p["m"], p["M"], 0.0, p["N"], _dev(U0), Ub, raise_on_error=False)
+    prob.close()
+    assert code in (fsi.FSI_OK, fsi.FSI_ERR_PARAREAL)
+    assert st.parareal_iters == p["N"]
+    Ug = _host(Ub)
+    for l in range(1, p["N"] + 1):
+        err = field_rel(Ug[l], seq[l], norm="l2")
+        assert max(err["v"], err["u"]) <= 1e-10, (l, err)
+
+
 def test_adjoint_gradient_parity(fsi):
     """GPU discrete adjoint vs the oracle adjoint (same functional, same trajectory)."""
     from oracle import adjoint as A
