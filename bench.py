@@ -262,8 +262,9 @@ def main():
         cpu = {"value": nd * done / cpu_wall, "unit": "dof\u00b7steps/s", "cores": cores_used,
                "threads_allowed": int(threads), "kind": "oracle",
                "sample": f"slice {l} of {args.workload}: {done} Newton-SuperLU steps, {cpu_wall:.1f} s"}
+        # the same number of steps per process as the single-process figure finished (bounded likewise)
         cpu["slice_parallel"] = oracle_slice_parallel(args.workload, [Uin[q].cpu().numpy() for q in range(N)], t0s, k,
-                                                      ns, args.cpu_procs, nd)
+                                                      done, args.cpu_procs, nd)
 
     roof = roofline_of(fams, lambda fam, pr: counter_traffic(args.workload, fam, pr), prec)
     ej = element_jacobian_roof(prob, p, N) if not args.no_extra else None
