@@ -37,7 +37,6 @@ namespace {
 
 constexpr int TPB = 256;
 constexpr int MAXLEV = 8;
-constexpr int NCHUNK_MAX = 1024;
 // elements per block of the Krylov dot products (one partial sum per block and
 // vector): at least KDOT_CHUNK, and about KDOT_BLOCKS blocks per slice, so a
 // slice batch fills the GPU and the partial sums stay few
@@ -914,7 +913,6 @@ template <int D, class S, bool CJ>
 fsi_status capture_step(fsi_problem* pb, int B, double k, int j, hipGraphExec_t* out, hipStream_t st) {
   FSI_DIM(D);
   Level& F = pb->lev[pb->nlev - 1];
-  const Geom g = F.geom();
   const int n = F.nn * NC;
   const int R = pb->R;
   const size_t vb = (size_t)(R + 1) * n, zb = (size_t)R * n;
