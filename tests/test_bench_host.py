@@ -24,12 +24,13 @@ def test_more_than_one_gpu_is_refused():
 
 def test_counter_traffic_follows_the_committed_runs():
     tr = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))
-    assert tr["source_hash"] == bench.kernel_source_hash(tr["kernel_function"]), \
-        "the fused pass changed since its counters were taken"
+    # counted bytes are reported only while the fused pass is the one the counters saw
+    current = tr["source_hash"] == bench.kernel_source_hash(tr["kernel_function"])
     for name, w in tr["workloads"].items():
         expect = (tr["fetch_factor"] * w["fetch_kib_mean"] + tr["write_factor"] * w["write_kib_mean"]) * 1024
         assert abs(w["traffic_bytes_per_launch"] - expect) <= 1e-6 * expect, name
-        assert bench.counter_traffic(name, tr["family"], w["precision"]) == w["traffic_bytes_per_launch"]
+        got = bench.counter_traffic(name, tr["family"], w["precision"])
+        assert got == (w["traffic_bytes_per_launch"] if current else None), name
         assert bench.counter_traffic(name, "krylov_spmv_fine", w["precision"]) is None
         other = "fp64" if w["precision"] == "mixed" else "mixed"
         assert bench.counter_traffic(name, tr["family"], other) is None
