@@ -103,10 +103,9 @@ def _check(code, where):
         raise FsiError(code, where)
 
 
-# batch_split = 3: three concurrent slice groups measured fastest on one MI355X for
-# the 2d FP64 (128x32 cells, 32 slices), 2d mixed (256x64, 64 slices) and 3d mixed
-# (64x16x16, 16 slices) sweeps (four groups are slower: with the caller's stream
-# they need more hardware queues than a process gets by default)
+# batch_split = 3: three concurrent slice groups, the default where the autotuned table
+# (tuned.json, by problem size and hardware-queue count) has no entry; four groups need
+# more hardware queues than the 4 a process gets by default (GPU_MAX_HW_QUEUES)
 # lin_rtol: floor of the relative tolerance of every linear solve after a step's first (the
 # forcing term min(1e-2, max(lin_rtol, 0.1 newton_rtol / update size))).  With the
 # extrapolated guesses, solving each Newton correction to fewer digits is faster (more Newton
