@@ -118,7 +118,7 @@ def main():
                     help="time one adjoint_gradient call of the c4 workload instead of the fine sweep")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU: the fine sweep's slices are batched on a single "
+        print(json.dumps({"error": "the fine propagator runs on one GPU: the sweep's slices are batched on a single "
                                    "MI355X; multi-GPU runs are not part of it", "n_gpus": args.gpus}))
         sys.exit(2)
 
